@@ -1,0 +1,235 @@
+"""CPU FP64 oracle -- TEST INFRASTRUCTURE ONLY.
+
+Thin ctypes wrapper around `vof_oracle.c` (plain C, built with
+-O2 -ffp-contract=off -fno-fast-math). Only the tests, the package smoke
+check and the benchmark's CPU-baseline leg may import this module; the
+product path never does, and nothing here imports the product package.
+
+Each function cites the passage of Fintzi, Pierson & Popinet (arXiv
+2407.07463) it follows; where the paper is silent the reading is stated in
+the C source next to the code.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SRC = [os.path.join(_HERE, "vof_oracle.c"), os.path.join(_HERE, "mlp_oracle.c")]
+_lib = None
+
+E_ARG, E_CAPACITY, E_EXTENT = -1, -3, -4
+
+
+def build(verbose: bool = False) -> str:
+    """Compile liboracle.so with gcc (no FMA contraction, no fast-math)."""
+    srcs = [s for s in SRC if os.path.exists(s)]
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+           "-o", LIB_PATH + ".tmp"] + srcs + ["-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        d, i64, i32, vp = ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+        L.orc_plane_volume.argtypes = [d, d, d, d]
+        L.orc_plane_volume.restype = d
+        L.orc_plane_alpha.argtypes = [d, d, d, d]
+        L.orc_plane_alpha.restype = d
+        L.orc_myc_normal.argtypes = [vp, vp]
+        L.orc_myc_normal.restype = ctypes.c_int
+        L.orc_face_flux.argtypes = [vp, i64, i64, i64, ctypes.c_int, i64, i64, i64, d]
+        L.orc_face_flux.restype = d
+        L.orc_sweep.argtypes = [i64, i64, i64, ctypes.c_int, vp, vp, vp, vp]
+        L.orc_sweep.restype = None
+        L.orc_advect.argtypes = [i64, i64, i64, ctypes.c_int, vp, vp, vp, vp, i64, ctypes.c_int]
+        L.orc_advect.restype = ctypes.c_int
+        L.orc_label.argtypes = [i64, i64, i64, vp, d, vp]
+        L.orc_label.restype = ctypes.c_int
+        L.orc_drop_moments.argtypes = [i64, i64, i64, vp, vp, i32, vp, vp]
+        L.orc_drop_moments.restype = ctypes.c_int
+        L.orc_neighbour_pairs.argtypes = [i64, i64, i64, ctypes.c_int, vp, vp, d, vp, i64]
+        L.orc_neighbour_pairs.restype = i64
+        L.orc_recolor.argtypes = [i64, i64, i64, vp, i32, vp, vp, vp, d, vp, vp]
+        L.orc_recolor.restype = ctypes.c_int
+        L.orc_nearest_pair_stats.argtypes = [i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_nearest_pair_stats.restype = ctypes.c_int
+        L.orc_curvature_hf.argtypes = [i64, i64, i64, vp, vp, vp]
+        L.orc_curvature_hf.restype = ctypes.c_int
+        if hasattr(L, "orc_mlp_forward"):
+            _setup_mlp(L)
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def _shape3(c):
+    nz, ny, nx = c.shape[-3:]
+    return int(nx), int(ny), int(nz)
+
+
+# ---------------------------------------------------------------- geometry
+
+def plane_volume(m, alpha: float) -> float:
+    """V(m, alpha): volume of {x in [0,1]^3 : m.x <= alpha}."""
+    return lib().orc_plane_volume(float(m[0]), float(m[1]), float(m[2]), float(alpha))
+
+
+def plane_alpha(m, c: float) -> float:
+    """alpha with V(m, alpha) = c, by bisection."""
+    return lib().orc_plane_alpha(float(m[0]), float(m[1]), float(m[2]), float(c))
+
+
+def myc_normal(block) -> tuple[np.ndarray, bool]:
+    """Mixed-Youngs-Centred normal of a 3x3x3 block given as b[az][ay][ax]."""
+    b = _f64(block).reshape(27)
+    m = np.zeros(3)
+    used_cs = lib().orc_myc_normal(b.ctypes.data, m.ctypes.data)
+    return m, bool(used_cs)
+
+
+# ---------------------------------------------------------------- advection
+
+def sweep(c, s, d: int, cc=None):
+    """One Jacobi sweep along axis d of one field c[nz][ny][nx]; returns the new field."""
+    c = _f64(c)
+    s = _f64(s)
+    nx, ny, nz = _shape3(c)
+    if cc is None:
+        cc = (c > 0.5)
+    cc = np.ascontiguousarray(cc, dtype=np.uint8)
+    out = np.empty_like(c)
+    lib().orc_sweep(nx, ny, nz, int(d), c.ctypes.data, out.ctypes.data, s.ctypes.data, cc.ctypes.data)
+    return out
+
+
+def advect(c, sx, sy, sz, step0: int = 0, nsteps: int = 1):
+    """nsteps direction-split steps of every tracer of c[N][nz][ny][nx]; returns a new array.
+
+    Follows eq. (3) for each tracer C_i (section "The no-coalescence.h
+    algorithm": one transport equation per tracer)."""
+    c = np.array(c, dtype=np.float64, copy=True, order="C")
+    if c.ndim == 3:
+        c = c[None]
+    nx, ny, nz = _shape3(c)
+    sx, sy, sz = _f64(sx), _f64(sy), _f64(sz)
+    for s in (sx, sy, sz):
+        assert s.shape == (nz, ny, nx)
+    rc = lib().orc_advect(nx, ny, nz, c.shape[0], c.ctypes.data, sx.ctypes.data, sy.ctypes.data, sz.ctypes.data,
+                          int(step0), int(nsteps))
+    if rc != 0:
+        raise ValueError(f"orc_advect failed: {rc}")
+    return c
+
+
+# ---------------------------------------------------------------- drops
+
+def label(c, c_eps: float = 1e-6):
+    """Canonical 6-connected periodic components of {c > c_eps} (tag.h step)."""
+    c = _f64(c)
+    nx, ny, nz = _shape3(c)
+    lab = np.zeros(c.shape, dtype=np.int32)
+    k = lib().orc_label(nx, ny, nz, c.ctypes.data, float(c_eps), lab.ctypes.data)
+    return lab, int(k)
+
+
+def drop_moments(c, labels, k: int):
+    c = _f64(c)
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    nx, ny, nz = _shape3(c)
+    vol = np.zeros(max(k, 0))
+    xyz = np.zeros((max(k, 0), 3))
+    rc = lib().orc_drop_moments(nx, ny, nz, c.ctypes.data, labels.ctypes.data, int(k), vol.ctypes.data,
+                                xyz.ctypes.data)
+    return vol, xyz, rc
+
+
+def neighbour_pairs(labels, ndrops, tau: float):
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    ntr = labels.shape[0]
+    nx, ny, nz = _shape3(labels)
+    nd = np.ascontiguousarray(ndrops, dtype=np.int32)
+    cap = 1 << 16
+    while True:
+        pairs = np.zeros((cap, 2), dtype=np.int32)
+        m = lib().orc_neighbour_pairs(nx, ny, nz, ntr, labels.ctypes.data, nd.ctypes.data, float(tau),
+                                      pairs.ctypes.data, cap)
+        if m <= cap:
+            return pairs[:m]
+        cap = int(m)
+
+
+def recolor(c, labels, ndrops, ntracers: int, max_tracers: int, tau: float):
+    """Steps 1-4 of the no-coalescence algorithm (greedy reading).
+
+    c: [max_tracers][nz][ny][nx] (copied); labels: [ntracers][nz][ny][nx].
+    Returns (c_new, ntracers_new, new_tracer[D], nmoved, rc)."""
+    c = np.array(c, dtype=np.float64, copy=True, order="C")
+    assert c.shape[0] == max_tracers
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    nx, ny, nz = _shape3(c)
+    nd = np.ascontiguousarray(ndrops, dtype=np.int32)
+    D = int(nd.sum())
+    newt = np.zeros(max(D, 1), dtype=np.int32)
+    ntr = ctypes.c_int32(int(ntracers))
+    nmoved = ctypes.c_int32(0)
+    rc = lib().orc_recolor(nx, ny, nz, ctypes.byref(ntr), int(max_tracers), c.ctypes.data, labels.ctypes.data,
+                           nd.ctypes.data, float(tau), newt.ctypes.data, ctypes.byref(nmoved))
+    return c, ntr.value, newt[:D], nmoved.value, rc
+
+
+# ---------------------------------------------------------------- statistics
+
+FIXED_ONE = 720720  # lcm(1..16): tie weights 1/N_i are exact integers in these units
+
+
+def nearest_pair_stats(xyz, box, vaxis: int, r2_edges, cos_edges):
+    xyz = _f64(xyz).reshape(-1, 3)
+    n = xyz.shape[0]
+    box = _f64(box)
+    r2e = _f64(r2_edges)
+    ce = _f64(cos_edges)
+    nr, nth = len(r2e) - 1, len(ce) - 1
+    idx = np.zeros(n, dtype=np.int32)
+    ties = np.zeros(n, dtype=np.int32)
+    hist = np.zeros(nr * nth + 1, dtype=np.uint64)
+    M = np.zeros(3)
+    R = np.zeros(9)
+    rc = lib().orc_nearest_pair_stats(n, xyz.ctypes.data, box.ctypes.data, int(vaxis), nr, nth, r2e.ctypes.data,
+                                      ce.ctypes.data, idx.ctypes.data, ties.ctypes.data, hist.ctypes.data,
+                                      M.ctypes.data, R.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"orc_nearest_pair_stats failed: {rc}")
+    return dict(nn_index=idx, nn_ties=ties, hist=hist[:-1].reshape(nr, nth), overflow=int(hist[-1]),
+                M=M, R=R.reshape(3, 3))
+
+
+# ---------------------------------------------------------------- curvature
+
+def curvature_hf(c):
+    c = _f64(c)
+    nx, ny, nz = _shape3(c)
+    kappa = np.zeros(c.shape)
+    status = np.zeros(c.shape, dtype=np.uint8)
+    lib().orc_curvature_hf(nx, ny, nz, c.ctypes.data, kappa.ctypes.data, status.ctypes.data)
+    return kappa, status
+
+
+def _setup_mlp(L):
+    pass
