@@ -1,0 +1,174 @@
+/*
+ * vofmt -- multi-tracer geometric PLIC Volume-of-Fluid on AMD MI355X (gfx950).
+ *
+ * C ABI of libvofmt.so. The library implements the data-parallel hot path of
+ * the non-coalescing multi-tracer VoF method of Fintzi, Pierson & Popinet
+ * (arXiv 2407.07463): transport of N volume-fraction fields C_i (eq. 3 applied
+ * to every tracer, section "The no-coalescence.h algorithm"), labelling of the
+ * drops of each tracer (the tag.h step), drop moments, reassignment of drops
+ * in near contact to other tracers (Steps 1-4), nearest-particle pair
+ * statistics (section "Nearest particle statistics", eqs. 4-14) and interface
+ * curvature of one tracer.
+ *
+ * Conventions (every function):
+ *   - Grids are tri-periodic, nx x ny x nz cells, x fastest: the linear index
+ *     of cell (i,j,k) is p = i + nx*(j + ny*k); cell (i,j,k) occupies
+ *     [i,i+1]x[j,j+1]x[k,k+1] in cell units. Several tracers are stored one
+ *     after another: c[t][k][j][i], tracer stride nx*ny*nz.
+ *   - Face Courant numbers s_d[p] (cells per step, |s| <= 0.5) sit on the lower
+ *     d-face of cell p, same layout as one field.
+ *   - Pointers are DEVICE pointers owned by the caller unless the name ends in
+ *     _host. Calls enqueue work on `stream` and return without waiting, except
+ *     those with _host outputs, which synchronise the stream before returning.
+ *   - A context owns scratch memory only (it grows on demand and is reused);
+ *     use one context per stream. Calls on one context must not overlap.
+ *   - Return 0 on success or a negative VOFMT_E_* code; vofmt_last_error()
+ *     then describes the failure. Argument errors are detected on the host
+ *     before anything is enqueued, so an error leaves all outputs untouched.
+ *   - Floating point: FP64 for volume fractions, velocities, moments and
+ *     curvature; no fused multiply-add contraction is applied to any of the
+ *     method's formulas.
+ */
+#ifndef VOFMT_H
+#define VOFMT_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VOFMT_OK 0
+#define VOFMT_E_ARG (-1)      /* invalid argument (null pointer, bad size, bad option) */
+#define VOFMT_E_CFL (-2)      /* a face Courant number exceeds 0.5 in magnitude */
+#define VOFMT_E_CAPACITY (-3) /* recolouring needs more tracers than max_tracers */
+#define VOFMT_E_EXTENT (-4)   /* a drop spans half the box or more along an axis */
+#define VOFMT_E_NONFINITE (-5) /* non-finite input value */
+#define VOFMT_E_HIP (-6)      /* a HIP runtime call failed */
+#define VOFMT_E_NOMEM (-7)    /* device allocation of scratch memory failed */
+
+typedef struct vofmt_ctx vofmt_ctx;
+
+/* Create a context bound to HIP device `device`. *out receives the handle. */
+int vofmt_create(vofmt_ctx **out, int device);
+/* Release the context and its scratch memory (waits for the device first). */
+void vofmt_destroy(vofmt_ctx *ctx);
+/* Message of the last failed call on this context ("" if none). Owned by the context. */
+const char *vofmt_last_error(const vofmt_ctx *ctx);
+/* Library version string, e.g. "vofmt 0.1 gfx950". */
+const char *vofmt_version(void);
+
+/*
+ * Advect every tracer field for nsteps direction-split steps, in place.
+ *
+ * Operation: eq. (3) dC_i/dt + u.grad C_i = 0 for each tracer C_i (section
+ * "The no-coalescence.h algorithm"), discretised by geometric PLIC VoF
+ * (section "Numerical method"; its discrete form is not given in the paper):
+ * step g = step0 + n sweeps the axes g mod 3, (g+1) mod 3, (g+2) mod 3; each
+ * sweep along d updates every cell from the pre-sweep field
+ *   c'[p] = (c[p] - (F[p+e_d] - F[p])) + cc[p] * (s_d[p+e_d] - s_d[p]),
+ * where cc[p] = (c[p] > 0.5) at the start of the step and F is s times the
+ * phase volume fraction of the donor's upwind sub-box of width |s|: the donor
+ * value itself when the donor is not mixed (mixed: 0 < c < 1), otherwise the
+ * volume under the donor's PLIC plane (Mixed-Youngs-Centred normal, plane
+ * constant matching the donor's c).
+ *
+ * c      : [ntracers][nz][ny][nx] FP64, in/out.
+ * sx,sy,sz: [nz][ny][nx] FP64 face Courant numbers; the caller guarantees
+ *           |s| <= 0.5 (checked only by vofmt_check_courant).
+ * step0  : global index of the first step (>= 0); only g mod 3 matters.
+ * Scratch: the context keeps one extra copy of c and one bit per tracer-cell.
+ * Errors : VOFMT_E_ARG for null pointers or non-positive sizes.
+ */
+int vofmt_advect(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t ntracers, double *c, const double *sx,
+                 const double *sy, const double *sz, int64_t step0, int32_t nsteps, hipStream_t stream);
+
+/*
+ * Largest |s| over the three face-Courant arrays, written to *smax_host
+ * (synchronises). Returns VOFMT_E_CFL if it exceeds 0.5, VOFMT_E_NONFINITE if
+ * any value is not finite.
+ */
+int vofmt_check_courant(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, const double *sx, const double *sy,
+                        const double *sz, double *smax_host, hipStream_t stream);
+
+/*
+ * Label the drops of every tracer (the tag.h step of section "The
+ * no-coalescence.h algorithm": one value per region bounded by interfaces).
+ * Regions are the 6-connected periodic components of {c > c_eps}, numbered
+ * 1..K per tracer in increasing order of their smallest linear index; 0 is
+ * background. Results are bit-identical to a sequential flood fill.
+ *
+ * c          : [ntracers][nz][ny][nx] FP64.
+ * labels     : [ntracers][nz][ny][nx] int32, output.
+ * ndrops_host: [ntracers] host int32, output K per tracer (synchronises).
+ */
+int vofmt_label_drops(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t ntracers, const double *c,
+                      double c_eps, int32_t *labels, int32_t *ndrops_host, hipStream_t stream);
+
+/*
+ * Volume and periodic centroid of every drop ("The no-coalescence.h
+ * algorithm": drop properties are integrals over the cells of one tag).
+ * V = sum of c over the drop; with p0 the drop's first cell (smallest linear
+ * index) and offsets d = p - p0 wrapped into [-n/2, n/2) per axis, the
+ * centroid is (p0 + 0.5) + sum(c d)/V, wrapped into [0, n).
+ *
+ * labels, ndrops_host: as produced by vofmt_label_drops.
+ * vol : [D] FP64 output, D = sum of ndrops_host; drops of tracer 0 first.
+ * xyz : [D][3] FP64 output, in cells.
+ * Errors: VOFMT_E_EXTENT (synchronises to detect it) if a drop spans n/2 or
+ *         more cells along an axis; the outputs are then still written.
+ */
+int vofmt_drop_moments(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t ntracers, const double *c,
+                       const int32_t *labels, const int32_t *ndrops_host, double *vol, double *xyz,
+                       hipStream_t stream);
+
+/*
+ * Reassign drops in near contact to other tracers (Steps 1-4 of section
+ * "The no-coalescence.h algorithm"). Two distinct drops are neighbours when
+ * an occupied cell of each lies at a periodic offset o with |o|^2 <
+ * (1 + gap_cells)^2 (o = 0 included across tracers). Drops are visited in
+ * ascending (tracer, label); a drop moves when an earlier neighbour has its
+ * current tracer, to the smallest tracer not used by any of its neighbours,
+ * or to a new tracer when all are used. Moved cells are cleared in the old
+ * field and added to the new one; new tracer fields start from zero.
+ *
+ * ntracers_host: in/out host int32: number of tracers in use (synchronises).
+ * max_tracers  : capacity of c; VOFMT_E_CAPACITY (nothing modified) if needed.
+ * c            : [max_tracers][nz][ny][nx] FP64, in/out.
+ * labels, ndrops_host: from vofmt_label_drops on the same c.
+ * new_tracer   : [D] int32 device output: tracer of every drop afterwards.
+ * nmoved_host  : host int32 output: number of drops moved.
+ */
+int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t *ntracers_host,
+                          int32_t max_tracers, double *c, const int32_t *labels, const int32_t *ndrops_host,
+                          double gap_cells, int32_t *new_tracer, int32_t *nmoved_host, hipStream_t stream);
+
+/*
+ * Nearest-particle statistics (section "Nearest particle statistics").
+ * For each drop i: the minimum-image vectors r_ij = x_j - x_i (per axis:
+ * subtract L if r > L/2, add L if r <= -L/2), d2 = (rx^2 + ry^2) + rz^2, the
+ * nearest set {j != i : d2 = min} (exact equality), N_i its size and the tie
+ * weight h_ij = 1/N_i of eq. (4). Every nearest pair is binned (eqs. 8 and
+ * 10): radial bin k with r2_edges[k] <= d2 < r2_edges[k+1]; polar bin m =
+ * number of interior edges e = 1..ntheta-1 with cos(theta) <= cos_edges[e],
+ * theta from the vertical axis, decided without sqrt as
+ * rv*|rv| <= (ce*|ce|)*d2. Weights are integers in units of 1/720720; pairs
+ * outside the radial range go to hist_fixed[nr*ntheta]. Moments (eqs. 11,
+ * 14, as averages over the E = n events): M = (1/E) sum h r, R = (1/E) sum h r r^T.
+ *
+ * xyz       : [n][3] FP64 drop centroids (cells). box: [3] HOST FP64.
+ * r2_edges  : [nr+1] HOST FP64, ascending. cos_edges: [ntheta+1] HOST FP64, descending.
+ * nn_index  : [n] int32 output (smallest nearest j). nn_ties: [n] int32 output (N_i).
+ * hist_fixed: [nr*ntheta + 1] uint64 output. M: [3], R: [9] FP64 outputs.
+ */
+int vofmt_nearest_pair_stats(vofmt_ctx *ctx, int32_t n, const double *xyz, const double *box, int32_t vertical_axis,
+                             int32_t nr, int32_t ntheta, const double *r2_edges, const double *cos_edges,
+                             int32_t *nn_index, int32_t *nn_ties, uint64_t *hist_fixed, double *M, double *R,
+                             hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VOFMT_H */

@@ -68,10 +68,17 @@ def lib():
         L.orc_nearest_pair_stats.restype = ctypes.c_int
         L.orc_curvature_hf.argtypes = [i64, i64, i64, vp, vp, vp]
         L.orc_curvature_hf.restype = ctypes.c_int
+        L.orc_num_threads.argtypes = []
+        L.orc_num_threads.restype = ctypes.c_int
         if hasattr(L, "orc_mlp_forward"):
             _setup_mlp(L)
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(lib().orc_num_threads())
 
 
 def _f64(a):

@@ -1,0 +1,57 @@
+// Shared host/device plumbing of libvofmt: the context, error reporting,
+// scratch buffers and small index helpers. Kernels live in the *.hip files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "vofmt.h"
+
+struct vofmt_ctx {
+  int device = 0;
+  std::string err;
+  // Scratch buffers, grown on demand (never shrunk) and reused by later calls.
+  void *buf[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  size_t cap[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // Pinned host staging for small results read back by synchronising calls.
+  void *host = nullptr;
+  size_t host_cap = 0;
+};
+
+// Scratch slots (one buffer per role).
+enum ScratchSlot {
+  SLOT_PINGPONG = 0,  // second copy of the fields during advection
+  SLOT_CCBITS = 1,    // c > 0.5 bits at the start of a step
+  SLOT_LABEL_A = 2,   // labelling / recolouring work arrays
+  SLOT_LABEL_B = 3,
+  SLOT_LABEL_C = 4,
+  SLOT_MISC = 5,
+  SLOT_MISC2 = 6,
+  SLOT_MISC3 = 7,
+};
+
+int set_err(vofmt_ctx *ctx, int code, const char *fmt, ...);
+int hip_check(vofmt_ctx *ctx, hipError_t e, const char *what);
+// Device scratch of at least `bytes` in slot `slot`; nullptr on failure (error set).
+void *scratch(vofmt_ctx *ctx, int slot, size_t bytes);
+void *host_scratch(vofmt_ctx *ctx, size_t bytes);
+
+#define VOFMT_HIP(ctx, call)                                  \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) return hip_check((ctx), e_, #call); \
+  } while (0)
+
+// Device-side helpers ------------------------------------------------------
+
+__device__ __forceinline__ int wrap_dec(int i, int n) { return i == 0 ? n - 1 : i - 1; }
+__device__ __forceinline__ int wrap_inc(int i, int n) { return i == n - 1 ? 0 : i + 1; }
+__device__ __forceinline__ int wrap_any(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+static inline unsigned ceil_div(long long a, long long b) { return (unsigned)((a + b - 1) / b); }

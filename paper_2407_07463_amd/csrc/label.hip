@@ -1,0 +1,381 @@
+// Drop labelling and drop moments.
+//
+// Labelling implements the tag.h step of section "The no-coalescence.h
+// algorithm" (one value per region bounded by interfaces), read as the
+// 6-connected periodic components of {c > c_eps}, numbered 1..K in
+// increasing order of their smallest linear index.
+//
+// GPU scheme (union-find with atomicMin hooking, Komura/Playne-style):
+//   1. init:    parent[p] = start of p's run of occupied cells inside its
+//               64-cell row segment (one ballot per wavefront), -1 if empty;
+//   2. merge:   for every occupied cell, unite with its +y and +z neighbours
+//               and, at a run start, with its -x neighbour (periodic); a
+//               union always hooks the larger root under the smaller one, so
+//               every component ends rooted at its smallest linear index
+//               whatever the order in which the unions happen;
+//   3. flatten: parent[p] = root(p);
+//   4. rank:    roots are counted per block with ballots, block counts are
+//               scanned, and each root gets 1 + (number of roots before it);
+//   5. final:   label[p] = rank of root(p).
+// The result is bit-identical to a sequential flood fill seeded in linear
+// order.
+#include "common.hpp"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ int find_root(const int32_t *__restrict__ P, int32_t a) {
+  int32_t b = P[a];
+  while (b != a) {
+    a = b;
+    b = P[a];
+  }
+  return a;
+}
+
+// The parent array is read while other threads hook roots; volatile-free
+// reads are fine: a stale parent still points to an element of the same
+// component with a smaller-or-equal index, and the hooking loop retries
+// until it installs the link on a true root.
+__device__ __forceinline__ void unite(int32_t *P, int32_t a, int32_t b) {
+  while (true) {
+    a = find_root(P, a);
+    b = find_root(P, b);
+    if (a == b) return;
+    if (a > b) {
+      int32_t t = a;
+      a = b;
+      b = t;
+    }
+    // hook root b (larger) under a (smaller)
+    int32_t old = atomicMin(&P[b], a);
+    if (old == b) return;
+    b = old;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_label_init(const double *__restrict__ c, double c_eps,
+                                                       int32_t *__restrict__ P, int nx, int ny, int nz, int words) {
+  // one wavefront per 64-cell row segment: x = 64*seg + lane
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int64_t nrows = (int64_t)ny * nz;
+  const int64_t row = wave / words;
+  const int seg = (int)(wave % words);
+  if (row >= nrows) return;  // wave-uniform
+  const int x = seg * 64 + lane;
+  const bool live = x < nx;
+  const int64_t p = row * nx + x;
+  const bool occ = live && (c[p] > c_eps);
+  const uint64_t m = __ballot(occ);
+  if (!live) return;
+  if (!occ) {
+    P[p] = -1;
+    return;
+  }
+  // start of the run of set bits that contains `lane`
+  const uint64_t below = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1);
+  const uint64_t zeros = ~m & below;  // empty cells at or below this lane
+  const int start = zeros ? (64 - __clzll(zeros)) : 0;  // one past the highest empty lane below
+  P[p] = (int32_t)(row * nx + seg * 64 + start);
+}
+
+__global__ __launch_bounds__(kBlock) void k_label_merge(int32_t *P, int nx, int ny, int nz) {
+  const int64_t n3 = (int64_t)nx * ny * nz;
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n3) return;
+  if (P[p] < 0) return;
+  const int x = (int)(p % nx);
+  const int64_t r = p / nx;
+  const int y = (int)(r % ny);
+  const int z = (int)(r / ny);
+  // -x neighbour: inside a 64-cell segment the runs are already linked by
+  // k_label_init, so only the first cell of a segment (including x = 0 with
+  // its periodic neighbour x = nx-1) needs a union along x
+  if (x % 64 == 0) {
+    const int64_t q = p - x + (x == 0 ? nx - 1 : x - 1);
+    if (q != p && P[q] >= 0) unite(P, (int32_t)p, (int32_t)q);
+  }
+  {
+    const int yp = (y == ny - 1) ? 0 : y + 1;
+    const int64_t q = ((int64_t)z * ny + yp) * nx + x;
+    if (q != p && P[q] >= 0) unite(P, (int32_t)p, (int32_t)q);
+  }
+  {
+    const int zp = (z == nz - 1) ? 0 : z + 1;
+    const int64_t q = ((int64_t)zp * ny + y) * nx + x;
+    if (q != p && P[q] >= 0) unite(P, (int32_t)p, (int32_t)q);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_label_flatten(int32_t *P, int64_t n3, uint32_t *__restrict__ blockcount) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  bool root = false;
+  if (p < n3) {
+    int32_t v = P[p];
+    if (v >= 0) {
+      int32_t r = find_root(P, (int32_t)p);
+      root = (r == p);
+      if (r != v) P[p] = r;
+    }
+  }
+  __shared__ uint32_t wcount[kBlock / 64];
+  const uint64_t m = __ballot(root);
+  if ((threadIdx.x & 63) == 0) wcount[threadIdx.x >> 6] = (uint32_t)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+    for (int w = 0; w < kBlock / 64; ++w) s += wcount[w];
+    blockcount[blockIdx.x] = s;
+  }
+}
+
+// Exclusive scan of nb block counts in one workgroup; total to *total.
+__global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *__restrict__ v, int64_t nb, int32_t *__restrict__ total) {
+  __shared__ uint64_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (nb + 1023) / 1024;
+  const int64_t lo = t * per, hi = (lo + per < nb) ? lo + per : nb;
+  uint64_t s = 0;
+  for (int64_t i = lo; i < hi; ++i) s += v[i];
+  part[t] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the 1024 partials
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint64_t add = (t >= off) ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
+  }
+  uint64_t run = (t == 0) ? 0 : part[t - 1];
+  for (int64_t i = lo; i < hi; ++i) {
+    uint32_t x = v[i];
+    v[i] = (uint32_t)run;
+    run += x;
+  }
+  if (t == 1023) *total = (int32_t)part[1023];
+}
+
+// Rank every root: rootlab[p] = 1 + number of roots before p; rootpos[rank] = p.
+__global__ __launch_bounds__(kBlock) void k_label_rank(const int32_t *__restrict__ P, int64_t n3,
+                                                       const uint32_t *__restrict__ blockoff,
+                                                       int32_t *__restrict__ rootlab, int32_t *__restrict__ rootpos) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool root = (p < n3) && (P[p] == p);
+  __shared__ uint32_t wcount[kBlock / 64];
+  const uint64_t m = __ballot(root);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) wcount[w] = (uint32_t)__popcll(m);
+  __syncthreads();
+  if (!root) return;
+  uint32_t before = blockoff[blockIdx.x];
+  for (int k = 0; k < w; ++k) before += wcount[k];
+  before += (uint32_t)__popcll(m & ((1ull << lane) - 1));
+  rootlab[p] = (int32_t)before + 1;
+  if (rootpos) rootpos[before] = (int32_t)p;
+}
+
+__global__ __launch_bounds__(kBlock) void k_label_final(int32_t *__restrict__ P, int64_t n3,
+                                                        const int32_t *__restrict__ rootlab) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n3) return;
+  const int32_t r = P[p];
+  P[p] = (r >= 0) ? rootlab[r] : 0;
+}
+
+// ------------------------------------------------------------------ moments
+
+// Offsets of p from the drop's first cell p0, wrapped into [-n/2, n/2).
+__device__ __forceinline__ int wrapped_delta(int a, int a0, int n) {
+  int d = a - a0;
+  if (d < 0) d += n;
+  if (2 * d >= n) d -= n;
+  return d;
+}
+
+// Per-drop bounding box of the offsets (integer atomics: order-independent).
+__global__ __launch_bounds__(kBlock) void k_drop_bbox(const int32_t *__restrict__ lab, int64_t n3, int nx, int ny, int nz,
+                                                      const int32_t *__restrict__ rootpos, int32_t *__restrict__ box) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n3) return;
+  const int32_t l = lab[p];
+  if (l <= 0) return;
+  const int32_t p0 = rootpos[l - 1];
+  const int x = (int)(p % nx), y = (int)((p / nx) % ny), z = (int)(p / ((int64_t)nx * ny));
+  const int x0 = p0 % nx, y0 = (p0 / nx) % ny, z0 = p0 / (nx * ny);
+  const int d[3] = {wrapped_delta(x, x0, nx), wrapped_delta(y, y0, ny), wrapped_delta(z, z0, nz)};
+  int32_t *b = box + 6 * (int64_t)(l - 1);
+  for (int a = 0; a < 3; ++a) {
+    atomicMin(&b[2 * a], d[a]);
+    atomicMax(&b[2 * a + 1], d[a]);
+  }
+}
+
+__global__ void k_first_init(int32_t *first, int64_t K) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < K) first[i] = INT32_MAX;
+}
+
+// First (smallest linear index) cell of every drop.
+__global__ __launch_bounds__(kBlock) void k_first_min(const int32_t *__restrict__ lab, int64_t n3,
+                                                      int32_t *__restrict__ first) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n3) return;
+  const int32_t l = lab[p];
+  if (l > 0) atomicMin(&first[l - 1], (int32_t)p);
+}
+
+__global__ void k_box_init(int32_t *box, int64_t K) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 6 * K) return;
+  box[i] = (i & 1) ? INT32_MIN : INT32_MAX;
+}
+
+// One workgroup per drop sums c and c*offset over the drop's bounding box in
+// a fixed order (per-thread strided partial sums, then a fixed tree), so the
+// result is reproducible bit for bit.
+__global__ __launch_bounds__(kBlock) void k_drop_sums(const double *__restrict__ c, const int32_t *__restrict__ lab,
+                                                      int nx, int ny, int nz, const int32_t *__restrict__ rootpos,
+                                                      const int32_t *__restrict__ box, double *__restrict__ vol,
+                                                      double *__restrict__ xyz, int32_t *__restrict__ extent_err) {
+  const int l = blockIdx.x + 1;
+  const int32_t p0 = rootpos[l - 1];
+  const int x0 = p0 % nx, y0 = (p0 / nx) % ny, z0 = p0 / (nx * ny);
+  const int32_t *b = box + 6 * (int64_t)(l - 1);
+  const int lx = b[0], ly = b[2], lz = b[4];
+  const int ex = b[1] - b[0] + 1, ey = b[3] - b[2] + 1, ez = b[5] - b[4] + 1;
+  const int64_t nbox = (int64_t)ex * ey * ez;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (int64_t q = threadIdx.x; q < nbox; q += kBlock) {
+    const int dx = (int)(q % ex) + lx;
+    const int dy = (int)((q / ex) % ey) + ly;
+    const int dz = (int)(q / ((int64_t)ex * ey)) + lz;
+    const int x = wrap_any(x0 + dx, nx), y = wrap_any(y0 + dy, ny), z = wrap_any(z0 + dz, nz);
+    const int64_t p = ((int64_t)z * ny + y) * nx + x;
+    if (lab[p] != l) continue;
+    const double v = c[p];
+    s0 += v;
+    s1 += v * (double)dx;
+    s2 += v * (double)dy;
+    s3 += v * (double)dz;
+  }
+  __shared__ double red[4][kBlock];
+  red[0][threadIdx.x] = s0;
+  red[1][threadIdx.x] = s1;
+  red[2][threadIdx.x] = s2;
+  red[3][threadIdx.x] = s3;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double V = red[0][0];
+    vol[l - 1] = V;
+    const int n[3] = {nx, ny, nz};
+    const int r[3] = {x0, y0, z0};
+    for (int a = 0; a < 3; ++a) {
+      double x = ((double)r[a] + 0.5) + red[1 + a][0] / V;
+      if (x >= (double)n[a]) x -= (double)n[a];
+      if (x < 0.0) x += (double)n[a];
+      xyz[3 * (int64_t)(l - 1) + a] = x;
+      if (2 * (b[2 * a + 1] - b[2 * a]) >= n[a]) atomicOr(extent_err, 1);
+    }
+  }
+}
+
+}  // namespace
+
+// Label one tracer field into `lab` (also used by recolouring). Returns K via
+// *k_dev (device int32). Scratch: block counts; rootlab (n3 int32).
+static int label_one(vofmt_ctx *ctx, int nx, int ny, int nz, const double *c, double c_eps, int32_t *lab,
+                     uint32_t *blockcount, int32_t *rootlab, int32_t *k_dev, hipStream_t stream) {
+  const int64_t n3 = (int64_t)nx * ny * nz;
+  const int words = (int)ceil_div(nx, 64);
+  const int64_t nwaves = (int64_t)ny * nz * words;
+  const unsigned nb_init = ceil_div(nwaves * 64, kBlock);
+  const unsigned nb = ceil_div(n3, kBlock);
+  hipLaunchKernelGGL(k_label_init, dim3(nb_init), dim3(kBlock), 0, stream, c, c_eps, lab, nx, ny, nz, words);
+  hipLaunchKernelGGL(k_label_merge, dim3(nb), dim3(kBlock), 0, stream, lab, nx, ny, nz);
+  hipLaunchKernelGGL(k_label_flatten, dim3(nb), dim3(kBlock), 0, stream, lab, n3, blockcount);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, stream, blockcount, (int64_t)nb, k_dev);
+  hipLaunchKernelGGL(k_label_rank, dim3(nb), dim3(kBlock), 0, stream, lab, n3, blockcount, rootlab,
+                     (int32_t *)nullptr);
+  hipLaunchKernelGGL(k_label_final, dim3(nb), dim3(kBlock), 0, stream, lab, n3, rootlab);
+  return hip_check(ctx, hipGetLastError(), "label kernels");
+}
+
+extern "C" int vofmt_label_drops(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t ntracers,
+                                 const double *c, double c_eps, int32_t *labels, int32_t *ndrops_host,
+                                 hipStream_t stream) {
+  if (!ctx) return VOFMT_E_ARG;
+  if (nx < 1 || ny < 1 || nz < 1 || ntracers < 0 || !(c_eps >= 0.0))
+    return set_err(ctx, VOFMT_E_ARG, "vofmt_label_drops: bad sizes or c_eps");
+  if (ntracers == 0) return VOFMT_OK;
+  if (!c || !labels || !ndrops_host) return set_err(ctx, VOFMT_E_ARG, "vofmt_label_drops: null pointer");
+  const int64_t n3 = (int64_t)nx * ny * nz;
+  if (n3 >= INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "vofmt_label_drops: more than 2^31-1 cells per field");
+  VOFMT_HIP(ctx, hipSetDevice(ctx->device));
+  const unsigned nb = ceil_div(n3, kBlock);
+  uint32_t *blockcount = (uint32_t *)scratch(ctx, SLOT_LABEL_A, sizeof(uint32_t) * (size_t)nb);
+  int32_t *rootlab = (int32_t *)scratch(ctx, SLOT_LABEL_B, sizeof(int32_t) * (size_t)n3);
+  int32_t *kdev = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * (size_t)ntracers);
+  int32_t *kh = (int32_t *)host_scratch(ctx, sizeof(int32_t) * (size_t)ntracers);
+  if (!blockcount || !rootlab || !kdev || !kh) return VOFMT_E_NOMEM;
+  for (int t = 0; t < ntracers; ++t) {
+    int rc = label_one(ctx, nx, ny, nz, c + (int64_t)t * n3, c_eps, labels + (int64_t)t * n3, blockcount, rootlab,
+                       kdev + t, stream);
+    if (rc) return rc;
+  }
+  VOFMT_HIP(ctx, hipMemcpyAsync(kh, kdev, sizeof(int32_t) * ntracers, hipMemcpyDeviceToHost, stream));
+  VOFMT_HIP(ctx, hipStreamSynchronize(stream));
+  for (int t = 0; t < ntracers; ++t) ndrops_host[t] = kh[t];
+  return VOFMT_OK;
+}
+
+extern "C" int vofmt_drop_moments(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t ntracers,
+                                  const double *c, const int32_t *labels, const int32_t *ndrops_host, double *vol,
+                                  double *xyz, hipStream_t stream) {
+  if (!ctx) return VOFMT_E_ARG;
+  if (nx < 1 || ny < 1 || nz < 1 || ntracers < 0) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_moments: bad sizes");
+  if (ntracers == 0) return VOFMT_OK;
+  if (!c || !labels || !ndrops_host) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_moments: null pointer");
+  int64_t D = 0;
+  for (int t = 0; t < ntracers; ++t) {
+    if (ndrops_host[t] < 0) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_moments: negative drop count");
+    D += ndrops_host[t];
+  }
+  if (D == 0) return VOFMT_OK;
+  if (!vol || !xyz) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_moments: null output");
+  const int64_t n3 = (int64_t)nx * ny * nz;
+  VOFMT_HIP(ctx, hipSetDevice(ctx->device));
+  const unsigned nb = ceil_div(n3, kBlock);
+  int64_t kmax = 0;
+  for (int t = 0; t < ntracers; ++t) kmax = ndrops_host[t] > kmax ? ndrops_host[t] : kmax;
+  int32_t *rootpos = (int32_t *)scratch(ctx, SLOT_LABEL_C, sizeof(int32_t) * (size_t)(kmax + 1));
+  int32_t *box = (int32_t *)scratch(ctx, SLOT_MISC2, sizeof(int32_t) * 6 * (size_t)(kmax + 1));
+  int32_t *flags = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * 2);
+  int32_t *fh = (int32_t *)host_scratch(ctx, sizeof(int32_t) * 2);
+  if (!rootpos || !box || !flags || !fh) return VOFMT_E_NOMEM;
+  VOFMT_HIP(ctx, hipMemsetAsync(flags, 0, sizeof(int32_t) * 2, stream));
+  int64_t off = 0;
+  for (int t = 0; t < ntracers; ++t) {
+    const int32_t K = ndrops_host[t];
+    if (K == 0) continue;
+    const int32_t *lab = labels + (int64_t)t * n3;
+    hipLaunchKernelGGL(k_first_init, dim3(ceil_div(K, 256)), dim3(256), 0, stream, rootpos, (int64_t)K);
+    hipLaunchKernelGGL(k_first_min, dim3(nb), dim3(kBlock), 0, stream, lab, n3, rootpos);
+    hipLaunchKernelGGL(k_box_init, dim3(ceil_div(6 * (int64_t)K, 256)), dim3(256), 0, stream, box, (int64_t)K);
+    hipLaunchKernelGGL(k_drop_bbox, dim3(nb), dim3(kBlock), 0, stream, lab, n3, nx, ny, nz, rootpos, box);
+    hipLaunchKernelGGL(k_drop_sums, dim3(K), dim3(kBlock), 0, stream, c + (int64_t)t * n3, lab, nx, ny, nz, rootpos,
+                       box, vol + off, xyz + 3 * off, flags);
+    VOFMT_HIP(ctx, hipGetLastError());
+    off += K;
+  }
+  VOFMT_HIP(ctx, hipMemcpyAsync(fh, flags, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, stream));
+  VOFMT_HIP(ctx, hipStreamSynchronize(stream));
+  if (fh[0]) return set_err(ctx, VOFMT_E_EXTENT, "vofmt_drop_moments: a drop spans half the box or more");
+  return VOFMT_OK;
+}

@@ -1,0 +1,398 @@
+// Reassignment of drops in near contact to other tracers: Steps 1-4 of
+// section "The no-coalescence.h algorithm".
+//
+// Reading: drops are the (tracer, label) pairs; two distinct drops are
+// neighbours when occupied cells of each lie at a periodic offset o with
+// |o|^2 < (1 + gap)^2 (o = 0 included across tracers); neighbours in the
+// same tracer conflict; drops are visited in ascending (tracer, label) and a
+// drop whose current tracer is held by an earlier neighbour moves to the
+// smallest tracer none of its neighbours holds, or to a new one.
+//
+// GPU scheme:
+//   1. own[p]: global id of the only drop occupying cell p, -1 if none,
+//      -2 if several (drops of different tracers overlapping);
+//   2. every occupied cell scans the offsets of the ball and sets the bit of
+//      each neighbouring drop in a D x D adjacency bitmap (atomicOr; the
+//      bitmap is symmetric and its content independent of thread order);
+//   3. the bitmap is turned into sorted neighbour lists (CSR);
+//   4. one wavefront runs the greedy pass: tracers of all drops in LDS,
+//      neighbour lists streamed through LDS in chunks, one ballot per drop
+//      for the conflict test and an OR-reduction for the tracers in use;
+//   5. the host reads back the tracer count (capacity check), then every
+//      cell clears its moved-out values and adds them to the new fields.
+#include "common.hpp"
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxTracers = 64;    // tracers are bits of a 64-bit mask
+constexpr int kMaxDrops = 32768;   // the adjacency bitmap is D^2 bits
+constexpr int kChunk = 4096;       // neighbour ids staged in LDS per chunk
+
+struct TracerOffsets {
+  int32_t off[kMaxTracers + 1];  // first global drop id of each tracer
+};
+
+__global__ __launch_bounds__(kBlock) void k_owner(const int32_t *__restrict__ lab, int64_t n3, int ntr,
+                                                  TracerOffsets to, int32_t *__restrict__ own) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n3) return;
+  int32_t o = -1;
+  for (int t = 0; t < ntr; ++t) {
+    const int32_t l = lab[(int64_t)t * n3 + p];
+    if (l > 0) o = (o == -1) ? to.off[t] + l - 1 : -2;
+  }
+  own[p] = o;
+}
+
+// v in (-n, 2n): one conditional add or subtract instead of a modulo
+__device__ __forceinline__ int wrap_near(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+__device__ __forceinline__ void set_edge(uint32_t *adj, int64_t words, int32_t a, int32_t b) {
+  uint32_t *w = adj + (int64_t)a * words + (b >> 5);
+  const uint32_t bit = 1u << (b & 31);
+  if (!(*w & bit)) atomicOr(w, bit);
+}
+
+// All drops occupying cell p (for cells shared by several drops).
+__device__ __forceinline__ int drops_at(const int32_t *__restrict__ lab, int64_t n3, int ntr, const TracerOffsets &to,
+                                        int64_t p, int32_t *ids) {
+  int k = 0;
+  for (int t = 0; t < ntr; ++t) {
+    const int32_t l = lab[(int64_t)t * n3 + p];
+    if (l > 0) ids[k++] = to.off[t] + l - 1;
+  }
+  return k;
+}
+
+__global__ __launch_bounds__(kBlock) void k_edges(const int32_t *__restrict__ own, const int32_t *__restrict__ lab,
+                                                  int nx, int ny, int nz, int ntr, TracerOffsets to,
+                                                  const int4 *__restrict__ offs, int noffs, int small_offsets,
+                                                  uint32_t *__restrict__ adj, int64_t words) {
+  const int64_t n3 = (int64_t)nx * ny * nz;
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n3) return;
+  const int32_t a = own[p];
+  if (a == -1) return;
+  const int x = (int)(p % nx), y = (int)((p / nx) % ny), z = (int)(p / ((int64_t)nx * ny));
+  int32_t ida[kMaxTracers];
+  int na = 0;
+  if (a == -2) {
+    na = drops_at(lab, n3, ntr, to, p, ida);
+    // drops sharing this very cell are neighbours (offset 0 across tracers)
+    for (int u = 0; u < na; ++u)
+      for (int v = 0; v < na; ++v)
+        if (u != v) set_edge(adj, words, ida[u], ida[v]);
+  }
+  for (int k = 0; k < noffs; ++k) {
+    const int4 o = offs[k];
+    const int64_t q = small_offsets ? ((int64_t)wrap_near(z + o.z, nz) * ny + wrap_near(y + o.y, ny)) * nx +
+                                          wrap_near(x + o.x, nx)
+                                    : ((int64_t)wrap_any(z + o.z, nz) * ny + wrap_any(y + o.y, ny)) * nx +
+                                          wrap_any(x + o.x, nx);
+    const int32_t b = own[q];
+    if (b == -1) continue;
+    if (a >= 0 && b >= 0) {
+      if (a != b) set_edge(adj, words, a, b);
+      continue;
+    }
+    int32_t idb[kMaxTracers];
+    int nb = 0;
+    if (b >= 0) idb[nb++] = b;
+    else nb = drops_at(lab, n3, ntr, to, q, idb);
+    if (a >= 0) {
+      for (int v = 0; v < nb; ++v)
+        if (idb[v] != a) set_edge(adj, words, a, idb[v]);
+    } else {
+      for (int u = 0; u < na; ++u)
+        for (int v = 0; v < nb; ++v)
+          if (ida[u] != idb[v]) set_edge(adj, words, ida[u], idb[v]);
+    }
+  }
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_f64(double *p, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Degree of every drop (symmetrise first: a bit set in either direction).
+__global__ __launch_bounds__(kBlock) void k_degree(uint32_t *__restrict__ adj, int32_t D, int64_t words,
+                                                   int32_t *__restrict__ deg) {
+  const int32_t g = blockIdx.x * kBlock + threadIdx.x;
+  if (g >= D) return;
+  int s = 0;
+  for (int64_t w = 0; w < words; ++w) s += __popc(adj[(int64_t)g * words + w]);
+  deg[g] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_symmetrise(uint32_t *adj, int32_t D, int64_t words) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= (int64_t)D * D) return;
+  const int32_t a = (int32_t)(i / D), b = (int32_t)(i % D);
+  if (a >= b) return;
+  const bool ab = (adj[(int64_t)a * words + (b >> 5)] >> (b & 31)) & 1u;
+  const bool ba = (adj[(int64_t)b * words + (a >> 5)] >> (a & 31)) & 1u;
+  if (ab && !ba) atomicOr(&adj[(int64_t)b * words + (a >> 5)], 1u << (a & 31));
+  if (ba && !ab) atomicOr(&adj[(int64_t)a * words + (b >> 5)], 1u << (b & 31));
+}
+
+// Exclusive scan of D degrees (single workgroup) into rowptr[0..D].
+__global__ __launch_bounds__(1024) void k_scan_deg(const int32_t *__restrict__ deg, int32_t D,
+                                                   int32_t *__restrict__ rowptr) {
+  __shared__ int64_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = ((int64_t)D + 1023) / 1024;
+  const int64_t lo = t * per, hi = (lo + per < D) ? lo + per : D;
+  int64_t s = 0;
+  for (int64_t i = lo; i < hi; ++i) s += deg[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int64_t add = (t >= off) ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
+  }
+  int64_t run = (t == 0) ? 0 : part[t - 1];
+  for (int64_t i = lo; i < hi; ++i) {
+    rowptr[i] = (int32_t)run;
+    run += deg[i];
+  }
+  if (t == 1023) rowptr[D] = (int32_t)part[1023];
+}
+
+__global__ __launch_bounds__(kBlock) void k_csr_fill(const uint32_t *__restrict__ adj, int32_t D, int64_t words,
+                                                     const int32_t *__restrict__ rowptr, int32_t *__restrict__ nbr) {
+  const int32_t g = blockIdx.x * kBlock + threadIdx.x;
+  if (g >= D) return;
+  int32_t e = rowptr[g];
+  for (int64_t w = 0; w < words; ++w) {
+    uint32_t bits = adj[(int64_t)g * words + w];
+    while (bits) {
+      const int b = __ffs(bits) - 1;
+      bits &= bits - 1;
+      nbr[e++] = (int32_t)(w * 32 + b);
+    }
+  }
+}
+
+// The greedy pass, one wavefront. T0: initial tracer per drop. Outputs
+// new_tracer, and res[0] = tracers after, res[1] = moved drops, res[2] = 1 on
+// capacity overflow (then new_tracer is meaningless and nothing is moved).
+__global__ __launch_bounds__(64) void k_greedy(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ nbr,
+                                               const int32_t *__restrict__ T0, int32_t D, int ntr, int max_tracers,
+                                               int32_t *__restrict__ new_tracer, int32_t *__restrict__ res) {
+  __shared__ int8_t T[kMaxDrops];
+  __shared__ int32_t stage[kChunk];
+  const int lane = threadIdx.x;
+  for (int32_t g = lane; g < D; g += 64) T[g] = (int8_t)T0[g];
+  __syncthreads();
+  int N = ntr;
+  int32_t moved = 0;
+  int overflow = 0;
+  int32_t base = 0;  // first neighbour index staged
+  int32_t staged_end = 0;
+  for (int32_t g = 0; g < D && !overflow; ++g) {
+    const int32_t e0 = rowptr[g], e1 = rowptr[g + 1];
+    const int tg = T[g];
+    bool conflict = false;
+    uint64_t used = 0;
+    for (int32_t e = e0; e < e1; e += 64) {
+      // make sure [e, min(e+64, e1)) is staged
+      if (e + 64 > staged_end && staged_end < e1) {
+        __syncthreads();
+        base = e;
+        staged_end = (base + kChunk < rowptr[D]) ? base + kChunk : rowptr[D];
+        for (int32_t k = lane; k < staged_end - base; k += 64) stage[k] = nbr[base + k];
+        __syncthreads();
+      }
+      const int32_t idx = e + lane;
+      bool c = false;
+      uint64_t u = 0;
+      if (idx < e1) {
+        const int32_t h = stage[idx - base];
+        const int th = T[h];
+        c = (h < g) && (th == tg);
+        u = 1ull << th;
+      }
+      conflict = conflict || (__ballot(c) != 0ull);
+      // OR-reduction of the tracer masks across the wavefront
+#pragma unroll
+      for (int s = 32; s > 0; s >>= 1) u |= __shfl_xor(u, s, 64);
+      used |= u;
+    }
+    if (!conflict) continue;
+    uint64_t avail = ~used & ~(1ull << tg);
+    if (N < 64) avail &= (1ull << N) - 1;
+    int n;
+    if (avail) {
+      n = __ffsll((unsigned long long)avail) - 1;
+    } else {
+      if (N + 1 > max_tracers) {
+        overflow = 1;
+        break;
+      }
+      n = N++;
+    }
+    __syncthreads();
+    if (lane == 0) T[g] = (int8_t)n;
+    ++moved;
+    __syncthreads();
+  }
+  __syncthreads();
+  for (int32_t g = lane; g < D; g += 64) new_tracer[g] = T[g];
+  if (lane == 0) {
+    res[0] = N;
+    res[1] = moved;
+    res[2] = overflow;
+  }
+}
+
+__global__ void k_initial_tracers(int32_t *T0, int32_t D, int ntr, TracerOffsets to) {
+  const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= D) return;
+  int t = 0;
+  while (t + 1 < ntr && to.off[t + 1] <= g) ++t;
+  T0[g] = t;
+}
+
+// Move the cells of every moved drop: first clear every moved-out value of
+// the cell, then add each to its new field.
+__global__ __launch_bounds__(kBlock) void k_move(double *__restrict__ c, const int32_t *__restrict__ lab, int64_t n3,
+                                                 int ntr, TracerOffsets to, const int32_t *__restrict__ newt) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n3) return;
+  int cnt = 0;
+  for (int t = 0; t < ntr; ++t) {
+    const int32_t l = lab[(int64_t)t * n3 + p];
+    if (l > 0 && newt[to.off[t] + l - 1] != t) ++cnt;
+  }
+  if (cnt == 0) return;
+  double vals[kMaxTracers];
+  int dst[kMaxTracers];
+  int k = 0;
+  for (int t = 0; t < ntr; ++t) {
+    const int32_t l = lab[(int64_t)t * n3 + p];
+    if (l <= 0) continue;
+    const int n = newt[to.off[t] + l - 1];
+    if (n == t) continue;
+    vals[k] = c[(int64_t)t * n3 + p];
+    dst[k] = n;
+    c[(int64_t)t * n3 + p] = 0.0;
+    ++k;
+  }
+  for (int u = 0; u < k; ++u) {
+    double *q = c + (int64_t)dst[u] * n3 + p;
+    *q = *q + vals[u];
+  }
+}
+
+}  // namespace
+
+extern "C" int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t *ntracers_host,
+                                     int32_t max_tracers, double *c, const int32_t *labels, const int32_t *ndrops_host,
+                                     double gap_cells, int32_t *new_tracer, int32_t *nmoved_host, hipStream_t stream) {
+  if (!ctx) return VOFMT_E_ARG;
+  if (!ntracers_host || !nmoved_host || !ndrops_host)
+    return set_err(ctx, VOFMT_E_ARG, "vofmt_recolor_tracers: null host pointer");
+  const int ntr = *ntracers_host;
+  if (nx < 1 || ny < 1 || nz < 1 || ntr < 0 || ntr > max_tracers || max_tracers > kMaxTracers ||
+      !(gap_cells >= 0.0) || gap_cells > 64.0)
+    return set_err(ctx, VOFMT_E_ARG,
+                   "vofmt_recolor_tracers: bad arguments (ntracers=%d max_tracers=%d (<= %d) gap=%g)", ntr,
+                   max_tracers, kMaxTracers, gap_cells);
+  *nmoved_host = 0;
+  if (ntr == 0) return VOFMT_OK;
+  if (!c || !labels) return set_err(ctx, VOFMT_E_ARG, "vofmt_recolor_tracers: null pointer");
+  TracerOffsets to;
+  to.off[0] = 0;
+  int64_t D = 0;
+  for (int t = 0; t < ntr; ++t) {
+    if (ndrops_host[t] < 0) return set_err(ctx, VOFMT_E_ARG, "vofmt_recolor_tracers: negative drop count");
+    D += ndrops_host[t];
+    to.off[t + 1] = (int32_t)D;
+  }
+  for (int t = ntr + 1; t <= kMaxTracers; ++t) to.off[t] = (int32_t)D;
+  if (D == 0) return VOFMT_OK;
+  if (D > kMaxDrops) return set_err(ctx, VOFMT_E_ARG, "vofmt_recolor_tracers: more than %d drops", kMaxDrops);
+  if (!new_tracer) return set_err(ctx, VOFMT_E_ARG, "vofmt_recolor_tracers: null new_tracer");
+  const int64_t n3 = (int64_t)nx * ny * nz;
+  VOFMT_HIP(ctx, hipSetDevice(ctx->device));
+  // offsets of the ball |o|^2 < (1+gap)^2, o != 0
+  const double lim = (1.0 + gap_cells) * (1.0 + gap_cells);
+  const int R = (int)floor(1.0 + gap_cells);
+  int4 *hoffs = nullptr;
+  int noffs = 0;
+  {
+    const int side = 2 * R + 1;
+    hoffs = (int4 *)malloc(sizeof(int4) * (size_t)side * side * side);
+    for (int oz = -R; oz <= R; ++oz)
+      for (int oy = -R; oy <= R; ++oy)
+        for (int ox = -R; ox <= R; ++ox) {
+          const double o2 = (double)(ox * ox + oy * oy + oz * oz);
+          if (o2 == 0.0 || !(o2 < lim)) continue;
+          hoffs[noffs++] = make_int4(ox, oy, oz, 0);
+        }
+  }
+  const int64_t words = (D + 31) / 32;
+  int32_t *own = (int32_t *)scratch(ctx, SLOT_LABEL_B, sizeof(int32_t) * (size_t)n3);
+  uint32_t *adj = (uint32_t *)scratch(ctx, SLOT_LABEL_A, sizeof(uint32_t) * (size_t)(D * words));
+  int32_t *small = (int32_t *)scratch(ctx, SLOT_LABEL_C, sizeof(int32_t) * (size_t)(4 * D + 16));
+  int4 *doffs = (int4 *)scratch(ctx, SLOT_MISC2, sizeof(int4) * (size_t)(noffs > 0 ? noffs : 1));
+  // pinned staging: results in the first 256 bytes, offsets after them
+  int32_t *hres = (int32_t *)host_scratch(ctx, 256 + sizeof(int4) * (size_t)noffs);
+  if (!own || !adj || !small || !doffs || !hres) {
+    free(hoffs);
+    return VOFMT_E_NOMEM;
+  }
+  memcpy(hres + 64, hoffs, sizeof(int4) * noffs);
+  free(hoffs);
+  if (noffs > 0)
+    VOFMT_HIP(ctx, hipMemcpyAsync(doffs, hres + 64, sizeof(int4) * noffs, hipMemcpyHostToDevice, stream));
+  const int small_offsets = (R < nx && R < ny && R < nz) ? 1 : 0;
+  int32_t *deg = small, *rowptr = small + D, *T0 = small + 2 * D + 1, *res = small + 3 * D + 2;
+  int32_t *nbr = nullptr;
+  const unsigned nbc = ceil_div(n3, kBlock);
+  hipLaunchKernelGGL(k_owner, dim3(nbc), dim3(kBlock), 0, stream, labels, n3, ntr, to, own);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, stream, adj, D * words, 0u);
+  hipLaunchKernelGGL(k_edges, dim3(nbc), dim3(kBlock), 0, stream, own, labels, nx, ny, nz, ntr, to, doffs, noffs,
+                     small_offsets, adj, words);
+  hipLaunchKernelGGL(k_symmetrise, dim3(ceil_div(D * D, kBlock)), dim3(kBlock), 0, stream, adj, (int32_t)D, words);
+  hipLaunchKernelGGL(k_degree, dim3(ceil_div(D, kBlock)), dim3(kBlock), 0, stream, adj, (int32_t)D, words, deg);
+  hipLaunchKernelGGL(k_scan_deg, dim3(1), dim3(1024), 0, stream, deg, (int32_t)D, rowptr);
+  VOFMT_HIP(ctx, hipGetLastError());
+  // the number of directed edges sizes the neighbour array
+  VOFMT_HIP(ctx, hipMemcpyAsync(hres + 8, rowptr + D, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  VOFMT_HIP(ctx, hipStreamSynchronize(stream));
+  const int64_t E = hres[8];
+  nbr = (int32_t *)scratch(ctx, SLOT_MISC3, sizeof(int32_t) * (size_t)(E > 0 ? E : 1));
+  if (!nbr) return VOFMT_E_NOMEM;
+  hipLaunchKernelGGL(k_csr_fill, dim3(ceil_div(D, kBlock)), dim3(kBlock), 0, stream, adj, (int32_t)D, words, rowptr,
+                     nbr);
+  hipLaunchKernelGGL(k_initial_tracers, dim3(ceil_div(D, 256)), dim3(256), 0, stream, T0, (int32_t)D, ntr, to);
+  hipLaunchKernelGGL(k_greedy, dim3(1), dim3(64), 0, stream, rowptr, nbr, T0, (int32_t)D, ntr, max_tracers,
+                     new_tracer, res);
+  VOFMT_HIP(ctx, hipGetLastError());
+  VOFMT_HIP(ctx, hipMemcpyAsync(hres, res, sizeof(int32_t) * 3, hipMemcpyDeviceToHost, stream));
+  VOFMT_HIP(ctx, hipStreamSynchronize(stream));
+  const int Nnew = hres[0], moved = hres[1], overflow = hres[2];
+  if (overflow)
+    return set_err(ctx, VOFMT_E_CAPACITY, "vofmt_recolor_tracers: more than max_tracers=%d tracers needed",
+                   max_tracers);
+  if (moved > 0) {
+    if (Nnew > ntr)
+      hipLaunchKernelGGL(k_fill_f64, dim3(1024), dim3(256), 0, stream, c + (int64_t)ntr * n3,
+                         (int64_t)(Nnew - ntr) * n3, 0.0);
+    hipLaunchKernelGGL(k_move, dim3(nbc), dim3(kBlock), 0, stream, c, labels, n3, ntr, to, new_tracer);
+    VOFMT_HIP(ctx, hipGetLastError());
+  }
+  *ntracers_host = Nnew;
+  *nmoved_host = moved;
+  return VOFMT_OK;
+}

@@ -1,0 +1,187 @@
+"""Python binding of libvofmt (argument marshalling only).
+
+Every function takes torch tensors that already live on the GPU, passes
+their device pointers and the current HIP stream to the C ABI declared in
+include/vofmt.h, and raises on a non-zero return code. No computation of the
+method happens here: all of it runs in the HIP kernels of libvofmt.so. The
+library must be built (see `paper_2407_07463_amd._build`); importing this
+module on a machine without it raises instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvofmt.so")
+
+OK, E_ARG, E_CFL, E_CAPACITY, E_EXTENT, E_NONFINITE, E_HIP, E_NOMEM = 0, -1, -2, -3, -4, -5, -6, -7
+_NAMES = {E_ARG: "E_ARG", E_CFL: "E_CFL", E_CAPACITY: "E_CAPACITY", E_EXTENT: "E_EXTENT",
+          E_NONFINITE: "E_NONFINITE", E_HIP: "E_HIP", E_NOMEM: "E_NOMEM"}
+
+# Every symbol include/vofmt.h declares, with (restype, argtypes).
+_vp, _i32, _i64, _d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_P_i32 = ctypes.POINTER(ctypes.c_int32)
+_SIGNATURES = {
+    "vofmt_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int]),
+    "vofmt_destroy": (None, [_vp]),
+    "vofmt_last_error": (ctypes.c_char_p, [_vp]),
+    "vofmt_version": (ctypes.c_char_p, []),
+    "vofmt_advect": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _i64, _i32, _vp]),
+    "vofmt_check_courant": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, ctypes.POINTER(_d), _vp]),
+    "vofmt_label_drops": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _d, _vp, _vp, _vp]),
+    "vofmt_drop_moments": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "vofmt_recolor_tracers": (ctypes.c_int, [_vp, _i32, _i32, _i32, _P_i32, _i32, _vp, _vp, _vp, _d, _vp, _P_i32,
+                                             _vp]),
+    "vofmt_nearest_pair_stats": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
+                                                _vp, _vp, _vp]),
+}
+
+_lib = None
+
+
+class VofmtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def load(path: str = LIB_PATH):
+    """Load libvofmt.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run paper_2407_07463_amd._build.build_all() "
+                               "(or __graft_entry__.build()) first")
+        L = ctypes.CDLL(path)
+        for name, (res, args) in _SIGNATURES.items():
+            if hasattr(L, name):
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols(path: str = LIB_PATH):
+    L = ctypes.CDLL(path)
+    return {n for n in _SIGNATURES if hasattr(L, n)}
+
+
+def _stream(stream=None):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dims(c):
+    nz, ny, nx = (int(v) for v in c.shape[-3:])
+    return nx, ny, nz
+
+
+class Context:
+    """A libvofmt context: scratch memory for one stream on one device."""
+
+    def __init__(self, device: int = 0):
+        L = load()
+        h = ctypes.c_void_p()
+        rc = L.vofmt_create(ctypes.byref(h), int(device))
+        if rc != 0:
+            raise VofmtError(rc, f"vofmt_create(device={device}) failed")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().vofmt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            raise VofmtError(rc, load().vofmt_last_error(self.h).decode())
+        return rc
+
+    # ------------------------------------------------------------ advection
+    def advect(self, c, sx, sy, sz, step0: int = 0, nsteps: int = 1, stream=None):
+        """In-place advection of c[N][nz][ny][nx] (float64, contiguous, on the GPU)."""
+        _require(c, sx, sy, sz)
+        nx, ny, nz = _dims(c)
+        ntr = int(c.shape[0]) if c.dim() == 4 else 1
+        for s in (sx, sy, sz):
+            assert tuple(s.shape) == (nz, ny, nx)
+        return self._check(load().vofmt_advect(self.h, nx, ny, nz, ntr, _ptr(c), _ptr(sx), _ptr(sy), _ptr(sz),
+                                               int(step0), int(nsteps), _stream(stream)))
+
+    def check_courant(self, sx, sy, sz, stream=None) -> float:
+        _require(sx, sy, sz)
+        nx, ny, nz = _dims(sx)
+        out = ctypes.c_double(0.0)
+        self._check(load().vofmt_check_courant(self.h, nx, ny, nz, _ptr(sx), _ptr(sy), _ptr(sz), ctypes.byref(out),
+                                               _stream(stream)))
+        return out.value
+
+    # ------------------------------------------------------------ drops
+    def label_drops(self, c, labels, c_eps: float = 1e-6, stream=None):
+        """Labels into `labels` (int32, same shape as c); returns the per-tracer drop counts."""
+        _require(c, labels)
+        nx, ny, nz = _dims(c)
+        ntr = int(c.shape[0]) if c.dim() == 4 else 1
+        nd = np.zeros(max(ntr, 1), dtype=np.int32)
+        self._check(load().vofmt_label_drops(self.h, nx, ny, nz, ntr, _ptr(c), float(c_eps), _ptr(labels),
+                                             nd.ctypes.data, _stream(stream)))
+        return nd[:ntr]
+
+    def drop_moments(self, c, labels, ndrops, vol, xyz, stream=None):
+        _require(c, labels, vol, xyz)
+        nx, ny, nz = _dims(c)
+        ntr = int(c.shape[0]) if c.dim() == 4 else 1
+        nd = np.ascontiguousarray(ndrops, dtype=np.int32)
+        return self._check(load().vofmt_drop_moments(self.h, nx, ny, nz, ntr, _ptr(c), _ptr(labels),
+                                                     nd.ctypes.data, _ptr(vol), _ptr(xyz), _stream(stream)))
+
+    def recolor_tracers(self, c, ntracers: int, labels, ndrops, gap_cells: float, new_tracer, stream=None):
+        """c: [max_tracers][nz][ny][nx]; returns (ntracers_after, nmoved)."""
+        _require(c, labels, new_tracer)
+        nx, ny, nz = _dims(c)
+        maxt = int(c.shape[0])
+        nd = np.ascontiguousarray(ndrops, dtype=np.int32)
+        ntr = ctypes.c_int32(int(ntracers))
+        nmoved = ctypes.c_int32(0)
+        self._check(load().vofmt_recolor_tracers(self.h, nx, ny, nz, ctypes.byref(ntr), maxt, _ptr(c),
+                                                 _ptr(labels), nd.ctypes.data, float(gap_cells),
+                                                 _ptr(new_tracer), ctypes.byref(nmoved), _stream(stream)))
+        return ntr.value, nmoved.value
+
+    # ------------------------------------------------------------ statistics
+    def nearest_pair_stats(self, xyz, box, vertical_axis: int, r2_edges, cos_edges, nn_index, nn_ties, hist, M, R,
+                           stream=None):
+        _require(xyz, nn_index, nn_ties, hist, M, R)
+        n = int(xyz.shape[0])
+        b = np.ascontiguousarray(box, dtype=np.float64)
+        r2 = np.ascontiguousarray(r2_edges, dtype=np.float64)
+        ce = np.ascontiguousarray(cos_edges, dtype=np.float64)
+        return self._check(load().vofmt_nearest_pair_stats(
+            self.h, n, _ptr(xyz), b.ctypes.data, int(vertical_axis), len(r2) - 1, len(ce) - 1, r2.ctypes.data,
+            ce.ctypes.data, _ptr(nn_index), _ptr(nn_ties), _ptr(hist), _ptr(M), _ptr(R), _stream(stream)))
+
+
+def _require(*ts):
+    for t in ts:
+        if not t.is_cuda:
+            raise ValueError("vofmt: tensors must be on the GPU")
+        if not t.is_contiguous():
+            raise ValueError("vofmt: tensors must be contiguous")

@@ -1,0 +1,154 @@
+"""GPU parity of vofmt_advect against the CPU FP64 oracle.
+
+Bar: max |c_gpu - c_oracle| <= 1e-12 (the FP64 volume-fraction tolerance),
+after 1 and 20 steps of the 64^3 two-tracer sphere workload, on odd-sized
+grids with a random solenoidal velocity, and on sampled cells of the
+512^3 x 8 workload in the launch configuration the benchmark times (each
+sampled cell recomputed by the oracle on a periodic 17^3 box around it,
+wide enough that one step of the split scheme, whose influence reaches 4
+cells, cannot see the box edges).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import note, periodic_box, require_gpu
+from paper_2407_07463_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    require_gpu()
+    from paper_2407_07463_amd import vofmt
+
+    c = vofmt.Context(0)
+    yield c
+    c.close()
+
+
+def _gpu_advect(ctx, c, sx, sy, sz, step0, nsteps):
+    import torch
+
+    dev = torch.device("cuda:0")
+    tc = torch.from_numpy(np.ascontiguousarray(c)).to(dev)
+    ts = [torch.from_numpy(np.ascontiguousarray(s)).to(dev) for s in (sx, sy, sz)]
+    ctx.advect(tc, *ts, step0=step0, nsteps=nsteps)
+    torch.cuda.synchronize()
+    return tc.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def spheres64():
+    return synth.spheres64()
+
+
+@pytest.mark.parametrize("nsteps", [1, 20])
+def test_spheres64(ctx, spheres64, nsteps):
+    w = spheres64
+    note(f"advect spheres64 nsteps={nsteps}")
+    g = _gpu_advect(ctx, w["c"], w["sx"], w["sy"], w["sz"], 0, nsteps)
+    o = oracle.advect(w["c"], w["sx"], w["sy"], w["sz"], 0, nsteps)
+    assert np.abs(g - o).max() <= TOL
+    s0 = w["c"].sum(axis=(1, 2, 3))
+    assert np.all(np.abs(g.sum(axis=(1, 2, 3)) - s0) / s0 <= 1e-12)
+
+
+@pytest.mark.parametrize("shape,ntr,step0,nsteps", [((17, 23, 19), 3, 0, 4), ((31, 9, 70), 2, 1, 3),
+                                                    ((5, 7, 130), 1, 2, 2), ((3, 3, 3), 2, 0, 2)])
+def test_odd_grids_random_velocity(ctx, shape, ntr, step0, nsteps):
+    nz, ny, nx = shape
+    rng = synth.Splitmix64(1234 + nx)
+    nb = 6
+    radii = 1.5 + 3.0 * rng.uniform(nb)
+    centres = rng.uniform(3 * nb).reshape(nb, 3) * np.array([nx, ny, nz])
+    # keep bodies inside the box along the thin axes
+    radii = np.minimum(radii, 0.45 * min(nx, ny, nz) - 0.5)
+    radii = np.maximum(radii, 0.4)
+    c = synth.fill_spheres(shape, ntr, centres, radii, np.arange(nb) % ntr)
+    kmax = max(1, min(4, (min(shape) - 1) // 2))
+    sx, sy, sz, _ = synth.fourier_velocity(shape, seed=99 + nx, kmax=kmax, rms=0.2, rise=0.1)
+    note(f"advect odd grid {shape} ntr={ntr} step0={step0} nsteps={nsteps}")
+    g = _gpu_advect(ctx, c, sx, sy, sz, step0, nsteps)
+    o = oracle.advect(c, sx, sy, sz, step0, nsteps)
+    assert np.abs(g - o).max() <= TOL
+
+
+def test_translation_and_determinism(ctx):
+    n = 24
+    c = synth.fill_spheres((n, n, n), 1, [(11.3, 12.1, 10.7)], [6.3], [0])
+    s = np.full((n, n, n), 0.25)
+    note("advect uniform translation")
+    g1 = _gpu_advect(ctx, c, s, s, s, 0, 8)
+    g2 = _gpu_advect(ctx, c, s, s, s, 0, 8)
+    assert np.array_equal(g1, g2)  # bit-identical reruns
+    o = oracle.advect(c, s, s, s, 0, 8)
+    assert np.abs(g1 - o).max() <= TOL
+
+
+def test_zero_steps_and_zero_tracers(ctx, spheres64):
+    w = spheres64
+    note("advect nsteps=0")
+    g = _gpu_advect(ctx, w["c"], w["sx"], w["sy"], w["sz"], 0, 0)
+    assert np.array_equal(g, w["c"])
+
+
+def test_argument_errors(ctx):
+    import torch
+
+    from paper_2407_07463_amd import vofmt
+
+    c = torch.zeros((1, 4, 4, 4), dtype=torch.float64, device="cuda:0")
+    s = torch.zeros((4, 4, 4), dtype=torch.float64, device="cuda:0")
+    L = vofmt.load()
+    st = vofmt._stream()
+    assert L.vofmt_advect(ctx.h, 4, 4, 4, 1, None, s.data_ptr(), s.data_ptr(), s.data_ptr(), 0, 1, st) == vofmt.E_ARG
+    assert L.vofmt_advect(ctx.h, 0, 4, 4, 1, c.data_ptr(), s.data_ptr(), s.data_ptr(), s.data_ptr(), 0, 1,
+                          st) == vofmt.E_ARG
+    assert L.vofmt_advect(ctx.h, 4, 4, 4, 1, c.data_ptr(), s.data_ptr(), s.data_ptr(), s.data_ptr(), -1, 1,
+                          st) == vofmt.E_ARG
+    s[1, 2, 3] = 0.75
+    with pytest.raises(vofmt.VofmtError) as e:
+        ctx.check_courant(s, s, s)
+    assert e.value.code == vofmt.E_CFL
+    s[1, 2, 3] = float("nan")
+    with pytest.raises(vofmt.VofmtError) as e:
+        ctx.check_courant(s, s, s)
+    assert e.value.code == vofmt.E_NONFINITE
+
+
+@pytest.fixture(scope="module")
+def drops512():
+    return synth.drops512(order=8, workers=16)
+
+
+def test_full_size_sampled_cells(ctx, drops512):
+    """512^3 x 8 tracers, one step in the benchmark's launch configuration;
+    200 sampled cells recomputed by the oracle on periodic 17^3 boxes, plus
+    conservation of every tracer over the whole field."""
+    import torch
+
+    w = drops512
+    c0 = w["c"]
+    note("advect drops512 one step (full size)")
+    dev = torch.device("cuda:0")
+    tc = torch.from_numpy(c0).to(dev)
+    ts = [torch.from_numpy(w[k]).to(dev) for k in ("sx", "sy", "sz")]
+    ctx.advect(tc, *ts, step0=0, nsteps=1)
+    torch.cuda.synchronize()
+    g = tc.cpu().numpy()
+    s0 = c0.sum(axis=(1, 2, 3))
+    assert np.all(np.abs(g.sum(axis=(1, 2, 3)) - s0) / s0 <= 1e-12)
+    rng = np.random.default_rng(5)
+    # half the samples on interface cells, half anywhere
+    mixed = np.argwhere((c0 > 0) & (c0 < 1))
+    pick = mixed[rng.choice(len(mixed), 100, replace=False)]
+    anyc = np.stack([rng.integers(0, s, 100) for s in c0.shape], axis=1)
+    half = 8
+    for t, k, j, i in np.concatenate([pick, anyc]):
+        box = periodic_box(c0[t], (i, j, k), half)
+        sb = [periodic_box(w[key], (i, j, k), half) for key in ("sx", "sy", "sz")]
+        o = oracle.advect(box, *sb, 0, 1)[0]
+        assert abs(o[half, half, half] - g[t, k, j, i]) <= TOL, (t, k, j, i)
