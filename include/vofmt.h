@@ -167,6 +167,25 @@ int vofmt_nearest_pair_stats(vofmt_ctx *ctx, int32_t n, const double *xyz, const
                              int32_t *nn_index, int32_t *nn_ties, uint64_t *hist_fixed, double *M, double *R,
                              hipStream_t stream);
 
+/*
+ * Height-function curvature of one tracer field (the paper computes kappa_i
+ * of every tracer "as for a single tracer", section "The no-coalescence.h
+ * algorithm"; method: fixed 7-cell height columns). For each mixed cell
+ * (0 < c < 1) the Mixed-Youngs-Centred normal orders the column axes by
+ * decreasing |m_d|; the first axis whose 3x3 columns all run from a full cell
+ * (c >= 1-1e-6, on the phase side) to an empty one (c <= 1e-6) gives the
+ * column sums H(u,v) over offsets -3..3 and
+ *   kappa*Delta = -[Hxx(1+Hy^2) + Hyy(1+Hx^2) - 2 Hxy Hx Hy] / (1+Hx^2+Hy^2)^{3/2}
+ * (+2/R on a sphere of radius R cells; negative for a bubble).
+ *
+ * c     : [nz][ny][nx] FP64, one tracer.
+ * kappa : [nz][ny][nx] FP64 output, kappa*Delta, NaN where undefined.
+ * status: [nz][ny][nx] uint8 output: 0 not an interface cell, 1..3 valid on
+ *         the 1st..3rd axis tried, 4 no valid axis.
+ */
+int vofmt_curvature_hf(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, const double *c, double *kappa,
+                       uint8_t *status, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

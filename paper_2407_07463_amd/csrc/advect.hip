@@ -2,114 +2,273 @@
 // paper applied to every tracer C_i; its discrete form is the conservative
 // split scheme of Weymouth & Yue 2010 with MYC normals).
 //
-// One launch performs one sweep along axis D for every tracer. A wavefront
-// owns 64 consecutive x-cells of one row, so every load and store of a field
-// row is a coalesced 512-byte transaction, and the c > 0.5 indicator of the
-// 64 cells is one 64-bit ballot word. Each thread keeps its two face Courant
-// numbers in registers and loops over the tracers, so the velocity is read
-// from memory once per sweep for all N tracers. Pure donors (c <= 0 or
-// c >= 1) cost a multiply; mixed donors take the PLIC path (3x3x3 gather,
-// MYC normal, plane constant, sub-box volume).
+// One launch performs one sweep along axis D for a group of up to 8 tracers.
+// A wavefront owns 64 consecutive x-cells of one row, so every load and store
+// of a field row is a coalesced 512-byte transaction and the c > 0.5
+// indicator of the 64 cells is one 64-bit ballot word. Pure donors (c <= 0 or
+// c >= 1) cost a multiply; mixed donors take the PLIC path (3x3x3 gather, MYC
+// normal, plane constant, sub-box volume), compacted across the workgroup.
 #include "common.hpp"
 #include "plic.hpp"
 
 namespace {
 
-constexpr int kRows = 4;  // rows of 64 cells per block (4 wavefronts)
+constexpr int kChunk = 32;        // cells per thread along its marching axis
 
-// Phase volume fraction of the donor's upwind sub-box for a mixed donor
-// (0 < cd < 1) at (i,j,k): the donor's PLIC plane {m.x <= alpha} restricted
-// to x_D in [x0, x0 + |s|], mapped affinely onto the unit cube.
-template <int D>
-__device__ __noinline__ double mixed_subbox_fraction(const double *__restrict__ c, int i, int j, int k, int nx,
-                                                     int ny, int nz, double cd, double s, double x0) {
-  const int im = wrap_dec(i, nx), ip = wrap_inc(i, nx);
-  const int jm = wrap_dec(j, ny), jp = wrap_inc(j, ny);
-  const int km = wrap_dec(k, nz), kp = wrap_inc(k, nz);
-  const int xs[3] = {im, i, ip};
-  const int ys[3] = {jm, j, jp};
-  const int zs[3] = {km, k, kp};
-  double b[27];
-#pragma unroll
-  for (int az = 0; az < 3; ++az)
-#pragma unroll
-    for (int ay = 0; ay < 3; ++ay) {
-      const double *row = c + ((int64_t)zs[az] * ny + ys[ay]) * nx;
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) b[ax + 3 * ay + 9 * az] = row[xs[ax]];
-    }
-  double mx, my, mz;
-  plic::myc_normal(b, mx, my, mz);
-  double alpha = plic::alpha_of(mx, my, mz, cd);
-  double md = (D == 0) ? mx : ((D == 1) ? my : mz);
-  double as = alpha - md * x0;
-  double ms = md * fabs(s);
-  if (D == 0) return plic::volume(ms, my, mz, as);
-  if (D == 1) return plic::volume(mx, ms, mz, as);
-  return plic::volume(mx, my, ms, as);
-}
+// ---------------------------------------------------------------------------
+// A sweep is two launches.
+//
+// k_plic<D>: one wavefront per region of the list of mixed cells (0 < c < 1)
+//   of the sweep's input field. Each entry gathers its 3x3x3 block, computes
+//   the MYC normal and the plane constant, and writes the flux of every face
+//   the cell donates through (its lower face if s < 0 there, its upper face
+//   if s > 0) into the face-flux array fmix[t][p] (the lower d-face of cell
+//   p). The list is compact, so this FP64 work runs at full SIMD width.
+//
+// k_stream<D,G>: one thread per (x, row) of the plane transverse to its
+//   marching axis, for G tracers at once. For a pure donor the flux is s*c;
+//   for a mixed donor it is read from fmix. Sweeps along y or z march along
+//   the sweep axis and carry c and the lower-face flux in registers, so every
+//   field value is read from memory once; the x-sweep takes the upper-face
+//   flux from the neighbouring lane. The new field is written in the same
+//   coalesced row layout, and every new mixed cell is appended to the list of
+//   the next sweep.
+//
+// The list is cut into regions, one per wavefront of the kernel that fills
+// it, each large enough for every cell that wavefront handles: entries are
+// written without atomics, in a fixed order, and the region's length is
+// stored at the end. No barrier, no LDS.
+// ---------------------------------------------------------------------------
+constexpr int kRegion = kChunk * 64 * 8;  // list entries per wavefront region (>= cells of one wavefront)
 
-// Flux through the face between cell a (lower along D) and cell b (upper).
-template <int D>
-__device__ __forceinline__ double face_flux(const double *__restrict__ c, double ca, double cb, int ai, int aj, int ak,
-                                            int bi, int bj, int bk, double s, int nx, int ny, int nz) {
-  if (s == 0.0) return 0.0;
-  const bool up = s > 0.0;
-  const double cd = up ? ca : cb;
-  if (!(cd > 0.0 && cd < 1.0)) return s * cd;
-  const double x0 = up ? 1.0 - s : 0.0;
-  const int di = up ? ai : bi, dj = up ? aj : bj, dk = up ? ak : bk;
-  return s * mixed_subbox_fraction<D>(c, di, dj, dk, nx, ny, nz, cd, s, x0);
-}
-
-template <int D>
-__global__ __launch_bounds__(64 * kRows) void k_sweep(const double *__restrict__ cin, double *__restrict__ cout,
-                                                      const double *__restrict__ s, uint64_t *__restrict__ ccbits,
-                                                      int write_cc, int nx, int ny, int nz, int ntr, int words) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  const int j = blockIdx.y * kRows + threadIdx.y;
-  const int k = blockIdx.z;
-  const bool live = (i < nx) && (j < ny);
-  const int64_t n3 = (int64_t)nx * ny * nz;
-  const int lane = threadIdx.x;  // 0..63 within the wavefront
-  const int64_t wrow = ((int64_t)k * ny + (live ? j : 0)) * words + blockIdx.x;  // word of this row segment
-
-  int ia = i, ja = j, ka = k, ib = i, jb = j, kb = k;  // neighbours along D: a = p - e_D, b = p + e_D
-  int64_t p = 0, pa = 0, pb = 0;
-  double s_lo = 0.0, s_hi = 0.0;
-  if (live) {
-    if (D == 0) { ia = wrap_dec(i, nx); ib = wrap_inc(i, nx); }
-    if (D == 1) { ja = wrap_dec(j, ny); jb = wrap_inc(j, ny); }
-    if (D == 2) { ka = wrap_dec(k, nz); kb = wrap_inc(k, nz); }
-    p = ((int64_t)k * ny + j) * nx + i;
-    pa = ((int64_t)ka * ny + ja) * nx + ia;
-    pb = ((int64_t)kb * ny + jb) * nx + ib;
-    s_lo = s[p];
-    s_hi = s[pb];
+// Mixed cells of the initial field: wavefront w scans tracer-cells
+// [w*kRegion, (w+1)*kRegion) of the whole array.
+__global__ __launch_bounds__(256) void k_scan_mixed(const double *__restrict__ c, int64_t total,
+                                                    uint32_t *__restrict__ list, int *__restrict__ counts,
+                                                    int64_t nregions) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (w >= nregions) return;
+  uint32_t *out = list + w * kRegion;
+  int n = 0;
+  const uint64_t below = (1ull << lane) - 1;
+  for (int64_t base = w * kRegion; base < (w + 1) * kRegion && base < total; base += 64) {
+    const int64_t q = base + lane;
+    const bool mixed = (q < total) && c[q] > 0.0 && c[q] < 1.0;
+    const uint64_t mask = __ballot(mixed);
+    if (mixed) out[n + __popcll(mask & below)] = (uint32_t)q;
+    n += __popcll(mask);
   }
-  for (int t = 0; t < ntr; ++t) {
-    const double *ct = cin + (int64_t)t * n3;
-    double c0 = 0.0, cm = 0.0, cp = 0.0;
-    if (live) {
-      c0 = ct[p];
-      cm = ct[pa];
-      cp = ct[pb];
+  if (lane == 0) counts[w] = n;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_plic(const double *__restrict__ cin, const double *__restrict__ s,
+                                              const uint32_t *__restrict__ list, const int *__restrict__ counts,
+                                              int64_t nregions, double *__restrict__ fmix, int nx, int ny, int nz) {
+  const int64_t n3 = (int64_t)nx * ny * nz;
+  const int lane = threadIdx.x & 63;
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (w >= nregions) return;
+  const int nq = counts[w];
+  const uint32_t *reg = list + w * kRegion;
+  for (int q = lane; q < nq; q += 64) {
+    const uint32_t e = reg[q];
+    const int64_t t = e / n3;
+    const int64_t p = e - t * n3;
+    const int i = (int)(p % nx), j = (int)((p / nx) % ny), k = (int)(p / ((int64_t)nx * ny));
+    const int64_t pu = (D == 0) ? p - i + wrap_inc(i, nx)
+                                : ((D == 1) ? ((int64_t)k * ny + wrap_inc(j, ny)) * nx + i
+                                            : ((int64_t)wrap_inc(k, nz) * ny + j) * nx + i);
+    const double s_lo = s[p], s_hi = s[pu];
+    if (!(s_lo < 0.0) && !(s_hi > 0.0)) continue;  // donates through neither face
+    const double *ct = cin + t * n3;
+    const double cd = ct[p];
+    double b[27];
+    {
+      const int im = wrap_dec(i, nx), ip = wrap_inc(i, nx);
+      const int jm = wrap_dec(j, ny), jp = wrap_inc(j, ny);
+      const int km = wrap_dec(k, nz), kp = wrap_inc(k, nz);
+      const int xs[3] = {im, i, ip};
+      const int ys[3] = {jm, j, jp};
+      const int zs[3] = {km, k, kp};
+#pragma unroll
+      for (int az = 0; az < 3; ++az)
+#pragma unroll
+        for (int ay = 0; ay < 3; ++ay) {
+          const double *rowp = ct + ((int64_t)zs[az] * ny + ys[ay]) * nx;
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax) b[ax + 3 * ay + 9 * az] = rowp[xs[ax]];
+        }
     }
-    uint64_t *bits = ccbits + (int64_t)t * nz * ny * words;
+    double mx, my, mz;
+    plic::myc_normal(b, mx, my, mz);
+    const double alpha = plic::alpha_of(mx, my, mz, cd);
+    const double md = (D == 0) ? mx : ((D == 1) ? my : mz);
+    double *ft = fmix + t * n3;
+    if (s_lo < 0.0) {
+      // lower face: sub-box [0, |s|] along D
+      const double as = alpha - md * 0.0;
+      const double ms = md * fabs(s_lo);
+      double v;
+      if (D == 0) v = plic::volume(ms, my, mz, as);
+      else if (D == 1) v = plic::volume(mx, ms, mz, as);
+      else v = plic::volume(mx, my, ms, as);
+      ft[p] = s_lo * v;
+    }
+    if (s_hi > 0.0) {
+      // upper face: sub-box [1 - s, 1] along D
+      const double as = alpha - md * (1.0 - s_hi);
+      const double ms = md * fabs(s_hi);
+      double v;
+      if (D == 0) v = plic::volume(ms, my, mz, as);
+      else if (D == 1) v = plic::volume(mx, ms, mz, as);
+      else v = plic::volume(mx, my, ms, as);
+      ft[pu] = s_hi * v;
+    }
+  }
+}
+
+template <int D, int G>
+__global__ __launch_bounds__(256) void k_stream(const double *__restrict__ cin, double *__restrict__ cout,
+                                                const double *__restrict__ s, const double *__restrict__ fmix,
+                                                uint64_t *__restrict__ ccbits, int write_cc, int t0, int nx, int ny,
+                                                int nz, int words, int chunk, uint32_t *__restrict__ list_next,
+                                                int *__restrict__ counts_next, int64_t region0) {
+  const int lane = threadIdx.x & 63;
+  const int x = blockIdx.x * 64 + lane;
+  const int row = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int nrow = (D == 1) ? nz : ny;
+  const int nm = (D == 1) ? ny : nz;
+  const int64_t wave = region0 + (((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * 4 +
+                       (threadIdx.x >> 6);
+  if (row >= nrow) {  // whole wavefront
+    if (lane == 0) counts_next[wave] = 0;
+    return;
+  }
+  uint32_t *reg = list_next + wave * kRegion;
+  int nlist = 0;  // wavefront-uniform
+  const uint64_t below = (1ull << lane) - 1;
+  const bool live = x < nx;
+  const int xs = live ? x : nx - 1;  // dead lanes shadow a valid cell, never store
+  const int64_t n3 = (int64_t)nx * ny * nz;
+  const int64_t nbits = (int64_t)nz * ny * words;
+  const int m0 = blockIdx.z * chunk;
+  const int m1 = (m0 + chunk < nm) ? m0 + chunk : nm;
+  const double *c_g = cin + (int64_t)t0 * n3;
+  double *o_g = cout + (int64_t)t0 * n3;
+  const double *f_g = fmix + (int64_t)t0 * n3;
+  uint64_t *b_g = ccbits + (int64_t)t0 * nbits;
+
+  auto cell = [&](int xx, int mm) -> int64_t {
+    if (D == 1) return ((int64_t)row * ny + mm) * nx + xx;
+    return ((int64_t)mm * ny + row) * nx + xx;
+  };
+  auto bitword = [&](int mm) -> int64_t {
+    if (D == 1) return ((int64_t)row * ny + mm) * words + blockIdx.x;
+    return ((int64_t)mm * ny + row) * words + blockIdx.x;
+  };
+  // flux through the lower face of cell pu: donor = the lower cell (value cl)
+  // if s > 0, else the upper cell (value cu); a mixed donor's flux is in fmix
+  auto flux = [&](int t, double sv, double cl, double cu, int64_t pu) -> double {
+    const double cd = (sv > 0.0) ? cl : cu;
+    const bool mixed = (sv != 0.0) && cd > 0.0 && cd < 1.0;
+    double fv = 0.0;
+    if (mixed) fv = f_g[t * n3 + pu];
+    return mixed ? fv : ((sv == 0.0) ? 0.0 : sv * cd);
+  };
+  // new value of cell pc, its c_c bit, and its entry in the next list
+  auto finish = [&](int t, double cold, double f_lo, double f_hi, double s_lo, double s_hi, int64_t pc, int64_t wrow) {
     double ccv;
     if (write_cc) {
-      const uint64_t word = __ballot(live && c0 > 0.5);
-      if (lane == 0 && live) bits[wrow] = word;
-      ccv = (live && c0 > 0.5) ? 1.0 : 0.0;
+      const uint64_t word = __ballot(live && cold > 0.5);
+      if (lane == 0) b_g[t * nbits + wrow] = word;
+      ccv = (cold > 0.5) ? 1.0 : 0.0;
     } else {
-      const uint64_t word = live ? bits[wrow] : 0ull;
+      const uint64_t word = b_g[t * nbits + wrow];
       ccv = ((word >> lane) & 1ull) ? 1.0 : 0.0;
     }
-    if (!live) continue;
-    const double f_lo = face_flux<D>(ct, cm, c0, ia, ja, ka, i, j, k, s_lo, nx, ny, nz);
-    const double f_hi = face_flux<D>(ct, c0, cp, i, j, k, ib, jb, kb, s_hi, nx, ny, nz);
-    cout[(int64_t)t * n3 + p] = (c0 - (f_hi - f_lo)) + ccv * (s_hi - s_lo);
+    const double cn = (cold - (f_hi - f_lo)) + ccv * (s_hi - s_lo);
+    if (live) o_g[t * n3 + pc] = cn;
+    const bool mixed = live && cn > 0.0 && cn < 1.0;
+    const uint64_t mask = __ballot(mixed);
+    if (mixed) reg[nlist + __popcll(mask & below)] = (uint32_t)((int64_t)(t0 + t) * n3 + pc);
+    nlist += __popcll(mask);
+  };
+
+  if (D != 0) {
+    // ---- march along the sweep axis: faces m0..m1, cells m0..m1-1
+    const int ml = (m0 == 0) ? nm - 1 : m0 - 1;
+    double cm[G], flo[G];
+    const int64_t p0 = cell(xs, m0);
+    const double s0 = s[p0];
+    double s_lo = s0;
+    {
+      const int64_t pl = cell(xs, ml);
+      double cl[G];
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        cl[t] = c_g[t * n3 + pl];
+        cm[t] = c_g[t * n3 + p0];
+      }
+#pragma unroll
+      for (int t = 0; t < G; ++t) flo[t] = flux(t, s0, cl[t], cm[t], p0);
+    }
+    for (int m = m0 + 1; m <= m1; ++m) {
+      const int mm = (m == nm) ? 0 : m;
+      const int64_t pu = cell(xs, mm);
+      const int64_t pc = cell(xs, m - 1);
+      const int64_t wrow = bitword(m - 1);
+      const double s_hi = s[pu];
+      double cu[G], fhi[G];
+#pragma unroll
+      for (int t = 0; t < G; ++t) cu[t] = c_g[t * n3 + pu];
+#pragma unroll
+      for (int t = 0; t < G; ++t) fhi[t] = flux(t, s_hi, cm[t], cu[t], pu);
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        finish(t, cm[t], flo[t], fhi[t], s_lo, s_hi, pc, wrow);
+        flo[t] = fhi[t];
+        cm[t] = cu[t];
+      }
+      s_lo = s_hi;
+    }
+  } else {
+    // ---- x-sweep: positions are z-planes; faces along x inside the row
+    const int xl = (xs == 0) ? nx - 1 : xs - 1;
+    const int x_last = (blockIdx.x * 64 + 63 < nx) ? blockIdx.x * 64 + 63 : nx - 1;
+    const bool is_last = (x == x_last);
+    const int xu = (x_last == nx - 1) ? 0 : x_last + 1;
+    for (int m = m0; m < m1; ++m) {
+      const int64_t pc = cell(xs, m);
+      const int64_t pl = cell(xl, m);
+      const int64_t pu = cell(xu, m);  // upper neighbour of the segment's last cell
+      const int64_t wrow = bitword(m);
+      const double s_lo = s[pc];
+      const double s_up = is_last ? s[pu] : 0.0;
+      const double s_hi_sh = __shfl_down(s_lo, 1, 64);
+      const double s_hi = is_last ? s_up : s_hi_sh;
+      double c0[G], cl[G], flo[G], fup[G];
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        c0[t] = c_g[t * n3 + pc];
+        cl[t] = c_g[t * n3 + pl];
+      }
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        flo[t] = flux(t, s_lo, cl[t], c0[t], pc);
+        fup[t] = 0.0;
+        if (is_last) fup[t] = flux(t, s_up, c0[t], c_g[t * n3 + pu], pu);
+      }
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        const double f_sh = __shfl_down(flo[t], 1, 64);
+        const double f_hi = is_last ? fup[t] : f_sh;
+        finish(t, c0[t], flo[t], f_hi, s_lo, s_hi, pc, wrow);
+      }
+    }
   }
+  if (lane == 0) counts_next[wave] = nlist;
 }
 
 // Per-block maximum of |s| over the three arrays and a non-finite flag.
@@ -133,6 +292,78 @@ __global__ __launch_bounds__(256) void k_courant_max(const double *__restrict__ 
 
 }  // namespace
 
+struct SweepBuffers {
+  double *fmix;
+  uint64_t *bits;
+  uint32_t *list[2];
+  int *counts[2];
+  int64_t nregions[2];  // regions filled into each list
+};
+
+// Wavefronts of one k_stream launch along axis d (each owns one list region).
+static int64_t stream_waves(int d, int nx, int ny, int nz, int chunk) {
+  const int nrow = (d == 1) ? nz : ny;
+  const int nm = (d == 1) ? ny : nz;
+  return 4 * (int64_t)ceil_div(nx, 64) * ceil_div(nrow, 4) * ceil_div(nm, chunk);
+}
+
+template <int D, int G>
+static void launch_stream(const double *cin, double *cout, const double *s, SweepBuffers &sb, int wcc, int t0, int nx,
+                          int ny, int nz, int words, int chunk, int nxt, int64_t region0, hipStream_t stream) {
+  const int nrow = (D == 1) ? nz : ny;
+  const int nm = (D == 1) ? ny : nz;
+  dim3 grid(words, ceil_div(nrow, 4), ceil_div(nm, chunk));
+  hipLaunchKernelGGL((k_stream<D, G>), grid, dim3(256), 0, stream, cin, cout, s, sb.fmix, sb.bits, wcc, t0, nx, ny,
+                     nz, words, chunk, sb.list[nxt], sb.counts[nxt], region0);
+}
+
+// Tracer groups of one sweep: kMaxGroup tracers at a time, then groups of
+// 4, 2 and 1 for the rest. Both the launches and the sizing of the list
+// regions use this one function.
+constexpr int kMaxGroup = 4;
+static_assert(kMaxGroup <= 8 && kRegion >= kChunk * 64 * kMaxGroup, "list regions must hold a wavefront's cells");
+static int group_size(int left) {
+  if (left >= kMaxGroup) return kMaxGroup;
+  if (left >= 4) return 4;
+  if (left >= 2) return 2;
+  return 1;
+}
+static int num_groups(int ntr) {
+  int n = 0;
+  for (int t = 0; t < ntr; t += group_size(ntr - t)) ++n;
+  return n;
+}
+
+template <int D>
+static void launch_sweep_axis(const double *cin, double *cout, const double *s, SweepBuffers &sb, int wcc, int cur,
+                              int nx, int ny, int nz, int ntr, int words, int chunk, hipStream_t stream) {
+  const int nxt = cur ^ 1;
+  const int64_t nreg = sb.nregions[cur];
+  hipLaunchKernelGGL((k_plic<D>), dim3(ceil_div(nreg, 4)), dim3(256), 0, stream, cin, s, sb.list[cur],
+                     sb.counts[cur], nreg, sb.fmix, nx, ny, nz);
+  const int64_t per = stream_waves(D, nx, ny, nz, chunk);
+  int64_t region0 = 0;
+  int t = 0;
+  while (t < ntr) {
+    const int g = group_size(ntr - t);
+    if (g == 8) launch_stream<D, 8>(cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, stream);
+    else if (g == 4) launch_stream<D, 4>(cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, stream);
+    else if (g == 2) launch_stream<D, 2>(cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, stream);
+    else launch_stream<D, 1>(cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, stream);
+    t += g;
+    region0 += per;
+  }
+  sb.nregions[nxt] = region0;
+}
+
+static int launch_sweep(int d, const double *cin, double *cout, const double *s, SweepBuffers &sb, int wcc, int cur,
+                        int nx, int ny, int nz, int ntr, int words, int chunk, hipStream_t stream) {
+  if (d == 0) launch_sweep_axis<0>(cin, cout, s, sb, wcc, cur, nx, ny, nz, ntr, words, chunk, stream);
+  else if (d == 1) launch_sweep_axis<1>(cin, cout, s, sb, wcc, cur, nx, ny, nz, ntr, words, chunk, stream);
+  else launch_sweep_axis<2>(cin, cout, s, sb, wcc, cur, nx, ny, nz, ntr, words, chunk, stream);
+  return (int)hipGetLastError();
+}
+
 extern "C" int vofmt_advect(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t ntracers, double *c,
                             const double *sx, const double *sy, const double *sz, int64_t step0, int32_t nsteps,
                             hipStream_t stream) {
@@ -142,32 +373,55 @@ extern "C" int vofmt_advect(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, 
                    nx, ny, nz, ntracers, nsteps, (long long)step0);
   if (ntracers == 0 || nsteps == 0) return VOFMT_OK;
   if (!c || !sx || !sy || !sz) return set_err(ctx, VOFMT_E_ARG, "vofmt_advect: null pointer");
-  if ((int64_t)ny * nz > (int64_t)65535 * kRows * 65535)
+  if (ceil_div(ny, 4) > 65535 || ceil_div(nz, 4) > 65535)
     return set_err(ctx, VOFMT_E_ARG, "vofmt_advect: grid too large");
-  if (nz > 65535 || ceil_div(ny, kRows) > 65535) return set_err(ctx, VOFMT_E_ARG, "vofmt_advect: grid too large");
   VOFMT_HIP(ctx, hipSetDevice(ctx->device));
   const int64_t n3 = (int64_t)nx * ny * nz;
+  if ((int64_t)ntracers * n3 >= ((int64_t)1 << 32))
+    return set_err(ctx, VOFMT_E_ARG, "vofmt_advect: ntracers * cells must stay below 2^32");
   const int words = (int)ceil_div(nx, 64);
-  double *tmp = (double *)scratch(ctx, SLOT_PINGPONG, sizeof(double) * (size_t)n3 * ntracers);
-  if (!tmp) return ctx->err.empty() ? VOFMT_E_NOMEM : VOFMT_E_NOMEM;
+  const size_t field_bytes = sizeof(double) * (size_t)n3 * ntracers;
+  double *tmp = (double *)scratch(ctx, SLOT_PINGPONG, field_bytes);
+  double *fmix = (double *)scratch(ctx, SLOT_FMIX, field_bytes);
   uint64_t *bits = (uint64_t *)scratch(ctx, SLOT_CCBITS, sizeof(uint64_t) * (size_t)ntracers * nz * ny * words);
-  if (!bits) return VOFMT_E_NOMEM;
+  // list regions: enough for the largest sweep launch set and for the initial scan
+  const int ngroups = num_groups(ntracers);
+  int64_t maxreg = 0;
+  for (int d = 0; d < 3; ++d) {
+    const int64_t r = stream_waves(d, nx, ny, nz, kChunk) * ngroups;
+    maxreg = r > maxreg ? r : maxreg;
+  }
+  const int64_t total = (int64_t)ntracers * n3;
+  const int64_t scanreg = (total + kRegion - 1) / kRegion;
+  maxreg = scanreg > maxreg ? scanreg : maxreg;
+  uint32_t *lists = (uint32_t *)scratch(ctx, SLOT_MIXLIST, sizeof(uint32_t) * 2 * (size_t)maxreg * kRegion);
+  int *counts = (int *)scratch(ctx, SLOT_COUNTS, sizeof(int) * 2 * (size_t)maxreg);
+  if (!tmp || !fmix || !bits || !lists || !counts) return VOFMT_E_NOMEM;
+  SweepBuffers sb;
+  sb.fmix = fmix;
+  sb.bits = bits;
+  sb.list[0] = lists;
+  sb.list[1] = lists + (size_t)maxreg * kRegion;
+  sb.counts[0] = counts;
+  sb.counts[1] = counts + maxreg;
+  sb.nregions[0] = scanreg;
+  sb.nregions[1] = 0;
   const double *s3[3] = {sx, sy, sz};
-  dim3 block(64, kRows, 1);
-  dim3 grid(words, ceil_div(ny, kRows), nz);
+  const int chunk = kChunk;
+  // mixed cells of the input field
+  hipLaunchKernelGGL(k_scan_mixed, dim3(ceil_div(scanreg, 4)), dim3(256), 0, stream, c, total, sb.list[0],
+                     sb.counts[0], scanreg);
+  VOFMT_HIP(ctx, hipGetLastError());
+  int cur_list = 0;
   double *cur = c, *nxt = tmp;
   for (int32_t st = 0; st < nsteps; ++st) {
     const int64_t g = step0 + st;
     for (int r = 0; r < 3; ++r) {
       const int d = (int)((g + r) % 3);
       const int wcc = (r == 0);
-      if (d == 0)
-        hipLaunchKernelGGL(k_sweep<0>, grid, block, 0, stream, cur, nxt, s3[0], bits, wcc, nx, ny, nz, ntracers, words);
-      else if (d == 1)
-        hipLaunchKernelGGL(k_sweep<1>, grid, block, 0, stream, cur, nxt, s3[1], bits, wcc, nx, ny, nz, ntracers, words);
-      else
-        hipLaunchKernelGGL(k_sweep<2>, grid, block, 0, stream, cur, nxt, s3[2], bits, wcc, nx, ny, nz, ntracers, words);
-      VOFMT_HIP(ctx, hipGetLastError());
+      int rc = launch_sweep(d, cur, nxt, s3[d], sb, wcc, cur_list, nx, ny, nz, ntracers, words, chunk, stream);
+      if (rc) return hip_check(ctx, (hipError_t)rc, "sweep launch");
+      cur_list ^= 1;
       double *t = cur;
       cur = nxt;
       nxt = t;

@@ -79,7 +79,7 @@ extern "C" void vofmt_destroy(vofmt_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < kNumSlots; ++i)
     if (ctx->buf[i]) (void)hipFree(ctx->buf[i]);
   if (ctx->host) (void)hipHostFree(ctx->host);
   delete ctx;

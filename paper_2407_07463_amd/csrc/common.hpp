@@ -14,8 +14,8 @@ struct vofmt_ctx {
   int device = 0;
   std::string err;
   // Scratch buffers, grown on demand (never shrunk) and reused by later calls.
-  void *buf[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  size_t cap[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  void *buf[16] = {};
+  size_t cap[16] = {};
   // Pinned host staging for small results read back by synchronising calls.
   void *host = nullptr;
   size_t host_cap = 0;
@@ -31,6 +31,10 @@ enum ScratchSlot {
   SLOT_MISC = 5,
   SLOT_MISC2 = 6,
   SLOT_MISC3 = 7,
+  SLOT_FMIX = 8,     // fluxes of the faces with a mixed donor
+  SLOT_MIXLIST = 9,  // two lists of mixed cells (input / output of a sweep)
+  SLOT_COUNTS = 10,  // their lengths
+  kNumSlots = 16,
 };
 
 int set_err(vofmt_ctx *ctx, int code, const char *fmt, ...);

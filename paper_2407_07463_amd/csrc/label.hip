@@ -196,11 +196,12 @@ __device__ __forceinline__ int wrapped_delta(int a, int a0, int n) {
 
 // Per-drop bounding box of the offsets (integer atomics: order-independent).
 __global__ __launch_bounds__(kBlock) void k_drop_bbox(const int32_t *__restrict__ lab, int64_t n3, int nx, int ny, int nz,
-                                                      const int32_t *__restrict__ rootpos, int32_t *__restrict__ box) {
+                                                      int32_t K, const int32_t *__restrict__ rootpos,
+                                                      int32_t *__restrict__ box) {
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= n3) return;
   const int32_t l = lab[p];
-  if (l <= 0) return;
+  if (l <= 0 || l > K) return;
   const int32_t p0 = rootpos[l - 1];
   const int x = (int)(p % nx), y = (int)((p / nx) % ny), z = (int)(p / ((int64_t)nx * ny));
   const int x0 = p0 % nx, y0 = (p0 / nx) % ny, z0 = p0 / (nx * ny);
@@ -218,12 +219,12 @@ __global__ void k_first_init(int32_t *first, int64_t K) {
 }
 
 // First (smallest linear index) cell of every drop.
-__global__ __launch_bounds__(kBlock) void k_first_min(const int32_t *__restrict__ lab, int64_t n3,
+__global__ __launch_bounds__(kBlock) void k_first_min(const int32_t *__restrict__ lab, int64_t n3, int32_t K,
                                                       int32_t *__restrict__ first) {
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= n3) return;
   const int32_t l = lab[p];
-  if (l > 0) atomicMin(&first[l - 1], (int32_t)p);
+  if (l > 0 && l <= K) atomicMin(&first[l - 1], (int32_t)p);
 }
 
 __global__ void k_box_init(int32_t *box, int64_t K) {
@@ -241,8 +242,12 @@ __global__ __launch_bounds__(kBlock) void k_drop_sums(const double *__restrict__
                                                       double *__restrict__ xyz, int32_t *__restrict__ extent_err) {
   const int l = blockIdx.x + 1;
   const int32_t p0 = rootpos[l - 1];
-  const int x0 = p0 % nx, y0 = (p0 / nx) % ny, z0 = p0 / (nx * ny);
   const int32_t *b = box + 6 * (int64_t)(l - 1);
+  if (p0 == INT32_MAX || b[0] > b[1]) {  // label without cells: inconsistent input
+    if (threadIdx.x == 0) atomicOr(extent_err, 2);
+    return;
+  }
+  const int x0 = p0 % nx, y0 = (p0 / nx) % ny, z0 = p0 / (nx * ny);
   const int lx = b[0], ly = b[2], lz = b[4];
   const int ex = b[1] - b[0] + 1, ey = b[3] - b[2] + 1, ez = b[5] - b[4] + 1;
   const int64_t nbox = (int64_t)ex * ey * ez;
@@ -366,9 +371,9 @@ extern "C" int vofmt_drop_moments(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_
     if (K == 0) continue;
     const int32_t *lab = labels + (int64_t)t * n3;
     hipLaunchKernelGGL(k_first_init, dim3(ceil_div(K, 256)), dim3(256), 0, stream, rootpos, (int64_t)K);
-    hipLaunchKernelGGL(k_first_min, dim3(nb), dim3(kBlock), 0, stream, lab, n3, rootpos);
+    hipLaunchKernelGGL(k_first_min, dim3(nb), dim3(kBlock), 0, stream, lab, n3, K, rootpos);
     hipLaunchKernelGGL(k_box_init, dim3(ceil_div(6 * (int64_t)K, 256)), dim3(256), 0, stream, box, (int64_t)K);
-    hipLaunchKernelGGL(k_drop_bbox, dim3(nb), dim3(kBlock), 0, stream, lab, n3, nx, ny, nz, rootpos, box);
+    hipLaunchKernelGGL(k_drop_bbox, dim3(nb), dim3(kBlock), 0, stream, lab, n3, nx, ny, nz, K, rootpos, box);
     hipLaunchKernelGGL(k_drop_sums, dim3(K), dim3(kBlock), 0, stream, c + (int64_t)t * n3, lab, nx, ny, nz, rootpos,
                        box, vol + off, xyz + 3 * off, flags);
     VOFMT_HIP(ctx, hipGetLastError());
@@ -376,6 +381,7 @@ extern "C" int vofmt_drop_moments(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_
   }
   VOFMT_HIP(ctx, hipMemcpyAsync(fh, flags, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, stream));
   VOFMT_HIP(ctx, hipStreamSynchronize(stream));
+  if (fh[0] & 2) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_moments: labels do not match ndrops_host");
   if (fh[0]) return set_err(ctx, VOFMT_E_EXTENT, "vofmt_drop_moments: a drop spans half the box or more");
   return VOFMT_OK;
 }

@@ -123,26 +123,26 @@ __device__ __forceinline__ double alpha_of(double mx, double my, double mz, doub
   } else if (m3 >= m12 && v >= m12 / (2.0 * m3)) {
     a = v * m3 + 0.5 * m12;
   } else {
-    // cubic cases on [m2, min(m3, m1+m2, M/2)] and beyond up to M/2
+    // cubic cases: alpha in [m2, M/2]; start from the chord between the
+    // bracket ends (V(m2) = v2, V(M/2) = 1/2) and take safeguarded Newton
+    // steps; V is convex-concave here, so a few steps reach the last bits
     double lo = m2, hi = 0.5 * M;
-    a = 0.5 * (lo + hi);
-    for (int it = 0; it < 40; ++it) {
+    a = lo + (hi - lo) * ((v - v2) / (0.5 - v2));
+    for (int it = 0; it < 12; ++it) {
       double V, dV;
       volume_deriv_sorted(m1, m2, m3, a, V, dV);
       double f = V - v;
       if (f < 0.0) lo = a;
       else hi = a;
       double an = (dV > 0.0) ? a - f / dV : 0.5 * (lo + hi);
-      if (!(an > lo && an < hi)) an = 0.5 * (lo + hi);
-      if (fabs(an - a) <= 1e-17 * (1.0 + fabs(a))) {
-        a = an;
-        break;
-      }
+      if (!(an >= lo && an <= hi)) an = 0.5 * (lo + hi);
+      const double step = fabs(an - a);
       a = an;
+      if (step <= 4e-16 * a) break;
     }
   }
-  // polish
-  for (int it = 0; it < 2; ++it) {
+  // one Newton polish step (the closed forms lose a few bits near case ends)
+  {
     double V, dV;
     volume_deriv_sorted(m1, m2, m3, a, V, dV);
     if (dV > 0.0) {

@@ -20,6 +20,9 @@
 //      for the conflict test and an OR-reduction for the tracers in use;
 //   5. the host reads back the tracer count (capacity check), then every
 //      cell clears its moved-out values and adds them to the new fields.
+#include <cstdlib>
+#include <cstring>
+
 #include "common.hpp"
 
 namespace {
@@ -40,7 +43,7 @@ __global__ __launch_bounds__(kBlock) void k_owner(const int32_t *__restrict__ la
   int32_t o = -1;
   for (int t = 0; t < ntr; ++t) {
     const int32_t l = lab[(int64_t)t * n3 + p];
-    if (l > 0) o = (o == -1) ? to.off[t] + l - 1 : -2;
+    if (l > 0 && to.off[t] + l <= to.off[t + 1]) o = (o == -1) ? to.off[t] + l - 1 : -2;
   }
   own[p] = o;
 }
@@ -60,7 +63,7 @@ __device__ __forceinline__ int drops_at(const int32_t *__restrict__ lab, int64_t
   int k = 0;
   for (int t = 0; t < ntr; ++t) {
     const int32_t l = lab[(int64_t)t * n3 + p];
-    if (l > 0) ids[k++] = to.off[t] + l - 1;
+    if (l > 0 && to.off[t] + l <= to.off[t + 1]) ids[k++] = to.off[t] + l - 1;
   }
   return k;
 }
@@ -271,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_move(double *__restrict__ c, const i
   int cnt = 0;
   for (int t = 0; t < ntr; ++t) {
     const int32_t l = lab[(int64_t)t * n3 + p];
-    if (l > 0 && newt[to.off[t] + l - 1] != t) ++cnt;
+    if (l > 0 && to.off[t] + l <= to.off[t + 1] && newt[to.off[t] + l - 1] != t) ++cnt;
   }
   if (cnt == 0) return;
   double vals[kMaxTracers];
@@ -279,7 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_move(double *__restrict__ c, const i
   int k = 0;
   for (int t = 0; t < ntr; ++t) {
     const int32_t l = lab[(int64_t)t * n3 + p];
-    if (l <= 0) continue;
+    if (l <= 0 || to.off[t] + l > to.off[t + 1]) continue;
     const int n = newt[to.off[t] + l - 1];
     if (n == t) continue;
     vals[k] = c[(int64_t)t * n3 + p];

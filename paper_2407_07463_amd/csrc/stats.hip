@@ -1,0 +1,190 @@
+// Nearest-particle statistics (section "Nearest particle statistics").
+//
+// For every drop i the minimum-image vectors to all other drops are formed
+// exactly as in the definition (per axis: subtract L if r > L/2, add L if
+// r <= -L/2; d2 = (rx^2 + ry^2) + rz^2); the nearest set is every j with d2
+// equal to the minimum, with tie weight h = 1/N_i (eq. 4). Each nearest pair
+// is binned in (r, theta) (eqs. 8 and 10) with integer weights 720720/N_i,
+// accumulated by 64-bit integer atomics (order-independent, exact), and
+// contributes h r and h r r^T to the moments M (eq. 11) and R (eq. 14).
+// Per-drop moment contributions are summed in a fixed tree order, so every
+// output is reproducible bit for bit.
+#include "common.hpp"
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr uint64_t kFixedOne = 720720ull;  // lcm(1..16)
+
+struct Box {
+  double L[3];
+};
+
+__device__ __forceinline__ double min_image(double d, double L) {
+  if (d > 0.5 * L) d -= L;
+  else if (d <= -0.5 * L) d += L;
+  return d;
+}
+
+__global__ __launch_bounds__(kBlock) void k_nearest(const double *__restrict__ xyz, int32_t n, Box box,
+                                                    int32_t *__restrict__ nn_index, int32_t *__restrict__ nn_ties,
+                                                    double *__restrict__ best_d2) {
+  __shared__ double sx[kBlock], sy[kBlock], sz[kBlock];
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  double xi = 0, yi = 0, zi = 0;
+  if (i < n) {
+    xi = xyz[3 * (int64_t)i];
+    yi = xyz[3 * (int64_t)i + 1];
+    zi = xyz[3 * (int64_t)i + 2];
+  }
+  double best = INFINITY;
+  int32_t bj = -1, ties = 0;
+  for (int32_t j0 = 0; j0 < n; j0 += kBlock) {
+    const int32_t jj = j0 + threadIdx.x;
+    __syncthreads();
+    if (jj < n) {
+      sx[threadIdx.x] = xyz[3 * (int64_t)jj];
+      sy[threadIdx.x] = xyz[3 * (int64_t)jj + 1];
+      sz[threadIdx.x] = xyz[3 * (int64_t)jj + 2];
+    }
+    __syncthreads();
+    const int32_t m = (n - j0 < kBlock) ? n - j0 : kBlock;
+    if (i < n) {
+      for (int k = 0; k < m; ++k) {
+        const int32_t j = j0 + k;
+        if (j == i) continue;
+        const double rx = min_image(sx[k] - xi, box.L[0]);
+        const double ry = min_image(sy[k] - yi, box.L[1]);
+        const double rz = min_image(sz[k] - zi, box.L[2]);
+        const double d2 = (rx * rx + ry * ry) + rz * rz;
+        if (d2 < best) {
+          best = d2;
+          bj = j;
+          ties = 1;
+        } else if (d2 == best) {
+          ties += 1;
+        }
+      }
+    }
+  }
+  if (i < n) {
+    nn_index[i] = bj;
+    nn_ties[i] = ties;
+    best_d2[i] = best;
+  }
+}
+
+// Bin the nearest pairs of drop i and write its moment contributions
+// part[12*i ..]: sum_j h r (3) and sum_j h r r^T (9), j ascending.
+__global__ __launch_bounds__(kBlock) void k_pairs(const double *__restrict__ xyz, int32_t n, Box box, int vaxis,
+                                                  int nr, int nth, const double *__restrict__ edges,
+                                                  const int32_t *__restrict__ nn_ties,
+                                                  const double *__restrict__ best_d2, uint64_t *__restrict__ hist,
+                                                  double *__restrict__ part) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double *r2e = edges;           // nr + 1
+  const double *ce = edges + nr + 1;   // nth + 1
+  const double xi = xyz[3 * (int64_t)i], yi = xyz[3 * (int64_t)i + 1], zi = xyz[3 * (int64_t)i + 2];
+  const double best = best_d2[i];
+  const int ties = nn_ties[i];
+  const double h = 1.0 / (double)ties;
+  const uint64_t wfix = kFixedOne / (uint64_t)ties;
+  double sm[3] = {0, 0, 0}, sr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int32_t j = 0; j < n; ++j) {
+    if (j == i) continue;
+    double r[3];
+    r[0] = min_image(xyz[3 * (int64_t)j] - xi, box.L[0]);
+    r[1] = min_image(xyz[3 * (int64_t)j + 1] - yi, box.L[1]);
+    r[2] = min_image(xyz[3 * (int64_t)j + 2] - zi, box.L[2]);
+    const double d2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
+    if (d2 != best) continue;
+    int k = -1;
+    for (int e = 0; e <= nr; ++e)
+      if (r2e[e] <= d2) k = e;
+    int m = 0;
+    const double rv = (vaxis == 0) ? r[0] : ((vaxis == 1) ? r[1] : r[2]);
+    for (int e = 1; e < nth; ++e) {
+      const double c = ce[e];
+      if (rv * fabs(rv) <= (c * fabs(c)) * d2) m = e;
+    }
+    if (k < 0 || k >= nr) atomicAdd((unsigned long long *)&hist[(int64_t)nr * nth], (unsigned long long)wfix);
+    else atomicAdd((unsigned long long *)&hist[(int64_t)k * nth + m], (unsigned long long)wfix);
+    for (int a = 0; a < 3; ++a) {
+      sm[a] += h * r[a];
+      for (int b = 0; b < 3; ++b) sr[3 * a + b] += h * (r[a] * r[b]);
+    }
+  }
+  double *o = part + 12 * (int64_t)i;
+  for (int a = 0; a < 3; ++a) o[a] = sm[a];
+  for (int a = 0; a < 9; ++a) o[3 + a] = sr[a];
+}
+
+// Fixed-order reduction of the per-drop contributions (one workgroup).
+__global__ __launch_bounds__(kBlock) void k_moments(const double *__restrict__ part, int32_t n, double *__restrict__ M,
+                                                    double *__restrict__ R) {
+  __shared__ double red[12][kBlock];
+  double acc[12];
+  for (int a = 0; a < 12; ++a) acc[a] = 0.0;
+  for (int32_t i = threadIdx.x; i < n; i += kBlock)
+    for (int a = 0; a < 12; ++a) acc[a] += part[12 * (int64_t)i + a];
+  for (int a = 0; a < 12; ++a) red[a][threadIdx.x] = acc[a];
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int a = 0; a < 12; ++a) red[a][threadIdx.x] += red[a][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) M[threadIdx.x] = red[threadIdx.x][0] / (double)n;
+  if (threadIdx.x < 9) R[threadIdx.x] = red[3 + threadIdx.x][0] / (double)n;
+}
+
+__global__ void k_zero_u64(uint64_t *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+}  // namespace
+
+extern "C" int vofmt_nearest_pair_stats(vofmt_ctx *ctx, int32_t n, const double *xyz, const double *box,
+                                        int32_t vertical_axis, int32_t nr, int32_t ntheta, const double *r2_edges,
+                                        const double *cos_edges, int32_t *nn_index, int32_t *nn_ties,
+                                        uint64_t *hist_fixed, double *M, double *R, hipStream_t stream) {
+  if (!ctx) return VOFMT_E_ARG;
+  if (n < 2 || vertical_axis < 0 || vertical_axis > 2 || nr < 1 || ntheta < 1)
+    return set_err(ctx, VOFMT_E_ARG, "vofmt_nearest_pair_stats: bad sizes (n=%d nr=%d ntheta=%d axis=%d)", n, nr,
+                   ntheta, vertical_axis);
+  if (!xyz || !box || !r2_edges || !cos_edges || !nn_index || !nn_ties || !hist_fixed || !M || !R)
+    return set_err(ctx, VOFMT_E_ARG, "vofmt_nearest_pair_stats: null pointer");
+  for (int a = 0; a < 3; ++a)
+    if (!(box[a] > 0.0)) return set_err(ctx, VOFMT_E_ARG, "vofmt_nearest_pair_stats: box must be positive");
+  for (int e = 0; e < nr; ++e)
+    if (!(r2_edges[e] < r2_edges[e + 1]))
+      return set_err(ctx, VOFMT_E_ARG, "vofmt_nearest_pair_stats: r2_edges must increase");
+  for (int e = 0; e < ntheta; ++e)
+    if (!(cos_edges[e] > cos_edges[e + 1]))
+      return set_err(ctx, VOFMT_E_ARG, "vofmt_nearest_pair_stats: cos_edges must decrease");
+  VOFMT_HIP(ctx, hipSetDevice(ctx->device));
+  const size_t nedge = (size_t)nr + 1 + (size_t)ntheta + 1;
+  double *dedge = (double *)scratch(ctx, SLOT_MISC, sizeof(double) * nedge);
+  double *best = (double *)scratch(ctx, SLOT_MISC2, sizeof(double) * (size_t)n);
+  double *part = (double *)scratch(ctx, SLOT_MISC3, sizeof(double) * 12 * (size_t)n);
+  double *hstage = (double *)host_scratch(ctx, sizeof(double) * nedge);
+  if (!dedge || !best || !part || !hstage) return VOFMT_E_NOMEM;
+  for (int e = 0; e <= nr; ++e) hstage[e] = r2_edges[e];
+  for (int e = 0; e <= ntheta; ++e) hstage[nr + 1 + e] = cos_edges[e];
+  VOFMT_HIP(ctx, hipMemcpyAsync(dedge, hstage, sizeof(double) * nedge, hipMemcpyHostToDevice, stream));
+  Box b;
+  for (int a = 0; a < 3; ++a) b.L[a] = box[a];
+  const int64_t nh = (int64_t)nr * ntheta + 1;
+  hipLaunchKernelGGL(k_zero_u64, dim3(ceil_div(nh, 256)), dim3(256), 0, stream, hist_fixed, nh);
+  hipLaunchKernelGGL(k_nearest, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, stream, xyz, n, b, nn_index, nn_ties,
+                     best);
+  hipLaunchKernelGGL(k_pairs, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, stream, xyz, n, b, vertical_axis, nr,
+                     ntheta, dedge, nn_ties, best, hist_fixed, part);
+  hipLaunchKernelGGL(k_moments, dim3(1), dim3(kBlock), 0, stream, part, n, M, R);
+  VOFMT_HIP(ctx, hipGetLastError());
+  // the staging buffer must stay valid until the copy has run
+  VOFMT_HIP(ctx, hipStreamSynchronize(stream));
+  return VOFMT_OK;
+}

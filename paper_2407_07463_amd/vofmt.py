@@ -37,6 +37,7 @@ _SIGNATURES = {
                                              _vp]),
     "vofmt_nearest_pair_stats": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
                                                 _vp, _vp, _vp]),
+    "vofmt_curvature_hf": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp]),
 }
 
 _lib = None
@@ -177,6 +178,15 @@ class Context:
         return self._check(load().vofmt_nearest_pair_stats(
             self.h, n, _ptr(xyz), b.ctypes.data, int(vertical_axis), len(r2) - 1, len(ce) - 1, r2.ctypes.data,
             ce.ctypes.data, _ptr(nn_index), _ptr(nn_ties), _ptr(hist), _ptr(M), _ptr(R), _stream(stream)))
+
+
+    # ------------------------------------------------------------ curvature
+    def curvature_hf(self, c, kappa, status, stream=None):
+        """Height-function curvature of one field c[nz][ny][nx] into kappa (float64) and status (uint8)."""
+        _require(c, kappa, status)
+        nx, ny, nz = _dims(c)
+        return self._check(load().vofmt_curvature_hf(self.h, nx, ny, nz, _ptr(c), _ptr(kappa), _ptr(status),
+                                                     _stream(stream)))
 
 
 def _require(*ts):

@@ -1,0 +1,306 @@
+"""GPU parity of labelling, drop moments, recolouring, pair statistics and
+height-function curvature against the CPU FP64 oracle.
+
+Bars: labels, drop counts, tracer assignment, moved counts, neighbour
+indices, tie counts and histograms bit-exact; FP64 volume fractions after
+recolouring bit-exact (cells are copied, not recomputed); moments and
+curvature within 1e-12 (relative for volumes; absolute in cells for
+centroids; relative to the scale sum h|r|^2 for M and R).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from fixtures import near_contact_panels, panel_fields, random_blobs
+from gpu_util import note, require_gpu
+from paper_2407_07463_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = require_gpu()
+    from paper_2407_07463_amd import vofmt
+
+    c = vofmt.Context(0)
+    yield c
+    c.close()
+    del torch
+
+
+def _dev(a, dtype=None):
+    import torch
+
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to("cuda:0")
+
+
+def _gpu_labels(ctx, c):
+    import torch
+
+    tc = _dev(c)
+    lab = torch.zeros(tc.shape, dtype=torch.int32, device="cuda:0")
+    nd = ctx.label_drops(tc, lab)
+    return lab.cpu().numpy(), nd
+
+
+# ------------------------------------------------------------------ labels
+
+@pytest.mark.parametrize("seed", range(5))
+def test_labels_random_blobs(ctx, seed):
+    rng = np.random.default_rng(seed)
+    shape = tuple(int(v) for v in rng.integers(5, 70, 3))
+    c = random_blobs(rng, shape, 3, 30, 1.0, 4.0)
+    c[:, rng.uniform(size=shape) < 0.01] = 1e-9  # sub-threshold values must not bridge drops
+    note(f"label random blobs shape={shape}")
+    lab, nd = _gpu_labels(ctx, c)
+    for t in range(3):
+        ol, k = oracle.label(c[t])
+        assert nd[t] == k
+        assert np.array_equal(lab[t], ol)
+
+
+def test_labels_long_runs_and_wrap(ctx):
+    # runs crossing 64-cell segment boundaries, spirals and full rows
+    c = np.zeros((1, 9, 7, 200))
+    c[0, 0, 0, :] = 1.0          # a full periodic row
+    c[0, 3, 2, 50:140] = 0.7     # a run over two segment boundaries
+    c[0, 3, 3, 139] = 0.4
+    c[0, 3, 4, 60:139] = 0.6     # joined through (139, 3)
+    c[0, 8, 6, 199] = 0.5
+    c[0, 0, 6, 199] = 0.5        # wraps in z to the previous cell
+    note("label runs and wrap")
+    lab, nd = _gpu_labels(ctx, c)
+    ol, k = oracle.label(c[0])
+    assert nd[0] == k and np.array_equal(lab[0], ol)
+
+
+def test_labels_figure_and_empty(ctx):
+    p = near_contact_panels()
+    c = panel_fields(p["right"])
+    note("label figure")
+    lab, nd = _gpu_labels(ctx, c)
+    assert list(nd) == [1, 0]
+    assert np.all(lab[1] == 0)
+
+
+@pytest.fixture(scope="module")
+def spheres64_after():
+    w = synth.spheres64()
+    return oracle.advect(w["c"], w["sx"], w["sy"], w["sz"], 0, 20)
+
+
+def test_labels_and_moments_spheres64(ctx, spheres64_after):
+    import torch
+
+    c = spheres64_after
+    note("label + moments spheres64")
+    tc = _dev(c)
+    lab = torch.zeros(tc.shape, dtype=torch.int32, device="cuda:0")
+    nd = ctx.label_drops(tc, lab)
+    D = int(nd.sum())
+    vol = torch.zeros(D, dtype=torch.float64, device="cuda:0")
+    xyz = torch.zeros((D, 3), dtype=torch.float64, device="cuda:0")
+    ctx.drop_moments(tc, lab, nd, vol, xyz)
+    torch.cuda.synchronize()
+    lab = lab.cpu().numpy()
+    g = 0
+    for t in range(2):
+        ol, k = oracle.label(c[t])
+        assert nd[t] == k and np.array_equal(lab[t], ol)
+        ov, ox, rc = oracle.drop_moments(c[t], ol, k)
+        assert rc == 0
+        gv = vol[g:g + k].cpu().numpy()
+        gx = xyz[g:g + k].cpu().numpy()
+        assert np.all(np.abs(gv - ov) <= 1e-12 * np.abs(ov))
+        assert np.abs(gx - ox).max() <= 1e-12 * 64
+        g += k
+
+
+def test_moments_extent_error(ctx):
+    import torch
+
+    from paper_2407_07463_amd import vofmt
+
+    c = np.zeros((1, 4, 4, 16))
+    c[0, 1, 1, :9] = 1.0
+    tc = _dev(c)
+    lab = torch.zeros(tc.shape, dtype=torch.int32, device="cuda:0")
+    nd = ctx.label_drops(tc, lab)
+    vol = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    xyz = torch.zeros((1, 3), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(vofmt.VofmtError) as e:
+        ctx.drop_moments(tc, lab, nd, vol, xyz)
+    assert e.value.code == vofmt.E_EXTENT
+
+
+# ------------------------------------------------------------------ recolouring
+
+def _gpu_recolour(ctx, c_full, ntr, tau):
+    import torch
+
+    tc = _dev(c_full)
+    lab = torch.zeros((ntr,) + c_full.shape[1:], dtype=torch.int32, device="cuda:0")
+    nd = ctx.label_drops(tc[:ntr], lab)
+    D = int(nd.sum())
+    newt = torch.zeros(max(D, 1), dtype=torch.int32, device="cuda:0")
+    ntr_new, nmoved = ctx.recolor_tracers(tc, ntr, lab, nd, tau, newt)
+    torch.cuda.synchronize()
+    return tc.cpu().numpy(), ntr_new, newt[:D].cpu().numpy(), nmoved, lab.cpu().numpy(), nd
+
+
+def test_recolour_figure_left(ctx):
+    p = near_contact_panels()
+    c2 = panel_fields(p["left"], pad=(8, 8))
+    c = np.zeros((4,) + c2.shape[1:])
+    c[:2] = c2
+    note("recolour figure left")
+    g, ntr, newt, nmoved, _, _ = _gpu_recolour(ctx, c, 2, 3.2)
+    assert list(newt) == [0, 2, 1] and ntr == 3 and nmoved == 1
+    labels = np.stack([oracle.label(c[t])[0] for t in range(2)])
+    o, ontr, onewt, onm, rc = oracle.recolor(c, labels, [2, 1], 2, 4, 3.2)
+    assert np.array_equal(g, o)
+
+
+def test_recolour_capacity_error(ctx):
+    import torch
+
+    from paper_2407_07463_amd import vofmt
+
+    p = near_contact_panels()
+    c = panel_fields(p["left"], pad=(8, 8))
+    tc = _dev(c)
+    before = tc.clone()
+    lab = torch.zeros(tc.shape, dtype=torch.int32, device="cuda:0")
+    nd = ctx.label_drops(tc, lab)
+    newt = torch.zeros(3, dtype=torch.int32, device="cuda:0")
+    with pytest.raises(vofmt.VofmtError) as e:
+        ctx.recolor_tracers(tc, 2, lab, nd, 3.2, newt)
+    assert e.value.code == vofmt.E_CAPACITY
+    assert torch.equal(tc, before)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_recolour_random(ctx, seed):
+    rng = np.random.default_rng(300 + seed)
+    shape = (21, 26, 33)
+    ntr, maxt = 3, 12
+    c = np.zeros((maxt,) + shape)
+    c[:ntr] = random_blobs(rng, shape, ntr, 40, 1.0, 2.6)
+    note(f"recolour random seed={seed}")
+    g, gntr, gnewt, gmoved, glab, gnd = _gpu_recolour(ctx, c, ntr, 1.5)
+    labels = np.stack([oracle.label(c[t])[0] for t in range(ntr)])
+    nd = labels.reshape(ntr, -1).max(1)
+    assert np.array_equal(glab, labels) and list(gnd) == list(nd)
+    o, ontr, onewt, omoved, rc = oracle.recolor(c, labels, nd, ntr, maxt, 1.5)
+    assert rc == 0
+    assert gntr == ontr and gmoved == omoved and np.array_equal(gnewt, onewt)
+    assert np.array_equal(g, o)
+
+
+def test_recolour_spheres64(ctx, spheres64_after):
+    c = np.zeros((4,) + spheres64_after.shape[1:])
+    c[:2] = spheres64_after
+    note("recolour spheres64")
+    g, gntr, gnewt, gmoved, glab, gnd = _gpu_recolour(ctx, c, 2, 1.5)
+    labels = np.stack([oracle.label(c[t])[0] for t in range(2)])
+    o, ontr, onewt, omoved, rc = oracle.recolor(c, labels, gnd, 2, 4, 1.5)
+    assert gntr == ontr and gmoved == omoved and np.array_equal(gnewt, onewt)
+    assert np.array_equal(g, o)
+
+
+# ------------------------------------------------------------------ statistics
+
+def _gpu_stats(ctx, xyz, box, vaxis, r2e, ce):
+    import torch
+
+    n = len(xyz)
+    nr, nth = len(r2e) - 1, len(ce) - 1
+    tx = _dev(xyz)
+    idx = torch.zeros(n, dtype=torch.int32, device="cuda:0")
+    ties = torch.zeros(n, dtype=torch.int32, device="cuda:0")
+    hist = torch.zeros(nr * nth + 1, dtype=torch.int64, device="cuda:0")
+    M = torch.zeros(3, dtype=torch.float64, device="cuda:0")
+    R = torch.zeros(9, dtype=torch.float64, device="cuda:0")
+    ctx.nearest_pair_stats(tx, box, vaxis, r2e, ce, idx, ties, hist, M, R)
+    torch.cuda.synchronize()
+    return dict(nn_index=idx.cpu().numpy(), nn_ties=ties.cpu().numpy(),
+                hist=hist.cpu().numpy().view(np.uint64), M=M.cpu().numpy(), R=R.cpu().numpy().reshape(3, 3))
+
+
+def _check_stats(g, o, xyz, box):
+    assert np.array_equal(g["nn_index"], o["nn_index"])
+    assert np.array_equal(g["nn_ties"], o["nn_ties"])
+    assert np.array_equal(g["hist"][:-1].reshape(o["hist"].shape), o["hist"]) and int(g["hist"][-1]) == o["overflow"]
+    scale = np.trace(o["R"]) + 1e-300
+    assert np.abs(g["M"] - o["M"]).max() <= 1e-12 * math.sqrt(scale)
+    assert np.abs(g["R"] - o["R"]).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("n", [2, 3, 257, 5508])
+def test_stats_random(ctx, n):
+    rng = synth.Splitmix64(40 + n)
+    box = np.array([512.0, 512.0, 512.0])
+    xyz = rng.uniform(3 * n).reshape(n, 3) * box
+    r2e = (np.arange(65) * (96.0 / 64)) ** 2
+    ce = np.cos(np.arange(33) * math.pi / 32)
+    note(f"pair stats n={n}")
+    g = _gpu_stats(ctx, xyz, box, 2, r2e, ce)
+    o = oracle.nearest_pair_stats(xyz, box, 2, r2e, ce)
+    _check_stats(g, o, xyz, box)
+
+
+def test_stats_lattice_ties(ctx):
+    a = 8.0
+    gr = np.arange(6) * a
+    xyz = np.array([(x, y, z) for z in gr for y in gr for x in gr])
+    box = np.array([48.0, 48.0, 48.0])
+    r2e = np.linspace(0, 20, 9) ** 2
+    ce = np.cos(np.linspace(0, math.pi, 7))
+    for vaxis in (0, 2):
+        note(f"pair stats lattice axis={vaxis}")
+        g = _gpu_stats(ctx, xyz, box, vaxis, r2e, ce)
+        o = oracle.nearest_pair_stats(xyz, box, vaxis, r2e, ce)
+        _check_stats(g, o, xyz, box)
+        assert np.all(g["nn_ties"] == 6)
+
+
+# ------------------------------------------------------------------ curvature
+
+def _gpu_curv(ctx, c):
+    import torch
+
+    tc = _dev(c)
+    k = torch.zeros(tc.shape, dtype=torch.float64, device="cuda:0")
+    st = torch.zeros(tc.shape, dtype=torch.uint8, device="cuda:0")
+    ctx.curvature_hf(tc, k, st)
+    torch.cuda.synchronize()
+    return k.cpu().numpy(), st.cpu().numpy()
+
+
+@pytest.mark.parametrize("R", [3.0, 6.5, 12.0])
+def test_curvature_spheres(ctx, R):
+    n = int(2 * R + 14)
+    c = synth.fill_spheres((n, n, n), 1, [(n / 2 + 0.37, n / 2 - 0.21, n / 2 + 0.11)], [R], [0])[0]
+    note(f"curvature sphere R={R}")
+    gk, gs = _gpu_curv(ctx, c)
+    ok, os_ = oracle.curvature_hf(c)
+    assert np.array_equal(gs, os_)
+    valid = (os_ >= 1) & (os_ <= 3)
+    assert np.abs(gk[valid] - ok[valid]).max() <= 1e-12
+    assert np.all(np.isnan(gk[~valid]))
+
+
+def test_curvature_advected_field(ctx, spheres64_after):
+    c = spheres64_after[1]
+    note("curvature advected field")
+    gk, gs = _gpu_curv(ctx, c)
+    ok, os_ = oracle.curvature_hf(c)
+    assert np.array_equal(gs, os_)
+    valid = (os_ >= 1) & (os_ <= 3)
+    assert np.abs(gk[valid] - ok[valid]).max() <= 1e-12
