@@ -146,13 +146,14 @@ static inline double blk_axis(const double *b, int d, int e, int u, int v) {
   return blk(b, a[0], a[1], a[2]);
 }
 
-/* Returns 1 if the centred-columns candidate was used, 0 for Youngs. */
+/* Returns 1 if the centred-columns candidate was used, 0 for Youngs.
+ * Centred columns: for each column axis d the candidate is
+ * (sigma, -g1, -g2)/D with D = (|g1| + |g2|) + 1 and quality 1/D; the best
+ * quality is the smallest D (ties: lowest axis), and only that candidate is
+ * normalised. */
 int orc_myc_normal(const double *b, double *m_out) {
-  double cs[3][3]; /* candidate normal per column axis */
-  double q[3];
+  double Dd[3], sg[3], g1d[3], g2d[3];
   for (int d = 0; d < 3; ++d) {
-    int t1 = (d == 0) ? 1 : 0;
-    int t2 = (d == 2) ? 1 : 2;
     double H[3][3]; /* H[u+1][v+1]: column sums along d */
     for (int v = -1; v <= 1; ++v)
       for (int u = -1; u <= 1; ++u)
@@ -163,18 +164,23 @@ int orc_myc_normal(const double *b, double *m_out) {
         slo += blk_axis(b, d, -1, u, v);
         shi += blk_axis(b, d, 1, u, v);
       }
-    double sigma = (slo >= shi) ? 1.0 : -1.0;
-    double g1 = (H[2][1] - H[0][1]) / 2.0;
-    double g2 = (H[1][2] - H[1][0]) / 2.0;
-    double D = (fabs(g1) + fabs(g2)) + 1.0;
-    cs[d][d] = sigma / D;
-    cs[d][t1] = -g1 / D;
-    cs[d][t2] = -g2 / D;
-    q[d] = 1.0 / D;
+    sg[d] = (slo >= shi) ? 1.0 : -1.0;
+    g1d[d] = (H[2][1] - H[0][1]) / 2.0;
+    g2d[d] = (H[1][2] - H[1][0]) / 2.0;
+    Dd[d] = (fabs(g1d[d]) + fabs(g2d[d])) + 1.0;
   }
   int ds = 0;
   for (int d = 1; d < 3; ++d)
-    if (q[d] > q[ds]) ds = d;
+    if (Dd[d] < Dd[ds]) ds = d;
+  double cs[3];
+  {
+    int t1 = (ds == 0) ? 1 : 0;
+    int t2 = (ds == 2) ? 1 : 2;
+    cs[ds] = sg[ds] / Dd[ds];
+    cs[t1] = -g1d[ds] / Dd[ds];
+    cs[t2] = -g2d[ds] / Dd[ds];
+  }
+  double qcs = 1.0 / Dd[ds];
   /* Youngs: weighted central differences over the 3x3x3 block */
   static const double w[3] = {1.0, 2.0, 1.0};
   double G[3] = {0.0, 0.0, 0.0};
@@ -193,9 +199,9 @@ int orc_myc_normal(const double *b, double *m_out) {
   if (L1 > 0.0) {
     for (int i = 0; i < 3; ++i) my[i] = -G[i] / L1;
     double qy = fmax(fmax(fabs(my[0]), fabs(my[1])), fabs(my[2]));
-    use_cs = (q[ds] <= qy);
+    use_cs = (qcs <= qy);
   }
-  for (int i = 0; i < 3; ++i) m_out[i] = use_cs ? cs[ds][i] : my[i];
+  for (int i = 0; i < 3; ++i) m_out[i] = use_cs ? cs[i] : my[i];
   return use_cs;
 }
 

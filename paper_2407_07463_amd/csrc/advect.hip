@@ -29,8 +29,9 @@ constexpr int kChunk = 32;        // cells per thread along its marching axis
 //   marching axis, for G tracers at once. For a pure donor the flux is s*c;
 //   for a mixed donor it is read from fmix. Sweeps along y or z march along
 //   the sweep axis and carry c and the lower-face flux in registers, so every
-//   field value is read from memory once; the x-sweep takes the upper-face
-//   flux from the neighbouring lane. The new field is written in the same
+//   field value is read from memory once; in the x-sweep each lane forms both
+//   of its faces from its own and its neighbour lanes' values. The new field
+//   is written in the same
 //   coalesced row layout, and every new mixed cell is appended to the list of
 //   the next sweep.
 //
@@ -62,10 +63,15 @@ __global__ __launch_bounds__(256) void k_scan_mixed(const double *__restrict__ c
   if (lane == 0) counts[w] = n;
 }
 
+struct Divisors {
+  FastDiv n3, nx, ny;  // entry -> (tracer, cell), cell -> (i, j, k)
+};
+
 template <int D>
 __global__ __launch_bounds__(256) void k_plic(const double *__restrict__ cin, const double *__restrict__ s,
                                               const uint32_t *__restrict__ list, const int *__restrict__ counts,
-                                              int64_t nregions, double *__restrict__ fmix, int nx, int ny, int nz) {
+                                              int64_t nregions, double *__restrict__ fmix, int nx, int ny, int nz,
+                                              Divisors dv) {
   const int64_t n3 = (int64_t)nx * ny * nz;
   const int lane = threadIdx.x & 63;
   const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -74,9 +80,13 @@ __global__ __launch_bounds__(256) void k_plic(const double *__restrict__ cin, co
   const uint32_t *reg = list + w * kRegion;
   for (int q = lane; q < nq; q += 64) {
     const uint32_t e = reg[q];
-    const int64_t t = e / n3;
-    const int64_t p = e - t * n3;
-    const int i = (int)(p % nx), j = (int)((p / nx) % ny), k = (int)(p / ((int64_t)nx * ny));
+    const uint32_t t = fast_div(e, dv.n3);
+    const uint32_t p32 = e - t * dv.n3.d;
+    const uint32_t row = fast_div(p32, dv.nx);
+    const int i = (int)(p32 - row * (uint32_t)nx);
+    const uint32_t k32 = fast_div(row, dv.ny);
+    const int j = (int)(row - k32 * (uint32_t)ny), k = (int)k32;
+    const int64_t p = p32;
     const int64_t pu = (D == 0) ? p - i + wrap_inc(i, nx)
                                 : ((D == 1) ? ((int64_t)k * ny + wrap_inc(j, ny)) * nx + i
                                             : ((int64_t)wrap_inc(k, nz) * ny + j) * nx + i);
@@ -106,25 +116,20 @@ __global__ __launch_bounds__(256) void k_plic(const double *__restrict__ cin, co
     const double alpha = plic::alpha_of(mx, my, mz, cd);
     const double md = (D == 0) ? mx : ((D == 1) ? my : mz);
     double *ft = fmix + t * n3;
-    if (s_lo < 0.0) {
-      // lower face: sub-box [0, |s|] along D
-      const double as = alpha - md * 0.0;
-      const double ms = md * fabs(s_lo);
+    // the faces this cell donates through: the lower one (sub-box [0, |s|]
+    // along D) when s < 0 there, the upper one (sub-box [1 - s, 1]) when s > 0
+#pragma unroll 1
+    for (int face = 0; face < 2; ++face) {
+      const double sv = (face == 0) ? s_lo : s_hi;
+      if (face == 0 ? !(sv < 0.0) : !(sv > 0.0)) continue;
+      const double x0 = (face == 0) ? 0.0 : 1.0 - sv;
+      const double as = alpha - md * x0;
+      const double ms = md * fabs(sv);
       double v;
       if (D == 0) v = plic::volume(ms, my, mz, as);
       else if (D == 1) v = plic::volume(mx, ms, mz, as);
       else v = plic::volume(mx, my, ms, as);
-      ft[p] = s_lo * v;
-    }
-    if (s_hi > 0.0) {
-      // upper face: sub-box [1 - s, 1] along D
-      const double as = alpha - md * (1.0 - s_hi);
-      const double ms = md * fabs(s_hi);
-      double v;
-      if (D == 0) v = plic::volume(ms, my, mz, as);
-      else if (D == 1) v = plic::volume(mx, ms, mz, as);
-      else v = plic::volume(mx, my, ms, as);
-      ft[pu] = s_hi * v;
+      ft[face == 0 ? p : pu] = sv * v;
     }
   }
 }
@@ -235,37 +240,54 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ cin, 
     }
   } else {
     // ---- x-sweep: positions are z-planes; faces along x inside the row
+    // each lane forms both of its faces; the neighbours' values come from the
+    // adjacent lanes, except at the two ends of the 64-cell segment
     const int xl = (xs == 0) ? nx - 1 : xs - 1;
+    const int xr = (xs == nx - 1) ? 0 : xs + 1;
     const int x_last = (blockIdx.x * 64 + 63 < nx) ? blockIdx.x * 64 + 63 : nx - 1;
-    const bool is_last = (x == x_last);
-    const int xu = (x_last == nx - 1) ? 0 : x_last + 1;
+    const bool first = (lane == 0);
+    const bool last = (x == x_last);
     for (int m = m0; m < m1; ++m) {
       const int64_t pc = cell(xs, m);
       const int64_t pl = cell(xl, m);
-      const int64_t pu = cell(xu, m);  // upper neighbour of the segment's last cell
+      const int64_t pr = cell(xr, m);
       const int64_t wrow = bitword(m);
       const double s_lo = s[pc];
-      const double s_up = is_last ? s[pu] : 0.0;
-      const double s_hi_sh = __shfl_down(s_lo, 1, 64);
-      const double s_hi = is_last ? s_up : s_hi_sh;
-      double c0[G], cl[G], flo[G], fup[G];
+      double c0[G], cl[G], cr[G];
+#pragma unroll
+      for (int t = 0; t < G; ++t) c0[t] = c_g[t * n3 + pc];
+      double s_end = 0.0, c_beg[G], c_end[G];
 #pragma unroll
       for (int t = 0; t < G; ++t) {
-        c0[t] = c_g[t * n3 + pc];
-        cl[t] = c_g[t * n3 + pl];
+        c_beg[t] = 0.0;
+        c_end[t] = 0.0;
       }
+      if (first) {
+#pragma unroll
+        for (int t = 0; t < G; ++t) c_beg[t] = c_g[t * n3 + pl];
+      }
+      if (last) {
+        s_end = s[pr];
+#pragma unroll
+        for (int t = 0; t < G; ++t) c_end[t] = c_g[t * n3 + pr];
+      }
+      const double s_dn = __shfl_down(s_lo, 1, 64);
+      const double s_hi = last ? s_end : s_dn;
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        const double up = __shfl_up(c0[t], 1, 64);
+        const double dn = __shfl_down(c0[t], 1, 64);
+        cl[t] = first ? c_beg[t] : up;
+        cr[t] = last ? c_end[t] : dn;
+      }
+      double flo[G], fhi[G];
 #pragma unroll
       for (int t = 0; t < G; ++t) {
         flo[t] = flux(t, s_lo, cl[t], c0[t], pc);
-        fup[t] = 0.0;
-        if (is_last) fup[t] = flux(t, s_up, c0[t], c_g[t * n3 + pu], pu);
+        fhi[t] = flux(t, s_hi, c0[t], cr[t], pr);
       }
 #pragma unroll
-      for (int t = 0; t < G; ++t) {
-        const double f_sh = __shfl_down(flo[t], 1, 64);
-        const double f_hi = is_last ? fup[t] : f_sh;
-        finish(t, c0[t], flo[t], f_hi, s_lo, s_hi, pc, wrow);
-      }
+      for (int t = 0; t < G; ++t) finish(t, c0[t], flo[t], fhi[t], s_lo, s_hi, pc, wrow);
     }
   }
   if (lane == 0) counts_next[wave] = nlist;
@@ -339,8 +361,12 @@ static void launch_sweep_axis(const double *cin, double *cout, const double *s, 
                               int nx, int ny, int nz, int ntr, int words, int chunk, hipStream_t stream) {
   const int nxt = cur ^ 1;
   const int64_t nreg = sb.nregions[cur];
+  Divisors dv;
+  dv.n3 = make_fastdiv((uint32_t)((int64_t)nx * ny * nz));
+  dv.nx = make_fastdiv((uint32_t)nx);
+  dv.ny = make_fastdiv((uint32_t)ny);
   hipLaunchKernelGGL((k_plic<D>), dim3(ceil_div(nreg, 4)), dim3(256), 0, stream, cin, s, sb.list[cur],
-                     sb.counts[cur], nreg, sb.fmix, nx, ny, nz);
+                     sb.counts[cur], nreg, sb.fmix, nx, ny, nz, dv);
   const int64_t per = stream_waves(D, nx, ny, nz, chunk);
   int64_t region0 = 0;
   int t = 0;

@@ -59,3 +59,32 @@ __device__ __forceinline__ int wrap_any(int i, int n) {
 }
 
 static inline unsigned ceil_div(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
+// Division of 32-bit unsigned integers by an invariant divisor d >= 1 with a
+// multiply-high, a shift and an add (Granlund & Montgomery 1994, "round-up"
+// variant): exact for every n < 2^32. Built on the host, used in kernels.
+struct FastDiv {
+  uint32_t d, m;
+  int l;
+};
+
+static inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  if (d <= 1) {
+    f.m = 0;
+    f.l = 0;
+    return f;
+  }
+  int l = 0;
+  while ((1ull << l) < d) ++l;  // ceil(log2 d)
+  f.l = l;
+  f.m = (uint32_t)((((unsigned __int128)1 << 32) * (((uint64_t)1 << l) - d)) / d + 1);
+  return f;
+}
+
+__device__ __forceinline__ uint32_t fast_div(uint32_t n, const FastDiv &f) {
+  if (f.d <= 1) return n;
+  const uint32_t hi = __umulhi(n, f.m);
+  return (hi + ((n - hi) >> 1)) >> (f.l - 1);
+}

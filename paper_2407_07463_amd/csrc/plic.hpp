@@ -97,11 +97,13 @@ __device__ __forceinline__ void volume_deriv_sorted(double m1, double m2, double
 }
 
 // Plane constant alpha with volume(m, alpha) = c for 0 < c < 1.
-// The half range c <= 1/2 is solved on the sorted, reflected normal: closed
-// forms where V is a monomial or quadratic in alpha (corner, prism and
-// parallel cases), safeguarded Newton iteration in the two cubic cases, then
-// Newton polishing to the last bits. The result is mapped back through the
-// symmetry and the reflections.
+// The half range v = min(c, 1-c) is solved on the sorted, reflected normal
+// m1 <= m2 <= m3 with den = 6 m2 m3, where 6 m1 m2 m3 V = alpha^3 -
+// sum (alpha - m_i)_+^3 + ...: closed forms where V is a monomial or a
+// quadratic in alpha (corner, prism and parallel cases), otherwise Newton
+// steps on N(alpha) = den V(alpha) (one division per step, reciprocal of m1
+// precomputed), then one Newton polish step on V itself. The result is
+// mapped back through the symmetry and the reflections.
 __device__ __forceinline__ double alpha_of(double mx, double my, double mz, double c) {
   double neg = 0.0;
   if (mx < 0.0) neg += mx;
@@ -109,44 +111,48 @@ __device__ __forceinline__ double alpha_of(double mx, double my, double mz, doub
   if (mz < 0.0) neg += mz;
   double m1 = fabs(mx), m2 = fabs(my), m3 = fabs(mz);
   sort3(m1, m2, m3);
-  double M = (m1 + m2) + m3;
-  bool flip = c > 0.5;
-  double v = flip ? 1.0 - c : c;
+  const double M = (m1 + m2) + m3;
+  const bool flip = c > 0.5;
+  const double v = flip ? 1.0 - c : c;
+  const double den = 6.0 * m2 * m3;
+  const double m12 = m1 + m2;
+  const double vden = v * den;
+  const double base2 = 3.0 * m2 * m2 - 3.0 * m2 * m1 + m1 * m1;  // den * V(m2)
   double a;
-  double v1 = (m1 > 0.0) ? m1 * m1 / (6.0 * m2 * m3) : 0.0;
-  double v2 = (m2 > 0.0) ? (3.0 * m2 * m2 - 3.0 * m2 * m1 + m1 * m1) / (6.0 * m2 * m3) : 0.0;
-  double m12 = m1 + m2;
-  if (v < v1) {
-    a = cbrt(6.0 * m1 * m2 * m3 * v);
-  } else if (v < v2) {
+  if (m1 > 0.0 && vden < m1 * m1) {
+    a = cbrt(vden * m1);
+  } else if (m2 > 0.0 && vden < base2) {
     a = 0.5 * m1 + sqrt(fmax(2.0 * m2 * m3 * v - m1 * m1 / 12.0, 0.0));
-  } else if (m3 >= m12 && v >= m12 / (2.0 * m3)) {
+  } else if (m3 >= m12 && 2.0 * m3 * v >= m12) {
     a = v * m3 + 0.5 * m12;
   } else {
-    // cubic cases: alpha in [m2, M/2]; start from the chord between the
-    // bracket ends (V(m2) = v2, V(M/2) = 1/2) and take safeguarded Newton
-    // steps; V is convex-concave here, so a few steps reach the last bits
+    // cubic cases, alpha in [m2, M/2]: start on the chord between the ends
+    // (den V = base2 at m2, den/2 at M/2) and take Newton steps on den V
+    const double inv1 = 1.0 / m1;
     double lo = m2, hi = 0.5 * M;
-    a = lo + (hi - lo) * ((v - v2) / (0.5 - v2));
-    for (int it = 0; it < 12; ++it) {
-      double V, dV;
-      volume_deriv_sorted(m1, m2, m3, a, V, dV);
-      double f = V - v;
+    a = lo + (hi - lo) * ((vden - base2) / (0.5 * den - base2));
+#pragma unroll 1
+    for (int it = 0; it < 8; ++it) {
+      const double u2 = a - m2;
+      const double u3 = fmax(a - m3, 0.0);
+      const double N = (3.0 * a * a - 3.0 * a * m1 + m1 * m1) - (u2 * u2 * u2 + u3 * u3 * u3) * inv1;
+      const double dN = (6.0 * a - 3.0 * m1) - 3.0 * (u2 * u2 + u3 * u3) * inv1;
+      const double f = N - vden;
       if (f < 0.0) lo = a;
       else hi = a;
-      double an = (dV > 0.0) ? a - f / dV : 0.5 * (lo + hi);
+      double an = (dN > 0.0) ? a - f / dN : 0.5 * (lo + hi);
       if (!(an >= lo && an <= hi)) an = 0.5 * (lo + hi);
       const double step = fabs(an - a);
       a = an;
-      if (step <= 4e-16 * a) break;
+      if (step <= 1e-15 * a) break;
     }
   }
-  // one Newton polish step (the closed forms lose a few bits near case ends)
+  // one Newton polish step on V itself (the closed forms lose bits near case ends)
   {
     double V, dV;
     volume_deriv_sorted(m1, m2, m3, a, V, dV);
     if (dV > 0.0) {
-      double an = a - (V - v) / dV;
+      const double an = a - (V - v) / dV;
       if (an >= 0.0 && an <= 0.5 * M) a = an;
     }
   }
@@ -159,16 +165,18 @@ __device__ __forceinline__ double alpha_of(double mx, double my, double mz, doub
 // L1-normalised. Centred-columns candidates: for each column axis d, column
 // sums H over the 3 cells along d, orientation from the two end layers, the
 // centred slopes g of H along the two transverse axes (in increasing axis
-// order), candidate (sigma, -g1, -g2)/(|g1|+|g2|+1) of quality 1/(|g1|+|g2|+1);
-// the best quality wins (ties to the lower axis). Youngs: weighted central
+// order), candidate (sigma, -g1, -g2)/D of quality 1/D, D = (|g1|+|g2|)+1;
+// the best quality (smallest D) wins, ties to the lower axis, and only that
+// candidate is normalised. Youngs: weighted central
 // differences (weights 1,2,1) of the block. The centred-columns candidate is
 // kept unless Youngs is defined and its largest component is strictly
 // smaller than the centred-columns quality. All sums run in increasing
 // stencil index.
 __device__ __forceinline__ void myc_normal(const double *b, double &nx_, double &ny_, double &nz_) {
 #define B(ax, ay, az) b[((ax) + 1) + 3 * ((ay) + 1) + 9 * ((az) + 1)]
-  double cs[3][3];
-  double q[3];
+  // best centred-columns axis: smallest D = (|g1| + |g2|) + 1, ties to the lower axis
+  int ds = 0;
+  double bD = 0.0, bs = 0.0, bg1 = 0.0, bg2 = 0.0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     double H[3][3];
@@ -185,19 +193,18 @@ __device__ __forceinline__ void myc_normal(const double *b, double &nx_, double 
         slo += e0;
         shi += e2;
       }
-    double sigma = (slo >= shi) ? 1.0 : -1.0;
-    double g1 = (H[2][1] - H[0][1]) / 2.0;
-    double g2 = (H[1][2] - H[1][0]) / 2.0;
-    double D = (fabs(g1) + fabs(g2)) + 1.0;
-    double nd = sigma / D, n1 = -g1 / D, n2 = -g2 / D;
-    if (d == 0) { cs[d][0] = nd; cs[d][1] = n1; cs[d][2] = n2; }
-    else if (d == 1) { cs[d][1] = nd; cs[d][0] = n1; cs[d][2] = n2; }
-    else { cs[d][2] = nd; cs[d][0] = n1; cs[d][1] = n2; }
-    q[d] = 1.0 / D;
+    const double sigma = (slo >= shi) ? 1.0 : -1.0;
+    const double g1 = (H[2][1] - H[0][1]) / 2.0;
+    const double g2 = (H[1][2] - H[1][0]) / 2.0;
+    const double D = (fabs(g1) + fabs(g2)) + 1.0;
+    if (d == 0 || D < bD) {
+      ds = d;
+      bD = D;
+      bs = sigma;
+      bg1 = g1;
+      bg2 = g2;
+    }
   }
-  int ds = 0;
-  if (q[1] > q[ds]) ds = 1;
-  if (q[2] > q[ds]) ds = 2;
   double Gx = 0.0, Gy = 0.0, Gz = 0.0;
   const double w[3] = {1.0, 2.0, 1.0};
 #pragma unroll
@@ -214,10 +221,7 @@ __device__ __forceinline__ void myc_normal(const double *b, double &nx_, double 
     for (int ax = -1; ax <= 1; ++ax) Gz += (w[ax + 1] * w[ay + 1]) * (B(ax, ay, 1) - B(ax, ay, -1));
 #undef B
   double L1 = (fabs(Gx) + fabs(Gy)) + fabs(Gz);
-  double cx = ds == 0 ? cs[0][0] : (ds == 1 ? cs[1][0] : cs[2][0]);
-  double cy = ds == 0 ? cs[0][1] : (ds == 1 ? cs[1][1] : cs[2][1]);
-  double cz = ds == 0 ? cs[0][2] : (ds == 1 ? cs[1][2] : cs[2][2]);
-  double qd = ds == 0 ? q[0] : (ds == 1 ? q[1] : q[2]);
+  const double qd = 1.0 / bD;
   if (L1 > 0.0) {
     double yx = -Gx / L1, yy = -Gy / L1, yz = -Gz / L1;
     double qy = fmax(fmax(fabs(yx), fabs(yy)), fabs(yz));
@@ -228,9 +232,10 @@ __device__ __forceinline__ void myc_normal(const double *b, double &nx_, double 
       return;
     }
   }
-  nx_ = cx;
-  ny_ = cy;
-  nz_ = cz;
+  const double nd = bs / bD, n1 = -bg1 / bD, n2 = -bg2 / bD;
+  if (ds == 0) { nx_ = nd; ny_ = n1; nz_ = n2; }
+  else if (ds == 1) { nx_ = n1; ny_ = nd; nz_ = n2; }
+  else { nx_ = n1; ny_ = n2; nz_ = nd; }
 }
 
 }  // namespace plic
