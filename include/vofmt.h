@@ -186,6 +186,78 @@ int vofmt_nearest_pair_stats(vofmt_ctx *ctx, int32_t n, const double *xyz, const
 int vofmt_curvature_hf(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, const double *c, double *kappa,
                        uint8_t *status, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Learned curvature (not in the paper, which uses height functions): a
+ * multilayer perceptron 27 (zero-padded to 32) -> 128 -> 128 -> 1 with ReLU,
+ * mapping the canonical 3x3x3 stencil of a mixed cell to kappa*Delta.
+ *
+ * Parameters: one FP32 array of VOFMT_MLP_NPARAMS values,
+ *   W1[32][128] (input k, unit j) | b1[128] | W2[128][128] | b2[128] |
+ *   W3[128] | b3 | 3 floats of padding,
+ * owned by the caller, device memory. Arithmetic: weights rounded to BF16
+ * (nearest even) for each use; inputs, activations and upstream gradients
+ * rounded to BF16 before every product; matrix products on the BF16 matrix
+ * cores with FP32 accumulation; biases, loss and Adam in FP32. Every batch
+ * reduction is done in a fixed order, so results are reproducible bit for bit.
+ * ------------------------------------------------------------------------ */
+#define VOFMT_MLP_NPARAMS 20868
+
+/*
+ * Forward pass on m stencils.
+ * x    : [m][27] FP32 canonical stencils, order (ax+1) + 3(ay+1) + 9(az+1).
+ * y    : [m] FP32 output, kappa*Delta of the canonical stencil.
+ * acts : nullable; [m][256] BF16 bit patterns output, the rounded hidden
+ *        activations h1 (first 128) and h2 (last 128) of every sample.
+ * Errors: VOFMT_E_ARG for m < 0 or null pointers (m = 0 is a no-op).
+ */
+int vofmt_mlp_forward(vofmt_ctx *ctx, const float *params, int32_t m, const float *x, float *y, uint16_t *acts,
+                      hipStream_t stream);
+
+/*
+ * One training step on a batch of m stencils: forward, backward and one Adam
+ * step (beta1 0.9, beta2 0.999, eps 1e-8, 1-based step, learning rate lr) on
+ * the FP32 masters params, adam_m, adam_v (all VOFMT_MLP_NPARAMS, updated in
+ * place). Loss: mean over the batch of (y - t)^2 / max(|t|, 0.05)^2.
+ * y_target : [m] FP32 target kappa*Delta of the canonical stencils.
+ * grads    : nullable; [VOFMT_MLP_NPARAMS] FP32 output, the batch gradient.
+ * trace    : nullable; [m][512] BF16 bit patterns output per sample: h1, h2,
+ *            dL/dz2 and dL/dz1 as rounded for the products (128 each).
+ * loss_host: HOST output, the batch loss before the update (synchronises).
+ * Errors: VOFMT_E_ARG for m < 1, step < 1, lr < 0 or null pointers.
+ */
+int vofmt_mlp_train_step(vofmt_ctx *ctx, float *params, float *adam_m, float *adam_v, int32_t step, float lr,
+                         int32_t m, const float *x, const float *y_target, float *grads, uint16_t *trace,
+                         float *loss_host, hipStream_t stream);
+
+/*
+ * Canonical stencils of the mixed cells (0 < c < 1) of one field, in
+ * increasing linear cell order. Canonicalisation over the 48 symmetries of
+ * the cube: reflect the axes along which the Mixed-Youngs-Centred normal is
+ * negative, order the axes by increasing |m_d| (ties: lower axis first), and
+ * when the centre exceeds 1/2 replace c by 1 - c (sign -1: the curvature
+ * changes sign). Periodic neighbours.
+ * c          : [nz][ny][nx] FP64, one tracer.
+ * capacity   : length of the outputs; VOFMT_E_ARG if fewer than the mixed cells.
+ * xs         : [capacity][27] FP32 output. cell: [capacity] int32 linear cell
+ *              index. sign: [capacity] int8, +1 or -1.
+ * count_host : HOST output, the number of mixed cells (synchronises).
+ */
+int vofmt_mlp_stencils(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, const double *c, int32_t capacity,
+                       float *xs, int32_t *cell, int8_t *sign, int32_t *count_host, hipStream_t stream);
+
+/*
+ * Curvature of one tracer by the network with height functions as the
+ * fallback: height functions first (as vofmt_curvature_hf); then for every
+ * mixed cell kappa = sign * MLP(canonical stencil) replaces the height-function
+ * value unless that value is valid and |kappa_mlp| < kappa_lo (radii the
+ * 3x3x3 stencil cannot resolve). status: the height-function status, plus 8
+ * where the network's value is used.
+ * nmixed_host: nullable HOST output, the number of mixed cells (the call
+ *              synchronises once to size its work).
+ */
+int vofmt_curvature_mlp(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, const double *c, const float *params,
+                        double kappa_lo, double *kappa, uint8_t *status, int32_t *nmixed_host, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -238,5 +238,107 @@ def curvature_hf(c):
     return kappa, status
 
 
+# ---------------------------------------------------------------- learned curvature
+# Not in the paper (it uses height functions); the reference arithmetic of the
+# network is in mlp_oracle.c.
+
+MLP_NPARAMS = 20868
+MLP_OFF = dict(W1=0, b1=4096, W2=4224, b2=20608, W3=20736, b3=20864)
+
+
 def _setup_mlp(L):
-    pass
+    vp, i32 = ctypes.c_void_p, ctypes.c_int
+    L.orc_mlp_nparams.argtypes = []
+    L.orc_mlp_nparams.restype = i32
+    L.orc_bf16.argtypes = [ctypes.c_float]
+    L.orc_bf16.restype = ctypes.c_float
+    L.orc_canonical_stencil.argtypes = [vp, vp]
+    L.orc_canonical_stencil.restype = i32
+    L.orc_mlp_forward.argtypes = [vp, i32, vp, i32, vp, vp]
+    L.orc_mlp_forward.restype = None
+    L.orc_mlp_grad.argtypes = [vp, i32, vp, vp, i32, vp]
+    L.orc_mlp_grad.restype = ctypes.c_double
+    L.orc_adam.argtypes = [vp, vp, vp, vp, i32, ctypes.c_double]
+    L.orc_adam.restype = None
+    L.orc_mlp_layer.argtypes = [vp, i32, i32, vp, i32, vp, vp, vp]
+    L.orc_mlp_layer.restype = None
+    L.orc_mlp_backward_given.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp]
+    L.orc_mlp_backward_given.restype = None
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def bf16(v) -> np.ndarray:
+    """FP32 -> BF16 -> FP32 with round to nearest even, elementwise."""
+    v = _f32(v)
+    f = lib().orc_bf16
+    return np.array([f(float(t)) for t in v.ravel()], dtype=np.float32).reshape(v.shape)
+
+
+def canonical_stencil(block) -> tuple[np.ndarray, int]:
+    """Canonical form of a 3x3x3 block b[az][ay][ax] -> (27 FP32, sign)."""
+    b = _f64(block).reshape(27)
+    out = np.zeros(27, dtype=np.float32)
+    s = lib().orc_canonical_stencil(b.ctypes.data, out.ctypes.data)
+    return out, int(s)
+
+
+def mlp_forward(params, x, exact: bool = False):
+    """Network output (FP64) and activations [n][512] = h1, h2, z1, z2."""
+    P, x = _f32(params), _f32(x).reshape(-1, 27)
+    n = x.shape[0]
+    y = np.zeros(n)
+    acts = np.zeros((n, 512))
+    lib().orc_mlp_forward(P.ctypes.data, n, x.ctypes.data, int(exact), y.ctypes.data, acts.ctypes.data)
+    return y, acts
+
+
+def mlp_grad(params, x, t, exact: bool = False):
+    """Batch loss and its gradient (FP64) with respect to every parameter."""
+    P, x, t = _f32(params), _f32(x).reshape(-1, 27), _f32(t)
+    g = np.zeros(MLP_NPARAMS)
+    loss = lib().orc_mlp_grad(P.ctypes.data, x.shape[0], x.ctypes.data, t.ctypes.data, int(exact), g.ctypes.data)
+    return loss, g
+
+
+def adam(params, m, v, grad, step: int, lr: float):
+    """One Adam step in FP64 on FP32 copies; returns (params, m, v)."""
+    P, M, V = _f32(params).copy(), _f32(m).copy(), _f32(v).copy()
+    g = _f64(grad)
+    lib().orc_adam(P.ctypes.data, M.ctypes.data, V.ctypes.data, g.ctypes.data, int(step), float(lr))
+    return P, M, V
+
+
+def mlp_layer(params, layer: int, inp, exact: bool = False):
+    """One layer on supplied inputs -> (pre, act, absacc)."""
+    P = _f32(params)
+    nin = 27 if layer == 1 else 128
+    inp = _f64(inp).reshape(-1, nin)
+    n = inp.shape[0]
+    nout = 1 if layer == 3 else 128
+    pre, act, aab = np.zeros((n, nout)), np.zeros((n, nout)), np.zeros((n, nout))
+    lib().orc_mlp_layer(P.ctypes.data, int(layer), n, inp.ctypes.data, int(exact), pre.ctypes.data,
+                        act.ctypes.data, aab.ctypes.data)
+    if layer == 3:
+        return pre[:, 0], act[:, 0], aab[:, 0]
+    return pre, act, aab
+
+
+def mlp_backward_given(params, x, g, h1, h2, dz2, dz1, exact: bool = False):
+    """Backward pass on supplied intermediates -> dict(dz2, dz1, dz1_abs, grad, grad_abs)."""
+    P, x = _f32(params), _f32(x).reshape(-1, 27)
+    n = x.shape[0]
+    g, h1, h2, dz2, dz1 = (_f64(a) for a in (g, h1, h2, dz2, dz1))
+    out = dict(dz2=np.zeros((n, 128)), dz1=np.zeros((n, 128)), dz1_abs=np.zeros((n, 128)),
+               grad=np.zeros(MLP_NPARAMS), grad_abs=np.zeros(MLP_NPARAMS))
+    lib().orc_mlp_backward_given(P.ctypes.data, n, x.ctypes.data, g.ctypes.data, h1.ctypes.data, h2.ctypes.data,
+                                 dz2.ctypes.data, dz1.ctypes.data, int(exact), out["dz2"].ctypes.data,
+                                 out["dz1"].ctypes.data, out["dz1_abs"].ctypes.data, out["grad"].ctypes.data,
+                                 out["grad_abs"].ctypes.data)
+    return out

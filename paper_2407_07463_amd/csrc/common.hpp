@@ -14,8 +14,8 @@ struct vofmt_ctx {
   int device = 0;
   std::string err;
   // Scratch buffers, grown on demand (never shrunk) and reused by later calls.
-  void *buf[16] = {};
-  size_t cap[16] = {};
+  void *buf[24] = {};
+  size_t cap[24] = {};
   // Pinned host staging for small results read back by synchronising calls.
   void *host = nullptr;
   size_t host_cap = 0;
@@ -34,7 +34,14 @@ enum ScratchSlot {
   SLOT_FMIX = 8,     // fluxes of the faces with a mixed donor
   SLOT_MIXLIST = 9,  // two lists of mixed cells (input / output of a sweep)
   SLOT_COUNTS = 10,  // their lengths
-  kNumSlots = 16,
+  SLOT_MLP_W = 11,     // BF16 copies of the network weights
+  SLOT_MLP_ACTS = 12,  // activations kept for the backward pass
+  SLOT_MLP_G = 13,     // upstream gradients and per-tile losses
+  SLOT_MLP_PART = 14,  // per-tile partial gradients
+  SLOT_MLP_X = 15,     // canonical stencils, network outputs
+  SLOT_MLP_CELL = 16,  // their cells
+  SLOT_MLP_SIGN = 17,  // and orientation signs
+  kNumSlots = 24,
 };
 
 int set_err(vofmt_ctx *ctx, int code, const char *fmt, ...);

@@ -1,0 +1,606 @@
+// Learned curvature: a multilayer perceptron 27 (zero-padded to 32) -> 128
+// -> 128 -> 1 with ReLU on canonicalised 3x3x3 volume-fraction stencils,
+// predicting kappa*Delta; its training step (forward, backward, Adam); and
+// curvature that uses it with height functions as the fallback.
+//
+// The paper computes curvature with the single-tracer method (height
+// functions); the network is an addition of this library. Arithmetic:
+// weights are FP32 masters rounded to BF16 (round to nearest even) for each
+// use; inputs, activations and upstream gradients are rounded to BF16 before
+// every product; all products run on the matrix cores
+// (v_mfma_f32_16x16x32_bf16) with FP32 accumulation; biases, loss and Adam in
+// FP32. ReLU'(z) is (activation > 0) on the rounded activation. Reductions
+// over the batch go through per-tile partial sums added in a fixed order, so
+// every result is reproducible bit for bit.
+//
+// MFMA fragment layout (16x16x32, one wavefront): lane l holds
+//   A[l%16][8*(l/16) + e], B[8*(l/16) + e][l%16] for e = 0..7 (bf16), and
+//   D[4*(l/16) + r][l%16] for r = 0..3 (fp32).
+#include <cstring>
+
+#include "common.hpp"
+#include "plic.hpp"
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int NIN = 32, NH = 128;
+constexpr int OFF_W1 = 0, OFF_B1 = NIN * NH, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH, OFF_W3 = OFF_B2 + NH,
+              OFF_B3 = OFF_W3 + NH, NPARAMS = OFF_B3 + 4;
+static_assert(NPARAMS == VOFMT_MLP_NPARAMS, "parameter layout");
+
+constexpr int TILE = 64;  // samples per tile
+constexpr int XP = 40;    // LDS row pitches (bf16 elements), padded against bank conflicts
+constexpr int HP = 136;
+constexpr int TP = 72;
+
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// 8 consecutive bf16 (16 bytes, 16-byte aligned) as an MFMA operand
+__device__ __forceinline__ bf16x8 frag(const uint16_t *p) {
+  const uint4 v = *reinterpret_cast<const uint4 *>(p);
+  bf16x8 r;
+  memcpy(&r, &v, 16);
+  return r;
+}
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// BF16 copies of the weights for one call: W1^T [128][32], W2^T [128][128],
+// W2 [128][128] (for the backward product), W3 [128].
+__global__ void k_mlp_prep(const float *__restrict__ P, uint16_t *__restrict__ w1t, uint16_t *__restrict__ w2t,
+                           uint16_t *__restrict__ w2n, uint16_t *__restrict__ w3) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < NIN * NH) {
+    const int k = i / NH, j = i % NH;
+    w1t[j * NIN + k] = bf16_bits(P[OFF_W1 + i]);
+  }
+  if (i < NH * NH) {
+    const int k = i / NH, j = i % NH;
+    const uint16_t b = bf16_bits(P[OFF_W2 + i]);
+    w2t[j * NH + k] = b;
+    w2n[i] = b;
+  }
+  if (i < NH) w3[i] = bf16_bits(P[OFF_W3 + i]);
+}
+
+// Forward pass, persistent over 64-sample tiles. With a target, also the
+// upstream gradient g = dL/dy of every sample and the loss of every tile.
+__global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ P, const uint16_t *__restrict__ w1t_g,
+                                                 const uint16_t *__restrict__ w2t_g, const uint16_t *__restrict__ w3_g,
+                                                 int m, const float *__restrict__ x, float *__restrict__ y,
+                                                 uint16_t *__restrict__ acts, const float *__restrict__ tgt,
+                                                 float *__restrict__ g_out, float *__restrict__ loss_part) {
+  __shared__ __attribute__((aligned(16))) uint16_t W1s[NH][XP];
+  __shared__ __attribute__((aligned(16))) uint16_t W2s[NH][HP];
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[TILE][XP];
+  __shared__ __attribute__((aligned(16))) uint16_t H1s[TILE][HP];
+  __shared__ float b1s[NH], b2s[NH], w3s[NH];
+  __shared__ float ypart[4][TILE];
+  __shared__ float lpart[TILE];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int i = tid; i < NH * NIN; i += 256) W1s[i / NIN][i % NIN] = w1t_g[i];
+  for (int i = tid; i < NH * NH; i += 256) W2s[i / NH][i % NH] = w2t_g[i];
+  for (int i = tid; i < NH; i += 256) {
+    b1s[i] = P[OFF_B1 + i];
+    b2s[i] = P[OFF_B2 + i];
+    w3s[i] = bf16_val(w3_g[i]);
+  }
+  const float b3 = P[OFF_B3];
+  const int ntiles = (m + TILE - 1) / TILE;
+  const int lr = lane & 15, lq = lane >> 4;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int s0 = tile * TILE;
+    __syncthreads();
+    for (int i = tid; i < TILE * NIN; i += 256) {
+      const int s = i / NIN, k = i % NIN;
+      const float v = (k < 27 && s0 + s < m) ? x[(int64_t)(s0 + s) * 27 + k] : 0.0f;
+      Xs[s][k] = bf16_bits(v);
+    }
+    __syncthreads();
+    // layer 1: wave w owns output columns [32w, 32w+32)
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int jn = 0; jn < 2; ++jn) {
+        const int nt = 2 * w + jn;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mfma(frag(&Xs[16 * mt + lr][8 * lq]), frag(&W1s[16 * nt + lr][8 * lq]), acc);
+        const int col = 16 * nt + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * mt + 4 * lq + r;
+          const float z = acc[r] + b1s[col];
+          const uint16_t h = bf16_bits(z > 0.0f ? z : 0.0f);
+          H1s[row][col] = h;
+          if (acts && s0 + row < m) acts[(int64_t)(s0 + row) * 256 + col] = h;
+        }
+      }
+    __syncthreads();
+    // layer 2 and the layer-3 partial products
+    float yp[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) yp[mt][r] = 0.0f;
+#pragma unroll
+    for (int jn = 0; jn < 2; ++jn) {
+      const int nt = 2 * w + jn;
+      const int col = 16 * nt + lr;
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < NH; kk += 32)
+          acc = mfma(frag(&H1s[16 * mt + lr][kk + 8 * lq]), frag(&W2s[16 * nt + lr][kk + 8 * lq]), acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * mt + 4 * lq + r;
+          const float z = acc[r] + b2s[col];
+          const uint16_t h = bf16_bits(z > 0.0f ? z : 0.0f);
+          if (acts && s0 + row < m) acts[(int64_t)(s0 + row) * 256 + NH + col] = h;
+          yp[mt][r] = yp[mt][r] + bf16_val(h) * w3s[col];
+        }
+      }
+    }
+    // sum the 16 columns of each row across lanes (fixed tree)
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float v = yp[mt][r];
+        v = v + __shfl_xor(v, 8, 64);
+        v = v + __shfl_xor(v, 4, 64);
+        v = v + __shfl_xor(v, 2, 64);
+        v = v + __shfl_xor(v, 1, 64);
+        if (lr == 0) ypart[w][16 * mt + 4 * lq + r] = v;
+      }
+    __syncthreads();
+    if (tid < TILE) {
+      const int s = s0 + tid;
+      float lv = 0.0f;
+      if (s < m) {
+        const float yy = (((ypart[0][tid] + ypart[1][tid]) + ypart[2][tid]) + ypart[3][tid]) + b3;
+        if (y) y[s] = yy;
+        if (tgt) {
+          const float t = tgt[s];
+          const float a = fabsf(t) > 0.05f ? fabsf(t) : 0.05f;
+          const float wgt = 1.0f / (a * a);
+          const float d = yy - t;
+          lv = (d * d) * wgt;
+          g_out[s] = ((2.0f * d) * wgt) / (float)m;
+        }
+      }
+      lpart[tid] = lv;
+    }
+    if (tgt) {
+      __syncthreads();
+      if (tid == 0) {
+        float acc = 0.0f;
+        for (int i = 0; i < TILE; ++i) acc += lpart[i];
+        loss_part[tile] = acc;
+      }
+    }
+  }
+}
+
+// Backward pass of one 64-sample tile: per-tile partial gradients of every
+// parameter (added later in a fixed order).
+__global__ __launch_bounds__(256) void k_mlp_bwd(const uint16_t *__restrict__ w2n_g, const uint16_t *__restrict__ w3_g,
+                                                 int m, const float *__restrict__ x,
+                                                 const uint16_t *__restrict__ acts, const float *__restrict__ g,
+                                                 float *__restrict__ partial, uint16_t *__restrict__ trace) {
+  __shared__ __attribute__((aligned(16))) uint16_t XT[NIN][TP];
+  __shared__ __attribute__((aligned(16))) uint16_t H1T[NH][TP];
+  __shared__ __attribute__((aligned(16))) uint16_t D2[TILE][HP];
+  __shared__ __attribute__((aligned(16))) uint16_t D2T[NH][TP];
+  __shared__ __attribute__((aligned(16))) uint16_t D1T[NH][TP];
+  __shared__ float gs[TILE];
+  __shared__ float w3s[NH];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int tile = blockIdx.x, s0 = tile * TILE;
+  float *part = partial + (int64_t)tile * NPARAMS;
+  if (tid < TILE) gs[tid] = (s0 + tid < m) ? g[s0 + tid] : 0.0f;
+  if (tid < NH) w3s[tid] = bf16_val(w3_g[tid]);
+  for (int i = tid; i < TILE * NIN; i += 256) {
+    const int s = i / NIN, k = i % NIN;
+    const float v = (k < 27 && s0 + s < m) ? x[(int64_t)(s0 + s) * 27 + k] : 0.0f;
+    XT[k][s] = bf16_bits(v);
+  }
+  for (int i = tid; i < TILE * NH; i += 256) {
+    const int s = i / NH, k = i % NH;
+    H1T[k][s] = (s0 + s < m) ? acts[(int64_t)(s0 + s) * 256 + k] : (uint16_t)0;
+  }
+  __syncthreads();
+  // dZ2 = bf16((h2 > 0) * g * W3)
+  for (int i = tid; i < TILE * NH; i += 256) {
+    const int s = i / NH, k = i % NH;
+    const uint16_t h2 = (s0 + s < m) ? acts[(int64_t)(s0 + s) * 256 + NH + k] : (uint16_t)0;
+    const float d = (bf16_val(h2) > 0.0f) ? gs[s] * w3s[k] : 0.0f;
+    const uint16_t b = bf16_bits(d);
+    D2[s][k] = b;
+    D2T[k][s] = b;
+    if (trace && s0 + s < m) trace[(int64_t)(s0 + s) * 512 + 2 * NH + k] = b;
+  }
+  __syncthreads();
+  // dH1 = dZ2 . W2^T; dZ1 = bf16((h1 > 0) * dH1); wave w owns hidden units [32w, 32w+32)
+#pragma unroll
+  for (int jn = 0; jn < 2; ++jn) {
+    const int nt = 2 * w + jn;
+    const int col = 16 * nt + lr;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < NH; kk += 32)
+        acc = mfma(frag(&D2[16 * mt + lr][kk + 8 * lq]), frag(&w2n_g[(16 * nt + lr) * NH + kk + 8 * lq]), acc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * mt + 4 * lq + r;
+        const float h1 = bf16_val(H1T[col][row]);
+        const uint16_t b = bf16_bits(h1 > 0.0f ? acc[r] : 0.0f);
+        D1T[col][row] = b;
+        if (trace && s0 + row < m) trace[(int64_t)(s0 + row) * 512 + 3 * NH + col] = b;
+      }
+    }
+  }
+  __syncthreads();
+  // dW2 = H1^T . dZ2 (128 x 128, K = 64 samples)
+#pragma unroll
+  for (int jn = 0; jn < 2; ++jn) {
+    const int nt = 2 * w + jn;
+    const int col = 16 * nt + lr;
+    for (int mt = 0; mt < 8; ++mt) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < TILE; kk += 32)
+        acc = mfma(frag(&H1T[16 * mt + lr][kk + 8 * lq]), frag(&D2T[16 * nt + lr][kk + 8 * lq]), acc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) part[OFF_W2 + (16 * mt + 4 * lq + r) * NH + col] = acc[r];
+    }
+  }
+  // dW1 = X^T . dZ1 (32 x 128, K = 64 samples)
+#pragma unroll
+  for (int jn = 0; jn < 2; ++jn) {
+    const int nt = 2 * w + jn;
+    const int col = 16 * nt + lr;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < TILE; kk += 32)
+        acc = mfma(frag(&XT[16 * mt + lr][kk + 8 * lq]), frag(&D1T[16 * nt + lr][kk + 8 * lq]), acc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) part[OFF_W1 + (16 * mt + 4 * lq + r) * NH + col] = acc[r];
+    }
+  }
+  // dW3, the biases, and the padding, as sequential FP32 sums over the tile
+  if (tid < NH) {
+    const int k = tid;
+    float a3 = 0.0f, a2 = 0.0f, a1 = 0.0f;
+    for (int s = 0; s < TILE; ++s) {
+      const uint16_t h2 = (s0 + s < m) ? acts[(int64_t)(s0 + s) * 256 + NH + k] : (uint16_t)0;
+      a3 = a3 + gs[s] * bf16_val(h2);
+      a2 = a2 + bf16_val(D2T[k][s]);
+      a1 = a1 + bf16_val(D1T[k][s]);
+    }
+    part[OFF_W3 + k] = a3;
+    part[OFF_B2 + k] = a2;
+    part[OFF_B1 + k] = a1;
+  } else if (tid == NH) {
+    float a = 0.0f;
+    for (int s = 0; s < TILE; ++s) a = a + gs[s];
+    part[OFF_B3] = a;
+    part[OFF_B3 + 1] = 0.0f;
+    part[OFF_B3 + 2] = 0.0f;
+    part[OFF_B3 + 3] = 0.0f;
+  }
+  if (trace) {
+    for (int i = tid; i < TILE * 2 * NH; i += 256) {
+      const int s = i / (2 * NH), k = i % (2 * NH);
+      if (s0 + s < m) trace[(int64_t)(s0 + s) * 512 + k] = acts[(int64_t)(s0 + s) * 256 + k];
+    }
+  }
+}
+
+// Gradient = fixed-order sum of the tile partials; Adam on the FP32 masters.
+__global__ __launch_bounds__(256) void k_mlp_adam(float *__restrict__ P, float *__restrict__ Mo,
+                                                  float *__restrict__ Vo, const float *__restrict__ partial, int ntiles,
+                                                  int step, float lrate, float *__restrict__ grads,
+                                                  const float *__restrict__ loss_part, float *__restrict__ loss_out,
+                                                  int m) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < NPARAMS) {
+    float gsum = 0.0f;
+    for (int t = 0; t < ntiles; ++t) gsum = gsum + partial[(int64_t)t * NPARAMS + i];
+    if (grads) grads[i] = gsum;
+    const float mm = 0.9f * Mo[i] + 0.1f * gsum;
+    const float vv = 0.999f * Vo[i] + 0.001f * (gsum * gsum);
+    Mo[i] = mm;
+    Vo[i] = vv;
+    // bias corrections 1 - beta^step, in FP64 so that small steps lose nothing
+    const float c1 = (float)(1.0 - pow(0.9, (double)step)), c2 = (float)(1.0 - pow(0.999, (double)step));
+    P[i] = P[i] - lrate * (mm / c1) / (sqrtf(vv / c2) + 1e-8f);
+  }
+  if (i == 0) {
+    float l = 0.0f;
+    for (int t = 0; t < ntiles; ++t) l = l + loss_part[t];
+    loss_out[0] = l / (float)m;
+  }
+}
+
+// ------------------------------------------------------------ stencils
+
+// Canonical stencil of the cell (i, j, k), over the 48 symmetries of the
+// cube and the exchange of the phases: when the centre exceeds 1/2 replace c
+// by 1 - c (sign -1: the curvature changes sign); then reflect the axes along
+// which the MYC normal of that block is negative and order the axes by
+// increasing |m| (ties: lower axis first). Every canonical stencil has its
+// centre at most 1/2 and a normal with non-negative ascending components.
+__device__ int canonical_stencil(const double *__restrict__ c, int i, int j, int k, int nx, int ny, int nz,
+                                 float *out) {
+  double b[27];
+  const int xs[3] = {wrap_dec(i, nx), i, wrap_inc(i, nx)};
+  const int ys[3] = {wrap_dec(j, ny), j, wrap_inc(j, ny)};
+  const int zs[3] = {wrap_dec(k, nz), k, wrap_inc(k, nz)};
+  for (int az = 0; az < 3; ++az)
+    for (int ay = 0; ay < 3; ++ay)
+      for (int ax = 0; ax < 3; ++ax) b[ax + 3 * ay + 9 * az] = c[((int64_t)zs[az] * ny + ys[ay]) * nx + xs[ax]];
+  const int sign = (b[13] > 0.5) ? -1 : 1;
+  if (sign < 0)
+    for (int q = 0; q < 27; ++q) b[q] = 1.0 - b[q];
+  double m[3];
+  plic::myc_normal(b, m[0], m[1], m[2]);
+  int ord[3] = {0, 1, 2};
+  for (int a = 0; a < 3; ++a)
+    for (int bb = a + 1; bb < 3; ++bb)
+      if (fabs(m[ord[bb]]) < fabs(m[ord[a]]) || (fabs(m[ord[bb]]) == fabs(m[ord[a]]) && ord[bb] < ord[a])) {
+        const int t = ord[a];
+        ord[a] = ord[bb];
+        ord[bb] = t;
+      }
+  // per canonical axis: stride in b and direction
+  int st[3], dir[3];
+  const int stride[3] = {1, 3, 9};
+  for (int kk = 0; kk < 3; ++kk) {
+    st[kk] = stride[ord[kk]];
+    dir[kk] = (m[ord[kk]] < 0.0) ? -1 : 1;
+  }
+  for (int q2 = -1; q2 <= 1; ++q2)
+    for (int q1 = -1; q1 <= 1; ++q1)
+      for (int q0 = -1; q0 <= 1; ++q0)
+        out[(q0 + 1) + 3 * (q1 + 1) + 9 * (q2 + 1)] =
+            (float)b[13 + dir[0] * q0 * st[0] + dir[1] * q1 * st[1] + dir[2] * q2 * st[2]];
+  return sign;
+}
+
+__global__ __launch_bounds__(256) void k_count_mixed(const double *__restrict__ c, int64_t n3, int *__restrict__ count) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool mixed = p < n3 && c[p] > 0.0 && c[p] < 1.0;
+  const uint64_t mask = __ballot(mixed);
+  if ((threadIdx.x & 63) == 0 && mask) atomicAdd(count, (int)__popcll(mask));
+}
+
+// Mixed cells in increasing linear index: block b writes from offset base[b].
+__global__ __launch_bounds__(256) void k_block_mixed(const double *__restrict__ c, int64_t n3, int *__restrict__ bc) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool mixed = p < n3 && c[p] > 0.0 && c[p] < 1.0;
+  __shared__ int wc[4];
+  const uint64_t mask = __ballot(mixed);
+  if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = (int)__popcll(mask);
+  __syncthreads();
+  if (threadIdx.x == 0) bc[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_exclusive(int *__restrict__ v, int64_t n) {
+  __shared__ int64_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t lo = t * per, hi = (lo + per < n) ? lo + per : n;
+  int64_t s = 0;
+  for (int64_t i = lo; i < hi; ++i) s += v[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int64_t add = (t >= off) ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
+  }
+  int64_t run = (t == 0) ? 0 : part[t - 1];
+  for (int64_t i = lo; i < hi; ++i) {
+    const int x = v[i];
+    v[i] = (int)run;
+    run += x;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_stencils(const double *__restrict__ c, int nx, int ny, int nz,
+                                                  const int *__restrict__ base, float *__restrict__ xs,
+                                                  int32_t *__restrict__ cell, int8_t *__restrict__ sgn) {
+  const int64_t n3 = (int64_t)nx * ny * nz;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool mixed = p < n3 && c[p] > 0.0 && c[p] < 1.0;
+  __shared__ int wc[4];
+  const uint64_t mask = __ballot(mixed);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) wc[w] = (int)__popcll(mask);
+  __syncthreads();
+  if (!mixed) return;
+  int idx = base[blockIdx.x];
+  for (int k = 0; k < w; ++k) idx += wc[k];
+  idx += (int)__popcll(mask & ((1ull << lane) - 1));
+  const int i = (int)(p % nx), j = (int)((p / nx) % ny), k = (int)(p / ((int64_t)nx * ny));
+  float out[27];
+  const int sg = canonical_stencil(c, i, j, k, nx, ny, nz, out);
+  for (int q = 0; q < 27; ++q) xs[(int64_t)idx * 27 + q] = out[q];
+  cell[idx] = (int32_t)p;
+  sgn[idx] = (int8_t)sg;
+}
+
+// Learned curvature with the height-function fallback: the network's value
+// unless the height function is valid and |kappa_net| < kappa_lo (large
+// radii, which a 3x3x3 stencil cannot resolve). status = HF status, +8 when
+// the network's value is used.
+__global__ __launch_bounds__(256) void k_curv_combine(const float *__restrict__ y, const int32_t *__restrict__ cell,
+                                                      const int8_t *__restrict__ sgn, int nm, double kappa_lo,
+                                                      double *__restrict__ kappa, uint8_t *__restrict__ status) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nm) return;
+  const int32_t p = cell[q];
+  const double kn = (double)sgn[q] * (double)y[q];
+  const uint8_t st = status[p];
+  const bool hf_ok = st >= 1 && st <= 3;
+  if (hf_ok && fabs(kn) < kappa_lo) return;  // keep the height-function value
+  kappa[p] = kn;
+  status[p] = (uint8_t)(st | 8);
+}
+
+}  // namespace
+
+static int mlp_prepare(vofmt_ctx *ctx, const float *params, uint16_t **w, hipStream_t stream) {
+  uint16_t *buf = (uint16_t *)scratch(ctx, SLOT_MLP_W, sizeof(uint16_t) * (NIN * NH + 2 * NH * NH + NH));
+  if (!buf) return VOFMT_E_NOMEM;
+  w[0] = buf;                       // W1^T
+  w[1] = buf + NIN * NH;            // W2^T
+  w[2] = buf + NIN * NH + NH * NH;  // W2
+  w[3] = buf + NIN * NH + 2 * NH * NH;
+  hipLaunchKernelGGL(k_mlp_prep, dim3(ceil_div(NH * NH, 256)), dim3(256), 0, stream, params, w[0], w[1], w[2], w[3]);
+  return hip_check(ctx, hipGetLastError(), "k_mlp_prep");
+}
+
+static int fwd_grid(vofmt_ctx *ctx, int ntiles) {
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
+    cus = 256;
+  const int g = 2 * cus;  // two 70 KB-LDS workgroups fit one compute unit
+  return ntiles < g ? ntiles : g;
+}
+
+extern "C" int vofmt_mlp_forward(vofmt_ctx *ctx, const float *params, int32_t m, const float *x, float *y,
+                                 uint16_t *acts, hipStream_t stream) {
+  if (!ctx) return VOFMT_E_ARG;
+  if (m < 0 || !params || (m > 0 && (!x || !y)))
+    return set_err(ctx, VOFMT_E_ARG, "vofmt_mlp_forward: bad arguments");
+  if (m == 0) return VOFMT_OK;
+  VOFMT_HIP(ctx, hipSetDevice(ctx->device));
+  uint16_t *w[4];
+  int rc = mlp_prepare(ctx, params, w, stream);
+  if (rc) return rc;
+  const int ntiles = (m + TILE - 1) / TILE;
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(fwd_grid(ctx, ntiles)), dim3(256), 0, stream, params, w[0], w[1], w[3], m, x, y,
+                     acts, (const float *)nullptr, (float *)nullptr, (float *)nullptr);
+  return hip_check(ctx, hipGetLastError(), "k_mlp_fwd");
+}
+
+extern "C" int vofmt_mlp_train_step(vofmt_ctx *ctx, float *params, float *adam_m, float *adam_v, int32_t step,
+                                    float lr, int32_t m, const float *x, const float *y_target, float *grads,
+                                    uint16_t *trace, float *loss_host, hipStream_t stream) {
+  if (!ctx) return VOFMT_E_ARG;
+  if (m < 1 || step < 1 || !params || !adam_m || !adam_v || !x || !y_target || !loss_host || !(lr >= 0.0f))
+    return set_err(ctx, VOFMT_E_ARG, "vofmt_mlp_train_step: bad arguments");
+  VOFMT_HIP(ctx, hipSetDevice(ctx->device));
+  uint16_t *w[4];
+  int rc = mlp_prepare(ctx, params, w, stream);
+  if (rc) return rc;
+  const int ntiles = (m + TILE - 1) / TILE;
+  uint16_t *acts = (uint16_t *)scratch(ctx, SLOT_MLP_ACTS, sizeof(uint16_t) * 256 * (size_t)m);
+  float *gbuf = (float *)scratch(ctx, SLOT_MLP_G, sizeof(float) * ((size_t)m + (size_t)ntiles + 4));
+  float *partial = (float *)scratch(ctx, SLOT_MLP_PART, sizeof(float) * (size_t)ntiles * NPARAMS);
+  float *hl = (float *)host_scratch(ctx, sizeof(float) * 4);
+  if (!acts || !gbuf || !partial || !hl) return VOFMT_E_NOMEM;
+  float *loss_part = gbuf + m;
+  float *loss_out = gbuf + m + ntiles;
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(fwd_grid(ctx, ntiles)), dim3(256), 0, stream, params, w[0], w[1], w[3], m, x,
+                     (float *)nullptr, acts, y_target, gbuf, loss_part);
+  hipLaunchKernelGGL(k_mlp_bwd, dim3(ntiles), dim3(256), 0, stream, w[2], w[3], m, x, acts, gbuf, partial, trace);
+  hipLaunchKernelGGL(k_mlp_adam, dim3(ceil_div(NPARAMS, 256)), dim3(256), 0, stream, params, adam_m, adam_v, partial,
+                     ntiles, step, lr, grads, loss_part, loss_out, m);
+  VOFMT_HIP(ctx, hipGetLastError());
+  VOFMT_HIP(ctx, hipMemcpyAsync(hl, loss_out, sizeof(float), hipMemcpyDeviceToHost, stream));
+  VOFMT_HIP(ctx, hipStreamSynchronize(stream));
+  *loss_host = hl[0];
+  return VOFMT_OK;
+}
+
+// Canonical stencils of the mixed cells (0 < c < 1) of one field, in
+// increasing cell order. Writes at most `capacity` entries; *count_host gets
+// the number of mixed cells (synchronises). xs: [capacity][27] FP32.
+extern "C" int vofmt_mlp_stencils(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, const double *c,
+                                  int32_t capacity, float *xs, int32_t *cell, int8_t *sign, int32_t *count_host,
+                                  hipStream_t stream) {
+  if (!ctx) return VOFMT_E_ARG;
+  if (nx < 1 || ny < 1 || nz < 1 || !c || !count_host || capacity < 0)
+    return set_err(ctx, VOFMT_E_ARG, "vofmt_mlp_stencils: bad arguments");
+  const int64_t n3 = (int64_t)nx * ny * nz;
+  if (n3 >= INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "vofmt_mlp_stencils: too many cells");
+  VOFMT_HIP(ctx, hipSetDevice(ctx->device));
+  const unsigned nb = ceil_div(n3, 256);
+  int *bc = (int *)scratch(ctx, SLOT_MISC, sizeof(int) * ((size_t)nb + 1));
+  int *hc = (int *)host_scratch(ctx, sizeof(int) * 2);
+  if (!bc || !hc) return VOFMT_E_NOMEM;
+  hipLaunchKernelGGL(k_block_mixed, dim3(nb), dim3(256), 0, stream, c, n3, bc);
+  hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, stream, bc, (int64_t)nb + 1);
+  VOFMT_HIP(ctx, hipGetLastError());
+  VOFMT_HIP(ctx, hipMemcpyAsync(hc, bc + nb, sizeof(int), hipMemcpyDeviceToHost, stream));
+  VOFMT_HIP(ctx, hipStreamSynchronize(stream));
+  const int total = hc[0];
+  *count_host = total;
+  if (total > capacity) return set_err(ctx, VOFMT_E_ARG, "vofmt_mlp_stencils: %d mixed cells, capacity %d", total,
+                                       capacity);
+  if (total == 0) return VOFMT_OK;
+  if (!xs || !cell || !sign) return set_err(ctx, VOFMT_E_ARG, "vofmt_mlp_stencils: null output");
+  hipLaunchKernelGGL(k_stencils, dim3(nb), dim3(256), 0, stream, c, nx, ny, nz, bc, xs, cell, sign);
+  return hip_check(ctx, hipGetLastError(), "k_stencils");
+}
+
+extern "C" int vofmt_curvature_mlp(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, const double *c,
+                                   const float *params, double kappa_lo, double *kappa, uint8_t *status,
+                                   int32_t *nmixed_host, hipStream_t stream) {
+  if (!ctx) return VOFMT_E_ARG;
+  if (nx < 1 || ny < 1 || nz < 1 || !c || !params || !kappa || !status || !(kappa_lo >= 0.0))
+    return set_err(ctx, VOFMT_E_ARG, "vofmt_curvature_mlp: bad arguments");
+  const int64_t n3 = (int64_t)nx * ny * nz;
+  if (n3 >= INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "vofmt_curvature_mlp: too many cells");
+  VOFMT_HIP(ctx, hipSetDevice(ctx->device));
+  int rc = vofmt_curvature_hf(ctx, nx, ny, nz, c, kappa, status, stream);
+  if (rc) return rc;
+  const unsigned nb = ceil_div(n3, 256);
+  int *bc = (int *)scratch(ctx, SLOT_MISC, sizeof(int) * ((size_t)nb + 1));
+  int *hc = (int *)host_scratch(ctx, sizeof(int) * 2);
+  if (!bc || !hc) return VOFMT_E_NOMEM;
+  hipLaunchKernelGGL(k_block_mixed, dim3(nb), dim3(256), 0, stream, c, n3, bc);
+  hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, stream, bc, (int64_t)nb + 1);
+  VOFMT_HIP(ctx, hipGetLastError());
+  VOFMT_HIP(ctx, hipMemcpyAsync(hc, bc + nb, sizeof(int), hipMemcpyDeviceToHost, stream));
+  VOFMT_HIP(ctx, hipStreamSynchronize(stream));
+  const int nm = hc[0];
+  if (nmixed_host) *nmixed_host = nm;
+  if (nm == 0) return VOFMT_OK;
+  float *xs = (float *)scratch(ctx, SLOT_MLP_X, sizeof(float) * 28 * (size_t)nm);
+  int32_t *cell = (int32_t *)scratch(ctx, SLOT_MLP_CELL, sizeof(int32_t) * (size_t)nm);
+  int8_t *sg = (int8_t *)scratch(ctx, SLOT_MLP_SIGN, (size_t)nm);
+  if (!xs || !cell || !sg) return VOFMT_E_NOMEM;
+  float *yv = xs + 27 * (size_t)nm;
+  hipLaunchKernelGGL(k_stencils, dim3(nb), dim3(256), 0, stream, c, nx, ny, nz, bc, xs, cell, sg);
+  uint16_t *w[4];
+  rc = mlp_prepare(ctx, params, w, stream);
+  if (rc) return rc;
+  const int ntiles = (nm + TILE - 1) / TILE;
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(fwd_grid(ctx, ntiles)), dim3(256), 0, stream, params, w[0], w[1], w[3], nm, xs,
+                     yv, (uint16_t *)nullptr, (const float *)nullptr, (float *)nullptr, (float *)nullptr);
+  hipLaunchKernelGGL(k_curv_combine, dim3(ceil_div(nm, 256)), dim3(256), 0, stream, yv, cell, sg, nm, kappa_lo, kappa,
+                     status);
+  return hip_check(ctx, hipGetLastError(), "curvature_mlp kernels");
+}

@@ -38,7 +38,14 @@ _SIGNATURES = {
     "vofmt_nearest_pair_stats": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
                                                 _vp, _vp, _vp]),
     "vofmt_curvature_hf": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp]),
+    "vofmt_mlp_forward": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _vp]),
+    "vofmt_mlp_train_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, ctypes.c_float, _i32, _vp, _vp, _vp, _vp,
+                                            ctypes.POINTER(ctypes.c_float), _vp]),
+    "vofmt_mlp_stencils": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _P_i32, _vp]),
+    "vofmt_curvature_mlp": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _d, _vp, _vp, _P_i32, _vp]),
 }
+
+MLP_NPARAMS = 20868
 
 _lib = None
 
@@ -187,6 +194,43 @@ class Context:
         nx, ny, nz = _dims(c)
         return self._check(load().vofmt_curvature_hf(self.h, nx, ny, nz, _ptr(c), _ptr(kappa), _ptr(status),
                                                      _stream(stream)))
+
+    # ------------------------------------------------------------ learned curvature
+    def mlp_forward(self, params, x, y, acts=None, stream=None):
+        """Network outputs y[m] (float32) of stencils x[m][27]; acts: optional uint16/int16 [m][256]."""
+        _require(params, x, y, *([acts] if acts is not None else []))
+        m = int(x.shape[0])
+        return self._check(load().vofmt_mlp_forward(self.h, _ptr(params), m, _ptr(x), _ptr(y), _ptr(acts),
+                                                    _stream(stream)))
+
+    def mlp_train_step(self, params, adam_m, adam_v, step: int, lr: float, x, y_target, grads=None, trace=None,
+                       stream=None) -> float:
+        """One forward + backward + Adam step in place; returns the batch loss before the update."""
+        _require(params, adam_m, adam_v, x, y_target, *[t for t in (grads, trace) if t is not None])
+        m = int(x.shape[0])
+        loss = ctypes.c_float(0.0)
+        self._check(load().vofmt_mlp_train_step(self.h, _ptr(params), _ptr(adam_m), _ptr(adam_v), int(step),
+                                                float(lr), m, _ptr(x), _ptr(y_target), _ptr(grads), _ptr(trace),
+                                                ctypes.byref(loss), _stream(stream)))
+        return loss.value
+
+    def mlp_stencils(self, c, xs, cell, sign, stream=None) -> int:
+        """Canonical stencils of the mixed cells of c[nz][ny][nx]; returns their number."""
+        _require(c, xs, cell, sign)
+        nx, ny, nz = _dims(c)
+        cnt = ctypes.c_int32(0)
+        self._check(load().vofmt_mlp_stencils(self.h, nx, ny, nz, _ptr(c), int(xs.shape[0]), _ptr(xs), _ptr(cell),
+                                              _ptr(sign), ctypes.byref(cnt), _stream(stream)))
+        return cnt.value
+
+    def curvature_mlp(self, c, params, kappa_lo: float, kappa, status, stream=None) -> int:
+        """Network curvature with height-function fallback; returns the number of mixed cells."""
+        _require(c, params, kappa, status)
+        nx, ny, nz = _dims(c)
+        cnt = ctypes.c_int32(0)
+        self._check(load().vofmt_curvature_mlp(self.h, nx, ny, nz, _ptr(c), _ptr(params), float(kappa_lo),
+                                               _ptr(kappa), _ptr(status), ctypes.byref(cnt), _stream(stream)))
+        return cnt.value
 
 
 def _require(*ts):
