@@ -194,11 +194,14 @@ int vofmt_curvature_hf(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, const
  * Parameters: one FP32 array of VOFMT_MLP_NPARAMS values,
  *   W1[32][128] (input k, unit j) | b1[128] | W2[128][128] | b2[128] |
  *   W3[128] | b3 | 3 floats of padding,
- * owned by the caller, device memory. Arithmetic: weights rounded to BF16
- * (nearest even) for each use; inputs, activations and upstream gradients
- * rounded to BF16 before every product; matrix products on the BF16 matrix
- * cores with FP32 accumulation; biases, loss and Adam in FP32. Every batch
- * reduction is done in a fixed order, so results are reproducible bit for bit.
+ * owned by the caller, device memory. Arithmetic: the matrix products run on
+ * the BF16 matrix cores with FP32 accumulation; their weights are rounded to
+ * BF16 (nearest even) for each use, the first-layer activations and the
+ * upstream gradients are rounded to BF16, and each input x enters as two BF16
+ * numbers hi = bf16(x), lo = bf16(x - hi) times the same weights. The last
+ * layer is an FP32 dot product of the unrounded second-layer activations with
+ * the FP32 W3. Biases, loss and Adam in FP32. Every batch reduction is done in
+ * a fixed order, so results are reproducible bit for bit.
  * ------------------------------------------------------------------------ */
 #define VOFMT_MLP_NPARAMS 20868
 
@@ -206,11 +209,12 @@ int vofmt_curvature_hf(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, const
  * Forward pass on m stencils.
  * x    : [m][27] FP32 canonical stencils, order (ax+1) + 3(ay+1) + 9(az+1).
  * y    : [m] FP32 output, kappa*Delta of the canonical stencil.
- * acts : nullable; [m][256] BF16 bit patterns output, the rounded hidden
- *        activations h1 (first 128) and h2 (last 128) of every sample.
+ * acts : nullable; [m] records of 768 bytes output: the first-layer
+ *        activations h1 as BF16 [128] (bytes 0..255) and the second-layer
+ *        activations h2 as FP32 [128] (bytes 256..767).
  * Errors: VOFMT_E_ARG for m < 0 or null pointers (m = 0 is a no-op).
  */
-int vofmt_mlp_forward(vofmt_ctx *ctx, const float *params, int32_t m, const float *x, float *y, uint16_t *acts,
+int vofmt_mlp_forward(vofmt_ctx *ctx, const float *params, int32_t m, const float *x, float *y, uint8_t *acts,
                       hipStream_t stream);
 
 /*
@@ -220,13 +224,14 @@ int vofmt_mlp_forward(vofmt_ctx *ctx, const float *params, int32_t m, const floa
  * place). Loss: mean over the batch of (y - t)^2 / max(|t|, 0.05)^2.
  * y_target : [m] FP32 target kappa*Delta of the canonical stencils.
  * grads    : nullable; [VOFMT_MLP_NPARAMS] FP32 output, the batch gradient.
- * trace    : nullable; [m][512] BF16 bit patterns output per sample: h1, h2,
- *            dL/dz2 and dL/dz1 as rounded for the products (128 each).
+ * trace    : nullable; [m] records of 1280 bytes output: the 768-byte
+ *            activation record of vofmt_mlp_forward, then dL/dz2 and dL/dz1
+ *            as BF16 [128] each, as rounded for the products.
  * loss_host: HOST output, the batch loss before the update (synchronises).
  * Errors: VOFMT_E_ARG for m < 1, step < 1, lr < 0 or null pointers.
  */
 int vofmt_mlp_train_step(vofmt_ctx *ctx, float *params, float *adam_m, float *adam_v, int32_t step, float lr,
-                         int32_t m, const float *x, const float *y_target, float *grads, uint16_t *trace,
+                         int32_t m, const float *x, const float *y_target, float *grads, uint8_t *trace,
                          float *loss_host, hipStream_t stream);
 
 /*

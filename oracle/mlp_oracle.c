@@ -7,12 +7,18 @@
  *   input 27 values (zero-padded to 32) -> 128 -> 128 -> 1, ReLU,
  * predicting kappa*Delta. This file is the reference implementation of its
  * arithmetic, written from that definition:
- *   - weights are FP32 masters, rounded to BF16 (round to nearest even) for
- *     each use; inputs, activations and upstream gradients are rounded to
- *     BF16 before each product; products and sums are accumulated here in
- *     FP64 (the GPU accumulates in FP32: the tests allow the FP32 bound);
+ *   - the two matrix products (layers 1 and 2) and the three of the backward
+ *     pass take BF16 operands: weights are FP32 masters rounded to BF16 (round
+ *     to nearest even) for each use; the first-layer activations and the
+ *     upstream gradients are rounded to BF16; each input value x is carried
+ *     as the sum of two BF16 numbers, hi = bf16(x) and lo = bf16(x - hi), both
+ *     multiplied by the same weights (about 16 significant bits);
+ *   - the last layer (128 -> 1) is a plain FP32 dot product: the second-layer
+ *     activations and W3 are not rounded to BF16;
+ *   - products and sums are accumulated here in FP64 (the GPU accumulates in
+ *     FP32: the tests allow the FP32 bound);
  *   - an activation is rounded to FP32 before its BF16 rounding, as on the GPU;
- *   - ReLU'(z) is taken as (activation > 0), the activation as rounded;
+ *   - ReLU'(z) is taken as (activation > 0), the activation as used;
  *   - loss: mean over the batch of (y - t)^2 / max(|t|, 0.05)^2;
  *   - Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 masters.
  * With exact = 1 no rounding is applied at all (pure FP64), which is what the
@@ -62,6 +68,15 @@ float orc_bf16(float f) {
 
 static double rnd(double v, int exact) { return exact ? v : (double)orc_bf16((float)v); }
 
+/* An input value as the matrix cores see it: hi + lo, two BF16 numbers. */
+static double rnd_in(double v, int exact) {
+  if (exact) return v;
+  float f = (float)v;
+  float hi = orc_bf16(f);
+  float lo = orc_bf16(f - hi); /* f - hi is exact in FP32 */
+  return (double)hi + (double)lo;
+}
+
 /* Canonical stencil of a 3x3x3 block b[(ax+1)+3(ay+1)+9(az+1)] (FP64), written
  * as 27 FP32 values; returns +1 or -1, the sign that maps the network output
  * back to the original orientation. Order of the steps: complement (when the
@@ -101,7 +116,7 @@ int orc_canonical_stencil(const double *b, float *x27) {
  * pre-activations z1, z2. */
 static double forward1(const float *P, const float *x, int exact, double *h1, double *h2, double *z1, double *z2) {
   double xb[NIN];
-  for (int k = 0; k < NIN; ++k) xb[k] = (k < 27) ? rnd((double)x[k], exact) : 0.0;
+  for (int k = 0; k < NIN; ++k) xb[k] = (k < 27) ? rnd_in((double)x[k], exact) : 0.0;
   for (int j = 0; j < NH; ++j) {
     double acc = 0.0;
     for (int k = 0; k < NIN; ++k) acc += xb[k] * rnd((double)P[OFF_W1 + k * NH + j], exact);
@@ -114,10 +129,10 @@ static double forward1(const float *P, const float *x, int exact, double *h1, do
     for (int k = 0; k < NH; ++k) acc += h1[k] * rnd((double)P[OFF_W2 + k * NH + j], exact);
     acc += (double)P[OFF_B2 + j];
     z2[j] = acc;
-    h2[j] = rnd(acc > 0.0 ? acc : 0.0, exact);
+    h2[j] = acc > 0.0 ? acc : 0.0;
   }
   double y = 0.0;
-  for (int k = 0; k < NH; ++k) y += h2[k] * rnd((double)P[OFF_W3 + k], exact);
+  for (int k = 0; k < NH; ++k) y += h2[k] * (double)P[OFF_W3 + k];
   y += (double)P[OFF_B3];
   return y;
 }
@@ -160,7 +175,7 @@ double orc_mlp_grad(const float *P, int n, const float *x, const float *t, int e
     for (int k = 0; k < NH; ++k) grad[OFF_W3 + k] += g * h2[k];
     grad[OFF_B3] += g;
     for (int k = 0; k < NH; ++k) {
-      double d = (h2[k] > 0.0) ? g * rnd((double)P[OFF_W3 + k], exact) : 0.0;
+      double d = (h2[k] > 0.0) ? g * (double)P[OFF_W3 + k] : 0.0;
       dz2[k] = rnd(d, exact);
     }
     /* layer 2 */
@@ -174,7 +189,7 @@ double orc_mlp_grad(const float *P, int n, const float *x, const float *t, int e
     }
     /* layer 1 */
     double xb[NIN];
-    for (int k = 0; k < NIN; ++k) xb[k] = (k < 27) ? rnd((double)xi[k], exact) : 0.0;
+    for (int k = 0; k < NIN; ++k) xb[k] = (k < 27) ? rnd_in((double)xi[k], exact) : 0.0;
     for (int k = 0; k < NIN; ++k)
       for (int j = 0; j < NH; ++j) grad[OFF_W1 + k * NH + j] += xb[k] * dz1[j];
     for (int j = 0; j < NH; ++j) grad[OFF_B1 + j] += dz1[j];
@@ -197,11 +212,11 @@ void orc_adam(float *P, float *M, float *V, const double *grad, int step, double
 }
 
 /* One layer on supplied inputs (for layer-by-layer comparison):
- *   layer 1: in [n][27] (rounded to BF16 here), out [n][128];
- *   layer 2: in [n][128] (rounded to BF16 here), out [n][128];
- *   layer 3: in [n][128], out [n] (no activation, no rounding).
- * pre: the pre-activation z = sum(in * W) + b; act: the rounded ReLU(z)
- * (layer 3: act = pre); absacc: sum |in * W| + |b|, the scale of the
+ *   layer 1: in [n][27] (split into hi + lo here), out [n][128], act rounded;
+ *   layer 2: in [n][128] (rounded to BF16 here), out [n][128], act not rounded;
+ *   layer 3: in [n][128], out [n] (no activation, no rounding, FP32 W3).
+ * pre: the pre-activation z = sum(in * W) + b; act: ReLU(z), rounded after
+ * layer 1 (layer 3: act = pre); absacc: sum |in * W| + |b|, the scale of the
  * accumulation-error bound. Any output may be NULL. */
 void orc_mlp_layer(const float *P, int layer, int n, const double *in, int exact, double *pre, double *act,
                    double *absacc) {
@@ -213,8 +228,9 @@ void orc_mlp_layer(const float *P, int layer, int n, const double *in, int exact
     for (int j = 0; j < nout; ++j) {
       double acc = 0.0, aabs = 0.0;
       for (int k = 0; k < nin; ++k) {
-        double a = rnd(in[(int64_t)i * nin + k], exact);
-        double w = rnd((double)P[woff + k * wstride + j], exact);
+        double a = layer == 1 ? rnd_in(in[(int64_t)i * nin + k], exact)
+                   : layer == 2 ? rnd(in[(int64_t)i * nin + k], exact) : in[(int64_t)i * nin + k];
+        double w = layer == 3 ? (double)P[woff + k * wstride + j] : rnd((double)P[woff + k * wstride + j], exact);
         acc += a * w;
         aabs += fabs(a * w);
       }
@@ -222,7 +238,7 @@ void orc_mlp_layer(const float *P, int layer, int n, const double *in, int exact
       aabs += fabs((double)P[boff + j]);
       int64_t o = (int64_t)i * nout + j;
       if (pre) pre[o] = acc;
-      if (act) act[o] = layer == 3 ? acc : rnd(acc > 0.0 ? acc : 0.0, exact);
+      if (act) act[o] = layer == 3 ? acc : layer == 2 ? (acc > 0.0 ? acc : 0.0) : rnd(acc > 0.0 ? acc : 0.0, exact);
       if (absacc) absacc[o] = aabs;
     }
   }
@@ -230,7 +246,7 @@ void orc_mlp_layer(const float *P, int layer, int n, const double *in, int exact
 
 /* Backward pass on supplied intermediates (for comparison against a run that
  * produced them): g [n] = dL/dy per sample; h1, h2, dz2_in, dz1_in [n][128].
- *   dz2_out = round(h2 > 0 ? g * W3 : 0)
+ *   dz2_out = round(h2 > 0 ? g * W3 : 0)   (W3 FP32)
  *   dz1_out = round(h1 > 0 ? sum_j dz2_in_j * W2[k][j] : 0), dz1_abs its |.| scale
  *   grad    = dW1 = sum x dz1_in, db1 = sum dz1_in, dW2 = sum h1 dz2_in,
  *             db2 = sum dz2_in, dW3 = sum g h2, db3 = sum g (over the batch);
@@ -245,10 +261,10 @@ void orc_mlp_backward_given(const float *P, int n, const float *x, const double 
     const double *a1 = h1 + (int64_t)i * NH, *a2 = h2 + (int64_t)i * NH;
     const double *d2 = dz2_in + (int64_t)i * NH, *d1 = dz1_in + (int64_t)i * NH;
     double xb[NIN];
-    for (int k = 0; k < NIN; ++k) xb[k] = (k < 27) ? rnd((double)x[27 * (int64_t)i + k], exact) : 0.0;
+    for (int k = 0; k < NIN; ++k) xb[k] = (k < 27) ? rnd_in((double)x[27 * (int64_t)i + k], exact) : 0.0;
     for (int k = 0; k < NH; ++k) {
       if (dz2_out)
-        dz2_out[(int64_t)i * NH + k] = rnd(a2[k] > 0.0 ? g[i] * rnd((double)P[OFF_W3 + k], exact) : 0.0, exact);
+        dz2_out[(int64_t)i * NH + k] = rnd(a2[k] > 0.0 ? g[i] * (double)P[OFF_W3 + k] : 0.0, exact);
       double acc = 0.0, aabs = 0.0;
       for (int j = 0; j < NH; ++j) {
         double t = d2[j] * rnd((double)P[OFF_W2 + k * NH + j], exact);

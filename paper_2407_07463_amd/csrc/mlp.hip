@@ -4,18 +4,25 @@
 // curvature that uses it with height functions as the fallback.
 //
 // The paper computes curvature with the single-tracer method (height
-// functions); the network is an addition of this library. Arithmetic:
-// weights are FP32 masters rounded to BF16 (round to nearest even) for each
-// use; inputs, activations and upstream gradients are rounded to BF16 before
-// every product; all products run on the matrix cores
-// (v_mfma_f32_16x16x32_bf16) with FP32 accumulation; biases, loss and Adam in
-// FP32. ReLU'(z) is (activation > 0) on the rounded activation. Reductions
-// over the batch go through per-tile partial sums added in a fixed order, so
-// every result is reproducible bit for bit.
+// functions); the network is an addition of this library. Arithmetic: the
+// matrix products (layers 1 and 2 forward; dH1, dW2, dW1 backward) run on the
+// matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation) with BF16
+// operands: weights are FP32 masters rounded to nearest even for each use,
+// the first-layer activations and the upstream gradients are rounded to BF16,
+// and every input value x enters as two BF16 numbers hi = bf16(x),
+// lo = bf16(x - hi) multiplied by the same weights (about 16 significant
+// bits). The last layer (128 -> 1) is an FP32 dot product of the unrounded
+// second-layer activations with the FP32 W3. Biases, loss and Adam in FP32.
+// ReLU'(z) is (activation > 0). Batch reductions go through per-tile partial
+// sums added in a fixed order, so every result is reproducible bit for bit.
 //
 // MFMA fragment layout (16x16x32, one wavefront): lane l holds
 //   A[l%16][8*(l/16) + e], B[8*(l/16) + e][l%16] for e = 0..7 (bf16), and
 //   D[4*(l/16) + r][l%16] for r = 0..3 (fp32).
+//
+// Per-sample activation record (bytes): h1 as BF16 [128] at 0, h2 as FP32
+// [128] at 256 (768 in all). Training trace adds dL/dz2 and dL/dz1 as BF16
+// [128] at 768 and 1024 (1280 in all).
 #include <cstring>
 
 #include "common.hpp"
@@ -56,10 +63,12 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+constexpr int ACT_BYTES = 768, TRACE_BYTES = 1280;
+
 // BF16 copies of the weights for one call: W1^T [128][32], W2^T [128][128],
-// W2 [128][128] (for the backward product), W3 [128].
+// W2 [128][128] (for the backward product).
 __global__ void k_mlp_prep(const float *__restrict__ P, uint16_t *__restrict__ w1t, uint16_t *__restrict__ w2t,
-                           uint16_t *__restrict__ w2n, uint16_t *__restrict__ w3) {
+                           uint16_t *__restrict__ w2n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < NIN * NH) {
     const int k = i / NH, j = i % NH;
@@ -71,19 +80,27 @@ __global__ void k_mlp_prep(const float *__restrict__ P, uint16_t *__restrict__ w
     w2t[j * NH + k] = b;
     w2n[i] = b;
   }
-  if (i < NH) w3[i] = bf16_bits(P[OFF_W3 + i]);
 }
 
-// Forward pass, persistent over 64-sample tiles. With a target, also the
-// upstream gradient g = dL/dy of every sample and the loss of every tile.
+__device__ __forceinline__ uint16_t *act_h1(uint8_t *rec, int64_t s, int stride) {
+  return reinterpret_cast<uint16_t *>(rec + s * stride);
+}
+__device__ __forceinline__ float *act_h2(uint8_t *rec, int64_t s, int stride) {
+  return reinterpret_cast<float *>(rec + s * stride + 256);
+}
+
+// Forward pass, persistent over 64-sample tiles. acts (nullable): the
+// activation records. With a target, also the upstream gradient g = dL/dy of
+// every sample and the loss of every tile.
 __global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ P, const uint16_t *__restrict__ w1t_g,
-                                                 const uint16_t *__restrict__ w2t_g, const uint16_t *__restrict__ w3_g,
-                                                 int m, const float *__restrict__ x, float *__restrict__ y,
-                                                 uint16_t *__restrict__ acts, const float *__restrict__ tgt,
+                                                 const uint16_t *__restrict__ w2t_g, int m,
+                                                 const float *__restrict__ x, float *__restrict__ y,
+                                                 uint8_t *__restrict__ acts, const float *__restrict__ tgt,
                                                  float *__restrict__ g_out, float *__restrict__ loss_part) {
   __shared__ __attribute__((aligned(16))) uint16_t W1s[NH][XP];
   __shared__ __attribute__((aligned(16))) uint16_t W2s[NH][HP];
-  __shared__ __attribute__((aligned(16))) uint16_t Xs[TILE][XP];
+  __shared__ __attribute__((aligned(16))) uint16_t Xh[TILE][XP];
+  __shared__ __attribute__((aligned(16))) uint16_t Xl[TILE][XP];
   __shared__ __attribute__((aligned(16))) uint16_t H1s[TILE][HP];
   __shared__ float b1s[NH], b2s[NH], w3s[NH];
   __shared__ float ypart[4][TILE];
@@ -94,7 +111,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ P, co
   for (int i = tid; i < NH; i += 256) {
     b1s[i] = P[OFF_B1 + i];
     b2s[i] = P[OFF_B2 + i];
-    w3s[i] = bf16_val(w3_g[i]);
+    w3s[i] = P[OFF_W3 + i];
   }
   const float b3 = P[OFF_B3];
   const int ntiles = (m + TILE - 1) / TILE;
@@ -105,7 +122,9 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ P, co
     for (int i = tid; i < TILE * NIN; i += 256) {
       const int s = i / NIN, k = i % NIN;
       const float v = (k < 27 && s0 + s < m) ? x[(int64_t)(s0 + s) * 27 + k] : 0.0f;
-      Xs[s][k] = bf16_bits(v);
+      const uint16_t hi = bf16_bits(v);
+      Xh[s][k] = hi;
+      Xl[s][k] = bf16_bits(v - bf16_val(hi));
     }
     __syncthreads();
     // layer 1: wave w owns output columns [32w, 32w+32)
@@ -114,8 +133,10 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ P, co
 #pragma unroll
       for (int jn = 0; jn < 2; ++jn) {
         const int nt = 2 * w + jn;
+        const bf16x8 wf = frag(&W1s[16 * nt + lr][8 * lq]);
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mfma(frag(&Xs[16 * mt + lr][8 * lq]), frag(&W1s[16 * nt + lr][8 * lq]), acc);
+        acc = mfma(frag(&Xh[16 * mt + lr][8 * lq]), wf, acc);
+        acc = mfma(frag(&Xl[16 * mt + lr][8 * lq]), wf, acc);
         const int col = 16 * nt + lr;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -123,7 +144,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ P, co
           const float z = acc[r] + b1s[col];
           const uint16_t h = bf16_bits(z > 0.0f ? z : 0.0f);
           H1s[row][col] = h;
-          if (acts && s0 + row < m) acts[(int64_t)(s0 + row) * 256 + col] = h;
+          if (acts && s0 + row < m) act_h1(acts, s0 + row, ACT_BYTES)[col] = h;
         }
       }
     __syncthreads();
@@ -147,9 +168,9 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ P, co
         for (int r = 0; r < 4; ++r) {
           const int row = 16 * mt + 4 * lq + r;
           const float z = acc[r] + b2s[col];
-          const uint16_t h = bf16_bits(z > 0.0f ? z : 0.0f);
-          if (acts && s0 + row < m) acts[(int64_t)(s0 + row) * 256 + NH + col] = h;
-          yp[mt][r] = yp[mt][r] + bf16_val(h) * w3s[col];
+          const float h = z > 0.0f ? z : 0.0f;
+          if (acts && s0 + row < m) act_h2(acts, s0 + row, ACT_BYTES)[col] = h;
+          yp[mt][r] = yp[mt][r] + h * w3s[col];
         }
       }
     }
@@ -195,12 +216,14 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ P, co
 }
 
 // Backward pass of one 64-sample tile: per-tile partial gradients of every
-// parameter (added later in a fixed order).
-__global__ __launch_bounds__(256) void k_mlp_bwd(const uint16_t *__restrict__ w2n_g, const uint16_t *__restrict__ w3_g,
-                                                 int m, const float *__restrict__ x,
-                                                 const uint16_t *__restrict__ acts, const float *__restrict__ g,
-                                                 float *__restrict__ partial, uint16_t *__restrict__ trace) {
-  __shared__ __attribute__((aligned(16))) uint16_t XT[NIN][TP];
+// parameter (added later in a fixed order). trace (nullable): the training
+// records of the tile's samples.
+__global__ __launch_bounds__(256) void k_mlp_bwd(const float *__restrict__ P, const uint16_t *__restrict__ w2n_g,
+                                                 int m, const float *__restrict__ x, uint8_t *__restrict__ acts,
+                                                 const float *__restrict__ g, float *__restrict__ partial,
+                                                 uint8_t *__restrict__ trace) {
+  __shared__ __attribute__((aligned(16))) uint16_t XTh[NIN][TP];
+  __shared__ __attribute__((aligned(16))) uint16_t XTl[NIN][TP];
   __shared__ __attribute__((aligned(16))) uint16_t H1T[NH][TP];
   __shared__ __attribute__((aligned(16))) uint16_t D2[TILE][HP];
   __shared__ __attribute__((aligned(16))) uint16_t D2T[NH][TP];
@@ -212,26 +235,28 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(const uint16_t *__restrict__ w2
   const int tile = blockIdx.x, s0 = tile * TILE;
   float *part = partial + (int64_t)tile * NPARAMS;
   if (tid < TILE) gs[tid] = (s0 + tid < m) ? g[s0 + tid] : 0.0f;
-  if (tid < NH) w3s[tid] = bf16_val(w3_g[tid]);
+  if (tid < NH) w3s[tid] = P[OFF_W3 + tid];
   for (int i = tid; i < TILE * NIN; i += 256) {
     const int s = i / NIN, k = i % NIN;
     const float v = (k < 27 && s0 + s < m) ? x[(int64_t)(s0 + s) * 27 + k] : 0.0f;
-    XT[k][s] = bf16_bits(v);
+    const uint16_t hi = bf16_bits(v);
+    XTh[k][s] = hi;
+    XTl[k][s] = bf16_bits(v - bf16_val(hi));
   }
   for (int i = tid; i < TILE * NH; i += 256) {
     const int s = i / NH, k = i % NH;
-    H1T[k][s] = (s0 + s < m) ? acts[(int64_t)(s0 + s) * 256 + k] : (uint16_t)0;
+    H1T[k][s] = (s0 + s < m) ? act_h1(acts, s0 + s, ACT_BYTES)[k] : (uint16_t)0;
   }
   __syncthreads();
   // dZ2 = bf16((h2 > 0) * g * W3)
   for (int i = tid; i < TILE * NH; i += 256) {
     const int s = i / NH, k = i % NH;
-    const uint16_t h2 = (s0 + s < m) ? acts[(int64_t)(s0 + s) * 256 + NH + k] : (uint16_t)0;
-    const float d = (bf16_val(h2) > 0.0f) ? gs[s] * w3s[k] : 0.0f;
+    const float h2 = (s0 + s < m) ? act_h2(acts, s0 + s, ACT_BYTES)[k] : 0.0f;
+    const float d = (h2 > 0.0f) ? gs[s] * w3s[k] : 0.0f;
     const uint16_t b = bf16_bits(d);
     D2[s][k] = b;
     D2T[k][s] = b;
-    if (trace && s0 + s < m) trace[(int64_t)(s0 + s) * 512 + 2 * NH + k] = b;
+    if (trace && s0 + s < m) reinterpret_cast<uint16_t *>(trace + (int64_t)(s0 + s) * TRACE_BYTES + 768)[k] = b;
   }
   __syncthreads();
   // dH1 = dZ2 . W2^T; dZ1 = bf16((h1 > 0) * dH1); wave w owns hidden units [32w, 32w+32)
@@ -251,7 +276,8 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(const uint16_t *__restrict__ w2
         const float h1 = bf16_val(H1T[col][row]);
         const uint16_t b = bf16_bits(h1 > 0.0f ? acc[r] : 0.0f);
         D1T[col][row] = b;
-        if (trace && s0 + row < m) trace[(int64_t)(s0 + row) * 512 + 3 * NH + col] = b;
+        if (trace && s0 + row < m)
+          reinterpret_cast<uint16_t *>(trace + (int64_t)(s0 + row) * TRACE_BYTES + 1024)[col] = b;
       }
     }
   }
@@ -270,7 +296,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(const uint16_t *__restrict__ w2
       for (int r = 0; r < 4; ++r) part[OFF_W2 + (16 * mt + 4 * lq + r) * NH + col] = acc[r];
     }
   }
-  // dW1 = X^T . dZ1 (32 x 128, K = 64 samples)
+  // dW1 = X^T . dZ1 (32 x 128, K = 64 samples), X as hi + lo
 #pragma unroll
   for (int jn = 0; jn < 2; ++jn) {
     const int nt = 2 * w + jn;
@@ -279,8 +305,11 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(const uint16_t *__restrict__ w2
     for (int mt = 0; mt < 2; ++mt) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kk = 0; kk < TILE; kk += 32)
-        acc = mfma(frag(&XT[16 * mt + lr][kk + 8 * lq]), frag(&D1T[16 * nt + lr][kk + 8 * lq]), acc);
+      for (int kk = 0; kk < TILE; kk += 32) {
+        const bf16x8 d1 = frag(&D1T[16 * nt + lr][kk + 8 * lq]);
+        acc = mfma(frag(&XTh[16 * mt + lr][kk + 8 * lq]), d1, acc);
+        acc = mfma(frag(&XTl[16 * mt + lr][kk + 8 * lq]), d1, acc);
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) part[OFF_W1 + (16 * mt + 4 * lq + r) * NH + col] = acc[r];
     }
@@ -290,8 +319,8 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(const uint16_t *__restrict__ w2
     const int k = tid;
     float a3 = 0.0f, a2 = 0.0f, a1 = 0.0f;
     for (int s = 0; s < TILE; ++s) {
-      const uint16_t h2 = (s0 + s < m) ? acts[(int64_t)(s0 + s) * 256 + NH + k] : (uint16_t)0;
-      a3 = a3 + gs[s] * bf16_val(h2);
+      const float h2 = (s0 + s < m) ? act_h2(acts, s0 + s, ACT_BYTES)[k] : 0.0f;
+      a3 = a3 + gs[s] * h2;
       a2 = a2 + bf16_val(D2T[k][s]);
       a1 = a1 + bf16_val(D1T[k][s]);
     }
@@ -307,9 +336,12 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(const uint16_t *__restrict__ w2
     part[OFF_B3 + 3] = 0.0f;
   }
   if (trace) {
-    for (int i = tid; i < TILE * 2 * NH; i += 256) {
-      const int s = i / (2 * NH), k = i % (2 * NH);
-      if (s0 + s < m) trace[(int64_t)(s0 + s) * 512 + k] = acts[(int64_t)(s0 + s) * 256 + k];
+    // the activation records of the tile, copied word by word
+    for (int i = tid; i < TILE * (ACT_BYTES / 4); i += 256) {
+      const int s = i / (ACT_BYTES / 4), q = i % (ACT_BYTES / 4);
+      if (s0 + s < m)
+        reinterpret_cast<uint32_t *>(trace + (int64_t)(s0 + s) * TRACE_BYTES)[q] =
+            reinterpret_cast<const uint32_t *>(acts + (int64_t)(s0 + s) * ACT_BYTES)[q];
     }
   }
 }
@@ -470,13 +502,12 @@ __global__ __launch_bounds__(256) void k_curv_combine(const float *__restrict__ 
 }  // namespace
 
 static int mlp_prepare(vofmt_ctx *ctx, const float *params, uint16_t **w, hipStream_t stream) {
-  uint16_t *buf = (uint16_t *)scratch(ctx, SLOT_MLP_W, sizeof(uint16_t) * (NIN * NH + 2 * NH * NH + NH));
+  uint16_t *buf = (uint16_t *)scratch(ctx, SLOT_MLP_W, sizeof(uint16_t) * (NIN * NH + 2 * NH * NH));
   if (!buf) return VOFMT_E_NOMEM;
   w[0] = buf;                       // W1^T
   w[1] = buf + NIN * NH;            // W2^T
   w[2] = buf + NIN * NH + NH * NH;  // W2
-  w[3] = buf + NIN * NH + 2 * NH * NH;
-  hipLaunchKernelGGL(k_mlp_prep, dim3(ceil_div(NH * NH, 256)), dim3(256), 0, stream, params, w[0], w[1], w[2], w[3]);
+  hipLaunchKernelGGL(k_mlp_prep, dim3(ceil_div(NH * NH, 256)), dim3(256), 0, stream, params, w[0], w[1], w[2]);
   return hip_check(ctx, hipGetLastError(), "k_mlp_prep");
 }
 
@@ -489,42 +520,42 @@ static int fwd_grid(vofmt_ctx *ctx, int ntiles) {
 }
 
 extern "C" int vofmt_mlp_forward(vofmt_ctx *ctx, const float *params, int32_t m, const float *x, float *y,
-                                 uint16_t *acts, hipStream_t stream) {
+                                 uint8_t *acts, hipStream_t stream) {
   if (!ctx) return VOFMT_E_ARG;
   if (m < 0 || !params || (m > 0 && (!x || !y)))
     return set_err(ctx, VOFMT_E_ARG, "vofmt_mlp_forward: bad arguments");
   if (m == 0) return VOFMT_OK;
   VOFMT_HIP(ctx, hipSetDevice(ctx->device));
-  uint16_t *w[4];
+  uint16_t *w[3];
   int rc = mlp_prepare(ctx, params, w, stream);
   if (rc) return rc;
   const int ntiles = (m + TILE - 1) / TILE;
-  hipLaunchKernelGGL(k_mlp_fwd, dim3(fwd_grid(ctx, ntiles)), dim3(256), 0, stream, params, w[0], w[1], w[3], m, x, y,
-                     acts, (const float *)nullptr, (float *)nullptr, (float *)nullptr);
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(fwd_grid(ctx, ntiles)), dim3(256), 0, stream, params, w[0], w[1], m, x, y, acts,
+                     (const float *)nullptr, (float *)nullptr, (float *)nullptr);
   return hip_check(ctx, hipGetLastError(), "k_mlp_fwd");
 }
 
 extern "C" int vofmt_mlp_train_step(vofmt_ctx *ctx, float *params, float *adam_m, float *adam_v, int32_t step,
                                     float lr, int32_t m, const float *x, const float *y_target, float *grads,
-                                    uint16_t *trace, float *loss_host, hipStream_t stream) {
+                                    uint8_t *trace, float *loss_host, hipStream_t stream) {
   if (!ctx) return VOFMT_E_ARG;
   if (m < 1 || step < 1 || !params || !adam_m || !adam_v || !x || !y_target || !loss_host || !(lr >= 0.0f))
     return set_err(ctx, VOFMT_E_ARG, "vofmt_mlp_train_step: bad arguments");
   VOFMT_HIP(ctx, hipSetDevice(ctx->device));
-  uint16_t *w[4];
+  uint16_t *w[3];
   int rc = mlp_prepare(ctx, params, w, stream);
   if (rc) return rc;
   const int ntiles = (m + TILE - 1) / TILE;
-  uint16_t *acts = (uint16_t *)scratch(ctx, SLOT_MLP_ACTS, sizeof(uint16_t) * 256 * (size_t)m);
+  uint8_t *acts = (uint8_t *)scratch(ctx, SLOT_MLP_ACTS, (size_t)ACT_BYTES * (size_t)m);
   float *gbuf = (float *)scratch(ctx, SLOT_MLP_G, sizeof(float) * ((size_t)m + (size_t)ntiles + 4));
   float *partial = (float *)scratch(ctx, SLOT_MLP_PART, sizeof(float) * (size_t)ntiles * NPARAMS);
   float *hl = (float *)host_scratch(ctx, sizeof(float) * 4);
   if (!acts || !gbuf || !partial || !hl) return VOFMT_E_NOMEM;
   float *loss_part = gbuf + m;
   float *loss_out = gbuf + m + ntiles;
-  hipLaunchKernelGGL(k_mlp_fwd, dim3(fwd_grid(ctx, ntiles)), dim3(256), 0, stream, params, w[0], w[1], w[3], m, x,
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(fwd_grid(ctx, ntiles)), dim3(256), 0, stream, params, w[0], w[1], m, x,
                      (float *)nullptr, acts, y_target, gbuf, loss_part);
-  hipLaunchKernelGGL(k_mlp_bwd, dim3(ntiles), dim3(256), 0, stream, w[2], w[3], m, x, acts, gbuf, partial, trace);
+  hipLaunchKernelGGL(k_mlp_bwd, dim3(ntiles), dim3(256), 0, stream, params, w[2], m, x, acts, gbuf, partial, trace);
   hipLaunchKernelGGL(k_mlp_adam, dim3(ceil_div(NPARAMS, 256)), dim3(256), 0, stream, params, adam_m, adam_v, partial,
                      ntiles, step, lr, grads, loss_part, loss_out, m);
   VOFMT_HIP(ctx, hipGetLastError());
@@ -594,12 +625,12 @@ extern "C" int vofmt_curvature_mlp(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32
   if (!xs || !cell || !sg) return VOFMT_E_NOMEM;
   float *yv = xs + 27 * (size_t)nm;
   hipLaunchKernelGGL(k_stencils, dim3(nb), dim3(256), 0, stream, c, nx, ny, nz, bc, xs, cell, sg);
-  uint16_t *w[4];
+  uint16_t *w[3];
   rc = mlp_prepare(ctx, params, w, stream);
   if (rc) return rc;
   const int ntiles = (nm + TILE - 1) / TILE;
-  hipLaunchKernelGGL(k_mlp_fwd, dim3(fwd_grid(ctx, ntiles)), dim3(256), 0, stream, params, w[0], w[1], w[3], nm, xs,
-                     yv, (uint16_t *)nullptr, (const float *)nullptr, (float *)nullptr, (float *)nullptr);
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(fwd_grid(ctx, ntiles)), dim3(256), 0, stream, params, w[0], w[1], nm, xs, yv,
+                     (uint8_t *)nullptr, (const float *)nullptr, (float *)nullptr, (float *)nullptr);
   hipLaunchKernelGGL(k_curv_combine, dim3(ceil_div(nm, 256)), dim3(256), 0, stream, yv, cell, sg, nm, kappa_lo, kappa,
                      status);
   return hip_check(ctx, hipGetLastError(), "curvature_mlp kernels");

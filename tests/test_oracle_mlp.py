@@ -52,10 +52,10 @@ def _selector_network(w_centre=1.0, b3=0.25):
     return P
 
 
-def test_forward_selector_network_rounds_inputs():
+def test_forward_selector_network_rounding_points():
     x = np.zeros((3, 27), dtype=np.float32)
-    x[0, 13] = 1.0 + 2.0 ** -8     # rounds to 1 in BF16
-    x[1, 13] = 0.3                 # rounds to 0.30078125
+    x[0, 13] = 1.0 + 2.0 ** -8     # hi = 1, lo = 2^-8; the first activation rounds it back to 1
+    x[1, 13] = 0.3
     x[2, 13] = 0.7
     x[2, 0] = 0.9                  # not connected
     y, acts = oracle.mlp_forward(_selector_network(), x)
@@ -63,6 +63,30 @@ def test_forward_selector_network_rounds_inputs():
     assert acts[1, 0] == 0.30078125 and acts[1, 128 + 5] == 0.30078125
     ye, _ = oracle.mlp_forward(_selector_network(), x, exact=True)
     assert ye[0] == 0.25 + (1.0 + 2.0 ** -8)
+
+
+def test_forward_inputs_carry_sixteen_bits():
+    # unit 0 of layer 1 takes the difference of two inputs that BF16 alone cannot tell apart
+    P = _selector_network(b3=0.0)
+    P[OFF["W1"] + 12 * 128 + 0] = -1.0
+    x = np.zeros((2, 27), dtype=np.float32)
+    x[:, 13] = 1.0 + 2.0 ** -8
+    x[:, 12] = 1.0
+    x[1, 13] = 1.0 + 2.0 ** -8 + 2.0 ** -15  # hi = 1 + 2^-7 (round up), lo = -2^-8 + 2^-15
+    y, acts = oracle.mlp_forward(P, x)
+    assert acts[0, 0] == 2.0 ** -8 and y[0] == 2.0 ** -8
+    assert y[1] == float(oracle.bf16([2.0 ** -8 + 2.0 ** -15])[0])
+
+
+def test_forward_last_layer_fp32():
+    P = _selector_network(b3=0.0)
+    P[OFF["b2"] + 5] = 2.0 ** -12          # second activation 1 + 2^-12: not rounded
+    P[OFF["W3"] + 5] = 1.0 + 2.0 ** -10    # W3 in FP32: not rounded
+    x = np.zeros((1, 27), dtype=np.float32)
+    x[0, 13] = 1.0
+    y, acts = oracle.mlp_forward(P, x)
+    assert acts[0, 128 + 5] == 1.0 + 2.0 ** -12
+    assert y[0] == (1.0 + 2.0 ** -12) * np.float64(np.float32(1.0 + 2.0 ** -10))
 
 
 def test_forward_relu_cuts_negative_units():
@@ -98,9 +122,14 @@ def test_forward_bf16_matches_torch_rounding_points():
     T = torch.from_numpy(P.astype(np.float64))
     W1 = b(T[OFF["W1"]:OFF["b1"]].reshape(32, 128)[:27])
     W2 = b(T[OFF["W2"]:OFF["b2"]].reshape(128, 128))
-    W3 = b(T[OFF["W3"]:OFF["b3"]])
-    h1 = b(torch.relu(b(torch.from_numpy(x.astype(np.float64))) @ W1 + T[OFF["b1"]:OFF["W2"]]))
-    h2 = b(torch.relu(h1 @ W2 + T[OFF["b2"]:OFF["W3"]]))
+    W3 = T[OFF["W3"]:OFF["b3"]]
+    X = torch.from_numpy(x)
+    hi = X.to(torch.bfloat16).to(torch.float32)
+    lo = (X - hi).to(torch.bfloat16).to(torch.float32)
+    Xs = hi.to(torch.float64) + lo.to(torch.float64)
+    assert torch.all((Xs - X.to(torch.float64)).abs() <= 2.0 ** -16 * X.abs().to(torch.float64))
+    h1 = b(torch.relu(Xs @ W1 + T[OFF["b1"]:OFF["W2"]]))
+    h2 = torch.relu(h1 @ W2 + T[OFF["b2"]:OFF["W3"]])
     yr = (h2 @ W3 + T[OFF["b3"]]).numpy()
     # summation order may move a rare pre-activation across a rounding boundary
     assert np.mean(acts[:, :128] != h1.numpy()) < 2e-3
