@@ -263,6 +263,52 @@ int vofmt_mlp_stencils(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, const
 int vofmt_curvature_mlp(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, const double *c, const float *params,
                         double kappa_lo, double *kappa, uint8_t *status, int32_t *nmixed_host, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Batched advection: many boxes of uneven sizes and tracer counts, each
+ * advanced exactly as vofmt_advect would (eq. 3 of the paper per tracer,
+ * direction-split sweeps in the order (g, g+1, g+2) mod 3 of global step g),
+ * in one graph launch. The results are bit-identical to one vofmt_advect
+ * call per box with the same step0 and nsteps, for every tuning.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t nx, ny, nz;  /* box size in cells (x fastest) */
+  int32_t ntracers;
+  double *c;           /* [ntracers][nz][ny][nx] FP64, device, advanced in place */
+  const double *sx, *sy, *sz; /* face Courant numbers, device, as for vofmt_advect */
+} vofmt_box;
+
+typedef struct {
+  int32_t chunk;             /* cells per thread along the marching axis: 8, 16, 32 or 64 */
+  int32_t workgroups_per_cu; /* persistent grid: workgroups per compute unit, 1..32 */
+} vofmt_tuning;
+
+/*
+ * boxes  : HOST array of nboxes descriptors (device pointers inside). Boxes
+ *          must not share fields.
+ * tuning : HOST, nullable (chunk 32, 8 workgroups per CU).
+ * The launch sequence of all sweeps is captured into a HIP graph on the
+ * context's own stream and launched on `stream`; a call with the same boxes,
+ * tuning, nsteps and step0 mod 3 relaunches the cached graph. A call that
+ * builds a new graph synchronises `stream` once (table upload). Scratch: per
+ * box a second field copy, a face-flux array, the c > 0.5 bits and the lists
+ * of mixed cells, in one slab owned by the context.
+ * Errors: VOFMT_E_ARG for bad sizes, null pointers, ntracers*cells >= 2^32 or
+ * a bad tuning; VOFMT_E_HIP / VOFMT_E_NOMEM from the runtime.
+ */
+int vofmt_advect_batched(vofmt_ctx *ctx, int32_t nboxes, const vofmt_box *boxes, int64_t step0, int32_t nsteps,
+                         const vofmt_tuning *tuning, hipStream_t stream);
+
+/*
+ * Autotuner of vofmt_advect_batched: advances copies of the boxes' fields
+ * (the caller's data is untouched) with each candidate tuning -- chunk
+ * {16, 32, 64} x workgroups per CU {2, 4, 8, 16} -- for nsteps steps, times
+ * each graph launch with HIP events (best of two), and returns the fastest.
+ * best_host: HOST output. best_ms_host: nullable HOST output, its time.
+ * Synchronises. Scratch: one copy of every field.
+ */
+int vofmt_autotune_batched(vofmt_ctx *ctx, int32_t nboxes, const vofmt_box *boxes, int32_t nsteps,
+                           vofmt_tuning *best_host, float *best_ms_host, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

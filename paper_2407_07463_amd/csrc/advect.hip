@@ -1,137 +1,26 @@
-// Direction-split geometric PLIC advection of N tracer fields (eq. 3 of the
-// paper applied to every tracer C_i; its discrete form is the conservative
-// split scheme of Weymouth & Yue 2010 with MYC normals).
-//
-// One launch performs one sweep along axis D for a group of up to 8 tracers.
-// A wavefront owns 64 consecutive x-cells of one row, so every load and store
-// of a field row is a coalesced 512-byte transaction and the c > 0.5
-// indicator of the 64 cells is one 64-bit ballot word. Pure donors (c <= 0 or
-// c >= 1) cost a multiply; mixed donors take the PLIC path (3x3x3 gather, MYC
-// normal, plane constant, sub-box volume), compacted across the workgroup.
-#include "common.hpp"
-#include "plic.hpp"
+// Plain advection entry points: one box, one launch per pass.
+// The kernels are thin wrappers around the shared sweep bodies.
+#include "advect_kernels.hpp"
+
+using namespace advect;
 
 namespace {
 
-constexpr int kChunk = 32;        // cells per thread along its marching axis
+constexpr int kChunk = 32;  // cells per thread along its marching axis
 
-// ---------------------------------------------------------------------------
-// A sweep is two launches.
-//
-// k_plic<D>: one wavefront per region of the list of mixed cells (0 < c < 1)
-//   of the sweep's input field. Each entry gathers its 3x3x3 block, computes
-//   the MYC normal and the plane constant, and writes the flux of every face
-//   the cell donates through (its lower face if s < 0 there, its upper face
-//   if s > 0) into the face-flux array fmix[t][p] (the lower d-face of cell
-//   p). The list is compact, so this FP64 work runs at full SIMD width.
-//
-// k_stream<D,G>: one thread per (x, row) of the plane transverse to its
-//   marching axis, for G tracers at once. For a pure donor the flux is s*c;
-//   for a mixed donor it is read from fmix. Sweeps along y or z march along
-//   the sweep axis and carry c and the lower-face flux in registers, so every
-//   field value is read from memory once; in the x-sweep each lane forms both
-//   of its faces from its own and its neighbour lanes' values. The new field
-//   is written in the same
-//   coalesced row layout, and every new mixed cell is appended to the list of
-//   the next sweep.
-//
-// The list is cut into regions, one per wavefront of the kernel that fills
-// it, each large enough for every cell that wavefront handles: entries are
-// written without atomics, in a fixed order, and the region's length is
-// stored at the end. No barrier, no LDS.
-// ---------------------------------------------------------------------------
-constexpr int kRegion = kChunk * 64 * 8;  // list entries per wavefront region (>= cells of one wavefront)
-
-// Mixed cells of the initial field: wavefront w scans tracer-cells
-// [w*kRegion, (w+1)*kRegion) of the whole array.
 __global__ __launch_bounds__(256) void k_scan_mixed(const double *__restrict__ c, int64_t total,
                                                     uint32_t *__restrict__ list, int *__restrict__ counts,
-                                                    int64_t nregions) {
-  const int lane = threadIdx.x & 63;
-  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (w >= nregions) return;
-  uint32_t *out = list + w * kRegion;
-  int n = 0;
-  const uint64_t below = (1ull << lane) - 1;
-  for (int64_t base = w * kRegion; base < (w + 1) * kRegion && base < total; base += 64) {
-    const int64_t q = base + lane;
-    const bool mixed = (q < total) && c[q] > 0.0 && c[q] < 1.0;
-    const uint64_t mask = __ballot(mixed);
-    if (mixed) out[n + __popcll(mask & below)] = (uint32_t)q;
-    n += __popcll(mask);
-  }
-  if (lane == 0) counts[w] = n;
+                                                    int64_t nregions, int rsize) {
+  scan_body(c, total, list, counts, nregions, rsize, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
 }
-
-struct Divisors {
-  FastDiv n3, nx, ny;  // entry -> (tracer, cell), cell -> (i, j, k)
-};
 
 template <int D>
 __global__ __launch_bounds__(256) void k_plic(const double *__restrict__ cin, const double *__restrict__ s,
                                               const uint32_t *__restrict__ list, const int *__restrict__ counts,
-                                              int64_t nregions, double *__restrict__ fmix, int nx, int ny, int nz,
-                                              Divisors dv) {
-  const int64_t n3 = (int64_t)nx * ny * nz;
-  const int lane = threadIdx.x & 63;
-  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (w >= nregions) return;
-  const int nq = counts[w];
-  const uint32_t *reg = list + w * kRegion;
-  for (int q = lane; q < nq; q += 64) {
-    const uint32_t e = reg[q];
-    const uint32_t t = fast_div(e, dv.n3);
-    const uint32_t p32 = e - t * dv.n3.d;
-    const uint32_t row = fast_div(p32, dv.nx);
-    const int i = (int)(p32 - row * (uint32_t)nx);
-    const uint32_t k32 = fast_div(row, dv.ny);
-    const int j = (int)(row - k32 * (uint32_t)ny), k = (int)k32;
-    const int64_t p = p32;
-    const int64_t pu = (D == 0) ? p - i + wrap_inc(i, nx)
-                                : ((D == 1) ? ((int64_t)k * ny + wrap_inc(j, ny)) * nx + i
-                                            : ((int64_t)wrap_inc(k, nz) * ny + j) * nx + i);
-    const double s_lo = s[p], s_hi = s[pu];
-    if (!(s_lo < 0.0) && !(s_hi > 0.0)) continue;  // donates through neither face
-    const double *ct = cin + t * n3;
-    const double cd = ct[p];
-    double b[27];
-    {
-      const int im = wrap_dec(i, nx), ip = wrap_inc(i, nx);
-      const int jm = wrap_dec(j, ny), jp = wrap_inc(j, ny);
-      const int km = wrap_dec(k, nz), kp = wrap_inc(k, nz);
-      const int xs[3] = {im, i, ip};
-      const int ys[3] = {jm, j, jp};
-      const int zs[3] = {km, k, kp};
-#pragma unroll
-      for (int az = 0; az < 3; ++az)
-#pragma unroll
-        for (int ay = 0; ay < 3; ++ay) {
-          const double *rowp = ct + ((int64_t)zs[az] * ny + ys[ay]) * nx;
-#pragma unroll
-          for (int ax = 0; ax < 3; ++ax) b[ax + 3 * ay + 9 * az] = rowp[xs[ax]];
-        }
-    }
-    double mx, my, mz;
-    plic::myc_normal(b, mx, my, mz);
-    const double alpha = plic::alpha_of(mx, my, mz, cd);
-    const double md = (D == 0) ? mx : ((D == 1) ? my : mz);
-    double *ft = fmix + t * n3;
-    // the faces this cell donates through: the lower one (sub-box [0, |s|]
-    // along D) when s < 0 there, the upper one (sub-box [1 - s, 1]) when s > 0
-#pragma unroll 1
-    for (int face = 0; face < 2; ++face) {
-      const double sv = (face == 0) ? s_lo : s_hi;
-      if (face == 0 ? !(sv < 0.0) : !(sv > 0.0)) continue;
-      const double x0 = (face == 0) ? 0.0 : 1.0 - sv;
-      const double as = alpha - md * x0;
-      const double ms = md * fabs(sv);
-      double v;
-      if (D == 0) v = plic::volume(ms, my, mz, as);
-      else if (D == 1) v = plic::volume(mx, ms, mz, as);
-      else v = plic::volume(mx, my, ms, as);
-      ft[face == 0 ? p : pu] = sv * v;
-    }
-  }
+                                              int64_t nregions, int rsize, double *__restrict__ fmix, int nx, int ny,
+                                              int nz, Divisors dv) {
+  plic_body<D>(cin, s, list, counts, nregions, rsize, fmix, nx, ny, nz, dv,
+               ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
 }
 
 template <int D, int G>
@@ -139,158 +28,9 @@ __global__ __launch_bounds__(256) void k_stream(const double *__restrict__ cin, 
                                                 const double *__restrict__ s, const double *__restrict__ fmix,
                                                 uint64_t *__restrict__ ccbits, int write_cc, int t0, int nx, int ny,
                                                 int nz, int words, int chunk, uint32_t *__restrict__ list_next,
-                                                int *__restrict__ counts_next, int64_t region0) {
-  const int lane = threadIdx.x & 63;
-  const int x = blockIdx.x * 64 + lane;
-  const int row = blockIdx.y * 4 + (threadIdx.x >> 6);
-  const int nrow = (D == 1) ? nz : ny;
-  const int nm = (D == 1) ? ny : nz;
-  const int64_t wave = region0 + (((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * 4 +
-                       (threadIdx.x >> 6);
-  if (row >= nrow) {  // whole wavefront
-    if (lane == 0) counts_next[wave] = 0;
-    return;
-  }
-  uint32_t *reg = list_next + wave * kRegion;
-  int nlist = 0;  // wavefront-uniform
-  const uint64_t below = (1ull << lane) - 1;
-  const bool live = x < nx;
-  const int xs = live ? x : nx - 1;  // dead lanes shadow a valid cell, never store
-  const int64_t n3 = (int64_t)nx * ny * nz;
-  const int64_t nbits = (int64_t)nz * ny * words;
-  const int m0 = blockIdx.z * chunk;
-  const int m1 = (m0 + chunk < nm) ? m0 + chunk : nm;
-  const double *c_g = cin + (int64_t)t0 * n3;
-  double *o_g = cout + (int64_t)t0 * n3;
-  const double *f_g = fmix + (int64_t)t0 * n3;
-  uint64_t *b_g = ccbits + (int64_t)t0 * nbits;
-
-  auto cell = [&](int xx, int mm) -> int64_t {
-    if (D == 1) return ((int64_t)row * ny + mm) * nx + xx;
-    return ((int64_t)mm * ny + row) * nx + xx;
-  };
-  auto bitword = [&](int mm) -> int64_t {
-    if (D == 1) return ((int64_t)row * ny + mm) * words + blockIdx.x;
-    return ((int64_t)mm * ny + row) * words + blockIdx.x;
-  };
-  // flux through the lower face of cell pu: donor = the lower cell (value cl)
-  // if s > 0, else the upper cell (value cu); a mixed donor's flux is in fmix
-  auto flux = [&](int t, double sv, double cl, double cu, int64_t pu) -> double {
-    const double cd = (sv > 0.0) ? cl : cu;
-    const bool mixed = (sv != 0.0) && cd > 0.0 && cd < 1.0;
-    double fv = 0.0;
-    if (mixed) fv = f_g[t * n3 + pu];
-    return mixed ? fv : ((sv == 0.0) ? 0.0 : sv * cd);
-  };
-  // new value of cell pc, its c_c bit, and its entry in the next list
-  auto finish = [&](int t, double cold, double f_lo, double f_hi, double s_lo, double s_hi, int64_t pc, int64_t wrow) {
-    double ccv;
-    if (write_cc) {
-      const uint64_t word = __ballot(live && cold > 0.5);
-      if (lane == 0) b_g[t * nbits + wrow] = word;
-      ccv = (cold > 0.5) ? 1.0 : 0.0;
-    } else {
-      const uint64_t word = b_g[t * nbits + wrow];
-      ccv = ((word >> lane) & 1ull) ? 1.0 : 0.0;
-    }
-    const double cn = (cold - (f_hi - f_lo)) + ccv * (s_hi - s_lo);
-    if (live) o_g[t * n3 + pc] = cn;
-    const bool mixed = live && cn > 0.0 && cn < 1.0;
-    const uint64_t mask = __ballot(mixed);
-    if (mixed) reg[nlist + __popcll(mask & below)] = (uint32_t)((int64_t)(t0 + t) * n3 + pc);
-    nlist += __popcll(mask);
-  };
-
-  if (D != 0) {
-    // ---- march along the sweep axis: faces m0..m1, cells m0..m1-1
-    const int ml = (m0 == 0) ? nm - 1 : m0 - 1;
-    double cm[G], flo[G];
-    const int64_t p0 = cell(xs, m0);
-    const double s0 = s[p0];
-    double s_lo = s0;
-    {
-      const int64_t pl = cell(xs, ml);
-      double cl[G];
-#pragma unroll
-      for (int t = 0; t < G; ++t) {
-        cl[t] = c_g[t * n3 + pl];
-        cm[t] = c_g[t * n3 + p0];
-      }
-#pragma unroll
-      for (int t = 0; t < G; ++t) flo[t] = flux(t, s0, cl[t], cm[t], p0);
-    }
-    for (int m = m0 + 1; m <= m1; ++m) {
-      const int mm = (m == nm) ? 0 : m;
-      const int64_t pu = cell(xs, mm);
-      const int64_t pc = cell(xs, m - 1);
-      const int64_t wrow = bitword(m - 1);
-      const double s_hi = s[pu];
-      double cu[G], fhi[G];
-#pragma unroll
-      for (int t = 0; t < G; ++t) cu[t] = c_g[t * n3 + pu];
-#pragma unroll
-      for (int t = 0; t < G; ++t) fhi[t] = flux(t, s_hi, cm[t], cu[t], pu);
-#pragma unroll
-      for (int t = 0; t < G; ++t) {
-        finish(t, cm[t], flo[t], fhi[t], s_lo, s_hi, pc, wrow);
-        flo[t] = fhi[t];
-        cm[t] = cu[t];
-      }
-      s_lo = s_hi;
-    }
-  } else {
-    // ---- x-sweep: positions are z-planes; faces along x inside the row
-    // each lane forms both of its faces; the neighbours' values come from the
-    // adjacent lanes, except at the two ends of the 64-cell segment
-    const int xl = (xs == 0) ? nx - 1 : xs - 1;
-    const int xr = (xs == nx - 1) ? 0 : xs + 1;
-    const int x_last = (blockIdx.x * 64 + 63 < nx) ? blockIdx.x * 64 + 63 : nx - 1;
-    const bool first = (lane == 0);
-    const bool last = (x == x_last);
-    for (int m = m0; m < m1; ++m) {
-      const int64_t pc = cell(xs, m);
-      const int64_t pl = cell(xl, m);
-      const int64_t pr = cell(xr, m);
-      const int64_t wrow = bitword(m);
-      const double s_lo = s[pc];
-      double c0[G], cl[G], cr[G];
-#pragma unroll
-      for (int t = 0; t < G; ++t) c0[t] = c_g[t * n3 + pc];
-      double s_end = 0.0, c_beg[G], c_end[G];
-#pragma unroll
-      for (int t = 0; t < G; ++t) {
-        c_beg[t] = 0.0;
-        c_end[t] = 0.0;
-      }
-      if (first) {
-#pragma unroll
-        for (int t = 0; t < G; ++t) c_beg[t] = c_g[t * n3 + pl];
-      }
-      if (last) {
-        s_end = s[pr];
-#pragma unroll
-        for (int t = 0; t < G; ++t) c_end[t] = c_g[t * n3 + pr];
-      }
-      const double s_dn = __shfl_down(s_lo, 1, 64);
-      const double s_hi = last ? s_end : s_dn;
-#pragma unroll
-      for (int t = 0; t < G; ++t) {
-        const double up = __shfl_up(c0[t], 1, 64);
-        const double dn = __shfl_down(c0[t], 1, 64);
-        cl[t] = first ? c_beg[t] : up;
-        cr[t] = last ? c_end[t] : dn;
-      }
-      double flo[G], fhi[G];
-#pragma unroll
-      for (int t = 0; t < G; ++t) {
-        flo[t] = flux(t, s_lo, cl[t], c0[t], pc);
-        fhi[t] = flux(t, s_hi, c0[t], cr[t], pr);
-      }
-#pragma unroll
-      for (int t = 0; t < G; ++t) finish(t, c0[t], flo[t], fhi[t], s_lo, s_hi, pc, wrow);
-    }
-  }
-  if (lane == 0) counts_next[wave] = nlist;
+                                                int *__restrict__ counts_next, int64_t region0, int rsize) {
+  stream_body<D, G>(cin, cout, s, fmix, ccbits, write_cc, t0, nx, ny, nz, words, chunk, list_next, counts_next,
+                    region0, rsize, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gridDim.y);
 }
 
 // Per-block maximum of |s| over the three arrays and a non-finite flag.
@@ -320,14 +60,8 @@ struct SweepBuffers {
   uint32_t *list[2];
   int *counts[2];
   int64_t nregions[2];  // regions filled into each list
+  int rsize;
 };
-
-// Wavefronts of one k_stream launch along axis d (each owns one list region).
-static int64_t stream_waves(int d, int nx, int ny, int nz, int chunk) {
-  const int nrow = (d == 1) ? nz : ny;
-  const int nm = (d == 1) ? ny : nz;
-  return 4 * (int64_t)ceil_div(nx, 64) * ceil_div(nrow, 4) * ceil_div(nm, chunk);
-}
 
 template <int D, int G>
 static void launch_stream(const double *cin, double *cout, const double *s, SweepBuffers &sb, int wcc, int t0, int nx,
@@ -336,24 +70,7 @@ static void launch_stream(const double *cin, double *cout, const double *s, Swee
   const int nm = (D == 1) ? ny : nz;
   dim3 grid(words, ceil_div(nrow, 4), ceil_div(nm, chunk));
   hipLaunchKernelGGL((k_stream<D, G>), grid, dim3(256), 0, stream, cin, cout, s, sb.fmix, sb.bits, wcc, t0, nx, ny,
-                     nz, words, chunk, sb.list[nxt], sb.counts[nxt], region0);
-}
-
-// Tracer groups of one sweep: kMaxGroup tracers at a time, then groups of
-// 4, 2 and 1 for the rest. Both the launches and the sizing of the list
-// regions use this one function.
-constexpr int kMaxGroup = 4;
-static_assert(kMaxGroup <= 8 && kRegion >= kChunk * 64 * kMaxGroup, "list regions must hold a wavefront's cells");
-static int group_size(int left) {
-  if (left >= kMaxGroup) return kMaxGroup;
-  if (left >= 4) return 4;
-  if (left >= 2) return 2;
-  return 1;
-}
-static int num_groups(int ntr) {
-  int n = 0;
-  for (int t = 0; t < ntr; t += group_size(ntr - t)) ++n;
-  return n;
+                     nz, words, chunk, sb.list[nxt], sb.counts[nxt], region0, sb.rsize);
 }
 
 template <int D>
@@ -366,14 +83,14 @@ static void launch_sweep_axis(const double *cin, double *cout, const double *s, 
   dv.nx = make_fastdiv((uint32_t)nx);
   dv.ny = make_fastdiv((uint32_t)ny);
   hipLaunchKernelGGL((k_plic<D>), dim3(ceil_div(nreg, 4)), dim3(256), 0, stream, cin, s, sb.list[cur],
-                     sb.counts[cur], nreg, sb.fmix, nx, ny, nz, dv);
+                     sb.counts[cur], nreg, sb.rsize, sb.fmix, nx, ny, nz, dv);
   const int64_t per = stream_waves(D, nx, ny, nz, chunk);
   int64_t region0 = 0;
   int t = 0;
   while (t < ntr) {
     const int g = group_size(ntr - t);
-    if (g == 8) launch_stream<D, 8>(cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, stream);
-    else if (g == 4) launch_stream<D, 4>(cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, stream);
+    static_assert(kMaxGroup == 4, "streaming passes are instantiated for groups of 4, 2 and 1");
+    if (g == 4) launch_stream<D, 4>(cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, stream);
     else if (g == 2) launch_stream<D, 2>(cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, stream);
     else launch_stream<D, 1>(cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, stream);
     t += g;
@@ -411,32 +128,28 @@ extern "C" int vofmt_advect(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, 
   double *fmix = (double *)scratch(ctx, SLOT_FMIX, field_bytes);
   uint64_t *bits = (uint64_t *)scratch(ctx, SLOT_CCBITS, sizeof(uint64_t) * (size_t)ntracers * nz * ny * words);
   // list regions: enough for the largest sweep launch set and for the initial scan
-  const int ngroups = num_groups(ntracers);
-  int64_t maxreg = 0;
-  for (int d = 0; d < 3; ++d) {
-    const int64_t r = stream_waves(d, nx, ny, nz, kChunk) * ngroups;
-    maxreg = r > maxreg ? r : maxreg;
-  }
+  const int rsize = region_size(kChunk);
+  const int64_t maxreg = max_regions(nx, ny, nz, ntracers, kChunk);
   const int64_t total = (int64_t)ntracers * n3;
-  const int64_t scanreg = (total + kRegion - 1) / kRegion;
-  maxreg = scanreg > maxreg ? scanreg : maxreg;
-  uint32_t *lists = (uint32_t *)scratch(ctx, SLOT_MIXLIST, sizeof(uint32_t) * 2 * (size_t)maxreg * kRegion);
+  const int64_t scanreg = (total + rsize - 1) / rsize;
+  uint32_t *lists = (uint32_t *)scratch(ctx, SLOT_MIXLIST, sizeof(uint32_t) * 2 * (size_t)maxreg * rsize);
   int *counts = (int *)scratch(ctx, SLOT_COUNTS, sizeof(int) * 2 * (size_t)maxreg);
   if (!tmp || !fmix || !bits || !lists || !counts) return VOFMT_E_NOMEM;
   SweepBuffers sb;
   sb.fmix = fmix;
   sb.bits = bits;
   sb.list[0] = lists;
-  sb.list[1] = lists + (size_t)maxreg * kRegion;
+  sb.list[1] = lists + (size_t)maxreg * rsize;
   sb.counts[0] = counts;
   sb.counts[1] = counts + maxreg;
   sb.nregions[0] = scanreg;
   sb.nregions[1] = 0;
+  sb.rsize = rsize;
   const double *s3[3] = {sx, sy, sz};
   const int chunk = kChunk;
   // mixed cells of the input field
   hipLaunchKernelGGL(k_scan_mixed, dim3(ceil_div(scanreg, 4)), dim3(256), 0, stream, c, total, sb.list[0],
-                     sb.counts[0], scanreg);
+                     sb.counts[0], scanreg, rsize);
   VOFMT_HIP(ctx, hipGetLastError());
   int cur_list = 0;
   double *cur = c, *nxt = tmp;

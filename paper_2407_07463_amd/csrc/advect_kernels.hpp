@@ -1,0 +1,330 @@
+// Device bodies of one advection sweep, shared by the plain launches
+// (vofmt_advect) and the batched persistent launches (vofmt_advect_batched):
+// both paths run exactly this code, so their results agree bit for bit.
+//
+// Direction-split geometric PLIC advection of N tracer fields (eq. 3 of the
+// paper applied to every tracer C_i; its discrete form is the conservative
+// split scheme of Weymouth & Yue 2010 with MYC normals).
+//
+// A sweep is two passes.
+//
+// plic_body<D>: one wavefront per region of the list of mixed cells
+//   (0 < c < 1) of the sweep's input field. Each entry gathers its 3x3x3
+//   block, computes the MYC normal and the plane constant, and writes the flux
+//   of every face the cell donates through (its lower face if s < 0 there, its
+//   upper face if s > 0) into the face-flux array fmix[t][p] (the lower d-face
+//   of cell p). The list is compact, so this FP64 work runs at full SIMD width.
+//
+// stream_body<D,G>: one thread per (x, row) of the plane transverse to its
+//   marching axis, for G tracers at once. For a pure donor the flux is s*c;
+//   for a mixed donor it is read from fmix. Sweeps along y or z march along
+//   the sweep axis and carry c and the lower-face flux in registers, so every
+//   field value is read from memory once; in the x-sweep each lane forms both
+//   of its faces from its own and its neighbour lanes' values. A wavefront
+//   owns 64 consecutive x-cells of one row, so every load and store of a field
+//   row is a coalesced 512-byte transaction and the c > 0.5 indicator of the
+//   64 cells is one 64-bit ballot word. The new field is written in the same
+//   row layout, and every new mixed cell is appended to the list of the next
+//   sweep.
+//
+// The list is cut into regions of rsize entries, one per wavefront of the
+// pass that fills it, each large enough for every cell that wavefront handles
+// (64 * chunk * G): entries are written without atomics, in a fixed order,
+// and the region's length is stored beside it. No barrier, no LDS.
+#pragma once
+
+#include "common.hpp"
+#include "plic.hpp"
+
+namespace advect {
+
+constexpr int kMaxGroup = 4;  // tracers per streaming pass (register budget)
+
+struct Divisors {
+  FastDiv n3, nx, ny;  // entry -> (tracer, cell), cell -> (i, j, k)
+};
+
+// Mixed cells of the initial field: wavefront w scans tracer-cells
+// [w*rsize, (w+1)*rsize) of the whole array.
+__device__ __forceinline__ void scan_body(const double *__restrict__ c, int64_t total, uint32_t *__restrict__ list,
+                                          int *__restrict__ counts, int64_t nregions, int rsize, int64_t w) {
+  const int lane = threadIdx.x & 63;
+  if (w >= nregions) return;
+  uint32_t *out = list + w * rsize;
+  int n = 0;
+  const uint64_t below = (1ull << lane) - 1;
+  for (int64_t base = w * rsize; base < (w + 1) * rsize && base < total; base += 64) {
+    const int64_t q = base + lane;
+    const bool mixed = (q < total) && c[q] > 0.0 && c[q] < 1.0;
+    const uint64_t mask = __ballot(mixed);
+    if (mixed) out[n + __popcll(mask & below)] = (uint32_t)q;
+    n += __popcll(mask);
+  }
+  if (lane == 0) counts[w] = n;
+}
+
+template <int D>
+__device__ __forceinline__ void plic_body(const double *__restrict__ cin, const double *__restrict__ s,
+                                          const uint32_t *__restrict__ list, const int *__restrict__ counts,
+                                          int64_t nregions, int rsize, double *__restrict__ fmix, int nx, int ny,
+                                          int nz, const Divisors &dv, int64_t w) {
+  const int64_t n3 = (int64_t)nx * ny * nz;
+  const int lane = threadIdx.x & 63;
+  if (w >= nregions) return;
+  const int nq = counts[w];
+  const uint32_t *reg = list + w * rsize;
+  for (int q = lane; q < nq; q += 64) {
+    const uint32_t e = reg[q];
+    const uint32_t t = fast_div(e, dv.n3);
+    const uint32_t p32 = e - t * dv.n3.d;
+    const uint32_t row = fast_div(p32, dv.nx);
+    const int i = (int)(p32 - row * (uint32_t)nx);
+    const uint32_t k32 = fast_div(row, dv.ny);
+    const int j = (int)(row - k32 * (uint32_t)ny), k = (int)k32;
+    const int64_t p = p32;
+    const int64_t pu = (D == 0) ? p - i + wrap_inc(i, nx)
+                                : ((D == 1) ? ((int64_t)k * ny + wrap_inc(j, ny)) * nx + i
+                                            : ((int64_t)wrap_inc(k, nz) * ny + j) * nx + i);
+    const double s_lo = s[p], s_hi = s[pu];
+    if (!(s_lo < 0.0) && !(s_hi > 0.0)) continue;  // donates through neither face
+    const double *ct = cin + t * n3;
+    const double cd = ct[p];
+    double b[27];
+    {
+      const int im = wrap_dec(i, nx), ip = wrap_inc(i, nx);
+      const int jm = wrap_dec(j, ny), jp = wrap_inc(j, ny);
+      const int km = wrap_dec(k, nz), kp = wrap_inc(k, nz);
+      const int xs[3] = {im, i, ip};
+      const int ys[3] = {jm, j, jp};
+      const int zs[3] = {km, k, kp};
+#pragma unroll
+      for (int az = 0; az < 3; ++az)
+#pragma unroll
+        for (int ay = 0; ay < 3; ++ay) {
+          const double *rowp = ct + ((int64_t)zs[az] * ny + ys[ay]) * nx;
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax) b[ax + 3 * ay + 9 * az] = rowp[xs[ax]];
+        }
+    }
+    double mx, my, mz;
+    plic::myc_normal(b, mx, my, mz);
+    const double alpha = plic::alpha_of(mx, my, mz, cd);
+    const double md = (D == 0) ? mx : ((D == 1) ? my : mz);
+    double *ft = fmix + t * n3;
+    // the faces this cell donates through: the lower one (sub-box [0, |s|]
+    // along D) when s < 0 there, the upper one (sub-box [1 - s, 1]) when s > 0
+#pragma unroll 1
+    for (int face = 0; face < 2; ++face) {
+      const double sv = (face == 0) ? s_lo : s_hi;
+      if (face == 0 ? !(sv < 0.0) : !(sv > 0.0)) continue;
+      const double x0 = (face == 0) ? 0.0 : 1.0 - sv;
+      const double as = alpha - md * x0;
+      const double ms = md * fabs(sv);
+      double v;
+      if (D == 0) v = plic::volume(ms, my, mz, as);
+      else if (D == 1) v = plic::volume(mx, ms, mz, as);
+      else v = plic::volume(mx, my, ms, as);
+      ft[face == 0 ? p : pu] = sv * v;
+    }
+  }
+}
+
+// Tile (bx, by, bz) of a streaming pass laid out as a gx x gy x gz grid of
+// 4-wavefront workgroups: bx picks 64 x-cells, by four rows, bz a chunk of
+// the marching axis.
+template <int D, int G>
+__device__ __forceinline__ void stream_body(const double *__restrict__ cin, double *__restrict__ cout,
+                                            const double *__restrict__ s, const double *__restrict__ fmix,
+                                            uint64_t *__restrict__ ccbits, int write_cc, int t0, int nx, int ny,
+                                            int nz, int words, int chunk, uint32_t *__restrict__ list_next,
+                                            int *__restrict__ counts_next, int64_t region0, int rsize, int bx, int by,
+                                            int bz, int gx, int gy) {
+  const int lane = threadIdx.x & 63;
+  const int x = bx * 64 + lane;
+  const int row = by * 4 + (threadIdx.x >> 6);
+  const int nrow = (D == 1) ? nz : ny;
+  const int nm = (D == 1) ? ny : nz;
+  const int64_t wave = region0 + (((int64_t)bz * gy + by) * gx + bx) * 4 + (threadIdx.x >> 6);
+  if (row >= nrow) {  // whole wavefront
+    if (lane == 0) counts_next[wave] = 0;
+    return;
+  }
+  uint32_t *reg = list_next + wave * rsize;
+  int nlist = 0;  // wavefront-uniform
+  const uint64_t below = (1ull << lane) - 1;
+  const bool live = x < nx;
+  const int xs = live ? x : nx - 1;  // dead lanes shadow a valid cell, never store
+  const int64_t n3 = (int64_t)nx * ny * nz;
+  const int64_t nbits = (int64_t)nz * ny * words;
+  const int m0 = bz * chunk;
+  const int m1 = (m0 + chunk < nm) ? m0 + chunk : nm;
+  const double *c_g = cin + (int64_t)t0 * n3;
+  double *o_g = cout + (int64_t)t0 * n3;
+  const double *f_g = fmix + (int64_t)t0 * n3;
+  uint64_t *b_g = ccbits + (int64_t)t0 * nbits;
+
+  auto cell = [&](int xx, int mm) -> int64_t {
+    if (D == 1) return ((int64_t)row * ny + mm) * nx + xx;
+    return ((int64_t)mm * ny + row) * nx + xx;
+  };
+  auto bitword = [&](int mm) -> int64_t {
+    if (D == 1) return ((int64_t)row * ny + mm) * words + bx;
+    return ((int64_t)mm * ny + row) * words + bx;
+  };
+  // flux through the lower face of cell pu: donor = the lower cell (value cl)
+  // if s > 0, else the upper cell (value cu); a mixed donor's flux is in fmix
+  auto flux = [&](int t, double sv, double cl, double cu, int64_t pu) -> double {
+    const double cd = (sv > 0.0) ? cl : cu;
+    const bool mixed = (sv != 0.0) && cd > 0.0 && cd < 1.0;
+    double fv = 0.0;
+    if (mixed) fv = f_g[t * n3 + pu];
+    return mixed ? fv : ((sv == 0.0) ? 0.0 : sv * cd);
+  };
+  // new value of cell pc, its c_c bit, and its entry in the next list
+  auto finish = [&](int t, double cold, double f_lo, double f_hi, double s_lo, double s_hi, int64_t pc, int64_t wrow) {
+    double ccv;
+    if (write_cc) {
+      const uint64_t word = __ballot(live && cold > 0.5);
+      if (lane == 0) b_g[t * nbits + wrow] = word;
+      ccv = (cold > 0.5) ? 1.0 : 0.0;
+    } else {
+      const uint64_t word = b_g[t * nbits + wrow];
+      ccv = ((word >> lane) & 1ull) ? 1.0 : 0.0;
+    }
+    const double cn = (cold - (f_hi - f_lo)) + ccv * (s_hi - s_lo);
+    if (live) o_g[t * n3 + pc] = cn;
+    const bool mixed = live && cn > 0.0 && cn < 1.0;
+    const uint64_t mask = __ballot(mixed);
+    if (mixed) reg[nlist + __popcll(mask & below)] = (uint32_t)((int64_t)(t0 + t) * n3 + pc);
+    nlist += __popcll(mask);
+  };
+
+  if (D != 0) {
+    // ---- march along the sweep axis: faces m0..m1, cells m0..m1-1
+    const int ml = (m0 == 0) ? nm - 1 : m0 - 1;
+    double cm[G], flo[G];
+    const int64_t p0 = cell(xs, m0);
+    const double s0 = s[p0];
+    double s_lo = s0;
+    {
+      const int64_t pl = cell(xs, ml);
+      double cl[G];
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        cl[t] = c_g[t * n3 + pl];
+        cm[t] = c_g[t * n3 + p0];
+      }
+#pragma unroll
+      for (int t = 0; t < G; ++t) flo[t] = flux(t, s0, cl[t], cm[t], p0);
+    }
+    for (int m = m0 + 1; m <= m1; ++m) {
+      const int mm = (m == nm) ? 0 : m;
+      const int64_t pu = cell(xs, mm);
+      const int64_t pc = cell(xs, m - 1);
+      const int64_t wrow = bitword(m - 1);
+      const double s_hi = s[pu];
+      double cu[G], fhi[G];
+#pragma unroll
+      for (int t = 0; t < G; ++t) cu[t] = c_g[t * n3 + pu];
+#pragma unroll
+      for (int t = 0; t < G; ++t) fhi[t] = flux(t, s_hi, cm[t], cu[t], pu);
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        finish(t, cm[t], flo[t], fhi[t], s_lo, s_hi, pc, wrow);
+        flo[t] = fhi[t];
+        cm[t] = cu[t];
+      }
+      s_lo = s_hi;
+    }
+  } else {
+    // ---- x-sweep: positions are z-planes; faces along x inside the row
+    // each lane forms both of its faces; the neighbours' values come from the
+    // adjacent lanes, except at the two ends of the 64-cell segment
+    const int xl = (xs == 0) ? nx - 1 : xs - 1;
+    const int xr = (xs == nx - 1) ? 0 : xs + 1;
+    const int x_last = (bx * 64 + 63 < nx) ? bx * 64 + 63 : nx - 1;
+    const bool first = (lane == 0);
+    const bool last = (x == x_last);
+    for (int m = m0; m < m1; ++m) {
+      const int64_t pc = cell(xs, m);
+      const int64_t pl = cell(xl, m);
+      const int64_t pr = cell(xr, m);
+      const int64_t wrow = bitword(m);
+      const double s_lo = s[pc];
+      double c0[G], cl[G], cr[G];
+#pragma unroll
+      for (int t = 0; t < G; ++t) c0[t] = c_g[t * n3 + pc];
+      double s_end = 0.0, c_beg[G], c_end[G];
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        c_beg[t] = 0.0;
+        c_end[t] = 0.0;
+      }
+      if (first) {
+#pragma unroll
+        for (int t = 0; t < G; ++t) c_beg[t] = c_g[t * n3 + pl];
+      }
+      if (last) {
+        s_end = s[pr];
+#pragma unroll
+        for (int t = 0; t < G; ++t) c_end[t] = c_g[t * n3 + pr];
+      }
+      const double s_dn = __shfl_down(s_lo, 1, 64);
+      const double s_hi = last ? s_end : s_dn;
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        const double up = __shfl_up(c0[t], 1, 64);
+        const double dn = __shfl_down(c0[t], 1, 64);
+        cl[t] = first ? c_beg[t] : up;
+        cr[t] = last ? c_end[t] : dn;
+      }
+      double flo[G], fhi[G];
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        flo[t] = flux(t, s_lo, cl[t], c0[t], pc);
+        fhi[t] = flux(t, s_hi, c0[t], cr[t], pr);
+      }
+#pragma unroll
+      for (int t = 0; t < G; ++t) finish(t, c0[t], flo[t], fhi[t], s_lo, s_hi, pc, wrow);
+    }
+  }
+  if (lane == 0) counts_next[wave] = nlist;
+}
+
+// ---------------------------------------------------------------- host side
+
+// Wavefronts of one streaming pass along axis d (each owns one list region).
+static inline int64_t stream_waves(int d, int nx, int ny, int nz, int chunk) {
+  const int nrow = (d == 1) ? nz : ny;
+  const int nm = (d == 1) ? ny : nz;
+  return 4 * (int64_t)ceil_div(nx, 64) * ceil_div(nrow, 4) * ceil_div(nm, chunk);
+}
+
+// Tracer groups of one sweep: kMaxGroup tracers at a time, then groups of
+// 2 and 1 for the rest. Launches and the sizing of the list regions both use
+// these functions.
+static inline int group_size(int left) {
+  if (left >= kMaxGroup) return kMaxGroup;
+  if (left >= 2) return 2;
+  return 1;
+}
+static inline int num_groups(int ntr) {
+  int n = 0;
+  for (int t = 0; t < ntr; t += group_size(ntr - t)) ++n;
+  return n;
+}
+// List entries per region: every cell a wavefront of a streaming pass writes.
+static inline int region_size(int chunk) { return 64 * chunk * kMaxGroup; }
+// Regions of one list: the largest streaming sweep, or the initial scan.
+static inline int64_t max_regions(int nx, int ny, int nz, int ntr, int chunk) {
+  int64_t r = 0;
+  for (int d = 0; d < 3; ++d) {
+    const int64_t w = stream_waves(d, nx, ny, nz, chunk) * num_groups(ntr);
+    r = w > r ? w : r;
+  }
+  const int64_t total = (int64_t)ntr * nx * ny * nz;
+  const int64_t scan = (total + region_size(chunk) - 1) / region_size(chunk);
+  return scan > r ? scan : r;
+}
+
+}  // namespace advect

@@ -79,6 +79,8 @@ extern "C" void vofmt_destroy(vofmt_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
+  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   for (int i = 0; i < kNumSlots; ++i)
     if (ctx->buf[i]) (void)hipFree(ctx->buf[i]);
   if (ctx->host) (void)hipHostFree(ctx->host);

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "vofmt.h"
 
@@ -19,6 +20,12 @@ struct vofmt_ctx {
   // Pinned host staging for small results read back by synchronising calls.
   void *host = nullptr;
   size_t host_cap = 0;
+  // Batched advection: the captured graph of the last configuration, the
+  // stream it was captured on, its key, and the host copy of its tables.
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  std::string graph_key;
+  std::vector<uint8_t> tables;
 };
 
 // Scratch slots (one buffer per role).
@@ -41,6 +48,8 @@ enum ScratchSlot {
   SLOT_MLP_X = 15,     // canonical stencils, network outputs
   SLOT_MLP_CELL = 16,  // their cells
   SLOT_MLP_SIGN = 17,  // and orientation signs
+  SLOT_BATCH = 18,     // batched advection: per-box work buffers and tables
+  SLOT_TUNE = 19,      // autotuner: copies of the fields it advects
   kNumSlots = 24,
 };
 

@@ -327,3 +327,24 @@ def drops512(seed: int | None = None, **kw):
     d = random_drops(512, 8, 0.3, 24.0, 0.1, 1.0, seed, **kw)
     d.update(name="drops512", nsteps=100)
     return d
+
+
+def batch_boxes(nboxes: int = 32, sizes=(64, 96, 128, 160, 192), seed: int | None = None,
+                diameter: float = 20.0, phi_range=(0.05, 0.3), tracer_range=(2, 8), gap: float = 1.0,
+                workers: int | None = None):
+    """Uneven boxes for batched advection: each box is cubic with its edge drawn
+    from `sizes`, 2-8 tracers and a drop volume fraction in [0.05, 0.3] (all
+    drawn from one seeded stream), filled like `random_drops` (surface gap of
+    1 cell, as for the 512^3 field: 2 cells jam random sequential addition
+    near phi = 0.3) with its own random Fourier velocity."""
+    seed = workload_seed(4) if seed is None else seed
+    rng = Splitmix64(seed)
+    out = []
+    for b in range(nboxes):
+        n = int(sizes[min(int(rng.uniform(1)[0] * len(sizes)), len(sizes) - 1)])
+        lo, hi = tracer_range
+        ntr = lo + min(int(rng.uniform(1)[0] * (hi - lo + 1)), hi - lo)
+        phi = phi_range[0] + (phi_range[1] - phi_range[0]) * rng.uniform(1)[0]
+        d = min(diameter, 0.3 * n)
+        out.append(random_drops(n, ntr, phi, d, 0.0, gap, seed + 7919 * (b + 1), workers=workers))
+    return out

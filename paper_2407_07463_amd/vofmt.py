@@ -21,6 +21,18 @@ OK, E_ARG, E_CFL, E_CAPACITY, E_EXTENT, E_NONFINITE, E_HIP, E_NOMEM = 0, -1, -2,
 _NAMES = {E_ARG: "E_ARG", E_CFL: "E_CFL", E_CAPACITY: "E_CAPACITY", E_EXTENT: "E_EXTENT",
           E_NONFINITE: "E_NONFINITE", E_HIP: "E_HIP", E_NOMEM: "E_NOMEM"}
 
+class Box(ctypes.Structure):
+    """vofmt_box: one box of a batched advection (device pointers inside)."""
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("ntracers", ctypes.c_int32), ("c", ctypes.c_void_p), ("sx", ctypes.c_void_p),
+                ("sy", ctypes.c_void_p), ("sz", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    """vofmt_tuning: tile parameters of the batched advection."""
+    _fields_ = [("chunk", ctypes.c_int32), ("workgroups_per_cu", ctypes.c_int32)]
+
+
 # Every symbol include/vofmt.h declares, with (restype, argtypes).
 _vp, _i32, _i64, _d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 _P_i32 = ctypes.POINTER(ctypes.c_int32)
@@ -43,6 +55,10 @@ _SIGNATURES = {
                                             ctypes.POINTER(ctypes.c_float), _vp]),
     "vofmt_mlp_stencils": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _P_i32, _vp]),
     "vofmt_curvature_mlp": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _d, _vp, _vp, _P_i32, _vp]),
+    "vofmt_advect_batched": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(Box), _i64, _i32, ctypes.POINTER(Tuning),
+                                            _vp]),
+    "vofmt_autotune_batched": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(Box), _i32, ctypes.POINTER(Tuning),
+                                              ctypes.POINTER(ctypes.c_float), _vp]),
 }
 
 MLP_NPARAMS = 20868
@@ -141,6 +157,34 @@ class Context:
         self._check(load().vofmt_check_courant(self.h, nx, ny, nz, _ptr(sx), _ptr(sy), _ptr(sz), ctypes.byref(out),
                                                _stream(stream)))
         return out.value
+
+    def _boxes(self, boxes):
+        """[(c, sx, sy, sz), ...] -> ctypes array of vofmt_box."""
+        arr = (Box * len(boxes))()
+        for i, (c, sx, sy, sz) in enumerate(boxes):
+            _require(c, sx, sy, sz)
+            nx, ny, nz = _dims(c)
+            for t in (sx, sy, sz):
+                assert tuple(t.shape) == (nz, ny, nx)
+            ntr = int(c.shape[0]) if c.dim() == 4 else 1
+            arr[i] = Box(nx, ny, nz, ntr, c.data_ptr(), sx.data_ptr(), sy.data_ptr(), sz.data_ptr())
+        return arr
+
+    def advect_batched(self, boxes, step0: int = 0, nsteps: int = 1, tuning=None, stream=None):
+        """Advect every (c, sx, sy, sz) of `boxes` in place with one graph launch."""
+        arr = self._boxes(boxes)
+        tp = None if tuning is None else ctypes.byref(Tuning(int(tuning[0]), int(tuning[1])))
+        return self._check(load().vofmt_advect_batched(self.h, len(boxes), arr, int(step0), int(nsteps), tp,
+                                                       _stream(stream)))
+
+    def autotune_batched(self, boxes, nsteps: int = 1, stream=None):
+        """Fastest (chunk, workgroups_per_cu) for these boxes, and its time in ms."""
+        arr = self._boxes(boxes)
+        best = Tuning(0, 0)
+        ms = ctypes.c_float(0.0)
+        self._check(load().vofmt_autotune_batched(self.h, len(boxes), arr, int(nsteps), ctypes.byref(best),
+                                                  ctypes.byref(ms), _stream(stream)))
+        return (best.chunk, best.workgroups_per_cu), ms.value
 
     # ------------------------------------------------------------ drops
     def label_drops(self, c, labels, c_eps: float = 1e-6, stream=None):
