@@ -182,6 +182,8 @@ int vofmt_nearest_pair_stats(vofmt_ctx *ctx, int32_t n, const double *xyz, const
  * kappa : [nz][ny][nx] FP64 output, kappa*Delta, NaN where undefined.
  * status: [nz][ny][nx] uint8 output: 0 not an interface cell, 1..3 valid on
  *         the 1st..3rd axis tried, 4 no valid axis.
+ * The mixed cells are first gathered into a list (scratch: one int32 per
+ * cell), then one thread per listed cell evaluates the columns.
  */
 int vofmt_curvature_hf(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, const double *c, double *kappa,
                        uint8_t *status, hipStream_t stream);
@@ -252,11 +254,12 @@ int vofmt_mlp_stencils(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, const
 
 /*
  * Curvature of one tracer by the network with height functions as the
- * fallback: height functions first (as vofmt_curvature_hf); then for every
- * mixed cell kappa = sign * MLP(canonical stencil) replaces the height-function
- * value unless that value is valid and |kappa_mlp| < kappa_lo (radii the
- * 3x3x3 stencil cannot resolve). status: the height-function status, plus 8
- * where the network's value is used.
+ * fallback: for every mixed cell kappa = sign * MLP(canonical stencil); where
+ * |kappa| < kappa_lo (radii the 3x3x3 stencil cannot resolve) the height
+ * function is evaluated and replaces it when valid. status: 0 not a mixed
+ * cell (kappa NaN); 8 the network's value; 1..3 the height function's value
+ * (valid on the 1st..3rd axis tried); 12 the network's value where the
+ * height function was tried and had no valid axis.
  * nmixed_host: nullable HOST output, the number of mixed cells (the call
  *              synchronises once to size its work).
  */
@@ -308,6 +311,24 @@ int vofmt_advect_batched(vofmt_ctx *ctx, int32_t nboxes, const vofmt_box *boxes,
  */
 int vofmt_autotune_batched(vofmt_ctx *ctx, int32_t nboxes, const vofmt_box *boxes, int32_t nsteps,
                            vofmt_tuning *best_host, float *best_ms_host, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Instrumentation: per-launch timing of this context's kernels with HIP
+ * events recorded on the launch stream around every launch of the plain
+ * advection passes, the curvature kernels and the network kernels (not inside
+ * the batched graph). For benchmarks and tests; adds two event records per
+ * launch while on.
+ * ------------------------------------------------------------------------ */
+/* Clears the records and starts recording. */
+int vofmt_profile_start(vofmt_ctx *ctx);
+/*
+ * Stops recording and reports, per kernel kind in order of first launch:
+ * names [max_kinds][48] (NUL-terminated), launches [max_kinds], total_ms
+ * [max_kinds] (HOST arrays). nkinds_host gets the number of kinds seen (kinds
+ * beyond max_kinds are not reported). Synchronises with every recorded event.
+ */
+int vofmt_profile_stop(vofmt_ctx *ctx, int32_t max_kinds, char *names, int32_t *launches, double *total_ms,
+                       int32_t *nkinds_host);
 
 #ifdef __cplusplus
 }

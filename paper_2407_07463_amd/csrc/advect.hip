@@ -63,47 +63,61 @@ struct SweepBuffers {
   int rsize;
 };
 
+static const char *stream_name(int d, int g) {
+  static const char *names[3][3] = {{"k_stream<0,1>", "k_stream<0,2>", "k_stream<0,4>"},
+                                    {"k_stream<1,1>", "k_stream<1,2>", "k_stream<1,4>"},
+                                    {"k_stream<2,1>", "k_stream<2,2>", "k_stream<2,4>"}};
+  return names[d][g == 4 ? 2 : (g == 2 ? 1 : 0)];
+}
+
 template <int D, int G>
-static void launch_stream(const double *cin, double *cout, const double *s, SweepBuffers &sb, int wcc, int t0, int nx,
-                          int ny, int nz, int words, int chunk, int nxt, int64_t region0, hipStream_t stream) {
+static void launch_stream(vofmt_ctx *ctx, const double *cin, double *cout, const double *s, SweepBuffers &sb, int wcc,
+                          int t0, int nx, int ny, int nz, int words, int chunk, int nxt, int64_t region0,
+                          hipStream_t stream) {
   const int nrow = (D == 1) ? nz : ny;
   const int nm = (D == 1) ? ny : nz;
   dim3 grid(words, ceil_div(nrow, 4), ceil_div(nm, chunk));
+  const int rec = prof_begin(ctx, stream_name(D, G), stream);
   hipLaunchKernelGGL((k_stream<D, G>), grid, dim3(256), 0, stream, cin, cout, s, sb.fmix, sb.bits, wcc, t0, nx, ny,
                      nz, words, chunk, sb.list[nxt], sb.counts[nxt], region0, sb.rsize);
+  prof_end(ctx, rec, stream);
 }
 
 template <int D>
-static void launch_sweep_axis(const double *cin, double *cout, const double *s, SweepBuffers &sb, int wcc, int cur,
-                              int nx, int ny, int nz, int ntr, int words, int chunk, hipStream_t stream) {
+static void launch_sweep_axis(vofmt_ctx *ctx, const double *cin, double *cout, const double *s, SweepBuffers &sb,
+                              int wcc, int cur, int nx, int ny, int nz, int ntr, int words, int chunk,
+                              hipStream_t stream) {
   const int nxt = cur ^ 1;
   const int64_t nreg = sb.nregions[cur];
   Divisors dv;
   dv.n3 = make_fastdiv((uint32_t)((int64_t)nx * ny * nz));
   dv.nx = make_fastdiv((uint32_t)nx);
   dv.ny = make_fastdiv((uint32_t)ny);
+  static const char *plic_names[3] = {"k_plic<0>", "k_plic<1>", "k_plic<2>"};
+  const int rec = prof_begin(ctx, plic_names[D], stream);
   hipLaunchKernelGGL((k_plic<D>), dim3(ceil_div(nreg, 4)), dim3(256), 0, stream, cin, s, sb.list[cur],
                      sb.counts[cur], nreg, sb.rsize, sb.fmix, nx, ny, nz, dv);
+  prof_end(ctx, rec, stream);
   const int64_t per = stream_waves(D, nx, ny, nz, chunk);
   int64_t region0 = 0;
   int t = 0;
   while (t < ntr) {
     const int g = group_size(ntr - t);
     static_assert(kMaxGroup == 4, "streaming passes are instantiated for groups of 4, 2 and 1");
-    if (g == 4) launch_stream<D, 4>(cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, stream);
-    else if (g == 2) launch_stream<D, 2>(cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, stream);
-    else launch_stream<D, 1>(cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, stream);
+    if (g == 4) launch_stream<D, 4>(ctx, cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, stream);
+    else if (g == 2) launch_stream<D, 2>(ctx, cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, stream);
+    else launch_stream<D, 1>(ctx, cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, stream);
     t += g;
     region0 += per;
   }
   sb.nregions[nxt] = region0;
 }
 
-static int launch_sweep(int d, const double *cin, double *cout, const double *s, SweepBuffers &sb, int wcc, int cur,
-                        int nx, int ny, int nz, int ntr, int words, int chunk, hipStream_t stream) {
-  if (d == 0) launch_sweep_axis<0>(cin, cout, s, sb, wcc, cur, nx, ny, nz, ntr, words, chunk, stream);
-  else if (d == 1) launch_sweep_axis<1>(cin, cout, s, sb, wcc, cur, nx, ny, nz, ntr, words, chunk, stream);
-  else launch_sweep_axis<2>(cin, cout, s, sb, wcc, cur, nx, ny, nz, ntr, words, chunk, stream);
+static int launch_sweep(vofmt_ctx *ctx, int d, const double *cin, double *cout, const double *s, SweepBuffers &sb,
+                        int wcc, int cur, int nx, int ny, int nz, int ntr, int words, int chunk, hipStream_t stream) {
+  if (d == 0) launch_sweep_axis<0>(ctx, cin, cout, s, sb, wcc, cur, nx, ny, nz, ntr, words, chunk, stream);
+  else if (d == 1) launch_sweep_axis<1>(ctx, cin, cout, s, sb, wcc, cur, nx, ny, nz, ntr, words, chunk, stream);
+  else launch_sweep_axis<2>(ctx, cin, cout, s, sb, wcc, cur, nx, ny, nz, ntr, words, chunk, stream);
   return (int)hipGetLastError();
 }
 
@@ -148,8 +162,10 @@ extern "C" int vofmt_advect(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, 
   const double *s3[3] = {sx, sy, sz};
   const int chunk = kChunk;
   // mixed cells of the input field
+  const int rec = prof_begin(ctx, "k_scan_mixed", stream);
   hipLaunchKernelGGL(k_scan_mixed, dim3(ceil_div(scanreg, 4)), dim3(256), 0, stream, c, total, sb.list[0],
                      sb.counts[0], scanreg, rsize);
+  prof_end(ctx, rec, stream);
   VOFMT_HIP(ctx, hipGetLastError());
   int cur_list = 0;
   double *cur = c, *nxt = tmp;
@@ -158,7 +174,7 @@ extern "C" int vofmt_advect(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, 
     for (int r = 0; r < 3; ++r) {
       const int d = (int)((g + r) % 3);
       const int wcc = (r == 0);
-      int rc = launch_sweep(d, cur, nxt, s3[d], sb, wcc, cur_list, nx, ny, nz, ntracers, words, chunk, stream);
+      int rc = launch_sweep(ctx, d, cur, nxt, s3[d], sb, wcc, cur_list, nx, ny, nz, ntracers, words, chunk, stream);
       if (rc) return hip_check(ctx, (hipError_t)rc, "sweep launch");
       cur_list ^= 1;
       double *t = cur;

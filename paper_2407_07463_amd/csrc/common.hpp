@@ -11,6 +11,12 @@
 
 #include "vofmt.h"
 
+// One timed launch: HIP events recorded before and after it on its stream.
+struct ProfRec {
+  const char *name;
+  hipEvent_t a, b;
+};
+
 struct vofmt_ctx {
   int device = 0;
   std::string err;
@@ -26,6 +32,11 @@ struct vofmt_ctx {
   hipGraphExec_t graph = nullptr;
   std::string graph_key;
   std::vector<uint8_t> tables;
+  // Per-launch timing (vofmt_profile_start / vofmt_profile_stop).
+  bool prof_on = false;
+  std::vector<ProfRec> prof;
+  std::vector<hipEvent_t> prof_pool;
+  size_t prof_used = 0;
 };
 
 // Scratch slots (one buffer per role).
@@ -50,6 +61,9 @@ enum ScratchSlot {
   SLOT_MLP_SIGN = 17,  // and orientation signs
   SLOT_BATCH = 18,     // batched advection: per-box work buffers and tables
   SLOT_TUNE = 19,      // autotuner: copies of the fields it advects
+  SLOT_CURV_LIST = 20,   // curvature: list of mixed cells
+  SLOT_CURV_COUNT = 21,  // its length and that of the fallback list
+  SLOT_CURV_HF = 22,     // cells handed to the height-function fallback
   kNumSlots = 24,
 };
 
@@ -58,6 +72,10 @@ int hip_check(vofmt_ctx *ctx, hipError_t e, const char *what);
 // Device scratch of at least `bytes` in slot `slot`; nullptr on failure (error set).
 void *scratch(vofmt_ctx *ctx, int slot, size_t bytes);
 void *host_scratch(vofmt_ctx *ctx, size_t bytes);
+// Timing of one launch when profiling is on: prof_begin before the launch
+// (returns a record index, or -1), prof_end after it.
+int prof_begin(vofmt_ctx *ctx, const char *name, hipStream_t stream);
+void prof_end(vofmt_ctx *ctx, int rec, hipStream_t stream);
 
 #define VOFMT_HIP(ctx, call)                                  \
   do {                                                        \

@@ -1,0 +1,118 @@
+// Lists of the mixed cells (0 < c < 1) of one field in increasing cell order:
+// block counts, a tiled scan, then a second pass that writes the list. No
+// atomics, so the order is fixed.
+#pragma once
+
+#include "common.hpp"
+
+namespace compact {
+namespace {  // each translation unit gets its own kernels
+
+constexpr int kBlock = 256;
+constexpr int kTile = 1024;  // entries per scan tile
+
+__device__ __forceinline__ bool is_mixed(double v) { return v > 0.0 && v < 1.0; }
+
+// Mixed cells per block of kBlock cells.
+__global__ __launch_bounds__(kBlock) void k_block_counts(const double *__restrict__ c, int64_t n3,
+                                                         int32_t *__restrict__ bc) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool mixed = p < n3 && is_mixed(c[p]);
+  __shared__ int wc[kBlock / 64];
+  const uint64_t mask = __ballot(mixed);
+  if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = (int)__popcll(mask);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < kBlock / 64; ++w) t += wc[w];
+    bc[blockIdx.x] = t;
+  }
+}
+
+// Exclusive scan of one tile of kTile entries in place; the tile total goes to tot[tile].
+__global__ __launch_bounds__(kTile) void k_scan_tile(int32_t *__restrict__ v, int64_t n, int32_t *__restrict__ tot) {
+  __shared__ int32_t s[kTile];
+  const int64_t i = (int64_t)blockIdx.x * kTile + threadIdx.x;
+  const int32_t x = (i < n) ? v[i] : 0;
+  s[threadIdx.x] = x;
+  __syncthreads();
+  for (int off = 1; off < kTile; off <<= 1) {
+    const int32_t add = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0;
+    __syncthreads();
+    s[threadIdx.x] += add;
+    __syncthreads();
+  }
+  if (i < n) v[i] = s[threadIdx.x] - x;
+  if (threadIdx.x == kTile - 1) tot[blockIdx.x] = s[kTile - 1];
+}
+
+// Exclusive scan of the tile totals (one workgroup, any length); the grand
+// total goes to tot[ntiles].
+__global__ __launch_bounds__(kTile) void k_scan_totals(int32_t *__restrict__ tot, int64_t ntiles) {
+  __shared__ int32_t s[kTile];
+  __shared__ int32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < ntiles; base += kTile) {
+    const int64_t i = base + threadIdx.x;
+    const int32_t x = (i < ntiles) ? tot[i] : 0;
+    s[threadIdx.x] = x;
+    __syncthreads();
+    for (int off = 1; off < kTile; off <<= 1) {
+      const int32_t add = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0;
+      __syncthreads();
+      s[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (i < ntiles) tot[i] = carry + s[threadIdx.x] - x;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += s[kTile - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tot[ntiles] = carry;
+}
+
+// Ordered list: block b writes its mixed cells from bc[b] + tot[b / kTile].
+// With kappa/status given, also writes NaN / 0 into every cell that is not
+// mixed.
+__global__ __launch_bounds__(kBlock) void k_write_ordered(const double *__restrict__ c, int64_t n3,
+                                                          const int32_t *__restrict__ bc,
+                                                          const int32_t *__restrict__ tot, int32_t *__restrict__ list,
+                                                          double *__restrict__ kappa, uint8_t *__restrict__ status) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool inside = p < n3;
+  const bool mixed = inside && is_mixed(c[p]);
+  if (inside && !mixed && kappa) {
+    kappa[p] = __builtin_nan("");
+    status[p] = 0;
+  }
+  __shared__ int wc[kBlock / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t mask = __ballot(mixed);
+  if (lane == 0) wc[w] = (int)__popcll(mask);
+  __syncthreads();
+  if (!mixed) return;
+  int idx = bc[blockIdx.x] + tot[blockIdx.x / kTile];
+  for (int k = 0; k < w; ++k) idx += wc[k];
+  idx += (int)__popcll(mask & ((1ull << lane) - 1));
+  list[idx] = (int32_t)p;
+}
+
+// The ordered list of the mixed cells of c into `list` (capacity n3), its
+// length into tot[ntiles] on the device. bc: ceil(n3 / kBlock) ints of
+// scratch; tot: ntiles + 1 ints, ntiles = ceil(bc length / kTile).
+inline void launch_ordered_list(const double *c, int64_t n3, int32_t *bc, int32_t *tot, int32_t *list, double *kappa,
+                                uint8_t *status, hipStream_t stream) {
+  const int64_t nb = (n3 + kBlock - 1) / kBlock;
+  const int64_t ntiles = (nb + kTile - 1) / kTile;
+  hipLaunchKernelGGL(k_block_counts, dim3((unsigned)nb), dim3(kBlock), 0, stream, c, n3, bc);
+  hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)ntiles), dim3(kTile), 0, stream, bc, nb, tot);
+  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kTile), 0, stream, tot, ntiles);
+  hipLaunchKernelGGL(k_write_ordered, dim3((unsigned)nb), dim3(kBlock), 0, stream, c, n3, bc, tot, list, kappa,
+                     status);
+}
+
+inline int64_t list_tiles(int64_t n3) { return ((n3 + kBlock - 1) / kBlock + kTile - 1) / kTile; }
+
+}  // namespace
+}  // namespace compact

@@ -12,96 +12,59 @@
 //   kappa*Delta = -[Hxx(1+Hy^2) + Hyy(1+Hx^2) - 2 Hxy Hx Hy] / (1+Hx^2+Hy^2)^{3/2},
 // +2/R on a sphere of radius R cells. Every expression is evaluated in the
 // written order.
-#include "common.hpp"
-#include "plic.hpp"
+#include "compact.hpp"
+#include "curv_hf.hpp"
 
 namespace {
 
 constexpr int kBlock = 256;
 
-__global__ __launch_bounds__(kBlock) void k_curv_hf(const double *__restrict__ c, int nx, int ny, int nz,
-                                                    double *__restrict__ kappa, uint8_t *__restrict__ status) {
-  const int64_t n3 = (int64_t)nx * ny * nz;
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= n3) return;
-  const double cp = c[p];
-  if (!(cp > 0.0 && cp < 1.0)) {
-    kappa[p] = __builtin_nan("");
-    status[p] = 0;
-    return;
+// Height-function curvature of the listed cells (persistent grid).
+__global__ __launch_bounds__(kBlock) void k_curv_hf_list(const double *__restrict__ c, int nx, int ny, int nz,
+                                                         const int32_t *__restrict__ list,
+                                                         const int32_t *__restrict__ count,
+                                                         double *__restrict__ kappa, uint8_t *__restrict__ status) {
+  const int n = *count;
+  for (int q = blockIdx.x * kBlock + threadIdx.x; q < n; q += gridDim.x * kBlock) {
+    const int64_t p = list[q];
+    double k;
+    uint8_t st;
+    curv::hf_cell(c, p, nx, ny, nz, k, st);
+    kappa[p] = k;
+    status[p] = st;
   }
-  const int n[3] = {nx, ny, nz};
-  const int x[3] = {(int)(p % nx), (int)((p / nx) % ny), (int)(p / ((int64_t)nx * ny))};
-  double b[27];
-  for (int az = -1; az <= 1; ++az)
-    for (int ay = -1; ay <= 1; ++ay)
-      for (int ax = -1; ax <= 1; ++ax)
-        b[(ax + 1) + 3 * (ay + 1) + 9 * (az + 1)] =
-            c[((int64_t)wrap_any(x[2] + az, nz) * ny + wrap_any(x[1] + ay, ny)) * nx + wrap_any(x[0] + ax, nx)];
-  double m[3];
-  plic::myc_normal(b, m[0], m[1], m[2]);
-  int order[3] = {0, 1, 2};
-  for (int a = 0; a < 3; ++a)
-    for (int bb = a + 1; bb < 3; ++bb)
-      if (fabs(m[order[bb]]) > fabs(m[order[a]]) ||
-          (fabs(m[order[bb]]) == fabs(m[order[a]]) && order[bb] < order[a])) {
-        int t = order[a];
-        order[a] = order[bb];
-        order[bb] = t;
-      }
-  double result = __builtin_nan("");
-  uint8_t st = 4;
-  for (int at = 0; at < 3; ++at) {
-    const int d = order[at];
-    const int t1 = (d == 0) ? 1 : 0;
-    const int t2 = (d == 2) ? 1 : 2;
-    const bool up = m[d] >= 0.0;
-    double H[3][3];
-    bool ok = true;
-    for (int v = -1; v <= 1 && ok; ++v)
-      for (int u = -1; u <= 1 && ok; ++u) {
-        int y[3] = {x[0], x[1], x[2]};
-        y[t1] = wrap_any(y[t1] + u, n[t1]);
-        y[t2] = wrap_any(y[t2] + v, n[t2]);
-        double h = 0.0, first = 0.0, last = 0.0;
-        for (int e = -3; e <= 3; ++e) {
-          int z[3] = {y[0], y[1], y[2]};
-          z[d] = wrap_any(z[d] + e, n[d]);
-          const double v_ = c[((int64_t)z[2] * ny + z[1]) * nx + z[0]];
-          if (e == -3) first = v_;
-          if (e == 3) last = v_;
-          h += v_;
-        }
-        const double full_end = up ? first : last;
-        const double empty_end = up ? last : first;
-        if (!(full_end >= 1.0 - 1e-6 && empty_end <= 1e-6)) ok = false;
-        H[u + 1][v + 1] = h;
-      }
-    if (!ok) continue;
-    const double Hx = (H[2][1] - H[0][1]) / 2.0;
-    const double Hy = (H[1][2] - H[1][0]) / 2.0;
-    const double Hxx = (H[2][1] - 2.0 * H[1][1]) + H[0][1];
-    const double Hyy = (H[1][2] - 2.0 * H[1][1]) + H[1][0];
-    const double Hxy = (((H[2][2] - H[2][0]) - H[0][2]) + H[0][0]) / 4.0;
-    const double num = (Hxx * (1.0 + Hy * Hy) + Hyy * (1.0 + Hx * Hx)) - ((2.0 * Hxy) * Hx) * Hy;
-    const double den = (1.0 + Hx * Hx) + Hy * Hy;
-    result = -num / (den * sqrt(den));
-    st = (uint8_t)(1 + at);
-    break;
-  }
-  kappa[p] = result;
-  status[p] = st;
 }
 
 }  // namespace
+
+// Persistent grid of the list kernels: enough workgroups to fill the chip.
+int list_grid(vofmt_ctx *ctx) {
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
+    cus = 256;
+  return 8 * cus;
+}
 
 extern "C" int vofmt_curvature_hf(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, const double *c,
                                   double *kappa, uint8_t *status, hipStream_t stream) {
   if (!ctx) return VOFMT_E_ARG;
   if (nx < 1 || ny < 1 || nz < 1 || !c || !kappa || !status)
     return set_err(ctx, VOFMT_E_ARG, "vofmt_curvature_hf: bad arguments");
-  VOFMT_HIP(ctx, hipSetDevice(ctx->device));
   const int64_t n3 = (int64_t)nx * ny * nz;
-  hipLaunchKernelGGL(k_curv_hf, dim3(ceil_div(n3, kBlock)), dim3(kBlock), 0, stream, c, nx, ny, nz, kappa, status);
-  return hip_check(ctx, hipGetLastError(), "k_curv_hf");
+  if (n3 >= INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "vofmt_curvature_hf: too many cells");
+  VOFMT_HIP(ctx, hipSetDevice(ctx->device));
+  const int64_t ntiles = compact::list_tiles(n3);
+  int32_t *list = (int32_t *)scratch(ctx, SLOT_CURV_LIST, sizeof(int32_t) * (size_t)n3);
+  int32_t *bc = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * (size_t)ceil_div(n3, compact::kBlock));
+  int32_t *tot = (int32_t *)scratch(ctx, SLOT_CURV_COUNT, sizeof(int32_t) * (size_t)(ntiles + 1));
+  if (!list || !bc || !tot) return VOFMT_E_NOMEM;
+  int rec = prof_begin(ctx, "mixed_list", stream);
+  compact::launch_ordered_list(c, n3, bc, tot, list, kappa, status, stream);
+  prof_end(ctx, rec, stream);
+  const int32_t *count = tot + ntiles;
+  rec = prof_begin(ctx, "k_curv_hf_list", stream);
+  hipLaunchKernelGGL(k_curv_hf_list, dim3(list_grid(ctx)), dim3(kBlock), 0, stream, c, nx, ny, nz, list, count, kappa,
+                     status);
+  prof_end(ctx, rec, stream);
+  return hip_check(ctx, hipGetLastError(), "curvature_hf kernels");
 }

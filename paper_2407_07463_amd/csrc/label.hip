@@ -195,21 +195,52 @@ __device__ __forceinline__ int wrapped_delta(int a, int a0, int n) {
 }
 
 // Per-drop bounding box of the offsets (integer atomics: order-independent).
+// Wavefront-wide minimum / maximum over the lanes in `mask` (others pass the
+// neutral value in).
+__device__ __forceinline__ int wave_min(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Bounding box of every drop as offsets from its first cell (periodic).
+// The lanes of a wavefront that hold the same drop are combined first, so
+// each drop sees one set of atomics per wavefront instead of one per cell.
 __global__ __launch_bounds__(kBlock) void k_drop_bbox(const int32_t *__restrict__ lab, int64_t n3, int nx, int ny, int nz,
                                                       int32_t K, const int32_t *__restrict__ rootpos,
                                                       int32_t *__restrict__ box) {
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= n3) return;
-  const int32_t l = lab[p];
-  if (l <= 0 || l > K) return;
-  const int32_t p0 = rootpos[l - 1];
-  const int x = (int)(p % nx), y = (int)((p / nx) % ny), z = (int)(p / ((int64_t)nx * ny));
-  const int x0 = p0 % nx, y0 = (p0 / nx) % ny, z0 = p0 / (nx * ny);
-  const int d[3] = {wrapped_delta(x, x0, nx), wrapped_delta(y, y0, ny), wrapped_delta(z, z0, nz)};
-  int32_t *b = box + 6 * (int64_t)(l - 1);
-  for (int a = 0; a < 3; ++a) {
-    atomicMin(&b[2 * a], d[a]);
-    atomicMax(&b[2 * a + 1], d[a]);
+  const int lane = threadIdx.x & 63;
+  const int32_t l = (p < n3) ? lab[p] : 0;
+  const bool valid = l > 0 && l <= K;
+  int d[3] = {0, 0, 0};
+  if (valid) {
+    const int32_t p0 = rootpos[l - 1];
+    const int x = (int)(p % nx), y = (int)((p / nx) % ny), z = (int)(p / ((int64_t)nx * ny));
+    const int x0 = p0 % nx, y0 = (p0 / nx) % ny, z0 = p0 / (nx * ny);
+    d[0] = wrapped_delta(x, x0, nx);
+    d[1] = wrapped_delta(y, y0, ny);
+    d[2] = wrapped_delta(z, z0, nz);
+  }
+  uint64_t todo = __ballot(valid);
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int32_t lv = __shfl(l, leader, 64);
+    const bool mine = valid && l == lv;
+    const uint64_t same = __ballot(mine);
+    int32_t *b = box + 6 * (int64_t)(lv - 1);
+    for (int a = 0; a < 3; ++a) {
+      const int mn = wave_min(mine ? d[a] : INT32_MAX);
+      const int mx = wave_max(mine ? d[a] : INT32_MIN);
+      if (lane == leader) {
+        atomicMin(&b[2 * a], mn);
+        atomicMax(&b[2 * a + 1], mx);
+      }
+    }
+    todo &= ~same;
   }
 }
 
@@ -218,13 +249,23 @@ __global__ void k_first_init(int32_t *first, int64_t K) {
   if (i < K) first[i] = INT32_MAX;
 }
 
-// First (smallest linear index) cell of every drop.
+// First (smallest linear index) cell of every drop; lanes of a wavefront
+// holding the same drop are combined before the atomic.
 __global__ __launch_bounds__(kBlock) void k_first_min(const int32_t *__restrict__ lab, int64_t n3, int32_t K,
                                                       int32_t *__restrict__ first) {
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= n3) return;
-  const int32_t l = lab[p];
-  if (l > 0 && l <= K) atomicMin(&first[l - 1], (int32_t)p);
+  const int lane = threadIdx.x & 63;
+  const int32_t l = (p < n3) ? lab[p] : 0;
+  const bool valid = l > 0 && l <= K;
+  uint64_t todo = __ballot(valid);
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int32_t lv = __shfl(l, leader, 64);
+    const uint64_t same = __ballot(valid && l == lv);
+    // lanes hold increasing indices: the lowest lane of the drop has its smallest cell
+    if (lane == leader) atomicMin(&first[lv - 1], (int32_t)p);
+    todo &= ~same;
+  }
 }
 
 __global__ void k_box_init(int32_t *box, int64_t K) {

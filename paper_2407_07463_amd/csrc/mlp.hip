@@ -26,6 +26,8 @@
 #include <cstring>
 
 #include "common.hpp"
+#include "compact.hpp"
+#include "curv_hf.hpp"
 #include "plic.hpp"
 
 namespace {
@@ -417,86 +419,64 @@ __device__ int canonical_stencil(const double *__restrict__ c, int i, int j, int
   return sign;
 }
 
-__global__ __launch_bounds__(256) void k_count_mixed(const double *__restrict__ c, int64_t n3, int *__restrict__ count) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool mixed = p < n3 && c[p] > 0.0 && c[p] < 1.0;
-  const uint64_t mask = __ballot(mixed);
-  if ((threadIdx.x & 63) == 0 && mask) atomicAdd(count, (int)__popcll(mask));
-}
-
-// Mixed cells in increasing linear index: block b writes from offset base[b].
-__global__ __launch_bounds__(256) void k_block_mixed(const double *__restrict__ c, int64_t n3, int *__restrict__ bc) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool mixed = p < n3 && c[p] > 0.0 && c[p] < 1.0;
-  __shared__ int wc[4];
-  const uint64_t mask = __ballot(mixed);
-  if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = (int)__popcll(mask);
-  __syncthreads();
-  if (threadIdx.x == 0) bc[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
-}
-
-__global__ __launch_bounds__(1024) void k_scan_exclusive(int *__restrict__ v, int64_t n) {
-  __shared__ int64_t part[1024];
-  const int t = threadIdx.x;
-  const int64_t per = (n + 1023) / 1024;
-  const int64_t lo = t * per, hi = (lo + per < n) ? lo + per : n;
-  int64_t s = 0;
-  for (int64_t i = lo; i < hi; ++i) s += v[i];
-  part[t] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int64_t add = (t >= off) ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += add;
-    __syncthreads();
-  }
-  int64_t run = (t == 0) ? 0 : part[t - 1];
-  for (int64_t i = lo; i < hi; ++i) {
-    const int x = v[i];
-    v[i] = (int)run;
-    run += x;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_stencils(const double *__restrict__ c, int nx, int ny, int nz,
-                                                  const int *__restrict__ base, float *__restrict__ xs,
-                                                  int32_t *__restrict__ cell, int8_t *__restrict__ sgn) {
-  const int64_t n3 = (int64_t)nx * ny * nz;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool mixed = p < n3 && c[p] > 0.0 && c[p] < 1.0;
-  __shared__ int wc[4];
-  const uint64_t mask = __ballot(mixed);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) wc[w] = (int)__popcll(mask);
-  __syncthreads();
-  if (!mixed) return;
-  int idx = base[blockIdx.x];
-  for (int k = 0; k < w; ++k) idx += wc[k];
-  idx += (int)__popcll(mask & ((1ull << lane) - 1));
+// Canonical stencils of the listed cells: xs[q], sign[q] for cell list[q].
+__global__ __launch_bounds__(256) void k_stencil_list(const double *__restrict__ c, int nx, int ny, int nz,
+                                                      const int32_t *__restrict__ list, int n, float *__restrict__ xs,
+                                                      int8_t *__restrict__ sgn) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const int64_t p = list[q];
   const int i = (int)(p % nx), j = (int)((p / nx) % ny), k = (int)(p / ((int64_t)nx * ny));
   float out[27];
   const int sg = canonical_stencil(c, i, j, k, nx, ny, nz, out);
-  for (int q = 0; q < 27; ++q) xs[(int64_t)idx * 27 + q] = out[q];
-  cell[idx] = (int32_t)p;
-  sgn[idx] = (int8_t)sg;
+  for (int e = 0; e < 27; ++e) xs[(int64_t)q * 27 + e] = out[e];
+  sgn[q] = (int8_t)sg;
 }
 
-// Learned curvature with the height-function fallback: the network's value
-// unless the height function is valid and |kappa_net| < kappa_lo (large
-// radii, which a 3x3x3 stencil cannot resolve). status = HF status, +8 when
-// the network's value is used.
-__global__ __launch_bounds__(256) void k_curv_combine(const float *__restrict__ y, const int32_t *__restrict__ cell,
+// The network's value for every listed cell (status 8); cells with
+// |kappa| < kappa_lo are appended to the height-function fallback list.
+__global__ __launch_bounds__(256) void k_curv_combine(const float *__restrict__ y, const int32_t *__restrict__ list,
                                                       const int8_t *__restrict__ sgn, int nm, double kappa_lo,
-                                                      double *__restrict__ kappa, uint8_t *__restrict__ status) {
+                                                      double *__restrict__ kappa, uint8_t *__restrict__ status,
+                                                      int32_t *__restrict__ hf_list, int32_t *__restrict__ hf_count) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nm) return;
-  const int32_t p = cell[q];
-  const double kn = (double)sgn[q] * (double)y[q];
-  const uint8_t st = status[p];
-  const bool hf_ok = st >= 1 && st <= 3;
-  if (hf_ok && fabs(kn) < kappa_lo) return;  // keep the height-function value
-  kappa[p] = kn;
-  status[p] = (uint8_t)(st | 8);
+  const int lane = threadIdx.x & 63;
+  bool flag = false;
+  int32_t p = 0;
+  if (q < nm) {
+    p = list[q];
+    const double kn = (double)sgn[q] * (double)y[q];
+    kappa[p] = kn;
+    status[p] = 8;
+    flag = fabs(kn) < kappa_lo;
+  }
+  const uint64_t mask = __ballot(flag);
+  if (!mask) return;
+  int base = 0;
+  if (lane == 0) base = atomicAdd(hf_count, (int)__popcll(mask));
+  base = __shfl(base, 0, 64);
+  if (flag) hf_list[base + __popcll(mask & ((1ull << lane) - 1))] = p;
+}
+
+// Height functions on the fallback cells: their value where valid (status
+// 1..3), else the network's value stays (status 4 + 8).
+__global__ __launch_bounds__(256) void k_curv_fallback(const double *__restrict__ c, int nx, int ny, int nz,
+                                                       const int32_t *__restrict__ hf_list,
+                                                       const int32_t *__restrict__ hf_count,
+                                                       double *__restrict__ kappa, uint8_t *__restrict__ status) {
+  const int n = *hf_count;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    const int64_t p = hf_list[q];
+    double k;
+    uint8_t st;
+    curv::hf_cell(c, p, nx, ny, nz, k, st);
+    if (st >= 1 && st <= 3) {
+      kappa[p] = k;
+      status[p] = st;
+    } else {
+      status[p] = (uint8_t)(st | 8);
+    }
+  }
 }
 
 }  // namespace
@@ -530,8 +510,10 @@ extern "C" int vofmt_mlp_forward(vofmt_ctx *ctx, const float *params, int32_t m,
   int rc = mlp_prepare(ctx, params, w, stream);
   if (rc) return rc;
   const int ntiles = (m + TILE - 1) / TILE;
+  const int rec = prof_begin(ctx, "k_mlp_fwd", stream);
   hipLaunchKernelGGL(k_mlp_fwd, dim3(fwd_grid(ctx, ntiles)), dim3(256), 0, stream, params, w[0], w[1], m, x, y, acts,
                      (const float *)nullptr, (float *)nullptr, (float *)nullptr);
+  prof_end(ctx, rec, stream);
   return hip_check(ctx, hipGetLastError(), "k_mlp_fwd");
 }
 
@@ -553,17 +535,25 @@ extern "C" int vofmt_mlp_train_step(vofmt_ctx *ctx, float *params, float *adam_m
   if (!acts || !gbuf || !partial || !hl) return VOFMT_E_NOMEM;
   float *loss_part = gbuf + m;
   float *loss_out = gbuf + m + ntiles;
+  int rec = prof_begin(ctx, "k_mlp_fwd(train)", stream);
   hipLaunchKernelGGL(k_mlp_fwd, dim3(fwd_grid(ctx, ntiles)), dim3(256), 0, stream, params, w[0], w[1], m, x,
                      (float *)nullptr, acts, y_target, gbuf, loss_part);
+  prof_end(ctx, rec, stream);
+  rec = prof_begin(ctx, "k_mlp_bwd", stream);
   hipLaunchKernelGGL(k_mlp_bwd, dim3(ntiles), dim3(256), 0, stream, params, w[2], m, x, acts, gbuf, partial, trace);
+  prof_end(ctx, rec, stream);
+  rec = prof_begin(ctx, "k_mlp_adam", stream);
   hipLaunchKernelGGL(k_mlp_adam, dim3(ceil_div(NPARAMS, 256)), dim3(256), 0, stream, params, adam_m, adam_v, partial,
                      ntiles, step, lr, grads, loss_part, loss_out, m);
+  prof_end(ctx, rec, stream);
   VOFMT_HIP(ctx, hipGetLastError());
   VOFMT_HIP(ctx, hipMemcpyAsync(hl, loss_out, sizeof(float), hipMemcpyDeviceToHost, stream));
   VOFMT_HIP(ctx, hipStreamSynchronize(stream));
   *loss_host = hl[0];
   return VOFMT_OK;
 }
+
+int list_grid(vofmt_ctx *ctx);
 
 // Canonical stencils of the mixed cells (0 < c < 1) of one field, in
 // increasing cell order. Writes at most `capacity` entries; *count_host gets
@@ -577,23 +567,27 @@ extern "C" int vofmt_mlp_stencils(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_
   const int64_t n3 = (int64_t)nx * ny * nz;
   if (n3 >= INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "vofmt_mlp_stencils: too many cells");
   VOFMT_HIP(ctx, hipSetDevice(ctx->device));
-  const unsigned nb = ceil_div(n3, 256);
-  int *bc = (int *)scratch(ctx, SLOT_MISC, sizeof(int) * ((size_t)nb + 1));
-  int *hc = (int *)host_scratch(ctx, sizeof(int) * 2);
-  if (!bc || !hc) return VOFMT_E_NOMEM;
-  hipLaunchKernelGGL(k_block_mixed, dim3(nb), dim3(256), 0, stream, c, n3, bc);
-  hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, stream, bc, (int64_t)nb + 1);
+  const int64_t nb = ceil_div(n3, compact::kBlock);
+  const int64_t ntiles = compact::list_tiles(n3);
+  int32_t *bc = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * (size_t)nb);
+  int32_t *tot = (int32_t *)scratch(ctx, SLOT_MISC2, sizeof(int32_t) * (size_t)(ntiles + 1));
+  int32_t *list = (int32_t *)scratch(ctx, SLOT_CURV_LIST, sizeof(int32_t) * (size_t)n3);
+  int32_t *hc = (int32_t *)host_scratch(ctx, sizeof(int32_t) * 2);
+  if (!bc || !tot || !list || !hc) return VOFMT_E_NOMEM;
+  compact::launch_ordered_list(c, n3, bc, tot, list, (double *)nullptr, (uint8_t *)nullptr, stream);
   VOFMT_HIP(ctx, hipGetLastError());
-  VOFMT_HIP(ctx, hipMemcpyAsync(hc, bc + nb, sizeof(int), hipMemcpyDeviceToHost, stream));
+  VOFMT_HIP(ctx, hipMemcpyAsync(hc, tot + ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
   VOFMT_HIP(ctx, hipStreamSynchronize(stream));
   const int total = hc[0];
   *count_host = total;
-  if (total > capacity) return set_err(ctx, VOFMT_E_ARG, "vofmt_mlp_stencils: %d mixed cells, capacity %d", total,
-                                       capacity);
+  if (total > capacity)
+    return set_err(ctx, VOFMT_E_ARG, "vofmt_mlp_stencils: %d mixed cells, capacity %d", total, capacity);
   if (total == 0) return VOFMT_OK;
   if (!xs || !cell || !sign) return set_err(ctx, VOFMT_E_ARG, "vofmt_mlp_stencils: null output");
-  hipLaunchKernelGGL(k_stencils, dim3(nb), dim3(256), 0, stream, c, nx, ny, nz, bc, xs, cell, sign);
-  return hip_check(ctx, hipGetLastError(), "k_stencils");
+  VOFMT_HIP(ctx, hipMemcpyAsync(cell, list, sizeof(int32_t) * (size_t)total, hipMemcpyDeviceToDevice, stream));
+  hipLaunchKernelGGL(k_stencil_list, dim3(ceil_div(total, 256)), dim3(256), 0, stream, c, nx, ny, nz, list, total, xs,
+                     sign);
+  return hip_check(ctx, hipGetLastError(), "vofmt_mlp_stencils kernels");
 }
 
 extern "C" int vofmt_curvature_mlp(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, const double *c,
@@ -605,33 +599,46 @@ extern "C" int vofmt_curvature_mlp(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32
   const int64_t n3 = (int64_t)nx * ny * nz;
   if (n3 >= INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "vofmt_curvature_mlp: too many cells");
   VOFMT_HIP(ctx, hipSetDevice(ctx->device));
-  int rc = vofmt_curvature_hf(ctx, nx, ny, nz, c, kappa, status, stream);
-  if (rc) return rc;
-  const unsigned nb = ceil_div(n3, 256);
-  int *bc = (int *)scratch(ctx, SLOT_MISC, sizeof(int) * ((size_t)nb + 1));
-  int *hc = (int *)host_scratch(ctx, sizeof(int) * 2);
-  if (!bc || !hc) return VOFMT_E_NOMEM;
-  hipLaunchKernelGGL(k_block_mixed, dim3(nb), dim3(256), 0, stream, c, n3, bc);
-  hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, stream, bc, (int64_t)nb + 1);
+  const int64_t lt = compact::list_tiles(n3);
+  int32_t *list = (int32_t *)scratch(ctx, SLOT_CURV_LIST, sizeof(int32_t) * (size_t)n3);
+  int32_t *bc = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * (size_t)ceil_div(n3, compact::kBlock));
+  int32_t *tot = (int32_t *)scratch(ctx, SLOT_CURV_COUNT, sizeof(int32_t) * (size_t)(lt + 2));
+  int32_t *hc = (int32_t *)host_scratch(ctx, sizeof(int32_t) * 2);
+  if (!list || !bc || !tot || !hc) return VOFMT_E_NOMEM;
+  int32_t *hf_count = tot + lt + 1;
+  VOFMT_HIP(ctx, hipMemsetAsync(hf_count, 0, sizeof(int32_t), stream));
+  int rec = prof_begin(ctx, "mixed_list", stream);
+  compact::launch_ordered_list(c, n3, bc, tot, list, kappa, status, stream);
+  prof_end(ctx, rec, stream);
   VOFMT_HIP(ctx, hipGetLastError());
-  VOFMT_HIP(ctx, hipMemcpyAsync(hc, bc + nb, sizeof(int), hipMemcpyDeviceToHost, stream));
+  VOFMT_HIP(ctx, hipMemcpyAsync(hc, tot + lt, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
   VOFMT_HIP(ctx, hipStreamSynchronize(stream));
   const int nm = hc[0];
   if (nmixed_host) *nmixed_host = nm;
   if (nm == 0) return VOFMT_OK;
   float *xs = (float *)scratch(ctx, SLOT_MLP_X, sizeof(float) * 28 * (size_t)nm);
-  int32_t *cell = (int32_t *)scratch(ctx, SLOT_MLP_CELL, sizeof(int32_t) * (size_t)nm);
   int8_t *sg = (int8_t *)scratch(ctx, SLOT_MLP_SIGN, (size_t)nm);
-  if (!xs || !cell || !sg) return VOFMT_E_NOMEM;
+  int32_t *hf_list = (int32_t *)scratch(ctx, SLOT_CURV_HF, sizeof(int32_t) * (size_t)nm);
+  if (!xs || !sg || !hf_list) return VOFMT_E_NOMEM;
   float *yv = xs + 27 * (size_t)nm;
-  hipLaunchKernelGGL(k_stencils, dim3(nb), dim3(256), 0, stream, c, nx, ny, nz, bc, xs, cell, sg);
+  rec = prof_begin(ctx, "k_stencil_list", stream);
+  hipLaunchKernelGGL(k_stencil_list, dim3(ceil_div(nm, 256)), dim3(256), 0, stream, c, nx, ny, nz, list, nm, xs, sg);
+  prof_end(ctx, rec, stream);
   uint16_t *w[3];
-  rc = mlp_prepare(ctx, params, w, stream);
+  int rc = mlp_prepare(ctx, params, w, stream);
   if (rc) return rc;
   const int ntiles = (nm + TILE - 1) / TILE;
+  rec = prof_begin(ctx, "k_mlp_fwd", stream);
   hipLaunchKernelGGL(k_mlp_fwd, dim3(fwd_grid(ctx, ntiles)), dim3(256), 0, stream, params, w[0], w[1], nm, xs, yv,
                      (uint8_t *)nullptr, (const float *)nullptr, (float *)nullptr, (float *)nullptr);
-  hipLaunchKernelGGL(k_curv_combine, dim3(ceil_div(nm, 256)), dim3(256), 0, stream, yv, cell, sg, nm, kappa_lo, kappa,
-                     status);
+  prof_end(ctx, rec, stream);
+  rec = prof_begin(ctx, "k_curv_combine", stream);
+  hipLaunchKernelGGL(k_curv_combine, dim3(ceil_div(nm, 256)), dim3(256), 0, stream, yv, list, sg, nm, kappa_lo, kappa,
+                     status, hf_list, hf_count);
+  prof_end(ctx, rec, stream);
+  rec = prof_begin(ctx, "k_curv_fallback", stream);
+  hipLaunchKernelGGL(k_curv_fallback, dim3(list_grid(ctx)), dim3(256), 0, stream, c, nx, ny, nz, hf_list, hf_count,
+                     kappa, status);
+  prof_end(ctx, rec, stream);
   return hip_check(ctx, hipGetLastError(), "curvature_mlp kernels");
 }

@@ -55,6 +55,8 @@ _SIGNATURES = {
                                             ctypes.POINTER(ctypes.c_float), _vp]),
     "vofmt_mlp_stencils": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _P_i32, _vp]),
     "vofmt_curvature_mlp": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _d, _vp, _vp, _P_i32, _vp]),
+    "vofmt_profile_start": (ctypes.c_int, [_vp]),
+    "vofmt_profile_stop": (ctypes.c_int, [_vp, _i32, ctypes.c_char_p, _P_i32, ctypes.POINTER(_d), _P_i32]),
     "vofmt_advect_batched": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(Box), _i64, _i32, ctypes.POINTER(Tuning),
                                             _vp]),
     "vofmt_autotune_batched": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(Box), _i32, ctypes.POINTER(Tuning),
@@ -185,6 +187,23 @@ class Context:
         self._check(load().vofmt_autotune_batched(self.h, len(boxes), arr, int(nsteps), ctypes.byref(best),
                                                   ctypes.byref(ms), _stream(stream)))
         return (best.chunk, best.workgroups_per_cu), ms.value
+
+    # ------------------------------------------------------------ instrumentation
+    def profile_start(self):
+        return self._check(load().vofmt_profile_start(self.h))
+
+    def profile_stop(self, max_kinds: int = 64):
+        """{kernel kind: (launches, total_ms)} of the launches since profile_start."""
+        names = ctypes.create_string_buffer(48 * max_kinds)
+        launches = (ctypes.c_int32 * max_kinds)()
+        total = (ctypes.c_double * max_kinds)()
+        nk = ctypes.c_int32(0)
+        self._check(load().vofmt_profile_stop(self.h, max_kinds, names, launches, total, ctypes.byref(nk)))
+        out = {}
+        for k in range(min(nk.value, max_kinds)):
+            name = names.raw[48 * k:48 * (k + 1)].split(b"\0", 1)[0].decode()
+            out[name] = (int(launches[k]), float(total[k]))
+        return out
 
     # ------------------------------------------------------------ drops
     def label_drops(self, c, labels, c_eps: float = 1e-6, stream=None):

@@ -252,12 +252,15 @@ def test_curvature_mlp_combination(ctx, R, kappa_lo):
     khf, shf = oracle.curvature_hf(c)
     khf, shf = khf.ravel(), shf.ravel()
     net = sg.astype(np.float64) * y
-    use_hf = (shf[cells] >= 1) & (shf[cells] <= 3) & (np.abs(net) < kappa_lo)
-    want_k = np.where(use_hf, khf[cells], net)
-    want_s = np.where(use_hf, shf[cells], shf[cells] | 8)
+    # the network's value unless |kappa| < kappa_lo and the height function is valid there
+    flag = np.abs(net) < kappa_lo
+    hs = shf[cells]
+    hf_ok = flag & (hs >= 1) & (hs <= 3)
+    want_k = np.where(hf_ok, khf[cells], net)
+    want_s = np.where(flag, np.where(hf_ok, hs, hs | 8), 8)
     assert np.array_equal(st[cells], want_s)
     assert np.array_equal(kap[cells], want_k)
     other = np.setdiff1d(np.arange(c.size), cells)
     assert np.all(st[other] == 0) and np.all(np.isnan(kap[other]))
     if kappa_lo == 0.0:
-        assert np.all(st[cells] & 8)
+        assert np.all(st[cells] == 8)
