@@ -16,7 +16,7 @@ from paper_2407_07463_amd import synth
 pytestmark = pytest.mark.gpu
 
 SHAPES = [((20, 24, 16), 3), ((17, 33, 70), 1), ((64, 64, 64), 5), ((36, 52, 40), 8), ((65, 9, 17), 2),
-          ((20, 16, 129), 4)]
+          ((20, 16, 129), 4), ((12, 10, 600), 2)]  # the last one splits its x-rows at chunk 8
 
 
 @pytest.fixture(scope="module")
@@ -87,6 +87,17 @@ def test_matches_oracle(ctx, boxes):
     for (c0, sx, sy, sz), (c, _, _, _) in zip(boxes[:3], dev):
         ref = oracle.advect(c0, sx, sy, sz, 2, 2)
         assert float(np.abs(c.cpu().numpy() - ref).max()) <= 1e-12
+
+
+def test_long_rows_split_between_wavefronts(ctx):
+    """x-rows longer than 64 * chunk cells are walked by several wavefronts."""
+    box = _box((4, 6, 2113), 1, 404)
+    note("plain advection 2113 x 6 x 4")
+    c, sx, sy, sz = box
+    t = _dev(c)
+    ctx.advect(t, _dev(sx), _dev(sy), _dev(sz), step0=0, nsteps=2)
+    ref = oracle.advect(c, sx, sy, sz, 0, 2)
+    assert float(np.abs(t.cpu().numpy() - ref).max()) <= 1e-12
 
 
 def test_graph_reuse(ctx, boxes):
