@@ -45,11 +45,12 @@ constexpr int XP = 40;    // LDS row pitches (bf16 elements), padded against ban
 constexpr int HP = 136;
 constexpr int TP = 72;
 
+// FP32 -> BF16, round to nearest even (the conversion instruction of gfx950).
 __device__ __forceinline__ uint16_t bf16_bits(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  const __bf16 h = (__bf16)f;
+  uint16_t u;
+  memcpy(&u, &h, 2);
+  return u;
 }
 __device__ __forceinline__ float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -382,41 +383,77 @@ __global__ __launch_bounds__(256) void k_mlp_adam(float *__restrict__ P, float *
 // which the MYC normal of that block is negative and order the axes by
 // increasing |m| (ties: lower axis first). Every canonical stencil has its
 // centre at most 1/2 and a normal with non-negative ascending components.
-__device__ int canonical_stencil(const double *__restrict__ c, int i, int j, int k, int nx, int ny, int nz,
-                                 float *out) {
-  double b[27];
+// Its two steps, kept in registers (no arrays indexed at run time): the
+// block of the cell (complemented when its centre exceeds 1/2; returns the
+// sign), then the canonical position of every block entry, handed to `put`.
+struct Canon {
+  int o0, o1, o2;  // source axis of canonical axis 0, 1, 2
+  int d0, d1, d2;  // and its direction (+1 or -1)
+};
+
+__device__ __forceinline__ void load_block(const double *__restrict__ c, int64_t p, int nx, int ny, int nz,
+                                           double *b) {
+  const int i = (int)(p % nx), j = (int)((p / nx) % ny), k = (int)(p / ((int64_t)nx * ny));
   const int xs[3] = {wrap_dec(i, nx), i, wrap_inc(i, nx)};
   const int ys[3] = {wrap_dec(j, ny), j, wrap_inc(j, ny)};
   const int zs[3] = {wrap_dec(k, nz), k, wrap_inc(k, nz)};
+#pragma unroll
   for (int az = 0; az < 3; ++az)
+#pragma unroll
     for (int ay = 0; ay < 3; ++ay)
+#pragma unroll
       for (int ax = 0; ax < 3; ++ax) b[ax + 3 * ay + 9 * az] = c[((int64_t)zs[az] * ny + ys[ay]) * nx + xs[ax]];
+}
+
+__device__ __forceinline__ int canonical_of_block(double *b, Canon &cn) {
   const int sign = (b[13] > 0.5) ? -1 : 1;
-  if (sign < 0)
+  if (sign < 0) {
+#pragma unroll
     for (int q = 0; q < 27; ++q) b[q] = 1.0 - b[q];
-  double m[3];
-  plic::myc_normal(b, m[0], m[1], m[2]);
-  int ord[3] = {0, 1, 2};
-  for (int a = 0; a < 3; ++a)
-    for (int bb = a + 1; bb < 3; ++bb)
-      if (fabs(m[ord[bb]]) < fabs(m[ord[a]]) || (fabs(m[ord[bb]]) == fabs(m[ord[a]]) && ord[bb] < ord[a])) {
-        const int t = ord[a];
-        ord[a] = ord[bb];
-        ord[bb] = t;
-      }
-  // per canonical axis: stride in b and direction
-  int st[3], dir[3];
-  const int stride[3] = {1, 3, 9};
-  for (int kk = 0; kk < 3; ++kk) {
-    st[kk] = stride[ord[kk]];
-    dir[kk] = (m[ord[kk]] < 0.0) ? -1 : 1;
   }
-  for (int q2 = -1; q2 <= 1; ++q2)
-    for (int q1 = -1; q1 <= 1; ++q1)
-      for (int q0 = -1; q0 <= 1; ++q0)
-        out[(q0 + 1) + 3 * (q1 + 1) + 9 * (q2 + 1)] =
-            (float)b[13 + dir[0] * q0 * st[0] + dir[1] * q1 * st[1] + dir[2] * q2 * st[2]];
+  double m0, m1, m2;
+  plic::myc_normal(b, m0, m1, m2);
+  auto mv = [&](int a) { return a == 0 ? m0 : (a == 1 ? m1 : m2); };
+  int o0 = 0, o1 = 1, o2 = 2;
+  auto order2 = [&](int &a, int &bb) {  // increasing |m|, ties to the lower axis
+    if (fabs(mv(bb)) < fabs(mv(a)) || (fabs(mv(bb)) == fabs(mv(a)) && bb < a)) {
+      const int t = a;
+      a = bb;
+      bb = t;
+    }
+  };
+  order2(o0, o1);
+  order2(o0, o2);
+  order2(o1, o2);
+  cn.o0 = o0;
+  cn.o1 = o1;
+  cn.o2 = o2;
+  cn.d0 = (mv(o0) < 0.0) ? -1 : 1;
+  cn.d1 = (mv(o1) < 0.0) ? -1 : 1;
+  cn.d2 = (mv(o2) < 0.0) ? -1 : 1;
   return sign;
+}
+
+__device__ __forceinline__ int canonical_block(const double *__restrict__ c, int64_t p, int nx, int ny, int nz,
+                                               double *b, Canon &cn) {
+  load_block(c, p, nx, ny, nz, b);
+  return canonical_of_block(b, cn);
+}
+
+// Entry a = (a0, a1, a2) of the block (offsets -1..1 along x, y, z) lands at
+// canonical offsets q_k = d_k * a[o_k]: index (q0+1) + 3(q1+1) + 9(q2+1).
+template <class Put>
+__device__ __forceinline__ void canonical_scatter(const double *b, const Canon &cn, Put put) {
+#pragma unroll
+  for (int a2 = -1; a2 <= 1; ++a2)
+#pragma unroll
+    for (int a1 = -1; a1 <= 1; ++a1)
+#pragma unroll
+      for (int a0 = -1; a0 <= 1; ++a0) {
+        auto along = [&](int o) { return o == 0 ? a0 : (o == 1 ? a1 : a2); };
+        const int q0 = cn.d0 * along(cn.o0), q1 = cn.d1 * along(cn.o1), q2 = cn.d2 * along(cn.o2);
+        put((q0 + 1) + 3 * (q1 + 1) + 9 * (q2 + 1), (float)b[(a0 + 1) + 3 * (a1 + 1) + 9 * (a2 + 1)]);
+      }
 }
 
 // Canonical stencils of the listed cells: xs[q], sign[q] for cell list[q].
@@ -426,10 +463,11 @@ __global__ __launch_bounds__(256) void k_stencil_list(const double *__restrict__
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   const int64_t p = list[q];
-  const int i = (int)(p % nx), j = (int)((p / nx) % ny), k = (int)(p / ((int64_t)nx * ny));
-  float out[27];
-  const int sg = canonical_stencil(c, i, j, k, nx, ny, nz, out);
-  for (int e = 0; e < 27; ++e) xs[(int64_t)q * 27 + e] = out[e];
+  double b[27];
+  Canon cn;
+  const int sg = canonical_block(c, p, nx, ny, nz, b, cn);
+  float *row = xs + (int64_t)q * 27;
+  canonical_scatter(b, cn, [&](int e, float v) { row[e] = v; });
   sgn[q] = (int8_t)sg;
 }
 
@@ -476,6 +514,163 @@ __global__ __launch_bounds__(256) void k_curv_fallback(const double *__restrict_
     } else {
       status[p] = (uint8_t)(st | 8);
     }
+  }
+}
+
+// Learned curvature of the listed mixed cells in one pass (persistent): each
+// wavefront takes tiles of 32 cells on its own -- stencil gather and
+// canonicalisation (one lane per cell), both matrix-core layers in its own LDS
+// slice, the FP32 last layer -- and writes kappa = sign * y with status 8,
+// appending cells with |kappa| < kappa_lo to the fallback list. No block
+// barrier after the weights are staged. The arithmetic and the order of every
+// sum are those of k_mlp_fwd, so y is bit-identical to vofmt_mlp_forward on
+// the same stencils.
+constexpr int FT = 32;     // cells per wavefront tile
+constexpr int FWAVES = 8;  // wavefronts per workgroup
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(64 * FWAVES) void k_curv_fused(
+    const float *__restrict__ P, const uint16_t *__restrict__ w1t_g, const uint16_t *__restrict__ w2t_g,
+    const double *__restrict__ c, int nx, int ny, int nz, const int32_t *__restrict__ list, int nm, double kappa_lo,
+    double *__restrict__ kappa, uint8_t *__restrict__ status, int32_t *__restrict__ hf_list,
+    int32_t *__restrict__ hf_count) {
+  __shared__ __attribute__((aligned(16))) uint16_t W1s[NH][XP];
+  __shared__ __attribute__((aligned(16))) uint16_t W2s[NH][HP];
+  __shared__ __attribute__((aligned(16))) uint16_t Xh[FWAVES][FT][XP];
+  __shared__ __attribute__((aligned(16))) uint16_t Xl[FWAVES][FT][XP];
+  __shared__ __attribute__((aligned(16))) uint16_t H1[FWAVES][FT][HP];
+  __shared__ float b1s[NH], b2s[NH], w3s[NH];
+  __shared__ float yb[FWAVES][FT];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int i = tid; i < NH * NIN; i += 64 * FWAVES) W1s[i / NIN][i % NIN] = w1t_g[i];
+  for (int i = tid; i < NH * NH; i += 64 * FWAVES) W2s[i / NH][i % NH] = w2t_g[i];
+  for (int i = tid; i < NH; i += 64 * FWAVES) {
+    b1s[i] = P[OFF_B1 + i];
+    b2s[i] = P[OFF_B2 + i];
+    w3s[i] = P[OFF_W3 + i];
+  }
+  // padding inputs 27..31 stay zero
+  for (int i = lane; i < FT * NIN; i += 64) {
+    Xh[w][i / NIN][i % NIN] = 0;
+    Xl[w][i / NIN][i % NIN] = 0;
+  }
+  const float b3 = P[OFF_B3];
+  __syncthreads();
+  const int lr = lane & 15, lq = lane >> 4;
+  const int ntiles = (nm + FT - 1) / FT;
+  for (int tile = blockIdx.x * FWAVES + w; tile < ntiles; tile += gridDim.x * FWAVES) {
+    // ---- canonical stencils, one lane per cell
+    const int q = tile * FT + lane;
+    const bool own = lane < FT && q < nm;
+    int sg = 1;
+    int32_t p = 0;
+    if (own) {
+      p = list[q];
+      double b[27];
+      Canon cn;
+      sg = canonical_block(c, p, nx, ny, nz, b, cn);
+      canonical_scatter(b, cn, [&](int e, float v) {
+        const uint16_t hi = bf16_bits(v);
+        Xh[w][lane][e] = hi;
+        Xl[w][lane][e] = bf16_bits(v - bf16_val(hi));
+      });
+    } else if (lane < FT) {
+      for (int e = 0; e < 27; ++e) {
+        Xh[w][lane][e] = 0;
+        Xl[w][lane][e] = 0;
+      }
+    }
+    wave_sync();
+    // ---- layer 1: 32 rows x 128 columns
+#pragma unroll
+    for (int mt = 0; mt < FT / 16; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NH / 16; ++nt) {
+        const bf16x8 wf = frag(&W1s[16 * nt + lr][8 * lq]);
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mfma(frag(&Xh[w][16 * mt + lr][8 * lq]), wf, acc);
+        acc = mfma(frag(&Xl[w][16 * mt + lr][8 * lq]), wf, acc);
+        const int col = 16 * nt + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float z = acc[r] + b1s[col];
+          H1[w][16 * mt + 4 * lq + r][col] = bf16_bits(z > 0.0f ? z : 0.0f);
+        }
+      }
+    wave_sync();
+    // ---- layer 2 and the layer-3 partial products, summed per 32 columns as k_mlp_fwd does
+    float yq[4][FT / 16][4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int mt = 0; mt < FT / 16; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) yq[g][mt][r] = 0.0f;
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int jn = 0; jn < 2; ++jn) {
+        const int nt = 2 * g + jn;
+        const int col = 16 * nt + lr;
+#pragma unroll
+        for (int mt = 0; mt < FT / 16; ++mt) {
+          f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int kk = 0; kk < NH; kk += 32)
+            acc = mfma(frag(&H1[w][16 * mt + lr][kk + 8 * lq]), frag(&W2s[16 * nt + lr][kk + 8 * lq]), acc);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float z = acc[r] + b2s[col];
+            const float h = z > 0.0f ? z : 0.0f;
+            yq[g][mt][r] = yq[g][mt][r] + h * w3s[col];
+          }
+        }
+      }
+    float ysum[FT / 16][4];
+#pragma unroll
+    for (int mt = 0; mt < FT / 16; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float part[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          float v = yq[g][mt][r];
+          v = v + __shfl_xor(v, 8, 64);
+          v = v + __shfl_xor(v, 4, 64);
+          v = v + __shfl_xor(v, 2, 64);
+          v = v + __shfl_xor(v, 1, 64);
+          part[g] = v;
+        }
+        ysum[mt][r] = (((part[0] + part[1]) + part[2]) + part[3]) + b3;
+      }
+    if (lr == 0) {
+#pragma unroll
+      for (int mt = 0; mt < FT / 16; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) yb[w][16 * mt + 4 * lq + r] = ysum[mt][r];
+    }
+    wave_sync();
+    // ---- kappa, status, fallback list
+    bool flag = false;
+    if (own) {
+      const double kn = (double)sg * (double)yb[w][lane];
+      kappa[p] = kn;
+      status[p] = 8;
+      flag = fabs(kn) < kappa_lo;
+    }
+    const uint64_t mask = __ballot(flag);
+    if (mask) {
+      int base = 0;
+      if (lane == 0) base = atomicAdd(hf_count, (int)__popcll(mask));
+      base = __shfl(base, 0, 64);
+      if (flag) hf_list[base + __popcll(mask & ((1ull << lane) - 1))] = p;
+    }
+    wave_sync();  // the next tile overwrites this wavefront's LDS slice
   }
 }
 
@@ -616,25 +811,19 @@ extern "C" int vofmt_curvature_mlp(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32
   const int nm = hc[0];
   if (nmixed_host) *nmixed_host = nm;
   if (nm == 0) return VOFMT_OK;
-  float *xs = (float *)scratch(ctx, SLOT_MLP_X, sizeof(float) * 28 * (size_t)nm);
-  int8_t *sg = (int8_t *)scratch(ctx, SLOT_MLP_SIGN, (size_t)nm);
   int32_t *hf_list = (int32_t *)scratch(ctx, SLOT_CURV_HF, sizeof(int32_t) * (size_t)nm);
-  if (!xs || !sg || !hf_list) return VOFMT_E_NOMEM;
-  float *yv = xs + 27 * (size_t)nm;
-  rec = prof_begin(ctx, "k_stencil_list", stream);
-  hipLaunchKernelGGL(k_stencil_list, dim3(ceil_div(nm, 256)), dim3(256), 0, stream, c, nx, ny, nz, list, nm, xs, sg);
-  prof_end(ctx, rec, stream);
+  if (!hf_list) return VOFMT_E_NOMEM;
   uint16_t *w[3];
   int rc = mlp_prepare(ctx, params, w, stream);
   if (rc) return rc;
-  const int ntiles = (nm + TILE - 1) / TILE;
-  rec = prof_begin(ctx, "k_mlp_fwd", stream);
-  hipLaunchKernelGGL(k_mlp_fwd, dim3(fwd_grid(ctx, ntiles)), dim3(256), 0, stream, params, w[0], w[1], nm, xs, yv,
-                     (uint8_t *)nullptr, (const float *)nullptr, (float *)nullptr, (float *)nullptr);
-  prof_end(ctx, rec, stream);
-  rec = prof_begin(ctx, "k_curv_combine", stream);
-  hipLaunchKernelGGL(k_curv_combine, dim3(ceil_div(nm, 256)), dim3(256), 0, stream, yv, list, sg, nm, kappa_lo, kappa,
-                     status, hf_list, hf_count);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
+    cus = 256;
+  const int ftiles = (nm + FT - 1) / FT;
+  const int fgrid = ftiles < cus * FWAVES ? (ftiles + FWAVES - 1) / FWAVES : cus;
+  rec = prof_begin(ctx, "k_curv_fused", stream);
+  hipLaunchKernelGGL(k_curv_fused, dim3(fgrid), dim3(64 * FWAVES), 0, stream, params, w[0], w[1], c, nx, ny, nz, list,
+                     nm, kappa_lo, kappa, status, hf_list, hf_count);
   prof_end(ctx, rec, stream);
   rec = prof_begin(ctx, "k_curv_fallback", stream);
   hipLaunchKernelGGL(k_curv_fallback, dim3(list_grid(ctx)), dim3(256), 0, stream, c, nx, ny, nz, hf_list, hf_count,
