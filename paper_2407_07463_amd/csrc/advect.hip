@@ -7,6 +7,7 @@ using namespace advect;
 namespace {
 
 constexpr int kChunk = 32;  // cells per thread along its marching axis
+constexpr int kXWaves = 8;  // wavefronts per workgroup of the x-sweep: a 512-cell row per workgroup
 
 __global__ __launch_bounds__(256) void k_scan_mixed(const double *__restrict__ c, int64_t total,
                                                     uint32_t *__restrict__ list, int *__restrict__ counts,
@@ -24,13 +25,14 @@ __global__ __launch_bounds__(256) void k_plic(const double *__restrict__ cin, co
 }
 
 template <int D, int G>
-__global__ __launch_bounds__(256) void k_stream(const double *__restrict__ cin, double *__restrict__ cout,
-                                                const double *__restrict__ s, const double *__restrict__ fmix,
-                                                uint64_t *__restrict__ ccbits, int write_cc, int t0, int nx, int ny,
-                                                int nz, int words, int chunk, uint32_t *__restrict__ list_next,
-                                                int *__restrict__ counts_next, int64_t region0, int rsize) {
-  stream_body<D, G>(cin, cout, s, fmix, ccbits, write_cc, t0, nx, ny, nz, words, chunk, list_next, counts_next,
-                    region0, rsize, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gridDim.y);
+__global__ __launch_bounds__(64 * kXWaves) void k_stream(const double *__restrict__ cin, double *__restrict__ cout,
+                                                        const double *__restrict__ s, const double *__restrict__ fmix,
+                                                        uint64_t *__restrict__ ccbits, int write_cc, int t0, int nx,
+                                                        int ny, int nz, int words, int chunk,
+                                                        uint32_t *__restrict__ list_next, int *__restrict__ counts_next,
+                                                        int64_t region0, int rsize) {
+  stream_body<D, G, kXWaves>(cin, cout, s, fmix, ccbits, write_cc, t0, nx, ny, nz, words, chunk, list_next,
+                             counts_next, region0, rsize, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gridDim.y);
 }
 
 // Per-block maximum of |s| over the three arrays and a non-finite flag.
@@ -74,11 +76,10 @@ template <int D, int G>
 static void launch_stream(vofmt_ctx *ctx, const double *cin, double *cout, const double *s, SweepBuffers &sb, int wcc,
                           int t0, int nx, int ny, int nz, int words, int chunk, int nxt, int64_t region0,
                           hipStream_t stream) {
-  const int nrow = (D == 1) ? nz : ny;
-  const int nm = (D == 1) ? ny : nz;
-  dim3 grid(words, ceil_div(nrow, 4), ceil_div(nm, chunk));
+  const Tiles tg = stream_tiles(D, nx, ny, nz, chunk, kXWaves);
+  dim3 grid(tg.gx, tg.gy, tg.gz);
   const int rec = prof_begin(ctx, stream_name(D, G), stream);
-  hipLaunchKernelGGL((k_stream<D, G>), grid, dim3(256), 0, stream, cin, cout, s, sb.fmix, sb.bits, wcc, t0, nx, ny,
+  hipLaunchKernelGGL((k_stream<D, G>), grid, dim3(D == 0 ? 64 * kXWaves : 256), 0, stream, cin, cout, s, sb.fmix, sb.bits, wcc, t0, nx, ny,
                      nz, words, chunk, sb.list[nxt], sb.counts[nxt], region0, sb.rsize);
   prof_end(ctx, rec, stream);
 }
@@ -98,7 +99,7 @@ static void launch_sweep_axis(vofmt_ctx *ctx, const double *cin, double *cout, c
   hipLaunchKernelGGL((k_plic<D>), dim3(ceil_div(nreg, 4)), dim3(256), 0, stream, cin, s, sb.list[cur],
                      sb.counts[cur], nreg, sb.rsize, sb.fmix, nx, ny, nz, dv);
   prof_end(ctx, rec, stream);
-  const int64_t per = stream_waves(D, nx, ny, nz, chunk);
+  const int64_t per = stream_waves(D, nx, ny, nz, chunk, kXWaves);
   int64_t region0 = 0;
   int t = 0;
   while (t < ntr) {
@@ -130,7 +131,7 @@ extern "C" int vofmt_advect(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, 
                    nx, ny, nz, ntracers, nsteps, (long long)step0);
   if (ntracers == 0 || nsteps == 0) return VOFMT_OK;
   if (!c || !sx || !sy || !sz) return set_err(ctx, VOFMT_E_ARG, "vofmt_advect: null pointer");
-  if (ceil_div(ny, 4) > 65535 || ceil_div(nz, 4) > 65535)
+  if (ny > 65535 || ceil_div(nz, 4) > 65535 || ceil_div(ny, kChunk) > 65535 || ceil_div(nz, kChunk) > 65535)
     return set_err(ctx, VOFMT_E_ARG, "vofmt_advect: grid too large");
   VOFMT_HIP(ctx, hipSetDevice(ctx->device));
   const int64_t n3 = (int64_t)nx * ny * nz;
@@ -143,7 +144,7 @@ extern "C" int vofmt_advect(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, 
   uint64_t *bits = (uint64_t *)scratch(ctx, SLOT_CCBITS, sizeof(uint64_t) * (size_t)ntracers * nz * ny * words);
   // list regions: enough for the largest sweep launch set and for the initial scan
   const int rsize = region_size(kChunk);
-  const int64_t maxreg = max_regions(nx, ny, nz, ntracers, kChunk);
+  const int64_t maxreg = max_regions(nx, ny, nz, ntracers, kChunk, kXWaves);
   const int64_t total = (int64_t)ntracers * n3;
   const int64_t scanreg = (total + rsize - 1) / rsize;
   uint32_t *lists = (uint32_t *)scratch(ctx, SLOT_MIXLIST, sizeof(uint32_t) * 2 * (size_t)maxreg * rsize);

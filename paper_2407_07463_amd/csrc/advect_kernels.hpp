@@ -40,6 +40,22 @@ namespace advect {
 
 constexpr int kMaxGroup = 4;  // tracers per streaming pass (register budget)
 
+// Workgroup grid of a streaming pass (4 wavefronts per workgroup, or wpb
+// for the x-sweep).
+//   d = 0: gx = groups of wpb consecutive 64-cell x-segments, gy = y-rows,
+//          gz = chunks of z; wavefront w takes segment wpb*bx + w of row by.
+//   d = 1: gx = 64-cell segments, gy = groups of 4 z-rows, gz = chunks of y.
+//   d = 2: gx = 64-cell segments, gy = groups of 4 y-rows, gz = chunks of z.
+struct Tiles {
+  int gx, gy, gz;
+};
+__host__ __device__ inline Tiles stream_tiles(int d, int nx, int ny, int nz, int chunk, int wpb = 4) {
+  const int words = (nx + 63) / 64;
+  if (d == 0) return Tiles{(words + wpb - 1) / wpb, ny, (nz + chunk - 1) / chunk};
+  if (d == 1) return Tiles{words, (nz + 3) / 4, (ny + chunk - 1) / chunk};
+  return Tiles{words, (ny + 3) / 4, (nz + chunk - 1) / chunk};
+}
+
 struct Divisors {
   FastDiv n3, nx, ny;  // entry -> (tracer, cell), cell -> (i, j, k)
 };
@@ -130,9 +146,8 @@ __device__ __forceinline__ void plic_body(const double *__restrict__ cin, const 
 }
 
 // Tile (bx, by, bz) of a streaming pass laid out as a gx x gy x gz grid of
-// 4-wavefront workgroups: bx picks 64 x-cells, by four rows, bz a chunk of
-// the marching axis.
-template <int D, int G>
+// workgroups (stream_tiles): 4 wavefronts, or WPB for the x-sweep.
+template <int D, int G, int WPB = 4>
 __device__ __forceinline__ void stream_body(const double *__restrict__ cin, double *__restrict__ cout,
                                             const double *__restrict__ s, const double *__restrict__ fmix,
                                             uint64_t *__restrict__ ccbits, int write_cc, int t0, int nx, int ny,
@@ -140,11 +155,15 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
                                             int *__restrict__ counts_next, int64_t region0, int rsize, int bx, int by,
                                             int bz, int gx, int gy) {
   const int lane = threadIdx.x & 63;
-  const int x = bx * 64 + lane;
-  const int row = by * 4 + (threadIdx.x >> 6);
+  const int wv = threadIdx.x >> 6;
+  // x-sweep: wavefront wv takes segment 4*bx + wv of row by; others: 64-cell segment bx of row 4*by + wv
+  constexpr int W = (D == 0) ? WPB : 4;  // wavefronts per workgroup
+  const int seg = (D == 0) ? W * bx + wv : bx;
+  const int x = seg * 64 + lane;
+  const int row = (D == 0) ? by : by * 4 + wv;
   const int nrow = (D == 1) ? nz : ny;
   const int nm = (D == 1) ? ny : nz;
-  const int64_t wave = region0 + (((int64_t)bz * gy + by) * gx + bx) * 4 + (threadIdx.x >> 6);
+  const int64_t wave = region0 + (((int64_t)bz * gy + by) * gx + bx) * W + wv;
   if (row >= nrow) {  // whole wavefront
     if (lane == 0) counts_next[wave] = 0;
     return;
@@ -152,7 +171,7 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
   uint32_t *reg = list_next + wave * rsize;
   int nlist = 0;  // wavefront-uniform
   const uint64_t below = (1ull << lane) - 1;
-  const bool live = x < nx;
+  const bool live = x < nx;  // (a segment past the row end has x >= nx in every lane)
   const int xs = live ? x : nx - 1;  // dead lanes shadow a valid cell, never store
   const int64_t n3 = (int64_t)nx * ny * nz;
   const int64_t nbits = (int64_t)nz * ny * words;
@@ -168,8 +187,8 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
     return ((int64_t)mm * ny + row) * nx + xx;
   };
   auto bitword = [&](int mm) -> int64_t {
-    if (D == 1) return ((int64_t)row * ny + mm) * words + bx;
-    return ((int64_t)mm * ny + row) * words + bx;
+    if (D == 1) return ((int64_t)row * ny + mm) * words + seg;
+    return ((int64_t)mm * ny + row) * words + seg;
   };
   // flux through the lower face of cell pu: donor = the lower cell (value cl)
   // if s > 0, else the upper cell (value cu); a mixed donor's flux is in fmix
@@ -185,10 +204,10 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
     double ccv;
     if (write_cc) {
       const uint64_t word = __ballot(live && cold > 0.5);
-      if (lane == 0) b_g[t * nbits + wrow] = word;
+      if (lane == 0 && seg < words) b_g[t * nbits + wrow] = word;
       ccv = (cold > 0.5) ? 1.0 : 0.0;
     } else {
-      const uint64_t word = b_g[t * nbits + wrow];
+      const uint64_t word = (seg < words) ? b_g[t * nbits + wrow] : 0ull;  // past the row end: no cells
       ccv = ((word >> lane) & 1ull) ? 1.0 : 0.0;
     }
     const double cn = (cold - (f_hi - f_lo)) + ccv * (s_hi - s_lo);
@@ -237,23 +256,47 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
       s_lo = s_hi;
     }
   } else {
-    // ---- x-sweep: positions are z-planes; faces along x inside the row
-    // each lane forms both of its faces; the neighbours' values come from the
-    // adjacent lanes, except at the two ends of the 64-cell segment
-    const int xl = (xs == 0) ? nx - 1 : xs - 1;
-    const int xr = (xs == nx - 1) ? 0 : xs + 1;
-    const int x_last = (bx * 64 + 63 < nx) ? bx * 64 + 63 : nx - 1;
+    // ---- x-sweep: positions are z-planes; faces along x inside the row.
+    // Each lane forms both of its faces from its own and its neighbour lanes'
+    // values. The values beyond a segment's two ends come from the adjacent
+    // wavefronts of the workgroup through LDS (one barrier per position,
+    // double-buffered); only the workgroup's own two ends read memory, or
+    // wrap inside the workgroup when it holds the whole row.
+    __shared__ double edge[2][W][2][G + 1];  // [parity][wavefront][first, last][tracers..., s]
+    const int ngs = (words - W * bx < W) ? words - W * bx : W;  // segments of this workgroup
+    const bool whole_row = (bx == 0) && (words <= W);
+    const int x_last = (seg * 64 + 63 < nx) ? seg * 64 + 63 : nx - 1;
     const bool first = (lane == 0);
     const bool last = (x == x_last);
+    const int xl = (xs == 0) ? nx - 1 : xs - 1;
+    const int xr = (xs == nx - 1) ? 0 : xs + 1;
+    // the neighbours come from LDS unless they lie outside the workgroup
+    const bool l_lds = (wv > 0) || whole_row;
+    const bool r_lds = (wv + 1 < ngs) || whole_row;
+    const int wl = (wv > 0) ? wv - 1 : ngs - 1;
+    const int wr = (wv + 1 < ngs) ? wv + 1 : 0;
     for (int m = m0; m < m1; ++m) {
       const int64_t pc = cell(xs, m);
       const int64_t pl = cell(xl, m);
       const int64_t pr = cell(xr, m);
       const int64_t wrow = bitword(m);
+      const int par = m & 1;
       const double s_lo = s[pc];
       double c0[G], cl[G], cr[G];
 #pragma unroll
       for (int t = 0; t < G; ++t) c0[t] = c_g[t * n3 + pc];
+      if (seg < words && (first || last)) {
+        const int side = first ? 0 : 1;
+#pragma unroll
+        for (int t = 0; t < G; ++t) edge[par][wv][side][t] = c0[t];
+        edge[par][wv][side][G] = s_lo;
+      }
+      if (first && last && seg < words) {  // a one-cell segment is both ends
+#pragma unroll
+        for (int t = 0; t < G; ++t) edge[par][wv][1][t] = c0[t];
+        edge[par][wv][1][G] = s_lo;
+      }
+      __syncthreads();
       double s_end = 0.0, c_beg[G], c_end[G];
 #pragma unroll
       for (int t = 0; t < G; ++t) {
@@ -261,13 +304,24 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
         c_end[t] = 0.0;
       }
       if (first) {
+        if (l_lds) {
 #pragma unroll
-        for (int t = 0; t < G; ++t) c_beg[t] = c_g[t * n3 + pl];
+          for (int t = 0; t < G; ++t) c_beg[t] = edge[par][wl][1][t];
+        } else {
+#pragma unroll
+          for (int t = 0; t < G; ++t) c_beg[t] = c_g[t * n3 + pl];
+        }
       }
       if (last) {
-        s_end = s[pr];
+        if (r_lds) {
+          s_end = edge[par][wr][0][G];
 #pragma unroll
-        for (int t = 0; t < G; ++t) c_end[t] = c_g[t * n3 + pr];
+          for (int t = 0; t < G; ++t) c_end[t] = edge[par][wr][0][t];
+        } else {
+          s_end = s[pr];
+#pragma unroll
+          for (int t = 0; t < G; ++t) c_end[t] = c_g[t * n3 + pr];
+        }
       }
       const double s_dn = __shfl_down(s_lo, 1, 64);
       const double s_hi = last ? s_end : s_dn;
@@ -294,10 +348,9 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
 // ---------------------------------------------------------------- host side
 
 // Wavefronts of one streaming pass along axis d (each owns one list region).
-static inline int64_t stream_waves(int d, int nx, int ny, int nz, int chunk) {
-  const int nrow = (d == 1) ? nz : ny;
-  const int nm = (d == 1) ? ny : nz;
-  return 4 * (int64_t)ceil_div(nx, 64) * ceil_div(nrow, 4) * ceil_div(nm, chunk);
+static inline int64_t stream_waves(int d, int nx, int ny, int nz, int chunk, int wpb = 4) {
+  const Tiles g = stream_tiles(d, nx, ny, nz, chunk, wpb);
+  return (d == 0 ? wpb : 4) * (int64_t)g.gx * g.gy * g.gz;
 }
 
 // Tracer groups of one sweep: kMaxGroup tracers at a time, then groups of
@@ -316,10 +369,10 @@ static inline int num_groups(int ntr) {
 // List entries per region: every cell a wavefront of a streaming pass writes.
 static inline int region_size(int chunk) { return 64 * chunk * kMaxGroup; }
 // Regions of one list: the largest streaming sweep, or the initial scan.
-static inline int64_t max_regions(int nx, int ny, int nz, int ntr, int chunk) {
+static inline int64_t max_regions(int nx, int ny, int nz, int ntr, int chunk, int wpb = 4) {
   int64_t r = 0;
   for (int d = 0; d < 3; ++d) {
-    const int64_t w = stream_waves(d, nx, ny, nz, chunk) * num_groups(ntr);
+    const int64_t w = stream_waves(d, nx, ny, nz, chunk, wpb) * num_groups(ntr);
     r = w > r ? w : r;
   }
   const int64_t total = (int64_t)ntr * nx * ny * nz;

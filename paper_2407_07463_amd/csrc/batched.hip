@@ -223,9 +223,8 @@ static size_t plan_layout(const vofmt_box *boxes, int nboxes, int chunk, Plan &p
       begin_table(pl.off_stream[d][kind], pl.n_stream[d][kind], pl.items_stream[d][kind]);
       for (int i = 0; i < nboxes; ++i) {
         const vofmt_box &b = boxes[i];
-        const int nrow = (d == 1) ? b.nz : b.ny;
-        const int nm = (d == 1) ? b.ny : b.nz;
-        const int gx = (int)ceil_div(b.nx, 64), gy = (int)ceil_div(nrow, 4), gz = (int)ceil_div(nm, chunk);
+        const Tiles tg = stream_tiles(d, b.nx, b.ny, b.nz, chunk);
+        const int gx = tg.gx, gy = tg.gy, gz = tg.gz;
         const int64_t per = stream_waves(d, b.nx, b.ny, b.nz, chunk);
         int64_t region0 = 0;
         for (int t = 0; t < b.ntracers;) {
