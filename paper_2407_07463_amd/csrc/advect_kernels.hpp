@@ -42,16 +42,22 @@ constexpr int kMaxGroup = 4;  // tracers per streaming pass (register budget)
 
 // Workgroup grid of a streaming pass (4 wavefronts per workgroup, or wpb
 // for the x-sweep).
-//   d = 0: gx = groups of wpb consecutive 64-cell x-segments, gy = y-rows,
-//          gz = chunks of z; wavefront w takes segment wpb*bx + w of row by.
+//   d = 0: a workgroup takes rpb y-rows of spw consecutive 64-cell
+//          x-segments each (spw = min(segments per row, wpb), rpb = wpb/spw);
+//          gx = chunks of spw segments, gy = groups of rpb rows, gz = chunks
+//          of z.
 //   d = 1: gx = 64-cell segments, gy = groups of 4 z-rows, gz = chunks of y.
 //   d = 2: gx = 64-cell segments, gy = groups of 4 y-rows, gz = chunks of z.
 struct Tiles {
   int gx, gy, gz;
 };
+__host__ __device__ inline int x_segments_per_row(int words, int wpb) { return words < wpb ? words : wpb; }
 __host__ __device__ inline Tiles stream_tiles(int d, int nx, int ny, int nz, int chunk, int wpb = 4) {
   const int words = (nx + 63) / 64;
-  if (d == 0) return Tiles{(words + wpb - 1) / wpb, ny, (nz + chunk - 1) / chunk};
+  if (d == 0) {
+    const int spw = x_segments_per_row(words, wpb), rpb = wpb / spw;
+    return Tiles{(words + spw - 1) / spw, (ny + rpb - 1) / rpb, (nz + chunk - 1) / chunk};
+  }
   if (d == 1) return Tiles{words, (nz + 3) / 4, (ny + chunk - 1) / chunk};
   return Tiles{words, (ny + 3) / 4, (nz + chunk - 1) / chunk};
 }
@@ -155,23 +161,29 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
                                             int *__restrict__ counts_next, int64_t region0, int rsize, int bx, int by,
                                             int bz, int gx, int gy) {
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  // wavefront-uniform: kept in a scalar register, like everything derived from it
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // x-sweep: wavefront wv takes segment 4*bx + wv of row by; others: 64-cell segment bx of row 4*by + wv
   constexpr int W = (D == 0) ? WPB : 4;  // wavefronts per workgroup
-  const int seg = (D == 0) ? W * bx + wv : bx;
+  // x-sweep: wavefront wv takes segment bx*spw + sw of row by*rpb + rr
+  const int spw = (D == 0) ? x_segments_per_row(words, W) : 1;
+  const int rpb = (D == 0) ? W / spw : 1;
+  const int rr = wv / spw, sw = wv % spw;
+  const bool tile_ok = (D != 0) || (rr < rpb && by * rpb + rr < ny && bx * spw + sw < words);
+  const int seg = (D == 0) ? bx * spw + sw : bx;
   const int x = seg * 64 + lane;
-  const int row = (D == 0) ? by : by * 4 + wv;
+  const int row = (D == 0) ? ((by * rpb + rr < ny) ? by * rpb + rr : ny - 1) : by * 4 + wv;
   const int nrow = (D == 1) ? nz : ny;
   const int nm = (D == 1) ? ny : nz;
   const int64_t wave = region0 + (((int64_t)bz * gy + by) * gx + bx) * W + wv;
-  if (row >= nrow) {  // whole wavefront
+  if (D != 0 && row >= nrow) {  // whole wavefront (the x-sweep keeps every wavefront for its barriers)
     if (lane == 0) counts_next[wave] = 0;
     return;
   }
   uint32_t *reg = list_next + wave * rsize;
   int nlist = 0;  // wavefront-uniform
   const uint64_t below = (1ull << lane) - 1;
-  const bool live = x < nx;  // (a segment past the row end has x >= nx in every lane)
+  const bool live = tile_ok && x < nx;  // (an idle x-sweep wavefront has no live lane)
   const int xs = live ? x : nx - 1;  // dead lanes shadow a valid cell, never store
   const int64_t n3 = (int64_t)nx * ny * nz;
   const int64_t nbits = (int64_t)nz * ny * words;
@@ -204,10 +216,10 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
     double ccv;
     if (write_cc) {
       const uint64_t word = __ballot(live && cold > 0.5);
-      if (lane == 0 && seg < words) b_g[t * nbits + wrow] = word;
+      if (lane == 0 && tile_ok && seg < words) b_g[t * nbits + wrow] = word;
       ccv = (cold > 0.5) ? 1.0 : 0.0;
     } else {
-      const uint64_t word = (seg < words) ? b_g[t * nbits + wrow] : 0ull;  // past the row end: no cells
+      const uint64_t word = (tile_ok && seg < words) ? b_g[t * nbits + wrow] : 0ull;  // idle: no cells
       ccv = ((word >> lane) & 1ull) ? 1.0 : 0.0;
     }
     const double cn = (cold - (f_hi - f_lo)) + ccv * (s_hi - s_lo);
@@ -263,18 +275,18 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
     // double-buffered); only the workgroup's own two ends read memory, or
     // wrap inside the workgroup when it holds the whole row.
     __shared__ double edge[2][W][2][G + 1];  // [parity][wavefront][first, last][tracers..., s]
-    const int ngs = (words - W * bx < W) ? words - W * bx : W;  // segments of this workgroup
-    const bool whole_row = (bx == 0) && (words <= W);
+    const int ngs = (words - bx * spw < spw) ? words - bx * spw : spw;  // segments of this row chunk
+    const bool whole_row = (bx == 0) && (words <= spw);
     const int x_last = (seg * 64 + 63 < nx) ? seg * 64 + 63 : nx - 1;
     const bool first = (lane == 0);
-    const bool last = (x == x_last);
+    const bool last = tile_ok && (x == x_last);
     const int xl = (xs == 0) ? nx - 1 : xs - 1;
     const int xr = (xs == nx - 1) ? 0 : xs + 1;
-    // the neighbours come from LDS unless they lie outside the workgroup
-    const bool l_lds = (wv > 0) || whole_row;
-    const bool r_lds = (wv + 1 < ngs) || whole_row;
-    const int wl = (wv > 0) ? wv - 1 : ngs - 1;
-    const int wr = (wv + 1 < ngs) ? wv + 1 : 0;
+    // the neighbours come from LDS unless they lie outside the workgroup's row chunk
+    const bool l_lds = tile_ok && ((sw > 0) || whole_row);
+    const bool r_lds = tile_ok && ((sw + 1 < ngs) || whole_row);
+    const int wl = !tile_ok ? wv : ((sw > 0) ? wv - 1 : wv + ngs - 1);
+    const int wr = !tile_ok ? wv : ((sw + 1 < ngs) ? wv + 1 : wv - sw);
     for (int m = m0; m < m1; ++m) {
       const int64_t pc = cell(xs, m);
       const int64_t pl = cell(xl, m);
@@ -285,13 +297,13 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
       double c0[G], cl[G], cr[G];
 #pragma unroll
       for (int t = 0; t < G; ++t) c0[t] = c_g[t * n3 + pc];
-      if (seg < words && (first || last)) {
+      if (tile_ok && (first || last)) {
         const int side = first ? 0 : 1;
 #pragma unroll
         for (int t = 0; t < G; ++t) edge[par][wv][side][t] = c0[t];
         edge[par][wv][side][G] = s_lo;
       }
-      if (first && last && seg < words) {  // a one-cell segment is both ends
+      if (first && last) {  // a one-cell segment is both ends
 #pragma unroll
         for (int t = 0; t < G; ++t) edge[par][wv][1][t] = c0[t];
         edge[par][wv][1][G] = s_lo;

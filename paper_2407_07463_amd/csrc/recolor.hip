@@ -78,6 +78,18 @@ __global__ __launch_bounds__(kBlock) void k_edges(const int32_t *__restrict__ ow
   const int32_t a = own[p];
   if (a == -1) return;
   const int x = (int)(p % nx), y = (int)((p / nx) % ny), z = (int)(p / ((int64_t)nx * ny));
+  if (a >= 0) {
+    // An interior cell (all six neighbours owned by the same drop) finds no
+    // pair that a boundary cell of its drop does not: a lattice path from it
+    // towards any other drop's cell, one axis step at a time, only gets
+    // closer and leaves the drop through a boundary cell.
+    const int64_t row = (int64_t)y * nx, plane = (int64_t)z * ny * nx;
+    const bool interior =
+        own[plane + row + wrap_dec(x, nx)] == a && own[plane + row + wrap_inc(x, nx)] == a &&
+        own[plane + (int64_t)wrap_dec(y, ny) * nx + x] == a && own[plane + (int64_t)wrap_inc(y, ny) * nx + x] == a &&
+        own[(int64_t)wrap_dec(z, nz) * ny * nx + row + x] == a && own[(int64_t)wrap_inc(z, nz) * ny * nx + row + x] == a;
+    if (interior) return;
+  }
   int32_t ida[kMaxTracers];
   int na = 0;
   if (a == -2) {
