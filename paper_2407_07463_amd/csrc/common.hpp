@@ -64,6 +64,7 @@ enum ScratchSlot {
   SLOT_CURV_LIST = 20,   // curvature: list of mixed cells
   SLOT_CURV_COUNT = 21,  // its length and that of the fallback list
   SLOT_CURV_HF = 22,     // cells handed to the height-function fallback
+  SLOT_RECOLOR_LIST = 23,  // recolouring: drop-boundary and shared cells
   kNumSlots = 24,
 };
 

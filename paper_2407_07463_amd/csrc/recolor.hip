@@ -24,6 +24,7 @@
 #include <cstring>
 
 #include "common.hpp"
+#include "compact.hpp"
 
 namespace {
 
@@ -57,47 +58,29 @@ __device__ __forceinline__ void set_edge(uint32_t *adj, int64_t words, int32_t a
   if (!(*w & bit)) atomicOr(w, bit);
 }
 
-// All drops occupying cell p (for cells shared by several drops).
-__device__ __forceinline__ int drops_at(const int32_t *__restrict__ lab, int64_t n3, int ntr, const TracerOffsets &to,
-                                        int64_t p, int32_t *ids) {
-  int k = 0;
+// Calls f(id) for every drop occupying cell p (for cells shared by several drops).
+template <class F>
+__device__ __forceinline__ void for_drops_at(const int32_t *__restrict__ lab, int64_t n3, int ntr,
+                                             const TracerOffsets &to, int64_t p, F f) {
   for (int t = 0; t < ntr; ++t) {
     const int32_t l = lab[(int64_t)t * n3 + p];
-    if (l > 0 && to.off[t] + l <= to.off[t + 1]) ids[k++] = to.off[t] + l - 1;
+    if (l > 0 && to.off[t] + l <= to.off[t + 1]) f(to.off[t] + l - 1);
   }
-  return k;
 }
 
-__global__ __launch_bounds__(kBlock) void k_edges(const int32_t *__restrict__ own, const int32_t *__restrict__ lab,
-                                                  int nx, int ny, int nz, int ntr, TracerOffsets to,
-                                                  const int4 *__restrict__ offs, int noffs, int small_offsets,
-                                                  uint32_t *__restrict__ adj, int64_t words) {
-  const int64_t n3 = (int64_t)nx * ny * nz;
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= n3) return;
+__device__ __forceinline__ void edges_of(const int32_t *__restrict__ own, const int32_t *__restrict__ lab, int nx,
+                                         int ny, int nz, int ntr, const TracerOffsets &to,
+                                         const int4 *__restrict__ offs, int noffs, int small_offsets,
+                                         uint32_t *__restrict__ adj, int64_t words, int64_t n3, int64_t p) {
   const int32_t a = own[p];
-  if (a == -1) return;
   const int x = (int)(p % nx), y = (int)((p / nx) % ny), z = (int)(p / ((int64_t)nx * ny));
-  if (a >= 0) {
-    // An interior cell (all six neighbours owned by the same drop) finds no
-    // pair that a boundary cell of its drop does not: a lattice path from it
-    // towards any other drop's cell, one axis step at a time, only gets
-    // closer and leaves the drop through a boundary cell.
-    const int64_t row = (int64_t)y * nx, plane = (int64_t)z * ny * nx;
-    const bool interior =
-        own[plane + row + wrap_dec(x, nx)] == a && own[plane + row + wrap_inc(x, nx)] == a &&
-        own[plane + (int64_t)wrap_dec(y, ny) * nx + x] == a && own[plane + (int64_t)wrap_inc(y, ny) * nx + x] == a &&
-        own[(int64_t)wrap_dec(z, nz) * ny * nx + row + x] == a && own[(int64_t)wrap_inc(z, nz) * ny * nx + row + x] == a;
-    if (interior) return;
-  }
-  int32_t ida[kMaxTracers];
-  int na = 0;
   if (a == -2) {
-    na = drops_at(lab, n3, ntr, to, p, ida);
     // drops sharing this very cell are neighbours (offset 0 across tracers)
-    for (int u = 0; u < na; ++u)
-      for (int v = 0; v < na; ++v)
-        if (u != v) set_edge(adj, words, ida[u], ida[v]);
+    for_drops_at(lab, n3, ntr, to, p, [&](int32_t u) {
+      for_drops_at(lab, n3, ntr, to, p, [&](int32_t v) {
+        if (u != v) set_edge(adj, words, u, v);
+      });
+    });
   }
   for (int k = 0; k < noffs; ++k) {
     const int4 o = offs[k];
@@ -111,18 +94,55 @@ __global__ __launch_bounds__(kBlock) void k_edges(const int32_t *__restrict__ ow
       if (a != b) set_edge(adj, words, a, b);
       continue;
     }
-    int32_t idb[kMaxTracers];
-    int nb = 0;
-    if (b >= 0) idb[nb++] = b;
-    else nb = drops_at(lab, n3, ntr, to, q, idb);
-    if (a >= 0) {
-      for (int v = 0; v < nb; ++v)
-        if (idb[v] != a) set_edge(adj, words, a, idb[v]);
-    } else {
-      for (int u = 0; u < na; ++u)
-        for (int v = 0; v < nb; ++v)
-          if (ida[u] != idb[v]) set_edge(adj, words, ida[u], idb[v]);
-    }
+    // a shared cell on either side: every drop of p with every drop of q
+    auto with_q = [&](int32_t u) {
+      if (b >= 0) {
+        if (u != b) set_edge(adj, words, u, b);
+      } else {
+        for_drops_at(lab, n3, ntr, to, q, [&](int32_t v) {
+          if (u != v) set_edge(adj, words, u, v);
+        });
+      }
+    };
+    if (a >= 0) with_q(a);
+    else for_drops_at(lab, n3, ntr, to, p, with_q);
+  }
+}
+
+
+// Cells that can find a pair: shared cells, and cells of one drop with a
+// six-neighbour not owned by that drop. An interior cell finds no pair that
+// a boundary cell of its drop does not: a lattice path from it towards any
+// other drop's cell, one axis step at a time, only gets closer and leaves the
+// drop through a boundary cell.
+struct PairSources {
+  const int32_t *own;
+  int nx, ny, nz;
+  __device__ bool operator()(int64_t p) const {
+    const int32_t a = own[p];
+    if (a == -1) return false;
+    if (a == -2) return true;
+    const int x = (int)(p % nx), y = (int)((p / nx) % ny), z = (int)(p / ((int64_t)nx * ny));
+    const int64_t row = (int64_t)y * nx, plane = (int64_t)z * ny * nx;
+    return !(own[plane + row + wrap_dec(x, nx)] == a && own[plane + row + wrap_inc(x, nx)] == a &&
+             own[plane + (int64_t)wrap_dec(y, ny) * nx + x] == a &&
+             own[plane + (int64_t)wrap_inc(y, ny) * nx + x] == a &&
+             own[(int64_t)wrap_dec(z, nz) * ny * nx + row + x] == a &&
+             own[(int64_t)wrap_inc(z, nz) * ny * nx + row + x] == a);
+  }
+};
+
+// Near-contact pairs seen from the listed cells (persistent grid).
+__global__ __launch_bounds__(kBlock) void k_edges(const int32_t *__restrict__ own, const int32_t *__restrict__ lab,
+                                                  int nx, int ny, int nz, int ntr, TracerOffsets to,
+                                                  const int4 *__restrict__ offs, int noffs, int small_offsets,
+                                                  const int32_t *__restrict__ list, const int32_t *__restrict__ count,
+                                                  uint32_t *__restrict__ adj, int64_t words) {
+  const int64_t n3 = (int64_t)nx * ny * nz;
+  const int nlist = *count;
+  for (int qi = blockIdx.x * kBlock + threadIdx.x; qi < nlist; qi += gridDim.x * kBlock) {
+    const int64_t p = list[qi];
+    edges_of(own, lab, nx, ny, nz, ntr, to, offs, noffs, small_offsets, adj, words, n3, p);
   }
 }
 
@@ -376,8 +396,20 @@ extern "C" int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int
   const unsigned nbc = ceil_div(n3, kBlock);
   hipLaunchKernelGGL(k_owner, dim3(nbc), dim3(kBlock), 0, stream, labels, n3, ntr, to, own);
   hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, stream, adj, D * words, 0u);
-  hipLaunchKernelGGL(k_edges, dim3(nbc), dim3(kBlock), 0, stream, own, labels, nx, ny, nz, ntr, to, doffs, noffs,
-                     small_offsets, adj, words);
+  {
+    // the cells that can see a pair, in order, then the pairs they see
+    const int64_t lt = compact::list_tiles(n3);
+    int32_t *srcs = (int32_t *)scratch(ctx, SLOT_RECOLOR_LIST, sizeof(int32_t) * (size_t)n3);
+    int32_t *bc = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * (size_t)nbc);
+    int32_t *tot = (int32_t *)scratch(ctx, SLOT_CURV_COUNT, sizeof(int32_t) * (size_t)(lt + 2));
+    if (!srcs || !bc || !tot) return VOFMT_E_NOMEM;
+    compact::launch_ordered_list_if(n3, PairSources{own, nx, ny, nz}, bc, tot, srcs, stream);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
+      cus = 256;
+    hipLaunchKernelGGL(k_edges, dim3(8 * cus), dim3(kBlock), 0, stream, own, labels, nx, ny, nz, ntr, to, doffs,
+                       noffs, small_offsets, srcs, tot + lt, adj, words);
+  }
   hipLaunchKernelGGL(k_symmetrise, dim3(ceil_div(D * D, kBlock)), dim3(kBlock), 0, stream, adj, (int32_t)D, words);
   hipLaunchKernelGGL(k_degree, dim3(ceil_div(D, kBlock)), dim3(kBlock), 0, stream, adj, (int32_t)D, words, deg);
   hipLaunchKernelGGL(k_scan_deg, dim3(1), dim3(1024), 0, stream, deg, (int32_t)D, rowptr);
