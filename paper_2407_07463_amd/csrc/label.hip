@@ -20,6 +20,7 @@
 // The result is bit-identical to a sequential flood fill seeded in linear
 // order.
 #include "common.hpp"
+#include "compact.hpp"
 
 namespace {
 
@@ -131,35 +132,17 @@ __global__ __launch_bounds__(kBlock) void k_label_flatten(int32_t *P, int64_t n3
   }
 }
 
-// Exclusive scan of nb block counts in one workgroup; total to *total.
-__global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *__restrict__ v, int64_t nb, int32_t *__restrict__ total) {
-  __shared__ uint64_t part[1024];
-  const int t = threadIdx.x;
-  const int64_t per = (nb + 1023) / 1024;
-  const int64_t lo = t * per, hi = (lo + per < nb) ? lo + per : nb;
-  uint64_t s = 0;
-  for (int64_t i = lo; i < hi; ++i) s += v[i];
-  part[t] = s;
-  __syncthreads();
-  // Hillis-Steele inclusive scan of the 1024 partials
-  for (int off = 1; off < 1024; off <<= 1) {
-    uint64_t add = (t >= off) ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += add;
-    __syncthreads();
-  }
-  uint64_t run = (t == 0) ? 0 : part[t - 1];
-  for (int64_t i = lo; i < hi; ++i) {
-    uint32_t x = v[i];
-    v[i] = (uint32_t)run;
-    run += x;
-  }
-  if (t == 1023) *total = (int32_t)part[1023];
+// The total of the tiled scan into *total.
+__global__ void k_copy_total(const int32_t *__restrict__ tot, int64_t ntiles, int32_t *__restrict__ total) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *total = tot[ntiles];
 }
 
 // Rank every root: rootlab[p] = 1 + number of roots before p; rootpos[rank] = p.
+// blockoff: per-block exclusive offsets within tiles of compact::kTile
+// blocks, tileoff: exclusive offsets of the tiles.
 __global__ __launch_bounds__(kBlock) void k_label_rank(const int32_t *__restrict__ P, int64_t n3,
-                                                       const uint32_t *__restrict__ blockoff,
+                                                       const int32_t *__restrict__ blockoff,
+                                                       const int32_t *__restrict__ tileoff,
                                                        int32_t *__restrict__ rootlab, int32_t *__restrict__ rootpos) {
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool root = (p < n3) && (P[p] == p);
@@ -169,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_label_rank(const int32_t *__restrict
   if (lane == 0) wcount[w] = (uint32_t)__popcll(m);
   __syncthreads();
   if (!root) return;
-  uint32_t before = blockoff[blockIdx.x];
+  uint32_t before = (uint32_t)(blockoff[blockIdx.x] + tileoff[blockIdx.x / compact::kTile]);
   for (int k = 0; k < w; ++k) before += wcount[k];
   before += (uint32_t)__popcll(m & ((1ull << lane) - 1));
   rootlab[p] = (int32_t)before + 1;
@@ -210,7 +193,8 @@ __device__ __forceinline__ int wave_max(int v) {
 // The lanes of a wavefront that hold the same drop are combined first, so
 // each drop sees one set of atomics per wavefront instead of one per cell.
 __global__ __launch_bounds__(kBlock) void k_drop_bbox(const int32_t *__restrict__ lab, int64_t n3, int nx, int ny, int nz,
-                                                      int32_t K, const int32_t *__restrict__ rootpos,
+                                                      FastDiv fnx, FastDiv fny, int32_t K,
+                                                      const int32_t *__restrict__ rootpos,
                                                       int32_t *__restrict__ box) {
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int lane = threadIdx.x & 63;
@@ -218,9 +202,12 @@ __global__ __launch_bounds__(kBlock) void k_drop_bbox(const int32_t *__restrict_
   const bool valid = l > 0 && l <= K;
   int d[3] = {0, 0, 0};
   if (valid) {
-    const int32_t p0 = rootpos[l - 1];
-    const int x = (int)(p % nx), y = (int)((p / nx) % ny), z = (int)(p / ((int64_t)nx * ny));
-    const int x0 = p0 % nx, y0 = (p0 / nx) % ny, z0 = p0 / (nx * ny);
+    const uint32_t p0 = (uint32_t)rootpos[l - 1];
+    // cell -> (x, y, z) by multiply-shift division (cells < 2^31)
+    const uint32_t r = fast_div((uint32_t)p, fnx), r0 = fast_div(p0, fnx);
+    const uint32_t zz = fast_div(r, fny), zz0 = fast_div(r0, fny);
+    const int x = (int)((uint32_t)p - r * (uint32_t)nx), y = (int)(r - zz * (uint32_t)ny), z = (int)zz;
+    const int x0 = (int)(p0 - r0 * (uint32_t)nx), y0 = (int)(r0 - zz0 * (uint32_t)ny), z0 = (int)zz0;
     d[0] = wrapped_delta(x, x0, nx);
     d[1] = wrapped_delta(y, y0, ny);
     d[2] = wrapped_delta(z, z0, nz);
@@ -293,10 +280,11 @@ __global__ __launch_bounds__(kBlock) void k_drop_sums(const double *__restrict__
   const int ex = b[1] - b[0] + 1, ey = b[3] - b[2] + 1, ez = b[5] - b[4] + 1;
   const int64_t nbox = (int64_t)ex * ey * ez;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  for (int64_t q = threadIdx.x; q < nbox; q += kBlock) {
-    const int dx = (int)(q % ex) + lx;
-    const int dy = (int)((q / ex) % ey) + ly;
-    const int dz = (int)(q / ((int64_t)ex * ey)) + lz;
+  // a drop spans less than half the box along each axis: its box has < 2^31 cells
+  for (int q = threadIdx.x; q < (int)nbox; q += kBlock) {
+    const int dx = q % ex + lx;
+    const int dy = (q / ex) % ey + ly;
+    const int dz = q / (ex * ey) + lz;
     const int x = wrap_any(x0 + dx, nx), y = wrap_any(y0 + dy, ny), z = wrap_any(z0 + dz, nz);
     const int64_t p = ((int64_t)z * ny + y) * nx + x;
     if (lab[p] != l) continue;
@@ -337,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_drop_sums(const double *__restrict__
 // Label one tracer field into `lab` (also used by recolouring). Returns K via
 // *k_dev (device int32). Scratch: block counts; rootlab (n3 int32).
 static int label_one(vofmt_ctx *ctx, int nx, int ny, int nz, const double *c, double c_eps, int32_t *lab,
-                     uint32_t *blockcount, int32_t *rootlab, int32_t *k_dev, hipStream_t stream) {
+                     uint32_t *blockcount, int32_t *tileoff, int32_t *rootlab, int32_t *k_dev, hipStream_t stream) {
   const int64_t n3 = (int64_t)nx * ny * nz;
   const int words = (int)ceil_div(nx, 64);
   const int64_t nwaves = (int64_t)ny * nz * words;
@@ -346,8 +334,14 @@ static int label_one(vofmt_ctx *ctx, int nx, int ny, int nz, const double *c, do
   hipLaunchKernelGGL(k_label_init, dim3(nb_init), dim3(kBlock), 0, stream, c, c_eps, lab, nx, ny, nz, words);
   hipLaunchKernelGGL(k_label_merge, dim3(nb), dim3(kBlock), 0, stream, lab, nx, ny, nz);
   hipLaunchKernelGGL(k_label_flatten, dim3(nb), dim3(kBlock), 0, stream, lab, n3, blockcount);
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, stream, blockcount, (int64_t)nb, k_dev);
-  hipLaunchKernelGGL(k_label_rank, dim3(nb), dim3(kBlock), 0, stream, lab, n3, blockcount, rootlab,
+  static_assert(kBlock == compact::kBlock, "block counts and the tiled scan share the block size");
+  const int64_t ntiles = (nb + compact::kTile - 1) / compact::kTile;
+  int32_t *bc = (int32_t *)blockcount;
+  hipLaunchKernelGGL(compact::k_scan_tile, dim3((unsigned)ntiles), dim3(compact::kTile), 0, stream, bc, (int64_t)nb,
+                     tileoff);
+  hipLaunchKernelGGL(compact::k_scan_totals, dim3(1), dim3(compact::kTile), 0, stream, tileoff, ntiles);
+  hipLaunchKernelGGL(k_copy_total, dim3(1), dim3(64), 0, stream, tileoff, ntiles, k_dev);
+  hipLaunchKernelGGL(k_label_rank, dim3(nb), dim3(kBlock), 0, stream, lab, n3, bc, tileoff, rootlab,
                      (int32_t *)nullptr);
   hipLaunchKernelGGL(k_label_final, dim3(nb), dim3(kBlock), 0, stream, lab, n3, rootlab);
   return hip_check(ctx, hipGetLastError(), "label kernels");
@@ -368,11 +362,12 @@ extern "C" int vofmt_label_drops(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t
   uint32_t *blockcount = (uint32_t *)scratch(ctx, SLOT_LABEL_A, sizeof(uint32_t) * (size_t)nb);
   int32_t *rootlab = (int32_t *)scratch(ctx, SLOT_LABEL_B, sizeof(int32_t) * (size_t)n3);
   int32_t *kdev = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * (size_t)ntracers);
+  int32_t *tileoff = (int32_t *)scratch(ctx, SLOT_MISC3, sizeof(int32_t) * (size_t)(compact::list_tiles(n3) + 1));
   int32_t *kh = (int32_t *)host_scratch(ctx, sizeof(int32_t) * (size_t)ntracers);
-  if (!blockcount || !rootlab || !kdev || !kh) return VOFMT_E_NOMEM;
+  if (!blockcount || !rootlab || !kdev || !tileoff || !kh) return VOFMT_E_NOMEM;
   for (int t = 0; t < ntracers; ++t) {
-    int rc = label_one(ctx, nx, ny, nz, c + (int64_t)t * n3, c_eps, labels + (int64_t)t * n3, blockcount, rootlab,
-                       kdev + t, stream);
+    int rc = label_one(ctx, nx, ny, nz, c + (int64_t)t * n3, c_eps, labels + (int64_t)t * n3, blockcount, tileoff,
+                       rootlab, kdev + t, stream);
     if (rc) return rc;
   }
   VOFMT_HIP(ctx, hipMemcpyAsync(kh, kdev, sizeof(int32_t) * ntracers, hipMemcpyDeviceToHost, stream));
@@ -396,6 +391,7 @@ extern "C" int vofmt_drop_moments(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_
   if (D == 0) return VOFMT_OK;
   if (!vol || !xyz) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_moments: null output");
   const int64_t n3 = (int64_t)nx * ny * nz;
+  if (n3 >= INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_moments: more than 2^31-1 cells per field");
   VOFMT_HIP(ctx, hipSetDevice(ctx->device));
   const unsigned nb = ceil_div(n3, kBlock);
   int64_t kmax = 0;
@@ -406,6 +402,7 @@ extern "C" int vofmt_drop_moments(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_
   int32_t *fh = (int32_t *)host_scratch(ctx, sizeof(int32_t) * 2);
   if (!rootpos || !box || !flags || !fh) return VOFMT_E_NOMEM;
   VOFMT_HIP(ctx, hipMemsetAsync(flags, 0, sizeof(int32_t) * 2, stream));
+  const FastDiv fnx = make_fastdiv((uint32_t)nx), fny = make_fastdiv((uint32_t)ny);
   int64_t off = 0;
   for (int t = 0; t < ntracers; ++t) {
     const int32_t K = ndrops_host[t];
@@ -414,7 +411,8 @@ extern "C" int vofmt_drop_moments(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_
     hipLaunchKernelGGL(k_first_init, dim3(ceil_div(K, 256)), dim3(256), 0, stream, rootpos, (int64_t)K);
     hipLaunchKernelGGL(k_first_min, dim3(nb), dim3(kBlock), 0, stream, lab, n3, K, rootpos);
     hipLaunchKernelGGL(k_box_init, dim3(ceil_div(6 * (int64_t)K, 256)), dim3(256), 0, stream, box, (int64_t)K);
-    hipLaunchKernelGGL(k_drop_bbox, dim3(nb), dim3(kBlock), 0, stream, lab, n3, nx, ny, nz, K, rootpos, box);
+    hipLaunchKernelGGL(k_drop_bbox, dim3(nb), dim3(kBlock), 0, stream, lab, n3, nx, ny, nz, fnx, fny, K, rootpos,
+                       box);
     hipLaunchKernelGGL(k_drop_sums, dim3(K), dim3(kBlock), 0, stream, c + (int64_t)t * n3, lab, nx, ny, nz, rootpos,
                        box, vol + off, xyz + 3 * off, flags);
     VOFMT_HIP(ctx, hipGetLastError());
