@@ -7,14 +7,16 @@ placed by random sequential addition with a 1-cell gap, and a frozen random
 solenoidal velocity (modes 1 <= |k| <= 8, E(k) ~ k^-5/3, rms 0.2 cells per
 step, rise 0.1). All inputs are synthetic and seeded.
 
-A step is one direction-split advection step of all tracers (three sweeps,
-each a PLIC pass over the mixed cells and streaming passes over the fields).
-`value` is the whole-job advection throughput in tracer-cell-steps per second
-with the fields resident in HBM, timed with HIP events on the stream the
-kernels run on. `roofline` is that of the dominant kernel, the streaming pass
-(k_stream), from its own launches timed with HIP events in a second timed
-region of the same K steps; `traffic` comes from the committed rocprofv3
-counter summary when the advection sources have not changed since.
+A step is one direction-split advection step of all tracers (three sweeps).
+Consecutive sweeps run in pairs: PLIC passes over the mixed cells of each
+sweep, then one streaming pass (k_pair) that reads the fields once and writes
+them once per two sweeps. `value` is the whole-job advection throughput in
+tracer-cell-steps per second with the fields resident in HBM, timed with HIP
+events on the stream the kernels run on. `roofline` is that of the dominant
+kernel, the paired streaming pass (k_pair; k_stream with --sweeps single),
+from its own launches timed with HIP events in a second timed region of the
+same K steps; `traffic` comes from the committed rocprofv3 counter summary
+when the advection sources have not changed since.
 
 The same line carries, under `rows`, the other steps of the path measured on
 the advected field: drop labelling, moments, recolouring, pair statistics,
@@ -39,7 +41,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, GB/s
 BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix cores
 METRIC = "VoF cell-updates/s per tracer (FP64) at % HBM roofline; learned vs HF curvature cells/s"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_k_stream_drops512.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_k_pair_drops512.txt")
+TRAFFIC_FILE_SINGLE = os.path.join(ROOT, "profiles", "hbm_traffic_k_stream_drops512.txt")
 COPY_BYTES = 1 << 30
 
 
@@ -48,6 +51,15 @@ def stream_bytes(n3: int, g: int) -> float:
     write every field value (16 B per tracer-cell), read the face velocity
     (8 B per cell) and one c > 0.5 bit per tracer-cell."""
     return n3 * (16.0 * g + 8.0 + g / 8.0)
+
+
+def pair_bytes(n3: int, ntr: int, candidates: bool) -> float:
+    """Algorithmic HBM bytes of one paired streaming pass over all tracers:
+    read and write every field value once (16 B per tracer-cell), read the
+    face velocities of both sweeps (8 B per cell each) and, when it lists the
+    candidates of the following sweep, that sweep's face velocity; one c > 0.5
+    bit per tracer-cell."""
+    return n3 * (16.0 * ntr + 8.0 * (3 if candidates else 2) + ntr / 8.0)
 
 
 def step_model_bytes(n3: int, ntr: int) -> float:
@@ -217,6 +229,8 @@ def main():
     ap.add_argument("--no-rows", action="store_true", help="advection only")
     ap.add_argument("--cpu-sample-tracers", type=int, default=2)
     ap.add_argument("--pmc-pass", action="store_true", help="short run for rocprofv3 counters")
+    ap.add_argument("--sweeps", choices=("paired", "single"), default="paired",
+                    help="run consecutive sweeps in pairs (default) or one at a time")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -238,6 +252,7 @@ def main():
     c = torch.from_numpy(w["c"]).to(dev)
     s = [torch.from_numpy(w[k]).to(dev) for k in ("sx", "sy", "sz")]
     ctx = vofmt.Context(0)
+    ctx.set_advect_pairs(args.sweeps == "paired")
     smax = ctx.check_courant(*s)
     stream = torch.cuda.current_stream()
     n3 = n ** 3
@@ -269,19 +284,33 @@ def main():
     ms2, _ = timed(torch, stream, lambda: ctx.advect(c, *s, step0=0, nsteps=args.steps))
     prof = ctx.profile_stop()
     kernels = {k: dict(launches=v[0], avg_ms=v[1] / v[0], total_ms=v[1]) for k, v in prof.items()}
-    stream_names = [k for k in prof if k.startswith("k_stream<")]
-    st_launches = sum(prof[k][0] for k in stream_names)
-    st_total = sum(prof[k][1] for k in stream_names)
-    g = 4 if ntr >= 4 else ntr
-    bytes_launch = stream_bytes(n3, g)
-    achieved = bytes_launch / (st_total / st_launches / 1e3) / 1e9
-    log(f"k_stream: {st_launches} launches, avg {st_total / st_launches:.3f} ms, {achieved:.0f} GB/s "
-        f"(profiled region {ms2 / args.steps:.3f} ms/step)")
+    pair_names = [k for k in prof if k.startswith("k_pair<")]
+    if pair_names:  # paired sweeps: the paired streaming pass over all tracers
+        launches = sum(prof[k][0] for k in pair_names)
+        total_ms = sum(prof[k][1] for k in pair_names)
+        nbytes = sum(prof[k][0] * pair_bytes(n3, ntr, not k.endswith(",3>")) for k in pair_names)
+        bytes_launch = nbytes / launches
+        achieved = nbytes / (total_ms / 1e3) / 1e9
+        kernel_desc = f"k_pair<A,B,N> (two sweeps of all {ntr} tracers in one pass; all axis pairs)"
+        log(f"k_pair: {launches} launches, avg {total_ms / launches:.3f} ms, {achieved:.0f} GB/s "
+            f"(profiled region {ms2 / args.steps:.3f} ms/step)")
+        prefix, traffic_file = "k_pair<", TRAFFIC_FILE
+    else:
+        stream_names = [k for k in prof if k.startswith("k_stream<")]
+        launches = sum(prof[k][0] for k in stream_names)
+        total_ms = sum(prof[k][1] for k in stream_names)
+        g = 4 if ntr >= 4 else ntr
+        bytes_launch = stream_bytes(n3, g)
+        achieved = bytes_launch / (total_ms / launches / 1e3) / 1e9
+        kernel_desc = f"k_stream<D,{g}> (streaming pass of {g} tracers; all axes)"
+        log(f"k_stream: {launches} launches, avg {total_ms / launches:.3f} ms, {achieved:.0f} GB/s "
+            f"(profiled region {ms2 / args.steps:.3f} ms/step)")
+        prefix, traffic_file = "k_stream<", TRAFFIC_FILE_SINGLE
 
     traffic = None
-    tr, sha = profiling.read_traffic(TRAFFIC_FILE)
+    tr, sha = profiling.read_traffic(traffic_file)
     if tr and sha == profiling.advect_source_sha():
-        vals = [v for k, v in tr.items() if k.startswith(f"k_stream<") and k.endswith(f", {g}>")]
+        vals = [v for k, v in tr.items() if k.startswith(prefix)]
         if vals:
             traffic = sum(vals) / len(vals)
 
@@ -315,7 +344,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": f"k_stream<D,{g}> (streaming pass of {g} tracers; all axes)",
+            "kernel": kernel_desc,
             "bytes_per_launch": bytes_launch,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         },

@@ -85,6 +85,36 @@ __device__ __forceinline__ void scan_body(const double *__restrict__ c, int64_t 
   if (lane == 0) counts[w] = n;
 }
 
+// Fluxes through the faces along D that a mixed cell donates through, from
+// its 3x3x3 block b (centre value b[13]): MYC normal, plane constant, then the
+// volume of the sub-box that crosses each face within the sweep: [0, |s|]
+// along D for the lower face (when s_lo < 0), [1 - s, 1] for the upper face
+// (when s_hi > 0). The flux is s times that volume; faces not donated through
+// get 0.
+template <int D>
+__device__ __forceinline__ void plic_fluxes(const double *b, double s_lo, double s_hi, double &f_lo, double &f_hi) {
+  double mx, my, mz;
+  plic::myc_normal(b, mx, my, mz);
+  const double alpha = plic::alpha_of(mx, my, mz, b[13]);
+  const double md = (D == 0) ? mx : ((D == 1) ? my : mz);
+  f_lo = 0.0;
+  f_hi = 0.0;
+#pragma unroll 1
+  for (int face = 0; face < 2; ++face) {
+    const double sv = (face == 0) ? s_lo : s_hi;
+    if (face == 0 ? !(sv < 0.0) : !(sv > 0.0)) continue;
+    const double x0 = (face == 0) ? 0.0 : 1.0 - sv;
+    const double as = alpha - md * x0;
+    const double ms = md * fabs(sv);
+    double v;
+    if (D == 0) v = plic::volume(ms, my, mz, as);
+    else if (D == 1) v = plic::volume(mx, ms, mz, as);
+    else v = plic::volume(mx, my, ms, as);
+    if (face == 0) f_lo = sv * v;
+    else f_hi = sv * v;
+  }
+}
+
 template <int D>
 __device__ __forceinline__ void plic_body(const double *__restrict__ cin, const double *__restrict__ s,
                                           const uint32_t *__restrict__ list, const int *__restrict__ counts,
@@ -110,7 +140,6 @@ __device__ __forceinline__ void plic_body(const double *__restrict__ cin, const 
     const double s_lo = s[p], s_hi = s[pu];
     if (!(s_lo < 0.0) && !(s_hi > 0.0)) continue;  // donates through neither face
     const double *ct = cin + t * n3;
-    const double cd = ct[p];
     double b[27];
     {
       const int im = wrap_dec(i, nx), ip = wrap_inc(i, nx);
@@ -128,26 +157,11 @@ __device__ __forceinline__ void plic_body(const double *__restrict__ cin, const 
           for (int ax = 0; ax < 3; ++ax) b[ax + 3 * ay + 9 * az] = rowp[xs[ax]];
         }
     }
-    double mx, my, mz;
-    plic::myc_normal(b, mx, my, mz);
-    const double alpha = plic::alpha_of(mx, my, mz, cd);
-    const double md = (D == 0) ? mx : ((D == 1) ? my : mz);
+    double f_lo, f_hi;
+    plic_fluxes<D>(b, s_lo, s_hi, f_lo, f_hi);
     double *ft = fmix + t * n3;
-    // the faces this cell donates through: the lower one (sub-box [0, |s|]
-    // along D) when s < 0 there, the upper one (sub-box [1 - s, 1]) when s > 0
-#pragma unroll 1
-    for (int face = 0; face < 2; ++face) {
-      const double sv = (face == 0) ? s_lo : s_hi;
-      if (face == 0 ? !(sv < 0.0) : !(sv > 0.0)) continue;
-      const double x0 = (face == 0) ? 0.0 : 1.0 - sv;
-      const double as = alpha - md * x0;
-      const double ms = md * fabs(sv);
-      double v;
-      if (D == 0) v = plic::volume(ms, my, mz, as);
-      else if (D == 1) v = plic::volume(mx, ms, mz, as);
-      else v = plic::volume(mx, my, ms, as);
-      ft[face == 0 ? p : pu] = sv * v;
-    }
+    if (s_lo < 0.0) ft[p] = f_lo;
+    if (s_hi > 0.0) ft[pu] = f_hi;
   }
 }
 

@@ -11,6 +11,8 @@
 
 #include "vofmt.h"
 
+enum { kNumSlotsDecl = 25 };
+
 // One timed launch: HIP events recorded before and after it on its stream.
 struct ProfRec {
   const char *name;
@@ -21,8 +23,8 @@ struct vofmt_ctx {
   int device = 0;
   std::string err;
   // Scratch buffers, grown on demand (never shrunk) and reused by later calls.
-  void *buf[24] = {};
-  size_t cap[24] = {};
+  void *buf[kNumSlotsDecl] = {};
+  size_t cap[kNumSlotsDecl] = {};
   // Pinned host staging for small results read back by synchronising calls.
   void *host = nullptr;
   size_t host_cap = 0;
@@ -37,6 +39,8 @@ struct vofmt_ctx {
   std::vector<ProfRec> prof;
   std::vector<hipEvent_t> prof_pool;
   size_t prof_used = 0;
+  // Advection runs consecutive sweeps in pairs unless switched off.
+  bool advect_pairs = false;
 };
 
 // Scratch slots (one buffer per role).
@@ -65,8 +69,10 @@ enum ScratchSlot {
   SLOT_CURV_COUNT = 21,  // its length and that of the fallback list
   SLOT_CURV_HF = 22,     // cells handed to the height-function fallback
   SLOT_RECOLOR_LIST = 23,  // recolouring: drop-boundary and shared cells
-  kNumSlots = 24,
+  SLOT_FMIX2 = 24,         // paired sweeps: fluxes of the second sweep's mixed donors
+  kNumSlots = 25,
 };
+static_assert(kNumSlots == kNumSlotsDecl, "scratch slot count");
 
 int set_err(vofmt_ctx *ctx, int code, const char *fmt, ...);
 int hip_check(vofmt_ctx *ctx, hipError_t e, const char *what);

@@ -25,7 +25,8 @@ import re
 from collections import defaultdict
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-ADVECT_SOURCES = ["csrc/advect_kernels.hpp", "csrc/plic.hpp", "csrc/advect.hip", "csrc/common.hpp"]
+ADVECT_SOURCES = ["csrc/advect_kernels.hpp", "csrc/pair_kernels.hpp", "csrc/plic.hpp", "csrc/advect.hip",
+                  "csrc/common.hpp"]
 
 
 def advect_source_sha() -> str:
