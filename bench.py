@@ -7,16 +7,15 @@ placed by random sequential addition with a 1-cell gap, and a frozen random
 solenoidal velocity (modes 1 <= |k| <= 8, E(k) ~ k^-5/3, rms 0.2 cells per
 step, rise 0.1). All inputs are synthetic and seeded.
 
-A step is one direction-split advection step of all tracers (three sweeps).
-Consecutive sweeps run in pairs: PLIC passes over the mixed cells of each
-sweep, then one streaming pass (k_pair) that reads the fields once and writes
-them once per two sweeps. `value` is the whole-job advection throughput in
-tracer-cell-steps per second with the fields resident in HBM, timed with HIP
-events on the stream the kernels run on. `roofline` is that of the dominant
-kernel, the paired streaming pass (k_pair; k_stream with --sweeps single),
-from its own launches timed with HIP events in a second timed region of the
-same K steps; `traffic` comes from the committed rocprofv3 counter summary
-when the advection sources have not changed since.
+A step is one direction-split advection step of all tracers (three sweeps,
+each a PLIC pass over the mixed cells and streaming passes over the fields;
+--sweeps paired runs two sweeps per streaming pass instead). `value` is the
+whole-job advection throughput in tracer-cell-steps per second with the
+fields resident in HBM, timed with HIP events on the stream the kernels run
+on. `roofline` is that of the dominant kernel, the streaming pass (k_stream;
+k_pair when paired), from its own launches timed with HIP events in a second
+timed region of the same K steps; `traffic` comes from the committed
+rocprofv3 counter summary when the advection sources have not changed since.
 
 The same line carries, under `rows`, the other steps of the path measured on
 the advected field: drop labelling, moments, recolouring, pair statistics,
@@ -229,8 +228,8 @@ def main():
     ap.add_argument("--no-rows", action="store_true", help="advection only")
     ap.add_argument("--cpu-sample-tracers", type=int, default=2)
     ap.add_argument("--pmc-pass", action="store_true", help="short run for rocprofv3 counters")
-    ap.add_argument("--sweeps", choices=("paired", "single"), default="paired",
-                    help="run consecutive sweeps in pairs (default) or one at a time")
+    ap.add_argument("--sweeps", choices=("single", "paired"), default="single",
+                    help="run the sweeps one at a time (default, the faster form on this GPU) or in pairs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)

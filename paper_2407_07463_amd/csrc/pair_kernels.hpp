@@ -290,14 +290,25 @@ __device__ __forceinline__ void plic_b_body(const double *__restrict__ cin, cons
       }
 #pragma unroll
       for (int o = 0; o < 4; ++o) s4[o] = sA[idx[o + 1]];
+      // face f (f = 0..3) is the lower face of the cell at offset f - 1: its
+      // mixed-donor flag, then all flux loads at once, then the three values
+      bool dm[4];
+      double fv[4];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) dm[f] = mixed_donor(s4[f], c5[f], c5[f + 1]);
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        fv[f] = 0.0;
+        if (dm[f]) fv[f] = fa[idx[f + 1]];
+      }
 #pragma unroll
       for (int o = 0; o < 3; ++o) {
         xyz[A] = P[o + 1];
         const double c0 = c5[o + 1];
         const double cc = cc_from_field ? ((c0 > 0.5) ? 1.0 : 0.0) : cc_bit(bt, xyz[0], xyz[1], xyz[2], ny, words);
         const double slo = s4[o], shi = s4[o + 1];
-        const double flo = face_flux(slo, c5[o], c0, fa, idx[o + 1]);
-        const double fhi = face_flux(shi, c0, c5[o + 2], fa, idx[o + 2]);
+        const double flo = dm[o] ? fv[o] : pure_flux(slo, c5[o], c0);
+        const double fhi = dm[o + 1] ? fv[o + 1] : pure_flux(shi, c0, c5[o + 2]);
         bl[block_index<A>(o - 1, u, v) * 64 + eb] = swept(c0, flo, fhi, slo, shi, cc);
       }
     }
@@ -515,6 +526,28 @@ __device__ __forceinline__ void pair_body(const PairArgs &a, int logical) {
       const double *src = f0 + ((j1 - jb) % D0) * P0;
       const double *srcl = (A == 2) ? f0 + ((j1 - 1 - jb) % D0) * P0 : src;
       const double *srcu = (A == 2) ? f0 + ((j1 + 1 - jb) % D0) * P0 : src;
+      // mixed donors first, then all their flux loads at once, then the values
+      bool dl[NQ1], dh[NQ1];
+      double fl[NQ1], fh[NQ1];
+#pragma unroll
+      for (int k = 0; k < NQ1; ++k) {
+        const int q = tid + k * kPairThreads;
+        dl[k] = dh[k] = false;
+        if (q < P1) {
+          const int ry = q / W1, rx = q - ry * W1;
+          const int i0 = (ry + (A == 1)) * W0 + rx + (A == 0);
+          const double c0 = src[i0], cl = srcl[i0 - oA], cu = srcu[i0 + oA];
+          dl[k] = mixed_donor(rA[k][0], cl, c0);
+          dh[k] = mixed_donor(rA[k][1], c0, cu);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NQ1; ++k) {
+        fl[k] = 0.0;
+        fh[k] = 0.0;
+        if (dl[k]) fl[k] = fa[pz + o1[k]];
+        if (dh[k]) fh[k] = fa[pzu + o1u[k]];
+      }
 #pragma unroll
       for (int k = 0; k < NQ1; ++k) {
         const int q = tid + k * kPairThreads;
@@ -524,8 +557,9 @@ __device__ __forceinline__ void pair_body(const PairArgs &a, int logical) {
           const double c0 = src[i0], cl = srcl[i0 - oA], cu = srcu[i0 + oA];
           const double slo = rA[k][0], shi = rA[k][1];
           const double cc = (phase == 0) ? ((c0 > 0.5) ? 1.0 : 0.0) : (((rW[k] >> sh1[k]) & 1ull) ? 1.0 : 0.0);
-          f1[s1 * P1 + q] = swept(c0, face_flux(slo, cl, c0, fa, pz + o1[k]),
-                                  face_flux(shi, c0, cu, fa, pzu + o1u[k]), slo, shi, cc);
+          const double flo = dl[k] ? fl[k] : pure_flux(slo, cl, c0);
+          const double fhi = dh[k] ? fh[k] : pure_flux(shi, c0, cu);
+          f1[s1 * P1 + q] = swept(c0, flo, fhi, slo, shi, cc);
           ca[s1 * P1 + q] = (cc != 0.0);
         }
       }
@@ -541,6 +575,27 @@ __device__ __forceinline__ void pair_body(const PairArgs &a, int logical) {
       const double *src = f1 + s1 * P1;
       const double *srcl = (B == 2) ? f1 + ((j2 - 1 - jb) % D1) * P1 : src;
       const double *srcu = (B == 2) ? f1 + ((j2 + 1 - jb) % D1) * P1 : src;
+      bool dl[NQ2], dh[NQ2];
+      double fl[NQ2], fh[NQ2];
+#pragma unroll
+      for (int k = 0; k < NQ2; ++k) {
+        const int q = tid + k * kPairThreads;
+        dl[k] = dh[k] = false;
+        if (q < P2) {
+          const int ry = q / W2, rx = q - ry * W2;
+          const int i1 = (ry + (B == 1)) * W1 + rx + (B == 0);
+          const double c0 = src[i1], cl = srcl[i1 - oB], cu = srcu[i1 + oB];
+          dl[k] = mixed_donor(rB[k][0], cl, c0);
+          dh[k] = mixed_donor(rB[k][1], c0, cu);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NQ2; ++k) {
+        fl[k] = 0.0;
+        fh[k] = 0.0;
+        if (dl[k]) fl[k] = fb[pz + o2[k]];
+        if (dh[k]) fh[k] = fb[pzu + o2u[k]];
+      }
 #pragma unroll
       for (int k = 0; k < NQ2; ++k) {
         const int q = tid + k * kPairThreads;
@@ -551,8 +606,9 @@ __device__ __forceinline__ void pair_body(const PairArgs &a, int logical) {
           const double slo = rB[k][0], shi = rB[k][1];
           const bool ccb = (phase == 2) ? (c0 > 0.5) : (ca[s1 * P1 + i1] != 0);
           const double cc = ccb ? 1.0 : 0.0;
-          f2[s2 * P2 + q] = swept(c0, face_flux(slo, cl, c0, fb, pz + o2[k]),
-                                  face_flux(shi, c0, cu, fb, pzu + o2u[k]), slo, shi, cc);
+          const double flo = dl[k] ? fl[k] : pure_flux(slo, cl, c0);
+          const double fhi = dh[k] ? fh[k] : pure_flux(shi, c0, cu);
+          f2[s2 * P2 + q] = swept(c0, flo, fhi, slo, shi, cc);
           cb[s2 * P2 + q] = ccb;
         }
       }
