@@ -77,44 +77,51 @@ __device__ __forceinline__ void unite(int32_t *P, int32_t a, int32_t b) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_label_init(const double *__restrict__ c, double c_eps,
-                                                       int32_t *__restrict__ P, int nx, int ny, int nz, int words) {
-  // one wavefront per 64-cell row segment: x = 64*seg + lane
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
-  const int64_t nrows = (int64_t)ny * nz;
-  const int64_t row = wave / words;
-  const int seg = (int)(wave % words);
-  if (row >= nrows) return;  // wave-uniform
-  const int x = seg * 64 + lane;
-  const bool live = x < nx;
-  const int64_t p = row * nx + x;
-  const bool occ = live && (c[p] > c_eps);
-  const uint64_t m = __ballot(occ);
-  if (!live) return;
-  if (!occ) {
-    P[p] = -1;
-    return;
-  }
-  // start of the run of set bits that contains `lane`
-  const uint64_t below = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1);
-  const uint64_t zeros = ~m & below;  // empty cells at or below this lane
-  const int start = zeros ? (64 - __clzll(zeros)) : 0;  // one past the highest empty lane below
-  P[p] = (int32_t)(row * nx + seg * 64 + start);
-}
+// Each wavefront walks kSegs consecutive 64-cell row segments (linear order
+// of the cells is the order of (segment, lane)), so a workgroup covers
+// 4 * kSegs segments.
+constexpr int kSegs = 8;
 
-// Row segment of wavefront `wave`: row = z * ny + y, x = 64 * seg + lane.
+// Row segment `sgi` (all segments of the field in linear order):
+// row = z * ny + y, x = 64 * seg + lane.
 struct Segment {
   int64_t row;
   int seg, y, z;
 };
-__device__ __forceinline__ Segment segment_of(int64_t wave, int words, int ny) {
+__device__ __forceinline__ Segment segment_of(int64_t sgi, int words, int ny) {
   Segment s;
-  s.row = wave / words;  // wavefront-uniform: scalar arithmetic
-  s.seg = (int)(wave - s.row * words);
+  s.row = sgi / words;  // wavefront-uniform: scalar arithmetic
+  s.seg = (int)(sgi - s.row * words);
   s.y = (int)(s.row % ny);
   s.z = (int)(s.row / ny);
   return s;
+}
+__device__ __forceinline__ int64_t first_segment() {
+  return (((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6) * kSegs;
+}
+
+__global__ __launch_bounds__(kBlock) void k_label_init(const double *__restrict__ c, double c_eps,
+                                                       int32_t *__restrict__ P, int nx, int ny, int nz, int words) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nseg = (int64_t)ny * nz * words, s0 = first_segment();
+  for (int64_t sgi = s0; sgi < s0 + kSegs && sgi < nseg; ++sgi) {  // wave-uniform
+    const Segment sg = segment_of(sgi, words, ny);
+    const int x = sg.seg * 64 + lane;
+    const bool live = x < nx;
+    const int64_t p = sg.row * nx + x;
+    const bool occ = live && (c[p] > c_eps);
+    const uint64_t m = __ballot(occ);
+    if (!live) continue;
+    if (!occ) {
+      P[p] = -1;
+      continue;
+    }
+    // start of the run of set bits that contains `lane`
+    const uint64_t below = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1);
+    const uint64_t zeros = ~m & below;  // empty cells at or below this lane
+    const int start = zeros ? (64 - __clzll(zeros)) : 0;  // one past the highest empty lane below
+    P[p] = (int32_t)(sg.row * nx + sg.seg * 64 + start);
+  }
 }
 
 // Lane of the first cell of the run of set bits of m that contains `lane`.
@@ -130,67 +137,69 @@ __device__ __forceinline__ int run_start_lane(uint64_t m, int lane) {
 // occupied cell keeps pointing at its own run's start.
 __global__ __launch_bounds__(kBlock) void k_label_merge(int32_t *P, int nx, int ny, int nz, int words) {
   const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
-  if (wave >= (int64_t)ny * nz * words) return;  // wave-uniform
-  const Segment sg = segment_of(wave, words, ny);
-  const int x = sg.seg * 64 + lane;
-  const bool live = x < nx;
-  const int64_t p = sg.row * nx + x;
-  const bool occ = live && P[p] >= 0;
-  const uint64_t mo = __ballot(occ);
-  if (mo == 0) return;  // wave-uniform
-  const int64_t seg0 = sg.row * nx + sg.seg * 64;
-  // -x: the segment's first cell (a run start) and its left neighbour (the
-  // previous segment's last cell, or x = nx-1 through the periodic
-  // boundary), represented by its parent, which is a run start
-  if (lane == 0 && occ) {
-    const int64_t q = sg.row * nx + (x == 0 ? nx - 1 : x - 1);
-    if (q != p) {
-      const int32_t pq = P[q];
-      if (pq >= 0) unite(P, (int32_t)p, pq);
+  const int64_t nseg = (int64_t)ny * nz * words, s0 = first_segment();
+  for (int64_t sgi = s0; sgi < s0 + kSegs && sgi < nseg; ++sgi) {  // wave-uniform
+    const Segment sg = segment_of(sgi, words, ny);
+    const int x = sg.seg * 64 + lane;
+    const bool live = x < nx;
+    const int64_t p = sg.row * nx + x;
+    const bool occ = live && P[p] >= 0;
+    const uint64_t mo = __ballot(occ);
+    if (mo == 0) continue;  // wave-uniform
+    const int64_t seg0 = sg.row * nx + sg.seg * 64;
+    // -x: the segment's first cell (a run start) and its left neighbour (the
+    // previous segment's last cell, or x = nx-1 through the periodic
+    // boundary), represented by its parent, which is a run start
+    if (lane == 0 && occ) {
+      const int64_t q = sg.row * nx + (x == 0 ? nx - 1 : x - 1);
+      if (q != p) {
+        const int32_t pq = P[q];
+        if (pq >= 0) unite(P, (int32_t)p, pq);
+      }
     }
+    // +y and +z: the first cell of every run occupied in both rows
+    const int yp = (sg.y == ny - 1) ? 0 : sg.y + 1;
+    const int zp = (sg.z == nz - 1) ? 0 : sg.z + 1;
+    const int64_t rowy = (int64_t)sg.z * ny + yp, rowz = (int64_t)zp * ny + sg.y;
+    const int64_t qy = rowy * nx + x, qz = rowz * nx + x;
+    const bool oy = live && P[qy] >= 0;
+    const bool oz = live && P[qz] >= 0;
+    const uint64_t my = __ballot(oy), mz = __ballot(oz);
+    const uint64_t by = mo & my, bz = mo & mz;
+    const uint64_t sy = by & ~(by << 1), sz = bz & ~(bz << 1);
+    const int32_t sp = (int32_t)(seg0 + run_start_lane(mo, lane));
+    if (((sy >> lane) & 1ull) && qy != p)
+      unite(P, sp, (int32_t)(rowy * nx + sg.seg * 64 + run_start_lane(my, lane)));
+    if (((sz >> lane) & 1ull) && qz != p)
+      unite(P, sp, (int32_t)(rowz * nx + sg.seg * 64 + run_start_lane(mz, lane)));
   }
-  // +y and +z: the first cell of every run occupied in both rows
-  const int yp = (sg.y == ny - 1) ? 0 : sg.y + 1;
-  const int zp = (sg.z == nz - 1) ? 0 : sg.z + 1;
-  const int64_t rowy = (int64_t)sg.z * ny + yp, rowz = (int64_t)zp * ny + sg.y;
-  const int64_t qy = rowy * nx + x, qz = rowz * nx + x;
-  const bool oy = live && P[qy] >= 0;
-  const bool oz = live && P[qz] >= 0;
-  const uint64_t my = __ballot(oy), mz = __ballot(oz);
-  const uint64_t by = mo & my, bz = mo & mz;
-  const uint64_t sy = by & ~(by << 1), sz = bz & ~(bz << 1);
-  const int32_t sp = (int32_t)(seg0 + run_start_lane(mo, lane));
-  if (((sy >> lane) & 1ull) && qy != p)
-    unite(P, sp, (int32_t)(rowy * nx + sg.seg * 64 + run_start_lane(my, lane)));
-  if (((sz >> lane) & 1ull) && qz != p)
-    unite(P, sp, (int32_t)(rowz * nx + sg.seg * 64 + run_start_lane(mz, lane)));
 }
 
-// Run starts: parent = root; roots counted per block (the block layout of
+// Run starts: parent = root; roots counted per block (the layout of
 // k_label_rank).
 __global__ __launch_bounds__(kBlock) void k_label_flatten(int32_t *P, int nx, int ny, int nz, int words,
                                                           uint32_t *__restrict__ blockcount) {
   const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
-  bool root = false;
-  if (wave < (int64_t)ny * nz * words) {  // wave-uniform
-    const Segment sg = segment_of(wave, words, ny);
+  const int64_t nseg = (int64_t)ny * nz * words, s0 = first_segment();
+  uint32_t nroot = 0;  // wave-uniform
+  for (int64_t sgi = s0; sgi < s0 + kSegs && sgi < nseg; ++sgi) {
+    const Segment sg = segment_of(sgi, words, ny);
     const int x = sg.seg * 64 + lane;
     const bool live = x < nx;
     const int64_t p = sg.row * nx + x;
     const int32_t v = live ? P[p] : -1;
     const uint64_t mo = __ballot(v >= 0);
     const uint64_t starts = mo & ~(mo << 1);
+    bool root = false;
     if ((starts >> lane) & 1ull) {
       const int32_t r = find_root(P, (int32_t)p);
       root = (r == p);
       if (r != v) P[p] = r;
     }
+    nroot += (uint32_t)__popcll(__ballot(root));
   }
   __shared__ uint32_t wcount[kBlock / 64];
-  const uint64_t m = __ballot(root);
-  if ((threadIdx.x & 63) == 0) wcount[threadIdx.x >> 6] = (uint32_t)__popcll(m);
+  if (lane == 0) wcount[threadIdx.x >> 6] = nroot;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t s = 0;
@@ -212,47 +221,56 @@ __global__ __launch_bounds__(kBlock) void k_label_rank(const int32_t *__restrict
                                                        const int32_t *__restrict__ tileoff,
                                                        int32_t *__restrict__ rootlab, int32_t *__restrict__ rootpos) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
-  bool root = false;
-  int64_t p = 0;
-  if (wave < (int64_t)ny * nz * words) {  // wave-uniform
-    const Segment sg = segment_of(wave, words, ny);
+  const int64_t nseg = (int64_t)ny * nz * words, s0 = first_segment();
+  // roots of each wavefront, then the offset of this wavefront in the block
+  uint32_t nroot = 0;
+  for (int64_t sgi = s0; sgi < s0 + kSegs && sgi < nseg; ++sgi) {
+    const Segment sg = segment_of(sgi, words, ny);
     const int x = sg.seg * 64 + lane;
-    p = sg.row * nx + x;
-    root = (x < nx) && (P[p] == p);
+    const int64_t p = sg.row * nx + x;
+    nroot += (uint32_t)__popcll(__ballot((x < nx) && (P[p] == p)));
   }
   __shared__ uint32_t wcount[kBlock / 64];
-  const uint64_t m = __ballot(root);
-  if (lane == 0) wcount[w] = (uint32_t)__popcll(m);
+  if (lane == 0) wcount[w] = nroot;
   __syncthreads();
-  if (!root) return;
   uint32_t before = (uint32_t)(blockoff[blockIdx.x] + tileoff[blockIdx.x / compact::kTile]);
   for (int k = 0; k < w; ++k) before += wcount[k];
-  before += (uint32_t)__popcll(m & ((1ull << lane) - 1));
-  rootlab[p] = (int32_t)before + 1;
-  if (rootpos) rootpos[before] = (int32_t)p;
+  for (int64_t sgi = s0; sgi < s0 + kSegs && sgi < nseg; ++sgi) {
+    const Segment sg = segment_of(sgi, words, ny);
+    const int x = sg.seg * 64 + lane;
+    const int64_t p = sg.row * nx + x;
+    const bool root = (x < nx) && (P[p] == p);
+    const uint64_t m = __ballot(root);
+    if (root) {
+      const uint32_t r = before + (uint32_t)__popcll(m & ((1ull << lane) - 1));
+      rootlab[p] = (int32_t)r + 1;
+      if (rootpos) rootpos[r] = (int32_t)p;
+    }
+    before += (uint32_t)__popcll(m);
+  }
 }
 
 // label[p] = rank of the root of p's run (0 if empty), in place.
 __global__ __launch_bounds__(kBlock) void k_label_final(int32_t *__restrict__ P, int nx, int ny, int nz, int words,
                                                         const int32_t *__restrict__ rootlab) {
   const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
-  if (wave >= (int64_t)ny * nz * words) return;  // wave-uniform
-  const Segment sg = segment_of(wave, words, ny);
-  const int x = sg.seg * 64 + lane;
-  const bool live = x < nx;
-  const int64_t p = sg.row * nx + x;
-  const int64_t seg0 = sg.row * nx + sg.seg * 64;
-  const int32_t v = live ? P[p] : -1;
-  const uint64_t mo = __ballot(v >= 0);
-  const uint64_t starts = mo & ~(mo << 1);
-  // a start holds its root; the others point at their start (in this segment)
-  int32_t lab = 0;
-  if ((starts >> lane) & 1ull) lab = rootlab[v];
-  const int src = (v >= 0) ? (int)((((starts >> lane) & 1ull) ? p : (int64_t)v) - seg0) : lane;
-  const int32_t got = __shfl(lab, src, 64);
-  if (live) P[p] = (v >= 0) ? got : 0;
+  const int64_t nseg = (int64_t)ny * nz * words, s0 = first_segment();
+  for (int64_t sgi = s0; sgi < s0 + kSegs && sgi < nseg; ++sgi) {  // wave-uniform
+    const Segment sg = segment_of(sgi, words, ny);
+    const int x = sg.seg * 64 + lane;
+    const bool live = x < nx;
+    const int64_t p = sg.row * nx + x;
+    const int64_t seg0 = sg.row * nx + sg.seg * 64;
+    const int32_t v = live ? P[p] : -1;
+    const uint64_t mo = __ballot(v >= 0);
+    const uint64_t starts = mo & ~(mo << 1);
+    // a start holds its root; the others point at their start (in this segment)
+    int32_t lab = 0;
+    if ((starts >> lane) & 1ull) lab = rootlab[v];
+    const int src = (v >= 0) ? (int)((((starts >> lane) & 1ull) ? p : (int64_t)v) - seg0) : lane;
+    const int32_t got = __shfl(lab, src, 64);
+    if (live) P[p] = (v >= 0) ? got : 0;
+  }
 }
 
 // ------------------------------------------------------------------ moments
@@ -501,10 +519,11 @@ __global__ void k_drop_finish(int32_t K, int nx, int ny, int nz, const int32_t *
 
 }  // namespace
 
-// Workgroups of the labelling kernels: one wavefront per 64-cell row segment.
+// Workgroups of the labelling kernels: kSegs row segments per wavefront.
 static inline int64_t label_blocks(int nx, int ny, int nz) {
   const int64_t words = (nx + 63) / 64;
-  return ((int64_t)ny * nz * words * 64 + kBlock - 1) / kBlock;
+  const int64_t per = (int64_t)(kBlock / 64) * kSegs;
+  return ((int64_t)ny * nz * words + per - 1) / per;
 }
 
 // Label one tracer field into `lab`. Returns K via *k_dev (device int32).
@@ -513,7 +532,7 @@ static inline int64_t label_blocks(int nx, int ny, int nz) {
 static int label_one(vofmt_ctx *ctx, int nx, int ny, int nz, const double *c, double c_eps, int32_t *lab,
                      uint32_t *blockcount, int32_t *tileoff, int32_t *rootlab, int32_t *k_dev, hipStream_t stream) {
   const int words = (int)ceil_div(nx, 64);
-  const unsigned nb = (unsigned)label_blocks(nx, ny, nz);  // every kernel: one wavefront per row segment
+  const unsigned nb = (unsigned)label_blocks(nx, ny, nz);  // every kernel: kSegs row segments per wavefront
   const unsigned nb_init = nb;
   hipLaunchKernelGGL(k_label_init, dim3(nb_init), dim3(kBlock), 0, stream, c, c_eps, lab, nx, ny, nz, words);
   hipLaunchKernelGGL(k_label_merge, dim3(nb), dim3(kBlock), 0, stream, lab, nx, ny, nz, words);
