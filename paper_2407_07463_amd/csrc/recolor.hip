@@ -289,6 +289,82 @@ __global__ __launch_bounds__(64) void k_greedy(const int32_t *__restrict__ rowpt
   }
 }
 
+// The same greedy pass decided in rounds by one workgroup. A drop's decision
+// reads the final tracers of its earlier neighbours and the initial tracers
+// of its later ones (a later neighbour cannot be decided before it), and the
+// number of tracers in use, which changes only when a drop needs a new
+// tracer. With no new tracer, a drop can be decided as soon as all its
+// earlier neighbours are, and the result is the sequential pass's: each round
+// decides every such drop (the smallest undecided drop always is one, so the
+// rounds end), then applies the decisions. If some drop needs a new tracer,
+// res[3] = 1 and the caller runs the sequential pass instead.
+__global__ __launch_bounds__(1024) void k_greedy_rounds(const int32_t *__restrict__ rowptr,
+                                                        const int32_t *__restrict__ nbr,
+                                                        const int32_t *__restrict__ T0, int32_t D, int ntr,
+                                                        int32_t *__restrict__ new_tracer, int32_t *__restrict__ res) {
+  __shared__ int8_t T[kMaxDrops];
+  __shared__ int8_t dec[kMaxDrops];  // this round's decisions, -1 for none
+  __shared__ uint32_t done[kMaxDrops / 32];
+  __shared__ int s_changed, s_moved, s_new;
+  const int tid = threadIdx.x;
+  for (int32_t g = tid; g < D; g += 1024) {
+    T[g] = (int8_t)T0[g];
+    dec[g] = -1;
+  }
+  for (int32_t i = tid; i < kMaxDrops / 32; i += 1024) done[i] = 0u;
+  if (tid == 0) {
+    s_moved = 0;
+    s_new = 0;
+  }
+  const uint64_t inuse = (ntr < 64) ? ((1ull << ntr) - 1) : ~0ull;
+  while (true) {
+    __syncthreads();
+    if (tid == 0) s_changed = 0;
+    __syncthreads();
+    for (int32_t g = tid; g < D; g += 1024) {
+      if ((done[g >> 5] >> (g & 31)) & 1u) continue;
+      const int tg = T[g];
+      bool ready = true, conflict = false;
+      uint64_t used = 0;
+      for (int32_t e = rowptr[g]; e < rowptr[g + 1]; ++e) {
+        const int32_t h = nbr[e];
+        if (h < g && !((done[h >> 5] >> (h & 31)) & 1u)) {
+          ready = false;
+          break;
+        }
+        const int th = T[h];
+        conflict = conflict || (h < g && th == tg);
+        used |= 1ull << th;
+      }
+      if (!ready) continue;
+      int n = tg;
+      if (conflict) {
+        const uint64_t avail = ~used & ~(1ull << tg) & inuse;
+        if (avail) n = __ffsll((unsigned long long)avail) - 1;
+        else s_new = 1;
+        atomicAdd(&s_moved, 1);
+      }
+      dec[g] = (int8_t)n;
+      s_changed = 1;
+    }
+    __syncthreads();
+    if (!s_changed || s_new) break;  // uniform: read after the barrier
+    for (int32_t g = tid; g < D; g += 1024)
+      if (dec[g] >= 0) {
+        T[g] = dec[g];
+        dec[g] = -1;
+        atomicOr(&done[g >> 5], 1u << (g & 31));
+      }
+  }
+  for (int32_t g = tid; g < D; g += 1024) new_tracer[g] = T[g];
+  if (tid == 0) {
+    res[0] = ntr;
+    res[1] = s_moved;
+    res[2] = 0;
+    res[3] = s_new;
+  }
+}
+
 __global__ void k_initial_tracers(int32_t *T0, int32_t D, int ntr, TracerOffsets to) {
   const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= D) return;
@@ -299,10 +375,26 @@ __global__ void k_initial_tracers(int32_t *T0, int32_t D, int ntr, TracerOffsets
 
 // Move the cells of every moved drop: first clear every moved-out value of
 // the cell, then add each to its new field.
+// Moves the cells of every drop whose tracer changes: the old field is
+// cleared first, then the values are added to the new fields. A cell owned by
+// one drop (own >= 0, tracer T0[own]) needs only the owner array; cells
+// shared by several drops read every tracer's labels.
 __global__ __launch_bounds__(kBlock) void k_move(double *__restrict__ c, const int32_t *__restrict__ lab, int64_t n3,
-                                                 int ntr, TracerOffsets to, const int32_t *__restrict__ newt) {
+                                                 int ntr, TracerOffsets to, const int32_t *__restrict__ own,
+                                                 const int32_t *__restrict__ T0, const int32_t *__restrict__ newt) {
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= n3) return;
+  const int32_t o = own[p];
+  if (o == -1) return;
+  if (o >= 0) {
+    const int t = T0[o], n = newt[o];
+    if (n == t) return;
+    double *src = c + (int64_t)t * n3 + p, *dst = c + (int64_t)n * n3 + p;
+    const double v = *src;
+    *src = 0.0;
+    *dst = *dst + v;
+    return;
+  }
   int cnt = 0;
   for (int t = 0; t < ntr; ++t) {
     const int32_t l = lab[(int64_t)t * n3 + p];
@@ -423,11 +515,18 @@ extern "C" int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int
   hipLaunchKernelGGL(k_csr_fill, dim3(ceil_div(D, kBlock)), dim3(kBlock), 0, stream, adj, (int32_t)D, words, rowptr,
                      nbr);
   hipLaunchKernelGGL(k_initial_tracers, dim3(ceil_div(D, 256)), dim3(256), 0, stream, T0, (int32_t)D, ntr, to);
-  hipLaunchKernelGGL(k_greedy, dim3(1), dim3(64), 0, stream, rowptr, nbr, T0, (int32_t)D, ntr, max_tracers,
-                     new_tracer, res);
+  hipLaunchKernelGGL(k_greedy_rounds, dim3(1), dim3(1024), 0, stream, rowptr, nbr, T0, (int32_t)D, ntr, new_tracer,
+                     res);
   VOFMT_HIP(ctx, hipGetLastError());
-  VOFMT_HIP(ctx, hipMemcpyAsync(hres, res, sizeof(int32_t) * 3, hipMemcpyDeviceToHost, stream));
+  VOFMT_HIP(ctx, hipMemcpyAsync(hres, res, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, stream));
   VOFMT_HIP(ctx, hipStreamSynchronize(stream));
+  if (hres[3]) {  // a drop needs a new tracer: the sequential pass
+    hipLaunchKernelGGL(k_greedy, dim3(1), dim3(64), 0, stream, rowptr, nbr, T0, (int32_t)D, ntr, max_tracers,
+                       new_tracer, res);
+    VOFMT_HIP(ctx, hipGetLastError());
+    VOFMT_HIP(ctx, hipMemcpyAsync(hres, res, sizeof(int32_t) * 3, hipMemcpyDeviceToHost, stream));
+    VOFMT_HIP(ctx, hipStreamSynchronize(stream));
+  }
   const int Nnew = hres[0], moved = hres[1], overflow = hres[2];
   if (overflow)
     return set_err(ctx, VOFMT_E_CAPACITY, "vofmt_recolor_tracers: more than max_tracers=%d tracers needed",
@@ -436,7 +535,7 @@ extern "C" int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int
     if (Nnew > ntr)
       hipLaunchKernelGGL(k_fill_f64, dim3(1024), dim3(256), 0, stream, c + (int64_t)ntr * n3,
                          (int64_t)(Nnew - ntr) * n3, 0.0);
-    hipLaunchKernelGGL(k_move, dim3(nbc), dim3(kBlock), 0, stream, c, labels, n3, ntr, to, new_tracer);
+    hipLaunchKernelGGL(k_move, dim3(nbc), dim3(kBlock), 0, stream, c, labels, n3, ntr, to, own, T0, new_tracer);
     VOFMT_HIP(ctx, hipGetLastError());
   }
   *ntracers_host = Nnew;

@@ -185,14 +185,17 @@ def test_recolour_capacity_error(ctx):
     assert torch.equal(tc, before)
 
 
-@pytest.mark.parametrize("seed", range(4))
-def test_recolour_random(ctx, seed):
+@pytest.mark.parametrize("seed,ntr", [(0, 3), (1, 3), (2, 3), (3, 3), (4, 8), (5, 8)])
+def test_recolour_random(ctx, seed, ntr):
+    """Dense random drops. Seeds 2 and 3 need new tracers (the sequential
+    greedy pass runs); the others resolve every conflict within the existing
+    tracers (the pass decided in rounds)."""
     rng = np.random.default_rng(300 + seed)
     shape = (21, 26, 33)
-    ntr, maxt = 3, 12
+    maxt = 12
     c = np.zeros((maxt,) + shape)
-    c[:ntr] = random_blobs(rng, shape, ntr, 40, 1.0, 2.6)
-    note(f"recolour random seed={seed}")
+    c[:ntr] = random_blobs(rng, shape, ntr, 40 if ntr == 3 else 60, 1.0, 2.6)
+    note(f"recolour random seed={seed} ntr={ntr}")
     g, gntr, gnewt, gmoved, glab, gnd = _gpu_recolour(ctx, c, ntr, 1.5)
     labels = np.stack([oracle.label(c[t])[0] for t in range(ntr)])
     nd = labels.reshape(ntr, -1).max(1)
