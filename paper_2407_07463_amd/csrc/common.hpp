@@ -67,7 +67,7 @@ enum ScratchSlot {
   SLOT_TUNE = 19,      // autotuner: copies of the fields it advects
   SLOT_CURV_LIST = 20,   // curvature: list of mixed cells
   SLOT_CURV_COUNT = 21,  // its length and that of the fallback list
-  SLOT_CURV_HF = 22,     // cells handed to the height-function fallback
+  SLOT_CURV_HF = 22,     // cells handed to the height-function fallback; recolouring: list predicate bits
   SLOT_RECOLOR_LIST = 23,  // recolouring: drop-boundary and shared cells
   SLOT_FMIX2 = 24,         // paired sweeps: fluxes of the second sweep's mixed donors
   kNumSlots = 25,

@@ -49,6 +49,23 @@ __global__ __launch_bounds__(kBlock) void k_owner(const int32_t *__restrict__ la
   own[p] = o;
 }
 
+// The same for 4 consecutive cells per thread with 16-byte label loads
+// (labels 16-byte aligned and n3 a multiple of 4).
+__global__ __launch_bounds__(kBlock) void k_owner4(const int4 *__restrict__ lab, int64_t n4, int ntr,
+                                                   TracerOffsets to, int4 *__restrict__ own) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n4) return;
+  int32_t o[4] = {-1, -1, -1, -1};
+  for (int t = 0; t < ntr; ++t) {
+    const int4 l4 = lab[(int64_t)t * n4 + i];
+    const int32_t l[4] = {l4.x, l4.y, l4.z, l4.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (l[k] > 0 && to.off[t] + l[k] <= to.off[t + 1]) o[k] = (o[k] == -1) ? to.off[t] + l[k] - 1 : -2;
+  }
+  own[i] = make_int4(o[0], o[1], o[2], o[3]);
+}
+
 // v in (-n, 2n): one conditional add or subtract instead of a modulo
 __device__ __forceinline__ int wrap_near(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
@@ -71,9 +88,11 @@ __device__ __forceinline__ void for_drops_at(const int32_t *__restrict__ lab, in
 __device__ __forceinline__ void edges_of(const int32_t *__restrict__ own, const int32_t *__restrict__ lab, int nx,
                                          int ny, int nz, int ntr, const TracerOffsets &to,
                                          const int4 *__restrict__ offs, int noffs, int small_offsets,
-                                         uint32_t *__restrict__ adj, int64_t words, int64_t n3, int64_t p) {
+                                         uint32_t *__restrict__ adj, int64_t words, int64_t n3, const FastDiv &fnx,
+                                         const FastDiv &fny, int64_t p) {
   const int32_t a = own[p];
-  const int x = (int)(p % nx), y = (int)((p / nx) % ny), z = (int)(p / ((int64_t)nx * ny));
+  const uint32_t r = fast_div((uint32_t)p, fnx), zz = fast_div(r, fny);  // cells < 2^31
+  const int x = (int)((uint32_t)p - r * (uint32_t)nx), y = (int)(r - zz * (uint32_t)ny), z = (int)zz;
   if (a == -2) {
     // drops sharing this very cell are neighbours (offset 0 across tracers)
     for_drops_at(lab, n3, ntr, to, p, [&](int32_t u) {
@@ -118,11 +137,13 @@ __device__ __forceinline__ void edges_of(const int32_t *__restrict__ own, const 
 struct PairSources {
   const int32_t *own;
   int nx, ny, nz;
+  FastDiv fnx, fny;  // cells < 2^31: multiply-shift division
   __device__ bool operator()(int64_t p) const {
     const int32_t a = own[p];
     if (a == -1) return false;
     if (a == -2) return true;
-    const int x = (int)(p % nx), y = (int)((p / nx) % ny), z = (int)(p / ((int64_t)nx * ny));
+    const uint32_t r = fast_div((uint32_t)p, fnx), zz = fast_div(r, fny);
+    const int x = (int)((uint32_t)p - r * (uint32_t)nx), y = (int)(r - zz * (uint32_t)ny), z = (int)zz;
     const int64_t row = (int64_t)y * nx, plane = (int64_t)z * ny * nx;
     return !(own[plane + row + wrap_dec(x, nx)] == a && own[plane + row + wrap_inc(x, nx)] == a &&
              own[plane + (int64_t)wrap_dec(y, ny) * nx + x] == a &&
@@ -137,12 +158,13 @@ __global__ __launch_bounds__(kBlock) void k_edges(const int32_t *__restrict__ ow
                                                   int nx, int ny, int nz, int ntr, TracerOffsets to,
                                                   const int4 *__restrict__ offs, int noffs, int small_offsets,
                                                   const int32_t *__restrict__ list, const int32_t *__restrict__ count,
-                                                  uint32_t *__restrict__ adj, int64_t words) {
+                                                  uint32_t *__restrict__ adj, int64_t words, FastDiv fnx,
+                                                  FastDiv fny) {
   const int64_t n3 = (int64_t)nx * ny * nz;
   const int nlist = *count;
   for (int qi = blockIdx.x * kBlock + threadIdx.x; qi < nlist; qi += gridDim.x * kBlock) {
     const int64_t p = list[qi];
-    edges_of(own, lab, nx, ny, nz, ntr, to, offs, noffs, small_offsets, adj, words, n3, p);
+    edges_of(own, lab, nx, ny, nz, ntr, to, offs, noffs, small_offsets, adj, words, n3, fnx, fny, p);
   }
 }
 
@@ -450,8 +472,14 @@ extern "C" int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int
   if (D > kMaxDrops) return set_err(ctx, VOFMT_E_ARG, "vofmt_recolor_tracers: more than %d drops", kMaxDrops);
   if (!new_tracer) return set_err(ctx, VOFMT_E_ARG, "vofmt_recolor_tracers: null new_tracer");
   const int64_t n3 = (int64_t)nx * ny * nz;
+  if (n3 >= INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "vofmt_recolor_tracers: more than 2^31-1 cells per field");
   VOFMT_HIP(ctx, hipSetDevice(ctx->device));
-  // offsets of the ball |o|^2 < (1+gap)^2, o != 0
+  // offsets of the half ball |o|^2 < (1+gap)^2, o > 0 in (z, y, x) order: a
+  // pair of drops is found from one side only, and k_symmetrise completes
+  // the adjacency. Every pair is still found: the two cells of the pair at
+  // the smallest offset are both listed (a cell whose six neighbours all
+  // held its drop would have a neighbour closer to the other drop), so the
+  // listed cell from which that offset points forward finds it.
   const double lim = (1.0 + gap_cells) * (1.0 + gap_cells);
   const int R = (int)floor(1.0 + gap_cells);
   int4 *hoffs = nullptr;
@@ -464,6 +492,7 @@ extern "C" int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int
         for (int ox = -R; ox <= R; ++ox) {
           const double o2 = (double)(ox * ox + oy * oy + oz * oz);
           if (o2 == 0.0 || !(o2 < lim)) continue;
+          if (!(oz > 0 || (oz == 0 && (oy > 0 || (oy == 0 && ox > 0))))) continue;
           hoffs[noffs++] = make_int4(ox, oy, oz, 0);
         }
   }
@@ -486,7 +515,11 @@ extern "C" int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int
   int32_t *deg = small, *rowptr = small + D, *T0 = small + 2 * D + 1, *res = small + 3 * D + 2;
   int32_t *nbr = nullptr;
   const unsigned nbc = ceil_div(n3, kBlock);
-  hipLaunchKernelGGL(k_owner, dim3(nbc), dim3(kBlock), 0, stream, labels, n3, ntr, to, own);
+  if (n3 % 4 == 0 && ((uintptr_t)labels & 15) == 0)
+    hipLaunchKernelGGL(k_owner4, dim3(ceil_div(n3 / 4, kBlock)), dim3(kBlock), 0, stream, (const int4 *)labels,
+                       n3 / 4, ntr, to, (int4 *)own);
+  else
+    hipLaunchKernelGGL(k_owner, dim3(nbc), dim3(kBlock), 0, stream, labels, n3, ntr, to, own);
   hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, stream, adj, D * words, 0u);
   {
     // the cells that can see a pair, in order, then the pairs they see
@@ -494,13 +527,17 @@ extern "C" int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int
     int32_t *srcs = (int32_t *)scratch(ctx, SLOT_RECOLOR_LIST, sizeof(int32_t) * (size_t)n3);
     int32_t *bc = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * (size_t)nbc);
     int32_t *tot = (int32_t *)scratch(ctx, SLOT_CURV_COUNT, sizeof(int32_t) * (size_t)(lt + 2));
-    if (!srcs || !bc || !tot) return VOFMT_E_NOMEM;
-    compact::launch_ordered_list_if(n3, PairSources{own, nx, ny, nz}, bc, tot, srcs, stream);
+    uint64_t *pbits = (uint64_t *)scratch(ctx, SLOT_CURV_HF, sizeof(uint64_t) * (size_t)((n3 + 63) / 64));
+    if (!srcs || !bc || !tot || !pbits) return VOFMT_E_NOMEM;
+    compact::launch_ordered_list_if(
+        n3, PairSources{own, nx, ny, nz, make_fastdiv((uint32_t)nx), make_fastdiv((uint32_t)ny)}, bc, tot, srcs,
+        pbits, stream);
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
       cus = 256;
     hipLaunchKernelGGL(k_edges, dim3(8 * cus), dim3(kBlock), 0, stream, own, labels, nx, ny, nz, ntr, to, doffs,
-                       noffs, small_offsets, srcs, tot + lt, adj, words);
+                       noffs, small_offsets, srcs, tot + lt, adj, words, make_fastdiv((uint32_t)nx),
+                       make_fastdiv((uint32_t)ny));
   }
   hipLaunchKernelGGL(k_symmetrise, dim3(ceil_div(D * D, kBlock)), dim3(kBlock), 0, stream, adj, (int32_t)D, words);
   hipLaunchKernelGGL(k_degree, dim3(ceil_div(D, kBlock)), dim3(kBlock), 0, stream, adj, (int32_t)D, words, deg);
