@@ -15,6 +15,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr uint64_t kFixedOne = 720720ull;  // lcm(1..16)
+constexpr int32_t kMaxSlices = 64;          // candidate slices of the nearest search
 
 struct Box {
   double L[3];
@@ -26,11 +27,16 @@ __device__ __forceinline__ double min_image(double d, double L) {
   return d;
 }
 
-__global__ __launch_bounds__(kBlock) void k_nearest(const double *__restrict__ xyz, int32_t n, Box box,
-                                                    int32_t *__restrict__ nn_index, int32_t *__restrict__ nn_ties,
-                                                    double *__restrict__ best_d2) {
+// Candidate slices: the j range is cut into `ns` slices of `len` indices
+// (a multiple of kBlock); workgroup (ib, s) scans slice s for the kBlock
+// drops of block ib and keeps, per drop, the slice's smallest d2, the first j
+// attaining it and how many j attain it.
+__global__ __launch_bounds__(kBlock) void k_nearest_slice(const double *__restrict__ xyz, int32_t n, Box box,
+                                                          int32_t len, double *__restrict__ sbest,
+                                                          int32_t *__restrict__ sbj, int32_t *__restrict__ sties) {
   __shared__ double sx[kBlock], sy[kBlock], sz[kBlock];
   const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  const int32_t s = blockIdx.y;
   double xi = 0, yi = 0, zi = 0;
   if (i < n) {
     xi = xyz[3 * (int64_t)i];
@@ -39,16 +45,18 @@ __global__ __launch_bounds__(kBlock) void k_nearest(const double *__restrict__ x
   }
   double best = INFINITY;
   int32_t bj = -1, ties = 0;
-  for (int32_t j0 = 0; j0 < n; j0 += kBlock) {
+  const int32_t jbeg = s * len;
+  const int32_t jend = (n - jbeg < len) ? n : jbeg + len;
+  for (int32_t j0 = jbeg; j0 < jend; j0 += kBlock) {
     const int32_t jj = j0 + threadIdx.x;
     __syncthreads();
-    if (jj < n) {
+    if (jj < jend) {
       sx[threadIdx.x] = xyz[3 * (int64_t)jj];
       sy[threadIdx.x] = xyz[3 * (int64_t)jj + 1];
       sz[threadIdx.x] = xyz[3 * (int64_t)jj + 2];
     }
     __syncthreads();
-    const int32_t m = (n - j0 < kBlock) ? n - j0 : kBlock;
+    const int32_t m = (jend - j0 < kBlock) ? jend - j0 : kBlock;
     if (i < n) {
       for (int k = 0; k < m; ++k) {
         const int32_t j = j0 + k;
@@ -68,16 +76,47 @@ __global__ __launch_bounds__(kBlock) void k_nearest(const double *__restrict__ x
     }
   }
   if (i < n) {
-    nn_index[i] = bj;
-    nn_ties[i] = ties;
-    best_d2[i] = best;
+    const int64_t o = (int64_t)s * n + i;
+    sbest[o] = best;
+    sbj[o] = bj;
+    sties[o] = ties;
   }
+}
+
+// Slices combined in increasing order: the minimum over slices, the first j
+// of the first slice that attains it, and the tie counts of every slice that
+// attains it, which is exactly what one scan over all j in order yields.
+__global__ __launch_bounds__(kBlock) void k_nearest_combine(int32_t n, int32_t ns, const double *__restrict__ sbest,
+                                                            const int32_t *__restrict__ sbj,
+                                                            const int32_t *__restrict__ sties,
+                                                            int32_t *__restrict__ nn_index,
+                                                            int32_t *__restrict__ nn_ties,
+                                                            double *__restrict__ best_d2) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double best = INFINITY;
+  int32_t bj = -1, ties = 0;
+  for (int32_t s = 0; s < ns; ++s) {
+    const int64_t o = (int64_t)s * n + i;
+    const double d2 = sbest[o];
+    if (d2 < best) {
+      best = d2;
+      bj = sbj[o];
+      ties = sties[o];
+    } else if (d2 == best && sties[o] > 0) {
+      ties += sties[o];
+    }
+  }
+  nn_index[i] = bj;
+  nn_ties[i] = ties;
+  best_d2[i] = best;
 }
 
 // Bin the nearest pairs of drop i and write its moment contributions
 // part[12*i ..]: sum_j h r (3) and sum_j h r r^T (9), j ascending.
 __global__ __launch_bounds__(kBlock) void k_pairs(const double *__restrict__ xyz, int32_t n, Box box, int vaxis,
                                                   int nr, int nth, const double *__restrict__ edges,
+                                                  const int32_t *__restrict__ nn_index,
                                                   const int32_t *__restrict__ nn_ties,
                                                   const double *__restrict__ best_d2, uint64_t *__restrict__ hist,
                                                   double *__restrict__ part) {
@@ -91,7 +130,12 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const double *__restrict__ xyz
   const double h = 1.0 / (double)ties;
   const uint64_t wfix = kFixedOne / (uint64_t)ties;
   double sm[3] = {0, 0, 0}, sr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int32_t j = 0; j < n; ++j) {
+  // No j before the first nearest index attains the minimum, and the scan
+  // ends once all `ties` nearest drops are found: the same j, in the same
+  // order, as a scan over every j.
+  int found = 0;
+  const int32_t jfirst = nn_index[i] < 0 ? 0 : nn_index[i];
+  for (int32_t j = jfirst; j < n && found < ties; ++j) {
     if (j == i) continue;
     double r[3];
     r[0] = min_image(xyz[3 * (int64_t)j] - xi, box.L[0]);
@@ -99,6 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const double *__restrict__ xyz
     r[2] = min_image(xyz[3 * (int64_t)j + 2] - zi, box.L[2]);
     const double d2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
     if (d2 != best) continue;
+    ++found;
     int k = -1;
     for (int e = 0; e <= nr; ++e)
       if (r2e[e] <= d2) k = e;
@@ -169,8 +214,17 @@ extern "C" int vofmt_nearest_pair_stats(vofmt_ctx *ctx, int32_t n, const double 
   double *dedge = (double *)scratch(ctx, SLOT_MISC, sizeof(double) * nedge);
   double *best = (double *)scratch(ctx, SLOT_MISC2, sizeof(double) * (size_t)n);
   double *part = (double *)scratch(ctx, SLOT_MISC3, sizeof(double) * 12 * (size_t)n);
+  // at most kMaxSlices slices, each a whole number of kBlock indices
+  const int32_t nblk = (int32_t)ceil_div(n, kBlock);
+  const int32_t per = (int32_t)ceil_div(nblk, kMaxSlices);
+  const int32_t len = per * kBlock;
+  const int32_t ns = (int32_t)ceil_div(n, len);
+  char *sl = (char *)scratch(ctx, SLOT_LABEL_A, (sizeof(double) + 2 * sizeof(int32_t)) * (size_t)ns * n);
   double *hstage = (double *)host_scratch(ctx, sizeof(double) * nedge);
-  if (!dedge || !best || !part || !hstage) return VOFMT_E_NOMEM;
+  if (!dedge || !best || !part || !sl || !hstage) return VOFMT_E_NOMEM;
+  double *sbest = (double *)sl;
+  int32_t *sbj = (int32_t *)(sbest + (size_t)ns * n);
+  int32_t *sties = sbj + (size_t)ns * n;
   for (int e = 0; e <= nr; ++e) hstage[e] = r2_edges[e];
   for (int e = 0; e <= ntheta; ++e) hstage[nr + 1 + e] = cos_edges[e];
   VOFMT_HIP(ctx, hipMemcpyAsync(dedge, hstage, sizeof(double) * nedge, hipMemcpyHostToDevice, stream));
@@ -178,10 +232,11 @@ extern "C" int vofmt_nearest_pair_stats(vofmt_ctx *ctx, int32_t n, const double 
   for (int a = 0; a < 3; ++a) b.L[a] = box[a];
   const int64_t nh = (int64_t)nr * ntheta + 1;
   hipLaunchKernelGGL(k_zero_u64, dim3(ceil_div(nh, 256)), dim3(256), 0, stream, hist_fixed, nh);
-  hipLaunchKernelGGL(k_nearest, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, stream, xyz, n, b, nn_index, nn_ties,
-                     best);
+  hipLaunchKernelGGL(k_nearest_slice, dim3(nblk, ns), dim3(kBlock), 0, stream, xyz, n, b, len, sbest, sbj, sties);
+  hipLaunchKernelGGL(k_nearest_combine, dim3(nblk), dim3(kBlock), 0, stream, n, ns, sbest, sbj, sties, nn_index,
+                     nn_ties, best);
   hipLaunchKernelGGL(k_pairs, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, stream, xyz, n, b, vertical_axis, nr,
-                     ntheta, dedge, nn_ties, best, hist_fixed, part);
+                     ntheta, dedge, nn_index, nn_ties, best, hist_fixed, part);
   hipLaunchKernelGGL(k_moments, dim3(1), dim3(kBlock), 0, stream, part, n, M, R);
   VOFMT_HIP(ctx, hipGetLastError());
   // the staging buffer must stay valid until the copy has run

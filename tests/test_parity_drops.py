@@ -245,7 +245,9 @@ def _check_stats(g, o, xyz, box):
     assert np.abs(g["R"] - o["R"]).max() <= 1e-12 * scale
 
 
-@pytest.mark.parametrize("n", [2, 3, 257, 5508])
+# 5508 and 16684 drops cut the candidate range into 22 slices of 256 and
+# 33 slices of 512 indices.
+@pytest.mark.parametrize("n", [2, 3, 257, 5508, 16684])
 def test_stats_random(ctx, n):
     rng = synth.Splitmix64(40 + n)
     box = np.array([512.0, 512.0, 512.0])
@@ -258,15 +260,18 @@ def test_stats_random(ctx, n):
     _check_stats(g, o, xyz, box)
 
 
-def test_stats_lattice_ties(ctx):
+# 12^3 drops: the six nearest neighbours of a drop lie in up to three
+# candidate slices.
+@pytest.mark.parametrize("m", [6, 12])
+def test_stats_lattice_ties(ctx, m):
     a = 8.0
-    gr = np.arange(6) * a
+    gr = np.arange(m) * a
     xyz = np.array([(x, y, z) for z in gr for y in gr for x in gr])
-    box = np.array([48.0, 48.0, 48.0])
+    box = np.array([m * a] * 3)
     r2e = np.linspace(0, 20, 9) ** 2
     ce = np.cos(np.linspace(0, math.pi, 7))
     for vaxis in (0, 2):
-        note(f"pair stats lattice axis={vaxis}")
+        note(f"pair stats lattice {m}^3 axis={vaxis}")
         g = _gpu_stats(ctx, xyz, box, vaxis, r2e, ce)
         o = oracle.nearest_pair_stats(xyz, box, vaxis, r2e, ce)
         _check_stats(g, o, xyz, box)
