@@ -117,12 +117,16 @@ def write_traffic(fetch_dir, write_dir, kernel_re, copy_re, copy_bytes, out, com
     copies_w = [v for k, v in wr.items() if cre.search(k)]
     if not copies_f or not copies_w:
         raise RuntimeError("copy kernel not found in the counter output")
+    if len(copies_f) > 1 or len(copies_w) > 1:
+        names = sorted(k for k in set(fe) | set(wr) if cre.search(k))
+        raise RuntimeError(f"copy pattern {copy_re!r} matches several kernels: {names}")
     kib = copy_bytes / 1024.0
     f_factor = copies_f[0][1] / kib  # counter KiB per true KiB read
     w_factor = copies_w[0][1] / kib
     lines = ["# HBM traffic per dispatch from rocprofv3 counters", "",
              f"FETCH_SIZE run: {command_fetch}", f"WRITE_SIZE run: {command_write}", "",
-             f"copy kernel reads and writes {copy_bytes} B per dispatch",
+             f"copy kernel: the dispatches whose name matches '{copy_re}'; it reads and writes "
+             f"{copy_bytes} B per dispatch",
              f"copy_fetch_factor = {f_factor:.6f}   (FETCH_SIZE KiB / true KiB read)",
              f"copy_write_factor = {w_factor:.6f}   (WRITE_SIZE KiB / true KiB written)",
              f"advect_source_sha256 = {advect_source_sha()}", ""]
