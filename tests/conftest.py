@@ -25,3 +25,12 @@ def _built_cpu_libraries():
 
         _build.build_synth()
     yield
+
+
+@pytest.fixture(scope="session")
+def drops512():
+    """The benchmark workload (512^3, 8 FP64 tracers, seeded), generated once
+    per session for the full-size parity tests."""
+    from paper_2407_07463_amd import synth
+
+    return synth.drops512(order=8, workers=16)

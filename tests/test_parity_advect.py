@@ -148,11 +148,6 @@ def test_argument_errors(ctx):
     assert e.value.code == vofmt.E_NONFINITE
 
 
-@pytest.fixture(scope="module")
-def drops512():
-    return synth.drops512(order=8, workers=16)
-
-
 def test_full_size_sampled_cells(ctx, drops512):
     """512^3 x 8 tracers, one step in the benchmark's launch configuration;
     200 sampled cells recomputed by the oracle on periodic 17^3 boxes, plus

@@ -1,15 +1,23 @@
 """GPU parity of the learned curvature (forward, training step, stencils,
 combined curvature) against the CPU oracle, through the C ABI.
 
-Bars:
+Every oracle value is computed by the oracle from the test's own inputs: the
+oracle runs the whole chain (x -> h1 -> h2 -> y, then dz2 -> dz1 -> gradient
+-> Adam) in FP64 with the kernels' BF16 rounding points, and each GPU stage is
+compared with the oracle's value of that stage.
+
+Bars, stage by stage:
 - stencils, cells and signs bit-exact (same FP64 decisions, exact FP32 casts);
-- each layer, fed the GPU's own rounded inputs, within the FP32 accumulation
-  bound K * 2^-23 * sum |a b| of the oracle's FP64 value, plus one BF16 ulp
-  where a rounded activation sits at a rounding boundary;
-- backward quantities likewise, on the GPU's own intermediates (trace);
-- Adam within FP32 rounding of the FP64 update;
-- combined curvature: exactly the height-function value or sign * network
-  output, chosen by the stated rule.
+- a stage within the FP32 accumulation bound K * 2^-23 * sum |a b| plus the
+  deviation of its GPU inputs from the oracle's, carried through the layer
+  (|W| times the input deviations; ReLU does not enlarge it); a rounded
+  stage also within one BF16 ulp where it sits at a rounding boundary, and a
+  ReLU mask may differ only where the stage's bound reaches zero;
+- Adam: the GPU update lies within the oracle's updates over the gradient's
+  bound, up to FP32 rounding;
+- combined curvature: the height-function value or sign * network output,
+  chosen by the stated rule; a cell whose oracle output lies within the
+  output bound of the threshold may take either branch.
 """
 import numpy as np
 import pytest
@@ -57,11 +65,6 @@ def _records(rec):
     return h1, h2, _bf(rec[:, 768:1024].view(np.uint16)), _bf(rec[:, 1024:1280].view(np.uint16))
 
 
-def _check_fp32(got, ref, absacc, K, what):
-    ok = np.abs(got - ref) <= K * U23 * absacc + 1e-30
-    assert ok.all(), (what, np.argwhere(~ok)[:5], got[~ok][:5], ref[~ok][:5])
-
-
 def _check_rounded(got, ref, absacc, K, what):
     """A rounded activation: FP32 accumulation bound, plus one BF16 ulp at a boundary."""
     bound = K * U23 * absacc
@@ -70,6 +73,37 @@ def _check_rounded(got, ref, absacc, K, what):
     assert ok.all(), (what, np.argwhere(~ok)[:5], got[~ok][:5], ref[~ok][:5])
     # boundary cases are rare
     assert np.mean(err > bound * 2 + 1e-30) < 0.02, what
+
+
+def _weights(P):
+    """Weights as the network uses them: BF16 W1 [32][128] and W2 [128][128]
+    (rows = inputs), FP32 W3 [128]."""
+    W1 = oracle.bf16(P[OFF["W1"]:OFF["b1"]]).astype(np.float64).reshape(32, 128)
+    W2 = oracle.bf16(P[OFF["W2"]:OFF["b2"]]).astype(np.float64).reshape(128, 128)
+    W3 = P[OFF["W3"]:OFF["b3"]].astype(np.float64)
+    return W1, W2, W3
+
+
+def _check_carried(got, ref, absacc, carried, K, what):
+    """FP32 accumulation over the GPU's inputs (scale absacc + carried) plus the
+    deviation of those inputs from the oracle's, carried through the layer."""
+    bound = K * U23 * (absacc + carried) + carried + 1e-30
+    ok = np.abs(got - ref) <= bound
+    assert ok.all(), (what, np.argwhere(~ok)[:5], got[~ok][:5], ref[~ok][:5])
+    return bound
+
+
+def _forward_chain(P, x, h1, h2, y):
+    """The GPU's h1, h2, y against the oracle's chain on the same inputs x.
+    Returns the oracle's h1, h2, y and the bound on |y - y_oracle|."""
+    _, W2, W3 = _weights(P)
+    _, h1o, ab1 = oracle.mlp_layer(P, 1, x.astype(np.float64))
+    _check_rounded(h1, h1o, ab1, 64, "h1")
+    _, h2o, ab2 = oracle.mlp_layer(P, 2, h1o)
+    _check_carried(h2, h2o, ab2, np.abs(h1 - h1o) @ np.abs(W2), 129, "h2")
+    yo, _, ab3 = oracle.mlp_layer(P, 3, h2o)
+    ybound = _check_carried(y, yo, ab3, np.abs(h2 - h2o) @ np.abs(W3), 128 + 8, "y")
+    return h1o, h2o, yo, ybound
 
 
 def _mixed_inputs(n_sphere_fields=3, seed=100):
@@ -100,16 +134,13 @@ def test_forward_layers(ctx, m, kind):
     torch.cuda.synchronize()
     if m == 0:
         return
-    y, acts = y.cpu().numpy()[:m], acts.cpu().numpy()[:m]
+    y, acts = y.cpu().numpy()[:m].astype(np.float64), acts.cpu().numpy()[:m]
     h1, h2 = _records(acts)
-    _, a1, ab1 = oracle.mlp_layer(P, 1, x.astype(np.float64))
-    _check_rounded(h1, a1, ab1, 64, "h1")
-    _, a2, ab2 = oracle.mlp_layer(P, 2, h1)
-    _check_fp32(h2, a2, ab2, 129, "h2")
-    y3, _, ab3 = oracle.mlp_layer(P, 3, h2)
-    assert np.all(np.abs(y - y3) <= (128 + 8) * U23 * ab3 + 1e-30)
-    # end to end against the oracle's own forward pass: same up to rare boundary flips
+    _, _, y3, _ = _forward_chain(P, x, h1, h2, y)
+    # the chain of single layers is the oracle's forward pass, and the GPU
+    # output differs from it only where a BF16 rounding sits at a boundary
     yo, _ = oracle.mlp_forward(P, x)
+    assert np.array_equal(y3, yo)
     assert np.median(np.abs(y - yo) / np.maximum(np.abs(yo), 1e-3)) < 1e-4
 
 
@@ -157,26 +188,66 @@ def test_train_step(ctx, m, step):
     # the training forward pass is the inference forward pass
     assert np.array_equal(tr[:, :768], acts)
     h1, h2, dz2, dz1 = _records(tr)
-    w = 1.0 / np.maximum(np.abs(t.astype(np.float64)), 0.05) ** 2
-    lo = np.mean((y - t) ** 2 * w)
-    assert abs(loss - lo) <= 2e-5 * lo + 1e-12
-    g = 2.0 * (y - t) * w / m
-    b = oracle.mlp_backward_given(P, x, g, h1, h2, dz2, dz1)
-    ok2 = np.abs(dz2 - b["dz2"]) <= BF_ULP * np.abs(b["dz2"]) + 1e-30
-    assert ok2.all()
-    _check_rounded(dz1, b["dz1"], b["dz1_abs"], 128, "dz1")
+    h1o, h2o, yo, ybound = _forward_chain(P, x, h1, h2, y)
+    _, W2, W3 = _weights(P)
+    tt = t.astype(np.float64)
+    w = 1.0 / np.maximum(np.abs(tt), 0.05) ** 2
+    dy = np.abs(y - yo)
+    # loss: FP32 sum, plus (y - t)^2 - (yo - t)^2 = dy (2 (yo - t) + dy)
+    lo = np.mean((yo - tt) ** 2 * w)
+    assert abs(loss - lo) <= 2e-5 * lo + np.mean(w * dy * (2 * np.abs(yo - tt) + dy)) + 1e-12
+    go = 2.0 * (yo - tt) * w / m
+    dg = 2.0 * dy * w / m + 4 * U23 * np.abs(go)
+    # the oracle's backward chain on its own forward chain
+    zero = np.zeros((m, 128))
+    dz2o = oracle.mlp_backward_given(P, x, go, h1o, h2o, zero, zero)["dz2"]
+    b = oracle.mlp_backward_given(P, x, go, h1o, h2o, dz2o, zero)
+    dz1o, dz1abs = b["dz1"], b["dz1_abs"]
+    b = oracle.mlp_backward_given(P, x, go, h1o, h2o, dz2o, dz1o)
+    # dz2 = round(h2 > 0 ? g W3 : 0)
+    a3 = np.abs(W3)[None, :]
+    flip2 = (h2 > 0) != (h2o > 0)
+    lim2 = np.where(flip2, (np.abs(go) + dg)[:, None] * a3, BF_ULP * np.abs(dz2o) + dg[:, None] * a3)
+    ok = np.abs(dz2 - dz2o) <= lim2 * (1 + BF_ULP) + 1e-30
+    assert ok.all(), ("dz2", np.argwhere(~ok)[:5])
+    # dz1 = round(h1 > 0 ? sum_j dz2_j W2[k][j] : 0)
+    c1 = np.abs(dz2 - dz2o) @ np.abs(W2).T
+    flip1 = (h1 > 0) != (h1o > 0)
+    acc1 = 2 * 128 * U23 * (dz1abs + c1) + c1
+    lim1 = np.where(flip1, dz1abs + c1, BF_ULP * np.abs(dz1o) + acc1)
+    ok = np.abs(dz1 - dz1o) <= lim1 * (1 + BF_ULP) + 1e-30
+    assert ok.all(), ("dz1", np.argwhere(~ok)[:5])
+    # gradient: FP32 sums over the batch of products whose factors carry the
+    # deviations checked above
+    dh1, dh2 = np.abs(h1 - h1o), np.abs(h2 - h2o)
+    dd2, dd1 = np.abs(dz2 - dz2o), np.abs(dz1 - dz1o)
+    xb = np.abs(x.astype(np.float64)) * (1 + 2.0 ** -15)  # hi + lo split of each input
+    carried = np.zeros(NP)
+    carried[OFF["W3"]:OFF["b3"]] = dg @ np.abs(h2o) + np.abs(go) @ dh2 + dg @ dh2
+    carried[OFF["b3"]] = dg.sum()
+    carried[OFF["W2"]:OFF["b2"]] = (dh1.T @ np.abs(dz2o) + np.abs(h1o).T @ dd2 + dh1.T @ dd2).ravel()
+    carried[OFF["b2"]:OFF["W3"]] = dd2.sum(axis=0)
+    carried[OFF["W1"]:OFF["W1"] + 27 * 128] = (xb.T @ dd1).ravel()
+    carried[OFF["b1"]:OFF["W2"]] = dd1.sum(axis=0)
     ntiles = (m + 63) // 64
     K = 128 + ntiles + 8  # dW1 sums hi and lo products: 2 x 64 per tile
-    err = np.abs(G - b["grad"])
-    ok = err <= K * U23 * b["grad_abs"] + 1e-30
-    assert ok.all(), (np.argwhere(~ok)[:5], G[~ok][:5], b["grad"][~ok][:5])
+    gbound = _check_carried(G, b["grad"], b["grad_abs"], carried, K, "grad")
     # padding rows of W1 see zero inputs
     assert np.all(G[OFF["W1"] + 27 * 128:OFF["b1"]] == 0.0)
-    # Adam on the GPU's gradient
-    Po, Mo, Vo = oracle.adam(P, M0, V0, G, step, lr)
-    assert np.all(np.abs(P1.astype(np.float64) - Po) <= 1e-5 * lr + 2 * U23 * np.abs(Po))
-    assert np.all(np.abs(M1.astype(np.float64) - Mo) <= 4 * U23 * (0.9 * np.abs(M0) + 0.1 * np.abs(G)) + 1e-38)
-    assert np.all(np.abs(V1.astype(np.float64) - Vo) <= 4 * U23 * (0.999 * V0 + 0.001 * G * G) + 1e-38)
+    # Adam: m and v are affine and quadratic in the gradient; the update lies
+    # within the oracle's updates over the gradient's bound
+    go_all = b["grad"]
+    Po, Mo, Vo = oracle.adam(P, M0, V0, go_all, step, lr)
+    ag = np.abs(go_all) + gbound
+    assert np.all(np.abs(M1.astype(np.float64) - Mo) <= 4 * U23 * (0.9 * np.abs(M0) + 0.1 * ag) + 0.1 * gbound
+                  + 1e-38)
+    assert np.all(np.abs(V1.astype(np.float64) - Vo) <= 4 * U23 * (0.999 * V0 + 0.001 * ag * ag)
+                  + 0.001 * (2 * np.abs(go_all) + gbound) * gbound + 1e-38)
+    outs = np.stack([oracle.adam(P, M0, V0, go_all + f * gbound, step, lr)[0].astype(np.float64)
+                     for f in np.linspace(-1.0, 1.0, 11)])
+    slack = 1e-5 * lr + 2 * U23 * np.abs(Po.astype(np.float64))
+    P1d = P1.astype(np.float64)
+    assert np.all(P1d >= outs.min(axis=0) - slack) and np.all(P1d <= outs.max(axis=0) + slack)
 
 
 def test_train_step_reproducible(ctx):
@@ -232,6 +303,35 @@ def test_stencils_edge_cases(ctx):
         ctx.mlp_stencils(c, xd, cd, sd)  # capacity 4 is too small
 
 
+def _check_combined(kc, sc, khf, shf, sg, y, yo, ybound, kappa_lo):
+    """Combined curvature of mixed cells (values kc, statuses sc) against the
+    rule: the network's value sign * y, unless |sign * y| < kappa_lo and the
+    height function is valid there (status 1-3), then the height function's
+    value; status 8 marks a network value, 8 | s one whose height function
+    (status s) was wanted but not valid. y: the GPU network outputs on the
+    same stencils, yo the oracle's, ybound the bound on their difference."""
+    sgn = sg.astype(np.float64)
+    net = sgn * yo
+    hf_valid = (shf >= 1) & (shf <= 3)
+
+    def expected(flag):
+        use_hf = flag & hf_valid
+        return use_hf, np.where(flag, np.where(use_hf, shf, shf | 8), 8)
+
+    flag = np.abs(net) < kappa_lo
+    # an oracle output within the bound of the threshold may fall on either side on the GPU
+    either = np.abs(np.abs(net) - kappa_lo) <= ybound
+    hf_a, st_a = expected(flag)
+    hf_b, st_b = expected(~flag)
+    took_a = sc == st_a
+    assert np.all(took_a | (either & (sc == st_b)))
+    use_hf = np.where(took_a, hf_a, hf_b)
+    assert np.all(np.abs(kc[use_hf] - khf[use_hf]) <= 1e-12)
+    assert np.all(np.abs(kc[~use_hf] - net[~use_hf]) <= ybound[~use_hf])
+    # the fused curvature kernel gives the forward kernel's outputs
+    assert np.array_equal(kc[~use_hf], (sgn * y)[~use_hf])
+
+
 @pytest.mark.parametrize("R,kappa_lo", [(3.0, 0.3), (8.0, 0.3), (8.0, 0.0)])
 def test_curvature_mlp_combination(ctx, R, kappa_lo):
     import torch
@@ -244,23 +344,59 @@ def test_curvature_mlp_combination(ctx, R, kappa_lo):
     kap = torch.zeros(c.shape, dtype=torch.float64, device="cuda:0")
     st = torch.zeros(c.shape, dtype=torch.uint8, device="cuda:0")
     nm = ctx.curvature_mlp(cd, _dev(P), kappa_lo, kap, st)
+    # the network on the oracle's stencils, with its records, bounds the GPU output
     y = torch.zeros(len(cells), dtype=torch.float32, device="cuda:0")
-    ctx.mlp_forward(_dev(P), _dev(xs), y)
+    acts = torch.zeros((len(cells), 768), dtype=torch.uint8, device="cuda:0")
+    ctx.mlp_forward(_dev(P), _dev(xs), y, acts)
     torch.cuda.synchronize()
     assert nm == len(cells)
-    kap, st, y = kap.cpu().numpy().ravel(), st.cpu().numpy().ravel(), y.cpu().numpy().astype(np.float64)
+    kap, st = kap.cpu().numpy().ravel(), st.cpu().numpy().ravel()
+    y = y.cpu().numpy().astype(np.float64)
+    h1, h2 = _records(acts.cpu().numpy())
+    _, _, yo, ybound = _forward_chain(P, xs, h1, h2, y)
     khf, shf = oracle.curvature_hf(c)
     khf, shf = khf.ravel(), shf.ravel()
-    net = sg.astype(np.float64) * y
-    # the network's value unless |kappa| < kappa_lo and the height function is valid there
-    flag = np.abs(net) < kappa_lo
-    hs = shf[cells]
-    hf_ok = flag & (hs >= 1) & (hs <= 3)
-    want_k = np.where(hf_ok, khf[cells], net)
-    want_s = np.where(flag, np.where(hf_ok, hs, hs | 8), 8)
-    assert np.array_equal(st[cells], want_s)
-    assert np.array_equal(kap[cells], want_k)
+    _check_combined(kap[cells], st[cells], khf[cells], shf[cells], sg, y, yo, ybound, kappa_lo)
     other = np.setdiff1d(np.arange(c.size), cells)
     assert np.all(st[other] == 0) and np.all(np.isnan(kap[other]))
     if kappa_lo == 0.0:
         assert np.all(st[cells] == 8)
+
+
+def test_curvature_mlp_full_size(ctx, drops512):
+    """One 512^3 field of the benchmark workload with the trained weights, as
+    the benchmark runs it: the count of mixed cells, and 4096 sampled mixed
+    cells against the oracle's stencils, network and height functions."""
+    import torch
+
+    from paper_2407_07463_amd import training
+    from mlp_fixtures import block_at
+
+    P, meta = training.load_weights()
+    c = drops512["c"][0]
+    note("curvature mlp drops512 tracer 0 (full size)")
+    cd = _dev(c)
+    kap = torch.zeros(c.shape, dtype=torch.float64, device="cuda:0")
+    st = torch.zeros(c.shape, dtype=torch.uint8, device="cuda:0")
+    nm = ctx.curvature_mlp(cd, _dev(P), meta["kappa_lo"], kap, st)
+    torch.cuda.synchronize()
+    mixed = np.flatnonzero((c > 0.0) & (c < 1.0))
+    assert nm == len(mixed)
+    rng = np.random.default_rng(7)
+    cells = np.sort(rng.choice(mixed, 4096, replace=False))
+    nz, ny, nx = c.shape
+    xs = np.zeros((len(cells), 27), dtype=np.float32)
+    sg = np.zeros(len(cells), dtype=np.int8)
+    for q, p in enumerate(cells):
+        xs[q], sg[q] = oracle.canonical_stencil(block_at(c, p // (nx * ny), (p // nx) % ny, p % nx))
+    y = torch.zeros(len(cells), dtype=torch.float32, device="cuda:0")
+    acts = torch.zeros((len(cells), 768), dtype=torch.uint8, device="cuda:0")
+    ctx.mlp_forward(_dev(P), _dev(xs), y, acts)
+    torch.cuda.synchronize()
+    y = y.cpu().numpy().astype(np.float64)
+    h1, h2 = _records(acts.cpu().numpy())
+    _, _, yo, ybound = _forward_chain(P, xs, h1, h2, y)
+    khf, shf = oracle.curvature_hf(c)
+    kc = kap.cpu().numpy().ravel()[cells]
+    sc = st.cpu().numpy().ravel()[cells]
+    _check_combined(kc, sc, khf.ravel()[cells], shf.ravel()[cells], sg, y, yo, ybound, meta["kappa_lo"])
