@@ -211,8 +211,12 @@ def test_recolour_spheres64(ctx, spheres64_after):
     c[:2] = spheres64_after
     note("recolour spheres64")
     g, gntr, gnewt, gmoved, glab, gnd = _gpu_recolour(ctx, c, 2, 1.5)
-    labels = np.stack([oracle.label(c[t])[0] for t in range(2)])
-    o, ontr, onewt, omoved, rc = oracle.recolor(c, labels, gnd, 2, 4, 1.5)
+    ol = [oracle.label(c[t]) for t in range(2)]
+    labels = np.stack([o[0] for o in ol])
+    nd = [o[1] for o in ol]
+    assert np.array_equal(glab, labels) and list(gnd) == nd
+    o, ontr, onewt, omoved, rc = oracle.recolor(c, labels, nd, 2, 4, 1.5)
+    assert rc == 0
     assert gntr == ontr and gmoved == omoved and np.array_equal(gnewt, onewt)
     assert np.array_equal(g, o)
 
