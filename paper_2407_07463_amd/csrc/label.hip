@@ -5,25 +5,28 @@
 // 6-connected periodic components of {c > c_eps}, numbered 1..K in
 // increasing order of their smallest linear index.
 //
-// GPU scheme (union-find with atomicMin hooking, Komura/Playne-style); every
-// kernel runs one wavefront per 64-cell row segment, so the lanes of a run of
-// occupied cells sit side by side in one wavefront:
-//   1. init:    parent[p] = start of p's run of occupied cells inside its
-//               segment (one ballot per wavefront), -1 if empty;
-//   2. merge:   one union per run of cells occupied in both this row and the
-//               +y (or +z) row — the cells of a run already share a parent —
-//               and one at the segment's first cell with its -x neighbour
-//               (periodic); a union always hooks the larger root under the
-//               smaller one, so every component ends rooted at its smallest
-//               linear index whatever the order of the unions;
-//   3. flatten: parent[start] = root(start) for every run start (the other
-//               cells keep pointing at their start);
-//   4. rank:    roots are counted per block with ballots, block counts are
-//               scanned, and each root gets 1 + (number of roots before it);
-//   5. final:   label[p] = rank of the root of p's run, read by the run's
-//               start lane and passed to the run by a lane shuffle.
-// The result is bit-identical to a sequential flood fill seeded in linear
-// order.
+// GPU scheme: union-find over row runs (atomicMin hooking, path halving).
+// A segment is 64 consecutive cells of one x-row; a run is a maximal set of
+// consecutive occupied cells inside one segment, and run r of segment g (in
+// x order) has the id g * S + r, S = the most runs a segment can hold, so
+// ids increase with the linear index of the runs' first cells.
+//   1. occupancy: one ballot word per segment (bit l: cell 64 * seg + l is
+//               occupied), read from c once; every run starts as its own root;
+//   2. union:   one thread per segment unites each of its runs with the runs
+//               it overlaps in the +y and +z rows (one union per overlap, at
+//               the overlap's first cell) and its first cell with its -x
+//               neighbour (the previous segment's last cell, or the row's
+//               last cell through the periodic boundary); a union hooks the
+//               larger root under the smaller, so every component ends rooted
+//               at its first run, whatever the order of the unions;
+//   3. flatten: every run points at its root; roots counted per workgroup;
+//   4. rank:    the counts are scanned and each root's entry becomes
+//               -(1 + number of roots before it);
+//   5. labels:  each cell reads its run's entry (and the root's) and writes
+//               the label, 0 for empty cells.
+// Passes 2-4 touch only the occupancy words and the run array (one entry per
+// run); the cells are read once (pass 1) and written once (pass 5). The
+// result is bit-identical to a sequential flood fill seeded in linear order.
 #include "common.hpp"
 #include "compact.hpp"
 
@@ -100,106 +103,100 @@ __device__ __forceinline__ int64_t first_segment() {
   return (((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6) * kSegs;
 }
 
-__global__ __launch_bounds__(kBlock) void k_label_init(const double *__restrict__ c, double c_eps,
-                                                       int32_t *__restrict__ P, int nx, int ny, int nz, int words) {
+// Index of the run of m that contains bit i (bit i set).
+__device__ __forceinline__ int run_index(uint64_t m, int i) {
+  const uint64_t starts = m & ~(m << 1);
+  const uint64_t upto = (i == 63) ? ~0ull : ((2ull << i) - 1);
+  return __popcll(starts & upto) - 1;
+}
+
+// Pass 1: occupancy words; run entries set to their own ids.
+__global__ __launch_bounds__(kBlock) void k_label_occ(const double *__restrict__ c, double c_eps,
+                                                      uint64_t *__restrict__ occ, int32_t *__restrict__ R, int nx,
+                                                      int ny, int nz, int words, int S) {
   const int lane = threadIdx.x & 63;
   const int64_t nseg = (int64_t)ny * nz * words, s0 = first_segment();
   for (int64_t sgi = s0; sgi < s0 + kSegs && sgi < nseg; ++sgi) {  // wave-uniform
     const Segment sg = segment_of(sgi, words, ny);
     const int x = sg.seg * 64 + lane;
     const bool live = x < nx;
-    const int64_t p = sg.row * nx + x;
-    const bool occ = live && (c[p] > c_eps);
-    const uint64_t m = __ballot(occ);
-    if (!live) continue;
-    if (!occ) {
-      P[p] = -1;
-      continue;
-    }
-    // start of the run of set bits that contains `lane`
-    const uint64_t below = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1);
-    const uint64_t zeros = ~m & below;  // empty cells at or below this lane
-    const int start = zeros ? (64 - __clzll(zeros)) : 0;  // one past the highest empty lane below
-    P[p] = (int32_t)(sg.row * nx + sg.seg * 64 + start);
+    const uint64_t m = __ballot(live && c[sg.row * nx + x] > c_eps);
+    if (lane == 0) occ[sgi] = m;
+    const int nr = __popcll(m & ~(m << 1));
+    if (lane < nr) R[sgi * S + lane] = (int32_t)(sgi * S + lane);
   }
 }
 
-// Lane of the first cell of the run of set bits of m that contains `lane`.
-__device__ __forceinline__ int run_start_lane(uint64_t m, int lane) {
-  const uint64_t upto = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1);
-  const uint64_t zeros = ~m & upto;
-  return zeros ? (64 - __clzll(zeros)) : 0;
-}
-
-// Unions are made between run starts only (the union at the first cell of an
-// overlap goes to the starts of the two runs), so the root searches, which
-// shorten the paths they walk, only ever rewrite run starts: every other
-// occupied cell keeps pointing at its own run's start.
-__global__ __launch_bounds__(kBlock) void k_label_merge(int32_t *P, int nx, int ny, int nz, int words) {
-  const int lane = threadIdx.x & 63;
-  const int64_t nseg = (int64_t)ny * nz * words, s0 = first_segment();
-  for (int64_t sgi = s0; sgi < s0 + kSegs && sgi < nseg; ++sgi) {  // wave-uniform
-    const Segment sg = segment_of(sgi, words, ny);
-    const int x = sg.seg * 64 + lane;
-    const bool live = x < nx;
-    const int64_t p = sg.row * nx + x;
-    const bool occ = live && P[p] >= 0;
-    const uint64_t mo = __ballot(occ);
-    if (mo == 0) continue;  // wave-uniform
-    const int64_t seg0 = sg.row * nx + sg.seg * 64;
-    // -x: the segment's first cell (a run start) and its left neighbour (the
-    // previous segment's last cell, or x = nx-1 through the periodic
-    // boundary), represented by its parent, which is a run start
-    if (lane == 0 && occ) {
-      const int64_t q = sg.row * nx + (x == 0 ? nx - 1 : x - 1);
-      if (q != p) {
-        const int32_t pq = P[q];
-        if (pq >= 0) unite(P, (int32_t)p, pq);
-      }
+// Pass 2: unions of each segment's runs with their +y, +z and -x neighbours.
+__global__ __launch_bounds__(kBlock) void k_label_union(const uint64_t *__restrict__ occ, int32_t *R, int nx, int ny,
+                                                        int nz, int words, int S) {
+  const int64_t sgi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t nseg = (int64_t)ny * nz * words;
+  if (sgi >= nseg) return;
+  const uint64_t m = occ[sgi];
+  if (m == 0) return;
+  const Segment sg = segment_of(sgi, words, ny);
+  const int32_t base = (int32_t)(sgi * S);
+  // -x: the first cell (bit 0, run 0) and its left neighbour
+  if (m & 1ull) {
+    const int64_t lsg = (sg.seg > 0) ? sgi - 1 : sgi + words - 1;
+    const int lbit = (sg.seg > 0) ? 63 : (nx - 1) - 64 * (words - 1);
+    if (!(lsg == sgi && lbit == 0)) {  // a one-cell row is its own neighbour
+      const uint64_t ml = (lsg == sgi) ? m : occ[lsg];
+      if ((ml >> lbit) & 1ull) unite(R, base, (int32_t)(lsg * S) + run_index(ml, lbit));
     }
-    // +y and +z: the first cell of every run occupied in both rows
-    const int yp = (sg.y == ny - 1) ? 0 : sg.y + 1;
-    const int zp = (sg.z == nz - 1) ? 0 : sg.z + 1;
-    const int64_t rowy = (int64_t)sg.z * ny + yp, rowz = (int64_t)zp * ny + sg.y;
-    const int64_t qy = rowy * nx + x, qz = rowz * nx + x;
-    const bool oy = live && P[qy] >= 0;
-    const bool oz = live && P[qz] >= 0;
-    const uint64_t my = __ballot(oy), mz = __ballot(oz);
-    const uint64_t by = mo & my, bz = mo & mz;
-    const uint64_t sy = by & ~(by << 1), sz = bz & ~(bz << 1);
-    const int32_t sp = (int32_t)(seg0 + run_start_lane(mo, lane));
-    if (((sy >> lane) & 1ull) && qy != p)
-      unite(P, sp, (int32_t)(rowy * nx + sg.seg * 64 + run_start_lane(my, lane)));
-    if (((sz >> lane) & 1ull) && qz != p)
-      unite(P, sp, (int32_t)(rowz * nx + sg.seg * 64 + run_start_lane(mz, lane)));
+  }
+  // +y, +z: the first cell of every overlap of a run with a run of that row
+  for (int dir = 0; dir < 2; ++dir) {
+    int64_t nrow;
+    if (dir == 0) {
+      if (ny == 1) continue;
+      nrow = (int64_t)sg.z * ny + ((sg.y == ny - 1) ? 0 : sg.y + 1);
+    } else {
+      if (nz == 1) continue;
+      nrow = (int64_t)((sg.z == nz - 1) ? 0 : sg.z + 1) * ny + sg.y;
+    }
+    const int64_t nsg = nrow * words + sg.seg;
+    const uint64_t mn = occ[nsg];
+    const uint64_t ov = m & mn;
+    uint64_t firsts = ov & ~(ov << 1);
+    while (firsts) {
+      const int i = __ffsll((unsigned long long)firsts) - 1;
+      firsts &= firsts - 1;
+      unite(R, base + run_index(m, i), (int32_t)(nsg * S) + run_index(mn, i));
+    }
   }
 }
 
-// Run starts: parent = root; roots counted per block (the layout of
-// k_label_rank).
-__global__ __launch_bounds__(kBlock) void k_label_flatten(int32_t *P, int nx, int ny, int nz, int words,
-                                                          uint32_t *__restrict__ blockcount) {
-  const int lane = threadIdx.x & 63;
-  const int64_t nseg = (int64_t)ny * nz * words, s0 = first_segment();
-  uint32_t nroot = 0;  // wave-uniform
-  for (int64_t sgi = s0; sgi < s0 + kSegs && sgi < nseg; ++sgi) {
-    const Segment sg = segment_of(sgi, words, ny);
-    const int x = sg.seg * 64 + lane;
-    const bool live = x < nx;
-    const int64_t p = sg.row * nx + x;
-    const int32_t v = live ? P[p] : -1;
-    const uint64_t mo = __ballot(v >= 0);
-    const uint64_t starts = mo & ~(mo << 1);
-    bool root = false;
-    if ((starts >> lane) & 1ull) {
-      const int32_t r = find_root(P, (int32_t)p);
-      root = (r == p);
-      if (r != v) P[p] = r;
-    }
-    nroot += (uint32_t)__popcll(__ballot(root));
+// Roots of the runs of segment sgi (thread-local loop).
+__device__ __forceinline__ int count_roots(const int32_t *R, uint64_t m, int64_t sgi, int S) {
+  const int nr = __popcll(m & ~(m << 1));
+  int n = 0;
+  for (int r = 0; r < nr; ++r) {
+    const int32_t id = (int32_t)(sgi * S + r);
+    n += (R[id] == id) ? 1 : 0;
   }
+  return n;
+}
+
+// Pass 3: every run points at its root; roots counted per workgroup.
+__global__ __launch_bounds__(kBlock) void k_label_flatten(const uint64_t *__restrict__ occ, int32_t *R, int64_t nseg,
+                                                          int S, uint32_t *__restrict__ blockcount) {
+  const int64_t sgi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  uint32_t nroot = 0;
+  if (sgi < nseg) {
+    const uint64_t m = occ[sgi];
+    const int nr = __popcll(m & ~(m << 1));
+    for (int r = 0; r < nr; ++r) {
+      const int32_t id = (int32_t)(sgi * S + r);
+      const int32_t root = find_root(R, id);
+      if (root == id) ++nroot;
+      else R[id] = root;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) nroot += __shfl_xor(nroot, o, 64);
   __shared__ uint32_t wcount[kBlock / 64];
-  if (lane == 0) wcount[threadIdx.x >> 6] = nroot;
+  if ((threadIdx.x & 63) == 0) wcount[threadIdx.x >> 6] = nroot;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t s = 0;
@@ -213,65 +210,67 @@ __global__ void k_copy_total(const int32_t *__restrict__ tot, int64_t ntiles, in
   if (blockIdx.x == 0 && threadIdx.x == 0) *total = tot[ntiles];
 }
 
-// Rank every root: rootlab[p] = 1 + number of roots before p; rootpos[rank] = p.
-// blockoff: per-block exclusive offsets within tiles of compact::kTile
-// blocks, tileoff: exclusive offsets of the tiles.
-__global__ __launch_bounds__(kBlock) void k_label_rank(const int32_t *__restrict__ P, int nx, int ny, int nz,
-                                                       int words, const int32_t *__restrict__ blockoff,
-                                                       const int32_t *__restrict__ tileoff,
-                                                       int32_t *__restrict__ rootlab, int32_t *__restrict__ rootpos) {
+// Pass 4: each root's entry becomes -(1 + number of roots before it), in
+// run order. blockoff: per-block exclusive offsets within tiles of
+// compact::kTile blocks, tileoff: exclusive offsets of the tiles.
+__global__ __launch_bounds__(kBlock) void k_label_rank(const uint64_t *__restrict__ occ, int32_t *R, int64_t nseg,
+                                                       int S, const int32_t *__restrict__ blockoff,
+                                                       const int32_t *__restrict__ tileoff) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t nseg = (int64_t)ny * nz * words, s0 = first_segment();
-  // roots of each wavefront, then the offset of this wavefront in the block
-  uint32_t nroot = 0;
-  for (int64_t sgi = s0; sgi < s0 + kSegs && sgi < nseg; ++sgi) {
-    const Segment sg = segment_of(sgi, words, ny);
-    const int x = sg.seg * 64 + lane;
-    const int64_t p = sg.row * nx + x;
-    nroot += (uint32_t)__popcll(__ballot((x < nx) && (P[p] == p)));
+  const int64_t sgi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint64_t m = (sgi < nseg) ? occ[sgi] : 0ull;
+  const int mine = (sgi < nseg) ? count_roots(R, m, sgi, S) : 0;
+  // exclusive prefix of the counts over the workgroup's threads
+  int incl = mine;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += v;
   }
-  __shared__ uint32_t wcount[kBlock / 64];
-  if (lane == 0) wcount[w] = nroot;
+  __shared__ int wtot[kBlock / 64];
+  if (lane == 63) wtot[w] = incl;
   __syncthreads();
-  uint32_t before = (uint32_t)(blockoff[blockIdx.x] + tileoff[blockIdx.x / compact::kTile]);
-  for (int k = 0; k < w; ++k) before += wcount[k];
-  for (int64_t sgi = s0; sgi < s0 + kSegs && sgi < nseg; ++sgi) {
-    const Segment sg = segment_of(sgi, words, ny);
-    const int x = sg.seg * 64 + lane;
-    const int64_t p = sg.row * nx + x;
-    const bool root = (x < nx) && (P[p] == p);
-    const uint64_t m = __ballot(root);
-    if (root) {
-      const uint32_t r = before + (uint32_t)__popcll(m & ((1ull << lane) - 1));
-      rootlab[p] = (int32_t)r + 1;
-      if (rootpos) rootpos[r] = (int32_t)p;
-    }
-    before += (uint32_t)__popcll(m);
+  int before = blockoff[blockIdx.x] + tileoff[blockIdx.x / compact::kTile] + incl - mine;
+  for (int k = 0; k < w; ++k) before += wtot[k];
+  if (mine == 0) return;
+  const int nr = __popcll(m & ~(m << 1));
+  for (int r = 0; r < nr; ++r) {
+    const int32_t id = (int32_t)(sgi * S + r);
+    if (R[id] == id) R[id] = -(++before);
   }
 }
 
-// label[p] = rank of the root of p's run (0 if empty), in place.
-__global__ __launch_bounds__(kBlock) void k_label_final(int32_t *__restrict__ P, int nx, int ny, int nz, int words,
-                                                        const int32_t *__restrict__ rootlab) {
+// Pass 5: label of every cell of the field (0 for empty cells).
+__global__ __launch_bounds__(kBlock) void k_label_write(const uint64_t *__restrict__ occ,
+                                                        const int32_t *__restrict__ R, int32_t *__restrict__ lab,
+                                                        int nx, int ny, int nz, int words, int S) {
   const int lane = threadIdx.x & 63;
   const int64_t nseg = (int64_t)ny * nz * words, s0 = first_segment();
   for (int64_t sgi = s0; sgi < s0 + kSegs && sgi < nseg; ++sgi) {  // wave-uniform
     const Segment sg = segment_of(sgi, words, ny);
     const int x = sg.seg * 64 + lane;
-    const bool live = x < nx;
-    const int64_t p = sg.row * nx + x;
-    const int64_t seg0 = sg.row * nx + sg.seg * 64;
-    const int32_t v = live ? P[p] : -1;
-    const uint64_t mo = __ballot(v >= 0);
-    const uint64_t starts = mo & ~(mo << 1);
-    // a start holds its root; the others point at their start (in this segment)
-    int32_t lab = 0;
-    if ((starts >> lane) & 1ull) lab = rootlab[v];
-    const int src = (v >= 0) ? (int)((((starts >> lane) & 1ull) ? p : (int64_t)v) - seg0) : lane;
-    const int32_t got = __shfl(lab, src, 64);
-    if (live) P[p] = (v >= 0) ? got : 0;
+    const uint64_t m = occ[sgi];
+    int32_t v = 0;
+    if ((m >> lane) & 1ull) {
+      const int32_t e = R[sgi * S + run_index(m, lane)];
+      v = (e < 0) ? -e : -R[e];
+    }
+    if (x < nx) lab[sg.row * nx + x] = v;
   }
 }
+
+// Workgroups of the per-cell labelling passes (kSegs row segments per
+// wavefront) and of the per-segment passes (one thread per segment).
+static inline int64_t label_blocks(int nx, int ny, int nz) {
+  const int64_t words = (nx + 63) / 64;
+  const int64_t per = (int64_t)(kBlock / 64) * kSegs;
+  return ((int64_t)ny * nz * words + per - 1) / per;
+}
+static inline int64_t segment_blocks(int nx, int ny, int nz) {
+  const int64_t words = (nx + 63) / 64;
+  return ((int64_t)ny * nz * words + kBlock - 1) / kBlock;
+}
+// Run slots per segment: a segment of w cells holds at most (w + 1) / 2 runs.
+static inline int run_slots(int nx) { return ((nx < 64 ? nx : 64) + 1) / 2; }
 
 // ------------------------------------------------------------------ moments
 
@@ -519,34 +518,30 @@ __global__ void k_drop_finish(int32_t K, int nx, int ny, int nz, const int32_t *
 
 }  // namespace
 
-// Workgroups of the labelling kernels: kSegs row segments per wavefront.
-static inline int64_t label_blocks(int nx, int ny, int nz) {
-  const int64_t words = (nx + 63) / 64;
-  const int64_t per = (int64_t)(kBlock / 64) * kSegs;
-  return ((int64_t)ny * nz * words + per - 1) / per;
-}
-
 // Label one tracer field into `lab`. Returns K via *k_dev (device int32).
-// Scratch: block counts (label_blocks entries), tile offsets
-// (label_blocks / compact::kTile + 2 entries), rootlab (n3 int32).
+// Scratch: occupancy words (one per segment), run array (S per segment),
+// block counts (segment_blocks entries), tile offsets
+// (segment_blocks / compact::kTile + 2 entries).
 static int label_one(vofmt_ctx *ctx, int nx, int ny, int nz, const double *c, double c_eps, int32_t *lab,
-                     uint32_t *blockcount, int32_t *tileoff, int32_t *rootlab, int32_t *k_dev, hipStream_t stream) {
+                     uint64_t *occ, int32_t *runs, uint32_t *blockcount, int32_t *tileoff, int32_t *k_dev,
+                     hipStream_t stream) {
   const int words = (int)ceil_div(nx, 64);
-  const unsigned nb = (unsigned)label_blocks(nx, ny, nz);  // every kernel: kSegs row segments per wavefront
-  const unsigned nb_init = nb;
-  hipLaunchKernelGGL(k_label_init, dim3(nb_init), dim3(kBlock), 0, stream, c, c_eps, lab, nx, ny, nz, words);
-  hipLaunchKernelGGL(k_label_merge, dim3(nb), dim3(kBlock), 0, stream, lab, nx, ny, nz, words);
-  hipLaunchKernelGGL(k_label_flatten, dim3(nb), dim3(kBlock), 0, stream, lab, nx, ny, nz, words, blockcount);
+  const int S = run_slots(nx);
+  const int64_t nseg = (int64_t)ny * nz * words;
+  const unsigned nbc = (unsigned)label_blocks(nx, ny, nz);  // per-cell passes
+  const unsigned nbs = (unsigned)segment_blocks(nx, ny, nz);  // per-segment passes
+  hipLaunchKernelGGL(k_label_occ, dim3(nbc), dim3(kBlock), 0, stream, c, c_eps, occ, runs, nx, ny, nz, words, S);
+  hipLaunchKernelGGL(k_label_union, dim3(nbs), dim3(kBlock), 0, stream, occ, runs, nx, ny, nz, words, S);
+  hipLaunchKernelGGL(k_label_flatten, dim3(nbs), dim3(kBlock), 0, stream, occ, runs, nseg, S, blockcount);
   static_assert(kBlock == compact::kBlock, "block counts and the tiled scan share the block size");
-  const int64_t ntiles = (nb + compact::kTile - 1) / compact::kTile;
+  const int64_t ntiles = (nbs + compact::kTile - 1) / compact::kTile;
   int32_t *bc = (int32_t *)blockcount;
-  hipLaunchKernelGGL(compact::k_scan_tile, dim3((unsigned)ntiles), dim3(compact::kTile), 0, stream, bc, (int64_t)nb,
+  hipLaunchKernelGGL(compact::k_scan_tile, dim3((unsigned)ntiles), dim3(compact::kTile), 0, stream, bc, (int64_t)nbs,
                      tileoff);
   hipLaunchKernelGGL(compact::k_scan_totals, dim3(1), dim3(compact::kTile), 0, stream, tileoff, ntiles);
   hipLaunchKernelGGL(k_copy_total, dim3(1), dim3(64), 0, stream, tileoff, ntiles, k_dev);
-  hipLaunchKernelGGL(k_label_rank, dim3(nb), dim3(kBlock), 0, stream, lab, nx, ny, nz, words, bc, tileoff, rootlab,
-                     (int32_t *)nullptr);
-  hipLaunchKernelGGL(k_label_final, dim3(nb), dim3(kBlock), 0, stream, lab, nx, ny, nz, words, rootlab);
+  hipLaunchKernelGGL(k_label_rank, dim3(nbs), dim3(kBlock), 0, stream, occ, runs, nseg, S, bc, tileoff);
+  hipLaunchKernelGGL(k_label_write, dim3(nbc), dim3(kBlock), 0, stream, occ, runs, lab, nx, ny, nz, words, S);
   return hip_check(ctx, hipGetLastError(), "label kernels");
 }
 
@@ -561,16 +556,20 @@ extern "C" int vofmt_label_drops(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t
   const int64_t n3 = (int64_t)nx * ny * nz;
   if (n3 >= INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "vofmt_label_drops: more than 2^31-1 cells per field");
   VOFMT_HIP(ctx, hipSetDevice(ctx->device));
-  const int64_t nb = label_blocks(nx, ny, nz);
-  uint32_t *blockcount = (uint32_t *)scratch(ctx, SLOT_LABEL_A, sizeof(uint32_t) * (size_t)nb);
-  int32_t *rootlab = (int32_t *)scratch(ctx, SLOT_LABEL_B, sizeof(int32_t) * (size_t)n3);
+  const int64_t nseg = (int64_t)ny * nz * ceil_div(nx, 64);
+  const int64_t nbs = segment_blocks(nx, ny, nz);
+  // run ids stay below 2^31: S runs per segment is at most n3 / nseg
+  const int64_t nrun = nseg * run_slots(nx);
+  uint32_t *blockcount = (uint32_t *)scratch(ctx, SLOT_LABEL_A, sizeof(uint32_t) * (size_t)nbs);
+  int32_t *runs = (int32_t *)scratch(ctx, SLOT_LABEL_B, sizeof(int32_t) * (size_t)nrun);
+  uint64_t *occ = (uint64_t *)scratch(ctx, SLOT_LABEL_C, sizeof(uint64_t) * (size_t)nseg);
   int32_t *kdev = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * (size_t)ntracers);
-  int32_t *tileoff = (int32_t *)scratch(ctx, SLOT_MISC3, sizeof(int32_t) * (size_t)(nb / compact::kTile + 2));
+  int32_t *tileoff = (int32_t *)scratch(ctx, SLOT_MISC3, sizeof(int32_t) * (size_t)(nbs / compact::kTile + 2));
   int32_t *kh = (int32_t *)host_scratch(ctx, sizeof(int32_t) * (size_t)ntracers);
-  if (!blockcount || !rootlab || !kdev || !tileoff || !kh) return VOFMT_E_NOMEM;
+  if (!blockcount || !runs || !occ || !kdev || !tileoff || !kh) return VOFMT_E_NOMEM;
   for (int t = 0; t < ntracers; ++t) {
-    int rc = label_one(ctx, nx, ny, nz, c + (int64_t)t * n3, c_eps, labels + (int64_t)t * n3, blockcount, tileoff,
-                       rootlab, kdev + t, stream);
+    int rc = label_one(ctx, nx, ny, nz, c + (int64_t)t * n3, c_eps, labels + (int64_t)t * n3, occ, runs, blockcount,
+                       tileoff, kdev + t, stream);
     if (rc) return rc;
   }
   VOFMT_HIP(ctx, hipMemcpyAsync(kh, kdev, sizeof(int32_t) * ntracers, hipMemcpyDeviceToHost, stream));
