@@ -86,17 +86,23 @@ __device__ __forceinline__ void unite(int32_t *P, int32_t a, int32_t b) {
 constexpr int kSegs = 8;
 
 // Row segment `sgi` (all segments of the field in linear order):
-// row = z * ny + y, x = 64 * seg + lane.
+// row = z * ny + y, x = 64 * seg + lane. Segment counts stay below 2^31 (at
+// most one segment per cell), so the divisions are 32-bit multiply-shifts.
 struct Segment {
   int64_t row;
   int seg, y, z;
 };
-__device__ __forceinline__ Segment segment_of(int64_t sgi, int words, int ny) {
+struct SegDiv {
+  FastDiv words, ny;
+};
+__device__ __forceinline__ Segment segment_of(int64_t sgi, const SegDiv &dv) {
   Segment s;
-  s.row = sgi / words;  // wavefront-uniform: scalar arithmetic
-  s.seg = (int)(sgi - s.row * words);
-  s.y = (int)(s.row % ny);
-  s.z = (int)(s.row / ny);
+  const uint32_t row = fast_div((uint32_t)sgi, dv.words);
+  const uint32_t z = fast_div(row, dv.ny);
+  s.row = row;
+  s.seg = (int)((uint32_t)sgi - row * dv.words.d);
+  s.y = (int)(row - z * dv.ny.d);
+  s.z = (int)z;
   return s;
 }
 __device__ __forceinline__ int64_t first_segment() {
@@ -110,17 +116,30 @@ __device__ __forceinline__ int run_index(uint64_t m, int i) {
   return __popcll(starts & upto) - 1;
 }
 
-// Pass 1: occupancy words; run entries set to their own ids.
+// Pass 1: occupancy words; run entries set to their own ids. The values of
+// the wavefront's kSegs segments are all loaded before the first ballot, so
+// their loads are in flight together.
 __global__ __launch_bounds__(kBlock) void k_label_occ(const double *__restrict__ c, double c_eps,
                                                       uint64_t *__restrict__ occ, int32_t *__restrict__ R, int nx,
-                                                      int ny, int nz, int words, int S) {
+                                                      int ny, int nz, int words, int S, SegDiv dv) {
   const int lane = threadIdx.x & 63;
   const int64_t nseg = (int64_t)ny * nz * words, s0 = first_segment();
-  for (int64_t sgi = s0; sgi < s0 + kSegs && sgi < nseg; ++sgi) {  // wave-uniform
-    const Segment sg = segment_of(sgi, words, ny);
-    const int x = sg.seg * 64 + lane;
-    const bool live = x < nx;
-    const uint64_t m = __ballot(live && c[sg.row * nx + x] > c_eps);
+  double v[kSegs];
+#pragma unroll
+  for (int k = 0; k < kSegs; ++k) {
+    v[k] = 0.0;  // not occupied: c_eps >= 0
+    const int64_t sgi = s0 + k;
+    if (sgi < nseg) {  // wave-uniform
+      const Segment sg = segment_of(sgi, dv);
+      const int x = sg.seg * 64 + lane;
+      if (x < nx) v[k] = c[sg.row * nx + x];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kSegs; ++k) {
+    const int64_t sgi = s0 + k;
+    if (sgi >= nseg) break;  // wave-uniform
+    const uint64_t m = __ballot(v[k] > c_eps);
     if (lane == 0) occ[sgi] = m;
     const int nr = __popcll(m & ~(m << 1));
     if (lane < nr) R[sgi * S + lane] = (int32_t)(sgi * S + lane);
@@ -129,13 +148,13 @@ __global__ __launch_bounds__(kBlock) void k_label_occ(const double *__restrict__
 
 // Pass 2: unions of each segment's runs with their +y, +z and -x neighbours.
 __global__ __launch_bounds__(kBlock) void k_label_union(const uint64_t *__restrict__ occ, int32_t *R, int nx, int ny,
-                                                        int nz, int words, int S) {
+                                                        int nz, int words, int S, SegDiv dv) {
   const int64_t sgi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t nseg = (int64_t)ny * nz * words;
   if (sgi >= nseg) return;
   const uint64_t m = occ[sgi];
   if (m == 0) return;
-  const Segment sg = segment_of(sgi, words, ny);
+  const Segment sg = segment_of(sgi, dv);
   const int32_t base = (int32_t)(sgi * S);
   // -x: the first cell (bit 0, run 0) and its left neighbour
   if (m & 1ull) {
@@ -239,22 +258,34 @@ __global__ __launch_bounds__(kBlock) void k_label_rank(const uint64_t *__restric
   }
 }
 
-// Pass 5: label of every cell of the field (0 for empty cells).
+// Pass 5: label of every cell of the field (0 for empty cells). The
+// occupancy words, then the run entries, then the roots' entries of the
+// wavefront's kSegs segments are each loaded together.
 __global__ __launch_bounds__(kBlock) void k_label_write(const uint64_t *__restrict__ occ,
                                                         const int32_t *__restrict__ R, int32_t *__restrict__ lab,
-                                                        int nx, int ny, int nz, int words, int S) {
+                                                        int nx, int ny, int nz, int words, int S, SegDiv dv) {
   const int lane = threadIdx.x & 63;
   const int64_t nseg = (int64_t)ny * nz * words, s0 = first_segment();
-  for (int64_t sgi = s0; sgi < s0 + kSegs && sgi < nseg; ++sgi) {  // wave-uniform
-    const Segment sg = segment_of(sgi, words, ny);
+  uint64_t m[kSegs];
+  int32_t e[kSegs];
+#pragma unroll
+  for (int k = 0; k < kSegs; ++k) m[k] = (s0 + k < nseg) ? occ[s0 + k] : 0ull;
+#pragma unroll
+  for (int k = 0; k < kSegs; ++k) {
+    e[k] = 0;
+    if ((m[k] >> lane) & 1ull) e[k] = R[(s0 + k) * S + run_index(m[k], lane)];
+  }
+#pragma unroll
+  for (int k = 0; k < kSegs; ++k) {
+    if ((m[k] >> lane) & 1ull) e[k] = (e[k] < 0) ? -e[k] : -R[e[k]];
+  }
+#pragma unroll
+  for (int k = 0; k < kSegs; ++k) {
+    const int64_t sgi = s0 + k;
+    if (sgi >= nseg) break;  // wave-uniform
+    const Segment sg = segment_of(sgi, dv);
     const int x = sg.seg * 64 + lane;
-    const uint64_t m = occ[sgi];
-    int32_t v = 0;
-    if ((m >> lane) & 1ull) {
-      const int32_t e = R[sgi * S + run_index(m, lane)];
-      v = (e < 0) ? -e : -R[e];
-    }
-    if (x < nx) lab[sg.row * nx + x] = v;
+    if (x < nx) lab[sg.row * nx + x] = e[k];
   }
 }
 
@@ -305,7 +336,9 @@ __device__ __forceinline__ int wave_max(int v) {
 // are order-independent, so the result does not depend on scheduling.
 constexpr int kChunk = 8192;   // cells per workgroup (32 per thread)
 constexpr int kTable = 64;     // LDS records per workgroup (power of two)
+constexpr int kBatch = 8;      // positions per thread whose loads are issued together
 static_assert(kTable == 64 && kChunk % kBlock == 0, "table_slot hashes to 6 bits");
+static_assert((kChunk / kBlock) % kBatch == 0, "whole batches per thread");
 
 __device__ __forceinline__ int table_slot(int32_t *key, int32_t l) {
   const uint32_t h = ((uint32_t)l * 2654435761u) >> 26;  // 6 bits: kTable = 64
@@ -334,49 +367,61 @@ __global__ __launch_bounds__(kBlock) void k_drop_bbox(const int32_t *__restrict_
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int64_t c0 = (int64_t)blockIdx.x * kChunk;
-  for (int it = 0; it < kChunk / kBlock; ++it) {
-    const int64_t p = c0 + (int64_t)it * kBlock + threadIdx.x;
-    const int32_t l = (p < n3) ? lab[p] : 0;
-    const bool valid = l > 0 && l <= K;
-    int d[3] = {0, 0, 0};
-    if (valid) {
-      const uint32_t p0 = (uint32_t)rootpos[l - 1];
-      // cell -> (x, y, z) by multiply-shift division (cells < 2^31)
-      const uint32_t r = fast_div((uint32_t)p, fnx), r0 = fast_div(p0, fnx);
-      const uint32_t zz = fast_div(r, fny), zz0 = fast_div(r0, fny);
-      const int x = (int)((uint32_t)p - r * (uint32_t)nx), y = (int)(r - zz * (uint32_t)ny), z = (int)zz;
-      const int x0 = (int)(p0 - r0 * (uint32_t)nx), y0 = (int)(r0 - zz0 * (uint32_t)ny), z0 = (int)zz0;
-      d[0] = wrapped_delta(x, x0, nx);
-      d[1] = wrapped_delta(y, y0, ny);
-      d[2] = wrapped_delta(z, z0, nz);
+  for (int it0 = 0; it0 < kChunk / kBlock; it0 += kBatch) {
+    // the labels, then the first cells, of kBatch positions are loaded together
+    int32_t lb[kBatch], fb[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int64_t p = c0 + (int64_t)(it0 + u) * kBlock + threadIdx.x;
+      lb[u] = (p < n3) ? lab[p] : 0;
     }
-    uint64_t todo = __ballot(valid);
-    while (todo) {
-      const int leader = __ffsll((long long)todo) - 1;
-      const int32_t lv = __shfl(l, leader, 64);
-      const bool mine = valid && l == lv;
-      const uint64_t same = __ballot(mine);
-      int mn[3], mx[3];
-      for (int a = 0; a < 3; ++a) {
-        mn[a] = wave_min(mine ? d[a] : INT32_MAX);
-        mx[a] = wave_max(mine ? d[a] : INT32_MIN);
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) fb[u] = (lb[u] > 0 && lb[u] <= K) ? rootpos[lb[u] - 1] : 0;
+#pragma unroll 1
+    for (int u = 0; u < kBatch; ++u) {
+      const int64_t p = c0 + (int64_t)(it0 + u) * kBlock + threadIdx.x;
+      const int32_t l = lb[u];
+      const bool valid = l > 0 && l <= K;
+      int d[3] = {0, 0, 0};
+      if (valid) {
+        const uint32_t p0 = (uint32_t)fb[u];
+        // cell -> (x, y, z) by multiply-shift division (cells < 2^31)
+        const uint32_t r = fast_div((uint32_t)p, fnx), r0 = fast_div(p0, fnx);
+        const uint32_t zz = fast_div(r, fny), zz0 = fast_div(r0, fny);
+        const int x = (int)((uint32_t)p - r * (uint32_t)nx), y = (int)(r - zz * (uint32_t)ny), z = (int)zz;
+        const int x0 = (int)(p0 - r0 * (uint32_t)nx), y0 = (int)(r0 - zz0 * (uint32_t)ny), z0 = (int)zz0;
+        d[0] = wrapped_delta(x, x0, nx);
+        d[1] = wrapped_delta(y, y0, ny);
+        d[2] = wrapped_delta(z, z0, nz);
       }
-      if (lane == leader) {
-        const int s = table_slot(key, lv);
-        if (s >= 0) {
-          for (int a = 0; a < 3; ++a) {
-            atomicMin(&rec[s][2 * a], mn[a]);
-            atomicMax(&rec[s][2 * a + 1], mx[a]);
-          }
-        } else {
-          int32_t *b = box + 6 * (int64_t)(lv - 1);
-          for (int a = 0; a < 3; ++a) {
-            atomicMin(&b[2 * a], mn[a]);
-            atomicMax(&b[2 * a + 1], mx[a]);
+      uint64_t todo = __ballot(valid);
+      while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int32_t lv = __shfl(l, leader, 64);
+        const bool mine = valid && l == lv;
+        const uint64_t same = __ballot(mine);
+        int mn[3], mx[3];
+        for (int a = 0; a < 3; ++a) {
+          mn[a] = wave_min(mine ? d[a] : INT32_MAX);
+          mx[a] = wave_max(mine ? d[a] : INT32_MIN);
+        }
+        if (lane == leader) {
+          const int s = table_slot(key, lv);
+          if (s >= 0) {
+            for (int a = 0; a < 3; ++a) {
+              atomicMin(&rec[s][2 * a], mn[a]);
+              atomicMax(&rec[s][2 * a + 1], mx[a]);
+            }
+          } else {
+            int32_t *b = box + 6 * (int64_t)(lv - 1);
+            for (int a = 0; a < 3; ++a) {
+              atomicMin(&b[2 * a], mn[a]);
+              atomicMax(&b[2 * a + 1], mx[a]);
+            }
           }
         }
+        todo &= ~same;
       }
-      todo &= ~same;
     }
   }
   __syncthreads();
@@ -409,21 +454,30 @@ __global__ __launch_bounds__(kBlock) void k_first_min(const int32_t *__restrict_
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int64_t c0 = (int64_t)blockIdx.x * kChunk;
-  for (int it = 0; it < kChunk / kBlock; ++it) {
-    const int64_t p = c0 + (int64_t)it * kBlock + threadIdx.x;
-    const int32_t l = (p < n3) ? lab[p] : 0;
-    const bool valid = l > 0 && l <= K;
-    uint64_t todo = __ballot(valid);
-    while (todo) {
-      const int leader = __ffsll((long long)todo) - 1;
-      const int32_t lv = __shfl(l, leader, 64);
-      const uint64_t same = __ballot(valid && l == lv);
-      if (lane == leader) {
-        const int s = table_slot(key, lv);
-        if (s >= 0) atomicMin(&rec[s], (int32_t)p);
-        else atomicMin(&first[lv - 1], (int32_t)p);
+  for (int it0 = 0; it0 < kChunk / kBlock; it0 += kBatch) {
+    int32_t lb[kBatch];  // the labels of kBatch positions are loaded together
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int64_t p = c0 + (int64_t)(it0 + u) * kBlock + threadIdx.x;
+      lb[u] = (p < n3) ? lab[p] : 0;
+    }
+#pragma unroll 1
+    for (int u = 0; u < kBatch; ++u) {
+      const int64_t p = c0 + (int64_t)(it0 + u) * kBlock + threadIdx.x;
+      const int32_t l = lb[u];
+      const bool valid = l > 0 && l <= K;
+      uint64_t todo = __ballot(valid);
+      while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int32_t lv = __shfl(l, leader, 64);
+        const uint64_t same = __ballot(valid && l == lv);
+        if (lane == leader) {
+          const int s = table_slot(key, lv);
+          if (s >= 0) atomicMin(&rec[s], (int32_t)p);
+          else atomicMin(&first[lv - 1], (int32_t)p);
+        }
+        todo &= ~same;
       }
-      todo &= ~same;
     }
   }
   __syncthreads();
@@ -530,8 +584,9 @@ static int label_one(vofmt_ctx *ctx, int nx, int ny, int nz, const double *c, do
   const int64_t nseg = (int64_t)ny * nz * words;
   const unsigned nbc = (unsigned)label_blocks(nx, ny, nz);  // per-cell passes
   const unsigned nbs = (unsigned)segment_blocks(nx, ny, nz);  // per-segment passes
-  hipLaunchKernelGGL(k_label_occ, dim3(nbc), dim3(kBlock), 0, stream, c, c_eps, occ, runs, nx, ny, nz, words, S);
-  hipLaunchKernelGGL(k_label_union, dim3(nbs), dim3(kBlock), 0, stream, occ, runs, nx, ny, nz, words, S);
+  const SegDiv dv{make_fastdiv((uint32_t)words), make_fastdiv((uint32_t)ny)};
+  hipLaunchKernelGGL(k_label_occ, dim3(nbc), dim3(kBlock), 0, stream, c, c_eps, occ, runs, nx, ny, nz, words, S, dv);
+  hipLaunchKernelGGL(k_label_union, dim3(nbs), dim3(kBlock), 0, stream, occ, runs, nx, ny, nz, words, S, dv);
   hipLaunchKernelGGL(k_label_flatten, dim3(nbs), dim3(kBlock), 0, stream, occ, runs, nseg, S, blockcount);
   static_assert(kBlock == compact::kBlock, "block counts and the tiled scan share the block size");
   const int64_t ntiles = (nbs + compact::kTile - 1) / compact::kTile;
@@ -541,7 +596,7 @@ static int label_one(vofmt_ctx *ctx, int nx, int ny, int nz, const double *c, do
   hipLaunchKernelGGL(compact::k_scan_totals, dim3(1), dim3(compact::kTile), 0, stream, tileoff, ntiles);
   hipLaunchKernelGGL(k_copy_total, dim3(1), dim3(64), 0, stream, tileoff, ntiles, k_dev);
   hipLaunchKernelGGL(k_label_rank, dim3(nbs), dim3(kBlock), 0, stream, occ, runs, nseg, S, bc, tileoff);
-  hipLaunchKernelGGL(k_label_write, dim3(nbc), dim3(kBlock), 0, stream, occ, runs, lab, nx, ny, nz, words, S);
+  hipLaunchKernelGGL(k_label_write, dim3(nbc), dim3(kBlock), 0, stream, occ, runs, lab, nx, ny, nz, words, S, dv);
   return hip_check(ctx, hipGetLastError(), "label kernels");
 }
 
