@@ -304,18 +304,22 @@ static inline int64_t segment_blocks(int nx, int ny, int nz) {
 static inline int run_slots(int nx) { return ((nx < 64 ? nx : 64) + 1) / 2; }
 
 // ------------------------------------------------------------------ moments
+//
+// Bounding box of a drop as offsets from its first cell p0 (the reference of
+// the centroid), wrapped into [-n/2, n/2) per axis. The cells of a connected
+// drop project onto each periodic axis as one contiguous arc. Two frames of
+// the axis are tracked: A, the coordinate a itself, and B, (a + n/2) mod n,
+// whose cuts (between n-1 and 0, and between n-n/2-1 and n-n/2) lie n/2
+// apart. An arc of L cells with 2 (L-1) < n contains at most one cut, so the
+// frame with the smaller span holds it uncut, with span L - 1, and its
+// min/max minus p0's coordinate in that frame are the wrapped offsets of the
+// arc's ends. When 2 (L-1) >= n both frames span at least n/2, which is the
+// extent error in either case. So one pass over the labels collects, per
+// drop, the first cell and the min/max of both frames on each axis, and a
+// per-drop step turns them into the box.
 
-// Offsets of p from the drop's first cell p0, wrapped into [-n/2, n/2).
-__device__ __forceinline__ int wrapped_delta(int a, int a0, int n) {
-  int d = a - a0;
-  if (d < 0) d += n;
-  if (2 * d >= n) d -= n;
-  return d;
-}
-
-// Per-drop bounding box of the offsets (integer atomics: order-independent).
-// Wavefront-wide minimum / maximum over the lanes in `mask` (others pass the
-// neutral value in).
+// Wavefront-wide minimum / maximum (every lane passes a value; lanes outside
+// the set pass the neutral value).
 __device__ __forceinline__ int wave_min(int v) {
   for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
   return v;
@@ -325,18 +329,19 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-// Per-drop reductions (first cell, bounding box) go through a small hash
-// table in LDS per workgroup: a workgroup sweeps kChunk consecutive cells,
-// the lanes of a wavefront holding the same drop are combined first, each
-// such group updates the drop's LDS record with LDS atomics, and at the end
-// the workgroup applies one set of global atomics per drop it met. Global
-// atomics on one address from many workgroups are serialised; this makes
-// them about kChunk / (cells of a drop's row run) times fewer. A drop that
-// finds the table full goes to the global atomics directly. Integer min/max
-// are order-independent, so the result does not depend on scheduling.
+// Per-drop reductions go through a small hash table in LDS per workgroup: a
+// workgroup sweeps kChunk consecutive cells, the lanes of a wavefront holding
+// the same drop are combined first, each such group updates the drop's LDS
+// record with LDS atomics, and at the end the workgroup applies one set of
+// global atomics per drop it met. Global atomics on one address from many
+// workgroups are serialised; this makes them about kChunk / (cells of a
+// drop's row run) times fewer. A drop that finds the table full goes to the
+// global atomics directly. Integer min/max are order-independent, so the
+// result does not depend on scheduling.
 constexpr int kChunk = 8192;   // cells per workgroup (32 per thread)
 constexpr int kTable = 64;     // LDS records per workgroup (power of two)
 constexpr int kBatch = 8;      // positions per thread whose loads are issued together
+constexpr int kFrames = 12;    // per drop: axis a -> min A, max A, min B, max B at 4a
 static_assert(kTable == 64 && kChunk % kBlock == 0, "table_slot hashes to 6 bits");
 static_assert((kChunk / kBlock) % kBatch == 0, "whole batches per thread");
 
@@ -350,109 +355,43 @@ __device__ __forceinline__ int table_slot(int32_t *key, int32_t l) {
   return -1;
 }
 
-// Bounding box of every drop as offsets from its first cell (periodic).
-__global__ __launch_bounds__(kBlock) void k_drop_bbox(const int32_t *__restrict__ lab, int64_t n3, int nx, int ny, int nz,
-                                                      FastDiv fnx, FastDiv fny, int32_t K,
-                                                      const int32_t *__restrict__ rootpos,
-                                                      int32_t *__restrict__ box) {
-  __shared__ int32_t key[kTable];
-  __shared__ int32_t rec[kTable][6];
-  for (int i = threadIdx.x; i < kTable; i += kBlock) {
-    key[i] = 0;
-    for (int a = 0; a < 3; ++a) {
-      rec[i][2 * a] = INT32_MAX;
-      rec[i][2 * a + 1] = INT32_MIN;
-    }
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int64_t c0 = (int64_t)blockIdx.x * kChunk;
-  for (int it0 = 0; it0 < kChunk / kBlock; it0 += kBatch) {
-    // the labels, then the first cells, of kBatch positions are loaded together
-    int32_t lb[kBatch], fb[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int64_t p = c0 + (int64_t)(it0 + u) * kBlock + threadIdx.x;
-      lb[u] = (p < n3) ? lab[p] : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) fb[u] = (lb[u] > 0 && lb[u] <= K) ? rootpos[lb[u] - 1] : 0;
-#pragma unroll 1
-    for (int u = 0; u < kBatch; ++u) {
-      const int64_t p = c0 + (int64_t)(it0 + u) * kBlock + threadIdx.x;
-      const int32_t l = lb[u];
-      const bool valid = l > 0 && l <= K;
-      int d[3] = {0, 0, 0};
-      if (valid) {
-        const uint32_t p0 = (uint32_t)fb[u];
-        // cell -> (x, y, z) by multiply-shift division (cells < 2^31)
-        const uint32_t r = fast_div((uint32_t)p, fnx), r0 = fast_div(p0, fnx);
-        const uint32_t zz = fast_div(r, fny), zz0 = fast_div(r0, fny);
-        const int x = (int)((uint32_t)p - r * (uint32_t)nx), y = (int)(r - zz * (uint32_t)ny), z = (int)zz;
-        const int x0 = (int)(p0 - r0 * (uint32_t)nx), y0 = (int)(r0 - zz0 * (uint32_t)ny), z0 = (int)zz0;
-        d[0] = wrapped_delta(x, x0, nx);
-        d[1] = wrapped_delta(y, y0, ny);
-        d[2] = wrapped_delta(z, z0, nz);
-      }
-      uint64_t todo = __ballot(valid);
-      while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const int32_t lv = __shfl(l, leader, 64);
-        const bool mine = valid && l == lv;
-        const uint64_t same = __ballot(mine);
-        int mn[3], mx[3];
-        for (int a = 0; a < 3; ++a) {
-          mn[a] = wave_min(mine ? d[a] : INT32_MAX);
-          mx[a] = wave_max(mine ? d[a] : INT32_MIN);
-        }
-        if (lane == leader) {
-          const int s = table_slot(key, lv);
-          if (s >= 0) {
-            for (int a = 0; a < 3; ++a) {
-              atomicMin(&rec[s][2 * a], mn[a]);
-              atomicMax(&rec[s][2 * a + 1], mx[a]);
-            }
-          } else {
-            int32_t *b = box + 6 * (int64_t)(lv - 1);
-            for (int a = 0; a < 3; ++a) {
-              atomicMin(&b[2 * a], mn[a]);
-              atomicMax(&b[2 * a + 1], mx[a]);
-            }
-          }
-        }
-        todo &= ~same;
-      }
-    }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < kTable; i += kBlock) {
-    const int32_t lv = key[i];
-    if (lv == 0) continue;
-    int32_t *b = box + 6 * (int64_t)(lv - 1);
-    for (int a = 0; a < 3; ++a) {
-      atomicMin(&b[2 * a], rec[i][2 * a]);
-      atomicMax(&b[2 * a + 1], rec[i][2 * a + 1]);
-    }
-  }
-}
-
-__global__ void k_first_init(int32_t *first, int64_t K) {
+__global__ void k_scan_init(int32_t *first, int32_t *frames, int64_t K) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < K) first[i] = INT32_MAX;
+  if (i < kFrames * K) frames[i] = (i & 1) ? INT32_MIN : INT32_MAX;
 }
 
-// First (smallest linear index) cell of every drop; the lowest lane of a
-// wavefront holding a drop has the wavefront's smallest cell of that drop.
-__global__ __launch_bounds__(kBlock) void k_first_min(const int32_t *__restrict__ lab, int64_t n3, int32_t K,
-                                                      int32_t *__restrict__ first) {
+// One drop's record (first cell, frame extents) merged into the workgroup's
+// LDS table, or into the global arrays when the table is full.
+__device__ __forceinline__ void merge_record(int32_t *key, int32_t *rfirst, int32_t (*rec)[kFrames],
+                                             int32_t *first, int32_t *frames, int32_t l, int32_t f,
+                                             const int32_t *e) {
+  const int s = table_slot(key, l);
+  int32_t *pf = (s >= 0) ? &rfirst[s] : &first[l - 1];
+  int32_t *g = (s >= 0) ? &rec[s][0] : &frames[kFrames * (int64_t)(l - 1)];
+  atomicMin(pf, f);
+  for (int k = 0; k < kFrames; k += 2) {
+    atomicMin(&g[k], e[k]);
+    atomicMax(&g[k + 1], e[k + 1]);
+  }
+}
+
+// First cell and the frame extents of every drop.
+__global__ __launch_bounds__(kBlock) void k_drop_scan(const int32_t *__restrict__ lab, int64_t n3, int nx, int ny,
+                                                      int nz, FastDiv fnx, FastDiv fny, int32_t K,
+                                                      int32_t *__restrict__ first, int32_t *__restrict__ frames) {
   __shared__ int32_t key[kTable];
-  __shared__ int32_t rec[kTable];
+  __shared__ int32_t rfirst[kTable];
+  __shared__ int32_t rec[kTable][kFrames];
   for (int i = threadIdx.x; i < kTable; i += kBlock) {
     key[i] = 0;
-    rec[i] = INT32_MAX;
+    rfirst[i] = INT32_MAX;
+    for (int k = 0; k < kFrames; ++k) rec[i][k] = (k & 1) ? INT32_MIN : INT32_MAX;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
+  const int n[3] = {nx, ny, nz};
+  const int h[3] = {nx / 2, ny / 2, nz / 2};
   const int64_t c0 = (int64_t)blockIdx.x * kChunk;
   for (int it0 = 0; it0 < kChunk / kBlock; it0 += kBatch) {
     int32_t lb[kBatch];  // the labels of kBatch positions are loaded together
@@ -463,32 +402,97 @@ __global__ __launch_bounds__(kBlock) void k_first_min(const int32_t *__restrict_
     }
 #pragma unroll 1
     for (int u = 0; u < kBatch; ++u) {
-      const int64_t p = c0 + (int64_t)(it0 + u) * kBlock + threadIdx.x;
+      const int64_t pw = c0 + (int64_t)(it0 + u) * kBlock + (threadIdx.x & ~63);  // the wavefront's first cell
+      const int64_t p = pw + lane;
       const int32_t l = lb[u];
       const bool valid = l > 0 && l <= K;
       uint64_t todo = __ballot(valid);
+      if (!todo) continue;  // wave-uniform
+      // coordinates of this lane's cell and of the wavefront's first cell
+      const uint32_t pc = valid ? (uint32_t)p : (uint32_t)pw;
+      const uint32_t r = fast_div(pc, fnx), zz = fast_div(r, fny);
+      const int c[3] = {(int)(pc - r * (uint32_t)nx), (int)(r - zz * (uint32_t)ny), (int)zz};
+      const uint32_t rw = fast_div((uint32_t)pw, fnx);
+      const uint32_t rl = fast_div((uint32_t)(pw + 63 < n3 ? pw + 63 : n3 - 1), fnx);
+      const bool one_row = (rw == rl);  // wave-uniform: cell x = x of the first cell + lane
+      const int xw = (int)((uint32_t)pw - rw * (uint32_t)nx);
       while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
+        const int leader = __ffsll((unsigned long long)todo) - 1;
         const int32_t lv = __shfl(l, leader, 64);
         const uint64_t same = __ballot(valid && l == lv);
-        if (lane == leader) {
-          const int s = table_slot(key, lv);
-          if (s >= 0) atomicMin(&rec[s], (int32_t)p);
-          else atomicMin(&first[lv - 1], (int32_t)p);
+        int e[kFrames];
+        if (one_row) {
+          // x: the group's lanes in increasing x; frame B cuts at x = nx - nx/2
+          const int lo = leader, hi = 63 - __clzll(same);
+          e[0] = xw + lo;
+          e[1] = xw + hi;
+          const int cut = nx - h[0] - xw;  // first lane with x >= nx - nx/2 (may be outside 0..63)
+          const uint64_t above = (cut <= 0) ? ~0ull : ((cut >= 64) ? 0ull : (~0ull << cut));
+          const uint64_t mhi = same & above, mlo = same & ~above;
+          e[2] = mhi ? xw + (__ffsll((unsigned long long)mhi) - 1) - (nx - h[0]) : xw + lo + h[0];
+          e[3] = mlo ? xw + (63 - __clzll(mlo)) + h[0] : xw + hi - (nx - h[0]);
+          // y and z are those of the row
+          const int yr = __shfl(c[1], leader, 64), zr = __shfl(c[2], leader, 64);
+          e[4] = e[5] = yr;
+          e[6] = e[7] = (yr + h[1] >= ny) ? yr + h[1] - ny : yr + h[1];
+          e[8] = e[9] = zr;
+          e[10] = e[11] = (zr + h[2] >= nz) ? zr + h[2] - nz : zr + h[2];
+        } else {
+          const bool mine = valid && l == lv;
+          for (int a = 0; a < 3; ++a) {
+            const int vb = (c[a] + h[a] >= n[a]) ? c[a] + h[a] - n[a] : c[a] + h[a];
+            e[4 * a] = wave_min(mine ? c[a] : INT32_MAX);
+            e[4 * a + 1] = wave_max(mine ? c[a] : INT32_MIN);
+            e[4 * a + 2] = wave_min(mine ? vb : INT32_MAX);
+            e[4 * a + 3] = wave_max(mine ? vb : INT32_MIN);
+          }
         }
+        if (lane == leader)  // the lowest lane holds the group's first cell
+          merge_record(key, rfirst, rec, first, frames, lv, (int32_t)p, e);
         todo &= ~same;
       }
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kTable; i += kBlock)
-    if (key[i] != 0) atomicMin(&first[key[i] - 1], rec[i]);
+  for (int i = threadIdx.x; i < kTable; i += kBlock) {
+    const int32_t lv = key[i];
+    if (lv == 0) continue;
+    atomicMin(&first[lv - 1], rfirst[i]);
+    int32_t *g = &frames[kFrames * (int64_t)(lv - 1)];
+    for (int k = 0; k < kFrames; k += 2) {
+      atomicMin(&g[k], rec[i][k]);
+      atomicMax(&g[k + 1], rec[i][k + 1]);
+    }
+  }
 }
 
-__global__ void k_box_init(int32_t *box, int64_t K) {
+// Box of every drop from its frames: per axis, the frame with the smaller
+// span, minus p0's coordinate in that frame. A label without cells keeps an
+// empty box (min > max).
+__global__ void k_drop_box(int32_t K, int nx, int ny, int nz, const int32_t *__restrict__ first,
+                           const int32_t *__restrict__ frames, int32_t *__restrict__ box) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 6 * K) return;
-  box[i] = (i & 1) ? INT32_MIN : INT32_MAX;
+  if (i >= K) return;
+  const int32_t p0 = first[i];
+  int32_t *b = box + 6 * i;
+  if (p0 == INT32_MAX) {
+    for (int a = 0; a < 3; ++a) {
+      b[2 * a] = INT32_MAX;
+      b[2 * a + 1] = INT32_MIN;
+    }
+    return;
+  }
+  const int n[3] = {nx, ny, nz};
+  const int r[3] = {p0 % nx, (p0 / nx) % ny, p0 / (nx * ny)};
+  const int32_t *f = frames + kFrames * i;
+  for (int a = 0; a < 3; ++a) {
+    const int h = n[a] / 2;
+    const int spanA = f[4 * a + 1] - f[4 * a], spanB = f[4 * a + 3] - f[4 * a + 2];
+    const int rb = (r[a] + h >= n[a]) ? r[a] + h - n[a] : r[a] + h;
+    const bool useA = spanA <= spanB;
+    b[2 * a] = useA ? f[4 * a] - r[a] : f[4 * a + 2] - rb;
+    b[2 * a + 1] = useA ? f[4 * a + 1] - r[a] : f[4 * a + 3] - rb;
+  }
 }
 
 // kSumSplit workgroups per drop sum c and c*offset over consecutive parts of
@@ -653,7 +657,8 @@ extern "C" int vofmt_drop_moments(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_
   int64_t kmax = 0;
   for (int t = 0; t < ntracers; ++t) kmax = ndrops_host[t] > kmax ? ndrops_host[t] : kmax;
   int32_t *rootpos = (int32_t *)scratch(ctx, SLOT_LABEL_C, sizeof(int32_t) * (size_t)(kmax + 1));
-  int32_t *box = (int32_t *)scratch(ctx, SLOT_MISC2, sizeof(int32_t) * 6 * (size_t)(kmax + 1));
+  int32_t *box = (int32_t *)scratch(ctx, SLOT_MISC2, sizeof(int32_t) * (6 + kFrames) * (size_t)(kmax + 1));
+  int32_t *frames = box ? box + 6 * (kmax + 1) : nullptr;
   int32_t *flags = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * 2);
   double *part = (double *)scratch(ctx, SLOT_LABEL_A, sizeof(double) * 4 * kSumSplit * (size_t)(kmax + 1));
   int32_t *fh = (int32_t *)host_scratch(ctx, sizeof(int32_t) * 2);
@@ -666,11 +671,11 @@ extern "C" int vofmt_drop_moments(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_
     const int32_t K = ndrops_host[t];
     if (K == 0) continue;
     const int32_t *lab = labels + (int64_t)t * n3;
-    hipLaunchKernelGGL(k_first_init, dim3(ceil_div(K, 256)), dim3(256), 0, stream, rootpos, (int64_t)K);
-    hipLaunchKernelGGL(k_first_min, dim3(nbc), dim3(kBlock), 0, stream, lab, n3, K, rootpos);
-    hipLaunchKernelGGL(k_box_init, dim3(ceil_div(6 * (int64_t)K, 256)), dim3(256), 0, stream, box, (int64_t)K);
-    hipLaunchKernelGGL(k_drop_bbox, dim3(nbc), dim3(kBlock), 0, stream, lab, n3, nx, ny, nz, fnx, fny, K, rootpos,
-                       box);
+    hipLaunchKernelGGL(k_scan_init, dim3(ceil_div(kFrames * (int64_t)K, 256)), dim3(256), 0, stream, rootpos, frames,
+                       (int64_t)K);
+    hipLaunchKernelGGL(k_drop_scan, dim3(nbc), dim3(kBlock), 0, stream, lab, n3, nx, ny, nz, fnx, fny, K, rootpos,
+                       frames);
+    hipLaunchKernelGGL(k_drop_box, dim3(ceil_div(K, 256)), dim3(256), 0, stream, K, nx, ny, nz, rootpos, frames, box);
     hipLaunchKernelGGL(k_drop_sums, dim3((unsigned)(K * kSumSplit)), dim3(kBlock), 0, stream, c + (int64_t)t * n3, lab,
                        nx, ny, nz, rootpos, box, part, flags);
     hipLaunchKernelGGL(k_drop_finish, dim3(ceil_div(K, 256)), dim3(256), 0, stream, K, nx, ny, nz, rootpos, box, part,
