@@ -27,6 +27,16 @@
 //   row layout, and every new mixed cell is appended to the list of the next
 //   sweep.
 //
+// Stores of unchanged values are skipped. The fields alternate between two
+// buffers, so a sweep's output buffer holds the field of two sweeps before;
+// a cell needs a store only where its value changed in this sweep or in the
+// previous one, which the sweeps record as one bit per cell (a 64-bit ballot
+// word per row segment, the layout of the c > 0.5 bits). Away from the
+// interfaces nearly every value is unchanged (empty cells stay 0, most full
+// cells give exactly 1 again), so most row segments are not stored at all.
+// The first sweep of a call stores every cell (its output buffer holds no
+// field yet).
+//
 // The list is cut into regions of rsize entries, one per wavefront of the
 // pass that fills it, each large enough for every cell that wavefront handles
 // (64 * chunk * G): entries are written without atomics, in a fixed order,
@@ -170,8 +180,10 @@ __device__ __forceinline__ void plic_body(const double *__restrict__ cin, const 
 template <int D, int G, int WPB = 4>
 __device__ __forceinline__ void stream_body(const double *__restrict__ cin, double *__restrict__ cout,
                                             const double *__restrict__ s, const double *__restrict__ fmix,
-                                            uint64_t *__restrict__ ccbits, int write_cc, int t0, int nx, int ny,
-                                            int nz, int words, int chunk, uint32_t *__restrict__ list_next,
+                                            uint64_t *__restrict__ ccbits, int write_cc,
+                                            const uint64_t *__restrict__ chg_prev, uint64_t *__restrict__ chg_cur,
+                                            int t0, int nx, int ny, int nz, int words, int chunk,
+                                            uint32_t *__restrict__ list_next,
                                             int *__restrict__ counts_next, int64_t region0, int rsize, int bx, int by,
                                             int bz, int gx, int gy) {
   const int lane = threadIdx.x & 63;
@@ -207,6 +219,12 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
   double *o_g = cout + (int64_t)t0 * n3;
   const double *f_g = fmix + (int64_t)t0 * n3;
   uint64_t *b_g = ccbits + (int64_t)t0 * nbits;
+  // changed-cell bits: of the previous sweep (null: store every cell) and of
+  // this one (null: not recorded). The x-sweep stores every cell (its
+  // per-position barrier leaves no room to wait for the extra words) and
+  // only records its changes.
+  const uint64_t *chp_g = (D != 0 && chg_prev) ? chg_prev + (int64_t)t0 * nbits : nullptr;
+  uint64_t *chc_g = chg_cur ? chg_cur + (int64_t)t0 * nbits : nullptr;
 
   auto cell = [&](int xx, int mm) -> int64_t {
     if (D == 1) return ((int64_t)row * ny + mm) * nx + xx;
@@ -225,19 +243,37 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
     if (mixed) fv = f_g[t * n3 + pu];
     return mixed ? fv : ((sv == 0.0) ? 0.0 : sv * cd);
   };
+  // the bit words of row word wrow that finish() reads: the c_c bits (unless
+  // this sweep writes them) and the previous sweep's changed cells; loaded
+  // ahead of their use so their latency overlaps other work
+  auto load_words = [&](int64_t wrow, uint64_t *ccw, uint64_t *chw) {
+    const bool ok = tile_ok && seg < words;  // idle: no cells
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+      ccw[t] = (!write_cc && ok) ? b_g[t * nbits + wrow] : 0ull;
+      chw[t] = (chp_g && ok) ? chp_g[t * nbits + wrow] : 0ull;
+    }
+  };
   // new value of cell pc, its c_c bit, and its entry in the next list
-  auto finish = [&](int t, double cold, double f_lo, double f_hi, double s_lo, double s_hi, int64_t pc, int64_t wrow) {
+  auto finish = [&](int t, double cold, double f_lo, double f_hi, double s_lo, double s_hi, int64_t pc, int64_t wrow,
+                    uint64_t ccw, uint64_t chw) {
     double ccv;
     if (write_cc) {
       const uint64_t word = __ballot(live && cold > 0.5);
       if (lane == 0 && tile_ok && seg < words) b_g[t * nbits + wrow] = word;
       ccv = (cold > 0.5) ? 1.0 : 0.0;
     } else {
-      const uint64_t word = (tile_ok && seg < words) ? b_g[t * nbits + wrow] : 0ull;  // idle: no cells
-      ccv = ((word >> lane) & 1ull) ? 1.0 : 0.0;
+      ccv = ((ccw >> lane) & 1ull) ? 1.0 : 0.0;
     }
     const double cn = (cold - (f_hi - f_lo)) + ccv * (s_hi - s_lo);
-    if (live) o_g[t * n3 + pc] = cn;
+    bool store = live;
+    if (chc_g) {
+      const bool chg = live && (__double_as_longlong(cn) != __double_as_longlong(cold));
+      const uint64_t word = __ballot(chg);
+      if (lane == 0 && tile_ok && seg < words) chc_g[t * nbits + wrow] = word;
+      if (chp_g) store = chg || (live && ((chw >> lane) & 1ull));
+    }
+    if (store) o_g[t * n3 + pc] = cn;
     const bool mixed = live && cn > 0.0 && cn < 1.0;
     const uint64_t mask = __ballot(mixed);
     if (mixed) reg[nlist + __popcll(mask & below)] = (uint32_t)((int64_t)(t0 + t) * n3 + pc);
@@ -262,20 +298,44 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
 #pragma unroll
       for (int t = 0; t < G; ++t) flo[t] = flux(t, s0, cl[t], cm[t], p0);
     }
+    // the upper cell's values, and the bit words of the cell finished next,
+    // are loaded one position ahead, so their latency overlaps the previous
+    // position's flux work and stores
+    double s_nx = 0.0, c_nx[G];
+    uint64_t ccw[G], chw[G];
+    if (m0 + 1 <= m1) {
+      const int64_t pu = cell(xs, (m0 + 1 == nm) ? 0 : m0 + 1);
+      s_nx = s[pu];
+#pragma unroll
+      for (int t = 0; t < G; ++t) c_nx[t] = c_g[t * n3 + pu];
+    }
+    load_words(bitword(m0), ccw, chw);
     for (int m = m0 + 1; m <= m1; ++m) {
       const int mm = (m == nm) ? 0 : m;
       const int64_t pu = cell(xs, mm);
       const int64_t pc = cell(xs, m - 1);
       const int64_t wrow = bitword(m - 1);
-      const double s_hi = s[pu];
+      const double s_hi = s_nx;
       double cu[G], fhi[G];
+      uint64_t ccc[G], chc[G];
 #pragma unroll
-      for (int t = 0; t < G; ++t) cu[t] = c_g[t * n3 + pu];
+      for (int t = 0; t < G; ++t) {
+        cu[t] = c_nx[t];
+        ccc[t] = ccw[t];
+        chc[t] = chw[t];
+      }
+      if (m + 1 <= m1) {
+        const int64_t pn = cell(xs, (m + 1 == nm) ? 0 : m + 1);
+        s_nx = s[pn];
+#pragma unroll
+        for (int t = 0; t < G; ++t) c_nx[t] = c_g[t * n3 + pn];
+        load_words(bitword(m), ccw, chw);
+      }
 #pragma unroll
       for (int t = 0; t < G; ++t) fhi[t] = flux(t, s_hi, cm[t], cu[t], pu);
 #pragma unroll
       for (int t = 0; t < G; ++t) {
-        finish(t, cm[t], flo[t], fhi[t], s_lo, s_hi, pc, wrow);
+        finish(t, cm[t], flo[t], fhi[t], s_lo, s_hi, pc, wrow, ccc[t], chc[t]);
         flo[t] = fhi[t];
         cm[t] = cu[t];
       }
@@ -365,7 +425,10 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
         fhi[t] = flux(t, s_hi, c0[t], cr[t], pr);
       }
 #pragma unroll
-      for (int t = 0; t < G; ++t) finish(t, c0[t], flo[t], fhi[t], s_lo, s_hi, pc, wrow);
+      for (int t = 0; t < G; ++t) {
+        const uint64_t ccw = (!write_cc && tile_ok && seg < words) ? b_g[t * nbits + wrow] : 0ull;
+        finish(t, c0[t], flo[t], fhi[t], s_lo, s_hi, pc, wrow, ccw, 0ull);
+      }
     }
   }
   if (lane == 0) counts_next[wave] = nlist;
