@@ -41,6 +41,20 @@ __global__ __launch_bounds__(64 * kXWaves) void k_stream(const double *__restric
                              counts_next, region0, rsize, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gridDim.y);
 }
 
+// The x-sweep marching along whole rows (4 wavefronts per workgroup).
+template <int G>
+__global__ __launch_bounds__(256) void k_stream_rows(const double *__restrict__ cin, double *__restrict__ cout,
+                                                     const double *__restrict__ s, const double *__restrict__ fmix,
+                                                     uint64_t *__restrict__ ccbits, int write_cc,
+                                                     const uint64_t *__restrict__ chg_prev,
+                                                     uint64_t *__restrict__ chg_cur, int t0, int nx, int ny, int nz,
+                                                     int words, int chunk, uint32_t *__restrict__ list_next,
+                                                     int *__restrict__ counts_next, int64_t region0, int rsize) {
+  stream_body<0, G, 0>(cin, cout, s, fmix, ccbits, write_cc, chg_prev, chg_cur, t0, nx, ny, nz, words, chunk,
+                       list_next, counts_next, region0, rsize, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x,
+                       gridDim.y);
+}
+
 template <int A>
 __global__ __launch_bounds__(256) void k_scan_pair(const double *__restrict__ c, const double *__restrict__ sA,
                                                    int64_t total, int nx, int ny, int nz, Divisors dv,
@@ -119,16 +133,27 @@ static const char *stream_name(int d, int g) {
   return names[d][g == 4 ? 2 : (g == 2 ? 1 : 0)];
 }
 
+// Workgroup layout of the x-sweep: whole-row wavefronts (0) when a row has at
+// most `chunk` segments (so a wavefront's cells fit its list region), else
+// kXWaves wavefronts sharing segment ends through LDS.
+static inline int x_wpb(int words, int chunk) { return words <= chunk ? 0 : kXWaves; }
+
 template <int D, int G>
 static void launch_stream(vofmt_ctx *ctx, const double *cin, double *cout, const double *s, SweepBuffers &sb, int wcc,
                           int t0, int nx, int ny, int nz, int words, int chunk, int nxt, int64_t region0,
                           hipStream_t stream) {
-  const Tiles tg = stream_tiles(D, nx, ny, nz, chunk, kXWaves);
+  const int wpb = (D == 0) ? x_wpb(words, chunk) : 4;
+  const Tiles tg = stream_tiles(D, nx, ny, nz, chunk, wpb);
   dim3 grid(tg.gx, tg.gy, tg.gz);
   const int rec = prof_begin(ctx, stream_name(D, G), stream);
-  hipLaunchKernelGGL((k_stream<D, G>), grid, dim3(D == 0 ? 64 * kXWaves : 256), 0, stream, cin, cout, s, sb.fmix,
-                     sb.bits, wcc, sb.chg_prev, sb.chg_cur, t0, nx, ny, nz, words, chunk, sb.list[nxt],
-                     sb.counts[nxt], region0, sb.rsize);
+  if (D == 0 && wpb == 0)
+    hipLaunchKernelGGL((k_stream_rows<G>), grid, dim3(256), 0, stream, cin, cout, s, sb.fmix, sb.bits, wcc,
+                       sb.chg_prev, sb.chg_cur, t0, nx, ny, nz, words, chunk, sb.list[nxt], sb.counts[nxt], region0,
+                       sb.rsize);
+  else
+    hipLaunchKernelGGL((k_stream<D, G>), grid, dim3(D == 0 ? 64 * kXWaves : 256), 0, stream, cin, cout, s,
+                       sb.fmix, sb.bits, wcc, sb.chg_prev, sb.chg_cur, t0, nx, ny, nz, words, chunk, sb.list[nxt],
+                       sb.counts[nxt], region0, sb.rsize);
   prof_end(ctx, rec, stream);
 }
 
@@ -147,7 +172,7 @@ static void launch_sweep_axis(vofmt_ctx *ctx, const double *cin, double *cout, c
   hipLaunchKernelGGL((k_plic<D>), dim3(ceil_div(nreg, 4)), dim3(256), 0, stream, cin, s, sb.list[cur],
                      sb.counts[cur], nreg, sb.rsize, sb.fmix, nx, ny, nz, dv);
   prof_end(ctx, rec, stream);
-  const int64_t per = stream_waves(D, nx, ny, nz, chunk, kXWaves);
+  const int64_t per = stream_waves(D, nx, ny, nz, chunk, D == 0 ? x_wpb(words, chunk) : 4);
   int64_t region0 = 0;
   int t = 0;
   while (t < ntr) {
@@ -293,7 +318,7 @@ static int advect_paired(vofmt_ctx *ctx, int nx, int ny, int nz, int ntr, double
   static_assert(2 * 64 * kPairTZ <= 64 * kChunk * kMaxGroup, "paired list regions");
   const int64_t nblocks = pair_blocks(nx, ny, nz, ntr);
   if (4 * nblocks > INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "vofmt_advect: grid too large");
-  int64_t maxreg = max_regions(nx, ny, nz, ntr, kChunk, kXWaves);
+  int64_t maxreg = max_regions(nx, ny, nz, ntr, kChunk, x_wpb((int)ceil_div(nx, 64), kChunk));
   if (4 * nblocks > maxreg) maxreg = 4 * nblocks;
   const int64_t scanreg = (total + rsize - 1) / rsize;
   const size_t field_bytes = sizeof(double) * (size_t)total;
@@ -410,7 +435,7 @@ extern "C" int vofmt_advect(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, 
   uint64_t *chg = (uint64_t *)scratch(ctx, SLOT_CHGBITS, sizeof(uint64_t) * 2 * nbt);
   // list regions: enough for the largest sweep launch set and for the initial scan
   const int rsize = region_size(kChunk);
-  const int64_t maxreg = max_regions(nx, ny, nz, ntracers, kChunk, kXWaves);
+  const int64_t maxreg = max_regions(nx, ny, nz, ntracers, kChunk, x_wpb(words, kChunk));
   const int64_t total = (int64_t)ntracers * n3;
   const int64_t scanreg = (total + rsize - 1) / rsize;
   uint32_t *lists = (uint32_t *)scratch(ctx, SLOT_MIXLIST, sizeof(uint32_t) * 2 * (size_t)maxreg * rsize);

@@ -52,7 +52,10 @@ constexpr int kMaxGroup = 4;  // tracers per streaming pass (register budget)
 
 // Workgroup grid of a streaming pass (4 wavefronts per workgroup, or wpb
 // for the x-sweep).
-//   d = 0: a workgroup takes rpb y-rows of spw consecutive 64-cell
+//   d = 0, wpb = 0 (whole rows): a wavefront takes one y-row and P =
+//          max(1, chunk / segments per row) positions along z; gx = 1,
+//          gy = groups of 4 rows, gz = groups of P positions;
+//   d = 0, wpb > 0: a workgroup takes rpb y-rows of spw consecutive 64-cell
 //          x-segments each (spw = min(segments per row, wpb), rpb = wpb/spw);
 //          gx = chunks of spw segments, gy = groups of rpb rows, gz = chunks
 //          of z.
@@ -62,8 +65,13 @@ struct Tiles {
   int gx, gy, gz;
 };
 __host__ __device__ inline int x_segments_per_row(int words, int wpb) { return words < wpb ? words : wpb; }
+__host__ __device__ inline int x_row_positions(int words, int chunk) { return chunk / words > 0 ? chunk / words : 1; }
 __host__ __device__ inline Tiles stream_tiles(int d, int nx, int ny, int nz, int chunk, int wpb = 4) {
   const int words = (nx + 63) / 64;
+  if (d == 0 && wpb == 0) {
+    const int P = x_row_positions(words, chunk);
+    return Tiles{1, (ny + 3) / 4, (nz + P - 1) / P};
+  }
   if (d == 0) {
     const int spw = x_segments_per_row(words, wpb), rpb = wpb / spw;
     return Tiles{(words + spw - 1) / spw, (ny + rpb - 1) / rpb, (nz + chunk - 1) / chunk};
@@ -175,6 +183,24 @@ __device__ __forceinline__ void plic_body(const double *__restrict__ cin, const 
   }
 }
 
+// Lane i receives lane i-1's value (lane 0 keeps its own): a DPP wave shift
+// right by one lane on each 32-bit half (all lanes active).
+__device__ __forceinline__ double from_lane_below(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = (int)b, hi = (int)(b >> 32);
+  const int rlo = __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false);
+  const int rhi = __builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)rhi << 32) | (long long)(unsigned)rlo);
+}
+// Lane i receives lane i+1's value (lane 63 keeps its own): wave shift left.
+__device__ __forceinline__ double from_lane_above(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = (int)b, hi = (int)(b >> 32);
+  const int rlo = __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false);
+  const int rhi = __builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)rhi << 32) | (long long)(unsigned)rlo);
+}
+
 // Tile (bx, by, bz) of a streaming pass laid out as a gx x gy x gz grid of
 // workgroups (stream_tiles): 4 wavefronts, or WPB for the x-sweep.
 template <int D, int G, int WPB = 4>
@@ -189,41 +215,44 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
   const int lane = threadIdx.x & 63;
   // wavefront-uniform: kept in a scalar register, like everything derived from it
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // x-sweep: wavefront wv takes segment 4*bx + wv of row by; others: 64-cell segment bx of row 4*by + wv
-  constexpr int W = (D == 0) ? WPB : 4;  // wavefronts per workgroup
-  // x-sweep: wavefront wv takes segment bx*spw + sw of row by*rpb + rr
-  const int spw = (D == 0) ? x_segments_per_row(words, W) : 1;
-  const int rpb = (D == 0) ? W / spw : 1;
+  // x-sweep with WPB = 0: the wavefront marches along whole rows (row 4*by + wv)
+  constexpr bool ROWS = (D == 0 && WPB == 0);
+  constexpr int W = (D == 0 && !ROWS) ? WPB : 4;  // wavefronts per workgroup
+  // x-sweep (WPB > 0): wavefront wv takes segment bx*spw + sw of row by*rpb + rr;
+  // others: 64-cell segment bx of row 4*by + wv
+  const int spw = (D == 0 && !ROWS) ? x_segments_per_row(words, W) : 1;
+  const int rpb = (D == 0 && !ROWS) ? W / spw : 1;
   const int rr = wv / spw, sw = wv % spw;
-  const bool tile_ok = (D != 0) || (rr < rpb && by * rpb + rr < ny && bx * spw + sw < words);
-  const int seg = (D == 0) ? bx * spw + sw : bx;
-  const int x = seg * 64 + lane;
-  const int row = (D == 0) ? ((by * rpb + rr < ny) ? by * rpb + rr : ny - 1) : by * 4 + wv;
+  const bool tile_ok = (D != 0 || ROWS) || (rr < rpb && by * rpb + rr < ny && bx * spw + sw < words);
+  int seg = (D == 0 && !ROWS) ? bx * spw + sw : bx;  // the whole-row march moves it along the row
+  int x = seg * 64 + lane;
+  const int row = (D == 0 && !ROWS) ? ((by * rpb + rr < ny) ? by * rpb + rr : ny - 1) : by * 4 + wv;
   const int nrow = (D == 1) ? nz : ny;
   const int nm = (D == 1) ? ny : nz;
   const int64_t wave = region0 + (((int64_t)bz * gy + by) * gx + bx) * W + wv;
-  if (D != 0 && row >= nrow) {  // whole wavefront (the x-sweep keeps every wavefront for its barriers)
+  if ((D != 0 || ROWS) && row >= nrow) {  // whole wavefront (the LDS x-sweep keeps every wavefront for its barriers)
     if (lane == 0) counts_next[wave] = 0;
     return;
   }
   uint32_t *reg = list_next + wave * rsize;
   int nlist = 0;  // wavefront-uniform
   const uint64_t below = (1ull << lane) - 1;
-  const bool live = tile_ok && x < nx;  // (an idle x-sweep wavefront has no live lane)
-  const int xs = live ? x : nx - 1;  // dead lanes shadow a valid cell, never store
+  bool live = tile_ok && x < nx;  // (an idle x-sweep wavefront has no live lane)
+  int xs = live ? x : nx - 1;  // dead lanes shadow a valid cell, never store
   const int64_t n3 = (int64_t)nx * ny * nz;
   const int64_t nbits = (int64_t)nz * ny * words;
-  const int m0 = bz * chunk;
-  const int m1 = (m0 + chunk < nm) ? m0 + chunk : nm;
+  const int mchunk = ROWS ? x_row_positions(words, chunk) : chunk;  // positions of this wavefront
+  const int m0 = bz * mchunk;
+  const int m1 = (m0 + mchunk < nm) ? m0 + mchunk : nm;
   const double *c_g = cin + (int64_t)t0 * n3;
   double *o_g = cout + (int64_t)t0 * n3;
   const double *f_g = fmix + (int64_t)t0 * n3;
   uint64_t *b_g = ccbits + (int64_t)t0 * nbits;
   // changed-cell bits: of the previous sweep (null: store every cell) and of
-  // this one (null: not recorded). The x-sweep stores every cell (its
+  // this one (null: not recorded). The LDS x-sweep stores every cell (its
   // per-position barrier leaves no room to wait for the extra words) and
   // only records its changes.
-  const uint64_t *chp_g = (D != 0 && chg_prev) ? chg_prev + (int64_t)t0 * nbits : nullptr;
+  const uint64_t *chp_g = ((D != 0 || ROWS) && chg_prev) ? chg_prev + (int64_t)t0 * nbits : nullptr;
   uint64_t *chc_g = chg_cur ? chg_cur + (int64_t)t0 * nbits : nullptr;
 
   auto cell = [&](int xx, int mm) -> int64_t {
@@ -280,7 +309,7 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
     nlist += __popcll(mask);
   };
 
-  if (D != 0) {
+  if constexpr (D != 0) {
     // ---- march along the sweep axis: faces m0..m1, cells m0..m1-1
     const int ml = (m0 == 0) ? nm - 1 : m0 - 1;
     double cm[G], flo[G];
@@ -340,6 +369,114 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
         cm[t] = cu[t];
       }
       s_lo = s_hi;
+    }
+  } else if constexpr (ROWS) {
+    // ---- x-sweep along whole rows: the wavefront takes its row's 64-cell
+    // segments in order, position after position (z-planes m0..m1-1). Lanes
+    // take their neighbours inside a segment by wave shifts; lane 0 takes the
+    // previous segment's last cell, the last cell the next segment's first,
+    // and the row closes periodically through its first and last cells. The
+    // next step's values, the last cell of its row and its bit words are
+    // loaded one step ahead. No barrier, no LDS: the wavefront skips the
+    // stores of unchanged values like the y- and z-sweeps.
+    auto readlane_d = [](double v, int l) {
+      const long long b = __double_as_longlong(v);
+      const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+      return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+    };
+    // values of (position mm, segment sk): lanes past the row's end shadow its last cell
+    auto load_step = [&](int mm, int sk, double *cv, double &sv) {
+      const int xk = sk * 64 + lane;
+      const int64_t p = ((int64_t)mm * ny + row) * nx + ((xk < nx) ? xk : nx - 1);
+      sv = s[p];
+#pragma unroll
+      for (int t = 0; t < G; ++t) cv[t] = c_g[t * n3 + p];
+    };
+    auto load_last = [&](int mm, double *cv) {
+      const int64_t p = ((int64_t)mm * ny + row) * nx + (nx - 1);
+#pragma unroll
+      for (int t = 0; t < G; ++t) cv[t] = c_g[t * n3 + p];
+    };
+    auto words_of = [&](int mm, int sk, uint64_t *ccw, uint64_t *chw) {
+      const int64_t w = ((int64_t)mm * ny + row) * words + sk;
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        ccw[t] = write_cc ? 0ull : b_g[t * nbits + w];
+        chw[t] = chp_g ? chp_g[t * nbits + w] : 0ull;
+      }
+    };
+    double c_cur[G], c_nxt[G], c_lst[G], c_lst_nxt[G], c_fst[G], c_prv[G];
+    double s_cur = 0.0, s_nxt = 0.0, s_fst = 0.0;
+    uint64_t ccw[G], chw[G], ccw_nxt[G], chw_nxt[G];
+#pragma unroll
+    for (int t = 0; t < G; ++t) c_prv[t] = c_fst[t] = 0.0;
+    if (m0 < m1) {
+      load_step(m0, 0, c_cur, s_cur);
+      load_last(m0, c_lst);
+      words_of(m0, 0, ccw, chw);
+    }
+    int mk = m0, sk = 0;
+    const int nk = (m1 - m0) * words;
+    for (int k = 0; k < nk; ++k) {
+      int mn = mk, sn = sk + 1;
+      if (sn == words) {
+        sn = 0;
+        mn = mk + 1;
+      }
+      if (mn < m1) {
+        load_step(mn, sn, c_nxt, s_nxt);
+        if (sn == 0) load_last(mn, c_lst_nxt);
+        words_of(mn, sn, ccw_nxt, chw_nxt);
+      }
+      seg = sk;
+      x = sk * 64 + lane;
+      live = x < nx;
+      xs = live ? x : nx - 1;
+      const int last = (sk == words - 1) ? (nx - 1) - 64 * sk : 63;  // the segment's last live lane
+      const bool at_end = (lane == last);
+      const bool row_end = (sk == words - 1);
+      if (sk == 0) {  // the row's first cell closes it at its end
+#pragma unroll
+        for (int t = 0; t < G; ++t) c_fst[t] = readlane_d(c_cur[t], 0);
+        s_fst = readlane_d(s_cur, 0);
+      }
+      const int64_t rb = ((int64_t)mk * ny + row) * nx;
+      const int64_t pc = rb + xs;
+      const int64_t pr = (xs == nx - 1) ? rb : pc + 1;
+      const int64_t wrow = ((int64_t)mk * ny + row) * words + sk;
+      const double s_lo = s_cur;
+      const double s_dn = from_lane_above(s_cur);
+      const double s_end = row_end ? s_fst : readlane_d(s_nxt, 0);
+      const double s_hi = at_end ? s_end : s_dn;
+      double cl[G], cr[G], flo[G], fhi[G];
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        const double up = from_lane_below(c_cur[t]);
+        const double dn = from_lane_above(c_cur[t]);
+        const double beg = (sk == 0) ? c_lst[t] : c_prv[t];
+        const double end = row_end ? c_fst[t] : readlane_d(c_nxt[t], 0);
+        cl[t] = (lane == 0) ? beg : up;
+        cr[t] = at_end ? end : dn;
+      }
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        flo[t] = flux(t, s_lo, cl[t], c_cur[t], pc);
+        fhi[t] = flux(t, s_hi, c_cur[t], cr[t], pr);
+      }
+#pragma unroll
+      for (int t = 0; t < G; ++t) finish(t, c_cur[t], flo[t], fhi[t], s_lo, s_hi, pc, wrow, ccw[t], chw[t]);
+      // carry to the next step
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        c_prv[t] = readlane_d(c_cur[t], 63);
+        c_cur[t] = c_nxt[t];
+        ccw[t] = ccw_nxt[t];
+        chw[t] = chw_nxt[t];
+        if (sn == 0) c_lst[t] = c_lst_nxt[t];
+      }
+      s_cur = s_nxt;
+      mk = mn;
+      sk = sn;
     }
   } else {
     // ---- x-sweep: positions are z-planes; faces along x inside the row.
@@ -439,7 +576,7 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
 // Wavefronts of one streaming pass along axis d (each owns one list region).
 static inline int64_t stream_waves(int d, int nx, int ny, int nz, int chunk, int wpb = 4) {
   const Tiles g = stream_tiles(d, nx, ny, nz, chunk, wpb);
-  return (d == 0 ? wpb : 4) * (int64_t)g.gx * g.gy * g.gz;
+  return ((d == 0 && wpb > 0) ? wpb : 4) * (int64_t)g.gx * g.gy * g.gz;
 }
 
 // Tracer groups of one sweep: kMaxGroup tracers at a time, then groups of
