@@ -37,6 +37,12 @@
 // The first sweep of a call stores every cell (its output buffer holds no
 // field yet).
 //
+// Loads of pure segments are skipped too: every sweep records, per tracer
+// and row segment, whether all its new values are exactly +0.0 or exactly
+// 1.0 (a byte per segment). The next sweep takes those values from the flag
+// instead of memory; the flag is uniform over the wavefront, so the whole
+// load is skipped. Away from the drops most segments are empty.
+//
 // The list is cut into regions of rsize entries, one per wavefront of the
 // pass that fills it, each large enough for every cell that wavefront handles
 // (64 * chunk * G): entries are written without atomics, in a fixed order,
@@ -208,7 +214,8 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
                                             const double *__restrict__ s, const double *__restrict__ fmix,
                                             uint64_t *__restrict__ ccbits, int write_cc,
                                             const uint64_t *__restrict__ chg_prev, uint64_t *__restrict__ chg_cur,
-                                            int t0, int nx, int ny, int nz, int words, int chunk,
+                                            const uint8_t *__restrict__ pure_prev, uint8_t *__restrict__ pure_cur,
+                                            int ntp, int t0, int nx, int ny, int nz, int words, int chunk,
                                             uint32_t *__restrict__ list_next,
                                             int *__restrict__ counts_next, int64_t region0, int rsize, int bx, int by,
                                             int bz, int gx, int gy) {
@@ -254,6 +261,36 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
   // only records its changes.
   const uint64_t *chp_g = ((D != 0 || ROWS) && chg_prev) ? chg_prev + (int64_t)t0 * nbits : nullptr;
   uint64_t *chc_g = chg_cur ? chg_cur + (int64_t)t0 * nbits : nullptr;
+  // purity flags (0: other, 1: all +0.0, 2: all 1.0) of the input field (null:
+  // unknown, every value is loaded) and of the output field (null: not
+  // recorded), one byte per tracer laid out [row word][tracer] with ntp
+  // tracers per word (the tracer count rounded up to 4): a group's flags
+  // are adjacent and move as one 1-, 2- or 4-byte word
+  const uint8_t *pur_in = (D != 0 && pure_prev) ? pure_prev + t0 : nullptr;
+  uint8_t *pur_out = pure_cur ? pure_cur + t0 : nullptr;
+  static_assert(G == 1 || G == 2 || G == 4, "flag words of 1, 2 or 4 bytes");
+  auto flags_at = [&](const uint8_t *base) -> uint32_t {
+    if (G == 4) return *reinterpret_cast<const uint32_t *>(base);
+    if (G == 2) return *reinterpret_cast<const uint16_t *>(base);
+    return *base;
+  };
+  uint32_t gflags = 0;  // this row word's flags, byte t for tracer t
+  auto store_flags = [&](int64_t wrow) {
+    if (pur_out && lane == 0 && tile_ok && seg < words) {
+      uint8_t *dst = pur_out + wrow * ntp;
+      if (G == 4) *reinterpret_cast<uint32_t *>(dst) = gflags;
+      else if (G == 2) *reinterpret_cast<uint16_t *>(dst) = (uint16_t)gflags;
+      else *dst = (uint8_t)gflags;
+    }
+    gflags = 0;
+  };
+  // value of tracer t at cell p of a segment with flag f (f is wave-uniform)
+  auto c_at = [&](int t, int64_t p, int f) -> double {
+    double v;
+    if (f == 0) v = c_g[t * n3 + p];
+    else v = (f == 1) ? 0.0 : 1.0;
+    return v;
+  };
 
   auto cell = [&](int xx, int mm) -> int64_t {
     if (D == 1) return ((int64_t)row * ny + mm) * nx + xx;
@@ -303,6 +340,12 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
       if (chp_g) store = chg || (live && ((chw >> lane) & 1ull));
     }
     if (store) o_g[t * n3 + pc] = cn;
+    if (pur_out) {
+      const long long bits = __double_as_longlong(cn);
+      const uint64_t zero = __ballot(!live || bits == 0ll);
+      const uint64_t one = __ballot(!live || bits == 0x3FF0000000000000ll);
+      gflags |= (uint32_t)((zero == ~0ull) ? 1 : ((one == ~0ull) ? 2 : 0)) << (8 * t);
+    }
     const bool mixed = live && cn > 0.0 && cn < 1.0;
     const uint64_t mask = __ballot(mixed);
     if (mixed) reg[nlist + __popcll(mask & below)] = (uint32_t)((int64_t)(t0 + t) * n3 + pc);
@@ -312,6 +355,16 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
   if constexpr (D != 0) {
     // ---- march along the sweep axis: faces m0..m1, cells m0..m1-1
     const int ml = (m0 == 0) ? nm - 1 : m0 - 1;
+    // purity flags of positions m0-1 .. m1 (wrapped): lane L holds m0 - 1 + L
+    int fl = 0;
+    {
+      int pos = m0 - 1 + lane;
+      pos += (pos < 0) ? nm : ((pos >= nm) ? -nm : 0);
+      if (pur_in && lane <= m1 - m0 + 1) fl = (int)flags_at(pur_in + bitword(pos) * ntp);
+    }
+    auto pure_at = [&](int t, int m) -> int {
+      return (__builtin_amdgcn_readlane(fl, m - (m0 - 1)) >> (8 * t)) & 0xff;
+    };
     double cm[G], flo[G];
     const int64_t p0 = cell(xs, m0);
     const double s0 = s[p0];
@@ -321,8 +374,8 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
       double cl[G];
 #pragma unroll
       for (int t = 0; t < G; ++t) {
-        cl[t] = c_g[t * n3 + pl];
-        cm[t] = c_g[t * n3 + p0];
+        cl[t] = c_at(t, pl, pure_at(t, m0 - 1));
+        cm[t] = c_at(t, p0, pure_at(t, m0));
       }
 #pragma unroll
       for (int t = 0; t < G; ++t) flo[t] = flux(t, s0, cl[t], cm[t], p0);
@@ -336,7 +389,7 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
       const int64_t pu = cell(xs, (m0 + 1 == nm) ? 0 : m0 + 1);
       s_nx = s[pu];
 #pragma unroll
-      for (int t = 0; t < G; ++t) c_nx[t] = c_g[t * n3 + pu];
+      for (int t = 0; t < G; ++t) c_nx[t] = c_at(t, pu, pure_at(t, m0 + 1));
     }
     load_words(bitword(m0), ccw, chw);
     for (int m = m0 + 1; m <= m1; ++m) {
@@ -357,7 +410,7 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
         const int64_t pn = cell(xs, (m + 1 == nm) ? 0 : m + 1);
         s_nx = s[pn];
 #pragma unroll
-        for (int t = 0; t < G; ++t) c_nx[t] = c_g[t * n3 + pn];
+        for (int t = 0; t < G; ++t) c_nx[t] = c_at(t, pn, pure_at(t, m + 1));
         load_words(bitword(m), ccw, chw);
       }
 #pragma unroll
@@ -368,6 +421,7 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
         flo[t] = fhi[t];
         cm[t] = cu[t];
       }
+      store_flags(wrow);
       s_lo = s_hi;
     }
   } else if constexpr (ROWS) {
@@ -385,17 +439,28 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
       return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
     };
     // values of (position mm, segment sk): lanes past the row's end shadow its last cell
+    // the wavefront's steps k = (position - m0) * words + segment: at most
+    // `chunk` of them (the x_row_positions rule), so lane k holds the
+    // purity flags of step k
+    const int nk = (m1 - m0) * words;
+    int fl = 0;
+    if (pur_in && lane < nk) {
+      const int pm = m0 + lane / words, ps = lane - (lane / words) * words;
+      fl = (int)flags_at(pur_in + (((int64_t)pm * ny + row) * words + ps) * ntp);
+    }
     auto load_step = [&](int mm, int sk, double *cv, double &sv) {
       const int xk = sk * 64 + lane;
       const int64_t p = ((int64_t)mm * ny + row) * nx + ((xk < nx) ? xk : nx - 1);
+      const int k = (mm - m0) * words + sk;
       sv = s[p];
 #pragma unroll
-      for (int t = 0; t < G; ++t) cv[t] = c_g[t * n3 + p];
+      for (int t = 0; t < G; ++t) cv[t] = c_at(t, p, (__builtin_amdgcn_readlane(fl, k) >> (8 * t)) & 0xff);
     };
     auto load_last = [&](int mm, double *cv) {
       const int64_t p = ((int64_t)mm * ny + row) * nx + (nx - 1);
+      const int k = (mm - m0) * words + words - 1;
 #pragma unroll
-      for (int t = 0; t < G; ++t) cv[t] = c_g[t * n3 + p];
+      for (int t = 0; t < G; ++t) cv[t] = c_at(t, p, (__builtin_amdgcn_readlane(fl, k) >> (8 * t)) & 0xff);
     };
     auto words_of = [&](int mm, int sk, uint64_t *ccw, uint64_t *chw) {
       const int64_t w = ((int64_t)mm * ny + row) * words + sk;
@@ -416,7 +481,6 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
       words_of(m0, 0, ccw, chw);
     }
     int mk = m0, sk = 0;
-    const int nk = (m1 - m0) * words;
     for (int k = 0; k < nk; ++k) {
       int mn = mk, sn = sk + 1;
       if (sn == words) {
@@ -465,6 +529,7 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
       }
 #pragma unroll
       for (int t = 0; t < G; ++t) finish(t, c_cur[t], flo[t], fhi[t], s_lo, s_hi, pc, wrow, ccw[t], chw[t]);
+      store_flags(wrow);
       // carry to the next step
 #pragma unroll
       for (int t = 0; t < G; ++t) {
@@ -566,6 +631,7 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
         const uint64_t ccw = (!write_cc && tile_ok && seg < words) ? b_g[t * nbits + wrow] : 0ull;
         finish(t, c0[t], flo[t], fhi[t], s_lo, s_hi, pc, wrow, ccw, 0ull);
       }
+      store_flags(wrow);
     }
   }
   if (lane == 0) counts_next[wave] = nlist;
