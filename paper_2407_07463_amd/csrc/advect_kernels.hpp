@@ -266,7 +266,7 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
   // recorded), one byte per tracer laid out [row word][tracer] with ntp
   // tracers per word (the tracer count rounded up to 4): a group's flags
   // are adjacent and move as one 1-, 2- or 4-byte word
-  const uint8_t *pur_in = (D != 0 && pure_prev) ? pure_prev + t0 : nullptr;
+  const uint8_t *pur_in = ((D != 0 || ROWS) && pure_prev) ? pure_prev + t0 : nullptr;
   uint8_t *pur_out = pure_cur ? pure_cur + t0 : nullptr;
   static_assert(G == 1 || G == 2 || G == 4, "flag words of 1, 2 or 4 bytes");
   auto flags_at = [&](const uint8_t *base) -> uint32_t {
