@@ -305,15 +305,17 @@ def main():
         g = 4 if ntr >= 4 else ntr
         bytes_launch = stream_bytes(n3, g)
         achieved = bytes_launch / (total_ms / launches / 1e3) / 1e9
-        kernel_desc = f"k_stream<D,{g}> (streaming pass of {g} tracers; all axes)"
+        kernel_desc = (f"k_stream<D,{g}> (streaming pass of {g} tracers; all axes; the x-sweep as "
+                       f"k_stream_rows<{g}>); achieved counts the method's bytes per tracer-cell-sweep, "
+                       f"actual_hbm_gbs the measured HBM bytes")
         log(f"k_stream: {launches} launches, avg {total_ms / launches:.3f} ms, {achieved:.0f} GB/s "
             f"(profiled region {ms2 / args.steps:.3f} ms/step)")
-        prefix, traffic_file = "k_stream<", TRAFFIC_FILE_SINGLE
+        prefix, traffic_file = ("k_stream<", "k_stream_rows<"), TRAFFIC_FILE_SINGLE
 
     traffic = None
     tr, sha = profiling.read_traffic(traffic_file)
     if tr and sha == profiling.advect_source_sha():
-        vals = [v for k, v in tr.items() if k.startswith(prefix)]
+        vals = [v for k, v in tr.items() if k.startswith(prefix)]  # str.startswith takes a tuple too
         if vals:
             traffic = sum(vals) / len(vals)
 
@@ -347,6 +349,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "actual_hbm_gbs": (traffic / (total_ms / launches / 1e3) / 1e9) if traffic else None,
             "kernel": kernel_desc,
             "bytes_per_launch": bytes_launch,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",

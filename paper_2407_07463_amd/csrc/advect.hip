@@ -31,15 +31,11 @@ __global__ __launch_bounds__(256) void k_plic(const double *__restrict__ cin, co
 template <int D, int G>
 __global__ __launch_bounds__(64 * kXWaves) void k_stream(const double *__restrict__ cin, double *__restrict__ cout,
                                                         const double *__restrict__ s, const double *__restrict__ fmix,
-                                                        uint64_t *__restrict__ ccbits, int write_cc,
-                                                        const uint64_t *__restrict__ chg_prev,
-                                                        uint64_t *__restrict__ chg_cur,
-                                                        const uint8_t *__restrict__ pure_prev,
-                                                        uint8_t *__restrict__ pure_cur, int ntp, int t0, int nx, int ny,
-                                                        int nz, int words, int chunk, uint32_t *__restrict__ list_next,
-                                                        int *__restrict__ counts_next, int64_t region0, int rsize) {
-  stream_body<D, G, kXWaves>(cin, cout, s, fmix, ccbits, write_cc, chg_prev, chg_cur, pure_prev, pure_cur, ntp, t0,
-                             nx, ny, nz, words, chunk, list_next,
+                                                        uint64_t *__restrict__ ccbits, int write_cc, int t0, int nx,
+                                                        int ny, int nz, int words, int chunk,
+                                                        uint32_t *__restrict__ list_next, int *__restrict__ counts_next,
+                                                        int64_t region0, int rsize) {
+  stream_body<D, G, kXWaves>(cin, cout, s, fmix, ccbits, write_cc, t0, nx, ny, nz, words, chunk, list_next,
                              counts_next, region0, rsize, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gridDim.y);
 }
 
@@ -47,16 +43,12 @@ __global__ __launch_bounds__(64 * kXWaves) void k_stream(const double *__restric
 template <int G>
 __global__ __launch_bounds__(256) void k_stream_rows(const double *__restrict__ cin, double *__restrict__ cout,
                                                      const double *__restrict__ s, const double *__restrict__ fmix,
-                                                     uint64_t *__restrict__ ccbits, int write_cc,
-                                                     const uint64_t *__restrict__ chg_prev,
-                                                     uint64_t *__restrict__ chg_cur,
-                                                     const uint8_t *__restrict__ pure_prev,
-                                                     uint8_t *__restrict__ pure_cur, int ntp, int t0, int nx, int ny,
-                                                     int nz, int words, int chunk, uint32_t *__restrict__ list_next,
-                                                     int *__restrict__ counts_next, int64_t region0, int rsize) {
-  stream_body<0, G, 0>(cin, cout, s, fmix, ccbits, write_cc, chg_prev, chg_cur, pure_prev, pure_cur, ntp, t0, nx, ny,
-                       nz, words, chunk, list_next, counts_next, region0, rsize, blockIdx.x, blockIdx.y, blockIdx.z,
-                       gridDim.x, gridDim.y);
+                                                     uint64_t *__restrict__ ccbits, int write_cc, int t0, int nx,
+                                                     int ny, int nz, int words, int chunk,
+                                                     uint32_t *__restrict__ list_next, int *__restrict__ counts_next,
+                                                     int64_t region0, int rsize) {
+  stream_body<0, G, 0>(cin, cout, s, fmix, ccbits, write_cc, t0, nx, ny, nz, words, chunk, list_next, counts_next,
+                       region0, rsize, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gridDim.y);
 }
 
 template <int A>
@@ -122,11 +114,6 @@ __global__ __launch_bounds__(256) void k_courant_max(const double *__restrict__ 
 struct SweepBuffers {
   double *fmix;
   uint64_t *bits;
-  const uint64_t *chg_prev = nullptr;  // cells changed by the previous sweep (null: store every cell)
-  uint64_t *chg_cur = nullptr;         // cells changed by this sweep (null: not recorded)
-  const uint8_t *pure_prev = nullptr;  // purity flags of the input field (null: load every value)
-  uint8_t *pure_cur = nullptr;         // purity flags of the output field (null: not recorded)
-  int ntp = 0;                         // tracers per row word of the flags: the tracer count rounded up to 4
   uint32_t *list[2];
   int *counts[2];
   int64_t nregions[2];  // regions filled into each list
@@ -155,11 +142,11 @@ static void launch_stream(vofmt_ctx *ctx, const double *cin, double *cout, const
   const int rec = prof_begin(ctx, stream_name(D, G), stream);
   if (D == 0 && wpb == 0)
     hipLaunchKernelGGL((k_stream_rows<G>), grid, dim3(256), 0, stream, cin, cout, s, sb.fmix, sb.bits, wcc,
-                       sb.chg_prev, sb.chg_cur, sb.pure_prev, sb.pure_cur, sb.ntp, t0, nx, ny, nz, words, chunk,
+                       t0, nx, ny, nz, words, chunk,
                        sb.list[nxt], sb.counts[nxt], region0, sb.rsize);
   else
     hipLaunchKernelGGL((k_stream<D, G>), grid, dim3(D == 0 ? 64 * kXWaves : 256), 0, stream, cin, cout, s,
-                       sb.fmix, sb.bits, wcc, sb.chg_prev, sb.chg_cur, sb.pure_prev, sb.pure_cur, sb.ntp, t0, nx, ny,
+                       sb.fmix, sb.bits, wcc, t0, nx, ny,
                        nz,
                        words, chunk, sb.list[nxt], sb.counts[nxt], region0, sb.rsize);
   prof_end(ctx, rec, stream);
@@ -438,14 +425,7 @@ extern "C" int vofmt_advect(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, 
   const size_t field_bytes = sizeof(double) * (size_t)n3 * ntracers;
   double *tmp = (double *)scratch(ctx, SLOT_PINGPONG, field_bytes);
   double *fmix = (double *)scratch(ctx, SLOT_FMIX, field_bytes);
-  const size_t nbt = (size_t)ntracers * nz * ny * words;  // bit words of all tracers
-  uint64_t *bits = (uint64_t *)scratch(ctx, SLOT_CCBITS, sizeof(uint64_t) * nbt);
-  // two halves of changed-cell bits ([tracer][row word]), then two halves of
-  // purity flags ([row word][tracer], the tracer count rounded up to 4)
-  const int ntp = (ntracers + 3) & ~3;
-  const size_t nbp = (size_t)ntp * nz * ny * words;
-  uint64_t *chg = (uint64_t *)scratch(ctx, SLOT_CHGBITS, sizeof(uint64_t) * 2 * nbt + 2 * nbp);
-  uint8_t *pure = chg ? (uint8_t *)(chg + 2 * nbt) : nullptr;
+  uint64_t *bits = (uint64_t *)scratch(ctx, SLOT_CCBITS, sizeof(uint64_t) * (size_t)ntracers * nz * ny * words);
   // list regions: enough for the largest sweep launch set and for the initial scan
   const int rsize = region_size(kChunk);
   const int64_t maxreg = max_regions(nx, ny, nz, ntracers, kChunk, x_wpb(words, kChunk));
@@ -453,7 +433,7 @@ extern "C" int vofmt_advect(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, 
   const int64_t scanreg = (total + rsize - 1) / rsize;
   uint32_t *lists = (uint32_t *)scratch(ctx, SLOT_MIXLIST, sizeof(uint32_t) * 2 * (size_t)maxreg * rsize);
   int *counts = (int *)scratch(ctx, SLOT_COUNTS, sizeof(int) * 2 * (size_t)maxreg);
-  if (!tmp || !fmix || !bits || !chg || !lists || !counts) return VOFMT_E_NOMEM;
+  if (!tmp || !fmix || !bits || !lists || !counts) return VOFMT_E_NOMEM;
   SweepBuffers sb;
   sb.fmix = fmix;
   sb.bits = bits;
@@ -478,13 +458,6 @@ extern "C" int vofmt_advect(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, 
     for (int r = 0; r < 3; ++r) {
       const int d = (int)((g + r) % 3);
       const int wcc = (r == 0);
-      // sweep k records its changed cells in half k & 1 and reads those of sweep k - 1
-      const int64_t k = 3 * (int64_t)st + r;
-      sb.chg_prev = (k == 0) ? nullptr : chg + (size_t)((k - 1) & 1) * nbt;
-      sb.chg_cur = chg + (size_t)(k & 1) * nbt;
-      sb.pure_prev = (k == 0) ? nullptr : pure + (size_t)((k - 1) & 1) * nbp;
-      sb.pure_cur = pure + (size_t)(k & 1) * nbp;
-      sb.ntp = ntp;
       int rc = launch_sweep(ctx, d, cur, nxt, s3[d], sb, wcc, cur_list, nx, ny, nz, ntracers, words, chunk, stream);
       if (rc) return hip_check(ctx, (hipError_t)rc, "sweep launch");
       cur_list ^= 1;

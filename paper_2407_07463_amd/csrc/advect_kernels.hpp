@@ -27,22 +27,6 @@
 //   row layout, and every new mixed cell is appended to the list of the next
 //   sweep.
 //
-// Stores of unchanged values are skipped. The fields alternate between two
-// buffers, so a sweep's output buffer holds the field of two sweeps before;
-// a cell needs a store only where its value changed in this sweep or in the
-// previous one, which the sweeps record as one bit per cell (a 64-bit ballot
-// word per row segment, the layout of the c > 0.5 bits). Away from the
-// interfaces nearly every value is unchanged (empty cells stay 0, most full
-// cells give exactly 1 again), so most row segments are not stored at all.
-// The first sweep of a call stores every cell (its output buffer holds no
-// field yet).
-//
-// Loads of pure segments are skipped too: every sweep records, per tracer
-// and row segment, whether all its new values are exactly +0.0 or exactly
-// 1.0 (a byte per segment). The next sweep takes those values from the flag
-// instead of memory; the flag is uniform over the wavefront, so the whole
-// load is skipped. Away from the drops most segments are empty.
-//
 // The list is cut into regions of rsize entries, one per wavefront of the
 // pass that fills it, each large enough for every cell that wavefront handles
 // (64 * chunk * G): entries are written without atomics, in a fixed order,
@@ -212,11 +196,8 @@ __device__ __forceinline__ double from_lane_above(double v) {
 template <int D, int G, int WPB = 4>
 __device__ __forceinline__ void stream_body(const double *__restrict__ cin, double *__restrict__ cout,
                                             const double *__restrict__ s, const double *__restrict__ fmix,
-                                            uint64_t *__restrict__ ccbits, int write_cc,
-                                            const uint64_t *__restrict__ chg_prev, uint64_t *__restrict__ chg_cur,
-                                            const uint8_t *__restrict__ pure_prev, uint8_t *__restrict__ pure_cur,
-                                            int ntp, int t0, int nx, int ny, int nz, int words, int chunk,
-                                            uint32_t *__restrict__ list_next,
+                                            uint64_t *__restrict__ ccbits, int write_cc, int t0, int nx, int ny,
+                                            int nz, int words, int chunk, uint32_t *__restrict__ list_next,
                                             int *__restrict__ counts_next, int64_t region0, int rsize, int bx, int by,
                                             int bz, int gx, int gy) {
   const int lane = threadIdx.x & 63;
@@ -255,42 +236,6 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
   double *o_g = cout + (int64_t)t0 * n3;
   const double *f_g = fmix + (int64_t)t0 * n3;
   uint64_t *b_g = ccbits + (int64_t)t0 * nbits;
-  // changed-cell bits: of the previous sweep (null: store every cell) and of
-  // this one (null: not recorded). The LDS x-sweep stores every cell (its
-  // per-position barrier leaves no room to wait for the extra words) and
-  // only records its changes.
-  const uint64_t *chp_g = ((D != 0 || ROWS) && chg_prev) ? chg_prev + (int64_t)t0 * nbits : nullptr;
-  uint64_t *chc_g = chg_cur ? chg_cur + (int64_t)t0 * nbits : nullptr;
-  // purity flags (0: other, 1: all +0.0, 2: all 1.0) of the input field (null:
-  // unknown, every value is loaded) and of the output field (null: not
-  // recorded), one byte per tracer laid out [row word][tracer] with ntp
-  // tracers per word (the tracer count rounded up to 4): a group's flags
-  // are adjacent and move as one 1-, 2- or 4-byte word
-  const uint8_t *pur_in = ((D != 0 || ROWS) && pure_prev) ? pure_prev + t0 : nullptr;
-  uint8_t *pur_out = pure_cur ? pure_cur + t0 : nullptr;
-  static_assert(G == 1 || G == 2 || G == 4, "flag words of 1, 2 or 4 bytes");
-  auto flags_at = [&](const uint8_t *base) -> uint32_t {
-    if (G == 4) return *reinterpret_cast<const uint32_t *>(base);
-    if (G == 2) return *reinterpret_cast<const uint16_t *>(base);
-    return *base;
-  };
-  uint32_t gflags = 0;  // this row word's flags, byte t for tracer t
-  auto store_flags = [&](int64_t wrow) {
-    if (pur_out && lane == 0 && tile_ok && seg < words) {
-      uint8_t *dst = pur_out + wrow * ntp;
-      if (G == 4) *reinterpret_cast<uint32_t *>(dst) = gflags;
-      else if (G == 2) *reinterpret_cast<uint16_t *>(dst) = (uint16_t)gflags;
-      else *dst = (uint8_t)gflags;
-    }
-    gflags = 0;
-  };
-  // value of tracer t at cell p of a segment with flag f (f is wave-uniform)
-  auto c_at = [&](int t, int64_t p, int f) -> double {
-    double v;
-    if (f == 0) v = c_g[t * n3 + p];
-    else v = (f == 1) ? 0.0 : 1.0;
-    return v;
-  };
 
   auto cell = [&](int xx, int mm) -> int64_t {
     if (D == 1) return ((int64_t)row * ny + mm) * nx + xx;
@@ -309,20 +254,17 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
     if (mixed) fv = f_g[t * n3 + pu];
     return mixed ? fv : ((sv == 0.0) ? 0.0 : sv * cd);
   };
-  // the bit words of row word wrow that finish() reads: the c_c bits (unless
-  // this sweep writes them) and the previous sweep's changed cells; loaded
-  // ahead of their use so their latency overlaps other work
-  auto load_words = [&](int64_t wrow, uint64_t *ccw, uint64_t *chw) {
+  // the c_c bit words of row word wrow that finish() reads (unless this
+  // sweep writes them), loaded ahead of their use so their latency overlaps
+  // other work
+  auto load_words = [&](int64_t wrow, uint64_t *ccw) {
     const bool ok = tile_ok && seg < words;  // idle: no cells
 #pragma unroll
-    for (int t = 0; t < G; ++t) {
-      ccw[t] = (!write_cc && ok) ? b_g[t * nbits + wrow] : 0ull;
-      chw[t] = (chp_g && ok) ? chp_g[t * nbits + wrow] : 0ull;
-    }
+    for (int t = 0; t < G; ++t) ccw[t] = (!write_cc && ok) ? b_g[t * nbits + wrow] : 0ull;
   };
   // new value of cell pc, its c_c bit, and its entry in the next list
   auto finish = [&](int t, double cold, double f_lo, double f_hi, double s_lo, double s_hi, int64_t pc, int64_t wrow,
-                    uint64_t ccw, uint64_t chw) {
+                    uint64_t ccw) {
     double ccv;
     if (write_cc) {
       const uint64_t word = __ballot(live && cold > 0.5);
@@ -332,20 +274,7 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
       ccv = ((ccw >> lane) & 1ull) ? 1.0 : 0.0;
     }
     const double cn = (cold - (f_hi - f_lo)) + ccv * (s_hi - s_lo);
-    bool store = live;
-    if (chc_g) {
-      const bool chg = live && (__double_as_longlong(cn) != __double_as_longlong(cold));
-      const uint64_t word = __ballot(chg);
-      if (lane == 0 && tile_ok && seg < words) chc_g[t * nbits + wrow] = word;
-      if (chp_g) store = chg || (live && ((chw >> lane) & 1ull));
-    }
-    if (store) o_g[t * n3 + pc] = cn;
-    if (pur_out) {
-      const long long bits = __double_as_longlong(cn);
-      const uint64_t zero = __ballot(!live || bits == 0ll);
-      const uint64_t one = __ballot(!live || bits == 0x3FF0000000000000ll);
-      gflags |= (uint32_t)((zero == ~0ull) ? 1 : ((one == ~0ull) ? 2 : 0)) << (8 * t);
-    }
+    if (live) o_g[t * n3 + pc] = cn;
     const bool mixed = live && cn > 0.0 && cn < 1.0;
     const uint64_t mask = __ballot(mixed);
     if (mixed) reg[nlist + __popcll(mask & below)] = (uint32_t)((int64_t)(t0 + t) * n3 + pc);
@@ -355,16 +284,6 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
   if constexpr (D != 0) {
     // ---- march along the sweep axis: faces m0..m1, cells m0..m1-1
     const int ml = (m0 == 0) ? nm - 1 : m0 - 1;
-    // purity flags of positions m0-1 .. m1 (wrapped): lane L holds m0 - 1 + L
-    int fl = 0;
-    {
-      int pos = m0 - 1 + lane;
-      pos += (pos < 0) ? nm : ((pos >= nm) ? -nm : 0);
-      if (pur_in && lane <= m1 - m0 + 1) fl = (int)flags_at(pur_in + bitword(pos) * ntp);
-    }
-    auto pure_at = [&](int t, int m) -> int {
-      return (__builtin_amdgcn_readlane(fl, m - (m0 - 1)) >> (8 * t)) & 0xff;
-    };
     double cm[G], flo[G];
     const int64_t p0 = cell(xs, m0);
     const double s0 = s[p0];
@@ -374,8 +293,8 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
       double cl[G];
 #pragma unroll
       for (int t = 0; t < G; ++t) {
-        cl[t] = c_at(t, pl, pure_at(t, m0 - 1));
-        cm[t] = c_at(t, p0, pure_at(t, m0));
+        cl[t] = c_g[t * n3 + pl];
+        cm[t] = c_g[t * n3 + p0];
       }
 #pragma unroll
       for (int t = 0; t < G; ++t) flo[t] = flux(t, s0, cl[t], cm[t], p0);
@@ -384,14 +303,14 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
     // are loaded one position ahead, so their latency overlaps the previous
     // position's flux work and stores
     double s_nx = 0.0, c_nx[G];
-    uint64_t ccw[G], chw[G];
+    uint64_t ccw[G];
     if (m0 + 1 <= m1) {
       const int64_t pu = cell(xs, (m0 + 1 == nm) ? 0 : m0 + 1);
       s_nx = s[pu];
 #pragma unroll
-      for (int t = 0; t < G; ++t) c_nx[t] = c_at(t, pu, pure_at(t, m0 + 1));
+      for (int t = 0; t < G; ++t) c_nx[t] = c_g[t * n3 + pu];
     }
-    load_words(bitword(m0), ccw, chw);
+    load_words(bitword(m0), ccw);
     for (int m = m0 + 1; m <= m1; ++m) {
       const int mm = (m == nm) ? 0 : m;
       const int64_t pu = cell(xs, mm);
@@ -399,29 +318,27 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
       const int64_t wrow = bitword(m - 1);
       const double s_hi = s_nx;
       double cu[G], fhi[G];
-      uint64_t ccc[G], chc[G];
+      uint64_t ccc[G];
 #pragma unroll
       for (int t = 0; t < G; ++t) {
         cu[t] = c_nx[t];
         ccc[t] = ccw[t];
-        chc[t] = chw[t];
       }
       if (m + 1 <= m1) {
         const int64_t pn = cell(xs, (m + 1 == nm) ? 0 : m + 1);
         s_nx = s[pn];
 #pragma unroll
-        for (int t = 0; t < G; ++t) c_nx[t] = c_at(t, pn, pure_at(t, m + 1));
-        load_words(bitword(m), ccw, chw);
+        for (int t = 0; t < G; ++t) c_nx[t] = c_g[t * n3 + pn];
+        load_words(bitword(m), ccw);
       }
 #pragma unroll
       for (int t = 0; t < G; ++t) fhi[t] = flux(t, s_hi, cm[t], cu[t], pu);
 #pragma unroll
       for (int t = 0; t < G; ++t) {
-        finish(t, cm[t], flo[t], fhi[t], s_lo, s_hi, pc, wrow, ccc[t], chc[t]);
+        finish(t, cm[t], flo[t], fhi[t], s_lo, s_hi, pc, wrow, ccc[t]);
         flo[t] = fhi[t];
         cm[t] = cu[t];
       }
-      store_flags(wrow);
       s_lo = s_hi;
     }
   } else if constexpr (ROWS) {
@@ -431,54 +348,40 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
     // previous segment's last cell, the last cell the next segment's first,
     // and the row closes periodically through its first and last cells. The
     // next step's values, the last cell of its row and its bit words are
-    // loaded one step ahead. No barrier, no LDS: the wavefront skips the
-    // stores of unchanged values like the y- and z-sweeps.
+    // loaded one step ahead. No barrier, no LDS.
     auto readlane_d = [](double v, int l) {
       const long long b = __double_as_longlong(v);
       const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
       return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
     };
     // values of (position mm, segment sk): lanes past the row's end shadow its last cell
-    // the wavefront's steps k = (position - m0) * words + segment: at most
-    // `chunk` of them (the x_row_positions rule), so lane k holds the
-    // purity flags of step k
-    const int nk = (m1 - m0) * words;
-    int fl = 0;
-    if (pur_in && lane < nk) {
-      const int pm = m0 + lane / words, ps = lane - (lane / words) * words;
-      fl = (int)flags_at(pur_in + (((int64_t)pm * ny + row) * words + ps) * ntp);
-    }
+    const int nk = (m1 - m0) * words;  // steps: (position - m0) * words + segment
     auto load_step = [&](int mm, int sk, double *cv, double &sv) {
       const int xk = sk * 64 + lane;
       const int64_t p = ((int64_t)mm * ny + row) * nx + ((xk < nx) ? xk : nx - 1);
-      const int k = (mm - m0) * words + sk;
       sv = s[p];
 #pragma unroll
-      for (int t = 0; t < G; ++t) cv[t] = c_at(t, p, (__builtin_amdgcn_readlane(fl, k) >> (8 * t)) & 0xff);
+      for (int t = 0; t < G; ++t) cv[t] = c_g[t * n3 + p];
     };
     auto load_last = [&](int mm, double *cv) {
       const int64_t p = ((int64_t)mm * ny + row) * nx + (nx - 1);
-      const int k = (mm - m0) * words + words - 1;
 #pragma unroll
-      for (int t = 0; t < G; ++t) cv[t] = c_at(t, p, (__builtin_amdgcn_readlane(fl, k) >> (8 * t)) & 0xff);
+      for (int t = 0; t < G; ++t) cv[t] = c_g[t * n3 + p];
     };
-    auto words_of = [&](int mm, int sk, uint64_t *ccw, uint64_t *chw) {
+    auto words_of = [&](int mm, int sk, uint64_t *ccw) {
       const int64_t w = ((int64_t)mm * ny + row) * words + sk;
 #pragma unroll
-      for (int t = 0; t < G; ++t) {
-        ccw[t] = write_cc ? 0ull : b_g[t * nbits + w];
-        chw[t] = chp_g ? chp_g[t * nbits + w] : 0ull;
-      }
+      for (int t = 0; t < G; ++t) ccw[t] = write_cc ? 0ull : b_g[t * nbits + w];
     };
     double c_cur[G], c_nxt[G], c_lst[G], c_lst_nxt[G], c_fst[G], c_prv[G];
     double s_cur = 0.0, s_nxt = 0.0, s_fst = 0.0;
-    uint64_t ccw[G], chw[G], ccw_nxt[G], chw_nxt[G];
+    uint64_t ccw[G], ccw_nxt[G];
 #pragma unroll
     for (int t = 0; t < G; ++t) c_prv[t] = c_fst[t] = 0.0;
     if (m0 < m1) {
       load_step(m0, 0, c_cur, s_cur);
       load_last(m0, c_lst);
-      words_of(m0, 0, ccw, chw);
+      words_of(m0, 0, ccw);
     }
     int mk = m0, sk = 0;
     for (int k = 0; k < nk; ++k) {
@@ -490,7 +393,7 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
       if (mn < m1) {
         load_step(mn, sn, c_nxt, s_nxt);
         if (sn == 0) load_last(mn, c_lst_nxt);
-        words_of(mn, sn, ccw_nxt, chw_nxt);
+        words_of(mn, sn, ccw_nxt);
       }
       seg = sk;
       x = sk * 64 + lane;
@@ -528,15 +431,13 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
         fhi[t] = flux(t, s_hi, c_cur[t], cr[t], pr);
       }
 #pragma unroll
-      for (int t = 0; t < G; ++t) finish(t, c_cur[t], flo[t], fhi[t], s_lo, s_hi, pc, wrow, ccw[t], chw[t]);
-      store_flags(wrow);
+      for (int t = 0; t < G; ++t) finish(t, c_cur[t], flo[t], fhi[t], s_lo, s_hi, pc, wrow, ccw[t]);
       // carry to the next step
 #pragma unroll
       for (int t = 0; t < G; ++t) {
         c_prv[t] = readlane_d(c_cur[t], 63);
         c_cur[t] = c_nxt[t];
         ccw[t] = ccw_nxt[t];
-        chw[t] = chw_nxt[t];
         if (sn == 0) c_lst[t] = c_lst_nxt[t];
       }
       s_cur = s_nxt;
@@ -629,9 +530,8 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
 #pragma unroll
       for (int t = 0; t < G; ++t) {
         const uint64_t ccw = (!write_cc && tile_ok && seg < words) ? b_g[t * nbits + wrow] : 0ull;
-        finish(t, c0[t], flo[t], fhi[t], s_lo, s_hi, pc, wrow, ccw, 0ull);
+        finish(t, c0[t], flo[t], fhi[t], s_lo, s_hi, pc, wrow, ccw);
       }
-      store_flags(wrow);
     }
   }
   if (lane == 0) counts_next[wave] = nlist;

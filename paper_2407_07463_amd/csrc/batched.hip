@@ -83,9 +83,8 @@ __global__ __launch_bounds__(256) void k_stream_b(const BoxDev *__restrict__ box
     const int bx = (int)(lb % sg.gx);
     const int by = (int)((lb / sg.gx) % sg.gy);
     const int bz = (int)(lb / ((int64_t)sg.gx * sg.gy));
-    stream_body<D, G>(b.f[par], b.f[par ^ 1], b.s[D], b.fmix, b.bits, write_cc, nullptr, nullptr, nullptr, nullptr, 0,
-                      sg.t0, b.nx, b.ny, b.nz, b.words, chunk, b.list[nxt], b.counts[nxt], sg.region0, rsize, bx,
-                      by, bz, sg.gx, sg.gy);
+    stream_body<D, G>(b.f[par], b.f[par ^ 1], b.s[D], b.fmix, b.bits, write_cc, sg.t0, b.nx, b.ny, b.nz, b.words,
+                      chunk, b.list[nxt], b.counts[nxt], sg.region0, rsize, bx, by, bz, sg.gx, sg.gy);
   }
 }
 

@@ -11,7 +11,7 @@
 
 #include "vofmt.h"
 
-enum { kNumSlotsDecl = 26 };
+enum { kNumSlotsDecl = 25 };
 
 // One timed launch: HIP events recorded before and after it on its stream.
 struct ProfRec {
@@ -70,8 +70,7 @@ enum ScratchSlot {
   SLOT_CURV_HF = 22,     // cells handed to the height-function fallback; recolouring: list predicate bits
   SLOT_RECOLOR_LIST = 23,  // recolouring: drop-boundary and shared cells
   SLOT_FMIX2 = 24,         // paired sweeps: fluxes of the second sweep's mixed donors
-  SLOT_CHGBITS = 25,       // advection: cells changed by the last two sweeps (one bit per cell)
-  kNumSlots = 26,
+  kNumSlots = 25,
 };
 static_assert(kNumSlots == kNumSlotsDecl, "scratch slot count");
 
