@@ -105,6 +105,22 @@ def test_paired_sweeps_match_single_sweeps(ctx, shape, ntr, step0, nsteps):
         assert np.abs(g_pair - o).max() <= TOL
 
 
+@pytest.mark.parametrize("shape,ntr,step0", [((2, 3, 2048), 2, 0), ((3, 2, 2049), 1, 1), ((2, 4, 2113), 2, 2)])
+def test_long_rows(ctx, shape, ntr, step0):
+    """Rows of 32 segments (the whole-row x-sweep, one position per
+    wavefront) and of 33 or more (the x-sweep whose wavefronts share segment
+    ends through LDS), with a partial last segment."""
+    nz, ny, nx = shape
+    rng = synth.Splitmix64(777 + nx)
+    v = rng.uniform(ntr * nx * ny * nz).reshape((ntr,) + shape)
+    c = np.where(v < 0.3, 0.0, np.where(v > 0.7, 1.0, (v - 0.3) / 0.4))
+    s = [(rng.uniform(nx * ny * nz).reshape(shape) - 0.5) * 0.9 for _ in range(3)]
+    note(f"advect long rows {shape} ntr={ntr} step0={step0}")
+    g = _gpu_advect(ctx, c, *s, step0, 2)
+    o = oracle.advect(c, *s, step0, 2)
+    assert np.abs(g - o).max() <= TOL
+
+
 def test_translation_and_determinism(ctx):
     n = 24
     c = synth.fill_spheres((n, n, n), 1, [(11.3, 12.1, 10.7)], [6.3], [0])
