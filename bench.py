@@ -160,7 +160,7 @@ def rows_bench(torch, np, ctx, stream, c, w, n, ntr):
     for _ in range(5):
         ctx.mlp_forward(Pd, xs, y)
     fprof = ctx.profile_stop()
-    nf, tf = fprof["k_mlp_fwd"]
+    nf, tf = fprof["k_mlp_infer"]
     fwd_ms = tf / nf
     # matrix-core work per sample: layer 1 as hi + lo (2 x 32 x 128), layer 2 (128 x 128), multiply-add = 2 flops
     mfma_flops = 2.0 * (2 * 32 * 128 + 128 * 128)

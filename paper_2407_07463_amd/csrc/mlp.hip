@@ -471,31 +471,6 @@ __global__ __launch_bounds__(256) void k_stencil_list(const double *__restrict__
   sgn[q] = (int8_t)sg;
 }
 
-// The network's value for every listed cell (status 8); cells with
-// |kappa| < kappa_lo are appended to the height-function fallback list.
-__global__ __launch_bounds__(256) void k_curv_combine(const float *__restrict__ y, const int32_t *__restrict__ list,
-                                                      const int8_t *__restrict__ sgn, int nm, double kappa_lo,
-                                                      double *__restrict__ kappa, uint8_t *__restrict__ status,
-                                                      int32_t *__restrict__ hf_list, int32_t *__restrict__ hf_count) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  bool flag = false;
-  int32_t p = 0;
-  if (q < nm) {
-    p = list[q];
-    const double kn = (double)sgn[q] * (double)y[q];
-    kappa[p] = kn;
-    status[p] = 8;
-    flag = fabs(kn) < kappa_lo;
-  }
-  const uint64_t mask = __ballot(flag);
-  if (!mask) return;
-  int base = 0;
-  if (lane == 0) base = atomicAdd(hf_count, (int)__popcll(mask));
-  base = __shfl(base, 0, 64);
-  if (flag) hf_list[base + __popcll(mask & ((1ull << lane) - 1))] = p;
-}
-
 // Height functions on the fallback cells: their value where valid (status
 // 1..3), else the network's value stays (status 4 + 8).
 __global__ __launch_bounds__(256) void k_curv_fallback(const double *__restrict__ c, int nx, int ny, int nz,
@@ -674,6 +649,125 @@ __global__ __launch_bounds__(64 * FWAVES) void k_curv_fused(
   }
 }
 
+// Network outputs (and optionally activation records) of given inputs
+// x[m][27], by the tile scheme of k_curv_fused: each wavefront takes tiles of
+// FT samples on its own, their inputs read as one contiguous block, no block
+// barrier after the weights are staged. The matrix-core sequences and the
+// order of every sum are those of k_mlp_fwd, so the outputs and records are
+// bit-identical to it.
+__global__ __launch_bounds__(64 * FWAVES) void k_mlp_infer(const float *__restrict__ P,
+                                                           const uint16_t *__restrict__ w1t_g,
+                                                           const uint16_t *__restrict__ w2t_g, int m,
+                                                           const float *__restrict__ x, float *__restrict__ y,
+                                                           uint8_t *__restrict__ acts) {
+  __shared__ __attribute__((aligned(16))) uint16_t W1s[NH][XP];
+  __shared__ __attribute__((aligned(16))) uint16_t W2s[NH][HP];
+  __shared__ __attribute__((aligned(16))) uint16_t Xh[FWAVES][FT][XP];
+  __shared__ __attribute__((aligned(16))) uint16_t Xl[FWAVES][FT][XP];
+  __shared__ __attribute__((aligned(16))) uint16_t H1[FWAVES][FT][HP];
+  __shared__ float b1s[NH], b2s[NH], w3s[NH];
+  __shared__ float yb[FWAVES][FT];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int i = tid; i < NH * NIN; i += 64 * FWAVES) W1s[i / NIN][i % NIN] = w1t_g[i];
+  for (int i = tid; i < NH * NH; i += 64 * FWAVES) W2s[i / NH][i % NH] = w2t_g[i];
+  for (int i = tid; i < NH; i += 64 * FWAVES) {
+    b1s[i] = P[OFF_B1 + i];
+    b2s[i] = P[OFF_B2 + i];
+    w3s[i] = P[OFF_W3 + i];
+  }
+  // padding inputs 27..31 stay zero
+  for (int i = lane; i < FT * NIN; i += 64) {
+    Xh[w][i / NIN][i % NIN] = 0;
+    Xl[w][i / NIN][i % NIN] = 0;
+  }
+  const float b3 = P[OFF_B3];
+  __syncthreads();
+  const int lr = lane & 15, lq = lane >> 4;
+  const int ntiles = (m + FT - 1) / FT;
+  for (int tile = blockIdx.x * FWAVES + w; tile < ntiles; tile += gridDim.x * FWAVES) {
+    const int s0 = tile * FT;
+    // ---- the tile's inputs: FT x 27 consecutive values, split into hi + lo
+    const int nvals = ((m - s0 < FT) ? m - s0 : FT) * 27;
+    for (int i = lane; i < FT * 27; i += 64) {
+      const int sr = i / 27, k = i - 27 * sr;
+      const float v = (i < nvals) ? x[(int64_t)s0 * 27 + i] : 0.0f;
+      const uint16_t hi = bf16_bits(v);
+      Xh[w][sr][k] = hi;
+      Xl[w][sr][k] = bf16_bits(v - bf16_val(hi));
+    }
+    wave_sync();
+    // ---- layer 1: FT rows x 128 columns
+#pragma unroll
+    for (int mt = 0; mt < FT / 16; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NH / 16; ++nt) {
+        const bf16x8 wf = frag(&W1s[16 * nt + lr][8 * lq]);
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mfma(frag(&Xh[w][16 * mt + lr][8 * lq]), wf, acc);
+        acc = mfma(frag(&Xl[w][16 * mt + lr][8 * lq]), wf, acc);
+        const int col = 16 * nt + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * mt + 4 * lq + r;
+          const float z = acc[r] + b1s[col];
+          const uint16_t h = bf16_bits(z > 0.0f ? z : 0.0f);
+          H1[w][row][col] = h;
+          if (acts && s0 + row < m) act_h1(acts, s0 + row, ACT_BYTES)[col] = h;
+        }
+      }
+    wave_sync();
+    // ---- layer 2 and the layer-3 partial products, summed per 32 columns as k_mlp_fwd does
+    float yq[4][FT / 16][4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int mt = 0; mt < FT / 16; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) yq[g][mt][r] = 0.0f;
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int jn = 0; jn < 2; ++jn) {
+        const int nt = 2 * g + jn;
+        const int col = 16 * nt + lr;
+#pragma unroll
+        for (int mt = 0; mt < FT / 16; ++mt) {
+          f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int kk = 0; kk < NH; kk += 32)
+            acc = mfma(frag(&H1[w][16 * mt + lr][kk + 8 * lq]), frag(&W2s[16 * nt + lr][kk + 8 * lq]), acc);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * mt + 4 * lq + r;
+            const float z = acc[r] + b2s[col];
+            const float h = z > 0.0f ? z : 0.0f;
+            if (acts && s0 + row < m) act_h2(acts, s0 + row, ACT_BYTES)[col] = h;
+            yq[g][mt][r] = yq[g][mt][r] + h * w3s[col];
+          }
+        }
+      }
+#pragma unroll
+    for (int mt = 0; mt < FT / 16; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float part[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          float v = yq[g][mt][r];
+          v = v + __shfl_xor(v, 8, 64);
+          v = v + __shfl_xor(v, 4, 64);
+          v = v + __shfl_xor(v, 2, 64);
+          v = v + __shfl_xor(v, 1, 64);
+          part[g] = v;
+        }
+        if (lr == 0) yb[w][16 * mt + 4 * lq + r] = (((part[0] + part[1]) + part[2]) + part[3]) + b3;
+      }
+    wave_sync();
+    if (lane < FT && s0 + lane < m) y[s0 + lane] = yb[w][lane];
+    wave_sync();  // the next tile overwrites this wavefront's LDS slice
+  }
+}
+
 }  // namespace
 
 static int mlp_prepare(vofmt_ctx *ctx, const float *params, uint16_t **w, hipStream_t stream) {
@@ -704,12 +798,15 @@ extern "C" int vofmt_mlp_forward(vofmt_ctx *ctx, const float *params, int32_t m,
   uint16_t *w[3];
   int rc = mlp_prepare(ctx, params, w, stream);
   if (rc) return rc;
-  const int ntiles = (m + TILE - 1) / TILE;
-  const int rec = prof_begin(ctx, "k_mlp_fwd", stream);
-  hipLaunchKernelGGL(k_mlp_fwd, dim3(fwd_grid(ctx, ntiles)), dim3(256), 0, stream, params, w[0], w[1], m, x, y, acts,
-                     (const float *)nullptr, (float *)nullptr, (float *)nullptr);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
+    cus = 256;
+  const int ftiles = (m + FT - 1) / FT;
+  const int fgrid = ftiles < cus * FWAVES ? (ftiles + FWAVES - 1) / FWAVES : cus;
+  const int rec = prof_begin(ctx, "k_mlp_infer", stream);
+  hipLaunchKernelGGL(k_mlp_infer, dim3(fgrid), dim3(64 * FWAVES), 0, stream, params, w[0], w[1], m, x, y, acts);
   prof_end(ctx, rec, stream);
-  return hip_check(ctx, hipGetLastError(), "k_mlp_fwd");
+  return hip_check(ctx, hipGetLastError(), "k_mlp_infer");
 }
 
 extern "C" int vofmt_mlp_train_step(vofmt_ctx *ctx, float *params, float *adam_m, float *adam_v, int32_t step,
