@@ -56,6 +56,8 @@ def lib():
         L.orc_sweep.restype = None
         L.orc_advect.argtypes = [i64, i64, i64, ctypes.c_int, vp, vp, vp, vp, i64, ctypes.c_int]
         L.orc_advect.restype = ctypes.c_int
+        L.orc_drop_shapes.argtypes = [i64, i64, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp]
+        L.orc_drop_shapes.restype = ctypes.c_int
         L.orc_label.argtypes = [i64, i64, i64, vp, d, vp]
         L.orc_label.restype = ctypes.c_int
         L.orc_drop_moments.argtypes = [i64, i64, i64, vp, vp, i32, vp, vp]
@@ -165,6 +167,40 @@ def drop_moments(c, labels, k: int):
     rc = lib().orc_drop_moments(nx, ny, nz, c.ctypes.data, labels.ctypes.data, int(k), vol.ctypes.data,
                                 xyz.ctypes.data)
     return vol, xyz, rc
+
+
+def drop_shapes(c, labels, k: int, xyz, s=None):
+    """Inertia tensor of every drop about its centroid xyz, [k][6] =
+    (Ixx, Iyy, Izz, Ixy, Ixz, Iyz), and with s = (sx, sy, sz) the drop's mean
+    velocity [k][3] (else None). Appendix "Deformation of the drops"."""
+    c = _f64(c)
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    nx, ny, nz = _shape3(c)
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    assert len(xyz) >= k
+    inertia = np.zeros((max(k, 0), 6))
+    vel = np.zeros((max(k, 0), 3)) if s is not None else None
+    sp = [_f64(a) for a in s] if s is not None else [None, None, None]
+    if s is not None:
+        assert all(a.shape == c.shape for a in sp)
+    rc = lib().orc_drop_shapes(nx, ny, nz, c.ctypes.data, labels.ctypes.data, int(k), xyz.ctypes.data,
+                               *[a.ctypes.data if a is not None else None for a in sp], inertia.ctypes.data,
+                               vel.ctypes.data if vel is not None else None)
+    return inertia, vel, rc
+
+
+def aspect_ratio(inertia):
+    """chi = sqrt(I1 / I2) with I1, I2 the largest and smallest eigenvalues of
+    each inertia tensor (appendix "Deformation of the drops"); eigenvalues by
+    LAPACK's symmetric solver. Returns (eigenvalues ascending [k][3], chi [k])."""
+    inertia = np.asarray(inertia, dtype=np.float64).reshape(-1, 6)
+    T = np.empty((len(inertia), 3, 3))
+    T[:, 0, 0], T[:, 1, 1], T[:, 2, 2] = inertia[:, 0], inertia[:, 1], inertia[:, 2]
+    T[:, 0, 1] = T[:, 1, 0] = inertia[:, 3]
+    T[:, 0, 2] = T[:, 2, 0] = inertia[:, 4]
+    T[:, 1, 2] = T[:, 2, 1] = inertia[:, 5]
+    ev = np.linalg.eigvalsh(T) if len(T) else np.zeros((0, 3))
+    return ev, np.sqrt(ev[:, 2] / ev[:, 0]) if len(T) else np.zeros(0)
 
 
 def neighbour_pairs(labels, ndrops, tau: float):

@@ -397,6 +397,72 @@ int orc_drop_moments(int64_t nx, int64_t ny, int64_t nz, const double *c, const 
 }
 
 /* =========================================================================
+ * Drop shape: inertia tensor about the centroid (appendix "Deformation of the
+ * drops": I is the volume integral over the drop of (r.r) delta - r r, with r
+ * measured from the drop's centre of mass) and, when face Courant numbers are
+ * given, the drop's mean velocity.
+ * Reading: the fluid of a cell fills it uniformly with density c, so the cell
+ * at offset r from the centroid contributes c ((r.r) delta - r r) + (c/6)
+ * delta (the second moment of a uniform unit cube about its centre is delta /
+ * 12). r is the cell centre minus the centroid xyz (as vofmt drop moments
+ * give it), wrapped into [-n/2, n/2) per axis. The cell velocity is the mean
+ * of its two faces' Courant numbers, (s_d[p] + s_d[p + e_d]) / 2, and the drop
+ * velocity is sum(c u) / sum(c), in cells per step.
+ * inertia: [K][6] = (Ixx, Iyy, Izz, Ixy, Ixz, Iyz). vel: [K][3] or NULL.
+ * ========================================================================= */
+int orc_drop_shapes(int64_t nx, int64_t ny, int64_t nz, const double *c, const int32_t *labels, int32_t K,
+                    const double *xyz, const double *sx, const double *sy, const double *sz, double *inertia,
+                    double *vel) {
+  int64_t n3 = nx * ny * nz;
+  int64_t n[3] = {nx, ny, nz};
+  const double *s[3] = {sx, sy, sz};
+  double *V = (double *)calloc((size_t)(K > 0 ? K : 1), sizeof(double));
+  double *U = (double *)calloc((size_t)(K > 0 ? K : 1) * 3, sizeof(double));
+  for (int64_t a = 0; a < 6 * (int64_t)K; ++a) inertia[a] = 0.0;
+  int rc = ORC_OK;
+  for (int64_t p = 0; p < n3; ++p) {
+    int32_t l = labels[p];
+    if (l <= 0) continue;
+    if (l > K) { rc = ORC_E_ARG; break; }
+    int32_t a = l - 1;
+    int64_t x[3] = {p % nx, (p / nx) % ny, p / (nx * ny)};
+    double r[3];
+    for (int e = 0; e < 3; ++e) {
+      double d = ((double)x[e] + 0.5) - xyz[3 * a + e];
+      if (d >= 0.5 * (double)n[e]) d -= (double)n[e];
+      if (d < -0.5 * (double)n[e]) d += (double)n[e];
+      r[e] = d;
+    }
+    double w = c[p];
+    double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double *I = inertia + 6 * (int64_t)a;
+    I[0] += w * (rr - r[0] * r[0]) + w / 6.0;
+    I[1] += w * (rr - r[1] * r[1]) + w / 6.0;
+    I[2] += w * (rr - r[2] * r[2]) + w / 6.0;
+    I[3] -= w * r[0] * r[1];
+    I[4] -= w * r[0] * r[2];
+    I[5] -= w * r[1] * r[2];
+    V[a] += w;
+    if (vel) {
+      for (int e = 0; e < 3; ++e) {
+        int64_t q[3] = {x[0], x[1], x[2]};
+        q[e] = wrapi(q[e] + 1, n[e]);
+        double u = 0.5 * (s[e][p] + s[e][q[0] + nx * (q[1] + ny * q[2])]);
+        U[3 * a + e] += w * u;
+      }
+    }
+  }
+  for (int32_t a = 0; a < K && rc == ORC_OK; ++a) {
+    if (!(V[a] > 0.0)) { rc = ORC_E_ARG; break; }
+    if (vel)
+      for (int e = 0; e < 3; ++e) vel[3 * a + e] = U[3 * a + e] / V[a];
+  }
+  free(V);
+  free(U);
+  return rc;
+}
+
+/* =========================================================================
  * Tracer recolouring: Steps 1-4 of the no-coalescence algorithm.
  * Reading: drops are (tracer t, label l); two distinct drops are neighbours
  * when occupied cells p, q of each satisfy |o|^2 < (1+tau)^2 for the periodic
