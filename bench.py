@@ -103,6 +103,17 @@ def rows_bench(torch, np, ctx, stream, c, w, n, ntr):
     ms, _ = timed(torch, stream, lambda: ctx.drop_moments(c, lab, nd, vol, xyz))
     rows["drop_moments"] = dict(ms=ms)
     log(f"drop_moments: {ms:.2f} ms")
+    # ---- drop shapes: inertia tensors, aspect ratios and mean velocities
+    sv = [torch.from_numpy(w[k]).to(dev) for k in ("sx", "sy", "sz")]
+    inertia = torch.zeros((D, 6), dtype=torch.float64, device=dev)
+    chi = torch.zeros(D, dtype=torch.float64, device=dev)
+    velo = torch.zeros((D, 3), dtype=torch.float64, device=dev)
+    ctx.drop_shapes(c, lab, nd, inertia, chi, sv, velo)
+    ms, _ = timed(torch, stream, lambda: ctx.drop_shapes(c, lab, nd, inertia, chi, sv, velo))
+    rows["drop_shapes"] = dict(ms=ms, drops=D, chi_mean=float(chi.mean().item()),
+                               chi_max=float(chi.max().item()))
+    log(f"drop_shapes: {ms:.2f} ms, mean aspect ratio {rows['drop_shapes']['chi_mean']:.4f}")
+    del sv, inertia, chi, velo
     # ---- recolouring (on a copy with room for 2N tracers)
     cap = 2 * ntr
     cr = torch.zeros((cap,) + tuple(c.shape[1:]), dtype=torch.float64, device=dev)

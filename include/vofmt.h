@@ -140,6 +140,31 @@ int vofmt_drop_moments(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32
                        hipStream_t stream);
 
 /*
+ * Shape of every drop (appendix "Deformation of the drops"): its inertia
+ * tensor about the centre of mass, I = sum over the drop's cells of
+ * c ((r.r) delta - r r) + (c/6) delta with r the cell centre minus the
+ * centroid (periodic, wrapped into [-n/2, n/2)); the c/6 term is the cell's own
+ * extent, read as filled uniformly with density c. The aspect ratio is
+ * chi = sqrt(I1/I2) with I1, I2 the largest and smallest eigenvalues of I.
+ * With face Courant numbers, also the drop's mean velocity sum(c u)/sum(c),
+ * u the mean of each cell's two face values per axis, in cells per step.
+ *
+ * labels, ndrops_host: as produced by vofmt_label_drops.
+ * sx, sy, sz: [nz][ny][nx] FP64 face Courant numbers (lower faces), or all
+ *             NULL together with vel.
+ * inertia   : [D][6] FP64 output (Ixx, Iyy, Izz, Ixy, Ixz, Iyz), in cells^5
+ *             (volume in cells^3 times length^2); drops of tracer 0 first.
+ * chi       : [D] FP64 output.
+ * vel       : [D][3] FP64 output, or NULL.
+ * Errors: VOFMT_E_ARG (synchronises) if a label 1..K has no cells;
+ *         VOFMT_E_EXTENT if a drop spans n/2 or more cells along an axis (the
+ *         outputs are then still written).
+ */
+int vofmt_drop_shapes(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t ntracers, const double *c,
+                      const int32_t *labels, const int32_t *ndrops_host, const double *sx, const double *sy,
+                      const double *sz, double *inertia, double *chi, double *vel, hipStream_t stream);
+
+/*
  * Reassign drops in near contact to other tracers (Steps 1-4 of section
  * "The no-coalescence.h algorithm"). Two distinct drops are neighbours when
  * an occupied cell of each lies at a periodic offset o with |o|^2 <

@@ -574,6 +574,153 @@ __global__ void k_drop_finish(int32_t K, int nx, int ny, int nz, const int32_t *
   }
 }
 
+// Shape sums of one drop part: with the offsets r of a cell from the centre
+// of the drop's box (integer part), c, c r (3), c r r^T (6: xx, yy, zz, xy,
+// xz, yz) and, given face Courant numbers, c u (3) with u the mean of the
+// cell's two faces on each axis. Same partition and fixed tree as
+// k_drop_sums, so the result is reproducible bit for bit.
+constexpr int kShapeSums = 13;
+__global__ __launch_bounds__(kBlock) void k_shape_sums(const double *__restrict__ c, const int32_t *__restrict__ lab,
+                                                       const double *__restrict__ sx, const double *__restrict__ sy,
+                                                       const double *__restrict__ sz, int nx, int ny, int nz,
+                                                       const int32_t *__restrict__ rootpos,
+                                                       const int32_t *__restrict__ box, double *__restrict__ part,
+                                                       int32_t *__restrict__ extent_err) {
+  const int l = blockIdx.x / kSumSplit + 1, sl = blockIdx.x % kSumSplit;
+  const int32_t p0 = rootpos[l - 1];
+  const int32_t *b = box + 6 * (int64_t)(l - 1);
+  if (p0 == INT32_MAX || b[0] > b[1]) {  // label without cells: inconsistent input
+    if (threadIdx.x == 0) atomicOr(extent_err, 2);
+    return;
+  }
+  const int x0 = p0 % nx, y0 = (p0 / nx) % ny, z0 = p0 / (nx * ny);
+  const int lx = b[0], ly = b[2], lz = b[4];
+  const int ex = b[1] - b[0] + 1, ey = b[3] - b[2] + 1, ez = b[5] - b[4] + 1;
+  // the box centre's offset (floor of the mean of its ends)
+  const int mx = (b[0] + b[1]) >> 1, my = (b[2] + b[3]) >> 1, mz = (b[4] + b[5]) >> 1;
+  const int nbox = ex * ey * ez;
+  const int q0 = (int)((int64_t)nbox * sl / kSumSplit), q1 = (int)((int64_t)nbox * (sl + 1) / kSumSplit);
+  const bool withu = sx != nullptr;
+  double acc[kShapeSums];
+#pragma unroll
+  for (int k = 0; k < kShapeSums; ++k) acc[k] = 0.0;
+  for (int q = q0 + (int)threadIdx.x; q < q1; q += kBlock) {
+    const int dx = q % ex + lx;
+    const int dy = (q / ex) % ey + ly;
+    const int dz = q / (ex * ey) + lz;
+    int x = x0 + dx, y = y0 + dy, z = z0 + dz;
+    x += (x < 0) ? nx : ((x >= nx) ? -nx : 0);
+    y += (y < 0) ? ny : ((y >= ny) ? -ny : 0);
+    z += (z < 0) ? nz : ((z >= nz) ? -nz : 0);
+    const int64_t p = ((int64_t)z * ny + y) * nx + x;
+    if (lab[p] != l) continue;
+    const double v = c[p];
+    const double rx = (double)(dx - mx), ry = (double)(dy - my), rz = (double)(dz - mz);
+    const double vx = v * rx, vy = v * ry, vz = v * rz;
+    acc[0] += v;
+    acc[1] += vx;
+    acc[2] += vy;
+    acc[3] += vz;
+    acc[4] += vx * rx;
+    acc[5] += vy * ry;
+    acc[6] += vz * rz;
+    acc[7] += vx * ry;
+    acc[8] += vx * rz;
+    acc[9] += vy * rz;
+    if (withu) {
+      const int xp = (x + 1 == nx) ? 0 : x + 1, yp = (y + 1 == ny) ? 0 : y + 1, zp = (z + 1 == nz) ? 0 : z + 1;
+      const int64_t row = (int64_t)y * nx + (int64_t)z * ny * nx;
+      acc[10] += v * (0.5 * (sx[p] + sx[row + xp]));
+      acc[11] += v * (0.5 * (sy[p] + sy[(int64_t)z * ny * nx + (int64_t)yp * nx + x]));
+      acc[12] += v * (0.5 * (sz[p] + sz[((int64_t)zp * ny + y) * nx + x]));
+    }
+  }
+  __shared__ double red[kShapeSums][kBlock];
+#pragma unroll
+  for (int k = 0; k < kShapeSums; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int k = 0; k < kShapeSums; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < kShapeSums)
+    part[((int64_t)(l - 1) * kSumSplit + sl) * kShapeSums + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Inertia tensor about the centroid, aspect ratio and mean velocity of every
+// drop from its kSumSplit parts. The second moments about the centroid are
+// the box-centred ones minus the centroid's share (parallel axes), plus V/12
+// per axis for the cells' own extent; I = tr(J) delta - J. Eigenvalues of the
+// symmetric 3x3 tensor by cyclic Jacobi rotations (Golub & Van Loan, the
+// symmetric Schur decomposition), which keep every eigenvalue within a few
+// ulps of the tensor's norm also for the (near-)equal pairs of round or
+// axisymmetric drops, where closed forms through the characteristic
+// polynomial lose half the digits.
+__global__ void k_shape_finish(int32_t K, int nx, int ny, int nz, const int32_t *__restrict__ rootpos,
+                               const int32_t *__restrict__ box, const double *__restrict__ part,
+                               double *__restrict__ inertia, double *__restrict__ chi, double *__restrict__ vel,
+                               int32_t *__restrict__ extent_err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  const int32_t p0 = rootpos[i];
+  const int32_t *b = box + 6 * i;
+  if (p0 == INT32_MAX || b[0] > b[1]) return;  // reported by k_shape_sums
+  double S[kShapeSums];
+  for (int k = 0; k < kShapeSums; ++k) S[k] = 0.0;
+  for (int sl = 0; sl < kSumSplit; ++sl)
+    for (int k = 0; k < kShapeSums; ++k) S[k] += part[(i * kSumSplit + sl) * kShapeSums + k];
+  const double V = S[0];
+  const double gx = S[1] / V, gy = S[2] / V, gz = S[3] / V;
+  const double self = V / 12.0;
+  const double Jxx = (S[4] - S[1] * gx) + self, Jyy = (S[5] - S[2] * gy) + self, Jzz = (S[6] - S[3] * gz) + self;
+  const double Jxy = S[7] - S[1] * gy, Jxz = S[8] - S[1] * gz, Jyz = S[9] - S[2] * gz;
+  const double Ixx = Jyy + Jzz, Iyy = Jxx + Jzz, Izz = Jxx + Jyy;
+  const double Ixy = -Jxy, Ixz = -Jxz, Iyz = -Jyz;
+  double *o = inertia + 6 * i;
+  o[0] = Ixx;
+  o[1] = Iyy;
+  o[2] = Izz;
+  o[3] = Ixy;
+  o[4] = Ixz;
+  o[5] = Iyz;
+  double A[3][3] = {{Ixx, Ixy, Ixz}, {Ixy, Iyy, Iyz}, {Ixz, Iyz, Izz}};
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    if (A[0][1] == 0.0 && A[0][2] == 0.0 && A[1][2] == 0.0) break;
+    for (int pq = 0; pq < 3; ++pq) {
+      const int pp = pq == 2 ? 1 : 0, qq = pq == 0 ? 1 : 2, rr = 3 - pp - qq;
+      const double apq = A[pp][qq];
+      if (apq == 0.0) continue;
+      const double g = 100.0 * fabs(apq);
+      if (fabs(A[pp][pp]) + g == fabs(A[pp][pp]) && fabs(A[qq][qq]) + g == fabs(A[qq][qq])) {
+        A[pp][qq] = A[qq][pp] = 0.0;  // negligible against both diagonal entries
+        continue;
+      }
+      // rotation angle zeroing A[pp][qq]: t = tan, the smaller root
+      const double tau = (A[qq][qq] - A[pp][pp]) / (2.0 * apq);
+      const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+      const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
+      A[pp][pp] -= t * apq;
+      A[qq][qq] += t * apq;
+      A[pp][qq] = A[qq][pp] = 0.0;
+      const double arp = A[rr][pp], arq = A[rr][qq];
+      A[rr][pp] = A[pp][rr] = cs * arp - sn * arq;
+      A[rr][qq] = A[qq][rr] = sn * arp + cs * arq;
+    }
+  }
+  const double lmax = fmax(A[0][0], fmax(A[1][1], A[2][2]));
+  const double lmin = fmin(A[0][0], fmin(A[1][1], A[2][2]));
+  chi[i] = sqrt(lmax / lmin);
+  if (vel) {
+    vel[3 * i] = S[10] / V;
+    vel[3 * i + 1] = S[11] / V;
+    vel[3 * i + 2] = S[12] / V;
+  }
+  const int n[3] = {nx, ny, nz};
+  for (int e = 0; e < 3; ++e)
+    if (2 * (b[2 * e + 1] - b[2 * e]) >= n[e]) atomicOr(extent_err, 1);
+}
+
 }  // namespace
 
 // Label one tracer field into `lab`. Returns K via *k_dev (device int32).
@@ -687,5 +834,62 @@ extern "C" int vofmt_drop_moments(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_
   VOFMT_HIP(ctx, hipStreamSynchronize(stream));
   if (fh[0] & 2) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_moments: labels do not match ndrops_host");
   if (fh[0]) return set_err(ctx, VOFMT_E_EXTENT, "vofmt_drop_moments: a drop spans half the box or more");
+  return VOFMT_OK;
+}
+
+extern "C" int vofmt_drop_shapes(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t ntracers,
+                                 const double *c, const int32_t *labels, const int32_t *ndrops_host,
+                                 const double *sx, const double *sy, const double *sz, double *inertia, double *chi,
+                                 double *vel, hipStream_t stream) {
+  if (!ctx) return VOFMT_E_ARG;
+  if (nx < 1 || ny < 1 || nz < 1 || ntracers < 0) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_shapes: bad sizes");
+  if (ntracers == 0) return VOFMT_OK;
+  if (!c || !labels || !ndrops_host) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_shapes: null pointer");
+  const bool withu = vel != nullptr;
+  if (withu != (sx != nullptr) || withu != (sy != nullptr) || withu != (sz != nullptr))
+    return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_shapes: vel, sx, sy and sz must be given together");
+  int64_t D = 0;
+  for (int t = 0; t < ntracers; ++t) {
+    if (ndrops_host[t] < 0) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_shapes: negative drop count");
+    D += ndrops_host[t];
+  }
+  if (D == 0) return VOFMT_OK;
+  if (!inertia || !chi) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_shapes: null output");
+  const int64_t n3 = (int64_t)nx * ny * nz;
+  if (n3 >= INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_shapes: more than 2^31-1 cells per field");
+  VOFMT_HIP(ctx, hipSetDevice(ctx->device));
+  int64_t kmax = 0;
+  for (int t = 0; t < ntracers; ++t) kmax = ndrops_host[t] > kmax ? ndrops_host[t] : kmax;
+  int32_t *rootpos = (int32_t *)scratch(ctx, SLOT_LABEL_C, sizeof(int32_t) * (size_t)(kmax + 1));
+  int32_t *box = (int32_t *)scratch(ctx, SLOT_MISC2, sizeof(int32_t) * (6 + kFrames) * (size_t)(kmax + 1));
+  int32_t *frames = box ? box + 6 * (kmax + 1) : nullptr;
+  int32_t *flags = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * 2);
+  double *part = (double *)scratch(ctx, SLOT_LABEL_A, sizeof(double) * kShapeSums * kSumSplit * (size_t)(kmax + 1));
+  int32_t *fh = (int32_t *)host_scratch(ctx, sizeof(int32_t) * 2);
+  if (!rootpos || !box || !flags || !part || !fh) return VOFMT_E_NOMEM;
+  VOFMT_HIP(ctx, hipMemsetAsync(flags, 0, sizeof(int32_t) * 2, stream));
+  const FastDiv fnx = make_fastdiv((uint32_t)nx), fny = make_fastdiv((uint32_t)ny);
+  const unsigned nbc = ceil_div(n3, kChunk);
+  int64_t off = 0;
+  for (int t = 0; t < ntracers; ++t) {
+    const int32_t K = ndrops_host[t];
+    if (K == 0) continue;
+    const int32_t *lab = labels + (int64_t)t * n3;
+    hipLaunchKernelGGL(k_scan_init, dim3(ceil_div(kFrames * (int64_t)K, 256)), dim3(256), 0, stream, rootpos, frames,
+                       (int64_t)K);
+    hipLaunchKernelGGL(k_drop_scan, dim3(nbc), dim3(kBlock), 0, stream, lab, n3, nx, ny, nz, fnx, fny, K, rootpos,
+                       frames);
+    hipLaunchKernelGGL(k_drop_box, dim3(ceil_div(K, 256)), dim3(256), 0, stream, K, nx, ny, nz, rootpos, frames, box);
+    hipLaunchKernelGGL(k_shape_sums, dim3((unsigned)(K * kSumSplit)), dim3(kBlock), 0, stream, c + (int64_t)t * n3,
+                       lab, sx, sy, sz, nx, ny, nz, rootpos, box, part, flags);
+    hipLaunchKernelGGL(k_shape_finish, dim3(ceil_div(K, 256)), dim3(256), 0, stream, K, nx, ny, nz, rootpos, box,
+                       part, inertia + 6 * off, chi + off, withu ? vel + 3 * off : nullptr, flags);
+    VOFMT_HIP(ctx, hipGetLastError());
+    off += K;
+  }
+  VOFMT_HIP(ctx, hipMemcpyAsync(fh, flags, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, stream));
+  VOFMT_HIP(ctx, hipStreamSynchronize(stream));
+  if (fh[0] & 2) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_shapes: labels do not match ndrops_host");
+  if (fh[0]) return set_err(ctx, VOFMT_E_EXTENT, "vofmt_drop_shapes: a drop spans half the box or more");
   return VOFMT_OK;
 }

@@ -46,6 +46,8 @@ _SIGNATURES = {
     "vofmt_set_advect_pairs": (ctypes.c_int, [_vp, _i32]),
     "vofmt_label_drops": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _d, _vp, _vp, _vp]),
     "vofmt_drop_moments": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "vofmt_drop_shapes": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                         _vp]),
     "vofmt_recolor_tracers": (ctypes.c_int, [_vp, _i32, _i32, _i32, _P_i32, _i32, _vp, _vp, _vp, _d, _vp, _P_i32,
                                              _vp]),
     "vofmt_nearest_pair_stats": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
@@ -230,6 +232,23 @@ class Context:
         nd = np.ascontiguousarray(ndrops, dtype=np.int32)
         return self._check(load().vofmt_drop_moments(self.h, nx, ny, nz, ntr, _ptr(c), _ptr(labels),
                                                      nd.ctypes.data, _ptr(vol), _ptr(xyz), _stream(stream)))
+
+    def drop_shapes(self, c, labels, ndrops, inertia, chi, s=None, vel=None, stream=None):
+        """Inertia tensors [D][6], aspect ratios [D] and, with s = (sx, sy, sz)
+        and vel [D][3], mean velocities."""
+        _require(c, labels, inertia, chi)
+        if (s is None) != (vel is None):
+            raise ValueError("drop_shapes: give s and vel together")
+        sp = [None, None, None]
+        if s is not None:
+            _require(*s, vel)
+            sp = [_ptr(a) for a in s]
+        nx, ny, nz = _dims(c)
+        ntr = int(c.shape[0]) if c.dim() == 4 else 1
+        nd = np.ascontiguousarray(ndrops, dtype=np.int32)
+        return self._check(load().vofmt_drop_shapes(self.h, nx, ny, nz, ntr, _ptr(c), _ptr(labels), nd.ctypes.data,
+                                                    *sp, _ptr(inertia), _ptr(chi),
+                                                    _ptr(vel) if vel is not None else None, _stream(stream)))
 
     def recolor_tracers(self, c, ntracers: int, labels, ndrops, gap_cells: float, new_tracer, stream=None):
         """c: [max_tracers][nz][ny][nx]; returns (ntracers_after, nmoved)."""

@@ -11,7 +11,9 @@ there are properties that hold at any size: every drop's cells appear
 unchanged in exactly the tracer it is assigned to, no cell receives two
 values, cells outside drops stay where they were, and the moved count is the
 number of drops whose tracer changed. Curvature: statuses bit-exact, values
-within 1e-12 where the height function is valid, NaN elsewhere.
+within 1e-12 where the height function is valid, NaN elsewhere. Drop
+shapes (inertia tensors, aspect ratios, mean velocities): the bars of
+test_parity_shapes.py.
 """
 import numpy as np
 import pytest
@@ -153,3 +155,39 @@ def test_curvature_hf(ctx, drops512):
     valid = (os_ >= 1) & (os_ <= 3)
     assert np.abs(gk[valid] - ok[valid]).max() <= 1e-12
     assert np.all(np.isnan(gk[~valid]))
+
+
+def test_drop_shapes(ctx, drops512, oracle_labels):
+    import torch
+
+    c = drops512["c"]
+    s = [drops512[k] for k in ("sx", "sy", "sz")]
+    note("drop shapes drops512 (full size, with velocity)")
+    olab, ond = oracle_labels
+    tc = torch.from_numpy(c).to("cuda:0")
+    lab = torch.from_numpy(olab).to("cuda:0")
+    D = int(ond.sum())
+    inertia = torch.zeros((D, 6), dtype=torch.float64, device="cuda:0")
+    chi = torch.zeros(D, dtype=torch.float64, device="cuda:0")
+    vel = torch.zeros((D, 3), dtype=torch.float64, device="cuda:0")
+    ctx.drop_shapes(tc, lab, ond, inertia, chi, [torch.from_numpy(a).to("cuda:0") for a in s], vel)
+    torch.cuda.synchronize()
+    gI, gchi, gvel = inertia.cpu().numpy(), chi.cpu().numpy(), vel.cpu().numpy()
+    del tc, lab
+    oI, ov = [], []
+    for t in range(c.shape[0]):
+        k = int(ond[t])
+        _, xyz, rc = oracle.drop_moments(c[t], olab[t], k)
+        assert rc == 0
+        it, vt, rc = oracle.drop_shapes(c[t], olab[t], k, xyz, s)
+        assert rc == 0
+        oI.append(it)
+        ov.append(vt)
+    oI, ov = np.concatenate(oI), np.concatenate(ov)
+    _, ochi = oracle.aspect_ratio(oI)
+    tr = oI[:, :3].sum(axis=1) / 2.0
+    assert (np.abs(gI - oI).max(axis=1) / tr).max() <= (1 << 17) * 2.2e-16
+    assert np.all(np.abs(gchi / ochi - 1.0) <= 1e-10)
+    assert np.abs(gvel - ov).max() <= 1e-13
+    # round drops: the aspect ratio is close to 1
+    assert 1.0 <= gchi.min() and np.median(gchi) < 1.1
