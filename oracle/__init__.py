@@ -58,6 +58,8 @@ def lib():
         L.orc_advect.restype = ctypes.c_int
         L.orc_drop_shapes.argtypes = [i64, i64, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp]
         L.orc_drop_shapes.restype = ctypes.c_int
+        L.orc_csf_force.argtypes = [i64, i64, i64, i32, vp, vp, d, vp, vp, vp]
+        L.orc_csf_force.restype = None
         L.orc_label.argtypes = [i64, i64, i64, vp, d, vp]
         L.orc_label.restype = ctypes.c_int
         L.orc_drop_moments.argtypes = [i64, i64, i64, vp, vp, i32, vp, vp]
@@ -201,6 +203,24 @@ def aspect_ratio(inertia):
     T[:, 1, 2] = T[:, 2, 1] = inertia[:, 5]
     ev = np.linalg.eigvalsh(T) if len(T) else np.zeros((0, 3))
     return ev, np.sqrt(ev[:, 2] / ev[:, 0]) if len(T) else np.zeros(0)
+
+
+def csf_force(c, kappa, gamma: float):
+    """Face-centred surface-tension force gamma * sum_i kappa_i grad C_i on the
+    lower faces, (fx, fy, fz) each [nz][ny][nx] (section "The no-coalescence.h
+    algorithm", balanced-force form). c, kappa: [ntr][nz][ny][nx], NaN where
+    a curvature is undefined."""
+    c = _f64(c)
+    kappa = _f64(kappa)
+    if c.ndim == 3:
+        c, kappa = c[None], kappa[None]
+    assert c.shape == kappa.shape
+    ntr = c.shape[0]
+    nx, ny, nz = _shape3(c)
+    out = [np.zeros(c.shape[1:]) for _ in range(3)]
+    lib().orc_csf_force(nx, ny, nz, ntr, c.ctypes.data, kappa.ctypes.data, float(gamma),
+                        *[o.ctypes.data for o in out])
+    return tuple(out)
 
 
 def neighbour_pairs(labels, ndrops, tau: float):

@@ -463,6 +463,49 @@ int orc_drop_shapes(int64_t nx, int64_t ny, int64_t nz, const double *c, const i
 }
 
 /* =========================================================================
+ * Multi-tracer surface-tension force (section "The no-coalescence.h
+ * algorithm": the force is the sum over the tracers of gamma kappa_i grad C_i,
+ * each kappa_i computed as for a single tracer), in the balanced-force
+ * face-centred form the paper refers to (Popinet 2018, section "Numerical
+ * method"): on the lower d-face of cell p, between m = p - e_d and p,
+ *   F_d[p] = gamma * sum_i phi_i (C_i[p] - C_i[m]),
+ * with phi_i the mean of kappa_i[p] and kappa_i[m] where both are defined,
+ * the defined one where only one is, and no contribution where neither is
+ * or where C_i[p] == C_i[m]. Undefined curvature is NaN (as the height
+ * functions leave it off the interface). Cell units: kappa in 1/cells, the
+ * difference per cell width. Tracers are summed in increasing order.
+ * c, kappa: [ntr][nz][ny][nx]; fx, fy, fz: [nz][ny][nx] outputs.
+ * ========================================================================= */
+static double csf_face(double cp, double cm, double kp, double km) {
+  double d = cp - cm;
+  if (d == 0.0) return 0.0;
+  int hp = !isnan(kp), hm = !isnan(km);
+  if (hp && hm) return ((kp + km) / 2.0) * d;
+  if (hp) return kp * d;
+  if (hm) return km * d;
+  return 0.0;
+}
+
+void orc_csf_force(int64_t nx, int64_t ny, int64_t nz, int32_t ntr, const double *c, const double *kappa,
+                   double gamma, double *fx, double *fy, double *fz) {
+  int64_t n3 = nx * ny * nz;
+  double *f[3] = {fx, fy, fz};
+  for (int64_t p = 0; p < n3; ++p) {
+    int64_t i = p % nx, j = (p / nx) % ny, k = p / (nx * ny);
+    int64_t m[3] = {wrapi(i - 1, nx) + nx * (j + ny * k), i + nx * (wrapi(j - 1, ny) + ny * k),
+                    i + nx * (j + ny * wrapi(k - 1, nz))};
+    for (int d = 0; d < 3; ++d) {
+      double sum = 0.0;
+      for (int32_t t = 0; t < ntr; ++t) {
+        const double *ct = c + (int64_t)t * n3, *kt = kappa + (int64_t)t * n3;
+        sum += csf_face(ct[p], ct[m[d]], kt[p], kt[m[d]]);
+      }
+      f[d][p] = gamma * sum;
+    }
+  }
+}
+
+/* =========================================================================
  * Tracer recolouring: Steps 1-4 of the no-coalescence algorithm.
  * Reading: drops are (tracer t, label l); two distinct drops are neighbours
  * when occupied cells p, q of each satisfy |o|^2 < (1+tau)^2 for the periodic
