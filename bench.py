@@ -191,6 +191,21 @@ def rows_bench(torch, np, ctx, stream, c, w, n, ntr):
     log(f"curvature: HF {ms_hf:.2f} ms (kernel {hf_kernel_ms:.3f}), MLP+HF {ms_comb:.2f} ms (kernels "
         f"{mlp_kernel_ms:.3f}), forward alone {fwd_ms:.3f} ms ({fwd_tflops:.1f} TFLOP/s) on {nmix} mixed cells")
     del kap, st, xs, cell, sg, y
+    # ---- surface-tension force of all tracers, curvature by height functions
+    kap8 = torch.empty(c.shape, dtype=torch.float64, device=dev)
+    st8 = torch.empty(c.shape, dtype=torch.uint8, device=dev)
+    for t in range(ntr):
+        ctx.curvature_hf(c[t], kap8[t], st8[t])
+    del st8
+    fxyz = [torch.empty(tuple(c.shape[1:]), dtype=torch.float64, device=dev) for _ in range(3)]
+    ctx.csf_force(c, kap8, 1.0, *fxyz)
+    ms, _ = timed(torch, stream, lambda: ctx.csf_force(c, kap8, 1.0, *fxyz))
+    csf_bytes = n3 * (16.0 * ntr + 24.0)  # every tracer's c and kappa read once, three face arrays written
+    rows["csf_force"] = dict(ms=ms, cells_per_s=n3 / (ms / 1e3), algorithmic_bytes=csf_bytes,
+                             achieved_gbs=csf_bytes / (ms / 1e3) / 1e9,
+                             hbm_frac=csf_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS)
+    log(f"csf_force: {ms:.2f} ms, {rows['csf_force']['achieved_gbs']:.0f} GB/s of the method's bytes")
+    del kap8, fxyz
     # ---- training step throughput (batch 4096)
     bsz = 4096
     rng = synth.Splitmix64(5)

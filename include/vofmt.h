@@ -229,6 +229,28 @@ int vofmt_nearest_pair_stats(vofmt_ctx *ctx, int32_t n, const double *xyz, const
 int vofmt_curvature_hf(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, const double *c, double *kappa,
                        uint8_t *status, hipStream_t stream);
 
+/*
+ * Surface-tension force of all tracers on the cell faces: the sum over the
+ * tracers of gamma kappa_i grad C_i (section "The no-coalescence.h
+ * algorithm"), in the balanced-force face-centred form (Popinet 2018). On the
+ * lower d-face of cell p, between m = p - e_d (periodic) and p:
+ *   F_d[p] = gamma * sum_i phi_i (C_i[p] - C_i[m]),
+ * phi_i = (kappa_i[p] + kappa_i[m]) / 2 where both are defined, the defined
+ * one where only one is; no contribution where neither is or where C_i[p] ==
+ * C_i[m]. Tracers are summed in increasing order, then scaled by gamma.
+ *
+ * c     : [ntracers][nz][ny][nx] FP64 volume fractions.
+ * kappa : [ntracers][nz][ny][nx] FP64 curvature kappa*Delta (as written by
+ *         vofmt_curvature_hf or vofmt_curvature_mlp), NaN where undefined.
+ * gamma : surface-tension coefficient (finite).
+ * fx, fy, fz: [nz][ny][nx] FP64 outputs on the lower x-, y- and z-faces, in
+ *         units of gamma per cell width squared; with ntracers == 0 they are
+ *         set to zero.
+ * Streams every tracer's c and kappa once; no scratch memory.
+ */
+int vofmt_csf_force(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t ntracers, const double *c,
+                    const double *kappa, double gamma, double *fx, double *fy, double *fz, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Learned curvature (not in the paper, which uses height functions): a
  * multilayer perceptron 27 (zero-padded to 32) -> 128 -> 128 -> 1 with ReLU,

@@ -1,0 +1,140 @@
+// Multi-tracer surface-tension force on the cell faces.
+//
+// The force is the sum over the tracers of gamma kappa_i grad C_i, each
+// curvature computed as for a single tracer (section "The no-coalescence.h
+// algorithm"), here in the balanced-force face-centred form (Popinet 2018,
+// referred to in section "Numerical method"): on the lower d-face of cell p,
+// between m = p - e_d and p,
+//   F_d[p] = gamma * sum_i phi_i (C_i[p] - C_i[m]),
+// phi_i the mean of kappa_i[p] and kappa_i[m] where both are defined, the
+// defined one where one is, no contribution where neither is or where C_i
+// does not jump. Undefined curvature is NaN. The tracers are summed in
+// increasing order, then scaled by gamma.
+//
+// One pass streams every tracer's C and kappa once: a wavefront holds 64
+// consecutive cells of a row, a workgroup four rows, and each thread marches
+// kZC planes along z keeping the previous plane's C and kappa of its tracers
+// in registers; the x and y neighbours are re-read through the caches.
+#include <cmath>
+
+#include "common.hpp"
+
+namespace {
+
+constexpr int kTX = 64, kTY = 4, kZC = 16;
+constexpr int kMaxGroup = 8;
+
+// Branch-free (selects only), so that every load of a plane is issued before
+// the first use.
+__device__ __forceinline__ double face_term(double cp, double cm, double kp, double km) {
+  const double d = cp - cm;
+  const bool hp = kp == kp, hm = km == km;  // defined: not NaN
+  const double phi = hp ? (hm ? (kp + km) * 0.5 : kp) : km;
+  return (d == 0.0 || !(hp || hm)) ? 0.0 : phi * d;
+}
+
+// Tracers [t0, t0 + G): the running sums start from 0 (first group) or from
+// the partial sums stored by the previous group, and the last group stores
+// gamma times the sums.
+template <int G>
+__global__ __launch_bounds__(kTX *kTY) void k_csf(const double *__restrict__ c, const double *__restrict__ kap,
+                                                  int nx, int ny, int nz, int t0, double gamma, int first, int last,
+                                                  double *__restrict__ fx, double *__restrict__ fy,
+                                                  double *__restrict__ fz) {
+  const int x = blockIdx.x * kTX + (threadIdx.x & (kTX - 1));
+  const int y = blockIdx.y * kTY + (threadIdx.x / kTX);
+  if (x >= nx || y >= ny) return;
+  const int z0 = blockIdx.z * kZC;
+  const int z1 = z0 + kZC < nz ? z0 + kZC : nz;
+  const int xm = x == 0 ? nx - 1 : x - 1, ym = y == 0 ? ny - 1 : y - 1;
+  const int64_t n3 = (int64_t)nx * ny * nz, plane = (int64_t)nx * ny;
+  const double *ct = c + (int64_t)t0 * n3;
+  const double *kt = kap + (int64_t)t0 * n3;
+  double cz[G > 0 ? G : 1], kz[G > 0 ? G : 1];
+  {
+    const int64_t q = (int64_t)(z0 == 0 ? nz - 1 : z0 - 1) * plane + (int64_t)y * nx + x;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      cz[g] = ct[g * n3 + q];
+      kz[g] = kt[g * n3 + q];
+    }
+  }
+  for (int z = z0; z < z1; ++z) {
+    const int64_t row = (int64_t)z * plane + (int64_t)y * nx;
+    const int64_t p = row + x, pxm = row + xm, pym = (int64_t)z * plane + (int64_t)ym * nx + x;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    if (!first) {
+      sx = fx[p];
+      sy = fy[p];
+      sz = fz[p];
+    }
+    double cp[G > 0 ? G : 1], kp[G > 0 ? G : 1], cxm[G > 0 ? G : 1], kxm[G > 0 ? G : 1], cym[G > 0 ? G : 1],
+        kym[G > 0 ? G : 1];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      cp[g] = ct[g * n3 + p];
+      kp[g] = kt[g * n3 + p];
+      cxm[g] = ct[g * n3 + pxm];
+      kxm[g] = kt[g * n3 + pxm];
+      cym[g] = ct[g * n3 + pym];
+      kym[g] = kt[g * n3 + pym];
+    }
+    // keep the plane's loads together, ahead of their first use
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      sx += face_term(cp[g], cxm[g], kp[g], kxm[g]);
+      sy += face_term(cp[g], cym[g], kp[g], kym[g]);
+      sz += face_term(cp[g], cz[g], kp[g], kz[g]);
+      cz[g] = cp[g];
+      kz[g] = kp[g];
+    }
+    if (last) {
+      sx = gamma * sx;
+      sy = gamma * sy;
+      sz = gamma * sz;
+    }
+    fx[p] = sx;
+    fy[p] = sy;
+    fz[p] = sz;
+  }
+}
+
+template <int G>
+void launch_csf(dim3 grid, hipStream_t stream, const double *c, const double *kap, int nx, int ny, int nz, int t0,
+                double gamma, int first, int last, double *fx, double *fy, double *fz) {
+  hipLaunchKernelGGL(k_csf<G>, grid, dim3(kTX * kTY), 0, stream, c, kap, nx, ny, nz, t0, gamma, first, last, fx, fy,
+                     fz);
+}
+
+}  // namespace
+
+extern "C" int vofmt_csf_force(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t ntracers,
+                               const double *c, const double *kappa, double gamma, double *fx, double *fy, double *fz,
+                               hipStream_t stream) {
+  if (!ctx) return VOFMT_E_ARG;
+  if (nx < 1 || ny < 1 || nz < 1 || ntracers < 0) return set_err(ctx, VOFMT_E_ARG, "vofmt_csf_force: bad sizes");
+  if (!std::isfinite(gamma)) return set_err(ctx, VOFMT_E_ARG, "vofmt_csf_force: gamma is not finite");
+  if (!fx || !fy || !fz || (ntracers > 0 && (!c || !kappa)))
+    return set_err(ctx, VOFMT_E_ARG, "vofmt_csf_force: null pointer");
+  VOFMT_HIP(ctx, hipSetDevice(ctx->device));
+  const dim3 grid(ceil_div(nx, kTX), ceil_div(ny, kTY), ceil_div(nz, kZC));
+  if (ntracers == 0) {  // no interface: zero force
+    launch_csf<0>(grid, stream, c, kappa, nx, ny, nz, 0, gamma, 1, 1, fx, fy, fz);
+    return hip_check(ctx, hipGetLastError(), "k_csf");
+  }
+  for (int t0 = 0; t0 < ntracers;) {
+    const int left = ntracers - t0;
+    const int g = left >= kMaxGroup ? kMaxGroup : (left >= 4 ? 4 : (left >= 2 ? 2 : 1));
+    const int first = t0 == 0, last = t0 + g == ntracers;
+    switch (g) {
+      case 8: launch_csf<8>(grid, stream, c, kappa, nx, ny, nz, t0, gamma, first, last, fx, fy, fz); break;
+      case 4: launch_csf<4>(grid, stream, c, kappa, nx, ny, nz, t0, gamma, first, last, fx, fy, fz); break;
+      case 2: launch_csf<2>(grid, stream, c, kappa, nx, ny, nz, t0, gamma, first, last, fx, fy, fz); break;
+      default: launch_csf<1>(grid, stream, c, kappa, nx, ny, nz, t0, gamma, first, last, fx, fy, fz); break;
+    }
+    VOFMT_HIP(ctx, hipGetLastError());
+    t0 += g;
+  }
+  return VOFMT_OK;
+}

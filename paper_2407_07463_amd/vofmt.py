@@ -46,6 +46,7 @@ _SIGNATURES = {
     "vofmt_set_advect_pairs": (ctypes.c_int, [_vp, _i32]),
     "vofmt_label_drops": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _d, _vp, _vp, _vp]),
     "vofmt_drop_moments": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "vofmt_csf_force": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _d, _vp, _vp, _vp, _vp]),
     "vofmt_drop_shapes": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                          _vp]),
     "vofmt_recolor_tracers": (ctypes.c_int, [_vp, _i32, _i32, _i32, _P_i32, _i32, _vp, _vp, _vp, _d, _vp, _P_i32,
@@ -249,6 +250,17 @@ class Context:
         return self._check(load().vofmt_drop_shapes(self.h, nx, ny, nz, ntr, _ptr(c), _ptr(labels), nd.ctypes.data,
                                                     *sp, _ptr(inertia), _ptr(chi),
                                                     _ptr(vel) if vel is not None else None, _stream(stream)))
+
+    def csf_force(self, c, kappa, gamma: float, fx, fy, fz, stream=None):
+        """Surface-tension force on the lower faces; c, kappa: [N][nz][ny][nx]
+        (or one field [nz][ny][nx]); fx, fy, fz: [nz][ny][nx]."""
+        _require(c, kappa, fx, fy, fz)
+        if tuple(c.shape) != tuple(kappa.shape):
+            raise ValueError("csf_force: c and kappa differ in shape")
+        nx, ny, nz = _dims(c)
+        ntr = int(c.shape[0]) if c.dim() == 4 else 1
+        return self._check(load().vofmt_csf_force(self.h, nx, ny, nz, ntr, _ptr(c), _ptr(kappa), float(gamma),
+                                                  _ptr(fx), _ptr(fy), _ptr(fz), _stream(stream)))
 
     def recolor_tracers(self, c, ntracers: int, labels, ndrops, gap_cells: float, new_tracer, stream=None):
         """c: [max_tracers][nz][ny][nx]; returns (ntracers_after, nmoved)."""

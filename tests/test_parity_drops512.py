@@ -13,7 +13,8 @@ values, cells outside drops stay where they were, and the moved count is the
 number of drops whose tracer changed. Curvature: statuses bit-exact, values
 within 1e-12 where the height function is valid, NaN elsewhere. Drop
 shapes (inertia tensors, aspect ratios, mean velocities): the bars of
-test_parity_shapes.py.
+test_parity_shapes.py. Surface-tension force of all eight tracers:
+bit-exact.
 """
 import numpy as np
 import pytest
@@ -191,3 +192,24 @@ def test_drop_shapes(ctx, drops512, oracle_labels):
     assert np.abs(gvel - ov).max() <= 1e-13
     # round drops: the aspect ratio is close to 1
     assert 1.0 <= gchi.min() and np.median(gchi) < 1.1
+
+
+def test_csf_force(ctx, drops512):
+    """All eight tracers, with a synthetic curvature on the interface cells
+    (0.3 (0.5 - c), NaN elsewhere) so that every branch of the face rule
+    occurs."""
+    import torch
+
+    c = drops512["c"]
+    kap = np.where((c > 0) & (c < 1), 0.3 * (0.5 - c), np.nan)
+    note("csf force drops512 (full size, 8 tracers)")
+    shape = c.shape[1:]
+    f = [torch.zeros(shape, dtype=torch.float64, device="cuda:0") for _ in range(3)]
+    tc, tk = torch.from_numpy(c).to("cuda:0"), torch.from_numpy(kap).to("cuda:0")
+    ctx.csf_force(tc, tk, 0.05, *f)
+    torch.cuda.synchronize()
+    del tc, tk
+    g = [a.cpu().numpy() for a in f]
+    o = oracle.csf_force(c, kap, 0.05)
+    for d in range(3):
+        assert np.array_equal(g[d].view(np.uint64), o[d].view(np.uint64)), d
