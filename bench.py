@@ -24,7 +24,8 @@ training, and batched advection of 32 uneven boxes (graph launch vs plain
 launches); and under `cpu_baseline` the CPU oracle timed on a bounded sample.
 
 --pmc-pass: a short run for rocprofv3 counter collection: a plain copy of
-1 GiB (the calibration kernel) then 2 advection steps; prints one line.
+1 GiB (the calibration kernel), 2 advection steps, then two surface-tension
+force evaluations of the advected tracers; prints one line.
 """
 from __future__ import annotations
 
@@ -292,8 +293,16 @@ def main():
         for _ in range(3):
             torch.mul(src, 1.0, out=dst)  # calibration: reads and writes COPY_BYTES
         ctx.advect(c, *s, step0=0, nsteps=2)
+        # the surface-tension force of the advected tracers (curvature by height functions)
+        kap8 = torch.empty(c.shape, dtype=torch.float64, device=dev)
+        st8 = torch.empty(c.shape, dtype=torch.uint8, device=dev)
+        for t in range(ntr):
+            ctx.curvature_hf(c[t], kap8[t], st8[t])
+        fxyz = [torch.empty(tuple(c.shape[1:]), dtype=torch.float64, device=dev) for _ in range(3)]
+        for _ in range(2):
+            ctx.csf_force(c, kap8, 1.0, *fxyz)
         torch.cuda.synchronize()
-        print(json.dumps({"pmc_pass": True, "copy_bytes": COPY_BYTES, "steps": 2}), flush=True)
+        print(json.dumps({"pmc_pass": True, "copy_bytes": COPY_BYTES, "steps": 2, "csf_calls": 2}), flush=True)
         ctx.close()
         return
 

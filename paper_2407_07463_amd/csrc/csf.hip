@@ -14,7 +14,9 @@
 // One pass streams every tracer's C and kappa once: a wavefront holds 64
 // consecutive cells of a row, a workgroup four rows, and each thread marches
 // kZC planes along z keeping the previous plane's C and kappa of its tracers
-// in registers; the x and y neighbours are re-read through the caches.
+// in registers; the x and y neighbours are re-read through the caches (the
+// halo rows and columns of a tile cost about a third more reads than the
+// fields' size).
 #include <cmath>
 
 #include "common.hpp"
@@ -41,10 +43,19 @@ __global__ __launch_bounds__(kTX *kTY) void k_csf(const double *__restrict__ c, 
                                                   int nx, int ny, int nz, int t0, double gamma, int first, int last,
                                                   double *__restrict__ fx, double *__restrict__ fy,
                                                   double *__restrict__ fz) {
-  const int x = blockIdx.x * kTX + (threadIdx.x & (kTX - 1));
-  const int y = blockIdx.y * kTY + (threadIdx.x / kTX);
+  // XCD-aware tile order: workgroups are dealt to the 8 XCDs in turn, so the
+  // hardware id is mapped to a tile index that gives each XCD a contiguous
+  // run of tiles; neighbouring tiles (whose rows are each other's halo) then
+  // share an L2.
+  const unsigned nwg = gridDim.x, id = blockIdx.x;
+  const unsigned per = nwg / 8, rem = nwg % 8, xk = id % 8;
+  const unsigned L = xk * per + (xk < rem ? xk : rem) + id / 8;
+  const unsigned tx = (nx + kTX - 1) / kTX, ty = (ny + kTY - 1) / kTY;
+  const unsigned bx = L % tx, by = (L / tx) % ty, bz = L / (tx * ty);
+  const int x = bx * kTX + (threadIdx.x & (kTX - 1));
+  const int y = by * kTY + (threadIdx.x / kTX);
   if (x >= nx || y >= ny) return;
-  const int z0 = blockIdx.z * kZC;
+  const int z0 = bz * kZC;
   const int z1 = z0 + kZC < nz ? z0 + kZC : nz;
   const int xm = x == 0 ? nx - 1 : x - 1, ym = y == 0 ? ny - 1 : y - 1;
   const int64_t n3 = (int64_t)nx * ny * nz, plane = (int64_t)nx * ny;
@@ -118,7 +129,9 @@ extern "C" int vofmt_csf_force(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t n
   if (!fx || !fy || !fz || (ntracers > 0 && (!c || !kappa)))
     return set_err(ctx, VOFMT_E_ARG, "vofmt_csf_force: null pointer");
   VOFMT_HIP(ctx, hipSetDevice(ctx->device));
-  const dim3 grid(ceil_div(nx, kTX), ceil_div(ny, kTY), ceil_div(nz, kZC));
+  const int64_t tiles = (int64_t)ceil_div(nx, kTX) * ceil_div(ny, kTY) * ceil_div(nz, kZC);
+  if (tiles > INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "vofmt_csf_force: grid too large");
+  const dim3 grid((unsigned)tiles);
   if (ntracers == 0) {  // no interface: zero force
     launch_csf<0>(grid, stream, c, kappa, nx, ny, nz, 0, gamma, 1, 1, fx, fy, fz);
     return hip_check(ctx, hipGetLastError(), "k_csf");

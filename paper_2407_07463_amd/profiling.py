@@ -29,9 +29,11 @@ ADVECT_SOURCES = ["csrc/advect_kernels.hpp", "csrc/pair_kernels.hpp", "csrc/plic
                   "csrc/common.hpp"]
 
 
-def advect_source_sha() -> str:
+def advect_source_sha(sources=None) -> str:
+    """SHA-256 over the given sources (paths relative to the package;
+    default: the advection kernels)."""
     h = hashlib.sha256()
-    for rel in ADVECT_SOURCES:
+    for rel in sources or ADVECT_SOURCES:
         with open(os.path.join(PKG, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -109,7 +111,8 @@ def write_stats(directory, out, command, title):
     return st
 
 
-def write_traffic(fetch_dir, write_dir, kernel_re, copy_re, copy_bytes, out, command_fetch, command_write):
+def write_traffic(fetch_dir, write_dir, kernel_re, copy_re, copy_bytes, out, command_fetch, command_write,
+                  sources=None):
     fe = counter_means(fetch_dir, "FETCH_SIZE")
     wr = counter_means(write_dir, "WRITE_SIZE")
     kre, cre = re.compile(kernel_re), re.compile(copy_re)
@@ -129,7 +132,8 @@ def write_traffic(fetch_dir, write_dir, kernel_re, copy_re, copy_bytes, out, com
              f"{copy_bytes} B per dispatch",
              f"copy_fetch_factor = {f_factor:.6f}   (FETCH_SIZE KiB / true KiB read)",
              f"copy_write_factor = {w_factor:.6f}   (WRITE_SIZE KiB / true KiB written)",
-             f"advect_source_sha256 = {advect_source_sha()}", ""]
+             (f"advect_source_sha256 = {advect_source_sha()}" if not sources else
+              f"source_sha256 = {advect_source_sha(sources)}   ({', '.join(sources)})"), ""]
     for k in sorted(set(fe) | set(wr)):
         if not kre.search(k):
             continue
@@ -175,13 +179,16 @@ def main(argv=None):
     b.add_argument("--out", required=True)
     b.add_argument("--command-fetch", required=True)
     b.add_argument("--command-write", required=True)
+    b.add_argument("--sources", nargs="*", default=None,
+                   help="sources of the counted kernel (relative to the package) whose hash the summary records; "
+                        "default: the advection kernels")
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         for name, calls, t, avg in write_stats(args.dir, args.out, args.command, args.title)[:12]:
             print(f"{name:60s} {calls:6d} {t / 1e6:10.3f} ms {avg / 1e3:10.2f} us")
     else:
         write_traffic(args.fetch, args.write, args.kernel, args.copy, args.copy_bytes, args.out,
-                      args.command_fetch, args.command_write)
+                      args.command_fetch, args.command_write, args.sources)
         print(open(args.out).read())
 
 
