@@ -260,7 +260,9 @@ __global__ __launch_bounds__(kBlock) void k_label_rank(const uint64_t *__restric
 
 // Pass 5: label of every cell of the field (0 for empty cells). The
 // occupancy words, then the run entries, then the roots' entries of the
-// wavefront's kSegs segments are each loaded together.
+// wavefront's kSegs segments are each loaded together: every lane loads
+// (from a valid slot when it has no cell) and selects afterwards, since a
+// load under a lane condition is compiled as a branch that waits for it.
 __global__ __launch_bounds__(kBlock) void k_label_write(const uint64_t *__restrict__ occ,
                                                         const int32_t *__restrict__ R, int32_t *__restrict__ lab,
                                                         int nx, int ny, int nz, int words, int S, SegDiv dv) {
@@ -270,15 +272,18 @@ __global__ __launch_bounds__(kBlock) void k_label_write(const uint64_t *__restri
   int32_t e[kSegs];
 #pragma unroll
   for (int k = 0; k < kSegs; ++k) m[k] = (s0 + k < nseg) ? occ[s0 + k] : 0ull;
+  bool on[kSegs];
 #pragma unroll
   for (int k = 0; k < kSegs; ++k) {
-    e[k] = 0;
-    if ((m[k] >> lane) & 1ull) e[k] = R[(s0 + k) * S + run_index(m[k], lane)];
+    on[k] = (m[k] >> lane) & 1ull;
+    const int64_t sg = (s0 + k < nseg) ? s0 + k : nseg - 1;
+    e[k] = R[sg * S + (on[k] ? run_index(m[k], lane) : 0)];
   }
+  int32_t root[kSegs];
 #pragma unroll
-  for (int k = 0; k < kSegs; ++k) {
-    if ((m[k] >> lane) & 1ull) e[k] = (e[k] < 0) ? -e[k] : -R[e[k]];
-  }
+  for (int k = 0; k < kSegs; ++k) root[k] = R[(on[k] && e[k] >= 0) ? e[k] : 0];
+#pragma unroll
+  for (int k = 0; k < kSegs; ++k) e[k] = on[k] ? ((e[k] < 0) ? -e[k] : -root[k]) : 0;
 #pragma unroll
   for (int k = 0; k < kSegs; ++k) {
     const int64_t sgi = s0 + k;
