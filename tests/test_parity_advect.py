@@ -57,7 +57,10 @@ def test_spheres64(ctx, spheres64, nsteps):
 
 
 @pytest.mark.parametrize("shape,ntr,step0,nsteps", [((17, 23, 19), 3, 0, 4), ((31, 9, 70), 2, 1, 3),
-                                                    ((5, 7, 130), 1, 2, 2), ((3, 3, 3), 2, 0, 2)])
+                                                    ((5, 7, 130), 1, 2, 2), ((3, 3, 3), 2, 0, 2),
+                                                    # several tracer groups per sweep (4 + 2, 4 + 4, 4 + 4 + 1)
+                                                    ((17, 23, 19), 6, 0, 3), ((12, 10, 64), 8, 1, 2),
+                                                    ((32, 32, 32), 9, 0, 2)])
 def test_odd_grids_random_velocity(ctx, shape, ntr, step0, nsteps):
     nz, ny, nx = shape
     rng = synth.Splitmix64(1234 + nx)
