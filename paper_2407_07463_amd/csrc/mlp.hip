@@ -32,6 +32,20 @@
 
 namespace {
 
+// Sum of each row of 16 lanes, received by every lane of the row, with the
+// additions of the butterfly v + v[lane ^ 8], ^ 4, ^ 2, ^ 1 in the same order
+// and on the same operands: after each step the partial sums repeat with the
+// step's period, so rotating the row by the step reads the value the
+// butterfly would. DPP row rotations (row_ror:8, 4, 2, 1) instead of LDS
+// permutes. Every lane of the wavefront must be active.
+__device__ __forceinline__ float row16_sum(float v) {
+  v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false));
+  v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xf, 0xf, false));
+  v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x122, 0xf, 0xf, false));
+  v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x121, 0xf, 0xf, false));
+  return v;
+}
+
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
@@ -183,10 +197,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ P, co
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         float v = yp[mt][r];
-        v = v + __shfl_xor(v, 8, 64);
-        v = v + __shfl_xor(v, 4, 64);
-        v = v + __shfl_xor(v, 2, 64);
-        v = v + __shfl_xor(v, 1, 64);
+        v = row16_sum(v);
         if (lr == 0) ypart[w][16 * mt + 4 * lq + r] = v;
       }
     __syncthreads();
@@ -615,10 +626,7 @@ __global__ __launch_bounds__(64 * FWAVES) void k_curv_fused(
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
           float v = yq[g][mt][r];
-          v = v + __shfl_xor(v, 8, 64);
-          v = v + __shfl_xor(v, 4, 64);
-          v = v + __shfl_xor(v, 2, 64);
-          v = v + __shfl_xor(v, 1, 64);
+          v = row16_sum(v);
           part[g] = v;
         }
         ysum[mt][r] = (((part[0] + part[1]) + part[2]) + part[3]) + b3;
@@ -754,10 +762,7 @@ __global__ __launch_bounds__(64 * FWAVES) void k_mlp_infer(const float *__restri
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
           float v = yq[g][mt][r];
-          v = v + __shfl_xor(v, 8, 64);
-          v = v + __shfl_xor(v, 4, 64);
-          v = v + __shfl_xor(v, 2, 64);
-          v = v + __shfl_xor(v, 1, 64);
+          v = row16_sum(v);
           part[g] = v;
         }
         if (lr == 0) yb[w][16 * mt + 4 * lq + r] = (((part[0] + part[1]) + part[2]) + part[3]) + b3;
