@@ -692,18 +692,36 @@ __global__ __launch_bounds__(64 * FWAVES) void k_mlp_infer(const float *__restri
   __syncthreads();
   const int lr = lane & 15, lq = lane >> 4;
   const int ntiles = (m + FT - 1) / FT;
-  for (int tile = blockIdx.x * FWAVES + w; tile < ntiles; tile += gridDim.x * FWAVES) {
-    const int s0 = tile * FT;
-    // ---- the tile's inputs: FT x 27 consecutive values, split into hi + lo
+  // A tile's inputs are FT x 27 consecutive values, NV per lane; the next
+  // tile's are loaded while the current one is computed.
+  constexpr int NV = (FT * 27 + 63) / 64;
+  float xv[NV];
+  auto load_inputs = [&](int t) {
+    const int s0 = t * FT;
     const int nvals = ((m - s0 < FT) ? m - s0 : FT) * 27;
-    for (int i = lane; i < FT * 27; i += 64) {
-      const int sr = i / 27, k = i - 27 * sr;
-      const float v = (i < nvals) ? x[(int64_t)s0 * 27 + i] : 0.0f;
-      const uint16_t hi = bf16_bits(v);
-      Xh[w][sr][k] = hi;
-      Xl[w][sr][k] = bf16_bits(v - bf16_val(hi));
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int i = lane + 64 * q;
+      xv[q] = (i < nvals) ? x[(int64_t)s0 * 27 + i] : 0.0f;
+    }
+  };
+  const int tstride = gridDim.x * FWAVES;
+  if (blockIdx.x * FWAVES + w < ntiles) load_inputs(blockIdx.x * FWAVES + w);
+  for (int tile = blockIdx.x * FWAVES + w; tile < ntiles; tile += tstride) {
+    const int s0 = tile * FT;
+    // ---- the tile's inputs, split into hi + lo
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int i = lane + 64 * q;
+      if (i < FT * 27) {
+        const int sr = i / 27, k = i - 27 * sr;
+        const uint16_t hi = bf16_bits(xv[q]);
+        Xh[w][sr][k] = hi;
+        Xl[w][sr][k] = bf16_bits(xv[q] - bf16_val(hi));
+      }
     }
     wave_sync();
+    if (tile + tstride < ntiles) load_inputs(tile + tstride);
     // ---- layer 1: FT rows x 128 columns
 #pragma unroll
     for (int mt = 0; mt < FT / 16; ++mt)
