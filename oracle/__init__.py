@@ -60,6 +60,8 @@ def lib():
         L.orc_drop_shapes.restype = ctypes.c_int
         L.orc_csf_force.argtypes = [i64, i64, i64, i32, vp, vp, d, vp, vp, vp]
         L.orc_csf_force.restype = None
+        L.orc_compact_tracers.argtypes = [i64, i32, vp, vp, vp, vp]
+        L.orc_compact_tracers.restype = ctypes.c_int
         L.orc_label.argtypes = [i64, i64, i64, vp, d, vp]
         L.orc_label.restype = ctypes.c_int
         L.orc_drop_moments.argtypes = [i64, i64, i64, vp, vp, i32, vp, vp]
@@ -221,6 +223,21 @@ def csf_force(c, kappa, gamma: float):
     lib().orc_csf_force(nx, ny, nz, ntr, c.ctypes.data, kappa.ctypes.data, float(gamma),
                         *[o.ctypes.data for o in out])
     return tuple(out)
+
+
+def compact_tracers(c, ndrops):
+    """Retire the tracers without drops (reading of the tracer count N(t),
+    section "The no-coalescence.h algorithm"). c: [ntr][nz][ny][nx] (copied).
+    Returns (c_new, n_new, new_index[ntr], discarded volume)."""
+    c = np.array(c, dtype=np.float64, order="C", copy=True)
+    ntr = c.shape[0]
+    n3 = int(np.prod(c.shape[1:]))
+    nd = np.ascontiguousarray(ndrops, dtype=np.int32)
+    assert len(nd) == ntr
+    idx = np.zeros(ntr, dtype=np.int32)
+    disc = ctypes.c_double(0.0)
+    k = lib().orc_compact_tracers(n3, ntr, c.ctypes.data, nd.ctypes.data, idx.ctypes.data, ctypes.byref(disc))
+    return c, int(k), idx, disc.value
 
 
 def neighbour_pairs(labels, ndrops, tau: float):

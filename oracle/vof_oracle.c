@@ -670,6 +670,35 @@ int orc_recolor(int64_t nx, int64_t ny, int64_t nz, int32_t *ntracers, int32_t m
 }
 
 /* =========================================================================
+ * Tracer compaction. The paper reports the number of tracers in use, N(t)
+ * (section "The no-coalescence.h algorithm"), and notes that its algorithm
+ * could be optimised. Reading: a tracer holding no drop is retired; the
+ * other fields keep their order and move down over the gaps; the freed
+ * fields are zeroed. The retired fields' values (none above the labelling
+ * threshold) are summed, tracer by tracer and cell by cell, into
+ * *discarded. new_index[t] is the new position of tracer t or -1. Returns
+ * the new tracer count.
+ * ========================================================================= */
+int orc_compact_tracers(int64_t n3, int32_t ntr, double *c, const int32_t *ndrops, int32_t *new_index,
+                        double *discarded) {
+  double sum = 0.0;
+  int32_t k = 0;
+  for (int32_t t = 0; t < ntr; ++t) {
+    if (ndrops[t] > 0) {
+      new_index[t] = k;
+      if (k != t) memcpy(c + (int64_t)k * n3, c + (int64_t)t * n3, sizeof(double) * n3);
+      ++k;
+    } else {
+      new_index[t] = -1;
+      for (int64_t p = 0; p < n3; ++p) sum += c[(int64_t)t * n3 + p];
+    }
+  }
+  for (int32_t t = k; t < ntr; ++t) memset(c + (int64_t)t * n3, 0, sizeof(double) * n3);
+  *discarded = sum;
+  return k;
+}
+
+/* =========================================================================
  * Nearest-particle statistics ("Nearest particle statistics" section,
  * eq. 4 with the tie weight h_ij = 1/N_i, the estimators eqs. 6, 8 and 10,
  * and the moments of eqs. 11 and 14 read as averages over the events:

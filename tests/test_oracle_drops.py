@@ -244,3 +244,28 @@ def test_recolour_near_contact_figure_right():
     c1, ntr, newt, nmoved, rc = oracle.recolor(c, labels, nd, 2, 3, 3.2)
     assert rc == 0 and nmoved == 0 and ntr == 2
     assert np.array_equal(c1, c)
+
+
+def test_compact_tracers_pins():
+    """Tracers 1 and 3 hold no drop, only dust of known size: they are
+    retired, 0, 2, 4 move to 0, 1, 2 unchanged, the freed fields are zero,
+    and the discarded volume is the dust's (exactly representable sums)."""
+    shape = (4, 5, 6)
+    c = np.zeros((5,) + shape)
+    c[0, 1, 1, 1:4] = [0.5, 1.0, 0.25]
+    c[2, 3, 2, 2] = 0.75
+    c[4, 0, 4, 5] = 1.0
+    c[1, 2, 2, 2] = 2.0 ** -30  # dust below the labelling threshold
+    c[3, 0, 0, 0] = 2.0 ** -31
+    nd = [oracle.label(c[t])[1] for t in range(5)]
+    assert nd == [1, 0, 1, 0, 1]
+    out, n, idx, disc = oracle.compact_tracers(c, nd)
+    assert n == 3 and list(idx) == [0, -1, 1, -1, 2]
+    assert np.array_equal(out[0], c[0]) and np.array_equal(out[1], c[2]) and np.array_equal(out[2], c[4])
+    assert not out[3:].any()
+    assert disc == 2.0 ** -30 + 2.0 ** -31
+    # nothing to retire; everything retired
+    out, n, idx, disc = oracle.compact_tracers(c[[0, 2]], [1, 1])
+    assert n == 2 and list(idx) == [0, 1] and disc == 0.0 and np.array_equal(out, c[[0, 2]])
+    out, n, idx, disc = oracle.compact_tracers(c[[1, 3]], [0, 0])
+    assert n == 0 and list(idx) == [-1, -1] and not out.any() and disc == 2.0 ** -30 + 2.0 ** -31
