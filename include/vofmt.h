@@ -186,6 +186,26 @@ int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, in
                           double gap_cells, int32_t *new_tracer, int32_t *nmoved_host, hipStream_t stream);
 
 /*
+ * Tracer compaction: the number of tracers in use, N(t), is what the paper
+ * reports for its runs (section "The no-coalescence.h algorithm"); a tracer
+ * holding no drop (every value at or below the labelling threshold) is
+ * retired here, the other fields keep their order and move down over the
+ * gaps, and the freed fields are set to zero.
+ *
+ * ntracers_host : in: N; out: the tracers kept.
+ * c             : [N][nz][ny][nx] FP64, in place.
+ * ndrops_host   : [N] drop counts (vofmt_label_drops); labels computed
+ *                 before the call are invalid afterwards.
+ * new_index_host: [N] host output, the new position of each tracer or -1.
+ * discarded_host: host output, the sum of the retired fields' values (in a
+ *                 fixed order, reproducible).
+ * Synchronises the stream.
+ */
+int vofmt_compact_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t *ntracers_host, double *c,
+                          const int32_t *ndrops_host, int32_t *new_index_host, double *discarded_host,
+                          hipStream_t stream);
+
+/*
  * Nearest-particle statistics (section "Nearest particle statistics").
  * For each drop i: the minimum-image vectors r_ij = x_j - x_i (per axis:
  * subtract L if r > L/2, add L if r <= -L/2), d2 = (rx^2 + ry^2) + rz^2, the

@@ -442,6 +442,38 @@ __global__ __launch_bounds__(kBlock) void k_move(double *__restrict__ c, const i
   }
 }
 
+// Sum of the retired tracers' fields for the compaction: workgroup b sums
+// cells [b*chunk, (b+1)*chunk) of the concatenation of the retired fields
+// (strided per thread, then a fixed tree); k_sum_parts adds the parts in
+// order. Reproducible bit for bit.
+constexpr int kSumBlock = 256;
+__global__ __launch_bounds__(kSumBlock) void k_sum_retired(const double *__restrict__ c, const int32_t *__restrict__ which,
+                                                          int nret, int64_t n3, int64_t chunk,
+                                                          double *__restrict__ part) {
+  const int64_t total = (int64_t)nret * n3;
+  const int64_t q0 = (int64_t)blockIdx.x * chunk;
+  const int64_t q1 = q0 + chunk < total ? q0 + chunk : total;
+  double acc = 0.0;
+  for (int64_t q = q0 + threadIdx.x; q < q1; q += kSumBlock) {
+    const int64_t r = q / n3;
+    acc += c[(int64_t)which[r] * n3 + (q - r * n3)];
+  }
+  __shared__ double red[kSumBlock];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kSumBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+__global__ void k_sum_parts(const double *__restrict__ part, int n, double *__restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += part[i];
+  *out = s;
+}
+
 }  // namespace
 
 extern "C" int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t *ntracers_host,
@@ -577,5 +609,62 @@ extern "C" int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int
   }
   *ntracers_host = Nnew;
   *nmoved_host = moved;
+  return VOFMT_OK;
+}
+
+extern "C" int vofmt_compact_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t *ntracers_host,
+                                     double *c, const int32_t *ndrops_host, int32_t *new_index_host,
+                                     double *discarded_host, hipStream_t stream) {
+  if (!ctx) return VOFMT_E_ARG;
+  if (nx < 1 || ny < 1 || nz < 1 || !ntracers_host || *ntracers_host < 0)
+    return set_err(ctx, VOFMT_E_ARG, "vofmt_compact_tracers: bad sizes");
+  const int ntr = *ntracers_host;
+  if (ntr > 0 && (!c || !ndrops_host || !new_index_host || !discarded_host))
+    return set_err(ctx, VOFMT_E_ARG, "vofmt_compact_tracers: null pointer");
+  if (discarded_host) *discarded_host = 0.0;
+  if (ntr == 0) return VOFMT_OK;
+  const int64_t n3 = (int64_t)nx * ny * nz;
+  std::vector<int32_t> retired;
+  int k = 0;
+  for (int t = 0; t < ntr; ++t) {
+    if (ndrops_host[t] < 0) return set_err(ctx, VOFMT_E_ARG, "vofmt_compact_tracers: negative drop count");
+    if (ndrops_host[t] > 0) new_index_host[t] = k++;
+    else {
+      new_index_host[t] = -1;
+      retired.push_back(t);
+    }
+  }
+  if (retired.empty()) return VOFMT_OK;
+  VOFMT_HIP(ctx, hipSetDevice(ctx->device));
+  // the discarded volume, before any field moves
+  const int nret = (int)retired.size();
+  const int64_t total = (int64_t)nret * n3;
+  const int64_t chunk = (int64_t)kSumBlock * 64;
+  const int64_t nparts = (total + chunk - 1) / chunk;
+  if (nparts > INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "vofmt_compact_tracers: fields too large");
+  int32_t *which = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * (size_t)nret);
+  double *part = (double *)scratch(ctx, SLOT_MISC2, sizeof(double) * ((size_t)nparts + 1));
+  double *hres = (double *)host_scratch(ctx, sizeof(double));
+  if (!which || !part || !hres) return VOFMT_E_NOMEM;
+  VOFMT_HIP(ctx, hipMemcpyAsync(which, retired.data(), sizeof(int32_t) * (size_t)nret, hipMemcpyHostToDevice,
+                                stream));
+  hipLaunchKernelGGL(k_sum_retired, dim3((unsigned)nparts), dim3(kSumBlock), 0, stream, c, which, nret, n3, chunk,
+                     part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, stream, part, (int)nparts, part + nparts);
+  VOFMT_HIP(ctx, hipGetLastError());
+  VOFMT_HIP(ctx, hipMemcpyAsync(hres, part + nparts, sizeof(double), hipMemcpyDeviceToHost, stream));
+  // kept fields move down in increasing order (each to a slot already read or retired)
+  for (int t = 0; t < ntr; ++t) {
+    const int d = new_index_host[t];
+    if (d >= 0 && d != t)
+      VOFMT_HIP(ctx, hipMemcpyAsync(c + (int64_t)d * n3, c + (int64_t)t * n3, sizeof(double) * (size_t)n3,
+                                    hipMemcpyDeviceToDevice, stream));
+  }
+  hipLaunchKernelGGL(k_fill_f64, dim3(1024), dim3(256), 0, stream, c + (int64_t)k * n3, (int64_t)(ntr - k) * n3,
+                     0.0);
+  VOFMT_HIP(ctx, hipGetLastError());
+  VOFMT_HIP(ctx, hipStreamSynchronize(stream));
+  *discarded_host = *hres;
+  *ntracers_host = k;
   return VOFMT_OK;
 }

@@ -46,6 +46,7 @@ _SIGNATURES = {
     "vofmt_set_advect_pairs": (ctypes.c_int, [_vp, _i32]),
     "vofmt_label_drops": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _d, _vp, _vp, _vp]),
     "vofmt_drop_moments": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "vofmt_compact_tracers": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "vofmt_csf_force": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _d, _vp, _vp, _vp, _vp]),
     "vofmt_drop_shapes": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                          _vp]),
@@ -274,6 +275,24 @@ class Context:
                                                  _ptr(labels), nd.ctypes.data, float(gap_cells),
                                                  _ptr(new_tracer), ctypes.byref(nmoved), _stream(stream)))
         return ntr.value, nmoved.value
+
+    def compact_tracers(self, c, ntracers: int, ndrops, stream=None):
+        """Retire the tracers without drops among the first `ntracers` fields of
+        c [max_tracers][nz][ny][nx]; returns (tracers kept, new index per
+        tracer, discarded volume)."""
+        _require(c)
+        nx, ny, nz = _dims(c)
+        if not 0 <= ntracers <= int(c.shape[0]):
+            raise ValueError("compact_tracers: ntracers outside the field array")
+        nd = np.ascontiguousarray(ndrops, dtype=np.int32)
+        if len(nd) != ntracers:
+            raise ValueError("compact_tracers: one drop count per tracer")
+        n = ctypes.c_int32(int(ntracers))
+        idx = np.zeros(max(ntracers, 1), dtype=np.int32)
+        disc = ctypes.c_double(0.0)
+        self._check(load().vofmt_compact_tracers(self.h, nx, ny, nz, ctypes.byref(n), _ptr(c), nd.ctypes.data,
+                                                 idx.ctypes.data, ctypes.byref(disc), _stream(stream)))
+        return n.value, idx[:ntracers], disc.value
 
     # ------------------------------------------------------------ statistics
     def nearest_pair_stats(self, xyz, box, vertical_axis: int, r2_edges, cos_edges, nn_index, nn_ties, hist, M, R,

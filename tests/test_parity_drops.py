@@ -316,3 +316,36 @@ def test_curvature_advected_field(ctx, spheres64_after):
     assert np.array_equal(gs, os_)
     valid = (os_ >= 1) & (os_ <= 3)
     assert np.abs(gk[valid] - ok[valid]).max() <= 1e-12
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_compact_tracers(ctx, seed):
+    """Fields moved bit-exact, indices and count exact; the discarded volume
+    within n eps sum|c| of the oracle's (the same values summed in another
+    order)."""
+    import torch
+
+    rng = np.random.default_rng(70 + seed)
+    shape = tuple(int(v) for v in rng.integers(6, 40, 3))
+    ntr = int(rng.integers(3, 9))
+    cap = ntr + 2
+    c = np.zeros((cap,) + shape)
+    c[:ntr] = random_blobs(rng, shape, ntr, 3 * ntr, 1.0, 3.0)
+    empty = rng.uniform(size=ntr) < 0.4
+    c[:ntr][empty] = 0.0
+    dust = (rng.uniform(size=(ntr,) + shape) < 0.05) * rng.uniform(0, 1e-7, (ntr,) + shape)
+    c[:ntr] += dust  # below the labelling threshold: never a drop
+    note(f"compact tracers shape={shape} ntr={ntr} retired={int(empty.sum())}")
+    tc = _dev(c)
+    lab = torch.zeros((ntr,) + shape, dtype=torch.int32, device="cuda:0")
+    nd = ctx.label_drops(tc[:ntr], lab)
+    nd_o = [oracle.label(c[t])[1] for t in range(ntr)]
+    assert list(nd) == nd_o
+    n, idx, disc = ctx.compact_tracers(tc, ntr, nd)
+    torch.cuda.synchronize()
+    o, on, oidx, odisc = oracle.compact_tracers(c[:ntr], nd_o)
+    assert n == on and list(idx) == list(oidx)
+    g = tc.cpu().numpy()
+    assert np.array_equal(g[:ntr], o)
+    assert not g[ntr:].any()
+    assert abs(disc - odisc) <= c.size * 2.2e-16 * np.abs(dust).sum() + 1e-300
