@@ -70,8 +70,10 @@ def lib():
         L.orc_neighbour_pairs.restype = i64
         L.orc_recolor.argtypes = [i64, i64, i64, vp, i32, vp, vp, vp, d, vp, vp]
         L.orc_recolor.restype = ctypes.c_int
-        L.orc_nearest_pair_stats.argtypes = [i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_nearest_pair_stats.argtypes = [i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_nearest_pair_stats.restype = ctypes.c_int
+        L.orc_pair_pdfs.argtypes = [i32, i32, vp, vp, vp, i64, vp, vp]
+        L.orc_pair_pdfs.restype = ctypes.c_int
         L.orc_curvature_hf.argtypes = [i64, i64, i64, vp, vp, vp]
         L.orc_curvature_hf.restype = ctypes.c_int
         L.orc_num_threads.argtypes = []
@@ -291,13 +293,30 @@ def nearest_pair_stats(xyz, box, vaxis: int, r2_edges, cos_edges):
     hist = np.zeros(nr * nth + 1, dtype=np.uint64)
     M = np.zeros(3)
     R = np.zeros(9)
+    A = np.zeros(9)
     rc = lib().orc_nearest_pair_stats(n, xyz.ctypes.data, box.ctypes.data, int(vaxis), nr, nth, r2e.ctypes.data,
                                       ce.ctypes.data, idx.ctypes.data, ties.ctypes.data, hist.ctypes.data,
-                                      M.ctypes.data, R.ctypes.data)
+                                      M.ctypes.data, R.ctypes.data, A.ctypes.data)
     if rc != 0:
         raise ValueError(f"orc_nearest_pair_stats failed: {rc}")
     return dict(nn_index=idx, nn_ties=ties, hist=hist[:-1].reshape(nr, nth), overflow=int(hist[-1]),
-                M=M, R=R.reshape(3, 3))
+                M=M, R=R.reshape(3, 3), A=A.reshape(3, 3), raw_hist=hist)
+
+
+def pair_pdfs(r_edges, th_edges, hist, events: int):
+    """P_nst(r, theta) [nr][nth] and P_r-nst(r) [nr] of an accumulated histogram (eqs. 8, 10 at
+    bin centres). hist: [nr*nth] or [nr][nth] uint64 in units of 1/720720 (overflow excluded)."""
+    re = _f64(r_edges)
+    te = _f64(th_edges)
+    nr, nth = len(re) - 1, len(te) - 1
+    h = np.ascontiguousarray(np.asarray(hist, dtype=np.uint64).reshape(-1)[: nr * nth])
+    P = np.zeros(nr * nth)
+    Pr = np.zeros(nr)
+    rc = lib().orc_pair_pdfs(nr, nth, re.ctypes.data, te.ctypes.data, h.ctypes.data, int(events), P.ctypes.data,
+                             Pr.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"orc_pair_pdfs failed: {rc}")
+    return P.reshape(nr, nth), Pr
 
 
 # ---------------------------------------------------------------- curvature

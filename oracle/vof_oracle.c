@@ -716,7 +716,7 @@ int orc_compact_tracers(int64_t n3, int32_t ntr, double *c, const int32_t *ndrop
  * ========================================================================= */
 int orc_nearest_pair_stats(int32_t n, const double *xyz, const double *box, int32_t vaxis, int32_t nr,
                            int32_t nth, const double *r2_edges, const double *cos_edges, int32_t *nn_index,
-                           int32_t *nn_ties, uint64_t *hist, double *M, double *R) {
+                           int32_t *nn_ties, uint64_t *hist, double *M, double *R, double *A) {
   if (n < 2 || vaxis < 0 || vaxis > 2 || nr < 1 || nth < 1) return ORC_E_ARG;
   memset(hist, 0, sizeof(uint64_t) * ((size_t)nr * nth + 1));
   double SM[3] = {0, 0, 0}, SR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -770,6 +770,45 @@ int orc_nearest_pair_stats(int32_t n, const double *xyz, const double *box, int3
   }
   for (int a = 0; a < 3; ++a) M[a] = SM[a] / (double)n;
   for (int a = 0; a < 9; ++a) R[a] = SR[a] / (double)n;
+  /* deviatoric part A = R - (tr R / 3) delta (second-moment section; its
+   * "3 tr(R)" in the text on the figure is read as tr(R) = R : delta) */
+  double tr = (R[0] + R[4]) + R[8];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) A[3 * a + b] = (a == b) ? R[3 * a + b] - tr / 3.0 : R[3 * a + b];
+  return ORC_OK;
+}
+
+/* =========================================================================
+ * Probability densities of the nearest-particle vector from an accumulated
+ * histogram ("Nearest particle statistics", eqs. 8 and 10): with E events
+ * and E_k the (fixed-point) weight of bin k,
+ *   P_nst(r, theta) = E_km / (E 2 pi r^2 sin(theta) dr dtheta),
+ *   P_r-nst(r)      = (sum over theta of E_km) / (E 4 pi r^2 dr),
+ * evaluated at the bin centres r_c = (r_k + r_k+1)/2, theta_c = (theta_m +
+ * theta_m+1)/2 (reading: the paper writes the left edges, which makes the
+ * first radial bin and the first polar bin singular). r_edges[nr+1] ascending
+ * and th_edges[nth+1] ascending in [0, pi] are the edges whose squares and
+ * cosines binned the histogram. Weights are in units of 1/720720.
+ * P[nr][nth], Pr[nr]. Returns ORC_E_ARG for bad sizes or events < 1.
+ * ========================================================================= */
+int orc_pair_pdfs(int32_t nr, int32_t nth, const double *r_edges, const double *th_edges, const uint64_t *hist,
+                  int64_t events, double *P, double *Pr) {
+  if (nr < 1 || nth < 1 || events < 1) return ORC_E_ARG;
+  const double pi = 3.14159265358979323846;
+  const double E = (double)events * 720720.0;
+  for (int32_t k = 0; k < nr; ++k) {
+    double rc = 0.5 * (r_edges[k] + r_edges[k + 1]);
+    double dr = r_edges[k + 1] - r_edges[k];
+    uint64_t row = 0;
+    for (int32_t m = 0; m < nth; ++m) {
+      double tc = 0.5 * (th_edges[m] + th_edges[m + 1]);
+      double dth = th_edges[m + 1] - th_edges[m];
+      uint64_t ek = hist[(size_t)k * nth + m];
+      row += ek;
+      P[(size_t)k * nth + m] = (double)ek / (E * (2.0 * pi * (rc * rc) * sin(tc) * dr * dth));
+    }
+    Pr[k] = (double)row / (E * (4.0 * pi * (rc * rc) * dr));
+  }
   return ORC_OK;
 }
 

@@ -137,3 +137,84 @@ def test_r_m_closed_form_values():
         mom = quad(lambda r: 4 * math.pi * r**4 * f(r), 1, np.inf)[0]
         assert mom / norm == pytest.approx(closed, rel=1e-9)
     assert 0.5 * (4 * math.pi / (3 * 0.01)) ** (1 / 3) == pytest.approx(3.7411, abs=1e-4)
+
+
+def test_deviator_on_lattices():
+    """A = R - tr(R)/3 delta (second-moment section). Cubic lattice: A = 0. A lattice with
+    spacings (a, a, b), b > a: the four in-plane neighbours tie (h = 1/4), R = diag(a^2/2,
+    a^2/2, 0), tr R = a^2 and A = diag(a^2/6, a^2/6, -a^2/3)."""
+    a, b = 6.0, 9.0
+    g = np.arange(4)
+    xyz = np.array([(x * a, y * a, z * b) for z in g for y in g for x in g])
+    L = np.array([4 * a, 4 * a, 4 * b])
+    r2e, ce = edges(4, 12.0, 4)
+    st = oracle.nearest_pair_stats(xyz, L, 2, r2e, ce)
+    assert np.all(st["nn_ties"] == 4)
+    assert np.allclose(st["R"], np.diag([a * a / 2, a * a / 2, 0.0]), rtol=0, atol=1e-12)
+    assert np.allclose(st["A"], np.diag([a * a / 6, a * a / 6, -a * a / 3]), rtol=0, atol=1e-12)
+    cube = np.array([(x * a, y * a, z * a) for z in g for y in g for x in g])
+    st = oracle.nearest_pair_stats(cube, np.array([4 * a] * 3), 2, r2e, ce)
+    assert np.abs(st["A"]).max() < 1e-12
+
+
+def _poisson_points(seed, n, L):
+    rng = synth.Splitmix64(seed)
+    return rng.uniform(3 * n).reshape(n, 3) * L
+
+
+def test_pdfs_of_uniform_points():
+    """Uniform (Poisson) points: the nearest neighbour lies at r with density
+    f(r) = n_p exp(-(4 pi / 3) n_p r^3) per unit volume, the same in every direction (the
+    point-particle limit of eq. 12, 8 phi (r/d)^3 = (4 pi/3) n_p r^3). A radial bin therefore
+    holds the fraction p_k = exp(-c r_k^3) - exp(-c r_k+1^3), c = (4 pi/3) n_p, of the events,
+    and a polar bin of it the share (cos theta_m - cos theta_m+1)/2. The estimators of eqs. (8)
+    and (10) at the bin centres must equal those fractions divided by 4 pi r_c^2 dr (and by
+    2 pi r_c^2 sin(theta_c) dr dtheta) within counting noise; away from r = 0 they also follow
+    f(r_c) up to the midpoint error."""
+    n, L = 20000, 100.0
+    xyz = _poisson_points(41, n, L)
+    npd = n / L**3
+    cc = 4 * math.pi / 3 * npd
+    rmean = gamma(4 / 3) * cc ** (-1 / 3)
+    nr, nth = 16, 6
+    r_edges = np.linspace(0.0, 2.5 * rmean, nr + 1)
+    th_edges = np.linspace(0.0, math.pi, nth + 1)
+    st = oracle.nearest_pair_stats(xyz, np.array([L] * 3), 2, r_edges**2, np.cos(th_edges))
+    P, Pr = oracle.pair_pdfs(r_edges, th_edges, st["hist"], n)
+    rc = 0.5 * (r_edges[1:] + r_edges[:-1])
+    dr = np.diff(r_edges)
+    pk = np.exp(-cc * r_edges[:-1] ** 3) - np.exp(-cc * r_edges[1:] ** 3)
+    expect = pk / (4 * math.pi * rc**2 * dr)
+    ok = pk * n > 20
+    assert ok.sum() >= 12
+    sig = expect[ok] / np.sqrt(pk[ok] * n)
+    assert np.all(np.abs(Pr[ok] - expect[ok]) <= 4 * sig), Pr[ok] / expect[ok]
+    # the radial estimator approximates the density itself once r_c >> dr
+    f = npd * np.exp(-cc * rc**3)
+    far = ok & (np.arange(nr) >= 3)
+    assert np.all(np.abs(Pr[far] - f[far]) <= 4 * f[far] / np.sqrt(pk[far] * n) + 0.01 * f[far])
+    # the (r, theta) estimator: isotropic shares of each radial bin
+    share = 0.5 * (np.cos(th_edges[:-1]) - np.cos(th_edges[1:]))
+    tc = 0.5 * (th_edges[1:] + th_edges[:-1])
+    for k in np.nonzero(pk * n > 1500)[0]:
+        e2 = pk[k] * share / (2 * math.pi * rc[k] ** 2 * np.sin(tc) * dr[k] * np.diff(th_edges))
+        assert np.all(np.abs(P[k] - e2) <= 4 * e2 / np.sqrt(pk[k] * share * n)), (k, P[k] / e2)
+
+
+def test_radial_pdf_is_the_sphere_average():
+    """Eq. (9): P_r-nst is the average of P_nst(r, theta, beta) over the sphere of radius r,
+    (1/4 pi) int int P sin(theta) dtheta dbeta; with the azimuth integrated out it is
+    (1/2) sum_m P(r, theta_m) sin(theta_m) dtheta at the same bin centres."""
+    n, L = 3000, 60.0
+    xyz = _poisson_points(43, n, L)
+    r_edges = np.linspace(0.0, 8.0, 9)
+    th_edges = np.linspace(0.0, math.pi, 9)
+    st = oracle.nearest_pair_stats(xyz, np.array([L] * 3), 1, r_edges**2, np.cos(th_edges))
+    P, Pr = oracle.pair_pdfs(r_edges, th_edges, st["hist"], n)
+    tc = 0.5 * (th_edges[1:] + th_edges[:-1])
+    avg = 0.5 * (P * np.sin(tc) * np.diff(th_edges)).sum(axis=1)
+    assert np.allclose(avg, Pr, rtol=1e-13, atol=0)
+    # and the binned density integrates to the fraction of events inside the radial range
+    rc = 0.5 * (r_edges[1:] + r_edges[:-1])
+    tot = (Pr * 4 * math.pi * rc**2 * np.diff(r_edges)).sum()
+    assert tot == pytest.approx(1.0 - st["overflow"] / (FIX * n), abs=1e-13)
