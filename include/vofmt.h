@@ -216,17 +216,46 @@ int vofmt_compact_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, in
  * theta from the vertical axis, decided without sqrt as
  * rv*|rv| <= (ce*|ce|)*d2. Weights are integers in units of 1/720720; pairs
  * outside the radial range go to hist_fixed[nr*ntheta]. Moments (eqs. 11,
- * 14, as averages over the E = n events): M = (1/E) sum h r, R = (1/E) sum h r r^T.
+ * 14, as averages over the E = n events): M = (1/E) sum h r, R = (1/E) sum h r r^T,
+ * and the deviatoric part A = R - (tr R / 3) delta of the second-moment
+ * section (its "3 tr(R)" read as tr(R) = R : delta).
  *
  * xyz       : [n][3] FP64 drop centroids (cells). box: [3] HOST FP64.
  * r2_edges  : [nr+1] HOST FP64, ascending. cos_edges: [ntheta+1] HOST FP64, descending.
  * nn_index  : [n] int32 output (smallest nearest j). nn_ties: [n] int32 output (N_i).
  * hist_fixed: [nr*ntheta + 1] uint64 output. M: [3], R: [9] FP64 outputs.
+ * A         : [9] FP64 output, or NULL.
+ * Synchronises the stream (host staging of the edges). Scratch: 16 bytes per
+ * drop and candidate slice (at most 64 slices) plus 104 bytes per drop.
  */
 int vofmt_nearest_pair_stats(vofmt_ctx *ctx, int32_t n, const double *xyz, const double *box, int32_t vertical_axis,
                              int32_t nr, int32_t ntheta, const double *r2_edges, const double *cos_edges,
                              int32_t *nn_index, int32_t *nn_ties, uint64_t *hist_fixed, double *M, double *R,
-                             hipStream_t stream);
+                             double *A, hipStream_t stream);
+
+/*
+ * Probability densities of the nearest-particle vector (section "Nearest
+ * particle statistics", eqs. 8 and 10) from a histogram of
+ * vofmt_nearest_pair_stats, or the sum of several over time (the paper
+ * averages over all events E):
+ *   P_nst(r, theta) = E_km / (E 2 pi r^2 sin(theta) dr dtheta),
+ *   P_r-nst(r)      = sum_m E_km / (E 4 pi r^2 dr),
+ * at the bin centres r = (r_k + r_k+1)/2, theta = (theta_m + theta_m+1)/2
+ * (the paper writes the left edges, which makes the first radial and polar
+ * bins singular). Operations in the written order, left to right.
+ *
+ * r_edges    : [nr+1] HOST FP64, ascending, r_edges[0] >= 0: the radii whose
+ *              squares were the histogram's r2_edges.
+ * theta_edges: [ntheta+1] HOST FP64, ascending within [0, pi]: the polar
+ *              angles whose cosines were its cos_edges.
+ * hist_fixed : [nr*ntheta] uint64 device, weights in units of 1/720720 (the
+ *              overflow slot, if present, is not read).
+ * events     : E, the number of drops summed over the histograms (>= 1).
+ * P          : [nr][ntheta] FP64 device output. Pr: [nr] FP64 device output.
+ * Synchronises the stream (host staging of the edges).
+ */
+int vofmt_pair_pdfs(vofmt_ctx *ctx, int32_t nr, int32_t ntheta, const double *r_edges, const double *theta_edges,
+                    const uint64_t *hist_fixed, int64_t events, double *P, double *Pr, hipStream_t stream);
 
 /*
  * Height-function curvature of one tracer field (the paper computes kappa_i

@@ -165,9 +165,10 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const double *__restrict__ xyz
   for (int a = 0; a < 9; ++a) o[3 + a] = sr[a];
 }
 
-// Fixed-order reduction of the per-drop contributions (one workgroup).
+// Fixed-order reduction of the per-drop contributions (one workgroup), then
+// the deviatoric part A = R - (tr R / 3) delta of the second moment.
 __global__ __launch_bounds__(kBlock) void k_moments(const double *__restrict__ part, int32_t n, double *__restrict__ M,
-                                                    double *__restrict__ R) {
+                                                    double *__restrict__ R, double *__restrict__ A) {
   __shared__ double red[12][kBlock];
   double acc[12];
   for (int a = 0; a < 12; ++a) acc[a] = 0.0;
@@ -182,6 +183,38 @@ __global__ __launch_bounds__(kBlock) void k_moments(const double *__restrict__ p
   }
   if (threadIdx.x < 3) M[threadIdx.x] = red[threadIdx.x][0] / (double)n;
   if (threadIdx.x < 9) R[threadIdx.x] = red[3 + threadIdx.x][0] / (double)n;
+  if (A != nullptr && threadIdx.x < 9) {
+    const double r0 = red[3][0] / (double)n, r4 = red[7][0] / (double)n, r8 = red[11][0] / (double)n;
+    const double tr = (r0 + r4) + r8;
+    const double rv = red[3 + threadIdx.x][0] / (double)n;
+    A[threadIdx.x] = (threadIdx.x % 4 == 0) ? rv - tr / 3.0 : rv;
+  }
+}
+
+// Densities of the nearest-pair vector at the bin centres from an
+// accumulated histogram (eqs. 8 and 10): P(r, theta) = E_km / (E 2 pi r^2
+// sin(theta) dr dtheta) and P_r(r) = sum_m E_km / (E 4 pi r^2 dr), E the
+// events in units of 1/720720. One thread per radial bin; edges[0..nr] are
+// the radii, edges[nr+1..] the polar angles.
+__global__ __launch_bounds__(kBlock) void k_pair_pdfs(int32_t nr, int32_t nth, const double *__restrict__ edges,
+                                                      const uint64_t *__restrict__ hist, int64_t events,
+                                                      double *__restrict__ P, double *__restrict__ Pr) {
+  const int32_t k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= nr) return;
+  const double pi = 3.14159265358979323846;
+  const double *re = edges, *te = edges + nr + 1;
+  const double E = (double)events * 720720.0;
+  const double rc = 0.5 * (re[k] + re[k + 1]);
+  const double dr = re[k + 1] - re[k];
+  uint64_t row = 0;
+  for (int32_t m = 0; m < nth; ++m) {
+    const double tc = 0.5 * (te[m] + te[m + 1]);
+    const double dth = te[m + 1] - te[m];
+    const uint64_t ek = hist[(int64_t)k * nth + m];
+    row += ek;
+    P[(int64_t)k * nth + m] = (double)ek / (E * (2.0 * pi * (rc * rc) * sin(tc) * dr * dth));
+  }
+  Pr[k] = (double)row / (E * (4.0 * pi * (rc * rc) * dr));
 }
 
 __global__ void k_zero_u64(uint64_t *p, int64_t n) {
@@ -194,7 +227,8 @@ __global__ void k_zero_u64(uint64_t *p, int64_t n) {
 extern "C" int vofmt_nearest_pair_stats(vofmt_ctx *ctx, int32_t n, const double *xyz, const double *box,
                                         int32_t vertical_axis, int32_t nr, int32_t ntheta, const double *r2_edges,
                                         const double *cos_edges, int32_t *nn_index, int32_t *nn_ties,
-                                        uint64_t *hist_fixed, double *M, double *R, hipStream_t stream) {
+                                        uint64_t *hist_fixed, double *M, double *R, double *A,
+                                        hipStream_t stream) {
   if (!ctx) return VOFMT_E_ARG;
   if (n < 2 || vertical_axis < 0 || vertical_axis > 2 || nr < 1 || ntheta < 1)
     return set_err(ctx, VOFMT_E_ARG, "vofmt_nearest_pair_stats: bad sizes (n=%d nr=%d ntheta=%d axis=%d)", n, nr,
@@ -237,7 +271,39 @@ extern "C" int vofmt_nearest_pair_stats(vofmt_ctx *ctx, int32_t n, const double 
                      nn_ties, best);
   hipLaunchKernelGGL(k_pairs, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, stream, xyz, n, b, vertical_axis, nr,
                      ntheta, dedge, nn_index, nn_ties, best, hist_fixed, part);
-  hipLaunchKernelGGL(k_moments, dim3(1), dim3(kBlock), 0, stream, part, n, M, R);
+  hipLaunchKernelGGL(k_moments, dim3(1), dim3(kBlock), 0, stream, part, n, M, R, A);
+  VOFMT_HIP(ctx, hipGetLastError());
+  // the staging buffer must stay valid until the copy has run
+  VOFMT_HIP(ctx, hipStreamSynchronize(stream));
+  return VOFMT_OK;
+}
+
+extern "C" int vofmt_pair_pdfs(vofmt_ctx *ctx, int32_t nr, int32_t ntheta, const double *r_edges,
+                               const double *theta_edges, const uint64_t *hist_fixed, int64_t events, double *P,
+                               double *Pr, hipStream_t stream) {
+  if (!ctx) return VOFMT_E_ARG;
+  if (nr < 1 || ntheta < 1 || events < 1)
+    return set_err(ctx, VOFMT_E_ARG, "vofmt_pair_pdfs: bad sizes (nr=%d ntheta=%d events=%lld)", nr, ntheta,
+                   (long long)events);
+  if (!r_edges || !theta_edges || !hist_fixed || !P || !Pr)
+    return set_err(ctx, VOFMT_E_ARG, "vofmt_pair_pdfs: null pointer");
+  if (!(r_edges[0] >= 0.0) || !(theta_edges[0] >= 0.0) || !(theta_edges[ntheta] <= 3.14159265358979323846))
+    return set_err(ctx, VOFMT_E_ARG, "vofmt_pair_pdfs: edges outside r >= 0, 0 <= theta <= pi");
+  for (int e = 0; e < nr; ++e)
+    if (!(r_edges[e] < r_edges[e + 1])) return set_err(ctx, VOFMT_E_ARG, "vofmt_pair_pdfs: r_edges must increase");
+  for (int e = 0; e < ntheta; ++e)
+    if (!(theta_edges[e] < theta_edges[e + 1]))
+      return set_err(ctx, VOFMT_E_ARG, "vofmt_pair_pdfs: theta_edges must increase");
+  VOFMT_HIP(ctx, hipSetDevice(ctx->device));
+  const size_t nedge = (size_t)nr + 1 + (size_t)ntheta + 1;
+  double *dedge = (double *)scratch(ctx, SLOT_MISC, sizeof(double) * nedge);
+  double *hstage = (double *)host_scratch(ctx, sizeof(double) * nedge);
+  if (!dedge || !hstage) return VOFMT_E_NOMEM;
+  for (int e = 0; e <= nr; ++e) hstage[e] = r_edges[e];
+  for (int e = 0; e <= ntheta; ++e) hstage[nr + 1 + e] = theta_edges[e];
+  VOFMT_HIP(ctx, hipMemcpyAsync(dedge, hstage, sizeof(double) * nedge, hipMemcpyHostToDevice, stream));
+  hipLaunchKernelGGL(k_pair_pdfs, dim3(ceil_div(nr, kBlock)), dim3(kBlock), 0, stream, nr, ntheta, dedge, hist_fixed,
+                     events, P, Pr);
   VOFMT_HIP(ctx, hipGetLastError());
   // the staging buffer must stay valid until the copy has run
   VOFMT_HIP(ctx, hipStreamSynchronize(stream));

@@ -53,7 +53,8 @@ _SIGNATURES = {
     "vofmt_recolor_tracers": (ctypes.c_int, [_vp, _i32, _i32, _i32, _P_i32, _i32, _vp, _vp, _vp, _d, _vp, _P_i32,
                                              _vp]),
     "vofmt_nearest_pair_stats": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
-                                                _vp, _vp, _vp]),
+                                                _vp, _vp, _vp, _vp]),
+    "vofmt_pair_pdfs": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "vofmt_curvature_hf": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp]),
     "vofmt_mlp_forward": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     "vofmt_mlp_train_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, ctypes.c_float, _i32, _vp, _vp, _vp, _vp,
@@ -296,15 +297,27 @@ class Context:
 
     # ------------------------------------------------------------ statistics
     def nearest_pair_stats(self, xyz, box, vertical_axis: int, r2_edges, cos_edges, nn_index, nn_ties, hist, M, R,
-                           stream=None):
-        _require(xyz, nn_index, nn_ties, hist, M, R)
+                           A=None, stream=None):
+        _require(xyz, nn_index, nn_ties, hist, M, R, *([A] if A is not None else []))
         n = int(xyz.shape[0])
         b = np.ascontiguousarray(box, dtype=np.float64)
         r2 = np.ascontiguousarray(r2_edges, dtype=np.float64)
         ce = np.ascontiguousarray(cos_edges, dtype=np.float64)
         return self._check(load().vofmt_nearest_pair_stats(
             self.h, n, _ptr(xyz), b.ctypes.data, int(vertical_axis), len(r2) - 1, len(ce) - 1, r2.ctypes.data,
-            ce.ctypes.data, _ptr(nn_index), _ptr(nn_ties), _ptr(hist), _ptr(M), _ptr(R), _stream(stream)))
+            ce.ctypes.data, _ptr(nn_index), _ptr(nn_ties), _ptr(hist), _ptr(M), _ptr(R), _ptr(A), _stream(stream)))
+
+    def pair_pdfs(self, r_edges, theta_edges, hist, events: int, P, Pr, stream=None):
+        """P_nst(r, theta) into P[nr][ntheta] and P_r-nst(r) into Pr[nr] (float64) from a uint64
+        histogram (the first nr*ntheta entries of hist are read)."""
+        _require(hist, P, Pr)
+        re = np.ascontiguousarray(r_edges, dtype=np.float64)
+        te = np.ascontiguousarray(theta_edges, dtype=np.float64)
+        nr, nth = len(re) - 1, len(te) - 1
+        if hist.numel() < nr * nth or P.numel() != nr * nth or Pr.numel() != nr:
+            raise ValueError("pair_pdfs: histogram or outputs do not match the edges")
+        return self._check(load().vofmt_pair_pdfs(self.h, nr, nth, re.ctypes.data, te.ctypes.data, _ptr(hist),
+                                                  int(events), _ptr(P), _ptr(Pr), _stream(stream)))
 
 
     # ------------------------------------------------------------ curvature

@@ -234,10 +234,12 @@ def _gpu_stats(ctx, xyz, box, vaxis, r2e, ce):
     hist = torch.zeros(nr * nth + 1, dtype=torch.int64, device="cuda:0")
     M = torch.zeros(3, dtype=torch.float64, device="cuda:0")
     R = torch.zeros(9, dtype=torch.float64, device="cuda:0")
-    ctx.nearest_pair_stats(tx, box, vaxis, r2e, ce, idx, ties, hist, M, R)
+    A = torch.zeros(9, dtype=torch.float64, device="cuda:0")
+    ctx.nearest_pair_stats(tx, box, vaxis, r2e, ce, idx, ties, hist, M, R, A)
     torch.cuda.synchronize()
     return dict(nn_index=idx.cpu().numpy(), nn_ties=ties.cpu().numpy(),
-                hist=hist.cpu().numpy().view(np.uint64), M=M.cpu().numpy(), R=R.cpu().numpy().reshape(3, 3))
+                hist=hist.cpu().numpy().view(np.uint64), M=M.cpu().numpy(), R=R.cpu().numpy().reshape(3, 3),
+                A=A.cpu().numpy().reshape(3, 3), hist_dev=hist)
 
 
 def _check_stats(g, o, xyz, box):
@@ -247,6 +249,25 @@ def _check_stats(g, o, xyz, box):
     scale = np.trace(o["R"]) + 1e-300
     assert np.abs(g["M"] - o["M"]).max() <= 1e-12 * math.sqrt(scale)
     assert np.abs(g["R"] - o["R"]).max() <= 1e-12 * scale
+    assert np.abs(g["A"] - o["A"]).max() <= 1e-12 * scale
+
+
+def _gpu_pdfs(ctx, r_edges, th_edges, hist_dev, events):
+    import torch
+
+    nr, nth = len(r_edges) - 1, len(th_edges) - 1
+    P = torch.zeros(nr * nth, dtype=torch.float64, device="cuda:0")
+    Pr = torch.zeros(nr, dtype=torch.float64, device="cuda:0")
+    ctx.pair_pdfs(r_edges, th_edges, hist_dev, events, P, Pr)
+    torch.cuda.synchronize()
+    return P.cpu().numpy().reshape(nr, nth), Pr.cpu().numpy()
+
+
+def _check_pdfs(gP, gPr, oP, oPr):
+    # same operations in the same order; sin() of the library and of the C
+    # library may differ in the last bit
+    assert np.all(np.abs(gP - oP) <= 1e-12 * np.abs(oP))
+    assert np.all(np.abs(gPr - oPr) <= 1e-12 * np.abs(oPr))
 
 
 # 5508 and 16684 drops cut the candidate range into 22 slices of 256 and
@@ -262,6 +283,55 @@ def test_stats_random(ctx, n):
     g = _gpu_stats(ctx, xyz, box, 2, r2e, ce)
     o = oracle.nearest_pair_stats(xyz, box, 2, r2e, ce)
     _check_stats(g, o, xyz, box)
+
+
+# The densities of eqs. 8 and 10 from one call's histogram, and from the sum
+# of three calls' histograms (events accumulated as the paper averages over
+# time), against the oracle on the same histogram.
+def test_pair_pdfs(ctx):
+    import torch
+
+    box = np.array([256.0, 256.0, 256.0])
+    r_edges = np.arange(65) * (48.0 / 64)
+    th_edges = np.arange(33) * (math.pi / 32)
+    r2e, ce = r_edges**2, np.cos(th_edges)
+    acc = torch.zeros(64 * 32 + 1, dtype=torch.int64, device="cuda:0")
+    acc_o = np.zeros(64 * 32, dtype=np.uint64)
+    events = 0
+    for call, n in enumerate((400, 1000, 2500)):
+        rng = synth.Splitmix64(90 + call)
+        xyz = rng.uniform(3 * n).reshape(n, 3) * box
+        note(f"pair pdfs call {call} n={n}")
+        g = _gpu_stats(ctx, xyz, box, 2, r2e, ce)
+        o = oracle.nearest_pair_stats(xyz, box, 2, r2e, ce)
+        _check_stats(g, o, xyz, box)
+        gP, gPr = _gpu_pdfs(ctx, r_edges, th_edges, g["hist_dev"], n)
+        oP, oPr = oracle.pair_pdfs(r_edges, th_edges, o["hist"], n)
+        _check_pdfs(gP, gPr, oP, oPr)
+        acc += g["hist_dev"]
+        acc_o += o["hist"].reshape(-1)
+        events += n
+    gP, gPr = _gpu_pdfs(ctx, r_edges, th_edges, acc, events)
+    oP, oPr = oracle.pair_pdfs(r_edges, th_edges, acc_o, events)
+    _check_pdfs(gP, gPr, oP, oPr)
+    assert np.count_nonzero(oPr) > 20
+
+
+def test_pair_pdfs_errors(ctx):
+    import torch
+
+    from paper_2407_07463_amd import vofmt
+
+    h = torch.zeros(4 * 2 + 1, dtype=torch.int64, device="cuda:0")
+    P = torch.zeros(8, dtype=torch.float64, device="cuda:0")
+    Pr = torch.zeros(4, dtype=torch.float64, device="cuda:0")
+    r = np.arange(5.0)
+    for re, te, ev in ((r, np.array([0.0, 1.0, 4.0]), 10),    # theta beyond pi
+                       (r[::-1].copy(), np.array([0.0, 1.0, 2.0]), 10),  # radii decreasing
+                       (r, np.array([0.0, 1.0, 2.0]), 0)):    # no events
+        with pytest.raises(vofmt.VofmtError) as e:
+            ctx.pair_pdfs(re, te, h, ev, P, Pr)
+        assert e.value.code == vofmt.E_ARG
 
 
 # 12^3 drops: the six nearest neighbours of a drop lie in up to three
