@@ -70,6 +70,12 @@ def lib():
         L.orc_neighbour_pairs.restype = i64
         L.orc_recolor.argtypes = [i64, i64, i64, vp, i32, vp, vp, vp, d, vp, vp]
         L.orc_recolor.restype = ctypes.c_int
+        L.orc_recolor_stencil.argtypes = [i64, i64, i64, vp, i32, vp, vp, vp, vp, vp]
+        L.orc_recolor_stencil.restype = ctypes.c_int
+        L.orc_stencil_flags.argtypes = [i64, i64, i64, vp, vp]
+        L.orc_stencil_flags.restype = None
+        L.orc_neighbour_pairs_stencil.argtypes = [i64, i64, i64, ctypes.c_int, vp, vp, vp, i64]
+        L.orc_neighbour_pairs_stencil.restype = i64
         L.orc_nearest_pair_stats.argtypes = [i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_nearest_pair_stats.restype = ctypes.c_int
         L.orc_pair_pdfs.argtypes = [i32, i32, vp, vp, vp, i64, vp, vp]
@@ -273,6 +279,50 @@ def recolor(c, labels, ndrops, ntracers: int, max_tracers: int, tau: float):
     nmoved = ctypes.c_int32(0)
     rc = lib().orc_recolor(nx, ny, nz, ctypes.byref(ntr), int(max_tracers), c.ctypes.data, labels.ctypes.data,
                            nd.ctypes.data, float(tau), newt.ctypes.data, ctypes.byref(nmoved))
+    return c, ntr.value, newt[:D], nmoved.value, rc
+
+
+def stencil_flags(labels):
+    """Literal near-contact criterion per cell of one tracer's labels [nz][ny][nx]: 0 no,
+    1 Step 1 (empty centre, two opposite occupied cells in the 5^3 stencil), 2 Steps 1 and 3
+    (their labels differ)."""
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    nx, ny, nz = _shape3(labels)
+    out = np.zeros(labels.shape, dtype=np.uint8)
+    lib().orc_stencil_flags(nx, ny, nz, labels.ctypes.data, out.ctypes.data)
+    return out
+
+
+def neighbour_pairs_stencil(labels, ndrops):
+    """Directed neighbour pairs of the literal mode (conflicts within a tracer, contacts across)."""
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    ntr = labels.shape[0]
+    nx, ny, nz = _shape3(labels)
+    nd = np.ascontiguousarray(ndrops, dtype=np.int32)
+    cap = 1 << 16
+    while True:
+        pairs = np.zeros((cap, 2), dtype=np.int32)
+        m = lib().orc_neighbour_pairs_stencil(nx, ny, nz, ntr, labels.ctypes.data, nd.ctypes.data,
+                                              pairs.ctypes.data, cap)
+        if m <= cap:
+            return pairs[:m]
+        cap = int(m)
+
+
+def recolor_stencil(c, labels, ndrops, ntracers: int, max_tracers: int):
+    """Steps 1-4 with the literal 5^3 stencil criterion. Returns (c_new, ntracers_new,
+    new_tracer[D], nmoved, rc) like recolor()."""
+    c = np.array(c, dtype=np.float64, copy=True, order="C")
+    assert c.shape[0] == max_tracers
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    nx, ny, nz = _shape3(c)
+    nd = np.ascontiguousarray(ndrops, dtype=np.int32)
+    D = int(nd.sum())
+    newt = np.zeros(max(D, 1), dtype=np.int32)
+    ntr = ctypes.c_int32(int(ntracers))
+    nmoved = ctypes.c_int32(0)
+    rc = lib().orc_recolor_stencil(nx, ny, nz, ctypes.byref(ntr), int(max_tracers), c.ctypes.data,
+                                   labels.ctypes.data, nd.ctypes.data, newt.ctypes.data, ctypes.byref(nmoved))
     return c, ntr.value, newt[:D], nmoved.value, rc
 
 

@@ -591,10 +591,122 @@ int64_t orc_neighbour_pairs(int64_t nx, int64_t ny, int64_t nz, int ntr, const i
   return m;
 }
 
-int orc_recolor(int64_t nx, int64_t ny, int64_t nz, int32_t *ntracers, int32_t max_tracers, double *c,
-                const int32_t *labels, const int32_t *ndrops, double tau, int32_t *new_tracer, int32_t *nmoved) {
+/* =========================================================================
+ * The near-contact criterion of Steps 1-3 read literally, on the 5x5(x5)
+ * stencil: a cell p of tracer t with no drop (label 0: "C_i = 0 at the
+ * centre") and two opposite cells p + o, p - o, o in {-2..2}^3 \ {0}, both
+ * occupied ("C_i > 1" read as C_i > 0, per the figure caption) -- Step 1 --
+ * whose labels differ -- Step 3. Per cell of one tracer's labels:
+ * flags[p] = 0 (no), 1 (Step 1 only), 2 (Steps 1 and 3).
+ * ========================================================================= */
+void orc_stencil_flags(int64_t nx, int64_t ny, int64_t nz, const int32_t *lab, uint8_t *flags) {
+  for (int64_t k = 0; k < nz; ++k)
+    for (int64_t j = 0; j < ny; ++j)
+      for (int64_t i = 0; i < nx; ++i) {
+        int64_t p = i + nx * (j + ny * k);
+        uint8_t f = 0;
+        if (lab[p] == 0) {
+          for (int oz = -2; oz <= 2; ++oz)
+            for (int oy = -2; oy <= 2; ++oy)
+              for (int ox = -2; ox <= 2; ++ox) {
+                if (ox == 0 && oy == 0 && oz == 0) continue;
+                int32_t a = lab[wrapi(i + ox, nx) + nx * (wrapi(j + oy, ny) + ny * wrapi(k + oz, nz))];
+                int32_t b = lab[wrapi(i - ox, nx) + nx * (wrapi(j - oy, ny) + ny * wrapi(k - oz, nz))];
+                if (a > 0 && b > 0) {
+                  if (f < 1) f = 1;
+                  if (a != b) f = 2;
+                }
+              }
+        }
+        flags[p] = f;
+      }
+}
+
+/* Neighbour list of the literal mode (symmetric, sorted, unique):
+ * - drops of one tracer are neighbours when the criterion of Steps 1-3
+ *   holds for some centre with one opposite cell in each (the conflicts);
+ * - drops of different tracers are in contact (Step 4's "tracers already
+ *   in contact with the region") when a cell of one lies within the
+ *   stencil's reach of a cell of the other: 4 cells along every axis (the
+ *   two opposite cells of a 5-cell stencil are 4 apart), overlap included.
+ *   Reading: the paper does not define this contact. */
+int64_t orc_neighbours_stencil(int64_t nx, int64_t ny, int64_t nz, int ntr, const int32_t *labels,
+                               const int32_t *ndrops, orc_edge **out) {
+  int64_t n3 = nx * ny * nz;
+  int32_t *off = (int32_t *)malloc(sizeof(int32_t) * (ntr + 1));
+  off[0] = 0;
+  for (int t = 0; t < ntr; ++t) off[t + 1] = off[t] + ndrops[t];
+  int64_t cap = 1024, ne = 0;
+  orc_edge *E = (orc_edge *)malloc(sizeof(orc_edge) * cap);
+#define ORC_ADD_EDGE(ga, gb)                                    \
+  do {                                                          \
+    if (ne == cap) {                                            \
+      cap *= 2;                                                 \
+      E = (orc_edge *)realloc(E, sizeof(orc_edge) * cap);       \
+    }                                                           \
+    E[ne].a = (ga);                                             \
+    E[ne].b = (gb);                                             \
+    ++ne;                                                       \
+  } while (0)
+  for (int t = 0; t < ntr; ++t) {
+    const int32_t *lab = labels + (int64_t)t * n3;
+    for (int64_t p = 0; p < n3; ++p) {
+      int64_t i = p % nx, j = (p / nx) % ny, k = p / (nx * ny);
+      int32_t l = lab[p];
+      if (l == 0) {
+        /* Steps 1 and 3 about centre p */
+        for (int oz = -2; oz <= 2; ++oz)
+          for (int oy = -2; oy <= 2; ++oy)
+            for (int ox = -2; ox <= 2; ++ox) {
+              if (ox == 0 && oy == 0 && oz == 0) continue;
+              int32_t a = lab[wrapi(i + ox, nx) + nx * (wrapi(j + oy, ny) + ny * wrapi(k + oz, nz))];
+              int32_t b = lab[wrapi(i - ox, nx) + nx * (wrapi(j - oy, ny) + ny * wrapi(k - oz, nz))];
+              if (a > 0 && b > 0 && a != b) ORC_ADD_EDGE(off[t] + a - 1, off[t] + b - 1);
+            }
+      } else if (l > 0) {
+        /* drops of other tracers within reach of this cell */
+        for (int oz = -4; oz <= 4; ++oz)
+          for (int oy = -4; oy <= 4; ++oy)
+            for (int ox = -4; ox <= 4; ++ox) {
+              int64_t q = wrapi(i + ox, nx) + nx * (wrapi(j + oy, ny) + ny * wrapi(k + oz, nz));
+              for (int u = 0; u < ntr; ++u) {
+                if (u == t) continue;
+                int32_t l2 = labels[(int64_t)u * n3 + q];
+                if (l2 > 0) ORC_ADD_EDGE(off[t] + l - 1, off[u] + l2 - 1);
+              }
+            }
+      }
+    }
+  }
+#undef ORC_ADD_EDGE
+  qsort(E, ne, sizeof(orc_edge), edge_cmp);
+  int64_t m = 0;
+  for (int64_t e = 0; e < ne; ++e)
+    if (m == 0 || edge_cmp(&E[m - 1], &E[e]) != 0) E[m++] = E[e];
+  free(off);
+  *out = E;
+  return m;
+}
+
+/* Export of the literal mode's neighbour list for tests (as orc_neighbour_pairs). */
+int64_t orc_neighbour_pairs_stencil(int64_t nx, int64_t ny, int64_t nz, int ntr, const int32_t *labels,
+                                    const int32_t *ndrops, int32_t *pairs, int64_t cap) {
+  orc_edge *E = NULL;
+  int64_t m = orc_neighbours_stencil(nx, ny, nz, ntr, labels, ndrops, &E);
+  for (int64_t e = 0; e < m && e < cap; ++e) {
+    pairs[2 * e] = E[e].a;
+    pairs[2 * e + 1] = E[e].b;
+  }
+  free(E);
+  return m;
+}
+
+/* Steps 4 and the cell moves, given the symmetric sorted neighbour list E
+ * (freed here). */
+static int recolor_given_edges(int64_t nx, int64_t ny, int64_t nz, int32_t *ntracers, int32_t max_tracers, double *c,
+                               const int32_t *labels, const int32_t *ndrops, orc_edge *E, int64_t ne,
+                               int32_t *new_tracer, int32_t *nmoved) {
   int ntr = *ntracers;
-  if (ntr < 0 || ntr > max_tracers || tau < 0.0) return ORC_E_ARG;
   int64_t n3 = nx * ny * nz;
   int32_t D = 0;
   for (int t = 0; t < ntr; ++t) D += ndrops[t];
@@ -604,8 +716,6 @@ int orc_recolor(int64_t nx, int64_t ny, int64_t nz, int32_t *ntracers, int32_t m
     for (int t = 0; t < ntr; ++t)
       for (int32_t l = 1; l <= ndrops[t]; ++l, ++g) T[g] = t;
   }
-  orc_edge *E = NULL;
-  int64_t ne = orc_neighbours(nx, ny, nz, ntr, labels, ndrops, tau, &E);
   int64_t *first = (int64_t *)malloc(sizeof(int64_t) * (D + 1));
   {
     int64_t e = 0;
@@ -667,6 +777,25 @@ int orc_recolor(int64_t nx, int64_t ny, int64_t nz, int32_t *ntracers, int32_t m
   free(first);
   free(used);
   return rc;
+}
+
+int orc_recolor(int64_t nx, int64_t ny, int64_t nz, int32_t *ntracers, int32_t max_tracers, double *c,
+                const int32_t *labels, const int32_t *ndrops, double tau, int32_t *new_tracer, int32_t *nmoved) {
+  int ntr = *ntracers;
+  if (ntr < 0 || ntr > max_tracers || tau < 0.0) return ORC_E_ARG;
+  orc_edge *E = NULL;
+  int64_t ne = orc_neighbours(nx, ny, nz, ntr, labels, ndrops, tau, &E);
+  return recolor_given_edges(nx, ny, nz, ntracers, max_tracers, c, labels, ndrops, E, ne, new_tracer, nmoved);
+}
+
+/* Steps 1-4 with the literal stencil criterion (orc_neighbours_stencil). */
+int orc_recolor_stencil(int64_t nx, int64_t ny, int64_t nz, int32_t *ntracers, int32_t max_tracers, double *c,
+                        const int32_t *labels, const int32_t *ndrops, int32_t *new_tracer, int32_t *nmoved) {
+  int ntr = *ntracers;
+  if (ntr < 0 || ntr > max_tracers) return ORC_E_ARG;
+  orc_edge *E = NULL;
+  int64_t ne = orc_neighbours_stencil(nx, ny, nz, ntr, labels, ndrops, &E);
+  return recolor_given_edges(nx, ny, nz, ntracers, max_tracers, c, labels, ndrops, E, ne, new_tracer, nmoved);
 }
 
 /* =========================================================================
