@@ -186,6 +186,27 @@ int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, in
                           double gap_cells, int32_t *new_tracer, int32_t *nmoved_host, hipStream_t stream);
 
 /*
+ * The same reassignment with the near-contact criterion of Steps 1-3 read
+ * literally (section "The no-coalescence.h algorithm", the near-contact
+ * criterion figure), selectable beside the distance threshold above:
+ *   - within a tracer, two drops are neighbours (a conflict) when a cell with
+ *     no drop of that tracer (label 0: "C_i = 0" at the centre) has a cell of
+ *     one drop and a cell of the other at opposite offsets +o, -o of the
+ *     5x5x5 stencil, o in {-2..2}^3 \ {0} (Step 1, "C_i > 1" read as C_i > 0;
+ *     Step 3, different tags);
+ *   - across tracers, two drops are in contact (Step 4: the tracers a moved
+ *     drop must avoid) when cells of the two lie within 4 cells of each other
+ *     along every axis, the reach of the stencil, overlap included (a
+ *     reading: the paper does not define this contact).
+ * Visiting order, choice of the new tracer, cell moves, arguments, outputs,
+ * scratch and errors as for vofmt_recolor_tracers (no gap argument). Extra
+ * scratch: one 64-bit occupancy word per 64-cell row segment per tracer.
+ */
+int vofmt_recolor_tracers_stencil(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t *ntracers_host,
+                                  int32_t max_tracers, double *c, const int32_t *labels, const int32_t *ndrops_host,
+                                  int32_t *new_tracer, int32_t *nmoved_host, hipStream_t stream);
+
+/*
  * Tracer compaction: the number of tracers in use, N(t), is what the paper
  * reports for its runs (section "The no-coalescence.h algorithm"); a tracer
  * holding no drop (every value at or below the labelling threshold) is

@@ -20,6 +20,16 @@
 //      for the conflict test and an OR-reduction for the tracers in use;
 //   5. the host reads back the tracer count (capacity check), then every
 //      cell clears its moved-out values and adds them to the new fields.
+//
+// Stencil mode (vofmt_recolor_tracers_stencil): the neighbour relation of
+// step 2 is the paper's criterion read literally. Within a tracer, two drops
+// are neighbours when an empty cell (label 0) has one of them and the other
+// at opposite offsets +o, -o of the 5x5x5 stencil (Steps 1-3): one wavefront
+// per 64-cell row segment tests the 62 opposite pairs on occupancy bits of
+// the 25 neighbouring rows and loads labels only for candidate pairs. Across
+// tracers, drops are neighbours ("in contact", Step 4) when cells of the two
+// lie within 4 cells along every axis (the stencil's reach), found by the
+// scan of step 2 over the half 9x9x9 cube, pairs within one tracer skipped.
 #include <cstdlib>
 #include <cstring>
 
@@ -89,7 +99,12 @@ __device__ __forceinline__ void edges_of(const int32_t *__restrict__ own, const 
                                          int ny, int nz, int ntr, const TracerOffsets &to,
                                          const int4 *__restrict__ offs, int noffs, int small_offsets,
                                          uint32_t *__restrict__ adj, int64_t words, int64_t n3, const FastDiv &fnx,
-                                         const FastDiv &fny, int64_t p) {
+                                         const FastDiv &fny, const int32_t *__restrict__ cross_T0, int64_t p) {
+  // cross_T0 != null: only drops of different tracers (initial tracer per drop) are related
+  auto set_edge = [&](uint32_t *adj_, int64_t words_, int32_t u, int32_t v) {
+    if (cross_T0 != nullptr && cross_T0[u] == cross_T0[v]) return;
+    ::set_edge(adj_, words_, u, v);
+  };
   const int32_t a = own[p];
   const uint32_t r = fast_div((uint32_t)p, fnx), zz = fast_div(r, fny);  // cells < 2^31
   const int x = (int)((uint32_t)p - r * (uint32_t)nx), y = (int)(r - zz * (uint32_t)ny), z = (int)zz;
@@ -159,13 +174,113 @@ __global__ __launch_bounds__(kBlock) void k_edges(const int32_t *__restrict__ ow
                                                   const int4 *__restrict__ offs, int noffs, int small_offsets,
                                                   const int32_t *__restrict__ list, const int32_t *__restrict__ count,
                                                   uint32_t *__restrict__ adj, int64_t words, FastDiv fnx,
-                                                  FastDiv fny) {
+                                                  FastDiv fny, const int32_t *__restrict__ cross_T0) {
   const int64_t n3 = (int64_t)nx * ny * nz;
   const int nlist = *count;
   for (int qi = blockIdx.x * kBlock + threadIdx.x; qi < nlist; qi += gridDim.x * kBlock) {
     const int64_t p = list[qi];
-    edges_of(own, lab, nx, ny, nz, ntr, to, offs, noffs, small_offsets, adj, words, n3, fnx, fny, p);
+    edges_of(own, lab, nx, ny, nz, ntr, to, offs, noffs, small_offsets, adj, words, n3, fnx, fny, cross_T0, p);
   }
+}
+
+// Occupancy of every 64-cell row segment of every tracer: bit l of word
+// occ[t][z][y][w] is (label > 0) of cell x = 64 w + l (0 beyond the row).
+__global__ __launch_bounds__(kBlock) void k_occ_words(const int32_t *__restrict__ lab, int nx, int64_t rows,
+                                                      int words, uint64_t *__restrict__ occ) {
+  const int64_t seg = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t nseg = rows * words;
+  if (seg >= nseg) return;  // whole wavefront
+  const int64_t row = seg / words;
+  const int w = (int)(seg - row * words);
+  const int x = 64 * w + lane;
+  const bool occ_ = x < nx && lab[row * nx + x] > 0;
+  const uint64_t b = __ballot(occ_);
+  if (lane == 0) occ[seg] = b;
+}
+
+// Bits of cells xs, xs+1, ..., xs+63 (periodic in x, xs any integer) of one
+// row of occupancy words.
+__device__ __forceinline__ uint64_t row_window(const uint64_t *__restrict__ rw, int nx, int xs) {
+  int x = wrap_any(xs, nx);
+  uint64_t res = 0;
+  int got = 0;
+  while (got < 64) {
+    const int b = x & 63;
+    int take = 64 - b;
+    if (take > nx - x) take = nx - x;
+    if (take > 64 - got) take = 64 - got;
+    uint64_t chunk = rw[x >> 6] >> b;
+    if (take < 64) chunk &= (1ull << take) - 1ull;
+    res |= chunk << got;
+    got += take;
+    x += take;
+    if (x == nx) x = 0;
+  }
+  return res;
+}
+
+// Steps 1-3 read literally, one wavefront per row segment (t, z, y, w), one
+// lane per centre cell: the centre is empty and the cells at +o and -o of the
+// 5x5x5 stencil are both occupied (tested on the occupancy bits of the 25
+// rows y-2..y+2, z-2..z+2); where they are, their labels are loaded and, if
+// they differ, the two drops are marked neighbours in both directions.
+__global__ __launch_bounds__(kBlock) void k_stencil_edges(const int32_t *__restrict__ lab,
+                                                          const uint64_t *__restrict__ occ, int nx, int ny, int nz,
+                                                          int ntr, int words, TracerOffsets to,
+                                                          uint32_t *__restrict__ adj, int64_t awords) {
+  const int64_t seg = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t rows = (int64_t)nz * ny;
+  if (seg >= (int64_t)ntr * rows * words) return;  // whole wavefront
+  const int64_t tr = seg / words;                  // (t, z, y) row of all tracers
+  const int w = (int)(seg - tr * words);
+  const int t = (int)(tr / rows);
+  const int64_t r = tr - (int64_t)t * rows;
+  const int z = (int)(r / ny), y = (int)(r - (int64_t)z * ny);
+  const uint64_t *occ_t = occ + (int64_t)t * rows * words;
+  const int x0 = 64 * w;
+  const int x = x0 + lane;
+  // 5-bit neighbourhoods of each lane: bit k of nb[5 (dy+2) + (dz+2)] is the
+  // occupancy of cell (x - 2 + k, y + dy, z + dz)
+  uint32_t nb[25];
+  uint64_t any = 0;
+#pragma unroll
+  for (int dy = -2; dy <= 2; ++dy)
+#pragma unroll
+    for (int dz = -2; dz <= 2; ++dz) {
+      const int yy = wrap_any(y + dy, ny), zz = wrap_any(z + dz, nz);
+      const uint64_t *rw = occ_t + ((int64_t)zz * ny + yy) * words;
+      const uint64_t wa = row_window(rw, nx, x0 - 2), wb = row_window(rw, nx, x0 + 62);
+      any |= wa | wb;
+      const uint64_t v = (lane == 0) ? wa : ((wa >> lane) | (wb << (64 - lane)));
+      nb[5 * (dy + 2) + (dz + 2)] = (uint32_t)(v & 31ull);
+    }
+  if (any == 0ull) return;  // no occupied cell near the segment (uniform)
+  const bool centre_empty = x < nx && !((nb[12] >> 2) & 1u);
+  if (!centre_empty) return;
+#pragma unroll
+  for (int oz = -2; oz <= 2; ++oz)
+#pragma unroll
+    for (int oy = -2; oy <= 2; ++oy)
+#pragma unroll
+      for (int ox = -2; ox <= 2; ++ox) {
+        // one of each opposite pair: o > 0 in (z, y, x) order
+        if (!(oz > 0 || (oz == 0 && (oy > 0 || (oy == 0 && ox > 0))))) continue;
+        const bool plus = (nb[5 * (oy + 2) + (oz + 2)] >> (ox + 2)) & 1u;
+        const bool minus = (nb[5 * (2 - oy) + (2 - oz)] >> (2 - ox)) & 1u;
+        if (!(plus && minus)) continue;
+        const int64_t qp = (((int64_t)t * nz + wrap_any(z + oz, nz)) * ny + wrap_any(y + oy, ny)) * nx +
+                           wrap_any(x + ox, nx);
+        const int64_t qm = (((int64_t)t * nz + wrap_any(z - oz, nz)) * ny + wrap_any(y - oy, ny)) * nx +
+                           wrap_any(x - ox, nx);
+        const int32_t la = lab[qp], lb = lab[qm];
+        if (la != lb && la > 0 && lb > 0 && to.off[t] + la <= to.off[t + 1] && to.off[t] + lb <= to.off[t + 1]) {
+          const int32_t ga = to.off[t] + la - 1, gb = to.off[t] + lb - 1;
+          set_edge(adj, awords, ga, gb);
+          set_edge(adj, awords, gb, ga);
+        }
+      }
 }
 
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
@@ -476,44 +591,52 @@ __global__ void k_sum_parts(const double *__restrict__ part, int n, double *__re
 
 }  // namespace
 
-extern "C" int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t *ntracers_host,
-                                     int32_t max_tracers, double *c, const int32_t *labels, const int32_t *ndrops_host,
-                                     double gap_cells, int32_t *new_tracer, int32_t *nmoved_host, hipStream_t stream) {
+// Both recolouring modes: stencil == 0 relates drops within the distance
+// threshold gap_cells, stencil != 0 by the literal 5x5x5 criterion (gap_cells
+// unused). `fn` names the entry point in error messages.
+static int recolor_impl(vofmt_ctx *ctx, const char *fn, int stencil, int32_t nx, int32_t ny, int32_t nz,
+                        int32_t *ntracers_host, int32_t max_tracers, double *c, const int32_t *labels,
+                        const int32_t *ndrops_host, double gap_cells, int32_t *new_tracer, int32_t *nmoved_host,
+                        hipStream_t stream) {
   if (!ctx) return VOFMT_E_ARG;
-  if (!ntracers_host || !nmoved_host || !ndrops_host)
-    return set_err(ctx, VOFMT_E_ARG, "vofmt_recolor_tracers: null host pointer");
+  if (!ntracers_host || !nmoved_host || !ndrops_host) return set_err(ctx, VOFMT_E_ARG, "%s: null host pointer", fn);
   const int ntr = *ntracers_host;
   if (nx < 1 || ny < 1 || nz < 1 || ntr < 0 || ntr > max_tracers || max_tracers > kMaxTracers ||
-      !(gap_cells >= 0.0) || gap_cells > 64.0)
-    return set_err(ctx, VOFMT_E_ARG,
-                   "vofmt_recolor_tracers: bad arguments (ntracers=%d max_tracers=%d (<= %d) gap=%g)", ntr,
+      (!stencil && (!(gap_cells >= 0.0) || gap_cells > 64.0)))
+    return set_err(ctx, VOFMT_E_ARG, "%s: bad arguments (ntracers=%d max_tracers=%d (<= %d) gap=%g)", fn, ntr,
                    max_tracers, kMaxTracers, gap_cells);
   *nmoved_host = 0;
   if (ntr == 0) return VOFMT_OK;
-  if (!c || !labels) return set_err(ctx, VOFMT_E_ARG, "vofmt_recolor_tracers: null pointer");
+  if (!c || !labels) return set_err(ctx, VOFMT_E_ARG, "%s: null pointer", fn);
   TracerOffsets to;
   to.off[0] = 0;
   int64_t D = 0;
   for (int t = 0; t < ntr; ++t) {
-    if (ndrops_host[t] < 0) return set_err(ctx, VOFMT_E_ARG, "vofmt_recolor_tracers: negative drop count");
+    if (ndrops_host[t] < 0) return set_err(ctx, VOFMT_E_ARG, "%s: negative drop count", fn);
     D += ndrops_host[t];
     to.off[t + 1] = (int32_t)D;
   }
   for (int t = ntr + 1; t <= kMaxTracers; ++t) to.off[t] = (int32_t)D;
   if (D == 0) return VOFMT_OK;
-  if (D > kMaxDrops) return set_err(ctx, VOFMT_E_ARG, "vofmt_recolor_tracers: more than %d drops", kMaxDrops);
-  if (!new_tracer) return set_err(ctx, VOFMT_E_ARG, "vofmt_recolor_tracers: null new_tracer");
+  if (D > kMaxDrops) return set_err(ctx, VOFMT_E_ARG, "%s: more than %d drops", fn, kMaxDrops);
+  if (!new_tracer) return set_err(ctx, VOFMT_E_ARG, "%s: null new_tracer", fn);
   const int64_t n3 = (int64_t)nx * ny * nz;
-  if (n3 >= INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "vofmt_recolor_tracers: more than 2^31-1 cells per field");
+  if (n3 >= INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "%s: more than 2^31-1 cells per field", fn);
   VOFMT_HIP(ctx, hipSetDevice(ctx->device));
-  // offsets of the half ball |o|^2 < (1+gap)^2, o > 0 in (z, y, x) order: a
-  // pair of drops is found from one side only, and k_symmetrise completes
-  // the adjacency. Every pair is still found: the two cells of the pair at
-  // the smallest offset are both listed (a cell whose six neighbours all
-  // held its drop would have a neighbour closer to the other drop), so the
-  // listed cell from which that offset points forward finds it.
-  const double lim = (1.0 + gap_cells) * (1.0 + gap_cells);
-  const int R = (int)floor(1.0 + gap_cells);
+  // Offsets scanned from the listed cells, one of each opposite pair (o > 0
+  // in (z, y, x) order): a pair of drops is found from one side only, and
+  // k_symmetrise completes the adjacency.
+  // - distance mode: the half ball |o|^2 < (1+gap)^2. Every pair is still
+  //   found: the two cells of the pair at the smallest offset are both listed
+  //   (a cell whose six neighbours all held its drop would have a neighbour
+  //   closer to the other drop), so the listed cell from which that offset
+  //   points forward finds it;
+  // - stencil mode (contacts across tracers): the half cube max|o_a| <= 4.
+  //   A pair of cells at the smallest (max|o_a|, sum|o_a|) is listed on both
+  //   sides: an axis step from an interior cell towards the other drop
+  //   lowers the sum and does not raise the maximum.
+  const int R = stencil ? 4 : (int)floor(1.0 + gap_cells);
+  const double lim = stencil ? 1e300 : (1.0 + gap_cells) * (1.0 + gap_cells);
   int4 *hoffs = nullptr;
   int noffs = 0;
   {
@@ -553,6 +676,22 @@ extern "C" int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int
   else
     hipLaunchKernelGGL(k_owner, dim3(nbc), dim3(kBlock), 0, stream, labels, n3, ntr, to, own);
   hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, stream, adj, D * words, 0u);
+  // initial tracer of every drop (the stencil mode's cross-tracer filter reads it)
+  hipLaunchKernelGGL(k_initial_tracers, dim3(ceil_div(D, 256)), dim3(256), 0, stream, T0, (int32_t)D, ntr, to);
+  if (stencil) {
+    // Steps 1-3 within every tracer, on occupancy bits per row segment
+    const int xw = (int)ceil_div(nx, 64);
+    const int64_t rows = (int64_t)nz * ny;
+    const int64_t nseg = (int64_t)ntr * rows * xw;
+    uint64_t *occ = (uint64_t *)scratch(ctx, SLOT_OCC, sizeof(uint64_t) * (size_t)nseg);
+    if (!occ) return VOFMT_E_NOMEM;
+    const int64_t nblk = (nseg * 64 + kBlock - 1) / kBlock;
+    if (nblk > INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "%s: grid too large", fn);
+    hipLaunchKernelGGL(k_occ_words, dim3((unsigned)nblk), dim3(kBlock), 0, stream, labels, nx, (int64_t)ntr * rows,
+                       xw, occ);
+    hipLaunchKernelGGL(k_stencil_edges, dim3((unsigned)nblk), dim3(kBlock), 0, stream, labels, occ, nx, ny, nz, ntr,
+                       xw, to, adj, words);
+  }
   {
     // the cells that can see a pair, in order, then the pairs they see
     const int64_t lt = compact::list_tiles(n3);
@@ -569,7 +708,7 @@ extern "C" int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int
       cus = 256;
     hipLaunchKernelGGL(k_edges, dim3(8 * cus), dim3(kBlock), 0, stream, own, labels, nx, ny, nz, ntr, to, doffs,
                        noffs, small_offsets, srcs, tot + lt, adj, words, make_fastdiv((uint32_t)nx),
-                       make_fastdiv((uint32_t)ny));
+                       make_fastdiv((uint32_t)ny), stencil ? (const int32_t *)T0 : nullptr);
   }
   hipLaunchKernelGGL(k_symmetrise, dim3(ceil_div(D * D, kBlock)), dim3(kBlock), 0, stream, adj, (int32_t)D, words);
   hipLaunchKernelGGL(k_degree, dim3(ceil_div(D, kBlock)), dim3(kBlock), 0, stream, adj, (int32_t)D, words, deg);
@@ -583,7 +722,6 @@ extern "C" int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int
   if (!nbr) return VOFMT_E_NOMEM;
   hipLaunchKernelGGL(k_csr_fill, dim3(ceil_div(D, kBlock)), dim3(kBlock), 0, stream, adj, (int32_t)D, words, rowptr,
                      nbr);
-  hipLaunchKernelGGL(k_initial_tracers, dim3(ceil_div(D, 256)), dim3(256), 0, stream, T0, (int32_t)D, ntr, to);
   hipLaunchKernelGGL(k_greedy_rounds, dim3(1), dim3(1024), 0, stream, rowptr, nbr, T0, (int32_t)D, ntr, new_tracer,
                      res);
   VOFMT_HIP(ctx, hipGetLastError());
@@ -597,9 +735,7 @@ extern "C" int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int
     VOFMT_HIP(ctx, hipStreamSynchronize(stream));
   }
   const int Nnew = hres[0], moved = hres[1], overflow = hres[2];
-  if (overflow)
-    return set_err(ctx, VOFMT_E_CAPACITY, "vofmt_recolor_tracers: more than max_tracers=%d tracers needed",
-                   max_tracers);
+  if (overflow) return set_err(ctx, VOFMT_E_CAPACITY, "%s: more than max_tracers=%d tracers needed", fn, max_tracers);
   if (moved > 0) {
     if (Nnew > ntr)
       hipLaunchKernelGGL(k_fill_f64, dim3(1024), dim3(256), 0, stream, c + (int64_t)ntr * n3,
@@ -610,6 +746,21 @@ extern "C" int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int
   *ntracers_host = Nnew;
   *nmoved_host = moved;
   return VOFMT_OK;
+}
+
+extern "C" int vofmt_recolor_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t *ntracers_host,
+                                     int32_t max_tracers, double *c, const int32_t *labels, const int32_t *ndrops_host,
+                                     double gap_cells, int32_t *new_tracer, int32_t *nmoved_host, hipStream_t stream) {
+  return recolor_impl(ctx, "vofmt_recolor_tracers", 0, nx, ny, nz, ntracers_host, max_tracers, c, labels,
+                      ndrops_host, gap_cells, new_tracer, nmoved_host, stream);
+}
+
+extern "C" int vofmt_recolor_tracers_stencil(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz,
+                                             int32_t *ntracers_host, int32_t max_tracers, double *c,
+                                             const int32_t *labels, const int32_t *ndrops_host, int32_t *new_tracer,
+                                             int32_t *nmoved_host, hipStream_t stream) {
+  return recolor_impl(ctx, "vofmt_recolor_tracers_stencil", 1, nx, ny, nz, ntracers_host, max_tracers, c, labels,
+                      ndrops_host, 0.0, new_tracer, nmoved_host, stream);
 }
 
 extern "C" int vofmt_compact_tracers(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t *ntracers_host,

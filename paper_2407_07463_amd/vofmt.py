@@ -52,6 +52,8 @@ _SIGNATURES = {
                                          _vp]),
     "vofmt_recolor_tracers": (ctypes.c_int, [_vp, _i32, _i32, _i32, _P_i32, _i32, _vp, _vp, _vp, _d, _vp, _P_i32,
                                              _vp]),
+    "vofmt_recolor_tracers_stencil": (ctypes.c_int, [_vp, _i32, _i32, _i32, _P_i32, _i32, _vp, _vp, _vp, _vp,
+                                                     _P_i32, _vp]),
     "vofmt_nearest_pair_stats": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
                                                 _vp, _vp, _vp, _vp]),
     "vofmt_pair_pdfs": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
@@ -275,6 +277,20 @@ class Context:
         self._check(load().vofmt_recolor_tracers(self.h, nx, ny, nz, ctypes.byref(ntr), maxt, _ptr(c),
                                                  _ptr(labels), nd.ctypes.data, float(gap_cells),
                                                  _ptr(new_tracer), ctypes.byref(nmoved), _stream(stream)))
+        return ntr.value, nmoved.value
+
+    def recolor_tracers_stencil(self, c, ntracers: int, labels, ndrops, new_tracer, stream=None):
+        """Literal 5x5x5 near-contact criterion; c: [max_tracers][nz][ny][nx]; returns (ntracers_after,
+        nmoved)."""
+        _require(c, labels, new_tracer)
+        nx, ny, nz = _dims(c)
+        maxt = int(c.shape[0])
+        nd = np.ascontiguousarray(ndrops, dtype=np.int32)
+        ntr = ctypes.c_int32(int(ntracers))
+        nmoved = ctypes.c_int32(0)
+        self._check(load().vofmt_recolor_tracers_stencil(self.h, nx, ny, nz, ctypes.byref(ntr), maxt, _ptr(c),
+                                                         _ptr(labels), nd.ctypes.data, _ptr(new_tracer),
+                                                         ctypes.byref(nmoved), _stream(stream)))
         return ntr.value, nmoved.value
 
     def compact_tracers(self, c, ntracers: int, ndrops, stream=None):

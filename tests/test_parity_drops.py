@@ -221,6 +221,100 @@ def test_recolour_spheres64(ctx, spheres64_after):
     assert np.array_equal(g, o)
 
 
+def test_recolour_drops256_eight_tracers(ctx):
+    """The medium workload (256^3, 8 tracers, ~400 drops of diameter 20 at phi = 0.1, gap
+    1.5): tracer count, assignment, moved count and fields bit-exact against the oracle's
+    greedy pass, so the visiting order and the choice of the new tracer are checked at a size
+    where many drops move within the existing tracers."""
+    w = synth.drops256(workers=16)
+    src = w["c"]
+    ntr = src.shape[0]
+    maxt = 2 * ntr
+    c = np.zeros((maxt,) + src.shape[1:])
+    c[:ntr] = src
+    note("recolour drops256, 8 tracers")
+    g, gntr, gnewt, gmoved, glab, gnd = _gpu_recolour(ctx, c, ntr, 1.5)
+    ol = [oracle.label(src[t]) for t in range(ntr)]
+    labels = np.stack([o[0] for o in ol])
+    nd = np.array([o[1] for o in ol], dtype=np.int32)
+    assert np.array_equal(glab, labels) and list(gnd) == list(nd)
+    o, ontr, onewt, omoved, rc = oracle.recolor(c, labels, nd, ntr, maxt, 1.5)
+    assert rc == 0 and omoved > 0
+    assert gntr == ontr and gmoved == omoved and np.array_equal(gnewt, onewt)
+    assert np.array_equal(g, o)
+
+
+# ------------------------------------------------------------------ recolouring, literal stencil criterion
+
+def _gpu_recolour_stencil(ctx, c_full, ntr):
+    import torch
+
+    tc = _dev(c_full)
+    lab = torch.zeros((ntr,) + c_full.shape[1:], dtype=torch.int32, device="cuda:0")
+    nd = ctx.label_drops(tc[:ntr], lab)
+    D = int(nd.sum())
+    newt = torch.zeros(max(D, 1), dtype=torch.int32, device="cuda:0")
+    ntr_new, nmoved = ctx.recolor_tracers_stencil(tc, ntr, lab, nd, newt)
+    torch.cuda.synchronize()
+    return tc.cpu().numpy(), ntr_new, newt[:D].cpu().numpy(), nmoved, lab.cpu().numpy(), nd
+
+
+def _check_stencil_case(ctx, c, ntr, maxt, expect_moves=None):
+    g, gntr, gnewt, gmoved, glab, gnd = _gpu_recolour_stencil(ctx, c, ntr)
+    ol = [oracle.label(c[t]) for t in range(ntr)]
+    labels = np.stack([o[0] for o in ol])
+    nd = np.array([o[1] for o in ol], dtype=np.int32)
+    assert np.array_equal(glab, labels) and list(gnd) == list(nd)
+    o, ontr, onewt, omoved, rc = oracle.recolor_stencil(c, labels, nd, ntr, maxt)
+    assert rc == 0
+    assert gntr == ontr and gmoved == omoved and np.array_equal(gnewt, onewt)
+    assert np.array_equal(g, o)
+    if expect_moves is not None:
+        assert omoved == expect_moves
+    return omoved
+
+
+def test_recolour_stencil_figure(ctx):
+    p = near_contact_panels()
+    for name, moves in (("left", 1), ("right", 0)):
+        c2 = panel_fields(p[name], pad=(8, 8))
+        c = np.zeros((4,) + c2.shape[1:])
+        c[:2] = c2
+        note(f"recolour stencil figure {name}")
+        _check_stencil_case(ctx, c, 2, 4, moves)
+
+
+@pytest.mark.parametrize("seed,ntr,shape", [(0, 3, (21, 26, 33)), (1, 3, (21, 26, 33)), (2, 8, (21, 26, 33)),
+                                            (3, 2, (9, 70, 130)), (4, 5, (40, 7, 66)), (5, 1, (30, 30, 30))])
+def test_recolour_stencil_random(ctx, seed, ntr, shape):
+    """Dense random drops on ragged grids: rows shorter and longer than one 64-cell segment,
+    thin axes (the stencil wraps around a 7-cell axis), one to eight tracers."""
+    rng = np.random.default_rng(500 + seed)
+    maxt = 12
+    c = np.zeros((maxt,) + shape)
+    nblobs = max(8, int(np.prod(shape) / 400))
+    c[:ntr] = random_blobs(rng, shape, ntr, nblobs, 1.0, 2.6)
+    note(f"recolour stencil random seed={seed} ntr={ntr} shape={shape}")
+    _check_stencil_case(ctx, c, ntr, maxt)
+
+
+def test_recolour_stencil_spheres(ctx, spheres64_after):
+    c = np.zeros((4,) + spheres64_after.shape[1:])
+    c[:2] = spheres64_after
+    note("recolour stencil spheres64")
+    _check_stencil_case(ctx, c, 2, 4)
+
+
+def test_recolour_stencil_drops96(ctx):
+    """Drops of diameter 20 at phi = 0.3 in a 96^3 box over four tracers (RSA gap 1): many
+    conflicts within reach of the stencil."""
+    w = synth.random_drops(96, 4, 0.3, 20.0, 0.1, 1.0, seed=synth.workload_seed(7), order=8, workers=16)
+    c = np.zeros((8,) + w["c"].shape[1:])
+    c[:4] = w["c"]
+    note("recolour stencil drops96")
+    assert _check_stencil_case(ctx, c, 4, 8) > 0
+
+
 # ------------------------------------------------------------------ statistics
 
 def _gpu_stats(ctx, xyz, box, vaxis, r2e, ce):

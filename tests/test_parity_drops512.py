@@ -213,3 +213,55 @@ def test_csf_force(ctx, drops512):
     o = oracle.csf_force(c, kap, 0.05)
     for d in range(3):
         assert np.array_equal(g[d].view(np.uint64), o[d].view(np.uint64)), d
+
+
+def _same_tracer_pairs_within(torch, lab, newt_dev, first, ntr, cap, tau):
+    """Pairs of drops assigned to one tracer with cells closer than (1 + tau) (offset 0
+    included), counted on the GPU by shifting per-tracer drop-id fields (test code)."""
+    lim = (1.0 + tau) ** 2
+    R = int(np.floor(1.0 + tau))
+    offs = [(ox, oy, oz) for oz in range(-R, R + 1) for oy in range(-R, R + 1) for ox in range(-R, R + 1)
+            if 0 < ox * ox + oy * oy + oz * oz < lim and (oz > 0 or (oz == 0 and (oy > 0 or (oy == 0 and ox > 0))))]
+    bad = 0
+    for n in range(cap):
+        ids = torch.zeros(lab.shape[1:], dtype=torch.int32, device=lab.device)
+        cnt = torch.zeros(lab.shape[1:], dtype=torch.int32, device=lab.device)
+        for t in range(ntr):
+            lt = lab[t].long()
+            g = torch.where(lt > 0, first[t] + lt - 1, torch.zeros_like(lt))
+            mine = (lt > 0) & (newt_dev[g] == n)
+            ids = torch.where(mine, (g + 1).int(), ids)
+            cnt += mine.int()
+        bad += int((cnt > 1).sum().item())  # two drops of tracer n in one cell
+        for ox, oy, oz in offs:
+            sh = torch.roll(ids, shifts=(oz, oy, ox), dims=(0, 1, 2))
+            bad += int(((ids > 0) & (sh > 0) & (ids != sh)).sum().item())
+    return bad
+
+
+def test_recolour_benchmark_configuration_is_a_proper_colouring(ctx, drops512):
+    """All eight tracers of the benchmark field: after the pass no two drops that share a
+    tracer have cells closer than the threshold (the property Step 4 exists for), checked
+    by brute force over every offset of the ball on every tracer's drop-id field."""
+    import torch
+
+    src = drops512["c"]
+    ntr = src.shape[0]
+    cap = 2 * ntr
+    shape = src.shape[1:]
+    note("recolour drops512, 8 tracers: proper colouring")
+    tc = torch.zeros((cap,) + shape, dtype=torch.float64, device="cuda:0")
+    tc[:ntr].copy_(torch.from_numpy(src))
+    lab = torch.zeros((ntr,) + shape, dtype=torch.int32, device="cuda:0")
+    nd = ctx.label_drops(tc[:ntr], lab)
+    D = int(nd.sum())
+    newt = torch.zeros(D, dtype=torch.int32, device="cuda:0")
+    gntr, gmoved = ctx.recolor_tracers(tc, ntr, lab, nd, GAP, newt)
+    torch.cuda.synchronize()
+    del tc
+    assert gmoved > 0
+    first = [0] + list(np.cumsum(nd)[:-1])
+    # before the pass the input has conflicts within tracers; after it none are left
+    home = torch.from_numpy(np.repeat(np.arange(ntr), nd).astype(np.int32)).to("cuda:0")
+    assert _same_tracer_pairs_within(torch, lab, home, first, ntr, ntr, GAP) > 0
+    assert _same_tracer_pairs_within(torch, lab, newt, first, ntr, gntr, GAP) == 0
