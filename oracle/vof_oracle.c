@@ -150,8 +150,21 @@ static inline double blk_axis(const double *b, int d, int e, int u, int v) {
  * Centred columns: for each column axis d the candidate is
  * (sigma, -g1, -g2)/D with D = (|g1| + |g2|) + 1 and quality 1/D; the best
  * quality is the smallest D (ties: lowest axis), and only that candidate is
- * normalised. */
-int orc_myc_normal(const double *b, double *m_out) {
+ * normalised.
+ * Reading: the normal is taken from the block with every value within
+ * ORC_RESIDUE of 0 or of 1 replaced by 0 or 1. Conservative fluxes leave such
+ * residues (+-1e-17 and below) in cells the interface never reached; they
+ * carry no interface information, yet the normal of an interface cell whose
+ * neighbours are all residues (a small isolated sliver) would be decided by
+ * their rounding noise. The plane constant still matches the cell's own c,
+ * so volume is conserved as before. */
+#define ORC_RESIDUE 1e-12
+int orc_myc_normal(const double *b_in, double *m_out) {
+  double b[27];
+  for (int q = 0; q < 27; ++q) {
+    double v = b_in[q];
+    b[q] = (v <= ORC_RESIDUE) ? 0.0 : ((v >= 1.0 - ORC_RESIDUE) ? 1.0 : v);
+  }
   double Dd[3], sg[3], g1d[3], g2d[3];
   for (int d = 0; d < 3; ++d) {
     double H[3][3]; /* H[u+1][v+1]: column sums along d */

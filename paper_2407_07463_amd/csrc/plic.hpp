@@ -171,8 +171,18 @@ __device__ __forceinline__ double alpha_of(double mx, double my, double mz, doub
 // differences (weights 1,2,1) of the block. The centred-columns candidate is
 // kept unless Youngs is defined and its largest component is strictly
 // smaller than the centred-columns quality. All sums run in increasing
-// stencil index.
-__device__ __forceinline__ void myc_normal(const double *b, double &nx_, double &ny_, double &nz_) {
+// stencil index. Values within kResidue of 0 or 1 enter as 0 or 1: the
+// round-off residue that conservative fluxes leave in cells the interface
+// never reached must not decide the normal of a small isolated sliver (the
+// plane constant still matches the cell's own value).
+constexpr double kResidue = 1e-12;
+__device__ __forceinline__ double clean_residue(double v) {
+  return (v <= kResidue) ? 0.0 : ((v >= 1.0 - kResidue) ? 1.0 : v);
+}
+__device__ __forceinline__ void myc_normal(const double *b_in, double &nx_, double &ny_, double &nz_) {
+  double b[27];
+#pragma unroll
+  for (int q = 0; q < 27; ++q) b[q] = clean_residue(b_in[q]);
 #define B(ax, ay, az) b[((ax) + 1) + 3 * ((ay) + 1) + 9 * ((az) + 1)]
   // best centred-columns axis: smallest D = (|g1| + |g2|) + 1, ties to the lower axis
   int ds = 0;

@@ -143,3 +143,46 @@ def test_sweep_order_cycles_with_global_step(spheres64):
     assert np.array_equal(a, b)
     c = oracle.advect(w["c"], w["sx"], w["sy"], w["sz"], 1, 6)
     assert not np.array_equal(b, c)
+
+
+def test_residues_do_not_decide_a_slivers_normal():
+    """An isolated small cell whose neighbours hold only round-off residues (+-1e-17 and below)
+    takes the isolated-cell normal (1, 0, 0) whatever the residues' signs and sizes; residues
+    near 1 count as full cells. Values above the residue level still act."""
+    rng = np.random.default_rng(11)
+    for _ in range(50):
+        b = rng.choice([-1, 1], size=(3, 3, 3)) * 10.0 ** rng.uniform(-37, -13, size=(3, 3, 3))
+        b[1, 1, 1] = 2.3e-7
+        m, used_cs = oracle.myc_normal(b)
+        assert used_cs and tuple(m) == (1.0, 0.0, 0.0)
+        full = 1.0 - np.abs(b) * (np.abs(b) < 1e-13)  # residues below 1: a full block
+        full[1, 1, 1] = 0.5
+        full[:, :, 2] = np.abs(b[:, :, 2]) * (np.abs(b[:, :, 2]) < 1e-13)  # an empty x-layer
+        m, _ = oracle.myc_normal(full)
+        assert m[0] == 1.0 and m[1] == 0.0 and m[2] == 0.0
+    b = np.zeros((3, 3, 3))
+    b[1, 1, 1] = 2.3e-7
+    b[2, 1, 1] = 1e-9  # a real (if small) neighbour above: the normal points away from it
+    m, _ = oracle.myc_normal(b)
+    assert m[2] < 0
+
+
+def test_chain_is_not_sensitive_to_rounding():
+    """Dense drops after a recolouring (slivers, isolated small cells, residues everywhere):
+    a one-ulp perturbation of the input stays at the rounding level over 12 steps. (Taking
+    the normal from the raw residues, the same perturbation grew to 1e-6.)"""
+    w = synth.random_drops(48, 2, 0.25, 12.0, 0.1, 1.0, seed=synth.workload_seed(9), order=8)
+    c0 = np.zeros((6,) + w["c"].shape[1:])
+    c0[:2] = w["c"]
+    ls = [oracle.label(c0[t]) for t in range(2)]
+    lab = np.stack([l for l, _ in ls])
+    nd = np.array([k for _, k in ls], dtype=np.int32)
+    c1, n, _, moved, rc = oracle.recolor(c0, lab, nd, 2, 6, 1.5)
+    assert rc == 0 and moved > 0
+    start = c1[:n]
+    rng = np.random.default_rng(1)
+    pert = start * (1 + 2.0 ** -52 * rng.choice([-1, 0, 1], size=start.shape))
+    s = [w["sx"], w["sy"], w["sz"]]
+    a = oracle.advect(start, *s, 0, 12)
+    b = oracle.advect(pert, *s, 0, 12)
+    assert np.abs(a - b).max() < 1e-13
