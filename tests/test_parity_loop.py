@@ -5,8 +5,8 @@ The paper reports the number of tracers in use, N(t) (section "The
 no-coalescence.h algorithm"). Both sides start from the same seeded field
 and each runs its own chain; N(t), the drops, the moves and the retirements
 of every block must agree exactly, and the fields at the end within 1e-12
-(the advection bar). One case starts with an empty tracer, so that the
-compaction retires it at the first block.
+(the advection bar). One case starts with an empty tracer between two
+others, so that the compaction retires it at the first block.
 """
 import numpy as np
 import pytest
@@ -58,23 +58,29 @@ def _oracle_loop(c0, ntr, s, steps, every, mode, gap):
     return N, recs, c
 
 
-@pytest.mark.parametrize("mode,empty_tracer", [("tau", False), ("stencil", False), ("tau", True)])
-def test_tracer_count_loop(ctx, mode, empty_tracer):
+@pytest.mark.parametrize("mode,case", [("tau", "dense"), ("stencil", "dense"), ("tau", "empty_tracer")])
+def test_tracer_count_loop(ctx, mode, case):
+    """dense: drops 1 cell apart in two tracers, many moves and new tracers. empty_tracer:
+    dilute drops (6 cells apart, no conflict) in tracers 0 and 2 with tracer 1 empty: the
+    first block retires it and tracer 2 moves down."""
     import torch
 
     from paper_2407_07463_amd import tracer_count
 
-    w = synth.random_drops(48, 2, 0.25, 12.0, 0.1, 1.0, seed=synth.workload_seed(9), order=8)
-    ntr = 3 if empty_tracer else 2
-    cap = 6
-    c0 = np.zeros((cap,) + w["c"].shape[1:])
-    if empty_tracer:  # tracer 1 holds nothing: retired at the first block
-        c0[0], c0[2] = w["c"][0], w["c"][1]
-    else:
+    cap = 12  # the stencil criterion reaches 4 cells: the dense field needs more than 6 tracers
+    if case == "dense":
+        w = synth.random_drops(48, 2, 0.25, 12.0, 0.1, 1.0, seed=synth.workload_seed(9), order=8)
+        ntr = 2
+        c0 = np.zeros((cap,) + w["c"].shape[1:])
         c0[:2] = w["c"]
+    else:
+        w = synth.random_drops(48, 2, 0.04, 10.0, 0.1, 6.0, seed=synth.workload_seed(10), order=8)
+        ntr = 3
+        c0 = np.zeros((cap,) + w["c"].shape[1:])
+        c0[0], c0[2] = w["c"][0], w["c"][1]
     s = [w["sx"], w["sy"], w["sz"]]
     steps, every = 12, 4
-    note(f"tracer-count loop mode={mode} empty_tracer={empty_tracer}")
+    note(f"tracer-count loop mode={mode} case={case}")
     tc = torch.from_numpy(c0).to("cuda:0")
     ts = [torch.from_numpy(a).to("cuda:0") for a in s]
     gN, grec = tracer_count.run(ctx, tc, *ts, ntr, steps, every, mode, 1.5)
@@ -84,6 +90,7 @@ def test_tracer_count_loop(ctx, mode, empty_tracer):
     assert [{k: r[k] for k in keys} for r in grec] == orec
     assert gN == oN
     assert np.abs(tc.cpu().numpy() - oc).max() <= 1e-12
-    assert any(r["moved"] > 0 for r in orec)
-    if empty_tracer:
-        assert orec[0]["retired"] == 1
+    if case == "dense":
+        assert any(r["moved"] > 0 for r in orec) and oN > 2
+    else:
+        assert orec[0]["retired"] == 1 and orec[0]["moved"] == 0 and orec[0]["ntracers"] == 2
