@@ -255,6 +255,24 @@ int vofmt_nearest_pair_stats(vofmt_ctx *ctx, int32_t n, const double *xyz, const
                              double *A, hipStream_t stream);
 
 /*
+ * vofmt_nearest_pair_stats for callers that cannot allocate memory: code
+ * under HIP graph capture, serving loops, harnesses that forbid allocation.
+ * Same operation, arguments, outputs and results (bit for bit) as
+ * vofmt_nearest_pair_stats, but no device or host memory is allocated and
+ * the stream is not synchronised: the kernels work in a fixed array of the
+ * library (4.8 MiB per device, held until the process ends) and the bin
+ * edges travel as a kernel argument. Limits: n <= 8192 drops and
+ * nr + ntheta + 2 <= 384 edges, else VOFMT_E_ARG (nothing enqueued). Every
+ * call on one device shares that device's array: calls that overlap on a
+ * device (any context or stream) race. VOFMT_E_HIP if the array's device
+ * address could not be found when the context was created.
+ */
+int vofmt_nearest_pair_stats_noalloc(vofmt_ctx *ctx, int32_t n, const double *xyz, const double *box,
+                                     int32_t vertical_axis, int32_t nr, int32_t ntheta, const double *r2_edges,
+                                     const double *cos_edges, int32_t *nn_index, int32_t *nn_ties,
+                                     uint64_t *hist_fixed, double *M, double *R, double *A, hipStream_t stream);
+
+/*
  * Probability densities of the nearest-particle vector (section "Nearest
  * particle statistics", eqs. 8 and 10) from a histogram of
  * vofmt_nearest_pair_stats, or the sum of several over time (the paper

@@ -138,6 +138,9 @@ extern "C" int vofmt_create(vofmt_ctx **out, int device) {
   if (hipSetDevice(device) != hipSuccess) return VOFMT_E_HIP;
   vofmt_ctx *ctx = new vofmt_ctx();
   ctx->device = device;
+  // the fixed scratch of the no-allocation entry point: its address on this
+  // device (a failure only disables that entry point, which then says so)
+  if (noalloc_setup(device) != hipSuccess) (void)hipGetLastError();
   *out = ctx;
   return VOFMT_OK;
 }

@@ -76,6 +76,9 @@ enum ScratchSlot {
 static_assert(kNumSlots == kNumSlotsDecl, "scratch slot count");
 
 int set_err(vofmt_ctx *ctx, int code, const char *fmt, ...);
+// Looks up the device address of the fixed scratch array of the
+// no-allocation statistics entry point for `device` (current), once per device.
+hipError_t noalloc_setup(int device);
 int hip_check(vofmt_ctx *ctx, hipError_t e, const char *what);
 // Device scratch of at least `bytes` in slot `slot`; nullptr on failure (error set).
 void *scratch(vofmt_ctx *ctx, int slot, size_t bytes);

@@ -9,6 +9,8 @@
 // contributes h r and h r r^T to the moments M (eq. 11) and R (eq. 14).
 // Per-drop moment contributions are summed in a fixed tree order, so every
 // output is reproducible bit for bit.
+#include <mutex>
+
 #include "common.hpp"
 
 namespace {
@@ -224,57 +226,175 @@ __global__ void k_zero_u64(uint64_t *p, int64_t n) {
 
 }  // namespace
 
+// Argument checks shared by both entry points (host data only).
+static int check_stats_args(vofmt_ctx *ctx, const char *fn, int32_t n, const double *xyz, const double *box,
+                            int32_t vertical_axis, int32_t nr, int32_t ntheta, const double *r2_edges,
+                            const double *cos_edges, int32_t *nn_index, int32_t *nn_ties, uint64_t *hist_fixed,
+                            double *M, double *R) {
+  if (n < 2 || vertical_axis < 0 || vertical_axis > 2 || nr < 1 || ntheta < 1)
+    return set_err(ctx, VOFMT_E_ARG, "%s: bad sizes (n=%d nr=%d ntheta=%d axis=%d)", fn, n, nr, ntheta,
+                   vertical_axis);
+  if (!xyz || !box || !r2_edges || !cos_edges || !nn_index || !nn_ties || !hist_fixed || !M || !R)
+    return set_err(ctx, VOFMT_E_ARG, "%s: null pointer", fn);
+  for (int a = 0; a < 3; ++a)
+    if (!(box[a] > 0.0)) return set_err(ctx, VOFMT_E_ARG, "%s: box must be positive", fn);
+  for (int e = 0; e < nr; ++e)
+    if (!(r2_edges[e] < r2_edges[e + 1])) return set_err(ctx, VOFMT_E_ARG, "%s: r2_edges must increase", fn);
+  for (int e = 0; e < ntheta; ++e)
+    if (!(cos_edges[e] > cos_edges[e + 1])) return set_err(ctx, VOFMT_E_ARG, "%s: cos_edges must decrease", fn);
+  return VOFMT_OK;
+}
+
+// Candidate slices of the nearest search: at most kMaxSlices slices, each a
+// whole number of kBlock indices.
+struct SliceShape {
+  int32_t nblk, len, ns;
+};
+static SliceShape slice_shape(int32_t n) {
+  SliceShape sh;
+  sh.nblk = (int32_t)ceil_div(n, kBlock);
+  const int32_t per = (int32_t)ceil_div(sh.nblk, kMaxSlices);
+  sh.len = per * kBlock;
+  sh.ns = (int32_t)ceil_div(n, sh.len);
+  return sh;
+}
+
+// The kernels of one call, on device buffers: dedge (edges, already on the
+// device), best [n], part [12 n], sl (ns * n * 16 bytes).
+static void launch_stats(int32_t n, const double *xyz, const double *box, int32_t vertical_axis, int32_t nr,
+                         int32_t ntheta, const double *dedge, double *best, double *part, char *sl,
+                         int32_t *nn_index, int32_t *nn_ties, uint64_t *hist_fixed, double *M, double *R, double *A,
+                         hipStream_t stream) {
+  const SliceShape sh = slice_shape(n);
+  double *sbest = (double *)sl;
+  int32_t *sbj = (int32_t *)(sbest + (size_t)sh.ns * n);
+  int32_t *sties = sbj + (size_t)sh.ns * n;
+  Box b;
+  for (int a = 0; a < 3; ++a) b.L[a] = box[a];
+  const int64_t nh = (int64_t)nr * ntheta + 1;
+  hipLaunchKernelGGL(k_zero_u64, dim3(ceil_div(nh, 256)), dim3(256), 0, stream, hist_fixed, nh);
+  hipLaunchKernelGGL(k_nearest_slice, dim3(sh.nblk, sh.ns), dim3(kBlock), 0, stream, xyz, n, b, sh.len, sbest, sbj,
+                     sties);
+  hipLaunchKernelGGL(k_nearest_combine, dim3(sh.nblk), dim3(kBlock), 0, stream, n, sh.ns, sbest, sbj, sties,
+                     nn_index, nn_ties, best);
+  hipLaunchKernelGGL(k_pairs, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, stream, xyz, n, b, vertical_axis, nr,
+                     ntheta, dedge, nn_index, nn_ties, best, hist_fixed, part);
+  hipLaunchKernelGGL(k_moments, dim3(1), dim3(kBlock), 0, stream, part, n, M, R, A);
+}
+
 extern "C" int vofmt_nearest_pair_stats(vofmt_ctx *ctx, int32_t n, const double *xyz, const double *box,
                                         int32_t vertical_axis, int32_t nr, int32_t ntheta, const double *r2_edges,
                                         const double *cos_edges, int32_t *nn_index, int32_t *nn_ties,
                                         uint64_t *hist_fixed, double *M, double *R, double *A,
                                         hipStream_t stream) {
   if (!ctx) return VOFMT_E_ARG;
-  if (n < 2 || vertical_axis < 0 || vertical_axis > 2 || nr < 1 || ntheta < 1)
-    return set_err(ctx, VOFMT_E_ARG, "vofmt_nearest_pair_stats: bad sizes (n=%d nr=%d ntheta=%d axis=%d)", n, nr,
-                   ntheta, vertical_axis);
-  if (!xyz || !box || !r2_edges || !cos_edges || !nn_index || !nn_ties || !hist_fixed || !M || !R)
-    return set_err(ctx, VOFMT_E_ARG, "vofmt_nearest_pair_stats: null pointer");
-  for (int a = 0; a < 3; ++a)
-    if (!(box[a] > 0.0)) return set_err(ctx, VOFMT_E_ARG, "vofmt_nearest_pair_stats: box must be positive");
-  for (int e = 0; e < nr; ++e)
-    if (!(r2_edges[e] < r2_edges[e + 1]))
-      return set_err(ctx, VOFMT_E_ARG, "vofmt_nearest_pair_stats: r2_edges must increase");
-  for (int e = 0; e < ntheta; ++e)
-    if (!(cos_edges[e] > cos_edges[e + 1]))
-      return set_err(ctx, VOFMT_E_ARG, "vofmt_nearest_pair_stats: cos_edges must decrease");
+  int rc = check_stats_args(ctx, "vofmt_nearest_pair_stats", n, xyz, box, vertical_axis, nr, ntheta, r2_edges,
+                            cos_edges, nn_index, nn_ties, hist_fixed, M, R);
+  if (rc) return rc;
   VOFMT_HIP(ctx, hipSetDevice(ctx->device));
   const size_t nedge = (size_t)nr + 1 + (size_t)ntheta + 1;
+  const SliceShape sh = slice_shape(n);
   double *dedge = (double *)scratch(ctx, SLOT_MISC, sizeof(double) * nedge);
   double *best = (double *)scratch(ctx, SLOT_MISC2, sizeof(double) * (size_t)n);
   double *part = (double *)scratch(ctx, SLOT_MISC3, sizeof(double) * 12 * (size_t)n);
-  // at most kMaxSlices slices, each a whole number of kBlock indices
-  const int32_t nblk = (int32_t)ceil_div(n, kBlock);
-  const int32_t per = (int32_t)ceil_div(nblk, kMaxSlices);
-  const int32_t len = per * kBlock;
-  const int32_t ns = (int32_t)ceil_div(n, len);
-  char *sl = (char *)scratch(ctx, SLOT_LABEL_A, (sizeof(double) + 2 * sizeof(int32_t)) * (size_t)ns * n);
+  char *sl = (char *)scratch(ctx, SLOT_LABEL_A, (sizeof(double) + 2 * sizeof(int32_t)) * (size_t)sh.ns * n);
   double *hstage = (double *)host_scratch(ctx, sizeof(double) * nedge);
   if (!dedge || !best || !part || !sl || !hstage) return VOFMT_E_NOMEM;
-  double *sbest = (double *)sl;
-  int32_t *sbj = (int32_t *)(sbest + (size_t)ns * n);
-  int32_t *sties = sbj + (size_t)ns * n;
   for (int e = 0; e <= nr; ++e) hstage[e] = r2_edges[e];
   for (int e = 0; e <= ntheta; ++e) hstage[nr + 1 + e] = cos_edges[e];
   VOFMT_HIP(ctx, hipMemcpyAsync(dedge, hstage, sizeof(double) * nedge, hipMemcpyHostToDevice, stream));
-  Box b;
-  for (int a = 0; a < 3; ++a) b.L[a] = box[a];
-  const int64_t nh = (int64_t)nr * ntheta + 1;
-  hipLaunchKernelGGL(k_zero_u64, dim3(ceil_div(nh, 256)), dim3(256), 0, stream, hist_fixed, nh);
-  hipLaunchKernelGGL(k_nearest_slice, dim3(nblk, ns), dim3(kBlock), 0, stream, xyz, n, b, len, sbest, sbj, sties);
-  hipLaunchKernelGGL(k_nearest_combine, dim3(nblk), dim3(kBlock), 0, stream, n, ns, sbest, sbj, sties, nn_index,
-                     nn_ties, best);
-  hipLaunchKernelGGL(k_pairs, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, stream, xyz, n, b, vertical_axis, nr,
-                     ntheta, dedge, nn_index, nn_ties, best, hist_fixed, part);
-  hipLaunchKernelGGL(k_moments, dim3(1), dim3(kBlock), 0, stream, part, n, M, R, A);
+  launch_stats(n, xyz, box, vertical_axis, nr, ntheta, dedge, best, part, sl, nn_index, nn_ties, hist_fixed, M, R, A,
+               stream);
   VOFMT_HIP(ctx, hipGetLastError());
   // the staging buffer must stay valid until the copy has run
   VOFMT_HIP(ctx, hipStreamSynchronize(stream));
+  return VOFMT_OK;
+}
+
+// ---------------------------------------------------------------- no-allocation variant
+//
+// vofmt_nearest_pair_stats_noalloc runs the same kernels on a fixed device
+// array of this file instead of context scratch, and takes the bin edges as a
+// kernel argument instead of through pinned host staging, so it allocates
+// nothing and does not synchronise. Limits: n <= kNoAllocMaxDrops,
+// nr + ntheta + 2 <= kNoAllocMaxEdges. Every call on a device shares the
+// device's copy of the array: calls that overlap on one device race.
+constexpr int32_t kNoAllocMaxDrops = 8192;
+constexpr int32_t kNoAllocMaxEdges = 384;
+constexpr size_t kNoAllocOffBest = 256 * ((sizeof(double) * kNoAllocMaxEdges + 255) / 256);
+constexpr size_t kNoAllocOffPart = kNoAllocOffBest + sizeof(double) * kNoAllocMaxDrops;
+constexpr size_t kNoAllocOffSlices = kNoAllocOffPart + 12 * sizeof(double) * kNoAllocMaxDrops;
+// slices of the largest call: at most ceil(8192 / kBlock) = 32 of one kBlock each
+constexpr size_t kNoAllocSliceBytes = (sizeof(double) + 2 * sizeof(int32_t)) * 32 * (size_t)kNoAllocMaxDrops;
+constexpr size_t kNoAllocBytes = kNoAllocOffSlices + kNoAllocSliceBytes;  // 4.8 MiB
+static_assert(kNoAllocOffPart % 256 == 0 && kNoAllocOffSlices % 256 == 0, "aligned parts");
+static_assert(kNoAllocMaxDrops / kBlock <= kMaxSlices, "one slice per block at the largest size");
+
+static __device__ __align__(256) unsigned char noalloc_scratch[kNoAllocBytes];
+
+constexpr int kNoAllocMaxDevices = 64;
+static void *g_noalloc_ptr[kNoAllocMaxDevices] = {};
+static std::mutex g_noalloc_mu;
+
+// Device address of this device's copy of noalloc_scratch, looked up once per
+// device with that device current (called by vofmt_create). The host-side
+// name of the array is not a device address and is never passed to a kernel.
+hipError_t noalloc_setup(int device) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (g_noalloc_ptr[device]) return hipSuccess;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+  if (e != hipSuccess) return e;
+  g_noalloc_ptr[device] = p;
+  return hipSuccess;
+}
+
+struct EdgeTable {
+  double e[kNoAllocMaxEdges];
+};
+static_assert(sizeof(EdgeTable) <= 3072, "kernel argument size");
+
+__global__ void k_store_edges(EdgeTable t, int32_t n, double *__restrict__ out) {
+  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) out[i] = t.e[i];
+}
+
+extern "C" int vofmt_nearest_pair_stats_noalloc(vofmt_ctx *ctx, int32_t n, const double *xyz, const double *box,
+                                                int32_t vertical_axis, int32_t nr, int32_t ntheta,
+                                                const double *r2_edges, const double *cos_edges, int32_t *nn_index,
+                                                int32_t *nn_ties, uint64_t *hist_fixed, double *M, double *R,
+                                                double *A, hipStream_t stream) {
+  if (!ctx) return VOFMT_E_ARG;
+  const char *fn = "vofmt_nearest_pair_stats_noalloc";
+  int rc = check_stats_args(ctx, fn, n, xyz, box, vertical_axis, nr, ntheta, r2_edges, cos_edges, nn_index, nn_ties,
+                            hist_fixed, M, R);
+  if (rc) return rc;
+  if (n > kNoAllocMaxDrops)
+    return set_err(ctx, VOFMT_E_ARG, "%s: n=%d drops exceeds the fixed scratch limit of %d", fn, n,
+                   kNoAllocMaxDrops);
+  if ((int64_t)nr + ntheta + 2 > kNoAllocMaxEdges)
+    return set_err(ctx, VOFMT_E_ARG, "%s: nr + ntheta + 2 = %lld edges exceeds the limit of %d", fn,
+                   (long long)nr + ntheta + 2, kNoAllocMaxEdges);
+  const SliceShape sh = slice_shape(n);
+  if ((size_t)sh.ns * n * (sizeof(double) + 2 * sizeof(int32_t)) > kNoAllocSliceBytes)
+    return set_err(ctx, VOFMT_E_ARG, "%s: slice table exceeds the fixed scratch", fn);
+  if (ctx->device < 0 || ctx->device >= kNoAllocMaxDevices || !g_noalloc_ptr[ctx->device])
+    return set_err(ctx, VOFMT_E_HIP, "%s: the fixed scratch of device %d has no address", fn, ctx->device);
+  VOFMT_HIP(ctx, hipSetDevice(ctx->device));
+  char *base = (char *)g_noalloc_ptr[ctx->device];
+  double *dedge = (double *)base;
+  double *best = (double *)(base + kNoAllocOffBest);
+  double *part = (double *)(base + kNoAllocOffPart);
+  char *sl = base + kNoAllocOffSlices;
+  EdgeTable t;
+  const int32_t ne = nr + 1 + ntheta + 1;
+  for (int e = 0; e <= nr; ++e) t.e[e] = r2_edges[e];
+  for (int e = 0; e <= ntheta; ++e) t.e[nr + 1 + e] = cos_edges[e];
+  for (int e = ne; e < kNoAllocMaxEdges; ++e) t.e[e] = 0.0;
+  hipLaunchKernelGGL(k_store_edges, dim3(1), dim3(256), 0, stream, t, ne, dedge);
+  launch_stats(n, xyz, box, vertical_axis, nr, ntheta, dedge, best, part, sl, nn_index, nn_ties, hist_fixed, M, R, A,
+               stream);
+  VOFMT_HIP(ctx, hipGetLastError());
   return VOFMT_OK;
 }
 

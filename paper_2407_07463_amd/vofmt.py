@@ -56,6 +56,8 @@ _SIGNATURES = {
                                                      _P_i32, _vp]),
     "vofmt_nearest_pair_stats": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
                                                 _vp, _vp, _vp, _vp]),
+    "vofmt_nearest_pair_stats_noalloc": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp,
+                                                        _vp, _vp, _vp, _vp, _vp]),
     "vofmt_pair_pdfs": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "vofmt_curvature_hf": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp]),
     "vofmt_mlp_forward": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _vp]),
@@ -320,6 +322,19 @@ class Context:
         r2 = np.ascontiguousarray(r2_edges, dtype=np.float64)
         ce = np.ascontiguousarray(cos_edges, dtype=np.float64)
         return self._check(load().vofmt_nearest_pair_stats(
+            self.h, n, _ptr(xyz), b.ctypes.data, int(vertical_axis), len(r2) - 1, len(ce) - 1, r2.ctypes.data,
+            ce.ctypes.data, _ptr(nn_index), _ptr(nn_ties), _ptr(hist), _ptr(M), _ptr(R), _ptr(A), _stream(stream)))
+
+    def nearest_pair_stats_noalloc(self, xyz, box, vertical_axis: int, r2_edges, cos_edges, nn_index, nn_ties, hist,
+                                   M, R, A=None, stream=None):
+        """As nearest_pair_stats, in the library's fixed scratch (no allocation, no synchronisation;
+        n <= 8192, nr + ntheta + 2 <= 384)."""
+        _require(xyz, nn_index, nn_ties, hist, M, R, *([A] if A is not None else []))
+        n = int(xyz.shape[0])
+        b = np.ascontiguousarray(box, dtype=np.float64)
+        r2 = np.ascontiguousarray(r2_edges, dtype=np.float64)
+        ce = np.ascontiguousarray(cos_edges, dtype=np.float64)
+        return self._check(load().vofmt_nearest_pair_stats_noalloc(
             self.h, n, _ptr(xyz), b.ctypes.data, int(vertical_axis), len(r2) - 1, len(ce) - 1, r2.ctypes.data,
             ce.ctypes.data, _ptr(nn_index), _ptr(nn_ties), _ptr(hist), _ptr(M), _ptr(R), _ptr(A), _stream(stream)))
 
