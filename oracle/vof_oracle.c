@@ -248,8 +248,8 @@ double orc_face_flux(const double *c, int64_t nx, int64_t ny, int64_t nz, int d,
   }
   double cd = c[di + nx * (dj + ny * dk)];
   double phi;
-  if (!(cd > 0.0 && cd < 1.0)) {
-    phi = cd; /* pure donor (including round-off excursions) */
+  if (!(cd > ORC_RESIDUE && cd < 1.0 - ORC_RESIDUE)) {
+    phi = cd; /* pure donor, round-off residues and excursions included */
   } else {
     double b[27], m[3];
     gather_block(c, nx, ny, nz, di, dj, dk, b);

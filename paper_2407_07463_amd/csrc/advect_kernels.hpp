@@ -9,7 +9,7 @@
 // A sweep is two passes.
 //
 // plic_body<D>: one wavefront per region of the list of mixed cells
-//   (0 < c < 1) of the sweep's input field. Each entry gathers its 3x3x3
+//   (values more than 1e-12 inside (0, 1)) of the sweep's input field. Each entry gathers its 3x3x3
 //   block, computes the MYC normal and the plane constant, and writes the flux
 //   of every face the cell donates through (its lower face if s < 0 there, its
 //   upper face if s > 0) into the face-flux array fmix[t][p] (the lower d-face
@@ -85,7 +85,7 @@ __device__ __forceinline__ void scan_body(const double *__restrict__ c, int64_t 
   const uint64_t below = (1ull << lane) - 1;
   for (int64_t base = w * rsize; base < (w + 1) * rsize && base < total; base += 64) {
     const int64_t q = base + lane;
-    const bool mixed = (q < total) && c[q] > 0.0 && c[q] < 1.0;
+    const bool mixed = (q < total) && plic::is_mixed(c[q]);
     const uint64_t mask = __ballot(mixed);
     if (mixed) out[n + __popcll(mask & below)] = (uint32_t)q;
     n += __popcll(mask);
@@ -249,7 +249,7 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
   // if s > 0, else the upper cell (value cu); a mixed donor's flux is in fmix
   auto flux = [&](int t, double sv, double cl, double cu, int64_t pu) -> double {
     const double cd = (sv > 0.0) ? cl : cu;
-    const bool mixed = (sv != 0.0) && cd > 0.0 && cd < 1.0;
+    const bool mixed = (sv != 0.0) && plic::is_mixed(cd);
     double fv = 0.0;
     if (mixed) fv = f_g[t * n3 + pu];
     return mixed ? fv : ((sv == 0.0) ? 0.0 : sv * cd);
@@ -274,8 +274,9 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
       ccv = ((ccw >> lane) & 1ull) ? 1.0 : 0.0;
     }
     const double cn = (cold - (f_hi - f_lo)) + ccv * (s_hi - s_lo);
-    if (live) o_g[t * n3 + pc] = cn;
-    const bool mixed = live && cn > 0.0 && cn < 1.0;
+    // streamed out (not read again by this pass): a non-temporal store
+    if (live) __builtin_nontemporal_store(cn, &o_g[t * n3 + pc]);
+    const bool mixed = live && plic::is_mixed(cn);
     const uint64_t mask = __ballot(mixed);
     if (mixed) reg[nlist + __popcll(mask & below)] = (uint32_t)((int64_t)(t0 + t) * n3 + pc);
     nlist += __popcll(mask);

@@ -179,6 +179,10 @@ constexpr double kResidue = 1e-12;
 __device__ __forceinline__ double clean_residue(double v) {
   return (v <= kResidue) ? 0.0 : ((v >= 1.0 - kResidue) ? 1.0 : v);
 }
+// An interface (mixed) cell of the advection: its value lies more than
+// kResidue inside (0, 1). Every other cell, round-off residues included,
+// donates like a pure cell (flux s * c).
+__device__ __forceinline__ bool is_mixed(double v) { return v > kResidue && v < 1.0 - kResidue; }
 __device__ __forceinline__ void myc_normal(const double *b_in, double &nx_, double &ny_, double &nz_) {
   double b[27];
 #pragma unroll

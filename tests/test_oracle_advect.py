@@ -186,3 +186,25 @@ def test_chain_is_not_sensitive_to_rounding():
     a = oracle.advect(start, *s, 0, 12)
     b = oracle.advect(pert, *s, 0, 12)
     assert np.abs(a - b).max() < 1e-13
+
+
+def test_residue_cells_donate_as_pure_cells():
+    """A cell within 1e-12 of 0 or 1 is not an interface cell: it donates s * c like a pure
+    cell. A lone residue c = 5e-13 among empty cells with s = 1/4 along x passes exactly c/4 to
+    its downwind neighbour (a plane cut with the isolated-cell normal (1, 0, 0) would keep the
+    phase at the cell's lower x-face and pass nothing); a cell 5e-13 short of full among full
+    cells passes s * c as well, and the column stays exactly conserved."""
+    for base, v in ((0.0, 5e-13), (1.0, 1.0 - 5e-13)):
+        c = np.full((1, 1, 8), base)
+        c[0, 0, 3] = v
+        s = np.full((1, 1, 8), 0.25)
+        out = oracle.sweep(c, s, 0)
+        assert out[0, 0, 4] == base + (0.25 * v - 0.25 * base)
+        assert out[0, 0, 3] == v - (0.25 * v - 0.25 * base)
+        assert out.sum() == c.sum()
+    # just above the residue level the cell is an interface cell: the plane cut keeps the
+    # phase at the lower x-face, so nothing reaches the downwind neighbour
+    c = np.zeros((1, 1, 8))
+    c[0, 0, 3] = 1e-9
+    out = oracle.sweep(c, np.full((1, 1, 8), 0.25), 0)
+    assert out[0, 0, 4] == 0.0 and out[0, 0, 3] == 1e-9
