@@ -78,27 +78,14 @@ const char *vofmt_version(void);
  * sx,sy,sz: [nz][ny][nx] FP64 face Courant numbers; the caller guarantees
  *           |s| <= 0.5 (checked only by vofmt_check_courant).
  * step0  : global index of the first step (>= 0); only g mod 3 matters.
- * Execution: consecutive sweeps run one at a time, or in pairs (one read
- *           and one write of c per two sweeps) after vofmt_set_advect_pairs;
- *           both forms give bit-identical results.
- * Scratch: the context keeps one extra copy of c, two arrays of per-face
- *           fluxes of mixed donors (one when pairing is off), three lists of
- *           up to one 32-bit entry per tracer-cell and two bits per
- *           tracer-cell.
+ * Scratch: the context keeps one extra copy of c, an array of per-face
+ *           fluxes of mixed donors, two lists of up to one 32-bit entry per
+ *           tracer-cell and one bit per tracer-cell.
  * Errors : VOFMT_E_ARG for null pointers or non-positive sizes, or when
  *           ntracers * nx * ny * nz reaches 2^32.
  */
 int vofmt_advect(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t ntracers, double *c, const double *sx,
                  const double *sy, const double *sz, int64_t step0, int32_t nsteps, hipStream_t stream);
-
-/*
- * Switch the pairing of consecutive sweeps in vofmt_advect on (on != 0) or
- * off (the default: every sweep as a PLIC pass and one streaming pass per
- * group of up to 4 tracers). The fields computed are bit-identical either way;
- * pairing moves fewer bytes, single sweeps need less scratch memory.
- * Errors: VOFMT_E_ARG for a null context.
- */
-int vofmt_set_advect_pairs(vofmt_ctx *ctx, int32_t on);
 
 /*
  * Largest |s| over the three face-Courant arrays, written to *smax_host

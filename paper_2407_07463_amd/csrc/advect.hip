@@ -1,10 +1,7 @@
 // Plain advection entry points: one box, one launch per pass.
-// The kernels are thin wrappers around the shared sweep bodies. Calls of
-// two or more sweeps run them in pairs (pair_kernels.hpp): four launches and
-// one read and one write of the fields per two sweeps; an odd last sweep,
-// and every sweep when pairing is switched off, runs as a single sweep (a
-// PLIC pass and one streaming pass per tracer group).
-#include "pair_kernels.hpp"
+// The kernels are thin wrappers around the shared sweep bodies: every sweep
+// is a PLIC pass over the mixed cells and one streaming pass per tracer group.
+#include "advect_kernels.hpp"
 
 using namespace advect;
 
@@ -49,45 +46,6 @@ __global__ __launch_bounds__(256) void k_stream_rows(const double *__restrict__ 
                                                      int64_t region0, int rsize) {
   stream_body<0, G, 0>(cin, cout, s, fmix, ccbits, write_cc, t0, nx, ny, nz, words, chunk, list_next, counts_next,
                        region0, rsize, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gridDim.y);
-}
-
-template <int A>
-__global__ __launch_bounds__(256) void k_scan_pair(const double *__restrict__ c, const double *__restrict__ sA,
-                                                   int64_t total, int nx, int ny, int nz, Divisors dv,
-                                                   uint32_t *__restrict__ listL, int *__restrict__ cntL,
-                                                   uint32_t *__restrict__ listC, int *__restrict__ cntC,
-                                                   int64_t nregions, int rsize) {
-  scan_pair_body<A>(c, sA, total, nx, ny, nz, dv, listL, cntL, listC, cntC, nregions, rsize,
-                    ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-}
-
-template <int A, int B>
-__global__ __launch_bounds__(256) void k_cand(const double *__restrict__ cin, const double *__restrict__ sA,
-                                              const double *__restrict__ sB, const double *__restrict__ fmA,
-                                              const uint64_t *__restrict__ bits, int cc_from_field,
-                                              const uint32_t *__restrict__ list, const int *__restrict__ counts,
-                                              int64_t nregions, int rsize, uint32_t *__restrict__ out,
-                                              int *__restrict__ out_counts, int nx, int ny, int nz, int words,
-                                              Divisors dv) {
-  cand_body<A, B>(cin, sA, sB, fmA, bits, cc_from_field, list, counts, nregions, rsize, out, out_counts, nx, ny, nz,
-                  words, dv, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-}
-
-template <int A, int B>
-__global__ __launch_bounds__(64) void k_plic_pair(const double *__restrict__ cin, const double *__restrict__ sA,
-                                                   const double *__restrict__ sB, const double *__restrict__ fmA,
-                                                   const uint64_t *__restrict__ bits, int cc_from_field,
-                                                   const uint32_t *__restrict__ list, const int *__restrict__ counts,
-                                                   int64_t nregions, int rsize, double *__restrict__ fmB, int nx,
-                                                   int ny, int nz, int words, Divisors dv) {
-  __shared__ double bl[kPlicPairSlice];  // one wavefront per workgroup: 13.5 KiB of LDS
-  plic_b_body<A, B>(cin, sA, sB, fmA, bits, cc_from_field, list, counts, nregions, rsize, fmB, nx, ny, nz, words, dv,
-                    bl, (int64_t)blockIdx.x);
-}
-
-template <int A, int B, int N>
-__global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_pair(PairArgs a) {
-  pair_body<A, B, N>(a, xcd_logical((int)blockIdx.x, (int)gridDim.x));
 }
 
 // Per-block maximum of |s| over the three arrays and a non-finite flag.
@@ -190,219 +148,6 @@ static int launch_sweep(vofmt_ctx *ctx, int d, const double *cin, double *cout, 
   return (int)hipGetLastError();
 }
 
-// ---------------------------------------------------------------- paired sweeps
-
-struct PairBuffers {
-  double *fmA, *fmB;  // face fluxes of the mixed donors of the first and second sweep
-  uint64_t *bits;     // two arrays of nbt words: c_c bits of even and odd steps
-  int64_t nbt;
-  uint32_t *L, *C, *E;  // mixed cells, candidates, kept candidates (region lists)
-  int *cL, *cC, *cE;
-  int64_t nL, nC;  // regions filled in L and C
-  int rsize;
-  int64_t nblocks;  // bricks of a paired pass
-};
-
-static const char *pair_kernel_name(int a, int b, int n) {
-  static char names[3][3][4][20];
-  static bool init = false;
-  if (!init) {
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j)
-        for (int k = 0; k < 4; ++k) snprintf(names[i][j][k], sizeof names[i][j][k], "k_pair<%d,%d,%d>", i, j, k);
-    init = true;
-  }
-  return names[a][b][n];
-}
-
-template <int A, int B, int N>
-static void launch_pair_brick(vofmt_ctx *ctx, const PairArgs &pa, int64_t nblocks, hipStream_t stream) {
-  const int rec = prof_begin(ctx, pair_kernel_name(A, B, N), stream);
-  hipLaunchKernelGGL((k_pair<A, B, N>), dim3((unsigned)nblocks), dim3(kPairThreads), 0, stream, pa);
-  prof_end(ctx, rec, stream);
-}
-
-// Sweeps i (axis A) and i+1 (axis B), phase = i mod 3, g = step of sweep i;
-// N = axis of sweep i+2 when another pair follows, else kNoAxis.
-template <int A, int B>
-static void launch_pair_ab(vofmt_ctx *ctx, int N, const double *cin, double *cout, const double *const s3[3],
-                           PairBuffers &pb, int phase, int64_t g, int nx, int ny, int nz, int ntr, int words,
-                           const Divisors &dv, hipStream_t stream) {
-  static const char *plic_names[3] = {"k_plic<0>", "k_plic<1>", "k_plic<2>"};
-  static const char *cand_names[3][3] = {{"", "k_cand<0,1>", "k_cand<0,2>"},
-                                         {"k_cand<1,0>", "", "k_cand<1,2>"},
-                                         {"k_cand<2,0>", "k_cand<2,1>", ""}};
-  static const char *plicp_names[3][3] = {{"", "k_plic_pair<0,1>", "k_plic_pair<0,2>"},
-                                          {"k_plic_pair<1,0>", "", "k_plic_pair<1,2>"},
-                                          {"k_plic_pair<2,0>", "k_plic_pair<2,1>", ""}};
-  const uint64_t *bits_rd = pb.bits + (g & 1) * pb.nbt;
-  uint64_t *bits_wr = pb.bits + (((phase == 0) ? g : g + 1) & 1) * pb.nbt;
-  const int ccf = (phase == 0);
-  int rec = prof_begin(ctx, plic_names[A], stream);
-  if (pb.nL > 0)
-    hipLaunchKernelGGL((k_plic<A>), dim3(ceil_div(pb.nL, 4)), dim3(256), 0, stream, cin, s3[A], pb.L, pb.cL, pb.nL,
-                       pb.rsize, pb.fmA, nx, ny, nz, dv);
-  prof_end(ctx, rec, stream);
-  rec = prof_begin(ctx, cand_names[A][B], stream);
-  if (pb.nC > 0)
-    hipLaunchKernelGGL((k_cand<A, B>), dim3(ceil_div(pb.nC, 4)), dim3(256), 0, stream, cin, s3[A], s3[B], pb.fmA,
-                       bits_rd, ccf, pb.C, pb.cC, pb.nC, pb.rsize, pb.E, pb.cE, nx, ny, nz, words, dv);
-  prof_end(ctx, rec, stream);
-  rec = prof_begin(ctx, plicp_names[A][B], stream);
-  if (pb.nC > 0)
-    hipLaunchKernelGGL((k_plic_pair<A, B>), dim3((unsigned)pb.nC), dim3(64), 0, stream, cin, s3[A], s3[B],
-                       pb.fmA, bits_rd, ccf, pb.E, pb.cE, pb.nC, pb.rsize, pb.fmB, nx, ny, nz, words, dv);
-  prof_end(ctx, rec, stream);
-  PairArgs pa;
-  pa.cin = cin;
-  pa.cout = cout;
-  pa.sA = s3[A];
-  pa.sB = s3[B];
-  pa.sN = (N < 3) ? s3[N] : nullptr;
-  pa.fmA = pb.fmA;
-  pa.fmB = pb.fmB;
-  pa.bits_rd = bits_rd;
-  pa.bits_wr = bits_wr;
-  pa.phase = phase;
-  pa.ntr = ntr;
-  pa.nx = nx;
-  pa.ny = ny;
-  pa.nz = nz;
-  pa.words = words;
-  pa.ntx = words;
-  pa.nty = (int)ceil_div(ny, kPairTY);
-  pa.nzc = (int)ceil_div(nz, kPairTZ);
-  pa.listL = pb.L;
-  pa.cntL = pb.cL;
-  pa.listC = pb.C;
-  pa.cntC = pb.cC;
-  pa.rsize = pb.rsize;
-  constexpr int T = 3 - A - B;  // the third axis
-  if (N == A) launch_pair_brick<A, B, A>(ctx, pa, pb.nblocks, stream);
-  else if (N == T) launch_pair_brick<A, B, T>(ctx, pa, pb.nblocks, stream);
-  else launch_pair_brick<A, B, kNoAxis>(ctx, pa, pb.nblocks, stream);
-  pb.nL = 4 * pb.nblocks;
-  if (N != kNoAxis) pb.nC = 4 * pb.nblocks;
-}
-
-static void launch_pair(vofmt_ctx *ctx, int A, int B, int N, const double *cin, double *cout,
-                        const double *const s3[3], PairBuffers &pb, int phase, int64_t g, int nx, int ny, int nz,
-                        int ntr, int words, const Divisors &dv, hipStream_t stream) {
-#define VOFMT_PAIR(a, b)                                                                                      \
-  if (A == a && B == b) {                                                                                     \
-    launch_pair_ab<a, b>(ctx, N, cin, cout, s3, pb, phase, g, nx, ny, nz, ntr, words, dv, stream);            \
-    return;                                                                                                   \
-  }
-  VOFMT_PAIR(0, 1)
-  VOFMT_PAIR(0, 2)
-  VOFMT_PAIR(1, 0)
-  VOFMT_PAIR(1, 2)
-  VOFMT_PAIR(2, 0)
-  VOFMT_PAIR(2, 1)
-#undef VOFMT_PAIR
-}
-
-static inline int sweep_axis(int64_t step0, int64_t i) { return (int)((step0 + i / 3 + i % 3) % 3); }
-
-static int advect_paired(vofmt_ctx *ctx, int nx, int ny, int nz, int ntr, double *c, const double *const s3[3],
-                         int64_t step0, int32_t nsteps, hipStream_t stream) {
-  const int64_t n3 = (int64_t)nx * ny * nz;
-  const int words = (int)ceil_div(nx, 64);
-  const int64_t total = (int64_t)ntr * n3;
-  const int rsize = region_size(kChunk);
-  static_assert(2 * 64 * kPairTZ <= 64 * kChunk * kMaxGroup, "paired list regions");
-  const int64_t nblocks = pair_blocks(nx, ny, nz, ntr);
-  if (4 * nblocks > INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "vofmt_advect: grid too large");
-  int64_t maxreg = max_regions(nx, ny, nz, ntr, kChunk, x_wpb((int)ceil_div(nx, 64), kChunk));
-  if (4 * nblocks > maxreg) maxreg = 4 * nblocks;
-  const int64_t scanreg = (total + rsize - 1) / rsize;
-  const size_t field_bytes = sizeof(double) * (size_t)total;
-  const int64_t nbt = (int64_t)ntr * nz * ny * words;
-  double *tmp = (double *)scratch(ctx, SLOT_PINGPONG, field_bytes);
-  double *fmA = (double *)scratch(ctx, SLOT_FMIX, field_bytes);
-  double *fmB = (double *)scratch(ctx, SLOT_FMIX2, field_bytes);
-  uint64_t *bits = (uint64_t *)scratch(ctx, SLOT_CCBITS, sizeof(uint64_t) * 2 * (size_t)nbt);
-  uint32_t *lists = (uint32_t *)scratch(ctx, SLOT_MIXLIST, sizeof(uint32_t) * 3 * (size_t)maxreg * rsize);
-  int *counts = (int *)scratch(ctx, SLOT_COUNTS, sizeof(int) * 3 * (size_t)maxreg);
-  if (!tmp || !fmA || !fmB || !bits || !lists || !counts) return VOFMT_E_NOMEM;
-  PairBuffers pb;
-  pb.fmA = fmA;
-  pb.fmB = fmB;
-  pb.bits = bits;
-  pb.nbt = nbt;
-  pb.L = lists;
-  pb.C = lists + (size_t)maxreg * rsize;
-  pb.E = lists + 2 * (size_t)maxreg * rsize;
-  pb.cL = counts;
-  pb.cC = counts + maxreg;
-  pb.cE = counts + 2 * maxreg;
-  pb.nL = scanreg;
-  pb.nC = scanreg;
-  pb.rsize = rsize;
-  pb.nblocks = nblocks;
-  Divisors dv;
-  dv.n3 = make_fastdiv((uint32_t)n3);
-  dv.nx = make_fastdiv((uint32_t)nx);
-  dv.ny = make_fastdiv((uint32_t)ny);
-  // mixed cells of the input and candidates of its first sweep
-  {
-    const int d0 = sweep_axis(step0, 0);
-    const int rec = prof_begin(ctx, "k_scan_pair", stream);
-    const dim3 grid(ceil_div(scanreg, 4)), block(256);
-    if (d0 == 0)
-      hipLaunchKernelGGL((k_scan_pair<0>), grid, block, 0, stream, c, s3[0], total, nx, ny, nz, dv, pb.L, pb.cL,
-                         pb.C, pb.cC, scanreg, rsize);
-    else if (d0 == 1)
-      hipLaunchKernelGGL((k_scan_pair<1>), grid, block, 0, stream, c, s3[1], total, nx, ny, nz, dv, pb.L, pb.cL,
-                         pb.C, pb.cC, scanreg, rsize);
-    else
-      hipLaunchKernelGGL((k_scan_pair<2>), grid, block, 0, stream, c, s3[2], total, nx, ny, nz, dv, pb.L, pb.cL,
-                         pb.C, pb.cC, scanreg, rsize);
-    prof_end(ctx, rec, stream);
-    VOFMT_HIP(ctx, hipGetLastError());
-  }
-  double *cur = c, *nxt = tmp;
-  const int64_t S = 3 * (int64_t)nsteps;
-  int64_t i = 0;
-  for (; i + 1 < S; i += 2) {
-    const int A = sweep_axis(step0, i), B = sweep_axis(step0, i + 1);
-    const int N = (i + 3 < S) ? sweep_axis(step0, i + 2) : kNoAxis;
-    launch_pair(ctx, A, B, N, cur, nxt, s3, pb, (int)(i % 3), step0 + i / 3, nx, ny, nz, ntr, words, dv, stream);
-    VOFMT_HIP(ctx, hipGetLastError());
-    double *t = cur;
-    cur = nxt;
-    nxt = t;
-  }
-  if (i < S) {  // odd number of sweeps: the last one alone (the third of its step)
-    const int64_t g = step0 + i / 3;
-    const int r = (int)(i % 3), d = sweep_axis(step0, i);
-    SweepBuffers sb;
-    sb.fmix = fmA;
-    sb.bits = bits + (g & 1) * nbt;
-    sb.list[0] = pb.L;
-    sb.list[1] = pb.C;
-    sb.counts[0] = pb.cL;
-    sb.counts[1] = pb.cC;
-    sb.nregions[0] = pb.nL;
-    sb.nregions[1] = 0;
-    sb.rsize = rsize;
-    int rc = launch_sweep(ctx, d, cur, nxt, s3[d], sb, r == 0, 0, nx, ny, nz, ntr, words, kChunk, stream);
-    if (rc) return hip_check(ctx, (hipError_t)rc, "sweep launch");
-    double *t = cur;
-    cur = nxt;
-    nxt = t;
-  }
-  if (cur != c)
-    VOFMT_HIP(ctx, hipMemcpyAsync(c, cur, sizeof(double) * (size_t)total, hipMemcpyDeviceToDevice, stream));
-  return VOFMT_OK;
-}
-
-extern "C" int vofmt_set_advect_pairs(vofmt_ctx *ctx, int32_t on) {
-  if (!ctx) return VOFMT_E_ARG;
-  ctx->advect_pairs = (on != 0);
-  return VOFMT_OK;
-}
-
 extern "C" int vofmt_advect(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t ntracers, double *c,
                             const double *sx, const double *sy, const double *sz, int64_t step0, int32_t nsteps,
                             hipStream_t stream) {
@@ -419,8 +164,6 @@ extern "C" int vofmt_advect(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, 
   if ((int64_t)ntracers * n3 >= ((int64_t)1 << 32))
     return set_err(ctx, VOFMT_E_ARG, "vofmt_advect: ntracers * cells must stay below 2^32");
   const double *s3[3] = {sx, sy, sz};
-  if (ctx->advect_pairs && 3 * (int64_t)nsteps >= 2)
-    return advect_paired(ctx, nx, ny, nz, ntracers, c, s3, step0, nsteps, stream);
   const int words = (int)ceil_div(nx, 64);
   const size_t field_bytes = sizeof(double) * (size_t)n3 * ntracers;
   double *tmp = (double *)scratch(ctx, SLOT_PINGPONG, field_bytes);

@@ -11,7 +11,7 @@
 
 #include "vofmt.h"
 
-enum { kNumSlotsDecl = 26 };
+enum { kNumSlotsDecl = 25 };
 
 // One timed launch: HIP events recorded before and after it on its stream.
 struct ProfRec {
@@ -39,8 +39,6 @@ struct vofmt_ctx {
   std::vector<ProfRec> prof;
   std::vector<hipEvent_t> prof_pool;
   size_t prof_used = 0;
-  // Advection runs consecutive sweeps in pairs unless switched off.
-  bool advect_pairs = false;
 };
 
 // Scratch slots (one buffer per role).
@@ -69,9 +67,8 @@ enum ScratchSlot {
   SLOT_CURV_COUNT = 21,  // its length and that of the fallback list
   SLOT_CURV_HF = 22,     // cells handed to the height-function fallback; recolouring: list predicate bits
   SLOT_RECOLOR_LIST = 23,  // recolouring: drop-boundary and shared cells
-  SLOT_FMIX2 = 24,         // paired sweeps: fluxes of the second sweep's mixed donors
-  SLOT_OCC = 25,           // recolouring, stencil mode: occupancy bits per 64-cell row segment
-  kNumSlots = 26,
+  SLOT_OCC = 24,           // recolouring, stencil mode: occupancy bits per 64-cell row segment
+  kNumSlots = 25,
 };
 static_assert(kNumSlots == kNumSlotsDecl, "scratch slot count");
 

@@ -25,7 +25,7 @@ import re
 from collections import defaultdict
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-ADVECT_SOURCES = ["csrc/advect_kernels.hpp", "csrc/pair_kernels.hpp", "csrc/plic.hpp", "csrc/advect.hip",
+ADVECT_SOURCES = ["csrc/advect_kernels.hpp", "csrc/plic.hpp", "csrc/advect.hip",
                   "csrc/common.hpp"]
 
 

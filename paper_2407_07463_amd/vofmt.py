@@ -43,7 +43,6 @@ _SIGNATURES = {
     "vofmt_version": (ctypes.c_char_p, []),
     "vofmt_advect": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _i64, _i32, _vp]),
     "vofmt_check_courant": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, ctypes.POINTER(_d), _vp]),
-    "vofmt_set_advect_pairs": (ctypes.c_int, [_vp, _i32]),
     "vofmt_label_drops": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _d, _vp, _vp, _vp]),
     "vofmt_drop_moments": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "vofmt_compact_tracers": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -74,7 +73,6 @@ _SIGNATURES = {
 }
 
 MLP_NPARAMS = 20868
-ADVECT_PAIRS_DEFAULT = False  # the library's setting for a new context (vofmt_set_advect_pairs)
 
 _lib = None
 
@@ -162,11 +160,6 @@ class Context:
             assert tuple(s.shape) == (nz, ny, nx)
         return self._check(load().vofmt_advect(self.h, nx, ny, nz, ntr, _ptr(c), _ptr(sx), _ptr(sy), _ptr(sz),
                                                int(step0), int(nsteps), _stream(stream)))
-
-    def set_advect_pairs(self, on: bool):
-        """Run consecutive sweeps of advect() in pairs or one at a time (both
-        give bit-identical fields; the library's default is ADVECT_PAIRS_DEFAULT)."""
-        return self._check(load().vofmt_set_advect_pairs(self.h, 1 if on else 0))
 
     def check_courant(self, sx, sy, sz, stream=None) -> float:
         _require(sx, sy, sz)

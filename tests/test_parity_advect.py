@@ -79,35 +79,6 @@ def test_odd_grids_random_velocity(ctx, shape, ntr, step0, nsteps):
     assert np.abs(g - o).max() <= TOL
 
 
-@pytest.mark.parametrize("shape,ntr,step0,nsteps", [((20, 24, 70), 3, 0, 3), ((9, 17, 130), 5, 1, 4),
-                                                    ((130, 10, 65), 2, 2, 5), ((1, 2, 3), 1, 0, 2),
-                                                    ((70, 9, 3), 4, 5, 1), ((64, 8, 64), 1, 4, 2)])
-def test_paired_sweeps_match_single_sweeps(ctx, shape, ntr, step0, nsteps):
-    """Sweeps run in pairs and one at a time give bit-identical
-    fields: partial and several tiles along x and y, several z-chunks, grids
-    thinner than the halos, every phase of a pair within the step cycle, odd
-    and even sweep counts."""
-    nz, ny, nx = shape
-    rng = synth.Splitmix64(4321 + nx + 7 * ny + 13 * nz)
-    v = rng.uniform(ntr * nx * ny * nz).reshape((ntr,) + shape)
-    c = np.where(v < 0.3, 0.0, np.where(v > 0.7, 1.0, (v - 0.3) / 0.4))  # empty, full and mixed cells
-    s = [(rng.uniform(nx * ny * nz).reshape(shape) - 0.5) * 0.9 for _ in range(3)]  # |s| < 0.45
-    from paper_2407_07463_amd import vofmt
-
-    note(f"advect pairs vs single sweeps {shape} ntr={ntr} step0={step0} nsteps={nsteps}")
-    try:
-        ctx.set_advect_pairs(True)
-        g_pair = _gpu_advect(ctx, c, *s, step0, nsteps)
-        ctx.set_advect_pairs(False)
-        g_single = _gpu_advect(ctx, c, *s, step0, nsteps)
-    finally:
-        ctx.set_advect_pairs(vofmt.ADVECT_PAIRS_DEFAULT)
-    assert np.array_equal(g_pair, g_single), float(np.abs(g_pair - g_single).max())
-    if nx * ny * nz <= 30000:
-        o = oracle.advect(c, *s, step0, nsteps)
-        assert np.abs(g_pair - o).max() <= TOL
-
-
 @pytest.mark.parametrize("shape,ntr,step0", [((2, 3, 2048), 2, 0), ((3, 2, 2049), 1, 1), ((2, 4, 2113), 2, 2)])
 def test_long_rows(ctx, shape, ntr, step0):
     """Rows of 32 segments (the whole-row x-sweep, one position per
