@@ -70,8 +70,10 @@ const char *vofmt_version(void);
  *   c'[p] = (c[p] - (F[p+e_d] - F[p])) + cc[p] * (s_d[p+e_d] - s_d[p]),
  * where cc[p] = (c[p] > 0.5) at the start of the step and F is s times the
  * phase volume fraction of the donor's upwind sub-box of width |s|: the donor
- * value itself when the donor is not mixed (mixed: 0 < c < 1), otherwise the
- * volume under the donor's PLIC plane (Mixed-Youngs-Centred normal, plane
+ * value itself when the donor is not mixed (mixed: more than 1e-12 inside
+ * (0, 1); round-off residues of pure cells donate like pure cells), otherwise
+ * the volume under the donor's PLIC plane (Mixed-Youngs-Centred normal from
+ * the block with values within 1e-12 of 0 or 1 taken as 0 or 1, plane
  * constant matching the donor's c).
  *
  * c      : [ntracers][nz][ny][nx] FP64, in/out.
@@ -286,8 +288,8 @@ int vofmt_pair_pdfs(vofmt_ctx *ctx, int32_t nr, int32_t ntheta, const double *r_
 /*
  * Height-function curvature of one tracer field (the paper computes kappa_i
  * of every tracer "as for a single tracer", section "The no-coalescence.h
- * algorithm"; method: fixed 7-cell height columns). For each mixed cell
- * (0 < c < 1) the Mixed-Youngs-Centred normal orders the column axes by
+ * algorithm"; method: fixed 7-cell height columns). For each interface cell
+ * (c more than 1e-12 inside (0, 1)) the Mixed-Youngs-Centred normal orders the column axes by
  * decreasing |m_d|; the first axis whose 3x3 columns all run from a full cell
  * (c >= 1-1e-6, on the phase side) to an empty one (c <= 1e-6) gives the
  * column sums H(u,v) over offsets -3..3 and
@@ -375,7 +377,8 @@ int vofmt_mlp_train_step(vofmt_ctx *ctx, float *params, float *adam_m, float *ad
                          float *loss_host, hipStream_t stream);
 
 /*
- * Canonical stencils of the mixed cells (0 < c < 1) of one field, in
+ * Canonical stencils of the interface cells (c more than 1e-12 inside (0, 1))
+ * of one field, in
  * increasing linear cell order. Canonicalisation over the 48 symmetries of
  * the cube: reflect the axes along which the Mixed-Youngs-Centred normal is
  * negative, order the axes by increasing |m_d| (ties: lower axis first), and
@@ -392,7 +395,8 @@ int vofmt_mlp_stencils(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, const
 
 /*
  * Curvature of one tracer by the network with height functions as the
- * fallback: for every mixed cell kappa = sign * MLP(canonical stencil); where
+ * fallback: for every interface cell (c more than 1e-12 inside (0, 1))
+ * kappa = sign * MLP(canonical stencil); where
  * |kappa| < kappa_lo (radii the 3x3x3 stencil cannot resolve) the height
  * function is evaluated and replaces it when valid. status: 0 not a mixed
  * cell (kappa NaN); 8 the network's value; 1..3 the height function's value

@@ -46,6 +46,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Sets the number of threads of the OpenMP loops (timing of the baseline). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 #define ORC_OK 0
 #define ORC_E_ARG -1
 #define ORC_E_CAPACITY -3
@@ -957,8 +966,9 @@ int orc_pair_pdfs(int32_t nr, int32_t nth, const double *r_edges, const double *
 /* =========================================================================
  * Height-function curvature of one tracer (the paper computes kappa_i of
  * each tracer "as for a single tracer", citing Popinet 2018). Reading:
- * fixed 7-cell columns (Cummins, Francois & Kothe 2005). For a mixed cell
- * (0 < c < 1) take the MYC normal m; try the column axes in order of
+ * fixed 7-cell columns (Cummins, Francois & Kothe 2005). For an interface
+ * cell (c more than ORC_RESIDUE inside (0, 1): round-off residues of pure
+ * cells are not interface cells) take the MYC normal m; try the column axes in order of
  * decreasing |m_d| (ties: lower axis first); an axis is valid when every one
  * of the 3x3 columns has its end on the phase side (-sign(m_d), sign(0)=+1)
  * full (c >= 1-1e-6) and its other end empty (c <= 1e-6). Heights are the
@@ -977,7 +987,7 @@ int orc_curvature_hf(int64_t nx, int64_t ny, int64_t nz, const double *c, double
     double cp = c[p];
     kappa[p] = NAN;
     status[p] = 0;
-    if (!(cp > 0.0 && cp < 1.0)) continue;
+    if (!(cp > ORC_RESIDUE && cp < 1.0 - ORC_RESIDUE)) continue; /* interface cells only */
     int64_t x[3] = {p % nx, (p / nx) % ny, p / (nx * ny)};
     double b[27], m[3];
     gather_block(c, nx, ny, nz, x[0], x[1], x[2], b);

@@ -1,6 +1,7 @@
-// Lists of the mixed cells (0 < c < 1) of one field in increasing cell order:
+// Lists of the interface (mixed) cells of one field in increasing cell order:
 // block counts, a tiled scan, then a second pass that writes the list. No
-// atomics, so the order is fixed.
+// atomics, so the order is fixed. A cell is an interface cell when its value
+// lies more than 1e-12 inside (0, 1); round-off residues of pure cells are not.
 #pragma once
 
 #include "common.hpp"
@@ -11,7 +12,8 @@ namespace {  // each translation unit gets its own kernels
 constexpr int kBlock = 256;
 constexpr int kTile = 1024;  // entries per scan tile
 
-__device__ __forceinline__ bool is_mixed(double v) { return v > 0.0 && v < 1.0; }
+constexpr double kResidue = 1e-12;
+__device__ __forceinline__ bool is_mixed(double v) { return v > kResidue && v < 1.0 - kResidue; }
 
 // Mixed cells per block of kBlock cells.
 __global__ __launch_bounds__(kBlock) void k_block_counts(const double *__restrict__ c, int64_t n3,

@@ -3,7 +3,8 @@
 // The paper computes the curvature kappa_i of each tracer "as for a single
 // tracer" (section "The no-coalescence.h algorithm", citing Popinet's review
 // of surface-tension methods). Reading: fixed 7-cell height columns
-// (Cummins, Francois & Kothe 2005). For every mixed cell (0 < c < 1): the MYC
+// (Cummins, Francois & Kothe 2005). For every interface cell (c more than
+// 1e-12 inside (0, 1); round-off residues of pure cells are not): the MYC
 // normal m orders the candidate column axes by decreasing |m_d| (ties to the
 // lower axis); an axis is usable when each of the 3x3 columns has its end on
 // the phase side (-sign(m_d), sign(0) = +1) full (c >= 1 - 1e-6) and its

@@ -91,7 +91,7 @@ def body_samples(ctx, axes, rot, rng, cap=None, dev="cuda:0"):
     Q = synth.ellipsoid_matrix(axes, rot)
     c = synth.fill_ellipsoids((L, L, L), 1, ctr[None], Q[None], [0])[0]
     cd = torch.from_numpy(c).to(dev)
-    nmix = int(((cd > 0) & (cd < 1)).sum().item())
+    nmix = int(((cd > 1e-12) & (cd < 1 - 1e-12)).sum().item())  # interface cells
     xs = torch.zeros((max(nmix, 1), 27), dtype=torch.float32, device=dev)
     cell = torch.zeros(max(nmix, 1), dtype=torch.int32, device=dev)
     sg = torch.zeros(max(nmix, 1), dtype=torch.int8, device=dev)

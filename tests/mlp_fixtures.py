@@ -43,8 +43,9 @@ def block_at(c, k, j, i):
 
 
 def canonical_inputs(c):
-    """Oracle canonical stencils of every mixed cell of c, in linear cell order."""
-    mixed = np.flatnonzero((c > 0.0) & (c < 1.0))
+    """Oracle canonical stencils of every interface cell of c (more than 1e-12 inside (0, 1)), in
+    linear cell order."""
+    mixed = np.flatnonzero((c > 1e-12) & (c < 1.0 - 1e-12))
     nz, ny, nx = c.shape
     xs = np.zeros((len(mixed), 27), dtype=np.float32)
     sg = np.zeros(len(mixed), dtype=np.int8)
