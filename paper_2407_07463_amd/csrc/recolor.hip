@@ -200,8 +200,14 @@ __global__ __launch_bounds__(kBlock) void k_occ_words(const int32_t *__restrict_
 }
 
 // Bits of cells xs, xs+1, ..., xs+63 (periodic in x, xs any integer) of one
-// row of occupancy words.
+// row of occupancy words. Windows inside the row take two aligned words; the
+// rest (the row's ends, rows shorter than 64 cells) assemble the bits piece by
+// piece.
 __device__ __forceinline__ uint64_t row_window(const uint64_t *__restrict__ rw, int nx, int xs) {
+  if (xs >= 0 && xs + 64 <= nx) {
+    const int w = xs >> 6, b = xs & 63;
+    return b == 0 ? rw[w] : ((rw[w] >> b) | (rw[w + 1] << (64 - b)));
+  }
   int x = wrap_any(xs, nx);
   uint64_t res = 0;
   int got = 0;
@@ -220,14 +226,38 @@ __device__ __forceinline__ uint64_t row_window(const uint64_t *__restrict__ rw, 
   return res;
 }
 
+// One of each opposite pair of offsets o of the 5x5x5 stencil (o > 0 in
+// (z, y, x) order): 62 pairs, as (ox, oy, oz) in -2..2.
+struct StencilPairs {
+  int8_t o[62][3];
+};
+static StencilPairs make_stencil_pairs() {
+  StencilPairs sp{};
+  int k = 0;
+  for (int oz = -2; oz <= 2; ++oz)
+    for (int oy = -2; oy <= 2; ++oy)
+      for (int ox = -2; ox <= 2; ++ox)
+        if (oz > 0 || (oz == 0 && (oy > 0 || (oy == 0 && ox > 0)))) {
+          sp.o[k][0] = (int8_t)ox;
+          sp.o[k][1] = (int8_t)oy;
+          sp.o[k][2] = (int8_t)oz;
+          ++k;
+        }
+  return sp;
+}
+
 // Steps 1-3 read literally, one wavefront per row segment (t, z, y, w), one
 // lane per centre cell: the centre is empty and the cells at +o and -o of the
-// 5x5x5 stencil are both occupied (tested on the occupancy bits of the 25
-// rows y-2..y+2, z-2..z+2); where they are, their labels are loaded and, if
-// they differ, the two drops are marked neighbours in both directions.
+// 5x5x5 stencil are both occupied. Lanes 0..49 first build the 64-bit
+// occupancy windows of the 25 rows y-2..y+2, z-2..z+2 (cells x0-2 .. x0+61
+// and x0+62 .. x0+125), which every lane then reads; each lane forms the
+// 5-bit neighbourhood of its cell in every row, and from them a mask of the
+// opposite pairs with both cells occupied. Only for those pairs are the two
+// labels loaded; if they differ, the two drops are marked neighbours in both
+// directions.
 __global__ __launch_bounds__(kBlock) void k_stencil_edges(const int32_t *__restrict__ lab,
                                                           const uint64_t *__restrict__ occ, int nx, int ny, int nz,
-                                                          int ntr, int words, TracerOffsets to,
+                                                          int ntr, int words, TracerOffsets to, StencilPairs sp,
                                                           uint32_t *__restrict__ adj, int64_t awords) {
   const int64_t seg = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
@@ -240,47 +270,52 @@ __global__ __launch_bounds__(kBlock) void k_stencil_edges(const int32_t *__restr
   const int z = (int)(r / ny), y = (int)(r - (int64_t)z * ny);
   const uint64_t *occ_t = occ + (int64_t)t * rows * words;
   const int x0 = 64 * w;
+  // offsets reach 2 cells: one conditional wrap when the axis has 3 cells or more
+  auto wrap2 = [](int v, int n) { return n >= 3 ? (v < 0 ? v + n : (v >= n ? v - n : v)) : wrap_any(v, n); };
+  // lane L < 50 builds window L & 1 of row L >> 1 (row = 5 (dy + 2) + (dz + 2))
+  uint64_t mine = 0;
+  if (lane < 50) {
+    const int row = lane >> 1, dy = row / 5 - 2, dz = row % 5 - 2;
+    const uint64_t *rw = occ_t + ((int64_t)wrap2(z + dz, nz) * ny + wrap2(y + dy, ny)) * words;
+    mine = row_window(rw, nx, (lane & 1) ? x0 + 62 : x0 - 2);
+  }
+  if (__ballot(mine != 0ull) == 0ull) return;  // no occupied cell near the segment
   const int x = x0 + lane;
-  // 5-bit neighbourhoods of each lane: bit k of nb[5 (dy+2) + (dz+2)] is the
-  // occupancy of cell (x - 2 + k, y + dy, z + dz)
+  // bit k of nb[row] is the occupancy of cell (x - 2 + k) in that row
   uint32_t nb[25];
-  uint64_t any = 0;
 #pragma unroll
-  for (int dy = -2; dy <= 2; ++dy)
+  for (int row = 0; row < 25; ++row) {
+    const uint32_t alo = __builtin_amdgcn_readlane((uint32_t)mine, 2 * row);
+    const uint32_t ahi = __builtin_amdgcn_readlane((uint32_t)(mine >> 32), 2 * row);
+    const uint32_t blo = __builtin_amdgcn_readlane((uint32_t)mine, 2 * row + 1);
+    const uint32_t bhi = __builtin_amdgcn_readlane((uint32_t)(mine >> 32), 2 * row + 1);
+    const uint64_t wa = ((uint64_t)ahi << 32) | alo, wb = ((uint64_t)bhi << 32) | blo;
+    const uint64_t v = (lane == 0) ? wa : ((wa >> lane) | (wb << (64 - lane)));
+    nb[row] = (uint32_t)(v & 31ull);
+  }
+  if (x >= nx || ((nb[12] >> 2) & 1u)) return;  // no cell, or the centre is occupied
+  // pairs with both cells occupied
+  uint64_t mask = 0;
 #pragma unroll
-    for (int dz = -2; dz <= 2; ++dz) {
-      const int yy = wrap_any(y + dy, ny), zz = wrap_any(z + dz, nz);
-      const uint64_t *rw = occ_t + ((int64_t)zz * ny + yy) * words;
-      const uint64_t wa = row_window(rw, nx, x0 - 2), wb = row_window(rw, nx, x0 + 62);
-      any |= wa | wb;
-      const uint64_t v = (lane == 0) ? wa : ((wa >> lane) | (wb << (64 - lane)));
-      nb[5 * (dy + 2) + (dz + 2)] = (uint32_t)(v & 31ull);
+  for (int k = 0; k < 62; ++k) {
+    const int ox = sp.o[k][0], oy = sp.o[k][1], oz = sp.o[k][2];
+    const uint32_t plus = nb[5 * (oy + 2) + (oz + 2)] >> (ox + 2);
+    const uint32_t minus = nb[5 * (2 - oy) + (2 - oz)] >> (2 - ox);
+    mask |= (uint64_t)(plus & minus & 1u) << k;
+  }
+  while (mask) {
+    const int k = __ffsll((unsigned long long)mask) - 1;
+    mask &= mask - 1;
+    const int ox = sp.o[k][0], oy = sp.o[k][1], oz = sp.o[k][2];
+    const int64_t qp = (((int64_t)t * nz + wrap2(z + oz, nz)) * ny + wrap2(y + oy, ny)) * nx + wrap2(x + ox, nx);
+    const int64_t qm = (((int64_t)t * nz + wrap2(z - oz, nz)) * ny + wrap2(y - oy, ny)) * nx + wrap2(x - ox, nx);
+    const int32_t la = lab[qp], lb = lab[qm];
+    if (la != lb && la > 0 && lb > 0 && to.off[t] + la <= to.off[t + 1] && to.off[t] + lb <= to.off[t + 1]) {
+      const int32_t ga = to.off[t] + la - 1, gb = to.off[t] + lb - 1;
+      set_edge(adj, awords, ga, gb);
+      set_edge(adj, awords, gb, ga);
     }
-  if (any == 0ull) return;  // no occupied cell near the segment (uniform)
-  const bool centre_empty = x < nx && !((nb[12] >> 2) & 1u);
-  if (!centre_empty) return;
-#pragma unroll
-  for (int oz = -2; oz <= 2; ++oz)
-#pragma unroll
-    for (int oy = -2; oy <= 2; ++oy)
-#pragma unroll
-      for (int ox = -2; ox <= 2; ++ox) {
-        // one of each opposite pair: o > 0 in (z, y, x) order
-        if (!(oz > 0 || (oz == 0 && (oy > 0 || (oy == 0 && ox > 0))))) continue;
-        const bool plus = (nb[5 * (oy + 2) + (oz + 2)] >> (ox + 2)) & 1u;
-        const bool minus = (nb[5 * (2 - oy) + (2 - oz)] >> (2 - ox)) & 1u;
-        if (!(plus && minus)) continue;
-        const int64_t qp = (((int64_t)t * nz + wrap_any(z + oz, nz)) * ny + wrap_any(y + oy, ny)) * nx +
-                           wrap_any(x + ox, nx);
-        const int64_t qm = (((int64_t)t * nz + wrap_any(z - oz, nz)) * ny + wrap_any(y - oy, ny)) * nx +
-                           wrap_any(x - ox, nx);
-        const int32_t la = lab[qp], lb = lab[qm];
-        if (la != lb && la > 0 && lb > 0 && to.off[t] + la <= to.off[t + 1] && to.off[t] + lb <= to.off[t + 1]) {
-          const int32_t ga = to.off[t] + la - 1, gb = to.off[t] + lb - 1;
-          set_edge(adj, awords, ga, gb);
-          set_edge(adj, awords, gb, ga);
-        }
-      }
+  }
 }
 
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
@@ -690,7 +725,7 @@ static int recolor_impl(vofmt_ctx *ctx, const char *fn, int stencil, int32_t nx,
     hipLaunchKernelGGL(k_occ_words, dim3((unsigned)nblk), dim3(kBlock), 0, stream, labels, nx, (int64_t)ntr * rows,
                        xw, occ);
     hipLaunchKernelGGL(k_stencil_edges, dim3((unsigned)nblk), dim3(kBlock), 0, stream, labels, occ, nx, ny, nz, ntr,
-                       xw, to, adj, words);
+                       xw, to, make_stencil_pairs(), adj, words);
   }
   {
     // the cells that can see a pair, in order, then the pairs they see
