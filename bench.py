@@ -8,30 +8,45 @@ solenoidal velocity (modes 1 <= |k| <= 8, E(k) ~ k^-5/3, rms 0.2 cells per
 step, rise 0.1). All inputs are synthetic and seeded.
 
 A step is one direction-split advection step of all tracers (three sweeps,
-each a PLIC pass over the mixed cells and streaming passes over the fields;
---sweeps paired runs two sweeps per streaming pass instead). `value` is the
-whole-job advection throughput in tracer-cell-steps per second with the
-fields resident in HBM, timed with HIP events on the stream the kernels run
-on. `roofline` is that of the dominant kernel, the streaming pass (k_stream;
-k_pair when paired), from its own launches timed with HIP events in a second
-timed region of the same K steps; `traffic` comes from the committed
-rocprofv3 counter summary when the advection sources have not changed since.
+each a PLIC pass over the mixed cells and streaming passes over the fields).
+After the warmup, K steps are timed `--runs` times with HIP events on the
+stream the kernels run on, each run bracketed by device synchronisations;
+`ms_per_step` and `value` come from the median run. `value` is the metric's
+per-tracer rate: cell updates per second of one tracer field while all 8 are
+advanced (n^3 * steps / t); the all-tracer rate is reported beside it.
+
+`roofline` is that of the dominant kernel, the streaming pass (k_stream; the
+x-sweep as k_stream_rows), from its launches timed with HIP events in a
+further run of K steps: `achieved` = the method's bytes of one launch (17.17
+B per tracer-cell-sweep at 8 tracers: read and write c, the face velocity
+shared by the 8 tracers, 1/6 B of c > 0.5 bits) times the tracer-cells of the
+launch, divided by its mean duration. `traffic` is the launch's HBM bytes
+from the committed rocprofv3 counter summary when the advection sources have
+not changed since. The end-to-end step against the same model (51.5 B per
+tracer-cell-step) is `step_model_frac`.
 
 The same line carries, under `rows`, the other steps of the path measured on
-the advected field: drop labelling, moments, recolouring, pair statistics,
-height-function and learned curvature (cells/s, matrix-core rate), network
-training, and batched advection of 32 uneven boxes (graph launch vs plain
-launches); and under `cpu_baseline` the CPU oracle timed on a bounded sample.
+the advected field (labelling, moments, shapes, recolouring in both
+near-contact modes, pair statistics with M, R, A and the densities, height-
+function and learned curvature of every tracer with their agreement, the
+surface-tension force, network training, the tracer count N(t) over the
+256^3 workload and batched advection of 32 uneven boxes), and under
+`cpu_baseline` the CPU oracle timed on a bounded sample, multi- and
+single-threaded.
 
---pmc-pass: a short run for rocprofv3 counter collection: a plain copy of
-1 GiB (the calibration kernel), 2 advection steps, then two surface-tension
-force evaluations of the advected tracers; prints one line.
+--pmc-pass advect: a short run for the traffic counters (a plain copy of
+1 GiB, the calibration kernel; 2 advection steps; two surface-tension force
+evaluations). --pmc-pass mlp: the network kernels a few times each (forward
+on given stencils, fused curvature, training steps). Each prints one line.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
+import platform
+import statistics
 import sys
 import time
 
@@ -41,32 +56,16 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, GB/s
 BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix cores
 METRIC = "VoF cell-updates/s per tracer (FP64) at % HBM roofline; learned vs HF curvature cells/s"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_k_pair_drops512.txt")
-TRAFFIC_FILE_SINGLE = os.path.join(ROOT, "profiles", "hbm_traffic_k_stream_drops512.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_k_stream_drops512.txt")
+MFMA_FILE = os.path.join(ROOT, "profiles", "mfma_mlp_kernels_drops512.txt")
 COPY_BYTES = 1 << 30
 
 
-def stream_bytes(n3: int, g: int) -> float:
-    """Algorithmic HBM bytes of one streaming pass over g tracers: read and
-    write every field value (16 B per tracer-cell), read the face velocity
-    (8 B per cell) and one c > 0.5 bit per tracer-cell."""
-    return n3 * (16.0 * g + 8.0 + g / 8.0)
-
-
-def pair_bytes(n3: int, ntr: int, candidates: bool) -> float:
-    """Algorithmic HBM bytes of one paired streaming pass over all tracers:
-    read and write every field value once (16 B per tracer-cell), read the
-    face velocities of both sweeps (8 B per cell each) and, when it lists the
-    candidates of the following sweep, that sweep's face velocity; one c > 0.5
-    bit per tracer-cell."""
-    return n3 * (16.0 * ntr + 8.0 * (3 if candidates else 2) + ntr / 8.0)
-
-
-def step_model_bytes(n3: int, ntr: int) -> float:
-    """Per-step model of the method: three sweeps, each reading and writing
-    every field once, reading the velocity once for all tracers and the
-    c > 0.5 bits (51.5 B per tracer-cell-step at 8 tracers)."""
-    return 3.0 * (n3 * ntr * 16.0 + n3 * 8.0 + n3 * ntr / 8.0)
+def sweep_model_bytes(ntr: int) -> float:
+    """The method's HBM bytes per tracer-cell-sweep: read and write c (16 B),
+    the face velocity shared by the ntr tracers (8/ntr B), 1/6 B of c > 0.5
+    bits (17.17 B at 8 tracers)."""
+    return 16.0 + 8.0 / ntr + 1.0 / 6.0
 
 
 def log(msg):
@@ -84,9 +83,51 @@ def timed(torch, stream, fn):
     return a.elapsed_time(b), r
 
 
+def cpu_info():
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return dict(cpu_model=model, nproc=avail, cpu_count=os.cpu_count())
+
+
+def read_mfma_summary(path=MFMA_FILE):
+    """{kernel: {MfmaUtil, MfmaFlopsBF16, ...}} from the committed counter summary, or {}."""
+    out = {}
+    if not os.path.exists(path):
+        return out
+    with open(path) as f:
+        for line in f:
+            if not line.startswith("kernel = "):
+                continue
+            parts = [p.strip() for p in line.split("|")]
+            name = parts[0][len("kernel = "):]
+            vals = {}
+            for p in parts[1:]:
+                if " = " in p:
+                    k, v = p.split(" = ", 1)
+                    try:
+                        vals[k] = float(v)
+                    except ValueError:
+                        vals[k] = v
+            out[name] = vals
+    return out
+
+
+# ------------------------------------------------------------------ rows
+
 def rows_bench(torch, np, ctx, stream, c, w, n, ntr):
     """Timings of the other steps of the path on the advected field."""
-    from paper_2407_07463_amd import synth, training
+    from paper_2407_07463_amd import training
 
     dev = c.device
     rows = {}
@@ -96,7 +137,9 @@ def rows_bench(torch, np, ctx, stream, c, w, n, ntr):
     ctx.label_drops(c, lab)  # warm
     ms, nd = timed(torch, stream, lambda: ctx.label_drops(c, lab))
     D = int(nd.sum())
-    rows["label_drops"] = dict(ms=ms, drops=D, cells_per_s=n3 * ntr / (ms / 1e3))
+    lab_bytes = n3 * ntr * (8.0 + 4.0)  # read c, write the label
+    rows["label_drops"] = dict(ms=ms, drops=D, cells_per_s=n3 * ntr / (ms / 1e3),
+                               hbm_frac=lab_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS)
     log(f"label_drops: {ms:.2f} ms, {D} drops")
     vol = torch.zeros(D, dtype=torch.float64, device=dev)
     xyz = torch.zeros((D, 3), dtype=torch.float64, device=dev)
@@ -115,41 +158,66 @@ def rows_bench(torch, np, ctx, stream, c, w, n, ntr):
                                chi_max=float(chi.max().item()))
     log(f"drop_shapes: {ms:.2f} ms, mean aspect ratio {rows['drop_shapes']['chi_mean']:.4f}")
     del sv, inertia, chi, velo
-    # ---- recolouring (on a copy with room for 2N tracers)
+    # ---- recolouring in both near-contact modes (each on a fresh copy with room for 2N tracers);
+    # one untimed call first (it sizes the scratch buffers), then the timed call
     cap = 2 * ntr
     cr = torch.zeros((cap,) + tuple(c.shape[1:]), dtype=torch.float64, device=dev)
     newt = torch.zeros(max(D, 1), dtype=torch.int32, device=dev)
-    # one untimed call first (it sizes the scratch buffers), then the timed
-    # call on a fresh copy of the same fields
-    for _ in range(2):
-        cr.zero_()
-        cr[:ntr].copy_(c)
-        ms, (ntr2, moved) = timed(torch, stream, lambda: ctx.recolor_tracers(cr, ntr, lab, nd, 1.5, newt))
-    rows["recolor_tracers"] = dict(ms=ms, tracers_after=ntr2, drops_moved=moved, gap_cells=1.5)
-    log(f"recolor_tracers: {ms:.2f} ms, {moved} drops moved, {ntr2} tracers")
+    for mode in ("tau", "stencil"):
+        for _ in range(2):
+            cr.zero_()
+            cr[:ntr].copy_(c)
+            if mode == "tau":
+                ms, (ntr2, moved) = timed(torch, stream, lambda: ctx.recolor_tracers(cr, ntr, lab, nd, 1.5, newt))
+            else:
+                ms, (ntr2, moved) = timed(torch, stream, lambda: ctx.recolor_tracers_stencil(cr, ntr, lab, nd, newt))
+        key = "recolor_tracers" if mode == "tau" else "recolor_tracers_stencil"
+        rows[key] = dict(ms=ms, tracers_after=ntr2, drops_moved=moved,
+                         criterion="distance gap 1.5 cells" if mode == "tau" else "5x5x5 stencil, Steps 1-3")
+        log(f"{key}: {ms:.2f} ms, {moved} drops moved, {ntr2} tracers")
     del cr, newt
-    # ---- nearest-particle pair statistics, 64 x 32 histogram
+    # ---- nearest-particle pair statistics: 64 x 32 histogram over r < 4 d, M, R, A, densities
     nr, nth = 64, 32
-    r2e = (np.arange(nr + 1) * (4 * 24.0 / nr)) ** 2
-    ce = np.linspace(1.0, -1.0, nth + 1)
+    r_edges = np.arange(nr + 1) * (4 * 24.0 / nr)
+    th_edges = np.arange(nth + 1) * (math.pi / nth)
+    r2e, ce = r_edges ** 2, np.cos(th_edges)
     idx = torch.zeros(D, dtype=torch.int32, device=dev)
     ties = torch.zeros(D, dtype=torch.int32, device=dev)
     hist = torch.zeros(nr * nth + 1, dtype=torch.int64, device=dev)
     M = torch.zeros(3, dtype=torch.float64, device=dev)
     R = torch.zeros(9, dtype=torch.float64, device=dev)
+    A = torch.zeros(9, dtype=torch.float64, device=dev)
     box = [float(n)] * 3
-    ctx.nearest_pair_stats(xyz, box, 2, r2e, ce, idx, ties, hist, M, R)
-    ms, _ = timed(torch, stream, lambda: ctx.nearest_pair_stats(xyz, box, 2, r2e, ce, idx, ties, hist, M, R))
-    rows["nearest_pair_stats"] = dict(ms=ms, drops=D, histogram=[nr, nth])
-    log(f"nearest_pair_stats: {ms:.2f} ms")
+    ctx.nearest_pair_stats(xyz, box, 2, r2e, ce, idx, ties, hist, M, R, A)
+    ms, _ = timed(torch, stream, lambda: ctx.nearest_pair_stats(xyz, box, 2, r2e, ce, idx, ties, hist, M, R, A))
+    P = torch.zeros(nr * nth, dtype=torch.float64, device=dev)
+    Pr = torch.zeros(nr, dtype=torch.float64, device=dev)
+    ms_pdf, _ = timed(torch, stream, lambda: ctx.pair_pdfs(r_edges, th_edges, hist, D, P, Pr))
+    ms_na = None
+    if D <= 8192:
+        ctx.nearest_pair_stats_noalloc(xyz, box, 2, r2e, ce, idx, ties, hist, M, R, A)
+        ms_na, _ = timed(torch, stream,
+                         lambda: ctx.nearest_pair_stats_noalloc(xyz, box, 2, r2e, ce, idx, ties, hist, M, R, A))
+    Rh = R.cpu().numpy().reshape(3, 3)
+    Ah = A.cpu().numpy().reshape(3, 3)
+    Prh = Pr.cpu().numpy()
+    rc = 0.5 * (r_edges[1:] + r_edges[:-1])
+    rows["nearest_pair_stats"] = dict(
+        ms=ms, pdfs_ms=ms_pdf, noalloc_ms=ms_na, drops=D, histogram=[nr, nth], vertical_axis="z",
+        M=[float(v) for v in M.cpu().numpy()], R=[[float(v) for v in r] for r in Rh],
+        A=[[float(v) for v in r] for r in Ah], trace_R=float(np.trace(Rh)),
+        A_zz_over_trR=float(Ah[2, 2] / np.trace(Rh)),
+        P_r_peak_r_over_d=float(rc[int(np.argmax(Prh))] / 24.0))
+    log(f"nearest_pair_stats: {ms:.2f} ms (+ densities {ms_pdf:.3f} ms); tr R {np.trace(Rh):.1f}, "
+        f"A_zz/tr R {Ah[2, 2] / np.trace(Rh):+.4f}")
     del lab
-    # ---- curvature of one tracer: height functions vs network + fallback
-    P, meta = training.load_weights()
-    Pd = torch.from_numpy(P).to(dev)
+    # ---- curvature: height functions vs network + fallback, tracer 0 in detail, then every tracer
+    P_w, meta = training.load_weights()
+    Pd = torch.from_numpy(P_w).to(dev)
     c0 = c[0].contiguous()
     kap = torch.zeros(c0.shape, dtype=torch.float64, device=dev)
     st = torch.zeros(c0.shape, dtype=torch.uint8, device=dev)
-    nmix = int(((c0 > 0) & (c0 < 1)).sum().item())
+    nmix = int(((c0 > 1e-12) & (c0 < 1 - 1e-12)).sum().item())  # interface cells
     # both methods' first pass (the ordered list of mixed cells, NaN elsewhere) is the same
     ctx.curvature_hf(c0, kap, st)
     ctx.profile_start()
@@ -174,24 +242,54 @@ def rows_bench(torch, np, ctx, stream, c, w, n, ntr):
     fprof = ctx.profile_stop()
     nf, tf = fprof["k_mlp_infer"]
     fwd_ms = tf / nf
-    # matrix-core work per sample: layer 1 as hi + lo (2 x 32 x 128), layer 2 (128 x 128), multiply-add = 2 flops
-    mfma_flops = 2.0 * (2 * 32 * 128 + 128 * 128)
-    alg_flops = 2.0 * (27 * 128 + 128 * 128 + 128)
-    fwd_tflops = nmix * mfma_flops / (fwd_ms / 1e3) / 1e12
+    alg_flops = 2.0 * (27 * 128 + 128 * 128 + 128)  # 41,216 per sample (the model's own product)
+    mfma_flops = 2.0 * (2 * 32 * 128 + 128 * 128)   # issued: layer 1 as hi + lo over 32 padded inputs, layer 2
+    fwd_alg_tflops = nmix * alg_flops / (fwd_ms / 1e3) / 1e12
+    del xs, cell, sg, y
+    # every tracer: mixed cells of the whole field, both estimators, their agreement where HF is valid
+    tot_mixed = 0
+    t_hf = t_mlp = 0.0
+    diffs = []
+    kh = torch.empty(c0.shape, dtype=torch.float64, device=dev)
+    sh = torch.empty(c0.shape, dtype=torch.uint8, device=dev)
+    for t in range(ntr):
+        ct = c[t].contiguous()
+        ms1, _ = timed(torch, stream, lambda: ctx.curvature_hf(ct, kh, sh))
+        ms2, nm = timed(torch, stream, lambda: ctx.curvature_mlp(ct, Pd, meta["kappa_lo"], kap, st))
+        t_hf += ms1
+        t_mlp += ms2
+        tot_mixed += nm
+        valid = (sh >= 1) & (sh <= 3) & (st == 8)  # HF valid and the network's own value kept
+        d = (kap[valid] - kh[valid]).abs() / kh[valid].abs().clamp_min(1e-3)
+        diffs.append(d.cpu().numpy())
+    diffs = np.concatenate(diffs) if diffs else np.zeros(1)
     rows["curvature"] = dict(
         tracer=0, mixed_cells=nmix,
         hf_ms=ms_hf, hf_mixed_cells_per_s=nmix / (ms_hf / 1e3),
         mlp_hf_ms=ms_comb, mlp_hf_mixed_cells_per_s=nmix / (ms_comb / 1e3),
         hf_kernel_ms=hf_kernel_ms, hf_kernel_cells_per_s=nmix / (hf_kernel_ms / 1e3),
         mlp_hf_kernel_ms=mlp_kernel_ms, mlp_hf_kernel_cells_per_s=nmix / (mlp_kernel_ms / 1e3),
+        learned_over_hf_kernel_speedup=hf_kernel_ms / mlp_kernel_ms,
         mlp_forward_ms=fwd_ms, mlp_forward_cells_per_s=nmix / (fwd_ms / 1e3),
-        mlp_forward_mfma_tflops=fwd_tflops, mlp_forward_mfma_frac=fwd_tflops / BF16_PEAK_TFLOPS,
-        mlp_forward_algorithmic_tflops=nmix * alg_flops / (fwd_ms / 1e3) / 1e12,
+        mlp_forward_algorithmic_tflops=fwd_alg_tflops,
+        mlp_forward_issued_mfma_tflops=nmix * mfma_flops / (fwd_ms / 1e3) / 1e12,
+        mlp_forward_frac_of_bf16_peak=fwd_alg_tflops / BF16_PEAK_TFLOPS,
         kappa_lo=meta["kappa_lo"],
-        kernels_ms={**{k: v[1] / v[0] for k, v in prof_hf.items()}, **{k: v[1] / v[0] for k, v in prof.items()}})
+        kernels_ms={**{k: v[1] / v[0] for k, v in prof_hf.items()}, **{k: v[1] / v[0] for k, v in prof.items()}},
+        all_tracers=dict(mixed_cells=tot_mixed, hf_ms=t_hf, mlp_hf_ms=t_mlp,
+                         hf_mixed_cells_per_s=tot_mixed / (t_hf / 1e3),
+                         mlp_hf_mixed_cells_per_s=tot_mixed / (t_mlp / 1e3),
+                         cells_compared=int(diffs.size),
+                         mlp_vs_hf_rel_diff_median=float(np.median(diffs)),
+                         mlp_vs_hf_rel_diff_p90=float(np.percentile(diffs, 90)),
+                         mlp_vs_hf_rel_diff_mean=float(np.mean(diffs))))
+    mf = read_mfma_summary()
+    if mf:
+        rows["curvature"]["mfma_counters"] = mf
     log(f"curvature: HF {ms_hf:.2f} ms (kernel {hf_kernel_ms:.3f}), MLP+HF {ms_comb:.2f} ms (kernels "
-        f"{mlp_kernel_ms:.3f}), forward alone {fwd_ms:.3f} ms ({fwd_tflops:.1f} TFLOP/s) on {nmix} mixed cells")
-    del kap, st, xs, cell, sg, y
+        f"{mlp_kernel_ms:.3f}), forward alone {fwd_ms:.3f} ms ({fwd_alg_tflops:.1f} TFLOP/s) on {nmix} mixed cells; "
+        f"all tracers {tot_mixed} mixed cells, MLP vs HF median rel. diff {np.median(diffs):.4f}")
+    del kap, st, kh, sh
     # ---- surface-tension force of all tracers, curvature by height functions
     kap8 = torch.empty(c.shape, dtype=torch.float64, device=dev)
     st8 = torch.empty(c.shape, dtype=torch.uint8, device=dev)
@@ -208,6 +306,8 @@ def rows_bench(torch, np, ctx, stream, c, w, n, ntr):
     log(f"csf_force: {ms:.2f} ms, {rows['csf_force']['achieved_gbs']:.0f} GB/s of the method's bytes")
     del kap8, fxyz
     # ---- training step throughput (batch 4096)
+    from paper_2407_07463_amd import synth
+
     bsz = 4096
     rng = synth.Splitmix64(5)
     xt = torch.from_numpy(rng.uniform(bsz * 27).astype(np.float32).reshape(bsz, 27)).to(dev)
@@ -223,6 +323,29 @@ def rows_bench(torch, np, ctx, stream, c, w, n, ntr):
     rows["mlp_train_step"] = dict(batch=bsz, ms_per_step=ms / nst, samples_per_s=bsz * nst / (ms / 1e3))
     log(f"mlp training: {ms / nst:.3f} ms per step of {bsz}")
     return rows
+
+
+def tracer_count_bench(torch, ctx, stream):
+    """N(t) over the 256^3 workload: 200 steps, reassignment every 10, both near-contact modes."""
+    from paper_2407_07463_amd import synth, tracer_count
+
+    t0 = time.time()
+    w = synth.drops256(workers=16)
+    log(f"drops256 generated in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    ntr = int(w["c"].shape[0])
+    s = [torch.from_numpy(w[k]).to(dev) for k in ("sx", "sy", "sz")]
+    out = {}
+    for mode in ("tau", "stencil"):
+        c = torch.zeros((24,) + tuple(w["c"].shape[1:]), dtype=torch.float64, device=dev)
+        c[:ntr].copy_(torch.from_numpy(w["c"]))
+        ms, (N, recs) = timed(torch, stream, lambda: tracer_count.run(ctx, c, *s, ntr, 200, 10, mode, 1.5))
+        out[mode] = dict(ms_total=ms, steps=200, every=10, n_of_t=[[r["step"], r["ntracers"]] for r in recs],
+                         moved_total=int(sum(r["moved"] for r in recs)),
+                         retired_total=int(sum(r["retired"] for r in recs)), final_ntracers=N)
+        log(f"tracer count ({mode}): N from {recs[0]['ntracers']} to {N} in 200 steps, {ms:.0f} ms")
+        del c
+    return out
 
 
 def batched_bench(torch, ctx, stream, nsteps=10):
@@ -249,18 +372,99 @@ def batched_bench(torch, ctx, stream, nsteps=10):
                 plain_tracer_cell_steps_per_s=cells * nsteps / (ms_plain / 1e3))
 
 
+def cpu_baseline(w, n, ntr):
+    """The oracle as it stands, on the GPU machine's host: the whole workload's 8 tracers for one
+    step with every thread the process may use, then one tracer for one step on one thread."""
+    import numpy as np
+
+    import oracle
+
+    info = cpu_info()
+    threads = oracle.num_threads()
+    log(f"cpu baseline: oracle, {ntr} tracers x 1 step on {threads} threads ({info['cpu_model']})")
+    t1 = time.time()
+    oracle.advect(w["c"], w["sx"], w["sy"], w["sz"], 0, 1)
+    dt_multi = time.time() - t1
+    log(f"cpu baseline: 1 tracer x 1 step on 1 thread")
+    oracle.set_num_threads(1)
+    t1 = time.time()
+    oracle.advect(np.ascontiguousarray(w["c"][:1]), w["sx"], w["sy"], w["sz"], 0, 1)
+    dt_single = time.time() - t1
+    oracle.set_num_threads(threads)
+    n3 = n ** 3
+    # per-tracer rate: one tracer field's cell updates per second while all ntr are advanced
+    return {
+        "value": n3 * 1 / dt_multi,
+        "unit": "cell-updates/s per tracer",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"oracle advection of all {ntr} tracer fields of the {n}^3 workload for 1 step "
+                  f"({dt_multi:.1f} s on {threads} threads); single thread: 1 tracer, 1 step ({dt_single:.1f} s)",
+        "single_thread_value": n3 / (dt_single * ntr),
+        "single_thread_tracer_cell_steps_per_s": n3 / dt_single,
+        "tracer_cell_steps_per_s": n3 * ntr / dt_multi,
+        "c3_100_steps_extrapolated_s": dt_multi * 100,
+        **info,
+    }
+
+
+def pmc_pass(torch, np, ctx, c, s, ntr, which):
+    dev = c.device
+    if which == "advect":
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)  # calibration: reads and writes COPY_BYTES
+        ctx.advect(c, *s, step0=0, nsteps=2)
+        kap8 = torch.empty(c.shape, dtype=torch.float64, device=dev)
+        st8 = torch.empty(c.shape, dtype=torch.uint8, device=dev)
+        for t in range(ntr):
+            ctx.curvature_hf(c[t], kap8[t], st8[t])
+        fxyz = [torch.empty(tuple(c.shape[1:]), dtype=torch.float64, device=dev) for _ in range(3)]
+        for _ in range(2):
+            ctx.csf_force(c, kap8, 1.0, *fxyz)
+        torch.cuda.synchronize()
+        return {"pmc_pass": "advect", "copy_bytes": COPY_BYTES, "steps": 2, "csf_calls": 2}
+    from paper_2407_07463_amd import synth, training
+
+    P_w, meta = training.load_weights()
+    Pd = torch.from_numpy(P_w).to(dev)
+    ctx.advect(c, *s, step0=0, nsteps=2)
+    c0 = c[0].contiguous()
+    nmix = int(((c0 > 1e-12) & (c0 < 1 - 1e-12)).sum().item())  # interface cells
+    xs = torch.zeros((nmix, 27), dtype=torch.float32, device=dev)
+    cell = torch.zeros(nmix, dtype=torch.int32, device=dev)
+    sg = torch.zeros(nmix, dtype=torch.int8, device=dev)
+    ctx.mlp_stencils(c0, xs, cell, sg)
+    y = torch.zeros(nmix, dtype=torch.float32, device=dev)
+    kap = torch.zeros(c0.shape, dtype=torch.float64, device=dev)
+    st = torch.zeros(c0.shape, dtype=torch.uint8, device=dev)
+    for _ in range(3):
+        ctx.mlp_forward(Pd, xs, y)
+        ctx.curvature_mlp(c0, Pd, meta["kappa_lo"], kap, st)
+    bsz = 4096
+    rng = synth.Splitmix64(5)
+    xt = torch.from_numpy(rng.uniform(bsz * 27).astype(np.float32).reshape(bsz, 27)).to(dev)
+    tt = torch.from_numpy((rng.uniform(bsz) * 0.5).astype(np.float32)).to(dev)
+    Pt = torch.from_numpy(training.init_params(3)).to(dev)
+    Mt, Vt = torch.zeros_like(Pt), torch.zeros_like(Pt)
+    for k in range(1, 4):
+        ctx.mlp_train_step(Pt, Mt, Vt, k, 1e-3, xt, tt)
+    torch.cuda.synchronize()
+    return {"pmc_pass": "mlp", "mixed_cells": nmix, "forward_calls": 3, "fused_calls": 3, "train_steps": 3}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--runs", type=int, default=5, help="timed runs of --steps steps; the median is reported")
     ap.add_argument("--n", type=int, default=512, help="box size (cells per side)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rows", action="store_true", help="advection only")
-    ap.add_argument("--cpu-sample-tracers", type=int, default=2)
-    ap.add_argument("--pmc-pass", action="store_true", help="short run for rocprofv3 counters")
-    ap.add_argument("--sweeps", choices=("single", "paired"), default="single",
-                    help="run the sweeps one at a time (default, the faster form on this GPU) or in pairs")
+    ap.add_argument("--pmc-pass", choices=("advect", "mlp"), default=None,
+                    help="short run for rocprofv3 counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -282,82 +486,61 @@ def main():
     c = torch.from_numpy(w["c"]).to(dev)
     s = [torch.from_numpy(w[k]).to(dev) for k in ("sx", "sy", "sz")]
     ctx = vofmt.Context(0)
-    ctx.set_advect_pairs(args.sweeps == "paired")
     smax = ctx.check_courant(*s)
     stream = torch.cuda.current_stream()
     n3 = n ** 3
 
     if args.pmc_pass:
-        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.mul(src, 1.0, out=dst)  # calibration: reads and writes COPY_BYTES
-        ctx.advect(c, *s, step0=0, nsteps=2)
-        # the surface-tension force of the advected tracers (curvature by height functions)
-        kap8 = torch.empty(c.shape, dtype=torch.float64, device=dev)
-        st8 = torch.empty(c.shape, dtype=torch.uint8, device=dev)
-        for t in range(ntr):
-            ctx.curvature_hf(c[t], kap8[t], st8[t])
-        fxyz = [torch.empty(tuple(c.shape[1:]), dtype=torch.float64, device=dev) for _ in range(3)]
-        for _ in range(2):
-            ctx.csf_force(c, kap8, 1.0, *fxyz)
-        torch.cuda.synchronize()
-        print(json.dumps({"pmc_pass": True, "copy_bytes": COPY_BYTES, "steps": 2, "csf_calls": 2}), flush=True)
+        res = pmc_pass(torch, np, ctx, c, s, ntr, args.pmc_pass)
+        print(json.dumps(res), flush=True)
         ctx.close()
         return
 
     # warmup
-    ctx.advect(c, *s, step0=0, nsteps=max(args.warmup, 1) * 2)
+    ctx.advect(c, *s, step0=0, nsteps=max(args.warmup, 1))
     torch.cuda.synchronize()
+    g = max(args.warmup, 1)
     log("warmup done")
 
-    # timed region 1: the throughput
-    ms, _ = timed(torch, stream, lambda: ctx.advect(c, *s, step0=0, nsteps=args.steps))
-    ms_step = ms / args.steps
-    value = n3 * ntr * args.steps / (ms / 1e3)
-    log(f"advection: {ms_step:.3f} ms/step, {value:.3e} tracer-cell-steps/s")
+    # timed runs: K steps each, bracketed by synchronisations; the median is reported
+    run_ms = []
+    for _ in range(args.runs):
+        ms, _ = timed(torch, stream, lambda: ctx.advect(c, *s, step0=g, nsteps=args.steps))
+        g += args.steps
+        run_ms.append(ms)
+    ms_med = statistics.median(run_ms)
+    ms_step = ms_med / args.steps
+    value = n3 * args.steps / (ms_med / 1e3)  # cell updates per second of one tracer field (all 8 advanced)
+    log(f"advection: {ms_step:.3f} ms/step (runs {', '.join(f'{m / args.steps:.3f}' for m in run_ms)}), "
+        f"{value:.3e} cell-updates/s per tracer")
 
-    # timed region 2: the same K steps with every launch timed by HIP events
+    # one more run of K steps with every launch timed by HIP events
     ctx.profile_start()
-    ms2, _ = timed(torch, stream, lambda: ctx.advect(c, *s, step0=0, nsteps=args.steps))
+    ms2, _ = timed(torch, stream, lambda: ctx.advect(c, *s, step0=g, nsteps=args.steps))
     prof = ctx.profile_stop()
+    g += args.steps
     kernels = {k: dict(launches=v[0], avg_ms=v[1] / v[0], total_ms=v[1]) for k, v in prof.items()}
-    pair_names = [k for k in prof if k.startswith("k_pair<")]
-    if pair_names:  # paired sweeps: the paired streaming pass over all tracers
-        launches = sum(prof[k][0] for k in pair_names)
-        total_ms = sum(prof[k][1] for k in pair_names)
-        nbytes = sum(prof[k][0] * pair_bytes(n3, ntr, not k.endswith(",3>")) for k in pair_names)
-        bytes_launch = nbytes / launches
-        achieved = nbytes / (total_ms / 1e3) / 1e9
-        kernel_desc = f"k_pair<A,B,N> (two sweeps of all {ntr} tracers in one pass; all axis pairs)"
-        log(f"k_pair: {launches} launches, avg {total_ms / launches:.3f} ms, {achieved:.0f} GB/s "
-            f"(profiled region {ms2 / args.steps:.3f} ms/step)")
-        prefix, traffic_file = "k_pair<", TRAFFIC_FILE
-    else:
-        stream_names = [k for k in prof if k.startswith("k_stream<")]
-        launches = sum(prof[k][0] for k in stream_names)
-        total_ms = sum(prof[k][1] for k in stream_names)
-        g = 4 if ntr >= 4 else ntr
-        bytes_launch = stream_bytes(n3, g)
-        achieved = bytes_launch / (total_ms / launches / 1e3) / 1e9
-        kernel_desc = (f"k_stream<D,{g}> (streaming pass of {g} tracers; all axes; the x-sweep as "
-                       f"k_stream_rows<{g}>); achieved counts the method's bytes per tracer-cell-sweep, "
-                       f"actual_hbm_gbs the measured HBM bytes")
-        log(f"k_stream: {launches} launches, avg {total_ms / launches:.3f} ms, {achieved:.0f} GB/s "
-            f"(profiled region {ms2 / args.steps:.3f} ms/step)")
-        prefix, traffic_file = ("k_stream<", "k_stream_rows<"), TRAFFIC_FILE_SINGLE
-
+    stream_names = [k for k in prof if k.startswith("k_stream<")]
+    launches = sum(prof[k][0] for k in stream_names)
+    total_ms = sum(prof[k][1] for k in stream_names)
+    gsz = 4 if ntr >= 4 else ntr  # tracers per streaming launch
+    bytes_launch = sweep_model_bytes(ntr) * gsz * n3
+    avg_launch_s = total_ms / launches / 1e3
+    achieved = bytes_launch / avg_launch_s / 1e9
+    log(f"k_stream: {launches} launches, avg {1e3 * avg_launch_s:.3f} ms, {achieved:.0f} GB/s of the method's "
+        f"bytes (profiled run {ms2 / args.steps:.3f} ms/step)")
     traffic = None
-    tr, sha = profiling.read_traffic(traffic_file)
+    tr, sha = profiling.read_traffic(TRAFFIC_FILE)
     if tr and sha == profiling.advect_source_sha():
-        vals = [v for k, v in tr.items() if k.startswith(prefix)]  # str.startswith takes a tuple too
+        vals = [v for k, v in tr.items() if k.startswith(("k_stream<", "k_stream_rows<"))]
         if vals:
             traffic = sum(vals) / len(vals)
+    step_bytes = 3.0 * sweep_model_bytes(ntr) * ntr * n3  # 51.5 B per tracer-cell-step at 8 tracers
 
     out = {
         "metric": METRIC,
         "value": value,
-        "unit": "tracer-cell-steps/s",
+        "unit": "cell-updates/s per tracer",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -374,9 +557,11 @@ def main():
             "grid": [n, n, n],
             "tracers": ntr,
         },
-        "per_tracer_cell_steps_per_s": value / ntr,
-        "step_model_gbs": step_model_bytes(n3, ntr) / (ms_step / 1e3) / 1e9,
-        "step_model_frac": step_model_bytes(n3, ntr) / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
+        "runs_ms_per_step": [m / args.steps for m in run_ms],
+        "all_tracer_cell_steps_per_s": value * ntr,
+        "step_model_bytes_per_tracer_cell_step": 3.0 * sweep_model_bytes(ntr),
+        "step_model_gbs": step_bytes / (ms_step / 1e3) / 1e9,
+        "step_model_frac": step_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,
@@ -384,9 +569,11 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "actual_hbm_gbs": (traffic / (total_ms / launches / 1e3) / 1e9) if traffic else None,
-            "kernel": kernel_desc,
+            "kernel": f"k_stream<D,{gsz}> / k_stream_rows<{gsz}> (streaming pass of {gsz} tracers, all axes)",
             "bytes_per_launch": bytes_launch,
+            "bytes_model": f"{sweep_model_bytes(ntr):.3f} B per tracer-cell-sweep x {gsz} x n^3",
+            "avg_launch_ms": 1e3 * avg_launch_s,
+            "actual_hbm_gbs": (traffic / avg_launch_s / 1e9) if traffic else None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         },
         "kernels": kernels,
@@ -396,25 +583,12 @@ def main():
         out["rows"] = rows_bench(torch, np, ctx, stream, c, w, n, ntr)
         del c, s
         torch.cuda.empty_cache()
+        out["rows"]["tracer_count_drops256"] = tracer_count_bench(torch, ctx, stream)
+        torch.cuda.empty_cache()
         out["rows"]["batched_advection"] = batched_bench(torch, ctx, stream)
 
     if not args.no_cpu_baseline:
-        import oracle
-
-        k = args.cpu_sample_tracers
-        host_c = w["c"][:k]
-        log(f"cpu baseline: oracle, {k} tracers of the same field, 1 step")
-        t1 = time.time()
-        oracle.advect(host_c, w["sx"], w["sy"], w["sz"], 0, 1)
-        dt = time.time() - t1
-        out["cpu_baseline"] = {
-            "value": n3 * k / dt,
-            "unit": "tracer-cell-steps/s",
-            "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"oracle advection of {k} of the {ntr} tracer fields of the same {n}^3 workload, "
-                      f"1 step ({dt:.1f} s)",
-        }
+        out["cpu_baseline"] = cpu_baseline(w, n, ntr)
     ctx.close()
     print(json.dumps(out), flush=True)
 

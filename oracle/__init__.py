@@ -84,6 +84,8 @@ def lib():
         L.orc_curvature_hf.restype = ctypes.c_int
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
+        L.orc_set_num_threads.restype = None
         if hasattr(L, "orc_mlp_forward"):
             _setup_mlp(L)
         _lib = L
@@ -93,6 +95,11 @@ def lib():
 def num_threads() -> int:
     """Threads the oracle's OpenMP loops use."""
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the oracle's OpenMP loops from now on."""
+    lib().orc_set_num_threads(int(n))
 
 
 def _f64(a):

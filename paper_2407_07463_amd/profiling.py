@@ -13,6 +13,11 @@ Usage (after the rocprofv3 runs, with their CSV output directories):
       same counter reads for a plain copy kernel that reads and writes B bytes.
       The summary records the SHA-256 of the advection sources, so that a
       reader can tell whether the kernel changed since.
+
+  python -m paper_2407_07463_amd.profiling counters DIR --kernel REGEX \
+      --counters NAME... --out FILE.txt --command "..." [--sources ...]
+      per-kernel mean of each counter per dispatch from a `--pmc` run
+      (derived metrics such as MfmaUtil as rocprofv3 reduces them).
 """
 from __future__ import annotations
 
@@ -147,6 +152,26 @@ def write_traffic(fetch_dir, write_dir, kernel_re, copy_re, copy_bytes, out, com
         fo.write("\n".join(lines) + "\n")
 
 
+def write_counters(directory, kernel_re, counters, out, command, title, sources=None):
+    """Per-kernel mean of each counter per dispatch (derived metrics included, as rocprofv3
+    reduces them), one line per kernel matching kernel_re."""
+    kre = re.compile(kernel_re)
+    means = {cn: counter_means(directory, cn) for cn in counters}
+    names = sorted({k for m in means.values() for k in m if kre.search(k)})
+    lines = [f"# {title}", "", f"Command: {command}", "",
+             f"source_sha256 = {advect_source_sha(sources)}   ({', '.join(sources or ADVECT_SOURCES)})", ""]
+    for k in names:
+        parts = [f"kernel = {k}"]
+        nd = max(means[cn].get(k, (0, 0.0))[0] for cn in counters)
+        parts.append(f"dispatches = {nd}")
+        for cn in counters:
+            n, v = means[cn].get(k, (0, float("nan")))
+            parts.append(f"{cn} = {v:.6g}")
+        lines.append(" | ".join(parts))
+    with open(out, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+
+
 def read_traffic(path):
     """{kernel: traffic bytes per dispatch} and the recorded source hash, or (None, None)."""
     if not os.path.exists(path):
@@ -182,7 +207,19 @@ def main(argv=None):
     b.add_argument("--sources", nargs="*", default=None,
                    help="sources of the counted kernel (relative to the package) whose hash the summary records; "
                         "default: the advection kernels")
+    c = sub.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--counters", nargs="+", required=True)
+    c.add_argument("--out", required=True)
+    c.add_argument("--command", required=True)
+    c.add_argument("--title", default="rocprofv3 counters per dispatch")
+    c.add_argument("--sources", nargs="*", default=None)
     args = ap.parse_args(argv)
+    if args.cmd == "counters":
+        write_counters(args.dir, args.kernel, args.counters, args.out, args.command, args.title, args.sources)
+        print(open(args.out).read())
+        return
     if args.cmd == "stats":
         for name, calls, t, avg in write_stats(args.dir, args.out, args.command, args.title)[:12]:
             print(f"{name:60s} {calls:6d} {t / 1e6:10.3f} ms {avg / 1e3:10.2f} us")
