@@ -340,10 +340,13 @@ int vofmt_csf_force(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t 
  * the BF16 matrix cores with FP32 accumulation; their weights are rounded to
  * BF16 (nearest even) for each use, the first-layer activations and the
  * upstream gradients are rounded to BF16, and each input x enters as two BF16
- * numbers hi = bf16(x), lo = bf16(x - hi) times the same weights. The last
- * layer is an FP32 dot product of the unrounded second-layer activations with
- * the FP32 W3. Biases, loss and Adam in FP32. Every batch reduction is done in
- * a fixed order, so results are reproducible bit for bit.
+ * numbers hi = bf16(x), lo = bf16(x - hi) times the same weights. The biases
+ * are FP32 and enter the forward products' FP32 accumulation: b1 as three
+ * BF16 numbers whose sum is b1 (exact for |b1| above 2^-100), b2 as the
+ * initial accumulator. The last layer is an FP32 dot product of the unrounded
+ * second-layer activations with the FP32 W3. Loss and Adam in FP32. Every
+ * batch reduction is done in a fixed order, so results are reproducible bit
+ * for bit.
  * ------------------------------------------------------------------------ */
 #define VOFMT_MLP_NPARAMS 20868
 

@@ -11,10 +11,12 @@
 // the first-layer activations and the upstream gradients are rounded to BF16,
 // and every input value x enters as two BF16 numbers hi = bf16(x),
 // lo = bf16(x - hi) multiplied by the same weights (about 16 significant
-// bits). The last layer (128 -> 1) is an FP32 dot product of the unrounded
-// second-layer activations with the FP32 W3. Biases, loss and Adam in FP32.
-// ReLU'(z) is (activation > 0). Batch reductions go through per-tile partial
-// sums added in a fixed order, so every result is reproducible bit for bit.
+// bits). The FP32 biases enter the forward products' accumulation (b1 as
+// three BF16 parts summing to it, b2 as the initial accumulator). The last
+// layer (128 -> 1) is an FP32 dot product of the unrounded second-layer
+// activations with the FP32 W3. Loss and Adam in FP32. ReLU'(z) is
+// (activation > 0). Batch reductions go through per-tile partial sums added
+// in a fixed order, so every result is reproducible bit for bit.
 //
 // MFMA fragment layout (16x16x32, one wavefront): lane l holds
 //   A[l%16][8*(l/16) + e], B[8*(l/16) + e][l%16] for e = 0..7 (bf16), and
@@ -32,20 +34,6 @@
 
 namespace {
 
-// Sum of each row of 16 lanes, received by every lane of the row, with the
-// additions of the butterfly v + v[lane ^ 8], ^ 4, ^ 2, ^ 1 in the same order
-// and on the same operands: after each step the partial sums repeat with the
-// step's period, so rotating the row by the step reads the value the
-// butterfly would. DPP row rotations (row_ror:8, 4, 2, 1) instead of LDS
-// permutes. Every lane of the wavefront must be active.
-__device__ __forceinline__ float row16_sum(float v) {
-  v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false));
-  v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xf, 0xf, false));
-  v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x122, 0xf, 0xf, false));
-  v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x121, 0xf, 0xf, false));
-  return v;
-}
-
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
@@ -54,9 +42,8 @@ constexpr int OFF_W1 = 0, OFF_B1 = NIN * NH, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_
               OFF_B3 = OFF_W3 + NH, NPARAMS = OFF_B3 + 4;
 static_assert(NPARAMS == VOFMT_MLP_NPARAMS, "parameter layout");
 
-constexpr int TILE = 64;  // samples per tile
-constexpr int XP = 40;    // LDS row pitches (bf16 elements), padded against bank conflicts
-constexpr int HP = 136;
+constexpr int TILE = 64;  // samples per tile of the backward pass
+constexpr int HP = 136;  // LDS row pitches (bf16 elements), padded against bank conflicts
 constexpr int TP = 72;
 
 // FP32 -> BF16, round to nearest even (the conversion instruction of gfx950).
@@ -82,20 +69,36 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 
 constexpr int ACT_BYTES = 768, TRACE_BYTES = 1280;
 
-// BF16 copies of the weights for one call: W1^T [128][32], W2^T [128][128],
-// W2 [128][128] (for the backward product).
-__global__ void k_mlp_prep(const float *__restrict__ P, uint16_t *__restrict__ w1t, uint16_t *__restrict__ w2t,
+// BF16 copies of the weights for one call: W1 and W2 in the order of the
+// forward pass's operand fragments (w1f [kk][half][lane][8], with b1 as
+// hi + mid + lo on the padding inputs 27..29; w2f [nt][kk][lane][8]), and W2
+// row-major [128][128] for the backward product.
+__global__ void k_mlp_prep(const float *__restrict__ P, uint16_t *__restrict__ w1f, uint16_t *__restrict__ w2f,
                            uint16_t *__restrict__ w2n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < NIN * NH) {
-    const int k = i / NH, j = i % NH;
-    w1t[j * NIN + k] = bf16_bits(P[OFF_W1 + i]);
+    const int f = i >> 3, e = i & 7, ln = f & 63, half = (f >> 6) & 1, kk = f >> 7;
+    const int lr = ln & 15, lq = ln >> 4;
+    const int u = 32 * kk + 8 * (lr >> 2) + 4 * half + (lr & 3);  // hidden unit of product row lr
+    const int k = 8 * lq + e;
+    uint16_t v = 0;
+    if (k < 27) {
+      v = bf16_bits(P[OFF_W1 + k * NH + u]);
+    } else if (k < 30) {
+      const float b = P[OFF_B1 + u];
+      const uint16_t hi = bf16_bits(b);
+      const float r1 = b - bf16_val(hi);
+      const uint16_t mid = bf16_bits(r1);
+      const float r2 = r1 - bf16_val(mid);
+      v = k == 27 ? hi : (k == 28 ? mid : bf16_bits(r2));
+    }
+    w1f[i] = v;
   }
   if (i < NH * NH) {
-    const int k = i / NH, j = i % NH;
-    const uint16_t b = bf16_bits(P[OFF_W2 + i]);
-    w2t[j * NH + k] = b;
-    w2n[i] = b;
+    const int f = i >> 3, e = i & 7, ln = f & 63, kk = (f >> 6) & 3, nt = f >> 8;
+    const int lr = ln & 15, lq = ln >> 4;
+    w2f[i] = bf16_bits(P[OFF_W2 + (32 * kk + 8 * lq + e) * NH + 16 * nt + lr]);
+    w2n[i] = bf16_bits(P[OFF_W2 + i]);
   }
 }
 
@@ -106,127 +109,259 @@ __device__ __forceinline__ float *act_h2(uint8_t *rec, int64_t s, int stride) {
   return reinterpret_cast<float *>(rec + s * stride + 256);
 }
 
-// Forward pass, persistent over 64-sample tiles. acts (nullable): the
-// activation records. With a target, also the upstream gradient g = dL/dy of
-// every sample and the loss of every tile.
-__global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ P, const uint16_t *__restrict__ w1t_g,
-                                                 const uint16_t *__restrict__ w2t_g, int m,
-                                                 const float *__restrict__ x, float *__restrict__ y,
-                                                 uint8_t *__restrict__ acts, const float *__restrict__ tgt,
-                                                 float *__restrict__ g_out, float *__restrict__ loss_part) {
-  __shared__ __attribute__((aligned(16))) uint16_t W1s[NH][XP];
-  __shared__ __attribute__((aligned(16))) uint16_t W2s[NH][HP];
-  __shared__ __attribute__((aligned(16))) uint16_t Xh[TILE][XP];
-  __shared__ __attribute__((aligned(16))) uint16_t Xl[TILE][XP];
-  __shared__ __attribute__((aligned(16))) uint16_t H1s[TILE][HP];
-  __shared__ float b1s[NH], b2s[NH], w3s[NH];
-  __shared__ float ypart[4][TILE];
-  __shared__ float lpart[TILE];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int i = tid; i < NH * NIN; i += 256) W1s[i / NIN][i % NIN] = w1t_g[i];
-  for (int i = tid; i < NH * NH; i += 256) W2s[i / NH][i % NH] = w2t_g[i];
-  for (int i = tid; i < NH; i += 256) {
-    b1s[i] = P[OFF_B1 + i];
-    b2s[i] = P[OFF_B2 + i];
-    w3s[i] = P[OFF_W3 + i];
+// ------------------------------------------------------------ forward pass
+//
+// A wavefront evaluates the network on a tile of WT = 64 samples by itself
+// (no workgroup barrier after the weights are staged), both matrix-core
+// layers chained in registers:
+// - layer 1 is computed transposed, Z1^T = W1^T X^T, in product tiles of 16
+//   hidden units x 16 samples whose rows are assigned to units so that lane
+//   (lr, lq) of the tile (kk, half) receives units 32kk + 8lq + 4half + r
+//   (r = 0..3) of sample lr: after both halves the lane holds, rounded to
+//   BF16, exactly its B operand of layer 2's product over the K block kk;
+// - layer 2 is computed transposed as well, Z2^T = W2^T H1^T, which leaves
+//   units 16nt + 4lq + r of sample lr in lane (lr, lq): the last layer is a
+//   dot product within the lane, then a sum over the four lane groups.
+// b1 enters layer 1's product through the padding inputs 27..29, which hold
+// the value one, with weights hi, mid, lo: three BF16 numbers whose sum is b1
+// (exactly, for |b1| above 2^-100); b2 is the initial accumulator of layer 2.
+// The weights sit in LDS in the order of the operand fragments, 16 bytes per
+// lane at consecutive addresses.
+constexpr int WT = 64;        // samples per wavefront tile
+constexpr int WMT = WT / 16;  // 16-sample product tiles per wavefront tile
+constexpr int L1P = 2;        // sample tiles per pass of layer 1 (bounds the live X operands)
+constexpr int NW1F = 4 * 2 * 64, NW2F = 8 * 4 * 64;  // operand fragments of W1 and W2
+static_assert(WT == TILE, "the loss of a forward tile is the loss of a backward tile");
+
+typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
+
+struct NetLds {
+  bf16x8 w1f[NW1F];  // [kk][half][lane]
+  bf16x8 w2f[NW2F];  // [nt][kk][lane]
+  float b2[NH], w3[NH];
+};
+
+__device__ __forceinline__ void stage_net(NetLds &L, const float *__restrict__ P, const uint4 *__restrict__ w1f_g,
+                                          const uint4 *__restrict__ w2f_g, int tid, int nthreads) {
+  uint4 *d1 = reinterpret_cast<uint4 *>(L.w1f);
+  uint4 *d2 = reinterpret_cast<uint4 *>(L.w2f);
+  for (int i = tid; i < NW1F; i += nthreads) d1[i] = w1f_g[i];
+  for (int i = tid; i < NW2F; i += nthreads) d2[i] = w2f_g[i];
+  for (int i = tid; i < NH; i += nthreads) {
+    L.b2[i] = P[OFF_B2 + i];
+    L.w3[i] = P[OFF_W3 + i];
   }
-  const float b3 = P[OFF_B3];
-  const int ntiles = (m + TILE - 1) / TILE;
+}
+
+typedef __attribute__((ext_vector_type(2))) float f32x2;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+
+// (a, b) rounded to BF16 (nearest even) in one packed conversion, a in the low half.
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
+}
+
+// relu(a), relu(b) as BF16, packed: the rounding first, then a signed 16-bit
+// maximum with zero, which clears exactly the values with the sign bit set --
+// the same bits as rounding relu(a), relu(b).
+__device__ __forceinline__ uint32_t relu_pack(float a, float b) {
+  typedef __attribute__((ext_vector_type(2))) short s16x2;
+  s16x2 v = __builtin_bit_cast(s16x2, pack_bf16(a, b));
+  v = __builtin_elementwise_max(v, (s16x2){0, 0});
+  return __builtin_bit_cast(uint32_t, v);
+}
+
+// Buffer resource over [base, base + bytes) (raw addressing, bounds checked
+// by the hardware): a vector access beyond it reads zero and writes nothing.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void *base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, bytes, 0x00020000);
+}
+
+// relu(z) = (z > 0 ? z : 0) for every z but NaN, in one instruction: a
+// signed 32-bit maximum with zero clears exactly the values with the sign
+// bit set.
+__device__ __forceinline__ float relu(float z) { return __int_as_float(max(__float_as_int(z), 0)); }
+
+// The layer-1 operand of a 16-sample tile from eight input values of the
+// lane (inputs 8lq .. 8lq+7 of sample lr), split into hi + lo, two values at
+// a time: hi = bf16(v), lo = bf16(v - hi).
+__device__ __forceinline__ void split_frag(const float (&v)[8], bf16x8 &h, bf16x8 &l) {
+  u32x4 hw, lw;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const uint32_t hp = pack_bf16(v[2 * p], v[2 * p + 1]);
+    hw[p] = hp;
+    lw[p] = pack_bf16(v[2 * p] - __uint_as_float(hp << 16), v[2 * p + 1] - __uint_as_float(hp & 0xffff0000u));
+  }
+  h = __builtin_bit_cast(bf16x8, hw);
+  l = __builtin_bit_cast(bf16x8, lw);
+}
+
+// The network on one wavefront tile. xfrag(mt, xh, xl) supplies the layer-1
+// operands of sample tile mt; h1out(mt, kk, bits) and h2out(mt, nt, h) see
+// the activations (units 32kk + 8lq .. +7 and 16nt + 4lq .. +3 of sample
+// 16mt + lr). Returns in y[mt] the output of sample 16mt + lr, in every lane
+// group.
+template <class XF, class H1Out, class H2Out>
+__device__ __forceinline__ void net_tile(const NetLds &L, int lane, float b3, XF xfrag, H1Out h1out, H2Out h2out,
+                                         float (&y)[WMT]) {
+  const int lq = lane >> 4;
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  u32x4 h1[WMT][4];
+#pragma unroll
+  for (int mp = 0; mp < WMT; mp += L1P) {
+    bf16x8 xh[L1P], xl[L1P];
+#pragma unroll
+    for (int j = 0; j < L1P; ++j) xfrag(mp + j, xh[j], xl[j]);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const bf16x8 a = L.w1f[(2 * kk + half) * 64 + lane];
+#pragma unroll
+        for (int j = 0; j < L1P; ++j) {
+          f32x4 acc = mfma(a, xh[j], zero);
+          acc = mfma(a, xl[j], acc);
+          h1[mp + j][kk][2 * half] = relu_pack(acc[0], acc[1]);
+          h1[mp + j][kk][2 * half + 1] = relu_pack(acc[2], acc[3]);
+        }
+      }
+  }
+#pragma unroll
+  for (int mt = 0; mt < WMT; ++mt)
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) h1out(mt, kk, h1[mt][kk]);
+  float yq[WMT];
+#pragma unroll
+  for (int mt = 0; mt < WMT; ++mt) yq[mt] = 0.0f;
+#pragma unroll
+  for (int nt = 0; nt < 8; ++nt) {
+    const f32x4 b2 = *reinterpret_cast<const f32x4 *>(&L.b2[16 * nt + 4 * lq]);
+    const f32x4 w3 = *reinterpret_cast<const f32x4 *>(&L.w3[16 * nt + 4 * lq]);
+    bf16x8 a[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) a[kk] = L.w2f[(4 * nt + kk) * 64 + lane];
+#pragma unroll
+    for (int mt = 0; mt < WMT; ++mt) {
+      f32x4 acc = b2;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) acc = mfma(a[kk], __builtin_bit_cast(bf16x8, h1[mt][kk]), acc);
+      f32x4 h;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h[r] = relu(acc[r]);
+      h2out(mt, nt, h);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) yq[mt] = fmaf(h[r], w3[r], yq[mt]);
+    }
+  }
+#pragma unroll
+  for (int mt = 0; mt < WMT; ++mt) {
+    float v = yq[mt];
+    v = v + __shfl_xor(v, 16);
+    v = v + __shfl_xor(v, 32);
+    y[mt] = v + b3;
+  }
+}
+
+// y[lq]: the output of the lane's own sample 16lq + lr = lane.
+__device__ __forceinline__ float own_output(const float (&y)[WMT], int lq) {
+  float v = y[0];
+  v = lq == 1 ? y[1] : v;
+  v = lq == 2 ? y[2] : v;
+  v = lq == 3 ? y[3] : v;
+  return v;
+}
+
+// Forward pass over x[m][27], persistent: wavefront tiles of WT samples.
+// acts (nullable): the activation records. With a target (training): also
+// the upstream gradient g = dL/dy of every sample and the loss of every tile.
+template <bool kTrain, bool kActs>
+__device__ __forceinline__ void mlp_tiles(const NetLds &L, const float *__restrict__ P, int m,
+                                          const float *__restrict__ x, float *__restrict__ y,
+                                          uint8_t *__restrict__ acts, const float *__restrict__ tgt,
+                                          float *__restrict__ g_out, float *__restrict__ loss_part, int waves) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: tile indices and buffer bases stay scalar
   const int lr = lane & 15, lq = lane >> 4;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int s0 = tile * TILE;
-    __syncthreads();
-    for (int i = tid; i < TILE * NIN; i += 256) {
-      const int s = i / NIN, k = i % NIN;
-      const float v = (k < 27 && s0 + s < m) ? x[(int64_t)(s0 + s) * 27 + k] : 0.0f;
-      const uint16_t hi = bf16_bits(v);
-      Xh[s][k] = hi;
-      Xl[s][k] = bf16_bits(v - bf16_val(hi));
-    }
-    __syncthreads();
-    // layer 1: wave w owns output columns [32w, 32w+32)
+  const float b3 = P[OFF_B3];
+  const int ntiles = (m + WT - 1) / WT;
+  const int xoff = (lr * 27 + 8 * lq) * 4;                  // byte offset of the lane's inputs in a row tile
+  const uint32_t keep = lq < 3 ? 0xffffffffu : 0u;          // inputs 8lq + 3 .. 8lq + 7 exist
+  const uint32_t one = lq == 3 ? __float_as_uint(1.0f) : 0u;  // else 27..29 are one
+  for (int tile = blockIdx.x * waves + w; tile < ntiles; tile += gridDim.x * waves) {
+    // the weight fragments are read from LDS tile by tile: kept out of the
+    // loop they would need 160 registers
+    __asm__ volatile("" ::: "memory");
+    const int s0 = tile * WT;
+    // the tile's rows of x and of the records: rows past m read zero and are not written
+    const int rows = m - s0 < WT ? m - s0 : WT;
+    const __amdgpu_buffer_rsrc_t xr = buffer_of(x + (int64_t)s0 * 27, rows * 27 * 4);
+    const __amdgpu_buffer_rsrc_t ar = buffer_of(kActs ? acts + (int64_t)s0 * ACT_BYTES : acts, kActs ? rows * ACT_BYTES : 0);
+    // inputs 8lq + e of sample row 16mt + lr, all loaded (inputs 27..31 read the
+    // next row or zero); the lanes of group 3 then put one on 27..29, zero on 30..31
+    auto xfrag = [&](int mt, bf16x8 &xh, bf16x8 &xl) {
+      float v[8];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-      for (int jn = 0; jn < 2; ++jn) {
-        const int nt = 2 * w + jn;
-        const bf16x8 wf = frag(&W1s[16 * nt + lr][8 * lq]);
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mfma(frag(&Xh[16 * mt + lr][8 * lq]), wf, acc);
-        acc = mfma(frag(&Xl[16 * mt + lr][8 * lq]), wf, acc);
-        const int col = 16 * nt + lr;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * mt + 4 * lq + r;
-          const float z = acc[r] + b1s[col];
-          const uint16_t h = bf16_bits(z > 0.0f ? z : 0.0f);
-          H1s[row][col] = h;
-          if (acts && s0 + row < m) act_h1(acts, s0 + row, ACT_BYTES)[col] = h;
-        }
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t xv = __builtin_amdgcn_raw_buffer_load_b32(xr, xoff + (16 * mt * 27 + e) * 4, 0, 0);
+        v[e] = __uint_as_float(e < 3 ? xv : ((xv & keep) | (e < 6 ? one : 0u)));
       }
-    __syncthreads();
-    // layer 2 and the layer-3 partial products
-    float yp[4][4];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) yp[mt][r] = 0.0f;
-#pragma unroll
-    for (int jn = 0; jn < 2; ++jn) {
-      const int nt = 2 * w + jn;
-      const int col = 16 * nt + lr;
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kk = 0; kk < NH; kk += 32)
-          acc = mfma(frag(&H1s[16 * mt + lr][kk + 8 * lq]), frag(&W2s[16 * nt + lr][kk + 8 * lq]), acc);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * mt + 4 * lq + r;
-          const float z = acc[r] + b2s[col];
-          const float h = z > 0.0f ? z : 0.0f;
-          if (acts && s0 + row < m) act_h2(acts, s0 + row, ACT_BYTES)[col] = h;
-          yp[mt][r] = yp[mt][r] + h * w3s[col];
-        }
-      }
-    }
-    // sum the 16 columns of each row across lanes (fixed tree)
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        float v = yp[mt][r];
-        v = row16_sum(v);
-        if (lr == 0) ypart[w][16 * mt + 4 * lq + r] = v;
-      }
-    __syncthreads();
-    if (tid < TILE) {
-      const int s = s0 + tid;
+      split_frag(v, xh, xl);
+    };
+    auto h1out = [&](int mt, int kk, u32x4 bits) {
+      if (kActs) __builtin_amdgcn_raw_buffer_store_b128(bits, ar, (16 * mt + lr) * ACT_BYTES + (32 * kk + 8 * lq) * 2, 0, 0);
+    };
+    auto h2out = [&](int mt, int nt, f32x4 h) {
+      if (kActs)
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, h), ar,
+                                               (16 * mt + lr) * ACT_BYTES + 256 + (16 * nt + 4 * lq) * 4, 0, 0);
+    };
+    float yv[WMT];
+    net_tile(L, lane, b3, xfrag, h1out, h2out, yv);
+    const float yy = own_output(yv, lq);
+    const int s = s0 + lane;
+    if (y && s < m) y[s] = yy;
+    if (kTrain) {
       float lv = 0.0f;
       if (s < m) {
-        const float yy = (((ypart[0][tid] + ypart[1][tid]) + ypart[2][tid]) + ypart[3][tid]) + b3;
-        if (y) y[s] = yy;
-        if (tgt) {
-          const float t = tgt[s];
-          const float a = fabsf(t) > 0.05f ? fabsf(t) : 0.05f;
-          const float wgt = 1.0f / (a * a);
-          const float d = yy - t;
-          lv = (d * d) * wgt;
-          g_out[s] = ((2.0f * d) * wgt) / (float)m;
-        }
+        const float t = tgt[s];
+        const float a = fabsf(t) > 0.05f ? fabsf(t) : 0.05f;
+        const float wgt = 1.0f / (a * a);
+        const float d = yy - t;
+        lv = (d * d) * wgt;
+        g_out[s] = ((2.0f * d) * wgt) / (float)m;
       }
-      lpart[tid] = lv;
-    }
-    if (tgt) {
-      __syncthreads();
-      if (tid == 0) {
-        float acc = 0.0f;
-        for (int i = 0; i < TILE; ++i) acc += lpart[i];
-        loss_part[tile] = acc;
-      }
+      // butterfly over the wavefront: every lane ends with the same sum
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) lv = lv + __shfl_xor(lv, off);
+      if (lane == 0) loss_part[tile] = lv;
     }
   }
+}
+
+constexpr int IWAVES = 8;  // wavefronts per workgroup of the forward kernels
+
+template <bool kActs>
+__global__ __launch_bounds__(64 * IWAVES) __attribute__((amdgpu_waves_per_eu(4))) void k_mlp_infer(const float *__restrict__ P,
+                                                           const uint4 *__restrict__ w1f_g,
+                                                           const uint4 *__restrict__ w2f_g, int m,
+                                                           const float *__restrict__ x, float *__restrict__ y,
+                                                           uint8_t *__restrict__ acts) {
+  __shared__ NetLds L;
+  stage_net(L, P, w1f_g, w2f_g, threadIdx.x, 64 * IWAVES);
+  __syncthreads();
+  mlp_tiles<false, kActs>(L, P, m, x, y, acts, nullptr, nullptr, nullptr, IWAVES);
+}
+
+__global__ __launch_bounds__(64 * IWAVES) __attribute__((amdgpu_waves_per_eu(4))) void k_mlp_fwd(const float *__restrict__ P, const uint4 *__restrict__ w1f_g,
+                                                         const uint4 *__restrict__ w2f_g, int m,
+                                                         const float *__restrict__ x, uint8_t *__restrict__ acts,
+                                                         const float *__restrict__ tgt, float *__restrict__ g_out,
+                                                         float *__restrict__ loss_part) {
+  __shared__ NetLds L;
+  stage_net(L, P, w1f_g, w2f_g, threadIdx.x, 64 * IWAVES);
+  __syncthreads();
+  mlp_tiles<true, true>(L, P, m, x, nullptr, acts, tgt, g_out, loss_part, IWAVES);
 }
 
 // Backward pass of one 64-sample tile: per-tile partial gradients of every
@@ -503,16 +638,14 @@ __global__ __launch_bounds__(256) void k_curv_fallback(const double *__restrict_
   }
 }
 
-// Learned curvature of the listed mixed cells in one pass (persistent): each
-// wavefront takes tiles of 32 cells on its own -- stencil gather and
-// canonicalisation (one lane per cell), both matrix-core layers in its own LDS
-// slice, the FP32 last layer -- and writes kappa = sign * y with status 8,
-// appending cells with |kappa| < kappa_lo to the fallback list. No block
-// barrier after the weights are staged. The arithmetic and the order of every
-// sum are those of k_mlp_fwd, so y is bit-identical to vofmt_mlp_forward on
-// the same stencils.
-constexpr int FT = 32;     // cells per wavefront tile
-constexpr int FWAVES = 8;  // wavefronts per workgroup
+// Learned curvature of the listed interface cells in one pass (persistent):
+// each wavefront takes tiles of WT cells on its own -- stencil gather and
+// canonicalisation (one lane per cell) into its LDS slice of layer-1
+// operands, then the network tile of the forward pass -- and writes
+// kappa = sign * y with status 8, appending cells with |kappa| < kappa_lo to
+// the fallback list. The network arithmetic is that of the forward kernels,
+// so y is bit-identical to vofmt_mlp_forward on the same stencils.
+constexpr int FWAVES = 12;  // wavefronts per workgroup (LDS: 41 KB of weights + 8 KB per wavefront)
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -521,38 +654,37 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 __global__ __launch_bounds__(64 * FWAVES) void k_curv_fused(
-    const float *__restrict__ P, const uint16_t *__restrict__ w1t_g, const uint16_t *__restrict__ w2t_g,
+    const float *__restrict__ P, const uint4 *__restrict__ w1f_g, const uint4 *__restrict__ w2f_g,
     const double *__restrict__ c, int nx, int ny, int nz, const int32_t *__restrict__ list, int nm, double kappa_lo,
     double *__restrict__ kappa, uint8_t *__restrict__ status, int32_t *__restrict__ hf_list,
     int32_t *__restrict__ hf_count) {
-  __shared__ __attribute__((aligned(16))) uint16_t W1s[NH][XP];
-  __shared__ __attribute__((aligned(16))) uint16_t W2s[NH][HP];
-  __shared__ __attribute__((aligned(16))) uint16_t Xh[FWAVES][FT][XP];
-  __shared__ __attribute__((aligned(16))) uint16_t Xl[FWAVES][FT][XP];
-  __shared__ __attribute__((aligned(16))) uint16_t H1[FWAVES][FT][HP];
-  __shared__ float b1s[NH], b2s[NH], w3s[NH];
-  __shared__ float yb[FWAVES][FT];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int i = tid; i < NH * NIN; i += 64 * FWAVES) W1s[i / NIN][i % NIN] = w1t_g[i];
-  for (int i = tid; i < NH * NH; i += 64 * FWAVES) W2s[i / NH][i % NH] = w2t_g[i];
-  for (int i = tid; i < NH; i += 64 * FWAVES) {
-    b1s[i] = P[OFF_B1 + i];
-    b2s[i] = P[OFF_B2 + i];
-    w3s[i] = P[OFF_W3 + i];
-  }
-  // padding inputs 27..31 stay zero
-  for (int i = lane; i < FT * NIN; i += 64) {
-    Xh[w][i / NIN][i % NIN] = 0;
-    Xl[w][i / NIN][i % NIN] = 0;
+  __shared__ NetLds L;
+  // layer-1 operands of the wavefront's tile: [mt][hi, lo][lane], the layout of net_tile's xfrag
+  __shared__ bf16x8 XF[FWAVES][WMT * 2 * 64];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  stage_net(L, P, w1f_g, w2f_g, tid, 64 * FWAVES);
+  // inputs 27..29 are one (hi part), 30..31 and the rest zero until written
+  {
+    uint16_t *xf = reinterpret_cast<uint16_t *>(XF[w]);
+    for (int i = lane; i < WMT * 2 * 64 * 8; i += 64) {
+      const int e = i & 7, ln = (i >> 3) & 63, hl = (i >> 9) & 1;
+      const int k = 8 * (ln >> 4) + e;
+      xf[i] = (hl == 0 && k >= 27 && k < 30) ? bf16_bits(1.0f) : (uint16_t)0;
+    }
   }
   const float b3 = P[OFF_B3];
   __syncthreads();
-  const int lr = lane & 15, lq = lane >> 4;
-  const int ntiles = (nm + FT - 1) / FT;
+  const int lq = lane >> 4;
+  uint16_t *xf = reinterpret_cast<uint16_t *>(XF[w]);
+  // the lane's cell is sample tile mt = lane / 16, row lane % 16: input k of
+  // it sits in lane group k / 8, element k % 8
+  const int cbase = ((lane >> 4) * 2 * 64 + (lane & 15)) * 8;
+  const int ntiles = (nm + WT - 1) / WT;
   for (int tile = blockIdx.x * FWAVES + w; tile < ntiles; tile += gridDim.x * FWAVES) {
     // ---- canonical stencils, one lane per cell
-    const int q = tile * FT + lane;
-    const bool own = lane < FT && q < nm;
+    const int q = tile * WT + lane;
+    const bool own = q < nm;
     int sg = 1;
     int32_t p = 0;
     if (own) {
@@ -560,88 +692,32 @@ __global__ __launch_bounds__(64 * FWAVES) void k_curv_fused(
       double b[27];
       Canon cn;
       sg = canonical_block(c, p, nx, ny, nz, b, cn);
-      canonical_scatter(b, cn, [&](int e, float v) {
+      canonical_scatter(b, cn, [&](int k, float v) {
         const uint16_t hi = bf16_bits(v);
-        Xh[w][lane][e] = hi;
-        Xl[w][lane][e] = bf16_bits(v - bf16_val(hi));
+        const int o = cbase + (k >> 3) * 128 + (k & 7);
+        xf[o] = hi;
+        xf[o + 64 * 8] = bf16_bits(v - bf16_val(hi));
       });
-    } else if (lane < FT) {
-      for (int e = 0; e < 27; ++e) {
-        Xh[w][lane][e] = 0;
-        Xl[w][lane][e] = 0;
+    } else {
+      for (int k = 0; k < 27; ++k) {
+        const int o = cbase + (k >> 3) * 128 + (k & 7);
+        xf[o] = 0;
+        xf[o + 64 * 8] = 0;
       }
     }
     wave_sync();
-    // ---- layer 1: 32 rows x 128 columns
-#pragma unroll
-    for (int mt = 0; mt < FT / 16; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < NH / 16; ++nt) {
-        const bf16x8 wf = frag(&W1s[16 * nt + lr][8 * lq]);
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mfma(frag(&Xh[w][16 * mt + lr][8 * lq]), wf, acc);
-        acc = mfma(frag(&Xl[w][16 * mt + lr][8 * lq]), wf, acc);
-        const int col = 16 * nt + lr;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float z = acc[r] + b1s[col];
-          H1[w][16 * mt + 4 * lq + r][col] = bf16_bits(z > 0.0f ? z : 0.0f);
-        }
-      }
-    wave_sync();
-    // ---- layer 2 and the layer-3 partial products, summed per 32 columns as k_mlp_fwd does
-    float yq[4][FT / 16][4];
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-#pragma unroll
-      for (int mt = 0; mt < FT / 16; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) yq[g][mt][r] = 0.0f;
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-#pragma unroll
-      for (int jn = 0; jn < 2; ++jn) {
-        const int nt = 2 * g + jn;
-        const int col = 16 * nt + lr;
-#pragma unroll
-        for (int mt = 0; mt < FT / 16; ++mt) {
-          f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int kk = 0; kk < NH; kk += 32)
-            acc = mfma(frag(&H1[w][16 * mt + lr][kk + 8 * lq]), frag(&W2s[16 * nt + lr][kk + 8 * lq]), acc);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const float z = acc[r] + b2s[col];
-            const float h = z > 0.0f ? z : 0.0f;
-            yq[g][mt][r] = yq[g][mt][r] + h * w3s[col];
-          }
-        }
-      }
-    float ysum[FT / 16][4];
-#pragma unroll
-    for (int mt = 0; mt < FT / 16; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        float part[4];
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          float v = yq[g][mt][r];
-          v = row16_sum(v);
-          part[g] = v;
-        }
-        ysum[mt][r] = (((part[0] + part[1]) + part[2]) + part[3]) + b3;
-      }
-    if (lr == 0) {
-#pragma unroll
-      for (int mt = 0; mt < FT / 16; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) yb[w][16 * mt + 4 * lq + r] = ysum[mt][r];
-    }
-    wave_sync();
+    auto xfrag = [&](int mt, bf16x8 &xh, bf16x8 &xl) {
+      xh = XF[w][(2 * mt) * 64 + lane];
+      xl = XF[w][(2 * mt + 1) * 64 + lane];
+    };
+    auto none1 = [](int, int, u32x4) {};
+    auto none2 = [](int, int, f32x4) {};
+    float yv[WMT];
+    net_tile(L, lane, b3, xfrag, none1, none2, yv);
     // ---- kappa, status, fallback list
     bool flag = false;
     if (own) {
-      const double kn = (double)sg * (double)yb[w][lane];
+      const double kn = (double)sg * (double)own_output(yv, lq);
       kappa[p] = kn;
       status[p] = 8;
       flag = fabs(kn) < kappa_lo;
@@ -653,141 +729,7 @@ __global__ __launch_bounds__(64 * FWAVES) void k_curv_fused(
       base = __shfl(base, 0, 64);
       if (flag) hf_list[base + __popcll(mask & ((1ull << lane) - 1))] = p;
     }
-    wave_sync();  // the next tile overwrites this wavefront's LDS slice
-  }
-}
-
-// Network outputs (and optionally activation records) of given inputs
-// x[m][27], by the tile scheme of k_curv_fused: each wavefront takes tiles of
-// FT samples on its own, their inputs read as one contiguous block, no block
-// barrier after the weights are staged. The matrix-core sequences and the
-// order of every sum are those of k_mlp_fwd, so the outputs and records are
-// bit-identical to it.
-__global__ __launch_bounds__(64 * FWAVES) void k_mlp_infer(const float *__restrict__ P,
-                                                           const uint16_t *__restrict__ w1t_g,
-                                                           const uint16_t *__restrict__ w2t_g, int m,
-                                                           const float *__restrict__ x, float *__restrict__ y,
-                                                           uint8_t *__restrict__ acts) {
-  __shared__ __attribute__((aligned(16))) uint16_t W1s[NH][XP];
-  __shared__ __attribute__((aligned(16))) uint16_t W2s[NH][HP];
-  __shared__ __attribute__((aligned(16))) uint16_t Xh[FWAVES][FT][XP];
-  __shared__ __attribute__((aligned(16))) uint16_t Xl[FWAVES][FT][XP];
-  __shared__ __attribute__((aligned(16))) uint16_t H1[FWAVES][FT][HP];
-  __shared__ float b1s[NH], b2s[NH], w3s[NH];
-  __shared__ float yb[FWAVES][FT];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int i = tid; i < NH * NIN; i += 64 * FWAVES) W1s[i / NIN][i % NIN] = w1t_g[i];
-  for (int i = tid; i < NH * NH; i += 64 * FWAVES) W2s[i / NH][i % NH] = w2t_g[i];
-  for (int i = tid; i < NH; i += 64 * FWAVES) {
-    b1s[i] = P[OFF_B1 + i];
-    b2s[i] = P[OFF_B2 + i];
-    w3s[i] = P[OFF_W3 + i];
-  }
-  // padding inputs 27..31 stay zero
-  for (int i = lane; i < FT * NIN; i += 64) {
-    Xh[w][i / NIN][i % NIN] = 0;
-    Xl[w][i / NIN][i % NIN] = 0;
-  }
-  const float b3 = P[OFF_B3];
-  __syncthreads();
-  const int lr = lane & 15, lq = lane >> 4;
-  const int ntiles = (m + FT - 1) / FT;
-  // A tile's inputs are FT x 27 consecutive values, NV per lane; the next
-  // tile's are loaded while the current one is computed.
-  constexpr int NV = (FT * 27 + 63) / 64;
-  float xv[NV];
-  auto load_inputs = [&](int t) {
-    const int s0 = t * FT;
-    const int nvals = ((m - s0 < FT) ? m - s0 : FT) * 27;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      const int i = lane + 64 * q;
-      xv[q] = (i < nvals) ? x[(int64_t)s0 * 27 + i] : 0.0f;
-    }
-  };
-  const int tstride = gridDim.x * FWAVES;
-  if (blockIdx.x * FWAVES + w < ntiles) load_inputs(blockIdx.x * FWAVES + w);
-  for (int tile = blockIdx.x * FWAVES + w; tile < ntiles; tile += tstride) {
-    const int s0 = tile * FT;
-    // ---- the tile's inputs, split into hi + lo
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      const int i = lane + 64 * q;
-      if (i < FT * 27) {
-        const int sr = i / 27, k = i - 27 * sr;
-        const uint16_t hi = bf16_bits(xv[q]);
-        Xh[w][sr][k] = hi;
-        Xl[w][sr][k] = bf16_bits(xv[q] - bf16_val(hi));
-      }
-    }
-    wave_sync();
-    if (tile + tstride < ntiles) load_inputs(tile + tstride);
-    // ---- layer 1: FT rows x 128 columns
-#pragma unroll
-    for (int mt = 0; mt < FT / 16; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < NH / 16; ++nt) {
-        const bf16x8 wf = frag(&W1s[16 * nt + lr][8 * lq]);
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mfma(frag(&Xh[w][16 * mt + lr][8 * lq]), wf, acc);
-        acc = mfma(frag(&Xl[w][16 * mt + lr][8 * lq]), wf, acc);
-        const int col = 16 * nt + lr;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * mt + 4 * lq + r;
-          const float z = acc[r] + b1s[col];
-          const uint16_t h = bf16_bits(z > 0.0f ? z : 0.0f);
-          H1[w][row][col] = h;
-          if (acts && s0 + row < m) act_h1(acts, s0 + row, ACT_BYTES)[col] = h;
-        }
-      }
-    wave_sync();
-    // ---- layer 2 and the layer-3 partial products, summed per 32 columns as k_mlp_fwd does
-    float yq[4][FT / 16][4];
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-#pragma unroll
-      for (int mt = 0; mt < FT / 16; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) yq[g][mt][r] = 0.0f;
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-#pragma unroll
-      for (int jn = 0; jn < 2; ++jn) {
-        const int nt = 2 * g + jn;
-        const int col = 16 * nt + lr;
-#pragma unroll
-        for (int mt = 0; mt < FT / 16; ++mt) {
-          f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int kk = 0; kk < NH; kk += 32)
-            acc = mfma(frag(&H1[w][16 * mt + lr][kk + 8 * lq]), frag(&W2s[16 * nt + lr][kk + 8 * lq]), acc);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = 16 * mt + 4 * lq + r;
-            const float z = acc[r] + b2s[col];
-            const float h = z > 0.0f ? z : 0.0f;
-            if (acts && s0 + row < m) act_h2(acts, s0 + row, ACT_BYTES)[col] = h;
-            yq[g][mt][r] = yq[g][mt][r] + h * w3s[col];
-          }
-        }
-      }
-#pragma unroll
-    for (int mt = 0; mt < FT / 16; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        float part[4];
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          float v = yq[g][mt][r];
-          v = row16_sum(v);
-          part[g] = v;
-        }
-        if (lr == 0) yb[w][16 * mt + 4 * lq + r] = (((part[0] + part[1]) + part[2]) + part[3]) + b3;
-      }
-    wave_sync();
-    if (lane < FT && s0 + lane < m) y[s0 + lane] = yb[w][lane];
-    wave_sync();  // the next tile overwrites this wavefront's LDS slice
+    wave_sync();  // the next tile overwrites this wavefront's operands
   }
 }
 
@@ -796,19 +738,25 @@ __global__ __launch_bounds__(64 * FWAVES) void k_mlp_infer(const float *__restri
 static int mlp_prepare(vofmt_ctx *ctx, const float *params, uint16_t **w, hipStream_t stream) {
   uint16_t *buf = (uint16_t *)scratch(ctx, SLOT_MLP_W, sizeof(uint16_t) * (NIN * NH + 2 * NH * NH));
   if (!buf) return VOFMT_E_NOMEM;
-  w[0] = buf;                       // W1^T
-  w[1] = buf + NIN * NH;            // W2^T
+  w[0] = buf;                       // W1 fragments
+  w[1] = buf + NIN * NH;            // W2 fragments
   w[2] = buf + NIN * NH + NH * NH;  // W2
   hipLaunchKernelGGL(k_mlp_prep, dim3(ceil_div(NH * NH, 256)), dim3(256), 0, stream, params, w[0], w[1], w[2]);
   return hip_check(ctx, hipGetLastError(), "k_mlp_prep");
 }
 
-static int fwd_grid(vofmt_ctx *ctx, int ntiles) {
-  int cus = 0;
+// Workgroups of a persistent kernel: as many as fit the device at once, at
+// most one per `waves` work tiles.
+template <class K>
+static int persistent_grid(vofmt_ctx *ctx, K kernel, int waves, int64_t tiles) {
+  int cus = 0, per_cu = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
     cus = 256;
-  const int g = 2 * cus;  // two 70 KB-LDS workgroups fit one compute unit
-  return ntiles < g ? ntiles : g;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64 * waves, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  const int64_t need = (tiles + waves - 1) / waves;
+  const int64_t g = (int64_t)cus * per_cu;
+  return (int)(need < g ? need : g);
 }
 
 extern "C" int vofmt_mlp_forward(vofmt_ctx *ctx, const float *params, int32_t m, const float *x, float *y,
@@ -821,13 +769,14 @@ extern "C" int vofmt_mlp_forward(vofmt_ctx *ctx, const float *params, int32_t m,
   uint16_t *w[3];
   int rc = mlp_prepare(ctx, params, w, stream);
   if (rc) return rc;
-  int cus = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
-    cus = 256;
-  const int ftiles = (m + FT - 1) / FT;
-  const int fgrid = ftiles < cus * FWAVES ? (ftiles + FWAVES - 1) / FWAVES : cus;
+  const int tiles = (m + WT - 1) / WT;
   const int rec = prof_begin(ctx, "k_mlp_infer", stream);
-  hipLaunchKernelGGL(k_mlp_infer, dim3(fgrid), dim3(64 * FWAVES), 0, stream, params, w[0], w[1], m, x, y, acts);
+  if (acts)
+    hipLaunchKernelGGL(k_mlp_infer<true>, dim3(persistent_grid(ctx, k_mlp_infer<true>, IWAVES, tiles)),
+                       dim3(64 * IWAVES), 0, stream, params, (const uint4 *)w[0], (const uint4 *)w[1], m, x, y, acts);
+  else
+    hipLaunchKernelGGL(k_mlp_infer<false>, dim3(persistent_grid(ctx, k_mlp_infer<false>, IWAVES, tiles)),
+                       dim3(64 * IWAVES), 0, stream, params, (const uint4 *)w[0], (const uint4 *)w[1], m, x, y, acts);
   prof_end(ctx, rec, stream);
   return hip_check(ctx, hipGetLastError(), "k_mlp_infer");
 }
@@ -851,8 +800,8 @@ extern "C" int vofmt_mlp_train_step(vofmt_ctx *ctx, float *params, float *adam_m
   float *loss_part = gbuf + m;
   float *loss_out = gbuf + m + ntiles;
   int rec = prof_begin(ctx, "k_mlp_fwd(train)", stream);
-  hipLaunchKernelGGL(k_mlp_fwd, dim3(fwd_grid(ctx, ntiles)), dim3(256), 0, stream, params, w[0], w[1], m, x,
-                     (float *)nullptr, acts, y_target, gbuf, loss_part);
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(persistent_grid(ctx, k_mlp_fwd, IWAVES, ntiles)), dim3(64 * IWAVES), 0, stream,
+                     params, (const uint4 *)w[0], (const uint4 *)w[1], m, x, acts, y_target, gbuf, loss_part);
   prof_end(ctx, rec, stream);
   rec = prof_begin(ctx, "k_mlp_bwd", stream);
   hipLaunchKernelGGL(k_mlp_bwd, dim3(ntiles), dim3(256), 0, stream, params, w[2], m, x, acts, gbuf, partial, trace);
@@ -936,13 +885,10 @@ extern "C" int vofmt_curvature_mlp(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32
   uint16_t *w[3];
   int rc = mlp_prepare(ctx, params, w, stream);
   if (rc) return rc;
-  int cus = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
-    cus = 256;
-  const int ftiles = (nm + FT - 1) / FT;
-  const int fgrid = ftiles < cus * FWAVES ? (ftiles + FWAVES - 1) / FWAVES : cus;
+  const int fgrid = persistent_grid(ctx, k_curv_fused, FWAVES, (nm + WT - 1) / WT);
   rec = prof_begin(ctx, "k_curv_fused", stream);
-  hipLaunchKernelGGL(k_curv_fused, dim3(fgrid), dim3(64 * FWAVES), 0, stream, params, w[0], w[1], c, nx, ny, nz, list,
+  hipLaunchKernelGGL(k_curv_fused, dim3(fgrid), dim3(64 * FWAVES), 0, stream, params, (const uint4 *)w[0],
+                     (const uint4 *)w[1], c, nx, ny, nz, list,
                      nm, kappa_lo, kappa, status, hf_list, hf_count);
   prof_end(ctx, rec, stream);
   rec = prof_begin(ctx, "k_curv_fallback", stream);
