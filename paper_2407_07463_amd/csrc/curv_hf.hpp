@@ -20,22 +20,37 @@
 
 namespace curv {
 
+// i + k for |k| <= 3, taken periodically into [0, n): one conditional add
+// for n >= 3, the general rule below that.
+__device__ __forceinline__ int wrap3(int i, int n) {
+  if (n < 3) return wrap_any(i, n);
+  return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
 // kappa*Delta and the status (1..3 valid on the 1st..3rd axis tried, 4 no
-// valid axis) of the mixed cell p of c.
+// valid axis) of the mixed cell p (below 2^31) of c.
 // Coordinates and axis choices are kept in scalars (no arrays indexed at run
-// time), so the function stays in registers.
+// time), so the function stays in registers. The three middle cells of every
+// column come from the 3x3x3 block; the other 36 cells of an axis are loaded
+// at once, then the columns are checked.
 __device__ __forceinline__ void hf_cell(const double *__restrict__ c, int64_t p, int nx, int ny, int nz,
                                         double &kappa_out, uint8_t &status_out) {
-  const int x0 = (int)(p % nx), x1 = (int)((p / nx) % ny), x2 = (int)(p / ((int64_t)nx * ny));
+  const uint32_t row = (uint32_t)p / (uint32_t)nx;
+  const int x0 = (int)((uint32_t)p - row * (uint32_t)nx);
+  const int x2 = (int)(row / (uint32_t)ny);
+  const int x1 = (int)(row - (uint32_t)x2 * (uint32_t)ny);
   double b[27];
+  {
+    const int xs[3] = {wrap_dec(x0, nx), x0, wrap_inc(x0, nx)};
+    const int ys[3] = {wrap_dec(x1, ny), x1, wrap_inc(x1, ny)};
+    const int zs[3] = {wrap_dec(x2, nz), x2, wrap_inc(x2, nz)};
 #pragma unroll
-  for (int az = -1; az <= 1; ++az)
+    for (int az = 0; az < 3; ++az)
 #pragma unroll
-    for (int ay = -1; ay <= 1; ++ay)
+      for (int ay = 0; ay < 3; ++ay)
 #pragma unroll
-      for (int ax = -1; ax <= 1; ++ax)
-        b[(ax + 1) + 3 * (ay + 1) + 9 * (az + 1)] =
-            c[((int64_t)wrap_any(x2 + az, nz) * ny + wrap_any(x1 + ay, ny)) * nx + wrap_any(x0 + ax, nx)];
+        for (int ax = 0; ax < 3; ++ax) b[ax + 3 * ay + 9 * az] = c[(int64_t)(zs[az] * ny + ys[ay]) * nx + xs[ax]];
+  }
   double m0, m1, m2;
   plic::myc_normal(b, m0, m1, m2);
   auto mv = [&](int a) { return a == 0 ? m0 : (a == 1 ? m1 : m2); };
@@ -53,38 +68,48 @@ __device__ __forceinline__ void hf_cell(const double *__restrict__ c, int64_t p,
   order2(o1, o2);
   double result = __builtin_nan("");
   uint8_t st = 4;
-  bool done = false;
 #pragma unroll 1
-  for (int at = 0; at < 3 && !done; ++at) {
+  for (int at = 0; at < 3; ++at) {
     const int d = (at == 0) ? o0 : ((at == 1) ? o1 : o2);
     const int t1 = (d == 0) ? 1 : 0;
     const int t2 = (d == 2) ? 1 : 2;
     const bool up = mv(d) >= 0.0;
+    // the cell's coordinates along d, t1, t2 and the strides of those axes
+    auto coord = [&](int a) { return a == 0 ? x0 : (a == 1 ? x1 : x2); };
+    auto extent = [&](int a) { return a == 0 ? nx : (a == 1 ? ny : nz); };
+    auto stride = [&](int a) { return a == 0 ? (int64_t)1 : (a == 1 ? (int64_t)nx : (int64_t)nx * ny); };
+    const int cd = coord(d), ed = extent(d);
+    const int64_t sd = stride(d), s1 = stride(t1), s2 = stride(t2);
+    const int c1 = coord(t1), e1 = extent(t1), c2 = coord(t2), e2 = extent(t2);
+    // rows of the columns along d at offsets -3, -2, 2, 3 (the middle three are in b)
+    const int64_t r_m3 = (int64_t)wrap3(cd - 3, ed) * sd, r_m2 = (int64_t)wrap3(cd - 2, ed) * sd;
+    const int64_t r_p2 = (int64_t)wrap3(cd + 2, ed) * sd, r_p3 = (int64_t)wrap3(cd + 3, ed) * sd;
     double H[3][3];
     bool ok = true;
 #pragma unroll
     for (int v = -1; v <= 1; ++v)
 #pragma unroll
       for (int u = -1; u <= 1; ++u) {
-        double h = 0.0, first = 0.0, last = 0.0;
-        if (ok) {
-          // column through the cell offset by u along t1 and v along t2
-          const int y0 = wrap_any(x0 + (t1 == 0 ? u : 0) + (t2 == 0 ? v : 0), nx);
-          const int y1 = wrap_any(x1 + (t1 == 1 ? u : 0) + (t2 == 1 ? v : 0), ny);
-          const int y2 = wrap_any(x2 + (t1 == 2 ? u : 0) + (t2 == 2 ? v : 0), nz);
-          for (int e = -3; e <= 3; ++e) {
-            const int z0 = (d == 0) ? wrap_any(y0 + e, nx) : y0;
-            const int z1 = (d == 1) ? wrap_any(y1 + e, ny) : y1;
-            const int z2 = (d == 2) ? wrap_any(y2 + e, nz) : y2;
-            const double v_ = c[((int64_t)z2 * ny + z1) * nx + z0];
-            if (e == -3) first = v_;
-            if (e == 3) last = v_;
-            h += v_;
-          }
-          const double full_end = up ? first : last;
-          const double empty_end = up ? last : first;
-          if (!(full_end >= 1.0 - 1e-6 && empty_end <= 1e-6)) ok = false;
-        }
+        const int64_t base = (int64_t)wrap3(c1 + u, e1) * s1 + (int64_t)wrap3(c2 + v, e2) * s2;
+        const double vm3 = c[base + r_m3], vm2 = c[base + r_m2], vp2 = c[base + r_p2], vp3 = c[base + r_p3];
+        // block entry at offset e along d, u along t1, v along t2
+        auto mid = [&](int e) {
+          const double a0 = b[(e + 1) + 3 * (u + 1) + 9 * (v + 1)];  // d = 0: t1 = y, t2 = z
+          const double a1 = b[(u + 1) + 3 * (e + 1) + 9 * (v + 1)];  // d = 1: t1 = x, t2 = z
+          const double a2 = b[(u + 1) + 3 * (v + 1) + 9 * (e + 1)];  // d = 2: t1 = x, t2 = y
+          return d == 0 ? a0 : (d == 1 ? a1 : a2);
+        };
+        double h = 0.0;
+        h += vm3;
+        h += vm2;
+        h += mid(-1);
+        h += mid(0);
+        h += mid(1);
+        h += vp2;
+        h += vp3;
+        const double full_end = up ? vm3 : vp3;
+        const double empty_end = up ? vp3 : vm3;
+        ok = ok && (full_end >= 1.0 - 1e-6 && empty_end <= 1e-6);
         H[u + 1][v + 1] = h;
       }
     if (ok) {
@@ -97,7 +122,7 @@ __device__ __forceinline__ void hf_cell(const double *__restrict__ c, int64_t p,
       const double den = (1.0 + Hx * Hx) + Hy * Hy;
       result = -num / (den * sqrt(den));
       st = (uint8_t)(1 + at);
-      done = true;
+      break;
     }
   }
   kappa_out = result;

@@ -537,9 +537,13 @@ struct Canon {
   int d0, d1, d2;  // and its direction (+1 or -1)
 };
 
-__device__ __forceinline__ void load_block(const double *__restrict__ c, int64_t p, int nx, int ny, int nz,
+// The 3x3x3 block around cell p (below 2^31, so 32-bit index arithmetic).
+__device__ __forceinline__ void load_block(const double *__restrict__ c, uint32_t p, int nx, int ny, int nz,
                                            double *b) {
-  const int i = (int)(p % nx), j = (int)((p / nx) % ny), k = (int)(p / ((int64_t)nx * ny));
+  const uint32_t row = p / (uint32_t)nx;
+  const int i = (int)(p - row * (uint32_t)nx);
+  const int k = (int)(row / (uint32_t)ny);
+  const int j = (int)(row - (uint32_t)k * (uint32_t)ny);
   const int xs[3] = {wrap_dec(i, nx), i, wrap_inc(i, nx)};
   const int ys[3] = {wrap_dec(j, ny), j, wrap_inc(j, ny)};
   const int zs[3] = {wrap_dec(k, nz), k, wrap_inc(k, nz)};
@@ -548,14 +552,19 @@ __device__ __forceinline__ void load_block(const double *__restrict__ c, int64_t
 #pragma unroll
     for (int ay = 0; ay < 3; ++ay)
 #pragma unroll
-      for (int ax = 0; ax < 3; ++ax) b[ax + 3 * ay + 9 * az] = c[((int64_t)zs[az] * ny + ys[ay]) * nx + xs[ax]];
+      for (int ax = 0; ax < 3; ++ax) b[ax + 3 * ay + 9 * az] = c[(int64_t)(zs[az] * ny + ys[ay]) * nx + xs[ax]];
 }
 
-__device__ __forceinline__ int canonical_of_block(double *b, Canon &cn) {
+// The block (complemented when its centre exceeds 1/2) is handed on as
+// FP32 values xf; the FP64 block itself is only needed for the normal.
+__device__ __forceinline__ int canonical_of_block(double *b, float *xf, Canon &cn) {
   const int sign = (b[13] > 0.5) ? -1 : 1;
-  if (sign < 0) {
+  // the complement 1 - b as one fused multiply-add (the same rounding as the subtraction)
+  const double sf = sign < 0 ? -1.0 : 1.0, sa = sign < 0 ? 1.0 : 0.0;
 #pragma unroll
-    for (int q = 0; q < 27; ++q) b[q] = 1.0 - b[q];
+  for (int q = 0; q < 27; ++q) {
+    b[q] = fma(sf, b[q], sa);
+    xf[q] = (float)b[q];
   }
   double m0, m1, m2;
   plic::myc_normal(b, m0, m1, m2);
@@ -580,26 +589,28 @@ __device__ __forceinline__ int canonical_of_block(double *b, Canon &cn) {
   return sign;
 }
 
-__device__ __forceinline__ int canonical_block(const double *__restrict__ c, int64_t p, int nx, int ny, int nz,
-                                               double *b, Canon &cn) {
+__device__ __forceinline__ int canonical_block(const double *__restrict__ c, uint32_t p, int nx, int ny, int nz,
+                                               float *xf, Canon &cn) {
+  double b[27];
   load_block(c, p, nx, ny, nz, b);
-  return canonical_of_block(b, cn);
+  return canonical_of_block(b, xf, cn);
 }
 
 // Entry a = (a0, a1, a2) of the block (offsets -1..1 along x, y, z) lands at
-// canonical offsets q_k = d_k * a[o_k]: index (q0+1) + 3(q1+1) + 9(q2+1).
+// canonical offsets q_k = d_k * a[o_k]: index (q0+1) + 3(q1+1) + 9(q2+1)
+// = 13 + a0 S0 + a1 S1 + a2 S2, where source axis o_k has the stride
+// S[o_k] = d_k 3^k.
 template <class Put>
-__device__ __forceinline__ void canonical_scatter(const double *b, const Canon &cn, Put put) {
+__device__ __forceinline__ void canonical_scatter(const float *xf, const Canon &cn, Put put) {
+  auto stride = [&](int j) { return cn.o0 == j ? cn.d0 : (cn.o1 == j ? 3 * cn.d1 : 9 * cn.d2); };
+  const int S0 = stride(0), S1 = stride(1), S2 = stride(2);
 #pragma unroll
   for (int a2 = -1; a2 <= 1; ++a2)
 #pragma unroll
     for (int a1 = -1; a1 <= 1; ++a1)
 #pragma unroll
-      for (int a0 = -1; a0 <= 1; ++a0) {
-        auto along = [&](int o) { return o == 0 ? a0 : (o == 1 ? a1 : a2); };
-        const int q0 = cn.d0 * along(cn.o0), q1 = cn.d1 * along(cn.o1), q2 = cn.d2 * along(cn.o2);
-        put((q0 + 1) + 3 * (q1 + 1) + 9 * (q2 + 1), (float)b[(a0 + 1) + 3 * (a1 + 1) + 9 * (a2 + 1)]);
-      }
+      for (int a0 = -1; a0 <= 1; ++a0)
+        put(13 + a0 * S0 + a1 * S1 + a2 * S2, xf[(a0 + 1) + 3 * (a1 + 1) + 9 * (a2 + 1)]);
 }
 
 // Canonical stencils of the listed cells: xs[q], sign[q] for cell list[q].
@@ -609,23 +620,28 @@ __global__ __launch_bounds__(256) void k_stencil_list(const double *__restrict__
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   const int64_t p = list[q];
-  double b[27];
+  float xf[27];
   Canon cn;
-  const int sg = canonical_block(c, p, nx, ny, nz, b, cn);
+  const int sg = canonical_block(c, (uint32_t)p, nx, ny, nz, xf, cn);
   float *row = xs + (int64_t)q * 27;
-  canonical_scatter(b, cn, [&](int e, float v) { row[e] = v; });
+  canonical_scatter(xf, cn, [&](int e, float v) { row[e] = v; });
   sgn[q] = (int8_t)sg;
 }
 
 // Height functions on the fallback cells: their value where valid (status
-// 1..3), else the network's value stays (status 4 + 8).
+// 1..3), else the network's value stays (status 4 + 8). The list is in
+// regions of region_cells entries, region g holding counts[g] cells; `sub`
+// workgroups share a region.
 __global__ __launch_bounds__(256) void k_curv_fallback(const double *__restrict__ c, int nx, int ny, int nz,
                                                        const int32_t *__restrict__ hf_list,
-                                                       const int32_t *__restrict__ hf_count,
-                                                       double *__restrict__ kappa, uint8_t *__restrict__ status) {
-  const int n = *hf_count;
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
-    const int64_t p = hf_list[q];
+                                                       const int32_t *__restrict__ counts, int64_t region_cells,
+                                                       int sub, double *__restrict__ kappa,
+                                                       uint8_t *__restrict__ status) {
+  const int g = blockIdx.x / sub, part = blockIdx.x % sub;
+  const int n = counts[g];
+  const int32_t *lst = hf_list + (int64_t)g * region_cells;
+  for (int q = part * blockDim.x + threadIdx.x; q < n; q += sub * blockDim.x) {
+    const int64_t p = lst[q];
     double k;
     uint8_t st;
     curv::hf_cell(c, p, nx, ny, nz, k, st);
@@ -645,7 +661,7 @@ __global__ __launch_bounds__(256) void k_curv_fallback(const double *__restrict_
 // kappa = sign * y with status 8, appending cells with |kappa| < kappa_lo to
 // the fallback list. The network arithmetic is that of the forward kernels,
 // so y is bit-identical to vofmt_mlp_forward on the same stencils.
-constexpr int FWAVES = 12;  // wavefronts per workgroup (LDS: 41 KB of weights + 8 KB per wavefront)
+constexpr int FWAVES = 12;  // wavefronts per workgroup (LDS: 41 KB of weights + 9 KB per wavefront)
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -653,62 +669,57 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+constexpr int XSP = 36;  // row pitch (floats) of the stencil rows in LDS: 16-byte rows, conflict-free reads
+
 __global__ __launch_bounds__(64 * FWAVES) void k_curv_fused(
     const float *__restrict__ P, const uint4 *__restrict__ w1f_g, const uint4 *__restrict__ w2f_g,
     const double *__restrict__ c, int nx, int ny, int nz, const int32_t *__restrict__ list, int nm, double kappa_lo,
     double *__restrict__ kappa, uint8_t *__restrict__ status, int32_t *__restrict__ hf_list,
-    int32_t *__restrict__ hf_count) {
+    int32_t *__restrict__ hf_counts, int tiles_per_group) {
   __shared__ NetLds L;
-  // layer-1 operands of the wavefront's tile: [mt][hi, lo][lane], the layout of net_tile's xfrag
-  __shared__ bf16x8 XF[FWAVES][WMT * 2 * 64];
+  __shared__ int nflag;  // cells of the workgroup's tiles appended to its region of the fallback list
+  // the canonical stencils of the wavefront's tile as FP32 rows [cell][input]
+  __shared__ __attribute__((aligned(16))) float XS[FWAVES][WT][XSP];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   stage_net(L, P, w1f_g, w2f_g, tid, 64 * FWAVES);
-  // inputs 27..29 are one (hi part), 30..31 and the rest zero until written
-  {
-    uint16_t *xf = reinterpret_cast<uint16_t *>(XF[w]);
-    for (int i = lane; i < WMT * 2 * 64 * 8; i += 64) {
-      const int e = i & 7, ln = (i >> 3) & 63, hl = (i >> 9) & 1;
-      const int k = 8 * (ln >> 4) + e;
-      xf[i] = (hl == 0 && k >= 27 && k < 30) ? bf16_bits(1.0f) : (uint16_t)0;
-    }
+  // inputs 27..29 are one, the rest of the padding zero (rows are written from 0 to 26 only)
+  for (int i = lane; i < WT * XSP; i += 64) {
+    const int col = i % XSP;
+    XS[w][i / XSP][col] = (col >= 27 && col < 30) ? 1.0f : 0.0f;
   }
   const float b3 = P[OFF_B3];
+  if (tid == 0) nflag = 0;
   __syncthreads();
-  const int lq = lane >> 4;
-  uint16_t *xf = reinterpret_cast<uint16_t *>(XF[w]);
-  // the lane's cell is sample tile mt = lane / 16, row lane % 16: input k of
-  // it sits in lane group k / 8, element k % 8
-  const int cbase = ((lane >> 4) * 2 * 64 + (lane & 15)) * 8;
+  const int lr = lane & 15, lq = lane >> 4;
+  float *xrow = XS[w][lane];
+  // the workgroup's tiles: one contiguous range, whose cells bound its region of the list
   const int ntiles = (nm + WT - 1) / WT;
-  for (int tile = blockIdx.x * FWAVES + w; tile < ntiles; tile += gridDim.x * FWAVES) {
-    // ---- canonical stencils, one lane per cell
+  const int t0 = blockIdx.x * tiles_per_group;
+  const int t1 = t0 + tiles_per_group < ntiles ? t0 + tiles_per_group : ntiles;
+  int32_t *region = hf_list + (int64_t)t0 * WT;
+  for (int tile = t0 + w; tile < t1; tile += FWAVES) {
+    // ---- canonical stencils, one lane per cell, into the lane's row
     const int q = tile * WT + lane;
     const bool own = q < nm;
     int sg = 1;
     int32_t p = 0;
     if (own) {
       p = list[q];
-      double b[27];
+      float xf[27];
       Canon cn;
-      sg = canonical_block(c, p, nx, ny, nz, b, cn);
-      canonical_scatter(b, cn, [&](int k, float v) {
-        const uint16_t hi = bf16_bits(v);
-        const int o = cbase + (k >> 3) * 128 + (k & 7);
-        xf[o] = hi;
-        xf[o + 64 * 8] = bf16_bits(v - bf16_val(hi));
-      });
+      sg = canonical_block(c, (uint32_t)p, nx, ny, nz, xf, cn);
+      canonical_scatter(xf, cn, [&](int k, float v) { xrow[k] = v; });
     } else {
-      for (int k = 0; k < 27; ++k) {
-        const int o = cbase + (k >> 3) * 128 + (k & 7);
-        xf[o] = 0;
-        xf[o + 64 * 8] = 0;
-      }
+      for (int k = 0; k < 27; ++k) xrow[k] = 0.0f;
     }
     wave_sync();
+    // ---- the network: inputs 8lq .. 8lq+7 of cell 16mt + lr, split into hi + lo
     auto xfrag = [&](int mt, bf16x8 &xh, bf16x8 &xl) {
-      xh = XF[w][(2 * mt) * 64 + lane];
-      xl = XF[w][(2 * mt + 1) * 64 + lane];
+      const f32x4 *src = reinterpret_cast<const f32x4 *>(&XS[w][16 * mt + lr][8 * lq]);
+      const f32x4 u = src[0], t = src[1];
+      const float v[8] = {u[0], u[1], u[2], u[3], t[0], t[1], t[2], t[3]};
+      split_frag(v, xh, xl);
     };
     auto none1 = [](int, int, u32x4) {};
     auto none2 = [](int, int, f32x4) {};
@@ -725,12 +736,14 @@ __global__ __launch_bounds__(64 * FWAVES) void k_curv_fused(
     const uint64_t mask = __ballot(flag);
     if (mask) {
       int base = 0;
-      if (lane == 0) base = atomicAdd(hf_count, (int)__popcll(mask));
+      if (lane == 0) base = atomicAdd(&nflag, (int)__popcll(mask));
       base = __shfl(base, 0, 64);
-      if (flag) hf_list[base + __popcll(mask & ((1ull << lane) - 1))] = p;
+      if (flag) region[base + __popcll(mask & ((1ull << lane) - 1))] = p;
     }
-    wave_sync();  // the next tile overwrites this wavefront's operands
+    wave_sync();  // the next tile overwrites this wavefront's rows
   }
+  __syncthreads();
+  if (tid == 0) hf_counts[blockIdx.x] = nflag;
 }
 
 }  // namespace
@@ -866,11 +879,11 @@ extern "C" int vofmt_curvature_mlp(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32
   const int64_t lt = compact::list_tiles(n3);
   int32_t *list = (int32_t *)scratch(ctx, SLOT_CURV_LIST, sizeof(int32_t) * (size_t)n3);
   int32_t *bc = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * (size_t)ceil_div(n3, compact::kBlock));
-  int32_t *tot = (int32_t *)scratch(ctx, SLOT_CURV_COUNT, sizeof(int32_t) * (size_t)(lt + 2));
+  const int fgrid_max = persistent_grid(ctx, k_curv_fused, FWAVES, INT32_MAX);
+  int32_t *tot = (int32_t *)scratch(ctx, SLOT_CURV_COUNT, sizeof(int32_t) * (size_t)(lt + 1 + fgrid_max));
   int32_t *hc = (int32_t *)host_scratch(ctx, sizeof(int32_t) * 2);
   if (!list || !bc || !tot || !hc) return VOFMT_E_NOMEM;
-  int32_t *hf_count = tot + lt + 1;
-  VOFMT_HIP(ctx, hipMemsetAsync(hf_count, 0, sizeof(int32_t), stream));
+  int32_t *hf_counts = tot + lt + 1;  // fallback cells per workgroup of the fused kernel
   int rec = prof_begin(ctx, "mixed_list", stream);
   compact::launch_ordered_list(c, n3, bc, tot, list, kappa, status, stream);
   prof_end(ctx, rec, stream);
@@ -885,15 +898,20 @@ extern "C" int vofmt_curvature_mlp(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32
   uint16_t *w[3];
   int rc = mlp_prepare(ctx, params, w, stream);
   if (rc) return rc;
-  const int fgrid = persistent_grid(ctx, k_curv_fused, FWAVES, (nm + WT - 1) / WT);
+  // every workgroup takes an equal contiguous range of tiles
+  const int ntiles = (nm + WT - 1) / WT;
+  int fgrid = ntiles < fgrid_max ? ntiles : fgrid_max;
+  const int per_group = (ntiles + fgrid - 1) / fgrid;
+  fgrid = (ntiles + per_group - 1) / per_group;
   rec = prof_begin(ctx, "k_curv_fused", stream);
   hipLaunchKernelGGL(k_curv_fused, dim3(fgrid), dim3(64 * FWAVES), 0, stream, params, (const uint4 *)w[0],
-                     (const uint4 *)w[1], c, nx, ny, nz, list,
-                     nm, kappa_lo, kappa, status, hf_list, hf_count);
+                     (const uint4 *)w[1], c, nx, ny, nz, list, nm, kappa_lo, kappa, status, hf_list, hf_counts,
+                     per_group);
   prof_end(ctx, rec, stream);
   rec = prof_begin(ctx, "k_curv_fallback", stream);
-  hipLaunchKernelGGL(k_curv_fallback, dim3(list_grid(ctx)), dim3(256), 0, stream, c, nx, ny, nz, hf_list, hf_count,
-                     kappa, status);
+  constexpr int kSub = 8;  // workgroups per region
+  hipLaunchKernelGGL(k_curv_fallback, dim3(fgrid * kSub), dim3(256), 0, stream, c, nx, ny, nz, hf_list, hf_counts,
+                     (int64_t)per_group * WT, kSub, kappa, status);
   prof_end(ctx, rec, stream);
   return hip_check(ctx, hipGetLastError(), "curvature_mlp kernels");
 }
