@@ -403,6 +403,8 @@ def _setup_mlp(L):
     L.orc_bf16.restype = ctypes.c_float
     L.orc_canonical_stencil.argtypes = [vp, vp]
     L.orc_canonical_stencil.restype = i32
+    L.orc_two_interfaces.argtypes = [vp]
+    L.orc_two_interfaces.restype = i32
     L.orc_mlp_forward.argtypes = [vp, i32, vp, i32, vp, vp]
     L.orc_mlp_forward.restype = None
     L.orc_mlp_grad.argtypes = [vp, i32, vp, vp, i32, vp]
@@ -436,6 +438,14 @@ def canonical_stencil(block) -> tuple[np.ndarray, int]:
     out = np.zeros(27, dtype=np.float32)
     s = lib().orc_canonical_stencil(b.ctypes.data, out.ctypes.data)
     return out, int(s)
+
+
+def two_interfaces(block) -> bool:
+    """Whether a 3x3x3 block b[az][ay][ax] holds two interfaces: MYC's
+    centred-columns orientation along the first height-function axis disagrees
+    with the height functions' orientation there (the second fallback trigger)."""
+    b = _f64(block).reshape(27)
+    return bool(lib().orc_two_interfaces(b.ctypes.data))
 
 
 def mlp_forward(params, x, exact: bool = False):

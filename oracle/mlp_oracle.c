@@ -40,6 +40,7 @@
 #include <string.h>
 
 int orc_myc_normal(const double *b, double *m_out);
+int orc_myc_normal_sigma(const double *b, double *m_out, double *sigma_out);
 
 #define NIN 32
 #define NH 128
@@ -109,6 +110,26 @@ int orc_canonical_stencil(const double *b, float *x27) {
         x27[(q0 + 1) + 3 * (q1 + 1) + 9 * (q2 + 1)] = (float)bc[(a[0] + 1) + 3 * (a[1] + 1) + 9 * (a[2] + 1)];
       }
   return sign;
+}
+
+/* Whether the 3x3x3 block b holds two interfaces, the second trigger of the
+ * height-function fallback: on the block as canonicalised (complemented when
+ * its centre exceeds 1/2), the centred-columns orientation sigma of MYC along
+ * the first axis the height functions try -- the axis of the largest |m_d|,
+ * ties to the lower axis -- disagrees with the orientation the height
+ * functions take there (full end on the low side when m_d >= 0). One planar
+ * interface gives the same side both ways; a second interface in the block
+ * can make the column sums and the normal point to opposite sides. */
+int orc_two_interfaces(const double *b) {
+  const int flip = b[13] > 0.5;
+  double bc[27];
+  for (int q = 0; q < 27; ++q) bc[q] = flip ? 1.0 - b[q] : b[q];
+  double m[3], sg[3];
+  orc_myc_normal_sigma(bc, m, sg);
+  int d = 0;
+  for (int k = 1; k < 3; ++k)
+    if (fabs(m[k]) > fabs(m[d])) d = k;
+  return (sg[d] > 0.0) != (m[d] >= 0.0);
 }
 
 /* Forward pass for one sample. x: 27 FP32. Outputs y and, if wanted, the

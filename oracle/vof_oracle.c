@@ -168,7 +168,14 @@ static inline double blk_axis(const double *b, int d, int e, int u, int v) {
  * their rounding noise. The plane constant still matches the cell's own c,
  * so volume is conserved as before. */
 #define ORC_RESIDUE 1e-12
-int orc_myc_normal(const double *b_in, double *m_out) {
+int orc_myc_normal_sigma(const double *b_in, double *m_out, double *sigma_out);
+
+int orc_myc_normal(const double *b_in, double *m_out) { return orc_myc_normal_sigma(b_in, m_out, NULL); }
+
+/* The MYC normal as above; sigma_out (nullable) receives the centred-columns
+ * orientation of every axis d: +1 when the column sums on the low side of the
+ * block (offset -1 along d) are at least those on the high side, else -1. */
+int orc_myc_normal_sigma(const double *b_in, double *m_out, double *sigma_out) {
   double b[27];
   for (int q = 0; q < 27; ++q) {
     double v = b_in[q];
@@ -224,6 +231,8 @@ int orc_myc_normal(const double *b_in, double *m_out) {
     use_cs = (qcs <= qy);
   }
   for (int i = 0; i < 3; ++i) m_out[i] = use_cs ? cs[i] : my[i];
+  if (sigma_out)
+    for (int d = 0; d < 3; ++d) sigma_out[d] = sg[d];
   return use_cs;
 }
 
