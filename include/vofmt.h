@@ -400,8 +400,12 @@ int vofmt_mlp_stencils(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, const
  * Curvature of one tracer by the network with height functions as the
  * fallback: for every interface cell (c more than 1e-12 inside (0, 1))
  * kappa = sign * MLP(canonical stencil); where
- * |kappa| < kappa_lo (radii the 3x3x3 stencil cannot resolve) the height
- * function is evaluated and replaces it when valid. status: 0 not a mixed
+ * |kappa| < kappa_lo (radii the 3x3x3 stencil cannot resolve) or the
+ * stencil holds two interfaces (on the canonicalised block, MYC's
+ * centred-columns orientation along the axis of the largest |m_d| disagrees
+ * with the height functions' orientation there, full end low when
+ * m_d >= 0), the height function is evaluated and replaces it when valid.
+ * status: 0 not a mixed
  * cell (kappa NaN); 8 the network's value; 1..3 the height function's value
  * (valid on the 1st..3rd axis tried); 12 the network's value where the
  * height function was tried and had no valid axis.

@@ -535,6 +535,7 @@ __global__ __launch_bounds__(256) void k_mlp_adam(float *__restrict__ P, float *
 struct Canon {
   int o0, o1, o2;  // source axis of canonical axis 0, 1, 2
   int d0, d1, d2;  // and its direction (+1 or -1)
+  bool two;        // the block holds two interfaces (see canonical_of_block)
 };
 
 // The 3x3x3 block around cell p (below 2^31, so 32-bit index arithmetic).
@@ -567,8 +568,17 @@ __device__ __forceinline__ int canonical_of_block(double *b, float *xf, Canon &c
     xf[q] = (float)b[q];
   }
   double m0, m1, m2;
-  plic::myc_normal(b, m0, m1, m2);
+  int sigma_low;
+  plic::myc_normal_sigma(b, m0, m1, m2, sigma_low);
   auto mv = [&](int a) { return a == 0 ? m0 : (a == 1 ? m1 : m2); };
+  // two interfaces: along the first height-function axis (largest |m_d|, ties
+  // to the lower axis) the centred-columns orientation disagrees with the
+  // height functions' (full end low when m_d >= 0)
+  {
+    const double a0 = fabs(m0), a1 = fabs(m1), a2 = fabs(m2);
+    const int ds = (a0 >= a1 && a0 >= a2) ? 0 : (a1 >= a2 ? 1 : 2);
+    cn.two = (((sigma_low >> ds) & 1) != 0) != (mv(ds) >= 0.0);
+  }
   int o0 = 0, o1 = 1, o2 = 2;
   auto order2 = [&](int &a, int &bb) {  // increasing |m|, ties to the lower axis
     if (fabs(mv(bb)) < fabs(mv(a)) || (fabs(mv(bb)) == fabs(mv(a)) && bb < a)) {
@@ -658,8 +668,8 @@ __global__ __launch_bounds__(256) void k_curv_fallback(const double *__restrict_
 // each wavefront takes tiles of WT cells on its own -- stencil gather and
 // canonicalisation (one lane per cell) into its LDS slice of layer-1
 // operands, then the network tile of the forward pass -- and writes
-// kappa = sign * y with status 8, appending cells with |kappa| < kappa_lo to
-// the fallback list. The network arithmetic is that of the forward kernels,
+// kappa = sign * y with status 8, appending cells with |kappa| < kappa_lo or
+// two interfaces in their block to the fallback list. The network arithmetic is that of the forward kernels,
 // so y is bit-identical to vofmt_mlp_forward on the same stencils.
 constexpr int FWAVES = 12;  // wavefronts per workgroup (LDS: 41 KB of weights + 9 KB per wavefront)
 
@@ -704,11 +714,13 @@ __global__ __launch_bounds__(64 * FWAVES) void k_curv_fused(
     const bool own = q < nm;
     int sg = 1;
     int32_t p = 0;
+    bool two = false;
     if (own) {
       p = list[q];
       float xf[27];
       Canon cn;
       sg = canonical_block(c, (uint32_t)p, nx, ny, nz, xf, cn);
+      two = cn.two;
       canonical_scatter(xf, cn, [&](int k, float v) { xrow[k] = v; });
     } else {
       for (int k = 0; k < 27; ++k) xrow[k] = 0.0f;
@@ -731,7 +743,7 @@ __global__ __launch_bounds__(64 * FWAVES) void k_curv_fused(
       const double kn = (double)sg * (double)own_output(yv, lq);
       kappa[p] = kn;
       status[p] = 8;
-      flag = fabs(kn) < kappa_lo;
+      flag = two || fabs(kn) < kappa_lo;
     }
     const uint64_t mask = __ballot(flag);
     if (mask) {

@@ -183,13 +183,16 @@ __device__ __forceinline__ double clean_residue(double v) {
 // kResidue inside (0, 1). Every other cell, round-off residues included,
 // donates like a pure cell (flux s * c).
 __device__ __forceinline__ bool is_mixed(double v) { return v > kResidue && v < 1.0 - kResidue; }
-__device__ __forceinline__ void myc_normal(const double *b_in, double &nx_, double &ny_, double &nz_) {
+// sigma_low: bit d set when the centred-columns orientation of axis d is +1
+// (the low end layer's sums at least the high one's).
+__device__ __forceinline__ void myc_normal_sigma(const double *b_in, double &nx_, double &ny_, double &nz_,
+                                                 int &sigma_low) {
   double b[27];
 #pragma unroll
   for (int q = 0; q < 27; ++q) b[q] = clean_residue(b_in[q]);
 #define B(ax, ay, az) b[((ax) + 1) + 3 * ((ay) + 1) + 9 * ((az) + 1)]
   // best centred-columns axis: smallest D = (|g1| + |g2|) + 1, ties to the lower axis
-  int ds = 0;
+  int ds = 0, sig = 0;
   double bD = 0.0, bs = 0.0, bg1 = 0.0, bg2 = 0.0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -208,6 +211,7 @@ __device__ __forceinline__ void myc_normal(const double *b_in, double &nx_, doub
         shi += e2;
       }
     const double sigma = (slo >= shi) ? 1.0 : -1.0;
+    if (slo >= shi) sig |= 1 << d;
     const double g1 = (H[2][1] - H[0][1]) / 2.0;
     const double g2 = (H[1][2] - H[1][0]) / 2.0;
     const double D = (fabs(g1) + fabs(g2)) + 1.0;
@@ -219,6 +223,7 @@ __device__ __forceinline__ void myc_normal(const double *b_in, double &nx_, doub
       bg2 = g2;
     }
   }
+  sigma_low = sig;
   double Gx = 0.0, Gy = 0.0, Gz = 0.0;
   const double w[3] = {1.0, 2.0, 1.0};
 #pragma unroll
@@ -250,6 +255,10 @@ __device__ __forceinline__ void myc_normal(const double *b_in, double &nx_, doub
   if (ds == 0) { nx_ = nd; ny_ = n1; nz_ = n2; }
   else if (ds == 1) { nx_ = n1; ny_ = nd; nz_ = n2; }
   else { nx_ = n1; ny_ = n2; nz_ = nd; }
+}
+__device__ __forceinline__ void myc_normal(const double *b_in, double &nx_, double &ny_, double &nz_) {
+  int sigma_low;
+  myc_normal_sigma(b_in, nx_, ny_, nz_, sigma_low);
 }
 
 }  // namespace plic
