@@ -37,7 +37,8 @@ single-threaded.
 --pmc-pass advect: a short run for the traffic counters (a plain copy of
 1 GiB, the calibration kernel; 2 advection steps; two surface-tension force
 evaluations). --pmc-pass mlp: the network kernels a few times each (forward
-on given stencils, fused curvature, training steps). Each prints one line.
+on given stencils, fused curvature, training steps at batch 262144). Each
+prints one line.
 """
 from __future__ import annotations
 
@@ -442,7 +443,7 @@ def pmc_pass(torch, np, ctx, c, s, ntr, which):
     for _ in range(3):
         ctx.mlp_forward(Pd, xs, y)
         ctx.curvature_mlp(c0, Pd, meta["kappa_lo"], kap, st)
-    bsz = 4096
+    bsz = 262144  # 4096 tiles: the training kernels fill the chip (the training row times batch 4096)
     rng = synth.Splitmix64(5)
     xt = torch.from_numpy(rng.uniform(bsz * 27).astype(np.float32).reshape(bsz, 27)).to(dev)
     tt = torch.from_numpy((rng.uniform(bsz) * 0.5).astype(np.float32)).to(dev)
@@ -451,7 +452,8 @@ def pmc_pass(torch, np, ctx, c, s, ntr, which):
     for k in range(1, 4):
         ctx.mlp_train_step(Pt, Mt, Vt, k, 1e-3, xt, tt)
     torch.cuda.synchronize()
-    return {"pmc_pass": "mlp", "mixed_cells": nmix, "forward_calls": 3, "fused_calls": 3, "train_steps": 3}
+    return {"pmc_pass": "mlp", "mixed_cells": nmix, "forward_calls": 3, "fused_calls": 3, "train_steps": 3,
+            "train_batch": bsz}
 
 
 def main():

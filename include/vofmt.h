@@ -346,7 +346,8 @@ int vofmt_csf_force(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t 
  * initial accumulator. The last layer is an FP32 dot product of the unrounded
  * second-layer activations with the FP32 W3. Loss and Adam in FP32. Every
  * batch reduction is done in a fixed order, so results are reproducible bit
- * for bit.
+ * for bit on a given device (the batch's 64-sample tiles are split into at
+ * most one contiguous range per compute unit).
  * ------------------------------------------------------------------------ */
 #define VOFMT_MLP_NPARAMS 20868
 

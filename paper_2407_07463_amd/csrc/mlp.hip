@@ -15,8 +15,9 @@
 // three BF16 parts summing to it, b2 as the initial accumulator). The last
 // layer (128 -> 1) is an FP32 dot product of the unrounded second-layer
 // activations with the FP32 W3. Loss and Adam in FP32. ReLU'(z) is
-// (activation > 0). Batch reductions go through per-tile partial sums added
-// in a fixed order, so every result is reproducible bit for bit.
+// (activation > 0). Batch reductions go through partial sums, each over a
+// contiguous range of tiles in order, added in a fixed order, so every result
+// is reproducible bit for bit.
 //
 // MFMA fragment layout (16x16x32, one wavefront): lane l holds
 //   A[l%16][8*(l/16) + e], B[8*(l/16) + e][l%16] for e = 0..7 (bf16), and
@@ -364,13 +365,17 @@ __global__ __launch_bounds__(64 * IWAVES) __attribute__((amdgpu_waves_per_eu(4))
   mlp_tiles<true, true>(L, P, m, x, nullptr, acts, tgt, g_out, loss_part, IWAVES);
 }
 
-// Backward pass of one 64-sample tile: per-tile partial gradients of every
-// parameter (added later in a fixed order). trace (nullable): the training
-// records of the tile's samples.
+// Backward pass, persistent: workgroup g takes the 64-sample tiles
+// [g T, (g+1) T) in order and accumulates its partial gradient of every
+// parameter across them -- the weight gradients in the matrix cores'
+// accumulators, the bias and W3 gradients as FP32 sums in fixed orders (per
+// thread over the samples it handles, then over the threads) -- then writes
+// it once (the partials are added later in a fixed order). trace
+// (nullable): the training records of the samples.
 __global__ __launch_bounds__(256) void k_mlp_bwd(const float *__restrict__ P, const uint16_t *__restrict__ w2n_g,
                                                  int m, const float *__restrict__ x, uint8_t *__restrict__ acts,
                                                  const float *__restrict__ g, float *__restrict__ partial,
-                                                 uint8_t *__restrict__ trace) {
+                                                 uint8_t *__restrict__ trace, int tiles_per_group) {
   __shared__ __attribute__((aligned(16))) uint16_t XTh[NIN][TP];
   __shared__ __attribute__((aligned(16))) uint16_t XTl[NIN][TP];
   __shared__ __attribute__((aligned(16))) uint16_t H1T[NH][TP];
@@ -381,130 +386,155 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(const float *__restrict__ P, co
   __shared__ float w3s[NH];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lq = lane >> 4;
-  const int tile = blockIdx.x, s0 = tile * TILE;
-  float *part = partial + (int64_t)tile * NPARAMS;
-  if (tid < TILE) gs[tid] = (s0 + tid < m) ? g[s0 + tid] : 0.0f;
+  const int ntiles = (m + TILE - 1) / TILE;
+  const int t0 = blockIdx.x * tiles_per_group;
+  const int t1 = t0 + tiles_per_group < ntiles ? t0 + tiles_per_group : ntiles;
+  float *part = partial + (int64_t)blockIdx.x * NPARAMS;
   if (tid < NH) w3s[tid] = P[OFF_W3 + tid];
-  for (int i = tid; i < TILE * NIN; i += 256) {
-    const int s = i / NIN, k = i % NIN;
-    const float v = (k < 27 && s0 + s < m) ? x[(int64_t)(s0 + s) * 27 + k] : 0.0f;
-    const uint16_t hi = bf16_bits(v);
-    XTh[k][s] = hi;
-    XTl[k][s] = bf16_bits(v - bf16_val(hi));
-  }
-  for (int i = tid; i < TILE * NH; i += 256) {
-    const int s = i / NH, k = i % NH;
-    H1T[k][s] = (s0 + s < m) ? act_h1(acts, s0 + s, ACT_BYTES)[k] : (uint16_t)0;
-  }
-  __syncthreads();
-  // dZ2 = bf16((h2 > 0) * g * W3)
-  for (int i = tid; i < TILE * NH; i += 256) {
-    const int s = i / NH, k = i % NH;
-    const float h2 = (s0 + s < m) ? act_h2(acts, s0 + s, ACT_BYTES)[k] : 0.0f;
-    const float d = (h2 > 0.0f) ? gs[s] * w3s[k] : 0.0f;
-    const uint16_t b = bf16_bits(d);
-    D2[s][k] = b;
-    D2T[k][s] = b;
-    if (trace && s0 + s < m) reinterpret_cast<uint16_t *>(trace + (int64_t)(s0 + s) * TRACE_BYTES + 768)[k] = b;
-  }
-  __syncthreads();
-  // dH1 = dZ2 . W2^T; dZ1 = bf16((h1 > 0) * dH1); wave w owns hidden units [32w, 32w+32)
+  // accumulators over the workgroup's tiles: dW2 rows 16mt.., columns of wave w; dW1 likewise
+  f32x4 accW2[2][8], accW1[2][2];
 #pragma unroll
   for (int jn = 0; jn < 2; ++jn) {
-    const int nt = 2 * w + jn;
-    const int col = 16 * nt + lr;
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int mt = 0; mt < 8; ++mt) accW2[jn][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kk = 0; kk < NH; kk += 32)
-        acc = mfma(frag(&D2[16 * mt + lr][kk + 8 * lq]), frag(&w2n_g[(16 * nt + lr) * NH + kk + 8 * lq]), acc);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 16 * mt + 4 * lq + r;
-        const float h1 = bf16_val(H1T[col][row]);
-        const uint16_t b = bf16_bits(h1 > 0.0f ? acc[r] : 0.0f);
-        D1T[col][row] = b;
-        if (trace && s0 + row < m)
-          reinterpret_cast<uint16_t *>(trace + (int64_t)(s0 + row) * TRACE_BYTES + 1024)[col] = b;
-      }
-    }
+    for (int mt = 0; mt < 2; ++mt) accW1[jn][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
-  __syncthreads();
-  // dW2 = H1^T . dZ2 (128 x 128, K = 64 samples)
-#pragma unroll
-  for (int jn = 0; jn < 2; ++jn) {
-    const int nt = 2 * w + jn;
-    const int col = 16 * nt + lr;
-    for (int mt = 0; mt < 8; ++mt) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kk = 0; kk < TILE; kk += 32)
-        acc = mfma(frag(&H1T[16 * mt + lr][kk + 8 * lq]), frag(&D2T[16 * nt + lr][kk + 8 * lq]), acc);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) part[OFF_W2 + (16 * mt + 4 * lq + r) * NH + col] = acc[r];
+  // dW3 and db2 of unit tid % 128 over the samples of parity tid / 128; db1 of the lane's
+  // units 16 (2w + jn) + lr over its rows 4lq + r of every 16-row tile; db3 (thread 0)
+  float a3 = 0.0f, a2 = 0.0f, a1[2] = {0.0f, 0.0f}, ab3 = 0.0f;
+  for (int tile = t0; tile < t1; ++tile) {
+    const int s0 = tile * TILE;
+    __syncthreads();  // the previous tile's LDS data is no longer read
+    if (tid < TILE) gs[tid] = (s0 + tid < m) ? g[s0 + tid] : 0.0f;
+    for (int i = tid; i < TILE * NIN; i += 256) {
+      const int s = i / NIN, k = i % NIN;
+      const float v = (k < 27 && s0 + s < m) ? x[(int64_t)(s0 + s) * 27 + k] : 0.0f;
+      const uint16_t hi = bf16_bits(v);
+      XTh[k][s] = hi;
+      XTl[k][s] = bf16_bits(v - bf16_val(hi));
     }
-  }
-  // dW1 = X^T . dZ1 (32 x 128, K = 64 samples), X as hi + lo
-#pragma unroll
-  for (int jn = 0; jn < 2; ++jn) {
-    const int nt = 2 * w + jn;
-    const int col = 16 * nt + lr;
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kk = 0; kk < TILE; kk += 32) {
-        const bf16x8 d1 = frag(&D1T[16 * nt + lr][kk + 8 * lq]);
-        acc = mfma(frag(&XTh[16 * mt + lr][kk + 8 * lq]), d1, acc);
-        acc = mfma(frag(&XTl[16 * mt + lr][kk + 8 * lq]), d1, acc);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) part[OFF_W1 + (16 * mt + 4 * lq + r) * NH + col] = acc[r];
+    for (int i = tid; i < TILE * NH; i += 256) {
+      const int s = i / NH, k = i % NH;
+      H1T[k][s] = (s0 + s < m) ? act_h1(acts, s0 + s, ACT_BYTES)[k] : (uint16_t)0;
     }
-  }
-  // dW3, the biases, and the padding, as sequential FP32 sums over the tile
-  if (tid < NH) {
-    const int k = tid;
-    float a3 = 0.0f, a2 = 0.0f, a1 = 0.0f;
-    for (int s = 0; s < TILE; ++s) {
+    __syncthreads();
+    // dZ2 = bf16((h2 > 0) * g * W3)
+    for (int i = tid; i < TILE * NH; i += 256) {
+      const int s = i / NH, k = i % NH;
       const float h2 = (s0 + s < m) ? act_h2(acts, s0 + s, ACT_BYTES)[k] : 0.0f;
+      const float d = (h2 > 0.0f) ? gs[s] * w3s[k] : 0.0f;
+      const uint16_t b = bf16_bits(d);
+      D2[s][k] = b;
+      D2T[k][s] = b;
       a3 = a3 + gs[s] * h2;
-      a2 = a2 + bf16_val(D2T[k][s]);
-      a1 = a1 + bf16_val(D1T[k][s]);
+      a2 = a2 + bf16_val(b);
+      if (trace && s0 + s < m) reinterpret_cast<uint16_t *>(trace + (int64_t)(s0 + s) * TRACE_BYTES + 768)[k] = b;
     }
-    part[OFF_W3 + k] = a3;
-    part[OFF_B2 + k] = a2;
-    part[OFF_B1 + k] = a1;
+    __syncthreads();
+    // dH1 = dZ2 . W2^T; dZ1 = bf16((h1 > 0) * dH1); wave w owns hidden units [32w, 32w+32)
+#pragma unroll
+    for (int jn = 0; jn < 2; ++jn) {
+      const int nt = 2 * w + jn;
+      const int col = 16 * nt + lr;
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < NH; kk += 32)
+          acc = mfma(frag(&D2[16 * mt + lr][kk + 8 * lq]), frag(&w2n_g[(16 * nt + lr) * NH + kk + 8 * lq]), acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * mt + 4 * lq + r;
+          const float h1 = bf16_val(H1T[col][row]);
+          const uint16_t b = bf16_bits(h1 > 0.0f ? acc[r] : 0.0f);
+          D1T[col][row] = b;
+          a1[jn] = a1[jn] + bf16_val(b);
+          if (trace && s0 + row < m)
+            reinterpret_cast<uint16_t *>(trace + (int64_t)(s0 + row) * TRACE_BYTES + 1024)[col] = b;
+        }
+      }
+    }
+    __syncthreads();
+    // dW2 += H1^T . dZ2 (128 x 128, K = 64 samples)
+#pragma unroll
+    for (int jn = 0; jn < 2; ++jn) {
+      const int nt = 2 * w + jn;
+#pragma unroll
+      for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+        for (int kk = 0; kk < TILE; kk += 32)
+          accW2[jn][mt] =
+              mfma(frag(&H1T[16 * mt + lr][kk + 8 * lq]), frag(&D2T[16 * nt + lr][kk + 8 * lq]), accW2[jn][mt]);
+    }
+    // dW1 += X^T . dZ1 (32 x 128, K = 64 samples), X as hi + lo
+#pragma unroll
+    for (int jn = 0; jn < 2; ++jn) {
+      const int nt = 2 * w + jn;
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int kk = 0; kk < TILE; kk += 32) {
+          const bf16x8 d1 = frag(&D1T[16 * nt + lr][kk + 8 * lq]);
+          accW1[jn][mt] = mfma(frag(&XTh[16 * mt + lr][kk + 8 * lq]), d1, accW1[jn][mt]);
+          accW1[jn][mt] = mfma(frag(&XTl[16 * mt + lr][kk + 8 * lq]), d1, accW1[jn][mt]);
+        }
+    }
+    if (tid == 0)
+      for (int s = 0; s < TILE; ++s) ab3 = ab3 + gs[s];
+    if (trace) {
+      // the activation records of the tile, copied word by word
+      for (int i = tid; i < TILE * (ACT_BYTES / 4); i += 256) {
+        const int s = i / (ACT_BYTES / 4), q = i % (ACT_BYTES / 4);
+        if (s0 + s < m)
+          reinterpret_cast<uint32_t *>(trace + (int64_t)(s0 + s) * TRACE_BYTES)[q] =
+              reinterpret_cast<const uint32_t *>(acts + (int64_t)(s0 + s) * ACT_BYTES)[q];
+      }
+    }
+  }
+  // the workgroup's partial gradient
+#pragma unroll
+  for (int jn = 0; jn < 2; ++jn) {
+    const int col = 16 * (2 * w + jn) + lr;
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) part[OFF_W2 + (16 * mt + 4 * lq + r) * NH + col] = accW2[jn][mt][r];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) part[OFF_W1 + (16 * mt + 4 * lq + r) * NH + col] = accW1[jn][mt][r];
+  }
+  // the per-thread sums combined in a fixed order (the tiles' LDS arrays are free now)
+  __syncthreads();
+  float *red = reinterpret_cast<float *>(&D2[0][0]);  // [2][128] dW3, [2][128] db2, [4][128] db1
+  red[tid] = a3;
+  red[256 + tid] = a2;
+#pragma unroll
+  for (int jn = 0; jn < 2; ++jn) red[512 + lq * NH + 16 * (2 * w + jn) + lr] = a1[jn];
+  __syncthreads();
+  if (tid < NH) {
+    part[OFF_W3 + tid] = red[tid] + red[NH + tid];
+    part[OFF_B2 + tid] = red[256 + tid] + red[256 + NH + tid];
+    part[OFF_B1 + tid] = ((red[512 + tid] + red[512 + NH + tid]) + red[512 + 2 * NH + tid]) + red[512 + 3 * NH + tid];
   } else if (tid == NH) {
-    float a = 0.0f;
-    for (int s = 0; s < TILE; ++s) a = a + gs[s];
-    part[OFF_B3] = a;
     part[OFF_B3 + 1] = 0.0f;
     part[OFF_B3 + 2] = 0.0f;
     part[OFF_B3 + 3] = 0.0f;
   }
-  if (trace) {
-    // the activation records of the tile, copied word by word
-    for (int i = tid; i < TILE * (ACT_BYTES / 4); i += 256) {
-      const int s = i / (ACT_BYTES / 4), q = i % (ACT_BYTES / 4);
-      if (s0 + s < m)
-        reinterpret_cast<uint32_t *>(trace + (int64_t)(s0 + s) * TRACE_BYTES)[q] =
-            reinterpret_cast<const uint32_t *>(acts + (int64_t)(s0 + s) * ACT_BYTES)[q];
-    }
-  }
+  if (tid == 0) part[OFF_B3] = ab3;
 }
 
-// Gradient = fixed-order sum of the tile partials; Adam on the FP32 masters.
+// Gradient = fixed-order sum of the workgroup partials; Adam on the FP32 masters.
 __global__ __launch_bounds__(256) void k_mlp_adam(float *__restrict__ P, float *__restrict__ Mo,
-                                                  float *__restrict__ Vo, const float *__restrict__ partial, int ntiles,
-                                                  int step, float lrate, float *__restrict__ grads,
+                                                  float *__restrict__ Vo, const float *__restrict__ partial, int nparts,
+                                                  int ntiles, int step, float lrate, float *__restrict__ grads,
                                                   const float *__restrict__ loss_part, float *__restrict__ loss_out,
                                                   int m) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < NPARAMS) {
     float gsum = 0.0f;
-    for (int t = 0; t < ntiles; ++t) gsum = gsum + partial[(int64_t)t * NPARAMS + i];
+    for (int t = 0; t < nparts; ++t) gsum = gsum + partial[(int64_t)t * NPARAMS + i];
     if (grads) grads[i] = gsum;
     const float mm = 0.9f * Mo[i] + 0.1f * gsum;
     const float vv = 0.999f * Vo[i] + 0.001f * (gsum * gsum);
@@ -514,10 +544,18 @@ __global__ __launch_bounds__(256) void k_mlp_adam(float *__restrict__ P, float *
     const float c1 = (float)(1.0 - pow(0.9, (double)step)), c2 = (float)(1.0 - pow(0.999, (double)step));
     P[i] = P[i] - lrate * (mm / c1) / (sqrtf(vv / c2) + 1e-8f);
   }
-  if (i == 0) {
+  // the loss: tile losses summed per thread of block 0 (stride 256), then a fixed tree
+  if (blockIdx.x == 0) {
+    __shared__ float lsum[256];
     float l = 0.0f;
-    for (int t = 0; t < ntiles; ++t) l = l + loss_part[t];
-    loss_out[0] = l / (float)m;
+    for (int t = threadIdx.x; t < ntiles; t += 256) l = l + loss_part[t];
+    lsum[threadIdx.x] = l;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+      if ((int)threadIdx.x < h) lsum[threadIdx.x] = lsum[threadIdx.x] + lsum[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) loss_out[0] = lsum[0] / (float)m;
   }
 }
 
@@ -817,9 +855,16 @@ extern "C" int vofmt_mlp_train_step(vofmt_ctx *ctx, float *params, float *adam_m
   int rc = mlp_prepare(ctx, params, w, stream);
   if (rc) return rc;
   const int ntiles = (m + TILE - 1) / TILE;
+  // backward: one workgroup per compute unit at most, each over a contiguous range of tiles
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
+    cus = 256;
+  int groups = ntiles < cus ? ntiles : cus;
+  const int per_group = (ntiles + groups - 1) / groups;
+  groups = (ntiles + per_group - 1) / per_group;
   uint8_t *acts = (uint8_t *)scratch(ctx, SLOT_MLP_ACTS, (size_t)ACT_BYTES * (size_t)m);
   float *gbuf = (float *)scratch(ctx, SLOT_MLP_G, sizeof(float) * ((size_t)m + (size_t)ntiles + 4));
-  float *partial = (float *)scratch(ctx, SLOT_MLP_PART, sizeof(float) * (size_t)ntiles * NPARAMS);
+  float *partial = (float *)scratch(ctx, SLOT_MLP_PART, sizeof(float) * (size_t)groups * NPARAMS);
   float *hl = (float *)host_scratch(ctx, sizeof(float) * 4);
   if (!acts || !gbuf || !partial || !hl) return VOFMT_E_NOMEM;
   float *loss_part = gbuf + m;
@@ -829,11 +874,12 @@ extern "C" int vofmt_mlp_train_step(vofmt_ctx *ctx, float *params, float *adam_m
                      params, (const uint4 *)w[0], (const uint4 *)w[1], m, x, acts, y_target, gbuf, loss_part);
   prof_end(ctx, rec, stream);
   rec = prof_begin(ctx, "k_mlp_bwd", stream);
-  hipLaunchKernelGGL(k_mlp_bwd, dim3(ntiles), dim3(256), 0, stream, params, w[2], m, x, acts, gbuf, partial, trace);
+  hipLaunchKernelGGL(k_mlp_bwd, dim3(groups), dim3(256), 0, stream, params, w[2], m, x, acts, gbuf, partial, trace,
+                     per_group);
   prof_end(ctx, rec, stream);
   rec = prof_begin(ctx, "k_mlp_adam", stream);
   hipLaunchKernelGGL(k_mlp_adam, dim3(ceil_div(NPARAMS, 256)), dim3(256), 0, stream, params, adam_m, adam_v, partial,
-                     ntiles, step, lr, grads, loss_part, loss_out, m);
+                     groups, ntiles, step, lr, grads, loss_part, loss_out, m);
   prof_end(ctx, rec, stream);
   VOFMT_HIP(ctx, hipGetLastError());
   VOFMT_HIP(ctx, hipMemcpyAsync(hl, loss_out, sizeof(float), hipMemcpyDeviceToHost, stream));

@@ -14,8 +14,8 @@ Usage (after the rocprofv3 runs, with their CSV output directories):
       The summary records the SHA-256 of the advection sources, so that a
       reader can tell whether the kernel changed since.
 
-  python -m paper_2407_07463_amd.profiling counters DIR --kernel REGEX \
-      --counters NAME... --out FILE.txt --command "..." [--sources ...]
+  python -m paper_2407_07463_amd.profiling counters DIR [DIR...] --kernel REGEX \
+      --counters NAME... --out FILE.txt --command "..." [--command "..."] [--sources ...]
       per-kernel mean of each counter per dispatch from a `--pmc` run
       (derived metrics such as MfmaUtil as rocprofv3 reduces them).
 """
@@ -152,14 +152,27 @@ def write_traffic(fetch_dir, write_dir, kernel_re, copy_re, copy_bytes, out, com
         fo.write("\n".join(lines) + "\n")
 
 
-def write_counters(directory, kernel_re, counters, out, command, title, sources=None):
+def write_counters(directories, kernel_re, counters, out, commands, title, sources=None):
     """Per-kernel mean of each counter per dispatch (derived metrics included, as rocprofv3
-    reduces them), one line per kernel matching kernel_re."""
+    reduces them), one line per kernel matching kernel_re. Counters may come from several
+    runs (one directory and command each): a counter is read from the first run that has it."""
+    if isinstance(directories, str):
+        directories = [directories]
+    if isinstance(commands, str):
+        commands = [commands]
     kre = re.compile(kernel_re)
-    means = {cn: counter_means(directory, cn) for cn in counters}
+    means = {}
+    for cn in counters:
+        for d in directories:
+            m = counter_means(d, cn)
+            if m:
+                means[cn] = m
+                break
+        else:
+            means[cn] = {}
     names = sorted({k for m in means.values() for k in m if kre.search(k)})
-    lines = [f"# {title}", "", f"Command: {command}", "",
-             f"source_sha256 = {advect_source_sha(sources)}   ({', '.join(sources or ADVECT_SOURCES)})", ""]
+    lines = [f"# {title}", ""] + [f"Command: {c}" for c in commands] + [
+        "", f"source_sha256 = {advect_source_sha(sources)}   ({', '.join(sources or ADVECT_SOURCES)})", ""]
     for k in names:
         parts = [f"kernel = {k}"]
         nd = max(means[cn].get(k, (0, 0.0))[0] for cn in counters)
@@ -208,11 +221,11 @@ def main(argv=None):
                    help="sources of the counted kernel (relative to the package) whose hash the summary records; "
                         "default: the advection kernels")
     c = sub.add_parser("counters")
-    c.add_argument("dir")
+    c.add_argument("dir", nargs="+")
     c.add_argument("--kernel", required=True)
     c.add_argument("--counters", nargs="+", required=True)
     c.add_argument("--out", required=True)
-    c.add_argument("--command", required=True)
+    c.add_argument("--command", required=True, action="append", help="the command of each run, in order")
     c.add_argument("--title", default="rocprofv3 counters per dispatch")
     c.add_argument("--sources", nargs="*", default=None)
     args = ap.parse_args(argv)

@@ -174,7 +174,7 @@ def test_forward_rejects_bad_arguments(ctx):
         ctx.mlp_train_step(P, torch.zeros_like(P), torch.zeros_like(P), 0, 1e-3, x, y)
 
 
-@pytest.mark.parametrize("m,step", [(203, 1), (64, 1), (1, 1), (4096, 3)])
+@pytest.mark.parametrize("m,step", [(203, 1), (64, 1), (1, 1), (4096, 3), (40000, 2)])
 def test_train_step(ctx, m, step):
     import torch
 
@@ -245,7 +245,12 @@ def test_train_step(ctx, m, step):
     carried[OFF["W1"]:OFF["W1"] + 27 * 128] = (xb.T @ dd1).ravel()
     carried[OFF["b1"]:OFF["W2"]] = dd1.sum(axis=0)
     ntiles = (m + 63) // 64
-    K = 128 + ntiles + 8  # dW1 sums hi and lo products: 2 x 64 per tile
+    # a workgroup per compute unit at most, each over T consecutive tiles: dW1 chains hi and lo
+    # products, 2 x 64 per tile, then the partials of the groups are added
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    T = -(-ntiles // min(ntiles, cus))
+    groups = -(-ntiles // T)
+    K = 128 * T + groups + 8
     gbound = _check_carried(G, b["grad"], b["grad_abs"], carried, K, "grad")
     # padding rows of W1 see zero inputs
     assert np.all(G[OFF["W1"] + 27 * 128:OFF["b1"]] == 0.0)
