@@ -32,7 +32,12 @@ __global__ __launch_bounds__(kBlock) void k_block_counts(const double *__restric
 }
 
 // Exclusive scan of one tile of kTile entries in place; the tile total goes to tot[tile].
-__global__ __launch_bounds__(kTile) void k_scan_tile(int32_t *__restrict__ v, int64_t n, int32_t *__restrict__ tot) {
+// Batches of arrays along blockIdx.y: array b starts at v + b * vstride, its totals at
+// tot + b * tstride.
+__global__ __launch_bounds__(kTile) void k_scan_tile(int32_t *__restrict__ v, int64_t n, int32_t *__restrict__ tot,
+                                                     int64_t vstride, int64_t tstride) {
+  v += blockIdx.y * vstride;
+  tot += blockIdx.y * tstride;
   __shared__ int32_t s[kTile];
   const int64_t i = (int64_t)blockIdx.x * kTile + threadIdx.x;
   const int32_t x = (i < n) ? v[i] : 0;
@@ -49,8 +54,9 @@ __global__ __launch_bounds__(kTile) void k_scan_tile(int32_t *__restrict__ v, in
 }
 
 // Exclusive scan of the tile totals (one workgroup, any length); the grand
-// total goes to tot[ntiles].
-__global__ __launch_bounds__(kTile) void k_scan_totals(int32_t *__restrict__ tot, int64_t ntiles) {
+// total goes to tot[ntiles]. Batches along blockIdx.y as in k_scan_tile.
+__global__ __launch_bounds__(kTile) void k_scan_totals(int32_t *__restrict__ tot, int64_t ntiles, int64_t tstride) {
+  tot += blockIdx.y * tstride;
   __shared__ int32_t s[kTile];
   __shared__ int32_t carry;
   if (threadIdx.x == 0) carry = 0;
@@ -108,8 +114,8 @@ inline void launch_ordered_list(const double *c, int64_t n3, int32_t *bc, int32_
   const int64_t nb = (n3 + kBlock - 1) / kBlock;
   const int64_t ntiles = (nb + kTile - 1) / kTile;
   hipLaunchKernelGGL(k_block_counts, dim3((unsigned)nb), dim3(kBlock), 0, stream, c, n3, bc);
-  hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)ntiles), dim3(kTile), 0, stream, bc, nb, tot);
-  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kTile), 0, stream, tot, ntiles);
+  hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)ntiles), dim3(kTile), 0, stream, bc, nb, tot, (int64_t)0, (int64_t)0);
+  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kTile), 0, stream, tot, ntiles, (int64_t)0);
   hipLaunchKernelGGL(k_write_ordered, dim3((unsigned)nb), dim3(kBlock), 0, stream, c, n3, bc, tot, list, kappa,
                      status);
 }
@@ -163,8 +169,8 @@ inline void launch_ordered_list_if(int64_t n, Pred pr, int32_t *bc, int32_t *tot
   const int64_t nb = (n + kBlock - 1) / kBlock;
   const int64_t ntiles = (nb + kTile - 1) / kTile;
   hipLaunchKernelGGL(k_block_counts_if<Pred>, dim3((unsigned)nb), dim3(kBlock), 0, stream, n, pr, bc, bits);
-  hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)ntiles), dim3(kTile), 0, stream, bc, nb, tot);
-  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kTile), 0, stream, tot, ntiles);
+  hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)ntiles), dim3(kTile), 0, stream, bc, nb, tot, (int64_t)0, (int64_t)0);
+  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kTile), 0, stream, tot, ntiles, (int64_t)0);
   hipLaunchKernelGGL(k_write_ordered_bits, dim3((unsigned)nb), dim3(kBlock), 0, stream, n, bits, bc, tot, list);
 }
 

@@ -121,9 +121,12 @@ __device__ __forceinline__ int run_index(uint64_t m, int i) {
 // their loads are in flight together.
 __global__ __launch_bounds__(kBlock) void k_label_occ(const double *__restrict__ c, double c_eps,
                                                       uint64_t *__restrict__ occ, int32_t *__restrict__ R, int nx,
-                                                      int ny, int nz, int words, int S, SegDiv dv) {
+                                                      int ny, int nz, int words, int S, SegDiv dv, int64_t nrun) {
   const int lane = threadIdx.x & 63;
   const int64_t nseg = (int64_t)ny * nz * words, s0 = first_segment();
+  c += blockIdx.y * ((int64_t)nx * ny * nz);  // field blockIdx.y and its work arrays
+  occ += blockIdx.y * nseg;
+  R += blockIdx.y * nrun;
   double v[kSegs];
 #pragma unroll
   for (int k = 0; k < kSegs; ++k) {
@@ -148,9 +151,11 @@ __global__ __launch_bounds__(kBlock) void k_label_occ(const double *__restrict__
 
 // Pass 2: unions of each segment's runs with their +y, +z and -x neighbours.
 __global__ __launch_bounds__(kBlock) void k_label_union(const uint64_t *__restrict__ occ, int32_t *R, int nx, int ny,
-                                                        int nz, int words, int S, SegDiv dv) {
+                                                        int nz, int words, int S, SegDiv dv, int64_t nrun) {
   const int64_t sgi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t nseg = (int64_t)ny * nz * words;
+  occ += blockIdx.y * nseg;
+  R += blockIdx.y * nrun;
   if (sgi >= nseg) return;
   const uint64_t m = occ[sgi];
   if (m == 0) return;
@@ -200,8 +205,11 @@ __device__ __forceinline__ int count_roots(const int32_t *R, uint64_t m, int64_t
 
 // Pass 3: every run points at its root; roots counted per workgroup.
 __global__ __launch_bounds__(kBlock) void k_label_flatten(const uint64_t *__restrict__ occ, int32_t *R, int64_t nseg,
-                                                          int S, uint32_t *__restrict__ blockcount) {
+                                                          int S, uint32_t *__restrict__ blockcount, int64_t nrun) {
   const int64_t sgi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  occ += blockIdx.y * nseg;
+  R += blockIdx.y * nrun;
+  blockcount += blockIdx.y * gridDim.x;
   uint32_t nroot = 0;
   if (sgi < nseg) {
     const uint64_t m = occ[sgi];
@@ -224,9 +232,11 @@ __global__ __launch_bounds__(kBlock) void k_label_flatten(const uint64_t *__rest
   }
 }
 
-// The total of the tiled scan into *total.
-__global__ void k_copy_total(const int32_t *__restrict__ tot, int64_t ntiles, int32_t *__restrict__ total) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *total = tot[ntiles];
+// The totals of the tiled scans (one per field, tstride apart) into total[].
+__global__ void k_copy_total(const int32_t *__restrict__ tot, int64_t ntiles, int64_t tstride, int nfields,
+                             int32_t *__restrict__ total) {
+  const int t = threadIdx.x;
+  if (t < nfields) total[t] = tot[t * tstride + ntiles];
 }
 
 // Pass 4: each root's entry becomes -(1 + number of roots before it), in
@@ -234,9 +244,14 @@ __global__ void k_copy_total(const int32_t *__restrict__ tot, int64_t ntiles, in
 // compact::kTile blocks, tileoff: exclusive offsets of the tiles.
 __global__ __launch_bounds__(kBlock) void k_label_rank(const uint64_t *__restrict__ occ, int32_t *R, int64_t nseg,
                                                        int S, const int32_t *__restrict__ blockoff,
-                                                       const int32_t *__restrict__ tileoff) {
+                                                       const int32_t *__restrict__ tileoff, int64_t nrun,
+                                                       int64_t tstride) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t sgi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  occ += blockIdx.y * nseg;
+  R += blockIdx.y * nrun;
+  blockoff += blockIdx.y * gridDim.x;
+  tileoff += blockIdx.y * tstride;
   const uint64_t m = (sgi < nseg) ? occ[sgi] : 0ull;
   const int mine = (sgi < nseg) ? count_roots(R, m, sgi, S) : 0;
   // exclusive prefix of the counts over the workgroup's threads
@@ -265,9 +280,13 @@ __global__ __launch_bounds__(kBlock) void k_label_rank(const uint64_t *__restric
 // load under a lane condition is compiled as a branch that waits for it.
 __global__ __launch_bounds__(kBlock) void k_label_write(const uint64_t *__restrict__ occ,
                                                         const int32_t *__restrict__ R, int32_t *__restrict__ lab,
-                                                        int nx, int ny, int nz, int words, int S, SegDiv dv) {
+                                                        int nx, int ny, int nz, int words, int S, SegDiv dv,
+                                                        int64_t nrun) {
   const int lane = threadIdx.x & 63;
   const int64_t nseg = (int64_t)ny * nz * words, s0 = first_segment();
+  occ += blockIdx.y * nseg;
+  R += blockIdx.y * nrun;
+  lab += blockIdx.y * ((int64_t)nx * ny * nz);
   uint64_t m[kSegs];
   int32_t e[kSegs];
 #pragma unroll
@@ -732,27 +751,35 @@ __global__ void k_shape_finish(int32_t K, int nx, int ny, int nz, const int32_t 
 // Scratch: occupancy words (one per segment), run array (S per segment),
 // block counts (segment_blocks entries), tile offsets
 // (segment_blocks / compact::kTile + 2 entries).
-static int label_one(vofmt_ctx *ctx, int nx, int ny, int nz, const double *c, double c_eps, int32_t *lab,
-                     uint64_t *occ, int32_t *runs, uint32_t *blockcount, int32_t *tileoff, int32_t *k_dev,
-                     hipStream_t stream) {
+// All passes over the T fields at once (blockIdx.y = field), each field with
+// its own work arrays.
+static int label_all(vofmt_ctx *ctx, int nx, int ny, int nz, int T, const double *c, double c_eps, int32_t *lab,
+                     uint64_t *occ, int32_t *runs, uint32_t *blockcount, int32_t *tileoff, int64_t tstride,
+                     int32_t *k_dev, hipStream_t stream) {
   const int words = (int)ceil_div(nx, 64);
   const int S = run_slots(nx);
   const int64_t nseg = (int64_t)ny * nz * words;
+  const int64_t nrun = nseg * S;
   const unsigned nbc = (unsigned)label_blocks(nx, ny, nz);  // per-cell passes
   const unsigned nbs = (unsigned)segment_blocks(nx, ny, nz);  // per-segment passes
   const SegDiv dv{make_fastdiv((uint32_t)words), make_fastdiv((uint32_t)ny)};
-  hipLaunchKernelGGL(k_label_occ, dim3(nbc), dim3(kBlock), 0, stream, c, c_eps, occ, runs, nx, ny, nz, words, S, dv);
-  hipLaunchKernelGGL(k_label_union, dim3(nbs), dim3(kBlock), 0, stream, occ, runs, nx, ny, nz, words, S, dv);
-  hipLaunchKernelGGL(k_label_flatten, dim3(nbs), dim3(kBlock), 0, stream, occ, runs, nseg, S, blockcount);
+  const unsigned nt = (unsigned)T;
+  hipLaunchKernelGGL(k_label_occ, dim3(nbc, nt), dim3(kBlock), 0, stream, c, c_eps, occ, runs, nx, ny, nz, words, S,
+                     dv, nrun);
+  hipLaunchKernelGGL(k_label_union, dim3(nbs, nt), dim3(kBlock), 0, stream, occ, runs, nx, ny, nz, words, S, dv, nrun);
+  hipLaunchKernelGGL(k_label_flatten, dim3(nbs, nt), dim3(kBlock), 0, stream, occ, runs, nseg, S, blockcount, nrun);
   static_assert(kBlock == compact::kBlock, "block counts and the tiled scan share the block size");
   const int64_t ntiles = (nbs + compact::kTile - 1) / compact::kTile;
   int32_t *bc = (int32_t *)blockcount;
-  hipLaunchKernelGGL(compact::k_scan_tile, dim3((unsigned)ntiles), dim3(compact::kTile), 0, stream, bc, (int64_t)nbs,
-                     tileoff);
-  hipLaunchKernelGGL(compact::k_scan_totals, dim3(1), dim3(compact::kTile), 0, stream, tileoff, ntiles);
-  hipLaunchKernelGGL(k_copy_total, dim3(1), dim3(64), 0, stream, tileoff, ntiles, k_dev);
-  hipLaunchKernelGGL(k_label_rank, dim3(nbs), dim3(kBlock), 0, stream, occ, runs, nseg, S, bc, tileoff);
-  hipLaunchKernelGGL(k_label_write, dim3(nbc), dim3(kBlock), 0, stream, occ, runs, lab, nx, ny, nz, words, S, dv);
+  hipLaunchKernelGGL(compact::k_scan_tile, dim3((unsigned)ntiles, nt), dim3(compact::kTile), 0, stream, bc,
+                     (int64_t)nbs, tileoff, (int64_t)nbs, tstride);
+  hipLaunchKernelGGL(compact::k_scan_totals, dim3(1, nt), dim3(compact::kTile), 0, stream, tileoff, ntiles, tstride);
+  hipLaunchKernelGGL(k_copy_total, dim3(1), dim3(64 * ((T + 63) / 64)), 0, stream, tileoff, ntiles, tstride, T,
+                     k_dev);
+  hipLaunchKernelGGL(k_label_rank, dim3(nbs, nt), dim3(kBlock), 0, stream, occ, runs, nseg, S, bc, tileoff, nrun,
+                     tstride);
+  hipLaunchKernelGGL(k_label_write, dim3(nbc, nt), dim3(kBlock), 0, stream, occ, runs, lab, nx, ny, nz, words, S, dv,
+                     nrun);
   return hip_check(ctx, hipGetLastError(), "label kernels");
 }
 
@@ -771,18 +798,20 @@ extern "C" int vofmt_label_drops(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t
   const int64_t nbs = segment_blocks(nx, ny, nz);
   // run ids stay below 2^31: S runs per segment is at most n3 / nseg
   const int64_t nrun = nseg * run_slots(nx);
-  uint32_t *blockcount = (uint32_t *)scratch(ctx, SLOT_LABEL_A, sizeof(uint32_t) * (size_t)nbs);
-  int32_t *runs = (int32_t *)scratch(ctx, SLOT_LABEL_B, sizeof(int32_t) * (size_t)nrun);
-  uint64_t *occ = (uint64_t *)scratch(ctx, SLOT_LABEL_C, sizeof(uint64_t) * (size_t)nseg);
-  int32_t *kdev = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * (size_t)ntracers);
-  int32_t *tileoff = (int32_t *)scratch(ctx, SLOT_MISC3, sizeof(int32_t) * (size_t)(nbs / compact::kTile + 2));
-  int32_t *kh = (int32_t *)host_scratch(ctx, sizeof(int32_t) * (size_t)ntracers);
+  // work arrays of every field (the run array holds a slot per possible run but is only
+  // touched at the runs that exist)
+  const int64_t tstride = nbs / compact::kTile + 2;
+  const size_t T = (size_t)ntracers;
+  uint32_t *blockcount = (uint32_t *)scratch(ctx, SLOT_LABEL_A, sizeof(uint32_t) * (size_t)nbs * T);
+  int32_t *runs = (int32_t *)scratch(ctx, SLOT_LABEL_B, sizeof(int32_t) * (size_t)nrun * T);
+  uint64_t *occ = (uint64_t *)scratch(ctx, SLOT_LABEL_C, sizeof(uint64_t) * (size_t)nseg * T);
+  int32_t *kdev = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * T);
+  int32_t *tileoff = (int32_t *)scratch(ctx, SLOT_MISC3, sizeof(int32_t) * (size_t)tstride * T);
+  int32_t *kh = (int32_t *)host_scratch(ctx, sizeof(int32_t) * T);
   if (!blockcount || !runs || !occ || !kdev || !tileoff || !kh) return VOFMT_E_NOMEM;
-  for (int t = 0; t < ntracers; ++t) {
-    int rc = label_one(ctx, nx, ny, nz, c + (int64_t)t * n3, c_eps, labels + (int64_t)t * n3, occ, runs, blockcount,
-                       tileoff, kdev + t, stream);
-    if (rc) return rc;
-  }
+  int rc = label_all(ctx, nx, ny, nz, ntracers, c, c_eps, labels, occ, runs, blockcount, tileoff, tstride, kdev,
+                     stream);
+  if (rc) return rc;
   VOFMT_HIP(ctx, hipMemcpyAsync(kh, kdev, sizeof(int32_t) * ntracers, hipMemcpyDeviceToHost, stream));
   VOFMT_HIP(ctx, hipStreamSynchronize(stream));
   for (int t = 0; t < ntracers; ++t) ndrops_host[t] = kh[t];
