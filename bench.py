@@ -158,6 +158,10 @@ def rows_bench(torch, np, ctx, stream, c, w, n, ntr):
     rows["drop_shapes"] = dict(ms=ms, drops=D, chi_mean=float(chi.mean().item()),
                                chi_max=float(chi.max().item()))
     log(f"drop_shapes: {ms:.2f} ms, mean aspect ratio {rows['drop_shapes']['chi_mean']:.4f}")
+    ctx.drop_moments_shapes(c, lab, nd, vol, xyz, inertia, chi, sv, velo)
+    ms, _ = timed(torch, stream, lambda: ctx.drop_moments_shapes(c, lab, nd, vol, xyz, inertia, chi, sv, velo))
+    rows["drop_moments_shapes"] = dict(ms=ms, separate_ms=rows["drop_moments"]["ms"] + rows["drop_shapes"]["ms"])
+    log(f"drop_moments_shapes: {ms:.2f} ms (separately {rows['drop_moments_shapes']['separate_ms']:.2f} ms)")
     del sv, inertia, chi, velo
     # ---- recolouring in both near-contact modes (each on a fresh copy with room for 2N tracers);
     # one untimed call first (it sizes the scratch buffers), then the timed call

@@ -154,6 +154,20 @@ int vofmt_drop_shapes(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_
                       const double *sz, double *inertia, double *chi, double *vel, hipStream_t stream);
 
 /*
+ * Moments and shapes of every drop in one pass over the labels (the
+ * combination of vofmt_drop_moments and vofmt_drop_shapes, each drop's cells
+ * summed once): vol and xyz as vofmt_drop_moments gives them (the centroid
+ * summed about the drop's box centre, so it may differ from that call's in
+ * the last bits), inertia, chi and vel as vofmt_drop_shapes.
+ * vol, xyz, inertia, chi: required outputs; vel with sx, sy, sz or all NULL.
+ * Errors: as vofmt_drop_shapes.
+ */
+int vofmt_drop_moments_shapes(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t ntracers, const double *c,
+                              const int32_t *labels, const int32_t *ndrops_host, const double *sx, const double *sy,
+                              const double *sz, double *vol, double *xyz, double *inertia, double *chi, double *vel,
+                              hipStream_t stream);
+
+/*
  * Reassign drops in near contact to other tracers (Steps 1-4 of section
  * "The no-coalescence.h algorithm"). Two distinct drops are neighbours when
  * an occupied cell of each lies at a periodic offset o with |o|^2 <

@@ -8,8 +8,11 @@
 // GPU scheme: union-find over row runs (atomicMin hooking, path halving).
 // A segment is 64 consecutive cells of one x-row; a run is a maximal set of
 // consecutive occupied cells inside one segment, and run r of segment g (in
-// x order) has the id g * S + r, S = the most runs a segment can hold, so
-// ids increase with the linear index of the runs' first cells.
+// x order) has the id g * S + r, S a power of two no smaller than the most
+// runs a segment can hold, so ids increase with the linear index of the
+// runs' first cells. The run entries are stored slot-major (entry of id
+// g * S + r at r * nseg + g): the first runs of consecutive segments, which
+// almost every pass reads, are adjacent in memory.
 //   1. occupancy: one ballot word per segment (bit l: cell 64 * seg + l is
 //               occupied), read from c once; every run starts as its own root;
 //   2. union:   one thread per segment unites each of its runs with the runs
@@ -22,11 +25,13 @@
 //   3. flatten: every run points at its root; roots counted per workgroup;
 //   4. rank:    the counts are scanned and each root's entry becomes
 //               -(1 + number of roots before it);
-//   5. labels:  each cell reads its run's entry (and the root's) and writes
-//               the label, 0 for empty cells.
-// Passes 2-4 touch only the occupancy words and the run array (one entry per
-// run); the cells are read once (pass 1) and written once (pass 5). The
+//   5. resolve: every other run's entry becomes its root's;
+//   6. labels:  each cell reads its run's entry and writes the label, 0 for
+//               empty cells.
+// Passes 2-5 touch only the occupancy words and the run array (one entry per
+// run); the cells are read once (pass 1) and written once (pass 6). The
 // result is bit-identical to a sequential flood fill seeded in linear order.
+// Every pass runs over all fields at once, the field in blockIdx.y.
 #include "common.hpp"
 #include "compact.hpp"
 
@@ -34,11 +39,21 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__device__ __forceinline__ int find_root(const int32_t *__restrict__ P, int32_t a) {
-  int32_t b = P[a];
+// The run entries of one field: the entry of run id g * S + r at r * nseg + g.
+struct RunTable {
+  int32_t *P;
+  int64_t nseg;
+  int shift;  // log2 S
+  __device__ __forceinline__ int32_t *at(int32_t id) const {
+    return P + (int64_t)(id & ((1 << shift) - 1)) * nseg + (id >> shift);
+  }
+};
+
+__device__ __forceinline__ int find_root(const RunTable &T, int32_t a) {
+  int32_t b = *T.at(a);
   while (b != a) {
     a = b;
-    b = P[a];
+    b = *T.at(a);
   }
   return a;
 }
@@ -48,11 +63,11 @@ __device__ __forceinline__ int find_root(const int32_t *__restrict__ P, int32_t 
 // an element of the same component of smaller index, so a concurrent hook
 // is never undone for good: a hook that lands on a node that stopped being
 // a root is retried by its union on the node's parent (see unite).
-__device__ __forceinline__ int find_root_halving(int32_t *P, int32_t a) {
-  int32_t b = P[a];
+__device__ __forceinline__ int find_root_halving(const RunTable &T, int32_t a) {
+  int32_t b = *T.at(a);
   while (b != a) {
-    const int32_t g = P[b];
-    if (g != b) P[a] = g;
+    const int32_t g = *T.at(b);
+    if (g != b) *T.at(a) = g;
     a = b;
     b = g;
   }
@@ -63,10 +78,10 @@ __device__ __forceinline__ int find_root_halving(int32_t *P, int32_t a) {
 // reads are fine: a stale parent still points to an element of the same
 // component with a smaller-or-equal index, and the hooking loop retries
 // until it installs the link on a true root.
-__device__ __forceinline__ void unite(int32_t *P, int32_t a, int32_t b) {
+__device__ __forceinline__ void unite(const RunTable &T, int32_t a, int32_t b) {
   while (true) {
-    a = find_root_halving(P, a);
-    b = find_root_halving(P, b);
+    a = find_root_halving(T, a);
+    b = find_root_halving(T, b);
     if (a == b) return;
     if (a > b) {
       int32_t t = a;
@@ -74,7 +89,7 @@ __device__ __forceinline__ void unite(int32_t *P, int32_t a, int32_t b) {
       b = t;
     }
     // hook root b (larger) under a (smaller)
-    int32_t old = atomicMin(&P[b], a);
+    int32_t old = atomicMin(T.at(b), a);
     if (old == b) return;
     b = old;
   }
@@ -83,7 +98,8 @@ __device__ __forceinline__ void unite(int32_t *P, int32_t a, int32_t b) {
 // Each wavefront walks kSegs consecutive 64-cell row segments (linear order
 // of the cells is the order of (segment, lane)), so a workgroup covers
 // 4 * kSegs segments.
-constexpr int kSegs = 8;
+constexpr int kSegs = 8;    // occupancy pass
+constexpr int kSegsW = 16;  // label-writing pass
 
 // Row segment `sgi` (all segments of the field in linear order):
 // row = z * ny + y, x = 64 * seg + lane. Segment counts stay below 2^31 (at
@@ -105,8 +121,9 @@ __device__ __forceinline__ Segment segment_of(int64_t sgi, const SegDiv &dv) {
   s.z = (int)z;
   return s;
 }
+template <int KS>
 __device__ __forceinline__ int64_t first_segment() {
-  return (((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6) * kSegs;
+  return (((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6) * KS;
 }
 
 // Index of the run of m that contains bit i (bit i set).
@@ -118,15 +135,17 @@ __device__ __forceinline__ int run_index(uint64_t m, int i) {
 
 // Pass 1: occupancy words; run entries set to their own ids. The values of
 // the wavefront's kSegs segments are all loaded before the first ballot, so
-// their loads are in flight together.
+// their loads are in flight together; the run entries are then written
+// 64 / kSegs runs of every segment at a time, lane l taking run l / kSegs of
+// segment l % kSegs (adjacent entries for the first runs).
 __global__ __launch_bounds__(kBlock) void k_label_occ(const double *__restrict__ c, double c_eps,
-                                                      uint64_t *__restrict__ occ, int32_t *__restrict__ R, int nx,
-                                                      int ny, int nz, int words, int S, SegDiv dv, int64_t nrun) {
+                                                      uint64_t *__restrict__ occ, RunTable T, int nx, int ny, int nz,
+                                                      int words, SegDiv dv, int64_t nrun) {
   const int lane = threadIdx.x & 63;
-  const int64_t nseg = (int64_t)ny * nz * words, s0 = first_segment();
+  const int64_t nseg = (int64_t)ny * nz * words, s0 = first_segment<kSegs>();
   c += blockIdx.y * ((int64_t)nx * ny * nz);  // field blockIdx.y and its work arrays
   occ += blockIdx.y * nseg;
-  R += blockIdx.y * nrun;
+  T.P += blockIdx.y * nrun;
   double v[kSegs];
 #pragma unroll
   for (int k = 0; k < kSegs; ++k) {
@@ -138,24 +157,36 @@ __global__ __launch_bounds__(kBlock) void k_label_occ(const double *__restrict__
       if (x < nx) v[k] = c[sg.row * nx + x];
     }
   }
+  uint64_t mk[kSegs];
+  int maxr = 0;
 #pragma unroll
   for (int k = 0; k < kSegs; ++k) {
     const int64_t sgi = s0 + k;
-    if (sgi >= nseg) break;  // wave-uniform
-    const uint64_t m = __ballot(v[k] > c_eps);
-    if (lane == 0) occ[sgi] = m;
-    const int nr = __popcll(m & ~(m << 1));
-    if (lane < nr) R[sgi * S + lane] = (int32_t)(sgi * S + lane);
+    mk[k] = (sgi < nseg) ? __ballot(v[k] > c_eps) : 0ull;
+    if (lane == 0 && sgi < nseg) occ[sgi] = mk[k];
+    const int nr = __popcll(mk[k] & ~(mk[k] << 1));
+    maxr = nr > maxr ? nr : maxr;
+  }
+  constexpr int kRuns = 64 / kSegs;  // runs per segment written per round
+  const int k = lane % kSegs;
+  uint64_t mm = mk[0];
+#pragma unroll
+  for (int kk = 1; kk < kSegs; ++kk) mm = (k == kk) ? mk[kk] : mm;
+  const int nr = __popcll(mm & ~(mm << 1));
+  for (int r0 = 0; r0 < maxr; r0 += kRuns) {  // wave-uniform
+    const int r = r0 + lane / kSegs;
+    if (r < nr) T.P[(int64_t)r * nseg + s0 + k] = (int32_t)(((s0 + k) << T.shift) + r);
   }
 }
 
 // Pass 2: unions of each segment's runs with their +y, +z and -x neighbours.
-__global__ __launch_bounds__(kBlock) void k_label_union(const uint64_t *__restrict__ occ, int32_t *R, int nx, int ny,
-                                                        int nz, int words, int S, SegDiv dv, int64_t nrun) {
+__global__ __launch_bounds__(kBlock) void k_label_union(const uint64_t *__restrict__ occ, RunTable T, int nx, int ny,
+                                                        int nz, int words, SegDiv dv, int64_t nrun) {
   const int64_t sgi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t nseg = (int64_t)ny * nz * words;
   occ += blockIdx.y * nseg;
-  R += blockIdx.y * nrun;
+  T.P += blockIdx.y * nrun;
+  const int S = 1 << T.shift;
   if (sgi >= nseg) return;
   const uint64_t m = occ[sgi];
   if (m == 0) return;
@@ -167,7 +198,7 @@ __global__ __launch_bounds__(kBlock) void k_label_union(const uint64_t *__restri
     const int lbit = (sg.seg > 0) ? 63 : (nx - 1) - 64 * (words - 1);
     if (!(lsg == sgi && lbit == 0)) {  // a one-cell row is its own neighbour
       const uint64_t ml = (lsg == sgi) ? m : occ[lsg];
-      if ((ml >> lbit) & 1ull) unite(R, base, (int32_t)(lsg * S) + run_index(ml, lbit));
+      if ((ml >> lbit) & 1ull) unite(T, base, (int32_t)(lsg * S) + run_index(ml, lbit));
     }
   }
   // +y, +z: the first cell of every overlap of a run with a run of that row
@@ -187,38 +218,38 @@ __global__ __launch_bounds__(kBlock) void k_label_union(const uint64_t *__restri
     while (firsts) {
       const int i = __ffsll((unsigned long long)firsts) - 1;
       firsts &= firsts - 1;
-      unite(R, base + run_index(m, i), (int32_t)(nsg * S) + run_index(mn, i));
+      unite(T, base + run_index(m, i), (int32_t)(nsg * S) + run_index(mn, i));
     }
   }
 }
 
 // Roots of the runs of segment sgi (thread-local loop).
-__device__ __forceinline__ int count_roots(const int32_t *R, uint64_t m, int64_t sgi, int S) {
+__device__ __forceinline__ int count_roots(const RunTable &T, uint64_t m, int64_t sgi) {
   const int nr = __popcll(m & ~(m << 1));
   int n = 0;
   for (int r = 0; r < nr; ++r) {
-    const int32_t id = (int32_t)(sgi * S + r);
-    n += (R[id] == id) ? 1 : 0;
+    const int32_t id = (int32_t)((sgi << T.shift) + r);
+    n += (*T.at(id) == id) ? 1 : 0;
   }
   return n;
 }
 
 // Pass 3: every run points at its root; roots counted per workgroup.
-__global__ __launch_bounds__(kBlock) void k_label_flatten(const uint64_t *__restrict__ occ, int32_t *R, int64_t nseg,
-                                                          int S, uint32_t *__restrict__ blockcount, int64_t nrun) {
+__global__ __launch_bounds__(kBlock) void k_label_flatten(const uint64_t *__restrict__ occ, RunTable T, int64_t nseg,
+                                                          uint32_t *__restrict__ blockcount, int64_t nrun) {
   const int64_t sgi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   occ += blockIdx.y * nseg;
-  R += blockIdx.y * nrun;
+  T.P += blockIdx.y * nrun;
   blockcount += blockIdx.y * gridDim.x;
   uint32_t nroot = 0;
   if (sgi < nseg) {
     const uint64_t m = occ[sgi];
     const int nr = __popcll(m & ~(m << 1));
     for (int r = 0; r < nr; ++r) {
-      const int32_t id = (int32_t)(sgi * S + r);
-      const int32_t root = find_root(R, id);
+      const int32_t id = (int32_t)((sgi << T.shift) + r);
+      const int32_t root = find_root(T, id);
       if (root == id) ++nroot;
-      else R[id] = root;
+      else *T.at(id) = root;
     }
   }
   for (int o = 32; o > 0; o >>= 1) nroot += __shfl_xor(nroot, o, 64);
@@ -242,18 +273,18 @@ __global__ void k_copy_total(const int32_t *__restrict__ tot, int64_t ntiles, in
 // Pass 4: each root's entry becomes -(1 + number of roots before it), in
 // run order. blockoff: per-block exclusive offsets within tiles of
 // compact::kTile blocks, tileoff: exclusive offsets of the tiles.
-__global__ __launch_bounds__(kBlock) void k_label_rank(const uint64_t *__restrict__ occ, int32_t *R, int64_t nseg,
-                                                       int S, const int32_t *__restrict__ blockoff,
+__global__ __launch_bounds__(kBlock) void k_label_rank(const uint64_t *__restrict__ occ, RunTable T, int64_t nseg,
+                                                       const int32_t *__restrict__ blockoff,
                                                        const int32_t *__restrict__ tileoff, int64_t nrun,
                                                        int64_t tstride) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t sgi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   occ += blockIdx.y * nseg;
-  R += blockIdx.y * nrun;
+  T.P += blockIdx.y * nrun;
   blockoff += blockIdx.y * gridDim.x;
   tileoff += blockIdx.y * tstride;
   const uint64_t m = (sgi < nseg) ? occ[sgi] : 0ull;
-  const int mine = (sgi < nseg) ? count_roots(R, m, sgi, S) : 0;
+  const int mine = (sgi < nseg) ? count_roots(T, m, sgi) : 0;
   // exclusive prefix of the counts over the workgroup's threads
   int incl = mine;
   for (int o = 1; o < 64; o <<= 1) {
@@ -268,43 +299,56 @@ __global__ __launch_bounds__(kBlock) void k_label_rank(const uint64_t *__restric
   if (mine == 0) return;
   const int nr = __popcll(m & ~(m << 1));
   for (int r = 0; r < nr; ++r) {
-    const int32_t id = (int32_t)(sgi * S + r);
-    if (R[id] == id) R[id] = -(++before);
+    const int32_t id = (int32_t)((sgi << T.shift) + r);
+    if (*T.at(id) == id) *T.at(id) = -(++before);
   }
 }
 
-// Pass 5: label of every cell of the field (0 for empty cells). The
-// occupancy words, then the run entries, then the roots' entries of the
-// wavefront's kSegs segments are each loaded together: every lane loads
-// (from a valid slot when it has no cell) and selects afterwards, since a
-// load under a lane condition is compiled as a branch that waits for it.
-__global__ __launch_bounds__(kBlock) void k_label_write(const uint64_t *__restrict__ occ,
-                                                        const int32_t *__restrict__ R, int32_t *__restrict__ lab,
-                                                        int nx, int ny, int nz, int words, int S, SegDiv dv,
-                                                        int64_t nrun) {
-  const int lane = threadIdx.x & 63;
-  const int64_t nseg = (int64_t)ny * nz * words, s0 = first_segment();
+// Pass 5: every run that is not a root takes its root's entry (the negative
+// label); roots are only read.
+__global__ __launch_bounds__(kBlock) void k_label_resolve(const uint64_t *__restrict__ occ, RunTable T, int64_t nseg,
+                                                          int64_t nrun) {
+  const int64_t sgi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   occ += blockIdx.y * nseg;
-  R += blockIdx.y * nrun;
+  T.P += blockIdx.y * nrun;
+  if (sgi >= nseg) return;
+  const uint64_t m = occ[sgi];
+  const int nr = __popcll(m & ~(m << 1));
+  for (int r = 0; r < nr; ++r) {
+    int32_t *e = T.at((int32_t)((sgi << T.shift) + r));
+    const int32_t v = *e;
+    if (v >= 0) *e = *T.at(v);
+  }
+}
+
+// Pass 6: label of every cell of the field (0 for empty cells). The
+// occupancy words, then the run entries of the wavefront's kSegsW segments
+// are each loaded together: every lane loads (from a valid slot when it has
+// no cell) and selects afterwards, since a load under a lane condition is
+// compiled as a branch that waits for it.
+__global__ __launch_bounds__(kBlock) void k_label_write(const uint64_t *__restrict__ occ, RunTable T,
+                                                        int32_t *__restrict__ lab, int nx, int ny, int nz, int words,
+                                                        SegDiv dv, int64_t nrun) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nseg = (int64_t)ny * nz * words, s0 = first_segment<kSegsW>();
+  occ += blockIdx.y * nseg;
+  T.P += blockIdx.y * nrun;
   lab += blockIdx.y * ((int64_t)nx * ny * nz);
-  uint64_t m[kSegs];
-  int32_t e[kSegs];
+  uint64_t m[kSegsW];
+  int32_t e[kSegsW];
 #pragma unroll
-  for (int k = 0; k < kSegs; ++k) m[k] = (s0 + k < nseg) ? occ[s0 + k] : 0ull;
-  bool on[kSegs];
+  for (int k = 0; k < kSegsW; ++k) m[k] = (s0 + k < nseg) ? occ[s0 + k] : 0ull;
+  bool on[kSegsW];
 #pragma unroll
-  for (int k = 0; k < kSegs; ++k) {
+  for (int k = 0; k < kSegsW; ++k) {
     on[k] = (m[k] >> lane) & 1ull;
     const int64_t sg = (s0 + k < nseg) ? s0 + k : nseg - 1;
-    e[k] = R[sg * S + (on[k] ? run_index(m[k], lane) : 0)];
+    e[k] = T.P[(int64_t)(on[k] ? run_index(m[k], lane) : 0) * nseg + sg];
   }
-  int32_t root[kSegs];
 #pragma unroll
-  for (int k = 0; k < kSegs; ++k) root[k] = R[(on[k] && e[k] >= 0) ? e[k] : 0];
+  for (int k = 0; k < kSegsW; ++k) e[k] = on[k] ? -e[k] : 0;
 #pragma unroll
-  for (int k = 0; k < kSegs; ++k) e[k] = on[k] ? ((e[k] < 0) ? -e[k] : -root[k]) : 0;
-#pragma unroll
-  for (int k = 0; k < kSegs; ++k) {
+  for (int k = 0; k < kSegsW; ++k) {
     const int64_t sgi = s0 + k;
     if (sgi >= nseg) break;  // wave-uniform
     const Segment sg = segment_of(sgi, dv);
@@ -315,17 +359,23 @@ __global__ __launch_bounds__(kBlock) void k_label_write(const uint64_t *__restri
 
 // Workgroups of the per-cell labelling passes (kSegs row segments per
 // wavefront) and of the per-segment passes (one thread per segment).
-static inline int64_t label_blocks(int nx, int ny, int nz) {
+static inline int64_t label_blocks(int nx, int ny, int nz, int segs_per_wave) {
   const int64_t words = (nx + 63) / 64;
-  const int64_t per = (int64_t)(kBlock / 64) * kSegs;
+  const int64_t per = (int64_t)(kBlock / 64) * segs_per_wave;
   return ((int64_t)ny * nz * words + per - 1) / per;
 }
 static inline int64_t segment_blocks(int nx, int ny, int nz) {
   const int64_t words = (nx + 63) / 64;
   return ((int64_t)ny * nz * words + kBlock - 1) / kBlock;
 }
-// Run slots per segment: a segment of w cells holds at most (w + 1) / 2 runs.
-static inline int run_slots(int nx) { return ((nx < 64 ? nx : 64) + 1) / 2; }
+// Run slots per segment, log2: a segment of w cells holds at most
+// (w + 1) / 2 runs; the slots are the next power of two.
+static inline int run_shift(int nx) {
+  const int most = ((nx < 64 ? nx : 64) + 1) / 2;
+  int sh = 0;
+  while ((1 << sh) < most) ++sh;
+  return sh;
+}
 
 // ------------------------------------------------------------------ moments
 //
@@ -681,10 +731,13 @@ __global__ __launch_bounds__(kBlock) void k_shape_sums(const double *__restrict_
 // ulps of the tensor's norm also for the (near-)equal pairs of round or
 // axisymmetric drops, where closed forms through the characteristic
 // polynomial lose half the digits.
+// vol, xyz (nullable): the volume and centroid as well, the centroid as the
+// first cell's centre plus the box centre's offset plus the mean offset from
+// it (the moments' quantities from the shape sums).
 __global__ void k_shape_finish(int32_t K, int nx, int ny, int nz, const int32_t *__restrict__ rootpos,
                                const int32_t *__restrict__ box, const double *__restrict__ part,
                                double *__restrict__ inertia, double *__restrict__ chi, double *__restrict__ vel,
-                               int32_t *__restrict__ extent_err) {
+                               double *__restrict__ vol, double *__restrict__ xyz, int32_t *__restrict__ extent_err) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= K) return;
   const int32_t p0 = rootpos[i];
@@ -741,6 +794,17 @@ __global__ void k_shape_finish(int32_t K, int nx, int ny, int nz, const int32_t 
     vel[3 * i + 2] = S[12] / V;
   }
   const int n[3] = {nx, ny, nz};
+  if (vol) {
+    vol[i] = V;
+    const int r[3] = {p0 % nx, (p0 / nx) % ny, p0 / (nx * ny)};
+    const double g[3] = {gx, gy, gz};
+    for (int a = 0; a < 3; ++a) {
+      double x = (((double)r[a] + 0.5) + (double)((b[2 * a] + b[2 * a + 1]) >> 1)) + g[a];
+      if (x >= (double)n[a]) x -= (double)n[a];
+      if (x < 0.0) x += (double)n[a];
+      xyz[3 * i + a] = x;
+    }
+  }
   for (int e = 0; e < 3; ++e)
     if (2 * (b[2 * e + 1] - b[2 * e]) >= n[e]) atomicOr(extent_err, 1);
 }
@@ -757,17 +821,18 @@ static int label_all(vofmt_ctx *ctx, int nx, int ny, int nz, int T, const double
                      uint64_t *occ, int32_t *runs, uint32_t *blockcount, int32_t *tileoff, int64_t tstride,
                      int32_t *k_dev, hipStream_t stream) {
   const int words = (int)ceil_div(nx, 64);
-  const int S = run_slots(nx);
   const int64_t nseg = (int64_t)ny * nz * words;
-  const int64_t nrun = nseg * S;
-  const unsigned nbc = (unsigned)label_blocks(nx, ny, nz);  // per-cell passes
+  const RunTable R{runs, nseg, run_shift(nx)};
+  const int64_t nrun = nseg << R.shift;
+  const unsigned nbc = (unsigned)label_blocks(nx, ny, nz, kSegs);    // occupancy pass
+  const unsigned nbw = (unsigned)label_blocks(nx, ny, nz, kSegsW);   // label-writing pass
   const unsigned nbs = (unsigned)segment_blocks(nx, ny, nz);  // per-segment passes
   const SegDiv dv{make_fastdiv((uint32_t)words), make_fastdiv((uint32_t)ny)};
   const unsigned nt = (unsigned)T;
-  hipLaunchKernelGGL(k_label_occ, dim3(nbc, nt), dim3(kBlock), 0, stream, c, c_eps, occ, runs, nx, ny, nz, words, S,
-                     dv, nrun);
-  hipLaunchKernelGGL(k_label_union, dim3(nbs, nt), dim3(kBlock), 0, stream, occ, runs, nx, ny, nz, words, S, dv, nrun);
-  hipLaunchKernelGGL(k_label_flatten, dim3(nbs, nt), dim3(kBlock), 0, stream, occ, runs, nseg, S, blockcount, nrun);
+  hipLaunchKernelGGL(k_label_occ, dim3(nbc, nt), dim3(kBlock), 0, stream, c, c_eps, occ, R, nx, ny, nz, words, dv,
+                     nrun);
+  hipLaunchKernelGGL(k_label_union, dim3(nbs, nt), dim3(kBlock), 0, stream, occ, R, nx, ny, nz, words, dv, nrun);
+  hipLaunchKernelGGL(k_label_flatten, dim3(nbs, nt), dim3(kBlock), 0, stream, occ, R, nseg, blockcount, nrun);
   static_assert(kBlock == compact::kBlock, "block counts and the tiled scan share the block size");
   const int64_t ntiles = (nbs + compact::kTile - 1) / compact::kTile;
   int32_t *bc = (int32_t *)blockcount;
@@ -776,10 +841,9 @@ static int label_all(vofmt_ctx *ctx, int nx, int ny, int nz, int T, const double
   hipLaunchKernelGGL(compact::k_scan_totals, dim3(1, nt), dim3(compact::kTile), 0, stream, tileoff, ntiles, tstride);
   hipLaunchKernelGGL(k_copy_total, dim3(1), dim3(64 * ((T + 63) / 64)), 0, stream, tileoff, ntiles, tstride, T,
                      k_dev);
-  hipLaunchKernelGGL(k_label_rank, dim3(nbs, nt), dim3(kBlock), 0, stream, occ, runs, nseg, S, bc, tileoff, nrun,
-                     tstride);
-  hipLaunchKernelGGL(k_label_write, dim3(nbc, nt), dim3(kBlock), 0, stream, occ, runs, lab, nx, ny, nz, words, S, dv,
-                     nrun);
+  hipLaunchKernelGGL(k_label_rank, dim3(nbs, nt), dim3(kBlock), 0, stream, occ, R, nseg, bc, tileoff, nrun, tstride);
+  hipLaunchKernelGGL(k_label_resolve, dim3(nbs, nt), dim3(kBlock), 0, stream, occ, R, nseg, nrun);
+  hipLaunchKernelGGL(k_label_write, dim3(nbw, nt), dim3(kBlock), 0, stream, occ, R, lab, nx, ny, nz, words, dv, nrun);
   return hip_check(ctx, hipGetLastError(), "label kernels");
 }
 
@@ -796,8 +860,8 @@ extern "C" int vofmt_label_drops(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t
   VOFMT_HIP(ctx, hipSetDevice(ctx->device));
   const int64_t nseg = (int64_t)ny * nz * ceil_div(nx, 64);
   const int64_t nbs = segment_blocks(nx, ny, nz);
-  // run ids stay below 2^31: S runs per segment is at most n3 / nseg
-  const int64_t nrun = nseg * run_slots(nx);
+  // run ids stay below 2^31: nseg * S <= n3 (S, a power of two, at most the segment width)
+  const int64_t nrun = nseg << run_shift(nx);
   // work arrays of every field (the run array holds a slot per possible run but is only
   // touched at the runs that exist)
   const int64_t tstride = nbs / compact::kTile + 2;
@@ -871,26 +935,29 @@ extern "C" int vofmt_drop_moments(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_
   return VOFMT_OK;
 }
 
-extern "C" int vofmt_drop_shapes(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t ntracers,
-                                 const double *c, const int32_t *labels, const int32_t *ndrops_host,
-                                 const double *sx, const double *sy, const double *sz, double *inertia, double *chi,
-                                 double *vel, hipStream_t stream) {
+// Shapes (and, with vol and xyz, the moments) of the drops: one scan of the
+// labels and one pass of sums per tracer.
+static int drop_shapes_impl(vofmt_ctx *ctx, const char *fn, bool moments, int32_t nx, int32_t ny, int32_t nz,
+                            int32_t ntracers,
+                            const double *c, const int32_t *labels, const int32_t *ndrops_host, const double *sx,
+                            const double *sy, const double *sz, double *vol, double *xyz, double *inertia,
+                            double *chi, double *vel, hipStream_t stream) {
   if (!ctx) return VOFMT_E_ARG;
-  if (nx < 1 || ny < 1 || nz < 1 || ntracers < 0) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_shapes: bad sizes");
+  if (nx < 1 || ny < 1 || nz < 1 || ntracers < 0) return set_err(ctx, VOFMT_E_ARG, "%s: bad sizes", fn);
   if (ntracers == 0) return VOFMT_OK;
-  if (!c || !labels || !ndrops_host) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_shapes: null pointer");
+  if (!c || !labels || !ndrops_host) return set_err(ctx, VOFMT_E_ARG, "%s: null pointer", fn);
   const bool withu = vel != nullptr;
   if (withu != (sx != nullptr) || withu != (sy != nullptr) || withu != (sz != nullptr))
-    return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_shapes: vel, sx, sy and sz must be given together");
+    return set_err(ctx, VOFMT_E_ARG, "%s: vel, sx, sy and sz must be given together", fn);
   int64_t D = 0;
   for (int t = 0; t < ntracers; ++t) {
-    if (ndrops_host[t] < 0) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_shapes: negative drop count");
+    if (ndrops_host[t] < 0) return set_err(ctx, VOFMT_E_ARG, "%s: negative drop count", fn);
     D += ndrops_host[t];
   }
   if (D == 0) return VOFMT_OK;
-  if (!inertia || !chi) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_shapes: null output");
+  if (!inertia || !chi || (moments && (!vol || !xyz))) return set_err(ctx, VOFMT_E_ARG, "%s: null output", fn);
   const int64_t n3 = (int64_t)nx * ny * nz;
-  if (n3 >= INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_shapes: more than 2^31-1 cells per field");
+  if (n3 >= INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "%s: more than 2^31-1 cells per field", fn);
   VOFMT_HIP(ctx, hipSetDevice(ctx->device));
   int64_t kmax = 0;
   for (int t = 0; t < ntracers; ++t) kmax = ndrops_host[t] > kmax ? ndrops_host[t] : kmax;
@@ -917,13 +984,30 @@ extern "C" int vofmt_drop_shapes(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t
     hipLaunchKernelGGL(k_shape_sums, dim3((unsigned)(K * kSumSplit)), dim3(kBlock), 0, stream, c + (int64_t)t * n3,
                        lab, sx, sy, sz, nx, ny, nz, rootpos, box, part, flags);
     hipLaunchKernelGGL(k_shape_finish, dim3(ceil_div(K, 256)), dim3(256), 0, stream, K, nx, ny, nz, rootpos, box,
-                       part, inertia + 6 * off, chi + off, withu ? vel + 3 * off : nullptr, flags);
+                       part, inertia + 6 * off, chi + off, withu ? vel + 3 * off : nullptr,
+                       vol ? vol + off : nullptr, xyz ? xyz + 3 * off : nullptr, flags);
     VOFMT_HIP(ctx, hipGetLastError());
     off += K;
   }
   VOFMT_HIP(ctx, hipMemcpyAsync(fh, flags, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, stream));
   VOFMT_HIP(ctx, hipStreamSynchronize(stream));
-  if (fh[0] & 2) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_shapes: labels do not match ndrops_host");
-  if (fh[0]) return set_err(ctx, VOFMT_E_EXTENT, "vofmt_drop_shapes: a drop spans half the box or more");
+  if (fh[0] & 2) return set_err(ctx, VOFMT_E_ARG, "%s: labels do not match ndrops_host", fn);
+  if (fh[0]) return set_err(ctx, VOFMT_E_EXTENT, "%s: a drop spans half the box or more", fn);
   return VOFMT_OK;
+}
+
+extern "C" int vofmt_drop_shapes(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t ntracers,
+                                 const double *c, const int32_t *labels, const int32_t *ndrops_host,
+                                 const double *sx, const double *sy, const double *sz, double *inertia, double *chi,
+                                 double *vel, hipStream_t stream) {
+  return drop_shapes_impl(ctx, "vofmt_drop_shapes", false, nx, ny, nz, ntracers, c, labels, ndrops_host, sx, sy, sz,
+                          nullptr, nullptr, inertia, chi, vel, stream);
+}
+
+extern "C" int vofmt_drop_moments_shapes(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t ntracers,
+                                         const double *c, const int32_t *labels, const int32_t *ndrops_host,
+                                         const double *sx, const double *sy, const double *sz, double *vol,
+                                         double *xyz, double *inertia, double *chi, double *vel, hipStream_t stream) {
+  return drop_shapes_impl(ctx, "vofmt_drop_moments_shapes", true, nx, ny, nz, ntracers, c, labels, ndrops_host, sx,
+                          sy, sz, vol, xyz, inertia, chi, vel, stream);
 }

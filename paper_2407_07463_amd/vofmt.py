@@ -49,6 +49,8 @@ _SIGNATURES = {
     "vofmt_csf_force": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _d, _vp, _vp, _vp, _vp]),
     "vofmt_drop_shapes": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                          _vp]),
+    "vofmt_drop_moments_shapes": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                                 _vp, _vp, _vp, _vp, _vp]),
     "vofmt_recolor_tracers": (ctypes.c_int, [_vp, _i32, _i32, _i32, _P_i32, _i32, _vp, _vp, _vp, _d, _vp, _P_i32,
                                              _vp]),
     "vofmt_recolor_tracers_stencil": (ctypes.c_int, [_vp, _i32, _i32, _i32, _P_i32, _i32, _vp, _vp, _vp, _vp,
@@ -249,6 +251,23 @@ class Context:
         return self._check(load().vofmt_drop_shapes(self.h, nx, ny, nz, ntr, _ptr(c), _ptr(labels), nd.ctypes.data,
                                                     *sp, _ptr(inertia), _ptr(chi),
                                                     _ptr(vel) if vel is not None else None, _stream(stream)))
+
+    def drop_moments_shapes(self, c, labels, ndrops, vol, xyz, inertia, chi, s=None, vel=None, stream=None):
+        """Volumes [D], centroids [D][3], inertia tensors [D][6], aspect ratios [D] and, with
+        s = (sx, sy, sz) and vel [D][3], mean velocities, in one pass over the drops."""
+        _require(c, labels, vol, xyz, inertia, chi)
+        if (s is None) != (vel is None):
+            raise ValueError("drop_moments_shapes: give s and vel together")
+        sp = [None, None, None]
+        if s is not None:
+            _require(*s, vel)
+            sp = [_ptr(a) for a in s]
+        nx, ny, nz = _dims(c)
+        ntr = int(c.shape[0]) if c.dim() == 4 else 1
+        nd = np.ascontiguousarray(ndrops, dtype=np.int32)
+        return self._check(load().vofmt_drop_moments_shapes(
+            self.h, nx, ny, nz, ntr, _ptr(c), _ptr(labels), nd.ctypes.data, *sp, _ptr(vol), _ptr(xyz), _ptr(inertia),
+            _ptr(chi), _ptr(vel) if vel is not None else None, _stream(stream)))
 
     def csf_force(self, c, kappa, gamma: float, fx, fy, fz, stream=None):
         """Surface-tension force on the lower faces; c, kappa: [N][nz][ny][nx]

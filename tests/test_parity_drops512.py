@@ -194,6 +194,44 @@ def test_drop_shapes(ctx, drops512, oracle_labels):
     assert 1.0 <= gchi.min() and np.median(gchi) < 1.1
 
 
+def test_drop_moments_shapes(ctx, drops512, oracle_labels):
+    """The combined pass: shapes bit-identical to drop_shapes, volumes to drop_moments (the same
+    sums in the same order), centroids (summed about the box centre) within the moments' bound
+    of the oracle's."""
+    import torch
+
+    c = drops512["c"]
+    s = [torch.from_numpy(drops512[k]).to("cuda:0") for k in ("sx", "sy", "sz")]
+    note("drop moments + shapes drops512 (full size, with velocity)")
+    olab, ond = oracle_labels
+    tc = torch.from_numpy(c).to("cuda:0")
+    lab = torch.from_numpy(olab).to("cuda:0")
+    D = int(ond.sum())
+
+    def z(*shape):
+        return torch.zeros(shape, dtype=torch.float64, device="cuda:0")
+
+    vol, xyz, inertia, chi, vel = z(D), z(D, 3), z(D, 6), z(D), z(D, 3)
+    ctx.drop_moments_shapes(tc, lab, ond, vol, xyz, inertia, chi, s, vel)
+    vol1, xyz1, inertia1, chi1, vel1 = z(D), z(D, 3), z(D, 6), z(D), z(D, 3)
+    ctx.drop_moments(tc, lab, ond, vol1, xyz1)
+    ctx.drop_shapes(tc, lab, ond, inertia1, chi1, s, vel1)
+    torch.cuda.synchronize()
+    for a, b in ((vol, vol1), (inertia, inertia1), (chi, chi1), (vel, vel1)):
+        assert torch.equal(a, b)
+    g = 0
+    gx = xyz.cpu().numpy()
+    del tc, lab
+    for t in range(c.shape[0]):
+        k = int(ond[t])
+        _, ox, rc = oracle.drop_moments(c[t], olab[t], k)
+        assert rc == 0
+        d = np.abs(gx[g:g + k] - ox)
+        d = np.minimum(d, 512.0 - d)  # periodic
+        assert d.max() <= 1e-12 * 512
+        g += k
+
+
 def test_csf_force(ctx, drops512):
     """All eight tracers, with a synthetic curvature on the interface cells
     (0.3 (0.5 - c), NaN elsewhere) so that every branch of the face rule
