@@ -19,6 +19,7 @@ namespace {
 
 struct BoxDev {
   int nx, ny, nz, ntr, words;
+  int xwpb;  // x-sweep: 0 whole-row wavefronts (a row's cells fit one list region), else 4 per workgroup
   Divisors dv;
   double *f[2];  // the caller's field and its ping-pong copy
   const double *s[3];
@@ -83,8 +84,12 @@ __global__ __launch_bounds__(256) void k_stream_b(const BoxDev *__restrict__ box
     const int bx = (int)(lb % sg.gx);
     const int by = (int)((lb / sg.gx) % sg.gy);
     const int bz = (int)(lb / ((int64_t)sg.gx * sg.gy));
-    stream_body<D, G>(b.f[par], b.f[par ^ 1], b.s[D], b.fmix, b.bits, write_cc, sg.t0, b.nx, b.ny, b.nz, b.words,
-                      chunk, b.list[nxt], b.counts[nxt], sg.region0, rsize, bx, by, bz, sg.gx, sg.gy);
+    if (D == 0 && b.xwpb == 0)  // uniform over the workgroup
+      stream_body<D, G, 0>(b.f[par], b.f[par ^ 1], b.s[D], b.fmix, b.bits, write_cc, sg.t0, b.nx, b.ny, b.nz,
+                           b.words, chunk, b.list[nxt], b.counts[nxt], sg.region0, rsize, bx, by, bz, sg.gx, sg.gy);
+    else
+      stream_body<D, G>(b.f[par], b.f[par ^ 1], b.s[D], b.fmix, b.bits, write_cc, sg.t0, b.nx, b.ny, b.nz, b.words,
+                        chunk, b.list[nxt], b.counts[nxt], sg.region0, rsize, bx, by, bz, sg.gx, sg.gy);
   }
 }
 
@@ -117,6 +122,11 @@ struct Plan {
 };
 
 int kind_of(int g) { return g == 4 ? 0 : (g == 2 ? 1 : 2); }
+
+// x-sweep layout of a box: whole-row wavefronts when a row has at most `chunk`
+// segments (its cells then fit a wavefront's list region), else 4 wavefronts
+// per workgroup sharing segment ends through LDS.
+int box_xwpb(int words, int chunk) { return words <= chunk ? 0 : 4; }
 
 }  // namespace
 
@@ -160,7 +170,8 @@ static size_t plan_layout(const vofmt_box *boxes, int nboxes, int chunk, Plan &p
     const vofmt_box &b = boxes[i];
     const int64_t n3 = (int64_t)b.nx * b.ny * b.nz;
     const int words = (int)ceil_div(b.nx, 64);
-    const int64_t maxreg = max_regions(b.nx, b.ny, b.nz, b.ntracers, chunk);
+    const int xw = box_xwpb(words, chunk);
+    const int64_t maxreg = max_regions(b.nx, b.ny, b.nz, b.ntracers, chunk, xw);
     const size_t field = sizeof(double) * (size_t)n3 * b.ntracers;
     box_off[6 * i + 0] = off;  // ping-pong field
     off = align256(off + field);
@@ -179,6 +190,7 @@ static size_t plan_layout(const vofmt_box *boxes, int nboxes, int chunk, Plan &p
     d.nz = b.nz;
     d.ntr = b.ntracers;
     d.words = words;
+    d.xwpb = xw;
     d.dv.n3 = make_fastdiv((uint32_t)n3);
     d.dv.nx = make_fastdiv((uint32_t)b.nx);
     d.dv.ny = make_fastdiv((uint32_t)b.ny);
@@ -211,7 +223,8 @@ static size_t plan_layout(const vofmt_box *boxes, int nboxes, int chunk, Plan &p
       const vofmt_box &b = boxes[i];
       Seg s{};
       s.item0 = pl.items_plic[d];
-      s.nitems = stream_waves(d, b.nx, b.ny, b.nz, chunk) * num_groups(b.ntracers);
+      const int xw = box_xwpb((b.nx + 63) / 64, chunk);
+      s.nitems = stream_waves(d, b.nx, b.ny, b.nz, chunk, xw) * num_groups(b.ntracers);
       s.box = i;
       seg_all.push_back(s);
       pl.items_plic[d] += s.nitems;
@@ -223,9 +236,10 @@ static size_t plan_layout(const vofmt_box *boxes, int nboxes, int chunk, Plan &p
       begin_table(pl.off_stream[d][kind], pl.n_stream[d][kind], pl.items_stream[d][kind]);
       for (int i = 0; i < nboxes; ++i) {
         const vofmt_box &b = boxes[i];
-        const Tiles tg = stream_tiles(d, b.nx, b.ny, b.nz, chunk);
+        const int xw = box_xwpb((b.nx + 63) / 64, chunk);
+        const Tiles tg = stream_tiles(d, b.nx, b.ny, b.nz, chunk, xw);
         const int gx = tg.gx, gy = tg.gy, gz = tg.gz;
-        const int64_t per = stream_waves(d, b.nx, b.ny, b.nz, chunk);
+        const int64_t per = stream_waves(d, b.nx, b.ny, b.nz, chunk, xw);
         int64_t region0 = 0;
         for (int t = 0; t < b.ntracers;) {
           const int g = group_size(b.ntracers - t);
