@@ -31,6 +31,7 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-Wno-unused-function",
+    "-Werror=shadow",  # a local that hides a parameter or outer local is an error
     f"-I{INCLUDE}",
     f"-I{CSRC}",
 ]
