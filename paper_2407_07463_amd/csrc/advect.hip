@@ -1,8 +1,6 @@
 // Plain advection entry points: one box, one launch per pass.
 // The kernels are thin wrappers around the shared sweep bodies: every sweep
 // is a PLIC pass over the mixed cells and one streaming pass per tracer group.
-#include <vector>
-
 #include "advect_kernels.hpp"
 
 using namespace advect;
@@ -14,8 +12,8 @@ constexpr int kXWaves = 8;  // wavefronts per workgroup of the x-sweep: a 512-ce
 
 __global__ __launch_bounds__(256) void k_scan_mixed(const double *__restrict__ c, int64_t total,
                                                     uint32_t *__restrict__ list, int *__restrict__ counts,
-                                                    int64_t nregions, int rsize, uint32_t first) {
-  scan_body(c, total, list, counts, nregions, rsize, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6, first);
+                                                    int64_t nregions, int rsize) {
+  scan_body(c, total, list, counts, nregions, rsize, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
 }
 
 template <int D>
@@ -76,22 +74,8 @@ struct SweepBuffers {
   uint64_t *bits;
   uint32_t *list[2];
   int *counts[2];
+  int64_t nregions[2];  // regions filled into each list
   int rsize;
-};
-
-// A chain of consecutive tracer groups [g0, g1) (tracers [t0, t1)) advanced
-// on one stream. The groups never read each other's data -- fields, face
-// fluxes and c > 0.5 words are per tracer, and each chain owns the list
-// regions [space0, space0 + nspace) of both lists -- so two chains run
-// concurrently: the latency-bound PLIC pass of one overlaps the
-// bandwidth-bound streaming passes of the other. The chains are not kept in
-// step, so one may write a list while the other still reads its own regions
-// of it from an earlier sweep: the spaces never overlap.
-struct Chain {
-  int g0, g1, t0, t1;
-  int64_t space0, nspace;
-  int64_t nreg[2];  // regions filled into each list (from space0)
-  hipStream_t st;
 };
 
 static const char *stream_name(int d, int g) {
@@ -128,42 +112,40 @@ static void launch_stream(vofmt_ctx *ctx, const double *cin, double *cout, const
 
 template <int D>
 static void launch_sweep_axis(vofmt_ctx *ctx, const double *cin, double *cout, const double *s, SweepBuffers &sb,
-                              int wcc, int cur, int nx, int ny, int nz, int words, int chunk, Chain &ch,
-                              const std::vector<int> &gsize) {
+                              int wcc, int cur, int nx, int ny, int nz, int ntr, int words, int chunk,
+                              hipStream_t stream) {
   const int nxt = cur ^ 1;
+  const int64_t nreg = sb.nregions[cur];
   Divisors dv;
   dv.n3 = make_fastdiv((uint32_t)((int64_t)nx * ny * nz));
   dv.nx = make_fastdiv((uint32_t)nx);
   dv.ny = make_fastdiv((uint32_t)ny);
   static const char *plic_names[3] = {"k_plic<0>", "k_plic<1>", "k_plic<2>"};
-  const int64_t nreg = ch.nreg[cur];
-  if (nreg > 0) {
-    const int rec = prof_begin(ctx, plic_names[D], ch.st);
-    hipLaunchKernelGGL((k_plic<D>), dim3(ceil_div(nreg, 4)), dim3(256), 0, ch.st, cin, s,
-                       sb.list[cur] + ch.space0 * sb.rsize, sb.counts[cur] + ch.space0, nreg, sb.rsize,
-                       sb.fmix, nx, ny, nz, dv);
-    prof_end(ctx, rec, ch.st);
-  }
+  const int rec = prof_begin(ctx, plic_names[D], stream);
+  hipLaunchKernelGGL((k_plic<D>), dim3(ceil_div(nreg, 4)), dim3(256), 0, stream, cin, s, sb.list[cur],
+                     sb.counts[cur], nreg, sb.rsize, sb.fmix, nx, ny, nz, dv);
+  prof_end(ctx, rec, stream);
   const int64_t per = stream_waves(D, nx, ny, nz, chunk, D == 0 ? x_wpb(words, chunk) : 4);
-  int t = ch.t0;
-  static_assert(kMaxGroup == 4, "streaming passes are instantiated for groups of 4, 2 and 1");
-  for (int gi = ch.g0; gi < ch.g1; ++gi) {
-    const int g = gsize[gi];
-    const int64_t region0 = ch.space0 + (gi - ch.g0) * per;
-    if (g == 4) launch_stream<D, 4>(ctx, cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, ch.st);
-    else if (g == 2) launch_stream<D, 2>(ctx, cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, ch.st);
-    else launch_stream<D, 1>(ctx, cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, ch.st);
+  int64_t region0 = 0;
+  int t = 0;
+  while (t < ntr) {
+    const int g = group_size(ntr - t);
+    static_assert(kMaxGroup == 4, "streaming passes are instantiated for groups of 4, 2 and 1");
+    if (g == 4) launch_stream<D, 4>(ctx, cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, stream);
+    else if (g == 2) launch_stream<D, 2>(ctx, cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, stream);
+    else launch_stream<D, 1>(ctx, cin, cout, s, sb, wcc, t, nx, ny, nz, words, chunk, nxt, region0, stream);
     t += g;
+    region0 += per;
   }
-  ch.nreg[nxt] = (ch.g1 - ch.g0) * per;
+  sb.nregions[nxt] = region0;
 }
 
-static void launch_sweep(vofmt_ctx *ctx, int d, const double *cin, double *cout, const double *s, SweepBuffers &sb,
-                         int wcc, int cur, int nx, int ny, int nz, int words, int chunk, Chain &ch,
-                         const std::vector<int> &gsize) {
-  if (d == 0) launch_sweep_axis<0>(ctx, cin, cout, s, sb, wcc, cur, nx, ny, nz, words, chunk, ch, gsize);
-  else if (d == 1) launch_sweep_axis<1>(ctx, cin, cout, s, sb, wcc, cur, nx, ny, nz, words, chunk, ch, gsize);
-  else launch_sweep_axis<2>(ctx, cin, cout, s, sb, wcc, cur, nx, ny, nz, words, chunk, ch, gsize);
+static int launch_sweep(vofmt_ctx *ctx, int d, const double *cin, double *cout, const double *s, SweepBuffers &sb,
+                        int wcc, int cur, int nx, int ny, int nz, int ntr, int words, int chunk, hipStream_t stream) {
+  if (d == 0) launch_sweep_axis<0>(ctx, cin, cout, s, sb, wcc, cur, nx, ny, nz, ntr, words, chunk, stream);
+  else if (d == 1) launch_sweep_axis<1>(ctx, cin, cout, s, sb, wcc, cur, nx, ny, nz, ntr, words, chunk, stream);
+  else launch_sweep_axis<2>(ctx, cin, cout, s, sb, wcc, cur, nx, ny, nz, ntr, words, chunk, stream);
+  return (int)hipGetLastError();
 }
 
 extern "C" int vofmt_advect(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t ntracers, double *c,
@@ -187,88 +169,46 @@ extern "C" int vofmt_advect(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, 
   double *tmp = (double *)scratch(ctx, SLOT_PINGPONG, field_bytes);
   double *fmix = (double *)scratch(ctx, SLOT_FMIX, field_bytes);
   uint64_t *bits = (uint64_t *)scratch(ctx, SLOT_CCBITS, sizeof(uint64_t) * (size_t)ntracers * nz * ny * words);
-  // list regions: per chain, enough for its largest sweep and for its initial scan
+  // list regions: enough for the largest sweep launch set and for the initial scan
   const int rsize = region_size(kChunk);
-  int64_t maxper = 0;  // streaming wavefronts (regions) of one group, largest over the axes
-  for (int d = 0; d < 3; ++d) {
-    const int64_t w = stream_waves(d, nx, ny, nz, kChunk, d == 0 ? x_wpb(words, kChunk) : 4);
-    maxper = w > maxper ? w : maxper;
-  }
-  // tracer groups, split into one or two chains
-  std::vector<int> gsize;
-  for (int t = 0; t < ntracers; t += gsize.back()) gsize.push_back(group_size(ntracers - t));
-  const int ng = (int)gsize.size();
-  const int nch = ng >= 2 ? 2 : 1;
-  Chain ch[2];
-  ch[0].g0 = 0;
-  ch[0].g1 = (nch == 2) ? (ng + 1) / 2 : ng;
-  ch[1].g0 = ch[0].g1;
-  ch[1].g1 = ng;
-  // the initial lists: each chain's tracers scanned into its own space
-  int64_t nlreg = 0;
-  for (int k = 0, t = 0; k < nch; ++k) {
-    ch[k].t0 = t;
-    for (int gi = ch[k].g0; gi < ch[k].g1; ++gi) t += gsize[gi];
-    ch[k].t1 = t;
-    const int64_t tot = (int64_t)(ch[k].t1 - ch[k].t0) * n3;
-    const int64_t sweepregs = (int64_t)(ch[k].g1 - ch[k].g0) * maxper;
-    ch[k].nreg[0] = (tot + rsize - 1) / rsize;
-    ch[k].nreg[1] = 0;
-    ch[k].space0 = nlreg;
-    ch[k].nspace = sweepregs > ch[k].nreg[0] ? sweepregs : ch[k].nreg[0];
-    nlreg += ch[k].nspace;
-  }
-  uint32_t *lists = (uint32_t *)scratch(ctx, SLOT_MIXLIST, sizeof(uint32_t) * 2 * (size_t)nlreg * rsize);
-  int *counts = (int *)scratch(ctx, SLOT_COUNTS, sizeof(int) * 2 * (size_t)nlreg);
+  const int64_t maxreg = max_regions(nx, ny, nz, ntracers, kChunk, x_wpb(words, kChunk));
+  const int64_t total = (int64_t)ntracers * n3;
+  const int64_t scanreg = (total + rsize - 1) / rsize;
+  uint32_t *lists = (uint32_t *)scratch(ctx, SLOT_MIXLIST, sizeof(uint32_t) * 2 * (size_t)maxreg * rsize);
+  int *counts = (int *)scratch(ctx, SLOT_COUNTS, sizeof(int) * 2 * (size_t)maxreg);
   if (!tmp || !fmix || !bits || !lists || !counts) return VOFMT_E_NOMEM;
   SweepBuffers sb;
   sb.fmix = fmix;
   sb.bits = bits;
   sb.list[0] = lists;
-  sb.list[1] = lists + (size_t)nlreg * rsize;
+  sb.list[1] = lists + (size_t)maxreg * rsize;
   sb.counts[0] = counts;
-  sb.counts[1] = counts + nlreg;
+  sb.counts[1] = counts + maxreg;
+  sb.nregions[0] = scanreg;
+  sb.nregions[1] = 0;
   sb.rsize = rsize;
   const int chunk = kChunk;
-  ch[0].st = stream;
-  if (nch == 2) {  // fork the second chain's stream from the caller's
-    if (!ctx->aux_stream) VOFMT_HIP(ctx, hipStreamCreateWithFlags(&ctx->aux_stream, hipStreamNonBlocking));
-    if (!ctx->fork_ev) VOFMT_HIP(ctx, hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
-    if (!ctx->join_ev) VOFMT_HIP(ctx, hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming));
-    ch[1].st = ctx->aux_stream;
-    VOFMT_HIP(ctx, hipEventRecord(ctx->fork_ev, stream));
-    VOFMT_HIP(ctx, hipStreamWaitEvent(ch[1].st, ctx->fork_ev, 0));
-  }
-  for (int k = 0; k < nch; ++k) {
-    const int rec = prof_begin(ctx, "k_scan_mixed", ch[k].st);
-    hipLaunchKernelGGL(k_scan_mixed, dim3(ceil_div(ch[k].nreg[0], 4)), dim3(256), 0, ch[k].st,
-                       c + (int64_t)ch[k].t0 * n3, (int64_t)(ch[k].t1 - ch[k].t0) * n3,
-                       sb.list[0] + ch[k].space0 * rsize, sb.counts[0] + ch[k].space0, ch[k].nreg[0], rsize,
-                       (uint32_t)((int64_t)ch[k].t0 * n3));
-    prof_end(ctx, rec, ch[k].st);
-  }
-  hipError_t err = hipGetLastError();
+  // mixed cells of the input field
+  const int rec = prof_begin(ctx, "k_scan_mixed", stream);
+  hipLaunchKernelGGL(k_scan_mixed, dim3(ceil_div(scanreg, 4)), dim3(256), 0, stream, c, total, sb.list[0],
+                     sb.counts[0], scanreg, rsize);
+  prof_end(ctx, rec, stream);
+  VOFMT_HIP(ctx, hipGetLastError());
   int cur_list = 0;
   double *cur = c, *nxt = tmp;
-  for (int32_t st = 0; st < nsteps && err == hipSuccess; ++st) {
+  for (int32_t st = 0; st < nsteps; ++st) {
     const int64_t g = step0 + st;
-    for (int r = 0; r < 3 && err == hipSuccess; ++r) {
+    for (int r = 0; r < 3; ++r) {
       const int d = (int)((g + r) % 3);
       const int wcc = (r == 0);
-      for (int k = 0; k < nch; ++k)
-        launch_sweep(ctx, d, cur, nxt, s3[d], sb, wcc, cur_list, nx, ny, nz, words, chunk, ch[k], gsize);
-      err = hipGetLastError();
+      int rc = launch_sweep(ctx, d, cur, nxt, s3[d], sb, wcc, cur_list, nx, ny, nz, ntracers, words, chunk, stream);
+      if (rc) return hip_check(ctx, (hipError_t)rc, "sweep launch");
       cur_list ^= 1;
       double *t = cur;
       cur = nxt;
       nxt = t;
     }
   }
-  if (nch == 2) {  // the caller's stream waits for the second chain (also after a failed launch)
-    VOFMT_HIP(ctx, hipEventRecord(ctx->join_ev, ch[1].st));
-    VOFMT_HIP(ctx, hipStreamWaitEvent(stream, ctx->join_ev, 0));
-  }
-  if (err != hipSuccess) return hip_check(ctx, err, "sweep launch");
   if (cur != c)
     VOFMT_HIP(ctx, hipMemcpyAsync(c, cur, sizeof(double) * (size_t)n3 * ntracers, hipMemcpyDeviceToDevice, stream));
   return VOFMT_OK;

@@ -76,11 +76,8 @@ struct Divisors {
 
 // Mixed cells of the initial field: wavefront w scans tracer-cells
 // [w*rsize, (w+1)*rsize) of the whole array.
-// Entries are first + the index in c (first: the tracer-cell of the whole
-// array that c starts at).
 __device__ __forceinline__ void scan_body(const double *__restrict__ c, int64_t total, uint32_t *__restrict__ list,
-                                          int *__restrict__ counts, int64_t nregions, int rsize, int64_t w,
-                                          uint32_t first) {
+                                          int *__restrict__ counts, int64_t nregions, int rsize, int64_t w) {
   const int lane = threadIdx.x & 63;
   if (w >= nregions) return;
   uint32_t *out = list + w * rsize;
@@ -90,7 +87,7 @@ __device__ __forceinline__ void scan_body(const double *__restrict__ c, int64_t 
     const int64_t q = base + lane;
     const bool mixed = (q < total) && plic::is_mixed(c[q]);
     const uint64_t mask = __ballot(mixed);
-    if (mixed) out[n + __popcll(mask & below)] = first + (uint32_t)q;
+    if (mixed) out[n + __popcll(mask & below)] = (uint32_t)q;
     n += __popcll(mask);
   }
   if (lane == 0) counts[w] = n;

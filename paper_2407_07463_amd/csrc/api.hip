@@ -151,9 +151,6 @@ extern "C" void vofmt_destroy(vofmt_ctx *ctx) {
   (void)hipDeviceSynchronize();
   if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
   if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
-  if (ctx->aux_stream) (void)hipStreamDestroy(ctx->aux_stream);
-  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
-  if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
   for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
   for (int i = 0; i < kNumSlots; ++i)
     if (ctx->buf[i]) (void)hipFree(ctx->buf[i]);

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void k_scan_b(const BoxDev *__restrict__ boxes
     const Seg sg = segs[find_seg(segs, nseg, gw)];
     const BoxDev &b = boxes[sg.box];
     const int64_t total = (int64_t)b.ntr * b.nx * b.ny * b.nz;
-    scan_body(b.f[0], total, b.list[0], b.counts[0], sg.nitems, rsize, gw - sg.item0, 0u);
+    scan_body(b.f[0], total, b.list[0], b.counts[0], sg.nitems, rsize, gw - sg.item0);
   }
 }
 

@@ -32,11 +32,6 @@ struct vofmt_ctx {
   // stream it was captured on, its key, and the host copy of its tables.
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t graph = nullptr;
-  // Advection: a second stream (default priority) for the second chain of
-  // tracer groups, and the events that fork it from and join it to the
-  // caller's stream.
-  hipStream_t aux_stream = nullptr;
-  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   std::string graph_key;
   std::vector<uint8_t> tables;
   // Per-launch timing (vofmt_profile_start / vofmt_profile_stop).
