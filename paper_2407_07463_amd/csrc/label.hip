@@ -154,7 +154,9 @@ __global__ __launch_bounds__(kBlock) void k_label_occ(const double *__restrict__
     if (sgi < nseg) {  // wave-uniform
       const Segment sg = segment_of(sgi, dv);
       const int x = sg.seg * 64 + lane;
-      if (x < nx) v[k] = c[sg.row * nx + x];
+      // read once in this call: a non-temporal load leaves the caches to
+      // the run entries the later passes reuse
+      if (x < nx) v[k] = __builtin_nontemporal_load(&c[sg.row * nx + x]);
     }
   }
   uint64_t mk[kSegs];
@@ -353,7 +355,7 @@ __global__ __launch_bounds__(kBlock) void k_label_write(const uint64_t *__restri
     if (sgi >= nseg) break;  // wave-uniform
     const Segment sg = segment_of(sgi, dv);
     const int x = sg.seg * 64 + lane;
-    if (x < nx) lab[sg.row * nx + x] = e[k];
+    if (x < nx) __builtin_nontemporal_store(e[k], &lab[sg.row * nx + x]);  // streamed out
   }
 }
 
