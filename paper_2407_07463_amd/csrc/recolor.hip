@@ -246,15 +246,14 @@ static StencilPairs make_stencil_pairs() {
   return sp;
 }
 
-// Steps 1-3 read literally, one wavefront per row segment (t, z, y, w), one
-// lane per centre cell: the centre is empty and the cells at +o and -o of the
-// 5x5x5 stencil are both occupied. Lanes 0..49 first build the 64-bit
-// occupancy windows of the 25 rows y-2..y+2, z-2..z+2 (cells x0-2 .. x0+61
-// and x0+62 .. x0+125), which every lane then reads; each lane forms the
-// 5-bit neighbourhood of its cell in every row, and from them a mask of the
-// opposite pairs with both cells occupied. Only for those pairs are the two
-// labels loaded; if they differ, the two drops are marked neighbours in both
-// directions.
+// Steps 1-3 within tracer t for the 64 cells of one row segment. Lane k < 62
+// takes the opposite pair k of the stencil, offsets +o and -o, and forms over
+// the segment's cells at once, from three 64-bit windows of occupancy bits,
+// the cells whose centre is empty (label 0) and whose cells at +o and -o are
+// both occupied; for each such cell it loads the two labels and records the
+// two drops as neighbours when they differ (Step 3). Every pair is tested for
+// every cell, as in the definition; a lane's bit operations replace 64
+// per-cell tests.
 __global__ __launch_bounds__(kBlock) void k_stencil_edges(const int32_t *__restrict__ lab,
                                                           const uint64_t *__restrict__ occ, int nx, int ny, int nz,
                                                           int ntr, int words, TracerOffsets to, StencilPairs sp,
@@ -272,48 +271,54 @@ __global__ __launch_bounds__(kBlock) void k_stencil_edges(const int32_t *__restr
   const int x0 = 64 * w;
   // offsets reach 2 cells: one conditional wrap when the axis has 3 cells or more
   auto wrap2 = [](int v, int n) { return n >= 3 ? (v < 0 ? v + n : (v >= n ? v - n : v)) : wrap_any(v, n); };
-  // lane L < 50 builds window L & 1 of row L >> 1 (row = 5 (dy + 2) + (dz + 2))
-  uint64_t mine = 0;
-  if (lane < 50) {
-    const int row = lane >> 1, dy = row / 5 - 2, dz = row % 5 - 2;
-    const uint64_t *rw = occ_t + ((int64_t)wrap2(z + dz, nz) * ny + wrap2(y + dy, ny)) * words;
-    mine = row_window(rw, nx, (lane & 1) ? x0 + 62 : x0 - 2);
+  const int nvalid = nx - x0 < 64 ? nx - x0 : 64;
+  const uint64_t valid = nvalid == 64 ? ~0ull : ((1ull << nvalid) - 1ull);
+  const uint64_t empty = ~occ_t[r * words + w] & valid;  // bit i: cell x0 + i has no drop of tracer t
+  uint64_t cand = 0;
+  int ox = 0, oy = 0, oz = 0;
+  if (lane < 62) {
+    ox = sp.o[lane][0];
+    oy = sp.o[lane][1];
+    oz = sp.o[lane][2];
+    const uint64_t *rp = occ_t + ((int64_t)wrap2(z + oz, nz) * ny + wrap2(y + oy, ny)) * words;
+    const uint64_t *rm = occ_t + ((int64_t)wrap2(z - oz, nz) * ny + wrap2(y - oy, ny)) * words;
+    // bit i: cell x0 + i + ox of the row at +o, cell x0 + i - ox of the row at -o
+    cand = row_window(rp, nx, x0 + ox) & row_window(rm, nx, x0 - ox) & empty;
   }
-  if (__ballot(mine != 0ull) == 0ull) return;  // no occupied cell near the segment
-  const int x = x0 + lane;
-  // bit k of nb[row] is the occupancy of cell (x - 2 + k) in that row
-  uint32_t nb[25];
+  if (__ballot(cand != 0ull) == 0ull) return;  // no pair around any empty cell of the segment
+  const int64_t rowp = ((int64_t)t * nz + wrap2(z + oz, nz)) * ny + wrap2(y + oy, ny);
+  const int64_t rowm = ((int64_t)t * nz + wrap2(z - oz, nz)) * ny + wrap2(y - oy, ny);
+  const int64_t qc = (((int64_t)t * nz + z) * ny + y) * nx + x0;  // a cell of the segment (x0 < nx)
+  // The labels of up to kBatch cells are loaded together (every lane loads,
+  // from the segment's first cell when it has no cell left, and selects
+  // afterwards); a pair of drops just recorded by this lane is not recorded
+  // again (the cells of a gap between two drops mostly see the same pair).
+  constexpr int kBatch = 8;
+  int32_t last_a = 0, last_b = 0;
+  while (cand) {
+    int32_t la[kBatch], lb[kBatch];
+    bool has[kBatch];
 #pragma unroll
-  for (int row = 0; row < 25; ++row) {
-    const uint32_t alo = __builtin_amdgcn_readlane((uint32_t)mine, 2 * row);
-    const uint32_t ahi = __builtin_amdgcn_readlane((uint32_t)(mine >> 32), 2 * row);
-    const uint32_t blo = __builtin_amdgcn_readlane((uint32_t)mine, 2 * row + 1);
-    const uint32_t bhi = __builtin_amdgcn_readlane((uint32_t)(mine >> 32), 2 * row + 1);
-    const uint64_t wa = ((uint64_t)ahi << 32) | alo, wb = ((uint64_t)bhi << 32) | blo;
-    const uint64_t v = (lane == 0) ? wa : ((wa >> lane) | (wb << (64 - lane)));
-    nb[row] = (uint32_t)(v & 31ull);
-  }
-  if (x >= nx || ((nb[12] >> 2) & 1u)) return;  // no cell, or the centre is occupied
-  // pairs with both cells occupied
-  uint64_t mask = 0;
+    for (int u = 0; u < kBatch; ++u) {
+      has[u] = cand != 0ull;
+      const int i = has[u] ? __ffsll((unsigned long long)cand) - 1 : 0;
+      cand &= cand - 1;
+      const int x = x0 + i;
+      const int64_t qp = rowp * nx + wrap2(x + ox, nx), qm = rowm * nx + wrap2(x - ox, nx);
+      la[u] = lab[has[u] ? qp : qc];
+      lb[u] = lab[has[u] ? qm : qc];
+    }
 #pragma unroll
-  for (int k = 0; k < 62; ++k) {
-    const int ox = sp.o[k][0], oy = sp.o[k][1], oz = sp.o[k][2];
-    const uint32_t plus = nb[5 * (oy + 2) + (oz + 2)] >> (ox + 2);
-    const uint32_t minus = nb[5 * (2 - oy) + (2 - oz)] >> (2 - ox);
-    mask |= (uint64_t)(plus & minus & 1u) << k;
-  }
-  while (mask) {
-    const int k = __ffsll((unsigned long long)mask) - 1;
-    mask &= mask - 1;
-    const int ox = sp.o[k][0], oy = sp.o[k][1], oz = sp.o[k][2];
-    const int64_t qp = (((int64_t)t * nz + wrap2(z + oz, nz)) * ny + wrap2(y + oy, ny)) * nx + wrap2(x + ox, nx);
-    const int64_t qm = (((int64_t)t * nz + wrap2(z - oz, nz)) * ny + wrap2(y - oy, ny)) * nx + wrap2(x - ox, nx);
-    const int32_t la = lab[qp], lb = lab[qm];
-    if (la != lb && la > 0 && lb > 0 && to.off[t] + la <= to.off[t + 1] && to.off[t] + lb <= to.off[t + 1]) {
-      const int32_t ga = to.off[t] + la - 1, gb = to.off[t] + lb - 1;
-      set_edge(adj, awords, ga, gb);
-      set_edge(adj, awords, gb, ga);
+    for (int u = 0; u < kBatch; ++u) {
+      const int32_t a = la[u], b = lb[u];
+      if (has[u] && a != b && a > 0 && b > 0 && to.off[t] + a <= to.off[t + 1] && to.off[t] + b <= to.off[t + 1] &&
+          !(a == last_a && b == last_b)) {
+        const int32_t ga = to.off[t] + a - 1, gb = to.off[t] + b - 1;
+        set_edge(adj, awords, ga, gb);
+        set_edge(adj, awords, gb, ga);
+        last_a = a;
+        last_b = b;
+      }
     }
   }
 }
