@@ -107,7 +107,11 @@ def _f64(a):
     return a
 
 
-def _shape3(c):
+def _shape3(c, ndim: int = 0):
+    """(nx, ny, nz) of a [nz][ny][nx] field or a [N][nz][ny][nx] stack; with ndim
+    given, other shapes raise ValueError (the C functions would read past them)."""
+    if ndim and c.ndim != ndim:
+        raise ValueError(f"expected a {ndim}-D array, got shape {c.shape}")
     nz, ny, nx = c.shape[-3:]
     return int(nx), int(ny), int(nz)
 
@@ -138,7 +142,7 @@ def sweep(c, s, d: int, cc=None):
     """One Jacobi sweep along axis d of one field c[nz][ny][nx]; returns the new field."""
     c = _f64(c)
     s = _f64(s)
-    nx, ny, nz = _shape3(c)
+    nx, ny, nz = _shape3(c, 3)
     if cc is None:
         cc = (c > 0.5)
     cc = np.ascontiguousarray(cc, dtype=np.uint8)
@@ -171,7 +175,7 @@ def advect(c, sx, sy, sz, step0: int = 0, nsteps: int = 1):
 def label(c, c_eps: float = 1e-6):
     """Canonical 6-connected periodic components of {c > c_eps} (tag.h step)."""
     c = _f64(c)
-    nx, ny, nz = _shape3(c)
+    nx, ny, nz = _shape3(c, 3)
     lab = np.zeros(c.shape, dtype=np.int32)
     k = lib().orc_label(nx, ny, nz, c.ctypes.data, float(c_eps), lab.ctypes.data)
     return lab, int(k)
@@ -180,7 +184,7 @@ def label(c, c_eps: float = 1e-6):
 def drop_moments(c, labels, k: int):
     c = _f64(c)
     labels = np.ascontiguousarray(labels, dtype=np.int32)
-    nx, ny, nz = _shape3(c)
+    nx, ny, nz = _shape3(c, 3)
     vol = np.zeros(max(k, 0))
     xyz = np.zeros((max(k, 0), 3))
     rc = lib().orc_drop_moments(nx, ny, nz, c.ctypes.data, labels.ctypes.data, int(k), vol.ctypes.data,
@@ -194,7 +198,7 @@ def drop_shapes(c, labels, k: int, xyz, s=None):
     velocity [k][3] (else None). Appendix "Deformation of the drops"."""
     c = _f64(c)
     labels = np.ascontiguousarray(labels, dtype=np.int32)
-    nx, ny, nz = _shape3(c)
+    nx, ny, nz = _shape3(c, 3)
     xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
     assert len(xyz) >= k
     inertia = np.zeros((max(k, 0), 6))
@@ -233,7 +237,7 @@ def csf_force(c, kappa, gamma: float):
         c, kappa = c[None], kappa[None]
     assert c.shape == kappa.shape
     ntr = c.shape[0]
-    nx, ny, nz = _shape3(c)
+    nx, ny, nz = _shape3(c, 4)
     out = [np.zeros(c.shape[1:]) for _ in range(3)]
     lib().orc_csf_force(nx, ny, nz, ntr, c.ctypes.data, kappa.ctypes.data, float(gamma),
                         *[o.ctypes.data for o in out])
@@ -258,7 +262,7 @@ def compact_tracers(c, ndrops):
 def neighbour_pairs(labels, ndrops, tau: float):
     labels = np.ascontiguousarray(labels, dtype=np.int32)
     ntr = labels.shape[0]
-    nx, ny, nz = _shape3(labels)
+    nx, ny, nz = _shape3(labels, 4)
     nd = np.ascontiguousarray(ndrops, dtype=np.int32)
     cap = 1 << 16
     while True:
@@ -278,7 +282,7 @@ def recolor(c, labels, ndrops, ntracers: int, max_tracers: int, tau: float):
     c = np.array(c, dtype=np.float64, copy=True, order="C")
     assert c.shape[0] == max_tracers
     labels = np.ascontiguousarray(labels, dtype=np.int32)
-    nx, ny, nz = _shape3(c)
+    nx, ny, nz = _shape3(c, 4)
     nd = np.ascontiguousarray(ndrops, dtype=np.int32)
     D = int(nd.sum())
     newt = np.zeros(max(D, 1), dtype=np.int32)
@@ -294,7 +298,7 @@ def stencil_flags(labels):
     1 Step 1 (empty centre, two opposite occupied cells in the 5^3 stencil), 2 Steps 1 and 3
     (their labels differ)."""
     labels = np.ascontiguousarray(labels, dtype=np.int32)
-    nx, ny, nz = _shape3(labels)
+    nx, ny, nz = _shape3(labels, 3)
     out = np.zeros(labels.shape, dtype=np.uint8)
     lib().orc_stencil_flags(nx, ny, nz, labels.ctypes.data, out.ctypes.data)
     return out
@@ -304,7 +308,7 @@ def neighbour_pairs_stencil(labels, ndrops):
     """Directed neighbour pairs of the literal mode (conflicts within a tracer, contacts across)."""
     labels = np.ascontiguousarray(labels, dtype=np.int32)
     ntr = labels.shape[0]
-    nx, ny, nz = _shape3(labels)
+    nx, ny, nz = _shape3(labels, 4)
     nd = np.ascontiguousarray(ndrops, dtype=np.int32)
     cap = 1 << 16
     while True:
@@ -322,7 +326,7 @@ def recolor_stencil(c, labels, ndrops, ntracers: int, max_tracers: int):
     c = np.array(c, dtype=np.float64, copy=True, order="C")
     assert c.shape[0] == max_tracers
     labels = np.ascontiguousarray(labels, dtype=np.int32)
-    nx, ny, nz = _shape3(c)
+    nx, ny, nz = _shape3(c, 4)
     nd = np.ascontiguousarray(ndrops, dtype=np.int32)
     D = int(nd.sum())
     newt = np.zeros(max(D, 1), dtype=np.int32)
@@ -380,7 +384,7 @@ def pair_pdfs(r_edges, th_edges, hist, events: int):
 
 def curvature_hf(c):
     c = _f64(c)
-    nx, ny, nz = _shape3(c)
+    nx, ny, nz = _shape3(c, 3)
     kappa = np.zeros(c.shape)
     status = np.zeros(c.shape, dtype=np.uint8)
     lib().orc_curvature_hf(nx, ny, nz, c.ctypes.data, kappa.ctypes.data, status.ctypes.data)

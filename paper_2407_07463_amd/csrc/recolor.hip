@@ -116,30 +116,52 @@ __device__ __forceinline__ void edges_of(const int32_t *__restrict__ own, const 
       });
     });
   }
-  for (int k = 0; k < noffs; ++k) {
-    const int4 o = offs[k];
-    const int64_t q = small_offsets ? ((int64_t)wrap_near(z + o.z, nz) * ny + wrap_near(y + o.y, ny)) * nx +
-                                          wrap_near(x + o.x, nx)
-                                    : ((int64_t)wrap_any(z + o.z, nz) * ny + wrap_any(y + o.y, ny)) * nx +
-                                          wrap_any(x + o.x, nx);
-    const int32_t b = own[q];
-    if (b == -1) continue;
-    if (a >= 0 && b >= 0) {
-      if (a != b) set_edge(adj, words, a, b);
-      continue;
+  // The owners of kBatch offsets are loaded together (past the last offset
+  // every lane loads its own cell and ignores it); a drop just paired with
+  // this cell's drop is not paired again (a boundary cell sees a neighbouring
+  // drop through many offsets).
+  constexpr int kBatch = 8;
+  int32_t last_b = -1;
+  for (int k0 = 0; k0 < noffs; k0 += kBatch) {
+    int32_t bs[kBatch];
+    int64_t qs[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const int k = k0 + j < noffs ? k0 + j : 0;
+      const int4 o = offs[k];
+      const int64_t q = small_offsets ? ((int64_t)wrap_near(z + o.z, nz) * ny + wrap_near(y + o.y, ny)) * nx +
+                                            wrap_near(x + o.x, nx)
+                                      : ((int64_t)wrap_any(z + o.z, nz) * ny + wrap_any(y + o.y, ny)) * nx +
+                                            wrap_any(x + o.x, nx);
+      qs[j] = (k0 + j < noffs) ? q : p;
+      bs[j] = own[qs[j]];
     }
-    // a shared cell on either side: every drop of p with every drop of q
-    auto with_q = [&](int32_t u) {
-      if (b >= 0) {
-        if (u != b) set_edge(adj, words, u, b);
-      } else {
-        for_drops_at(lab, n3, ntr, to, q, [&](int32_t v) {
-          if (u != v) set_edge(adj, words, u, v);
-        });
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      if (k0 + j >= noffs) break;
+      const int64_t q = qs[j];
+      const int32_t b = bs[j];
+      if (b == -1) continue;
+      if (a >= 0 && b >= 0) {
+        if (a != b && b != last_b) {
+          set_edge(adj, words, a, b);
+          last_b = b;
+        }
+        continue;
       }
-    };
-    if (a >= 0) with_q(a);
-    else for_drops_at(lab, n3, ntr, to, p, with_q);
+      // a shared cell on either side: every drop of p with every drop of q
+      auto with_q = [&](int32_t u) {
+        if (b >= 0) {
+          if (u != b) set_edge(adj, words, u, b);
+        } else {
+          for_drops_at(lab, n3, ntr, to, q, [&](int32_t v) {
+            if (u != v) set_edge(adj, words, u, v);
+          });
+        }
+      };
+      if (a >= 0) with_q(a);
+      else for_drops_at(lab, n3, ntr, to, p, with_q);
+    }
   }
 }
 
@@ -197,6 +219,34 @@ __global__ __launch_bounds__(kBlock) void k_occ_words(const int32_t *__restrict_
   const bool occ_ = x < nx && lab[row * nx + x] > 0;
   const uint64_t b = __ballot(occ_);
   if (lane == 0) occ[seg] = b;
+}
+
+// Bit m of v (m < 16) to bit 4m.
+__device__ __forceinline__ uint64_t spread4(uint64_t v) {
+  v &= 0xFFFFull;
+  v = (v | (v << 24)) & 0x000000FF000000FFull;
+  v = (v | (v << 12)) & 0x000F000F000F000Full;
+  v = (v | (v << 6)) & 0x0303030303030303ull;
+  v = (v | (v << 3)) & 0x1111111111111111ull;
+  return v;
+}
+
+// The same words when rows hold a multiple of 256 cells: one wavefront per
+// four segments of a row, each lane loading four labels at once (cells
+// 4l .. 4l+3 of the 256); ballot k holds component k of every lane, and the
+// word of segment j interleaves 16 bits of each ballot.
+__global__ __launch_bounds__(kBlock) void k_occ_words4(const int4 *__restrict__ lab4, int64_t ngroups,
+                                                       uint64_t *__restrict__ occ) {
+  const int64_t g = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (g >= ngroups) return;  // whole wavefront
+  const int4 v = lab4[g * 64 + lane];  // segments 4g .. 4g+3 are cells 256g .. 256g+255 of the fields
+  const uint64_t b0 = __ballot(v.x > 0), b1 = __ballot(v.y > 0), b2 = __ballot(v.z > 0), b3 = __ballot(v.w > 0);
+  if (lane < 4) {
+    const int sh = 16 * lane;
+    occ[4 * g + lane] = spread4(b0 >> sh) | (spread4(b1 >> sh) << 1) | (spread4(b2 >> sh) << 2) |
+                        (spread4(b3 >> sh) << 3);
+  }
 }
 
 // Bits of cells xs, xs+1, ..., xs+63 (periodic in x, xs any integer) of one
@@ -727,8 +777,14 @@ static int recolor_impl(vofmt_ctx *ctx, const char *fn, int stencil, int32_t nx,
     if (!occ) return VOFMT_E_NOMEM;
     const int64_t nblk = (nseg * 64 + kBlock - 1) / kBlock;
     if (nblk > INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "%s: grid too large", fn);
-    hipLaunchKernelGGL(k_occ_words, dim3((unsigned)nblk), dim3(kBlock), 0, stream, labels, nx, (int64_t)ntr * rows,
-                       xw, occ);
+    if (nx % 256 == 0 && ((uintptr_t)labels & 15) == 0) {
+      const int64_t ngroups = nseg / 4;  // rows of whole 256-cell groups: segment 4g + j is cells 64(4g + j) ..
+      hipLaunchKernelGGL(k_occ_words4, dim3((unsigned)((ngroups * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                         stream, (const int4 *)labels, ngroups, occ);
+    } else {
+      hipLaunchKernelGGL(k_occ_words, dim3((unsigned)nblk), dim3(kBlock), 0, stream, labels, nx,
+                         (int64_t)ntr * rows, xw, occ);
+    }
     hipLaunchKernelGGL(k_stencil_edges, dim3((unsigned)nblk), dim3(kBlock), 0, stream, labels, occ, nx, ny, nz, ntr,
                        xw, to, make_stencil_pairs(), adj, words);
   }
