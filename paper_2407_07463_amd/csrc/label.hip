@@ -359,6 +359,46 @@ __global__ __launch_bounds__(kBlock) void k_label_write(const uint64_t *__restri
   }
 }
 
+// Pass 6 when rows hold a multiple of 256 cells: lane l of a wavefront
+// writes cells 4l .. 4l+3 of each of its kGroupsW 256-cell groups (segment
+// 4g + l/16, bits 4(l%16) .. +3) with one 16-byte store. The occupancy
+// words and then the run entries of all the wavefront's groups are loaded
+// before the first store, as in k_label_write.
+constexpr int kGroupsW = 4;
+typedef int32_t v4i32 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(kBlock) void k_label_write4(const uint64_t *__restrict__ occ, RunTable T,
+                                                         int32_t *__restrict__ lab, int64_t n3, int64_t nrun) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nseg = T.nseg, ngroups = nseg / 4;
+  const int64_t g0 = (((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6) * kGroupsW;
+  occ += blockIdx.y * nseg;
+  T.P += blockIdx.y * nrun;
+  v4i32 *lab4 = reinterpret_cast<v4i32 *>(lab + blockIdx.y * n3);
+  const int j = lane >> 4, b0 = 4 * (lane & 15);
+  uint64_t m[kGroupsW];
+  int64_t sg[kGroupsW];
+#pragma unroll
+  for (int k = 0; k < kGroupsW; ++k) {
+    sg[k] = (g0 + k < ngroups) ? 4 * (g0 + k) + j : nseg - 1;
+    m[k] = occ[sg[k]];
+  }
+  int32_t e[kGroupsW][4];
+#pragma unroll
+  for (int k = 0; k < kGroupsW; ++k)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const bool on = (m[k] >> (b0 + i)) & 1ull;
+      const int32_t v = T.P[(int64_t)(on ? run_index(m[k], b0 + i) : 0) * nseg + sg[k]];
+      e[k][i] = on ? -v : 0;
+    }
+#pragma unroll
+  for (int k = 0; k < kGroupsW; ++k) {
+    if (g0 + k >= ngroups) break;  // wave-uniform
+    const v4i32 v = {e[k][0], e[k][1], e[k][2], e[k][3]};
+    __builtin_nontemporal_store(v, &lab4[(g0 + k) * 64 + lane]);  // streamed out
+  }
+}
+
 // Workgroups of the per-cell labelling passes (kSegs row segments per
 // wavefront) and of the per-segment passes (one thread per segment).
 static inline int64_t label_blocks(int nx, int ny, int nz, int segs_per_wave) {
@@ -845,7 +885,15 @@ static int label_all(vofmt_ctx *ctx, int nx, int ny, int nz, int T, const double
                      k_dev);
   hipLaunchKernelGGL(k_label_rank, dim3(nbs, nt), dim3(kBlock), 0, stream, occ, R, nseg, bc, tileoff, nrun, tstride);
   hipLaunchKernelGGL(k_label_resolve, dim3(nbs, nt), dim3(kBlock), 0, stream, occ, R, nseg, nrun);
-  hipLaunchKernelGGL(k_label_write, dim3(nbw, nt), dim3(kBlock), 0, stream, occ, R, lab, nx, ny, nz, words, dv, nrun);
+  if (nx % 256 == 0 && ((uintptr_t)lab & 15) == 0) {
+    const int64_t ngroups = nseg / 4;  // whole 256-cell groups: segment s is cells 64 s .. 64 s + 63
+    const int64_t per = (int64_t)(kBlock / 64) * kGroupsW;
+    hipLaunchKernelGGL(k_label_write4, dim3((unsigned)((ngroups + per - 1) / per), nt), dim3(kBlock), 0, stream, occ,
+                       R, lab, (int64_t)nx * ny * nz, nrun);
+  } else {
+    hipLaunchKernelGGL(k_label_write, dim3(nbw, nt), dim3(kBlock), 0, stream, occ, R, lab, nx, ny, nz, words, dv,
+                       nrun);
+  }
   return hip_check(ctx, hipGetLastError(), "label kernels");
 }
 

@@ -65,6 +65,22 @@ def test_labels_random_blobs(ctx, seed):
         assert np.array_equal(lab[t], ol)
 
 
+@pytest.mark.parametrize("shape", [(6, 11, 256), (3, 5, 768)])
+def test_labels_rows_of_256_cells(ctx, shape):
+    """Rows of a multiple of 256 cells take the 16-byte label stores: random blobs, runs
+    across the 256-cell groups and a periodic full row."""
+    rng = np.random.default_rng(sum(shape))
+    c = random_blobs(rng, shape, 2, 12, 1.0, 3.0)
+    c[0, 0, 0, :] = 1.0
+    c[1, 1, 2, 250:520 if shape[2] > 520 else shape[2]] = 0.6
+    note(f"label rows of 256 cells shape={shape}")
+    lab, nd = _gpu_labels(ctx, c)
+    for t in range(2):
+        ol, k = oracle.label(c[t])
+        assert nd[t] == k
+        assert np.array_equal(lab[t], ol)
+
+
 def test_labels_long_runs_and_wrap(ctx):
     # runs crossing 64-cell segment boundaries, spirals and full rows
     c = np.zeros((1, 9, 7, 200))
