@@ -49,8 +49,10 @@ constexpr int kMaxGroup = 4;  // tracers per streaming pass (register budget)
 //          x-segments each (spw = min(segments per row, wpb), rpb = wpb/spw);
 //          gx = chunks of spw segments, gy = groups of rpb rows, gz = chunks
 //          of z.
-//   d = 1: gx = 64-cell segments, gy = groups of 4 z-rows, gz = chunks of y.
-//   d = 2: gx = 64-cell segments, gy = groups of 4 y-rows, gz = chunks of z.
+//   d = 1: gx = groups of 4 consecutive 64-cell segments (one per wavefront,
+//          so a workgroup's loads at each position are one contiguous run),
+//          gy = z-rows, gz = chunks of y.
+//   d = 2: the same with gy = y-rows, gz = chunks of z.
 struct Tiles {
   int gx, gy, gz;
 };
@@ -66,8 +68,8 @@ __host__ __device__ inline Tiles stream_tiles(int d, int nx, int ny, int nz, int
     const int spw = x_segments_per_row(words, wpb), rpb = wpb / spw;
     return Tiles{(words + spw - 1) / spw, (ny + rpb - 1) / rpb, (nz + chunk - 1) / chunk};
   }
-  if (d == 1) return Tiles{words, (nz + 3) / 4, (ny + chunk - 1) / chunk};
-  return Tiles{words, (ny + 3) / 4, (nz + chunk - 1) / chunk};
+  if (d == 1) return Tiles{(words + 3) / 4, nz, (ny + chunk - 1) / chunk};
+  return Tiles{(words + 3) / 4, ny, (nz + chunk - 1) / chunk};
 }
 
 struct Divisors {
@@ -207,18 +209,20 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
   constexpr bool ROWS = (D == 0 && WPB == 0);
   constexpr int W = (D == 0 && !ROWS) ? WPB : 4;  // wavefronts per workgroup
   // x-sweep (WPB > 0): wavefront wv takes segment bx*spw + sw of row by*rpb + rr;
-  // others: 64-cell segment bx of row 4*by + wv
+  // whole-row x-sweep: row 4*by + wv; y- and z-sweeps: segment 4*bx + wv of row by
   const int spw = (D == 0 && !ROWS) ? x_segments_per_row(words, W) : 1;
   const int rpb = (D == 0 && !ROWS) ? W / spw : 1;
   const int rr = wv / spw, sw = wv % spw;
   const bool tile_ok = (D != 0 || ROWS) || (rr < rpb && by * rpb + rr < ny && bx * spw + sw < words);
-  int seg = (D == 0 && !ROWS) ? bx * spw + sw : bx;  // the whole-row march moves it along the row
+  // (the whole-row march moves seg along the row)
+  int seg = (D == 0 && !ROWS) ? bx * spw + sw : (D != 0 ? bx * 4 + wv : bx);
   int x = seg * 64 + lane;
-  const int row = (D == 0 && !ROWS) ? ((by * rpb + rr < ny) ? by * rpb + rr : ny - 1) : by * 4 + wv;
+  const int row = (D == 0 && !ROWS) ? ((by * rpb + rr < ny) ? by * rpb + rr : ny - 1) : (D != 0 ? by : by * 4 + wv);
   const int nrow = (D == 1) ? nz : ny;
   const int nm = (D == 1) ? ny : nz;
   const int64_t wave = region0 + (((int64_t)bz * gy + by) * gx + bx) * W + wv;
-  if ((D != 0 || ROWS) && row >= nrow) {  // whole wavefront (the LDS x-sweep keeps every wavefront for its barriers)
+  // whole wavefront (the LDS x-sweep keeps every wavefront for its barriers)
+  if ((D != 0 || ROWS) && (row >= nrow || (D != 0 && seg >= words))) {
     if (lane == 0) counts_next[wave] = 0;
     return;
   }
