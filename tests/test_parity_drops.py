@@ -40,11 +40,16 @@ def _dev(a, dtype=None):
     return t.to("cuda:0")
 
 
-def _gpu_labels(ctx, c):
+def _gpu_labels(ctx, c, misaligned=False):
     import torch
 
     tc = _dev(c)
-    lab = torch.zeros(tc.shape, dtype=torch.int32, device="cuda:0")
+    if misaligned:  # labels 4 bytes past a 16-byte boundary: the 4-byte store path
+        buf = torch.zeros(tc.numel() + 1, dtype=torch.int32, device="cuda:0")
+        lab = buf[1:].view(tc.shape)
+        assert lab.data_ptr() % 16 != 0
+    else:
+        lab = torch.zeros(tc.shape, dtype=torch.int32, device="cuda:0")
     nd = ctx.label_drops(tc, lab)
     return lab.cpu().numpy(), nd
 
@@ -65,16 +70,18 @@ def test_labels_random_blobs(ctx, seed):
         assert np.array_equal(lab[t], ol)
 
 
-@pytest.mark.parametrize("shape", [(6, 11, 256), (3, 5, 768)])
-def test_labels_rows_of_256_cells(ctx, shape):
-    """Rows of a multiple of 256 cells take the 16-byte label stores: random blobs, runs
-    across the 256-cell groups and a periodic full row."""
+@pytest.mark.parametrize("shape,misaligned", [((6, 11, 256), False), ((3, 5, 768), False),
+                                              ((6, 11, 256), True)])
+def test_labels_rows_of_256_cells(ctx, shape, misaligned):
+    """Rows of a multiple of 256 cells take the 16-byte label stores (and, with a label array
+    off a 16-byte boundary, the 4-byte ones): random blobs, runs across the 256-cell groups
+    and a periodic full row."""
     rng = np.random.default_rng(sum(shape))
     c = random_blobs(rng, shape, 2, 12, 1.0, 3.0)
     c[0, 0, 0, :] = 1.0
     c[1, 1, 2, 250:520 if shape[2] > 520 else shape[2]] = 0.6
-    note(f"label rows of 256 cells shape={shape}")
-    lab, nd = _gpu_labels(ctx, c)
+    note(f"label rows of 256 cells shape={shape} misaligned={misaligned}")
+    lab, nd = _gpu_labels(ctx, c, misaligned)
     for t in range(2):
         ol, k = oracle.label(c[t])
         assert nd[t] == k
