@@ -12,18 +12,19 @@
 // increasing order, then scaled by gamma.
 //
 // One pass streams every tracer's C and kappa once: a wavefront holds 64
-// consecutive cells of a row, a workgroup four rows, and each thread marches
+// consecutive cells of a row, a workgroup eight rows, and each thread marches
 // kZC planes along z keeping the previous plane's C and kappa of its tracers
-// in registers; the x and y neighbours are re-read through the caches (the
-// halo rows and columns of a tile cost about a third more reads than the
-// fields' size).
+// in registers. The y neighbours of rows 1..7 come from the wavefront below
+// through LDS, so only the row below the tile is read twice; the x
+// neighbours are re-read through the caches. HBM reads are about 1.1 times
+// the fields' size (1.3 with four-row tiles and every y neighbour re-read).
 #include <cmath>
 
 #include "common.hpp"
 
 namespace {
 
-constexpr int kTX = 64, kTY = 4, kZC = 16;
+constexpr int kTX = 64, kTY = 8, kZC = 16;
 constexpr int kMaxGroup = 8;
 
 // Branch-free (selects only), so that every load of a plane is issued before
@@ -37,33 +38,40 @@ __device__ __forceinline__ double face_term(double cp, double cm, double kp, dou
 
 // Tracers [t0, t0 + G): the running sums start from 0 (first group) or from
 // the partial sums stored by the previous group, and the last group stores
-// gamma times the sums.
+// gamma times the sums. Wavefront w of a workgroup holds row by*kTY + w; the
+// y-neighbour values of rows 1.. come from the wavefront below through LDS
+// (one barrier per tracer, two buffers alternating by tracer), only
+// wavefront 0 loads the row below the tile. Every thread takes part in every
+// barrier; threads without a cell load a clamped cell and store nothing.
 template <int G>
 __global__ __launch_bounds__(kTX *kTY) void k_csf(const double *__restrict__ c, const double *__restrict__ kap,
                                                   int nx, int ny, int nz, int t0, double gamma, int first, int last,
                                                   double *__restrict__ fx, double *__restrict__ fy,
                                                   double *__restrict__ fz) {
+  __shared__ double xc[2][kTY][kTX], xk[2][kTY][kTX];
   // XCD-aware tile order: workgroups are dealt to the 8 XCDs in turn, so the
   // hardware id is mapped to a tile index that gives each XCD a contiguous
   // run of tiles; neighbouring tiles (whose rows are each other's halo) then
   // share an L2.
   const unsigned nwg = gridDim.x, id = blockIdx.x;
-  const unsigned per = nwg / 8, rem = nwg % 8, xk = id % 8;
-  const unsigned L = xk * per + (xk < rem ? xk : rem) + id / 8;
+  const unsigned per = nwg / 8, rem = nwg % 8, xk8 = id % 8;
+  const unsigned L = xk8 * per + (xk8 < rem ? xk8 : rem) + id / 8;
   const unsigned tx = (nx + kTX - 1) / kTX, ty = (ny + kTY - 1) / kTY;
   const unsigned bx = L % tx, by = (L / tx) % ty, bz = L / (tx * ty);
-  const int x = bx * kTX + (threadIdx.x & (kTX - 1));
-  const int y = by * kTY + (threadIdx.x / kTX);
-  if (x >= nx || y >= ny) return;
+  const int lane = threadIdx.x & (kTX - 1), w = __builtin_amdgcn_readfirstlane(threadIdx.x / kTX);
+  const int x = bx * kTX + lane;
+  const int y = by * kTY + w;
+  const bool act = x < nx && y < ny;
+  const int xc_ = x < nx ? x : nx - 1, yc = y < ny ? y : ny - 1;  // clamped cell of an inactive thread
   const int z0 = bz * kZC;
   const int z1 = z0 + kZC < nz ? z0 + kZC : nz;
-  const int xm = x == 0 ? nx - 1 : x - 1, ym = y == 0 ? ny - 1 : y - 1;
+  const int xm = xc_ == 0 ? nx - 1 : xc_ - 1, ym = yc == 0 ? ny - 1 : yc - 1;
   const int64_t n3 = (int64_t)nx * ny * nz, plane = (int64_t)nx * ny;
   const double *ct = c + (int64_t)t0 * n3;
   const double *kt = kap + (int64_t)t0 * n3;
   double cz[G > 0 ? G : 1], kz[G > 0 ? G : 1];
   {
-    const int64_t q = (int64_t)(z0 == 0 ? nz - 1 : z0 - 1) * plane + (int64_t)y * nx + x;
+    const int64_t q = (int64_t)(z0 == 0 ? nz - 1 : z0 - 1) * plane + (int64_t)yc * nx + xc_;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       cz[g] = ct[g * n3 + q];
@@ -71,10 +79,10 @@ __global__ __launch_bounds__(kTX *kTY) void k_csf(const double *__restrict__ c, 
     }
   }
   for (int z = z0; z < z1; ++z) {
-    const int64_t row = (int64_t)z * plane + (int64_t)y * nx;
-    const int64_t p = row + x, pxm = row + xm, pym = (int64_t)z * plane + (int64_t)ym * nx + x;
+    const int64_t row = (int64_t)z * plane + (int64_t)yc * nx;
+    const int64_t p = row + xc_, pxm = row + xm, pym = (int64_t)z * plane + (int64_t)ym * nx + xc_;
     double sx = 0.0, sy = 0.0, sz = 0.0;
-    if (!first) {
+    if (!first && act) {
       sx = fx[p];
       sy = fy[p];
       sz = fz[p];
@@ -87,15 +95,22 @@ __global__ __launch_bounds__(kTX *kTY) void k_csf(const double *__restrict__ c, 
       kp[g] = kt[g * n3 + p];
       cxm[g] = ct[g * n3 + pxm];
       kxm[g] = kt[g * n3 + pxm];
-      cym[g] = ct[g * n3 + pym];
-      kym[g] = kt[g * n3 + pym];
+      // the row below the tile: wavefront 0 only (the others read it from LDS)
+      cym[g] = (w == 0) ? ct[g * n3 + pym] : 0.0;
+      kym[g] = (w == 0) ? kt[g * n3 + pym] : 0.0;
     }
     // keep the plane's loads together, ahead of their first use
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
+      const int bf = g & 1;
+      xc[bf][w][lane] = cp[g];
+      xk[bf][w][lane] = kp[g];
+      __syncthreads();
+      const double cyv = (w == 0) ? cym[g] : xc[bf][w - 1][lane];
+      const double kyv = (w == 0) ? kym[g] : xk[bf][w - 1][lane];
       sx += face_term(cp[g], cxm[g], kp[g], kxm[g]);
-      sy += face_term(cp[g], cym[g], kp[g], kym[g]);
+      sy += face_term(cp[g], cyv, kp[g], kyv);
       sz += face_term(cp[g], cz[g], kp[g], kz[g]);
       cz[g] = cp[g];
       kz[g] = kp[g];
@@ -105,9 +120,11 @@ __global__ __launch_bounds__(kTX *kTY) void k_csf(const double *__restrict__ c, 
       sy = gamma * sy;
       sz = gamma * sz;
     }
-    fx[p] = sx;
-    fy[p] = sy;
-    fz[p] = sz;
+    if (act) {
+      fx[p] = sx;
+      fy[p] = sy;
+      fz[p] = sz;
+    }
   }
 }
 
