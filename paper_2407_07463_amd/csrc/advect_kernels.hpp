@@ -49,10 +49,12 @@ constexpr int kMaxGroup = 4;  // tracers per streaming pass (register budget)
 //          x-segments each (spw = min(segments per row, wpb), rpb = wpb/spw);
 //          gx = chunks of spw segments, gy = groups of rpb rows, gz = chunks
 //          of z.
-//   d = 1: gx = groups of 4 consecutive 64-cell segments (one per wavefront,
-//          so a workgroup's loads at each position are one contiguous run),
-//          gy = z-rows, gz = chunks of y.
-//   d = 2: the same with gy = y-rows, gz = chunks of z.
+//   d = 1: rows of a multiple of 4 segments: gx = groups of 4 consecutive
+//          64-cell segments (one per wavefront, so a workgroup's loads at
+//          each position are one contiguous run), gy = z-rows; other rows:
+//          gx = segments, gy = groups of 4 z-rows (no idle wavefronts on
+//          short rows); gz = chunks of y.
+//   d = 2: the same with y-rows and chunks of z.
 struct Tiles {
   int gx, gy, gz;
 };
@@ -68,8 +70,10 @@ __host__ __device__ inline Tiles stream_tiles(int d, int nx, int ny, int nz, int
     const int spw = x_segments_per_row(words, wpb), rpb = wpb / spw;
     return Tiles{(words + spw - 1) / spw, (ny + rpb - 1) / rpb, (nz + chunk - 1) / chunk};
   }
-  if (d == 1) return Tiles{(words + 3) / 4, nz, (ny + chunk - 1) / chunk};
-  return Tiles{(words + 3) / 4, ny, (nz + chunk - 1) / chunk};
+  const bool seg4 = words % 4 == 0;
+  if (d == 1) return seg4 ? Tiles{words / 4, nz, (ny + chunk - 1) / chunk}
+                          : Tiles{words, (nz + 3) / 4, (ny + chunk - 1) / chunk};
+  return seg4 ? Tiles{words / 4, ny, (nz + chunk - 1) / chunk} : Tiles{words, (ny + 3) / 4, (nz + chunk - 1) / chunk};
 }
 
 struct Divisors {
@@ -209,15 +213,17 @@ __device__ __forceinline__ void stream_body(const double *__restrict__ cin, doub
   constexpr bool ROWS = (D == 0 && WPB == 0);
   constexpr int W = (D == 0 && !ROWS) ? WPB : 4;  // wavefronts per workgroup
   // x-sweep (WPB > 0): wavefront wv takes segment bx*spw + sw of row by*rpb + rr;
-  // whole-row x-sweep: row 4*by + wv; y- and z-sweeps: segment 4*bx + wv of row by
+  // whole-row x-sweep: row 4*by + wv; y- and z-sweeps: segment 4*bx + wv of
+  // row by when a row has a multiple of 4 segments, else segment bx of row 4*by + wv
   const int spw = (D == 0 && !ROWS) ? x_segments_per_row(words, W) : 1;
   const int rpb = (D == 0 && !ROWS) ? W / spw : 1;
   const int rr = wv / spw, sw = wv % spw;
   const bool tile_ok = (D != 0 || ROWS) || (rr < rpb && by * rpb + rr < ny && bx * spw + sw < words);
   // (the whole-row march moves seg along the row)
-  int seg = (D == 0 && !ROWS) ? bx * spw + sw : (D != 0 ? bx * 4 + wv : bx);
+  const bool seg4 = D != 0 && words % 4 == 0;
+  int seg = (D == 0 && !ROWS) ? bx * spw + sw : (seg4 ? bx * 4 + wv : bx);
   int x = seg * 64 + lane;
-  const int row = (D == 0 && !ROWS) ? ((by * rpb + rr < ny) ? by * rpb + rr : ny - 1) : (D != 0 ? by : by * 4 + wv);
+  const int row = (D == 0 && !ROWS) ? ((by * rpb + rr < ny) ? by * rpb + rr : ny - 1) : (seg4 ? by : by * 4 + wv);
   const int nrow = (D == 1) ? nz : ny;
   const int nm = (D == 1) ? ny : nz;
   const int64_t wave = region0 + (((int64_t)bz * gy + by) * gx + bx) * W + wv;
