@@ -15,14 +15,26 @@ constexpr int kTile = 1024;  // entries per scan tile
 constexpr double kResidue = 1e-12;
 __device__ __forceinline__ bool is_mixed(double v) { return v > kResidue && v < 1.0 - kResidue; }
 
-// Mixed cells per block of kBlock cells.
+// The mixed-cell list takes kPer cells per thread: block b covers cells
+// [b kCells, (b + 1) kCells) as kPer coalesced sub-chunks of kBlock cells
+// (sub-chunk k at b kCells + k kBlock), whose values are all loaded before
+// the first is used. Far fewer, longer-lived workgroups than one per
+// kBlock cells.
+constexpr int kPer = 8;
+constexpr int64_t kCells = (int64_t)kBlock * kPer;
+
+// Mixed cells per block of kCells cells.
 __global__ __launch_bounds__(kBlock) void k_block_counts(const double *__restrict__ c, int64_t n3,
                                                          int32_t *__restrict__ bc) {
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool mixed = p < n3 && is_mixed(c[p]);
+  const int64_t p0 = (int64_t)blockIdx.x * kCells + threadIdx.x;
+  double v[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) v[k] = (p0 + k * kBlock < n3) ? c[p0 + k * kBlock] : 0.0;
+  int n = 0;  // wavefront-uniform
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) n += (int)__popcll(__ballot(p0 + k * kBlock < n3 && is_mixed(v[k])));
   __shared__ int wc[kBlock / 64];
-  const uint64_t mask = __ballot(mixed);
-  if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = (int)__popcll(mask);
+  if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = n;
   __syncthreads();
   if (threadIdx.x == 0) {
     int t = 0;
@@ -80,30 +92,42 @@ __global__ __launch_bounds__(kTile) void k_scan_totals(int32_t *__restrict__ tot
   if (threadIdx.x == 0) tot[ntiles] = carry;
 }
 
-// Ordered list: block b writes its mixed cells from bc[b] + tot[b / kTile].
-// With kappa/status given, also writes NaN / 0 into every cell that is not
-// mixed.
+// Ordered list: block b writes its mixed cells from bc[b] + tot[b / kTile],
+// sub-chunk by sub-chunk, wavefront by wavefront. With kappa/status given,
+// also writes NaN / 0 into every cell that is not mixed.
 __global__ __launch_bounds__(kBlock) void k_write_ordered(const double *__restrict__ c, int64_t n3,
                                                           const int32_t *__restrict__ bc,
                                                           const int32_t *__restrict__ tot, int32_t *__restrict__ list,
                                                           double *__restrict__ kappa, uint8_t *__restrict__ status) {
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool inside = p < n3;
-  const bool mixed = inside && is_mixed(c[p]);
-  if (inside && !mixed && kappa) {
-    kappa[p] = __builtin_nan("");
-    status[p] = 0;
-  }
-  __shared__ int wc[kBlock / 64];
+  const int64_t p0 = (int64_t)blockIdx.x * kCells + threadIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint64_t mask = __ballot(mixed);
-  if (lane == 0) wc[w] = (int)__popcll(mask);
+  double v[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) v[k] = (p0 + k * kBlock < n3) ? c[p0 + k * kBlock] : 0.0;
+  __shared__ int wc[kPer][kBlock / 64];
+  uint64_t mk[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int64_t p = p0 + k * kBlock;
+    const bool inside = p < n3;
+    const bool mixed = inside && is_mixed(v[k]);
+    if (inside && !mixed && kappa) {
+      kappa[p] = __builtin_nan("");
+      status[p] = 0;
+    }
+    mk[k] = __ballot(mixed);
+    if (lane == 0) wc[k][w] = (int)__popcll(mk[k]);
+  }
   __syncthreads();
-  if (!mixed) return;
-  int idx = bc[blockIdx.x] + tot[blockIdx.x / kTile];
-  for (int k = 0; k < w; ++k) idx += wc[k];
-  idx += (int)__popcll(mask & ((1ull << lane) - 1));
-  list[idx] = (int32_t)p;
+  int run = bc[blockIdx.x] + tot[blockIdx.x / kTile];  // entries of the cells before sub-chunk k
+  const uint64_t below = (1ull << lane) - 1;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    int idx = run;
+    for (int j = 0; j < w; ++j) idx += wc[k][j];
+    if ((mk[k] >> lane) & 1ull) list[idx + (int)__popcll(mk[k] & below)] = (int32_t)(p0 + k * kBlock);
+    for (int j = 0; j < kBlock / 64; ++j) run += wc[k][j];
+  }
 }
 
 // The ordered list of the mixed cells of c into `list` (capacity n3), its
@@ -111,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_write_ordered(const double *__restri
 // scratch; tot: ntiles + 1 ints, ntiles = ceil(bc length / kTile).
 inline void launch_ordered_list(const double *c, int64_t n3, int32_t *bc, int32_t *tot, int32_t *list, double *kappa,
                                 uint8_t *status, hipStream_t stream) {
-  const int64_t nb = (n3 + kBlock - 1) / kBlock;
+  const int64_t nb = (n3 + kCells - 1) / kCells;
   const int64_t ntiles = (nb + kTile - 1) / kTile;
   hipLaunchKernelGGL(k_block_counts, dim3((unsigned)nb), dim3(kBlock), 0, stream, c, n3, bc);
   hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)ntiles), dim3(kTile), 0, stream, bc, nb, tot, (int64_t)0, (int64_t)0);
@@ -120,7 +144,10 @@ inline void launch_ordered_list(const double *c, int64_t n3, int32_t *bc, int32_
                      status);
 }
 
-inline int64_t list_tiles(int64_t n3) { return ((n3 + kBlock - 1) / kBlock + kTile - 1) / kTile; }
+// Scan tiles of the mixed-cell list of n3 cells (its length is at tot[list_tiles(n3)]).
+inline int64_t list_tiles(int64_t n3) { return ((n3 + kCells - 1) / kCells + kTile - 1) / kTile; }
+// Scan tiles of a predicate list of n cells (one block count per kBlock cells).
+inline int64_t list_tiles_if(int64_t n) { return ((n + kBlock - 1) / kBlock + kTile - 1) / kTile; }
 
 // The same for any predicate pr(p) over cells 0..n-1. The counting pass also
 // stores the predicate as one bit per cell (`bits`, one 64-bit word per
@@ -161,7 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_write_ordered_bits(int64_t n, const 
   list[idx] = (int32_t)p;
 }
 
-// Ordered list of the cells p < n with pr(p); its length into tot[list_tiles(n)].
+// Ordered list of the cells p < n with pr(p); its length into tot[list_tiles_if(n)].
 // bits: scratch of (n + 63) / 64 words.
 template <class Pred>
 inline void launch_ordered_list_if(int64_t n, Pred pr, int32_t *bc, int32_t *tot, int32_t *list, uint64_t *bits,

@@ -790,7 +790,7 @@ static int recolor_impl(vofmt_ctx *ctx, const char *fn, int stencil, int32_t nx,
   }
   {
     // the cells that can see a pair, in order, then the pairs they see
-    const int64_t lt = compact::list_tiles(n3);
+    const int64_t lt = compact::list_tiles_if(n3);
     int32_t *srcs = (int32_t *)scratch(ctx, SLOT_RECOLOR_LIST, sizeof(int32_t) * (size_t)n3);
     int32_t *bc = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * (size_t)nbc);
     int32_t *tot = (int32_t *)scratch(ctx, SLOT_CURV_COUNT, sizeof(int32_t) * (size_t)(lt + 2));
