@@ -340,6 +340,18 @@ def test_recolour_stencil_drops96(ctx):
     assert _check_stencil_case(ctx, c, 4, 8) > 0
 
 
+def test_recolour_stencil_drops128_eight_tracers(ctx):
+    """The benchmark's recipe (diameter 24 +-10%, phi = 0.3, RSA gap 1) at 128^3 over all eight
+    tracers: the literal criterion bit-exact against the oracle (tracer count, assignment,
+    moved count, fields) at the tracer count the benchmark runs, with drops moved within the
+    existing tracers."""
+    w = synth.random_drops(128, 8, 0.3, 24.0, 0.1, 1.0, seed=synth.workload_seed(8), workers=16)
+    c = np.zeros((16,) + w["c"].shape[1:])
+    c[:8] = w["c"]
+    note("recolour stencil drops128, 8 tracers")
+    assert _check_stencil_case(ctx, c, 8, 16) > 0
+
+
 # ------------------------------------------------------------------ statistics
 
 def _gpu_stats(ctx, xyz, box, vaxis, r2e, ce):
