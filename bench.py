@@ -529,8 +529,10 @@ def main():
     stream_names = [k for k in prof if k.startswith("k_stream<")]
     launches = sum(prof[k][0] for k in stream_names)
     total_ms = sum(prof[k][1] for k in stream_names)
-    gsz = 4 if ntr >= 4 else ntr  # tracers per streaming launch
-    bytes_launch = sweep_model_bytes(ntr) * gsz * n3
+    # tracers per streaming launch: every full group of 4 in one launch
+    gsz = 4 if ntr >= 4 else ntr  # tracers per group (template argument)
+    tpl = 4 * (ntr // 4) if ntr >= 4 else ntr
+    bytes_launch = sweep_model_bytes(ntr) * tpl * n3
     avg_launch_s = total_ms / launches / 1e3
     achieved = bytes_launch / avg_launch_s / 1e9
     log(f"k_stream: {launches} launches, avg {1e3 * avg_launch_s:.3f} ms, {achieved:.0f} GB/s of the method's "
@@ -575,9 +577,9 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": f"k_stream<D,{gsz}> / k_stream_rows<{gsz}> (streaming pass of {gsz} tracers, all axes)",
+            "kernel": f"k_stream<D,{gsz}> / k_stream_rows<{gsz}> (streaming pass of {tpl} tracers in groups of {gsz}, all axes)",
             "bytes_per_launch": bytes_launch,
-            "bytes_model": f"{sweep_model_bytes(ntr):.3f} B per tracer-cell-sweep x {gsz} x n^3",
+            "bytes_model": f"{sweep_model_bytes(ntr):.3f} B per tracer-cell-sweep x {tpl} x n^3",
             "avg_launch_ms": 1e3 * avg_launch_s,
             "actual_hbm_gbs": (traffic / avg_launch_s / 1e9) if traffic else None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
