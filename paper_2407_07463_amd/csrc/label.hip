@@ -15,13 +15,15 @@
 // almost every pass reads, are adjacent in memory.
 //   1. occupancy: one ballot word per segment (bit l: cell 64 * seg + l is
 //               occupied), read from c once; every run starts as its own root;
-//   2. union:   one thread per segment unites each of its runs with the runs
-//               it overlaps in the +y and +z rows (one union per overlap, at
-//               the overlap's first cell) and its first cell with its -x
-//               neighbour (the previous segment's last cell, or the row's
-//               last cell through the periodic boundary); a union hooks the
-//               larger root under the smaller, so every component ends rooted
-//               at its first run, whatever the order of the unions;
+//   2. union:   each run is united with the runs it overlaps in the +y and
+//               +z rows (one union per overlap, at the overlap's first
+//               cell), and a segment's first cell with its -x neighbour (the
+//               previous segment's last cell, or the row's last cell through
+//               the periodic boundary); a union hooks the larger root under
+//               the smaller, so every component ends rooted at its first
+//               run, whatever the order of the unions. The unions inside
+//               tiles of whole rows are made in LDS, one workgroup per tile
+//               (2a), then those across tile boundaries on the run table (2b);
 //   3. flatten: every run points at its root; roots counted per workgroup;
 //   4. rank:    the counts are scanned and each root's entry becomes
 //               -(1 + number of roots before it);
@@ -181,23 +183,245 @@ __global__ __launch_bounds__(kBlock) void k_label_occ(const double *__restrict__
   }
 }
 
-// Pass 2: unions of each segment's runs with their +y, +z and -x neighbours.
-__global__ __launch_bounds__(kBlock) void k_label_union(const uint64_t *__restrict__ occ, RunTable T, int nx, int ny,
-                                                        int nz, int words, SegDiv dv, int64_t nrun) {
-  const int64_t sgi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+// Tiles of the local union pass: ty x tz rows of whole x-rows, at most
+// TS segments, so every -x neighbour lies in the tile.
+struct RowTiles {
+  int ty, tz;  // rows per tile along y and z; ty = 0: no tiling (every union is global)
+  int nty;     // tiles along y
+};
+// Root search and union inside a workgroup's LDS parent array (the same
+// hooking and halving rules as on the global run table).
+__device__ __forceinline__ int find_root_lds(int32_t *par, int a) {
+  int b = par[a];
+  while (b != a) {
+    const int g = par[b];
+    if (g != b) par[a] = g;
+    a = b;
+    b = g;
+  }
+  return a;
+}
+__device__ __forceinline__ void unite_lds(int32_t *par, int a, int b) {
+  while (true) {
+    a = find_root_lds(par, a);
+    b = find_root_lds(par, b);
+    if (a == b) return;
+    if (a > b) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    const int old = atomicMin(&par[b], a);
+    if (old == b) return;
+    b = old;
+  }
+}
+
+// Pass 2a: unions inside tiles of rows, in LDS. Thread i holds local
+// segments PER*i .. PER*i + PER-1 (ls = (lz * tye + ly) * words + seg), and
+// the runs of the tile are numbered in (ls, run) order by a prefix sum of
+// the per-segment run counts: the order of their global ids, so a local
+// component's root (its smallest local number) is also its smallest global
+// id. Every run then gets its local root's global id as its entry; the
+// roots keep their own. A tile with more than CAP runs makes its unions on
+// the global run table instead (its runs are touched by no other workgroup
+// in this pass). A workgroup takes tiles blockIdx.x, + gridDim.x, ... and
+// loads the next tile's occupancy words while it works on the current one.
+template <int TS>
+__global__ __launch_bounds__(kBlock) void k_label_local(const uint64_t *__restrict__ occ, RunTable T, int nx, int ny,
+                                                        int nz, int words, RowTiles rt, int ntile, int64_t nrun) {
+  static_assert(TS % kBlock == 0, "whole segments per thread");
+  constexpr int PER = TS / kBlock;  // segments per thread
+  constexpr int CAP = 2 * TS;       // runs per tile held in LDS (2 per segment on average)
+  __shared__ uint64_t om[TS];
+  __shared__ int32_t first[TS];     // local number of each segment's first run
+  __shared__ int32_t par[CAP];      // parents, then the roots' global ids
+  __shared__ int32_t wsum[kBlock / 64];
   const int64_t nseg = (int64_t)ny * nz * words;
   occ += blockIdx.y * nseg;
   T.P += blockIdx.y * nrun;
+  const int sh = T.shift;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  struct Tile {
+    int y0, z0, tye, tze, nls, rw;
+  };
+  auto tile_of = [&](int tl) -> Tile {
+    Tile t;
+    t.y0 = (tl % rt.nty) * rt.ty;
+    t.z0 = (tl / rt.nty) * rt.tz;
+    t.tye = min(rt.ty, ny - t.y0);
+    t.tze = min(rt.tz, nz - t.z0);
+    t.rw = t.tye * words;  // local segments per z-plane of the tile
+    t.nls = t.tze * t.rw;
+    return t;
+  };
+  auto gseg = [&](const Tile &t, int ls) -> int64_t {
+    const int lz = ls / t.rw, rem = ls - lz * t.rw;
+    const int ly = rem / words, sgx = rem - ly * words;
+    return ((int64_t)(t.z0 + lz) * ny + (t.y0 + ly)) * words + sgx;
+  };
+  auto load = [&](int tl, uint64_t *w) {
+    const Tile t = tile_of(tl);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int ls = (int)threadIdx.x * PER + k;
+      w[k] = (ls < t.nls) ? occ[gseg(t, ls)] : 0ull;
+    }
+  };
+  // the pairs of runs of the tile to unite: -x neighbour of the first cell,
+  // overlaps with the +y and +z rows inside the tile (through the periodic
+  // boundary when the tile spans the whole axis); f(ls, r, ls2, r2)
+  auto tile_pairs = [&](const Tile &t, int ls, uint64_t m, auto &&f) {
+    const int lz = ls / t.rw, rem = ls - lz * t.rw;
+    const int ly = rem / words, sgx = rem - ly * words;
+    if (m & 1ull) {
+      const int lsl = (sgx > 0) ? ls - 1 : ls + words - 1;
+      const int lbit = (sgx > 0) ? 63 : (nx - 1) - 64 * (words - 1);
+      if (!(lsl == ls && lbit == 0)) {
+        const uint64_t ml = om[lsl];
+        if ((ml >> lbit) & 1ull) f(ls, 0, lsl, run_index(ml, lbit));
+      }
+    }
+    for (int dir = 0; dir < 2; ++dir) {
+      int lsn;
+      if (dir == 0) {
+        if (ny == 1) continue;
+        if (ly + 1 < t.tye) lsn = ls + words;
+        else if (t.tye == ny) lsn = ls - (ny - 1) * words;
+        else continue;
+      } else {
+        if (nz == 1) continue;
+        if (lz + 1 < t.tze) lsn = ls + t.rw;
+        else if (t.tze == nz) lsn = ls - (nz - 1) * t.rw;
+        else continue;
+      }
+      const uint64_t mn = om[lsn];
+      const uint64_t ov = m & mn;
+      uint64_t firsts = ov & ~(ov << 1);
+      while (firsts) {
+        const int i = __ffsll((unsigned long long)firsts) - 1;
+        firsts &= firsts - 1;
+        f(ls, run_index(m, i), lsn, run_index(mn, i));
+      }
+    }
+  };
+  uint64_t nxt[PER];
+  if ((int)blockIdx.x < ntile) load(blockIdx.x, nxt);
+  for (int tl = blockIdx.x; tl < ntile; tl += gridDim.x) {  // workgroup-uniform
+    const Tile t = tile_of(tl);
+    uint64_t cur[PER];
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      cur[k] = nxt[k];
+      om[threadIdx.x * PER + k] = cur[k];
+      cnt += __popcll(cur[k] & ~(cur[k] << 1));
+    }
+    if (tl + (int)gridDim.x < ntile) load(tl + gridDim.x, nxt);
+    // exclusive prefix sum of the run counts over the threads
+    int inc = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += v;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    int off = inc - cnt, total = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+      const int v = wsum[w];
+      off += (w < wv) ? v : 0;
+      total += v;
+    }
+    if (total <= CAP) {  // workgroup-uniform
+      {
+        int o = off;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+          const int ls = (int)threadIdx.x * PER + k;
+          first[ls] = o;
+          const int nr = __popcll(cur[k] & ~(cur[k] << 1));
+          for (int r = 0; r < nr; ++r) par[o + r] = o + r;
+          o += nr;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int ls = (int)threadIdx.x * PER + k;
+        if (ls >= t.nls || cur[k] == 0) continue;
+        tile_pairs(t, ls, cur[k], [&](int l1, int r1, int l2, int r2) {
+          unite_lds(par, first[l1] + r1, first[l2] + r2);
+        });
+      }
+      __syncthreads();
+      // the roots (self parents once the unions are done) take ~(global
+      // id) as parent, negative where local numbers are not (each thread
+      // tests and rewrites only its own runs)
+      uint32_t isroot[PER];
+      {
+        int o = off;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+          const int ls = (int)threadIdx.x * PER + k;
+          const int nr = __popcll(cur[k] & ~(cur[k] << 1));
+          isroot[k] = 0;
+          for (int r = 0; r < nr; ++r) isroot[k] |= (par[o + r] == o + r) ? (1u << r) : 0u;
+          if (isroot[k]) {
+            const int64_t g = gseg(t, ls);
+            for (int r = 0; r < nr; ++r)
+              if ((isroot[k] >> r) & 1u) par[o + r] = ~(int32_t)((g << sh) + r);
+          }
+          o += nr;
+        }
+      }
+      __syncthreads();
+      // ... and every other run walks up to its root and takes that id (a
+      // root's entry already holds its own)
+      {
+        int o = off;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+          const int ls = (int)threadIdx.x * PER + k;
+          const int nr = __popcll(cur[k] & ~(cur[k] << 1));
+          if (nr > 0) {
+            const int64_t g = gseg(t, ls);
+            for (int r = 0; r < nr; ++r) {
+              if ((isroot[k] >> r) & 1u) continue;
+              int v = par[o + r];
+              while (v >= 0) v = par[v];
+              T.P[(int64_t)r * nseg + g] = ~v;
+            }
+          }
+          o += nr;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int ls = (int)threadIdx.x * PER + k;
+        if (ls >= t.nls || cur[k] == 0) continue;
+        tile_pairs(t, ls, cur[k], [&](int l1, int r1, int l2, int r2) {
+          unite(T, (int32_t)((gseg(t, l1) << sh) + r1), (int32_t)((gseg(t, l2) << sh) + r2));
+        });
+      }
+    }
+    __syncthreads();  // om, first and par are rewritten for the next tile
+  }
+}
+
+// Unions of segment sgi (row (y, z), x-segment seg, occupancy m) with its -x
+// neighbour and its +y and +z rows, as selected.
+__device__ __forceinline__ void segment_unions(const uint64_t *__restrict__ occ, const RunTable &T, int nx, int ny,
+                                               int nz, int words, int64_t sgi, int seg, int y, int z, uint64_t m,
+                                               bool do_x, bool do_y, bool do_z) {
   const int S = 1 << T.shift;
-  if (sgi >= nseg) return;
-  const uint64_t m = occ[sgi];
-  if (m == 0) return;
-  const Segment sg = segment_of(sgi, dv);
   const int32_t base = (int32_t)(sgi * S);
   // -x: the first cell (bit 0, run 0) and its left neighbour
-  if (m & 1ull) {
-    const int64_t lsg = (sg.seg > 0) ? sgi - 1 : sgi + words - 1;
-    const int lbit = (sg.seg > 0) ? 63 : (nx - 1) - 64 * (words - 1);
+  if (do_x && (m & 1ull)) {
+    const int64_t lsg = (seg > 0) ? sgi - 1 : sgi + words - 1;
+    const int lbit = (seg > 0) ? 63 : (nx - 1) - 64 * (words - 1);
     if (!(lsg == sgi && lbit == 0)) {  // a one-cell row is its own neighbour
       const uint64_t ml = (lsg == sgi) ? m : occ[lsg];
       if ((ml >> lbit) & 1ull) unite(T, base, (int32_t)(lsg * S) + run_index(ml, lbit));
@@ -205,15 +429,10 @@ __global__ __launch_bounds__(kBlock) void k_label_union(const uint64_t *__restri
   }
   // +y, +z: the first cell of every overlap of a run with a run of that row
   for (int dir = 0; dir < 2; ++dir) {
-    int64_t nrow;
-    if (dir == 0) {
-      if (ny == 1) continue;
-      nrow = (int64_t)sg.z * ny + ((sg.y == ny - 1) ? 0 : sg.y + 1);
-    } else {
-      if (nz == 1) continue;
-      nrow = (int64_t)((sg.z == nz - 1) ? 0 : sg.z + 1) * ny + sg.y;
-    }
-    const int64_t nsg = nrow * words + sg.seg;
+    if (!(dir == 0 ? do_y : do_z)) continue;
+    const int64_t nrow = (dir == 0) ? (int64_t)z * ny + ((y == ny - 1) ? 0 : y + 1)
+                                    : (int64_t)((z == nz - 1) ? 0 : z + 1) * ny + y;
+    const int64_t nsg = nrow * words + seg;
     const uint64_t mn = occ[nsg];
     const uint64_t ov = m & mn;
     uint64_t firsts = ov & ~(ov << 1);
@@ -223,6 +442,72 @@ __global__ __launch_bounds__(kBlock) void k_label_union(const uint64_t *__restri
       unite(T, base + run_index(m, i), (int32_t)(nsg * S) + run_index(mn, i));
     }
   }
+}
+
+// Pass 2 without row tiles: every segment's unions with its -x, +y and +z
+// neighbours.
+__global__ __launch_bounds__(kBlock) void k_label_union(const uint64_t *__restrict__ occ, RunTable T, int nx, int ny,
+                                                        int nz, int words, SegDiv dv, int64_t nrun) {
+  const int64_t sgi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t nseg = (int64_t)ny * nz * words;
+  occ += blockIdx.y * nseg;
+  T.P += blockIdx.y * nrun;
+  if (sgi >= nseg) return;
+  const uint64_t m = occ[sgi];
+  if (m == 0) return;
+  const Segment sg = segment_of(sgi, dv);
+  segment_unions(occ, T, nx, ny, nz, words, sgi, sg.seg, sg.y, sg.z, m, true, ny > 1, nz > 1);
+}
+
+// The rows whose +y or +z neighbour lies in another tile: set A, every row
+// of the nzb top planes of the z tiles (their +z unions, and +y where the
+// row is also the top of its y tile), then set B, the nyb top rows of the y
+// tiles in the other planes (their +y unions). nzb = 0 (nyb = 0) when one
+// tile spans the axis or it has one cell.
+struct EdgeRows {
+  int nzb, nyb;
+};
+static inline EdgeRows edge_rows(const RowTiles &rt, int ny, int nz) {
+  EdgeRows e;
+  e.nzb = (nz > 1 && nz > rt.tz) ? (int)ceil_div(nz, rt.tz) : 0;
+  e.nyb = (ny > 1 && ny > rt.ty) ? (int)ceil_div(ny, rt.ty) : 0;
+  return e;
+}
+
+// Pass 2b: the unions across tile boundaries, one thread per segment of the
+// rows of EdgeRows.
+__global__ __launch_bounds__(kBlock) void k_label_union_edges(const uint64_t *__restrict__ occ, RunTable T, int nx,
+                                                              int ny, int nz, int words, RowTiles rt, EdgeRows e,
+                                                              int64_t nedge, int64_t nrun) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t nseg = (int64_t)ny * nz * words;
+  occ += blockIdx.y * nseg;
+  T.P += blockIdx.y * nrun;
+  if (i >= nedge) return;
+  const int64_t q = i / words;
+  const int seg = (int)(i - q * words);
+  const int64_t na = (int64_t)e.nzb * ny;
+  int y, z;
+  bool do_y, do_z;
+  if (q < na) {
+    const int k = (int)(q / ny);
+    y = (int)(q - (int64_t)k * ny);
+    z = min(k * rt.tz + rt.tz - 1, nz - 1);
+    do_z = true;
+    do_y = e.nyb > 0 && (y % rt.ty == rt.ty - 1 || y == ny - 1);
+  } else {
+    const int64_t qb = q - na;
+    const int kz = (int)(qb / e.nyb), ky = (int)(qb - (int64_t)kz * e.nyb);
+    y = min(ky * rt.ty + rt.ty - 1, ny - 1);
+    // the kz-th plane that is not the top of its z tile
+    z = (e.nzb == 0) ? kz : (kz / (rt.tz - 1)) * rt.tz + kz % (rt.tz - 1);
+    do_y = true;
+    do_z = false;
+  }
+  const int64_t sgi = ((int64_t)z * ny + y) * words + seg;
+  const uint64_t m = occ[sgi];
+  if (m == 0) return;
+  segment_unions(occ, T, nx, ny, nz, words, sgi, seg, y, z, m, false, do_y, do_z);
 }
 
 // Roots of the runs of segment sgi (thread-local loop).
@@ -856,6 +1141,40 @@ __global__ void k_shape_finish(int32_t K, int nx, int ny, int nz, const int32_t 
 
 }  // namespace
 
+// Segments per tile of the local union pass (measured on 512^3 x 8:
+// 256: 0.44 ms for passes 2a + 2b, 1024: 0.28, 2048: 0.27, 4096: 0.59 with
+// one workgroup per CU).
+constexpr int kTileSegs = 2048;
+// Row tiles of the local union pass: as many whole rows as fit ts segments,
+// tz the largest power of two up to their square root (at most nz), the rest
+// along y. Rows longer than ts segments take the global unions only (ty = 0).
+static inline RowTiles row_tiles(int ny, int nz, int words, int ts) {
+  RowTiles rt{0, 0, 0};
+  if (words > ts) return rt;
+  const int rows = ts / words;
+  int tz = 1;
+  while ((2 * tz) * (2 * tz) <= rows) tz *= 2;
+  rt.tz = tz < nz ? tz : nz;
+  rt.ty = rows / rt.tz;
+  if (rt.ty > ny) rt.ty = ny;
+  rt.nty = (int)ceil_div(ny, rt.ty);
+  return rt;
+}
+// The local union pass: as many workgroups per field as fill the chip once
+// over all fields (each then loops over its tiles), at most one per tile.
+template <int TS>
+static void launch_local(vofmt_ctx *ctx, int ntile, unsigned nt, hipStream_t stream, const uint64_t *occ,
+                         const RunTable &R, int nx, int ny, int nz, int words, const RowTiles &rt, int64_t nrun) {
+  int cus = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_label_local<TS>, kBlock, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  int64_t gx = ((int64_t)cus * per_cu + nt - 1) / nt;
+  if (gx > ntile) gx = ntile;
+  hipLaunchKernelGGL(k_label_local<TS>, dim3((unsigned)gx, nt), dim3(kBlock), 0, stream, occ, R, nx, ny, nz, words, rt,
+                     ntile, nrun);
+}
 // Label one tracer field into `lab`. Returns K via *k_dev (device int32).
 // Scratch: occupancy words (one per segment), run array (S per segment),
 // block counts (segment_blocks entries), tile offsets
@@ -876,7 +1195,18 @@ static int label_all(vofmt_ctx *ctx, int nx, int ny, int nz, int T, const double
   const unsigned nt = (unsigned)T;
   hipLaunchKernelGGL(k_label_occ, dim3(nbc, nt), dim3(kBlock), 0, stream, c, c_eps, occ, R, nx, ny, nz, words, dv,
                      nrun);
-  hipLaunchKernelGGL(k_label_union, dim3(nbs, nt), dim3(kBlock), 0, stream, occ, R, nx, ny, nz, words, dv, nrun);
+  const RowTiles rt = row_tiles(ny, nz, words, kTileSegs);
+  if (rt.ty > 0) {
+    const int ntile = (int)(rt.nty * ceil_div(nz, rt.tz));
+    launch_local<kTileSegs>(ctx, ntile, nt, stream, occ, R, nx, ny, nz, words, rt, nrun);
+    const EdgeRows e = edge_rows(rt, ny, nz);
+    const int64_t nedge = ((int64_t)e.nzb * ny + (int64_t)e.nyb * (nz - e.nzb)) * words;
+    if (nedge > 0)
+      hipLaunchKernelGGL(k_label_union_edges, dim3((unsigned)ceil_div(nedge, kBlock), nt), dim3(kBlock), 0, stream, occ,
+                         R, nx, ny, nz, words, rt, e, nedge, nrun);
+  } else {
+    hipLaunchKernelGGL(k_label_union, dim3(nbs, nt), dim3(kBlock), 0, stream, occ, R, nx, ny, nz, words, dv, nrun);
+  }
   hipLaunchKernelGGL(k_label_flatten, dim3(nbs, nt), dim3(kBlock), 0, stream, occ, R, nseg, blockcount, nrun);
   static_assert(kBlock == compact::kBlock, "block counts and the tiled scan share the block size");
   const int64_t ntiles = (nbs + compact::kTile - 1) / compact::kTile;

@@ -88,6 +88,43 @@ def test_labels_rows_of_256_cells(ctx, shape, misaligned):
         assert np.array_equal(lab[t], ol)
 
 
+@pytest.mark.parametrize("shape", [(1, 40, 100), (7, 1, 130), (3, 200, 64), (5, 9, 4500), (2, 3, 16448),
+                                   (40, 70, 64), (20, 40, 512), (3, 4, 140000)])
+def test_labels_row_tiles(ctx, shape):
+    """Tiles of the local union pass (2048 segments): one plane, one row per plane, one tile
+    spanning the box, 28 rows of 71 segments per tile (2 x 2 tiles, the last of each axis
+    partial), 32 x 64 rows of 1 segment (2 x 2, partial), 16 x 16 rows of 8 segments (2 x 3),
+    and rows of 2188 segments (no tiles: every union global)."""
+    rng = np.random.default_rng(sum(shape) + 7)
+    c = random_blobs(rng, shape, 2, 10, 1.0, 3.5)
+    c[0, 0, 0, :] = 1.0  # a full periodic row
+    c[1, shape[0] - 1, shape[1] - 1, :] = 0.5  # the last row, touching the first ones periodically
+    c[1, 0, 0, ::3] = 0.8
+    note(f"label row tiles shape={shape}")
+    lab, nd = _gpu_labels(ctx, c)
+    for t in range(2):
+        ol, k = oracle.label(c[t])
+        assert nd[t] == k
+        assert np.array_equal(lab[t], ol)
+
+
+def test_labels_dense_runs(ctx):
+    """Tiles with more runs than the local pass holds in LDS (32 runs in every segment): even-x
+    columns joined through y and z, and a 3-D checkerboard of one-cell drops."""
+    shape = (8, 16, 512)
+    c = np.zeros((2,) + shape)
+    zz, yy, xx = np.meshgrid(*(np.arange(n) for n in shape), indexing="ij")
+    c[0][(xx % 2 == 0) & (zz < 5)] = 0.7
+    c[0][6, 3, 100:300] = 0.9  # a long run joining some columns in one plane
+    c[1][(xx + yy + zz) % 2 == 0] = 0.6
+    note("label dense runs")
+    lab, nd = _gpu_labels(ctx, c)
+    for t in range(2):
+        ol, k = oracle.label(c[t])
+        assert nd[t] == k
+        assert np.array_equal(lab[t], ol)
+
+
 def test_labels_long_runs_and_wrap(ctx):
     # runs crossing 64-cell segment boundaries, spirals and full rows
     c = np.zeros((1, 9, 7, 200))
