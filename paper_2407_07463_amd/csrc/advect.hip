@@ -25,41 +25,6 @@ __global__ __launch_bounds__(256) void k_plic(const double *__restrict__ cin, co
                ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
 }
 
-// Workgroup -> (tile, tracer group) of a streaming launch that covers ngrp
-// groups of G tracers over a gx x gy x gz tile grid (launched as gx x gy x
-// gz*ngrp). Workgroups are dealt to the 8 XCDs in turn by linear id, so each
-// block of 8*ngrp consecutive ids holds 8 tiles (fewer in the last block) and
-// gives the groups of one tile ids that are a multiple of 8 apart: they land
-// on the same XCD at about the same time, and the face velocity the groups
-// share is read from HBM once and from that XCD's L2 by the others.
-// Tiles are numbered row-first (bx, then by, then the chunk bz), or with
-// cfast chunk-first (bx, bz, by). The y-sweep takes the latter: neighbouring
-// workgroups then march one z-plane at different y (128 KiB apart at 512^2
-// planes) instead of neighbouring z-planes at the same y (2 MiB apart); it
-// measured 7% faster there and slower on the other two sweeps.
-struct GroupTile {
-  int bx, by, bz, grp;
-};
-__device__ __forceinline__ GroupTile group_tile(int ngrp, bool cfast) {
-  const int gx = gridDim.x, gy = gridDim.y, gz = gridDim.z / ngrp;
-  const int L = ((int)blockIdx.z * gy + (int)blockIdx.y) * gx + (int)blockIdx.x;
-  const int ntile = gx * gy * gz;
-  const int blk = L / (8 * ngrp), r = L - blk * 8 * ngrp;
-  const int q = min(8, ntile - blk * 8);  // tiles in this block
-  const int tile = blk * 8 + r % q;
-  GroupTile o;
-  o.grp = r / q;
-  o.bx = tile % gx;
-  if (cfast) {
-    o.bz = (tile / gx) % gz;
-    o.by = tile / (gx * gz);
-  } else {
-    o.by = (tile / gx) % gy;
-    o.bz = tile / (gx * gy);
-  }
-  return o;
-}
-
 template <int D, int G>
 __global__ __launch_bounds__(64 * kXWaves) void k_stream(const double *__restrict__ cin, double *__restrict__ cout,
                                                         const double *__restrict__ s, const double *__restrict__ fmix,
@@ -67,7 +32,8 @@ __global__ __launch_bounds__(64 * kXWaves) void k_stream(const double *__restric
                                                         int ny, int nz, int words, int chunk,
                                                         uint32_t *__restrict__ list_next, int *__restrict__ counts_next,
                                                         int64_t region0, int rsize, int ngrp, int64_t gstride) {
-  const GroupTile g = group_tile(ngrp, D == 1);
+  const GroupTile g = group_tile(((int)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x, gridDim.x,
+                                 gridDim.y, gridDim.z / ngrp, ngrp, D == 1);
   stream_body<D, G, kXWaves>(cin, cout, s, fmix, ccbits, write_cc, t0 + g.grp * G, nx, ny, nz, words, chunk,
                              list_next, counts_next, region0 + g.grp * gstride, rsize, g.bx, g.by, g.bz, gridDim.x,
                              gridDim.y);
@@ -81,7 +47,8 @@ __global__ __launch_bounds__(256) void k_stream_rows(const double *__restrict__ 
                                                      int ny, int nz, int words, int chunk,
                                                      uint32_t *__restrict__ list_next, int *__restrict__ counts_next,
                                                      int64_t region0, int rsize, int ngrp, int64_t gstride) {
-  const GroupTile g = group_tile(ngrp, false);
+  const GroupTile g = group_tile(((int)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x, gridDim.x,
+                                 gridDim.y, gridDim.z / ngrp, ngrp, false);
   stream_body<0, G, 0>(cin, cout, s, fmix, ccbits, write_cc, t0 + g.grp * G, nx, ny, nz, words, chunk, list_next,
                        counts_next, region0 + g.grp * gstride, rsize, g.bx, g.by, g.bz, gridDim.x, gridDim.y);
 }

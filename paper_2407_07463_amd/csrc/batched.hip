@@ -29,13 +29,16 @@ struct BoxDev {
   int *counts[2];
 };
 
-// A run of work items that belong to one box (and one tracer group).
+// A run of work items that belong to one box (and, in a streaming pass, to
+// ngrp consecutive tracer groups of one size).
 struct Seg {
   int64_t item0;    // first global work item of the run
   int64_t nitems;   // its length
-  int box, t0;      // box, first tracer of the group
-  int64_t region0;  // first list region of the group
-  int gx, gy;       // tile grid of the streaming pass (x blocks, row blocks)
+  int box, t0;      // box, first tracer of the first group
+  int64_t region0;  // first list region of the first group
+  int gx, gy, gz;   // tile grid of the streaming pass (x blocks, row blocks, chunks)
+  int ngrp;         // groups (group k: tracers from t0 + k * G, regions from region0 + k * gstride)
+  int64_t gstride;
 };
 
 __device__ __forceinline__ int find_seg(const Seg *__restrict__ segs, int nseg, int64_t item) {
@@ -80,16 +83,16 @@ __global__ __launch_bounds__(256) void k_stream_b(const BoxDev *__restrict__ box
   for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
     const Seg sg = segs[find_seg(segs, nseg, item)];
     const BoxDev &b = boxes[sg.box];
-    const int64_t lb = item - sg.item0;
-    const int bx = (int)(lb % sg.gx);
-    const int by = (int)((lb / sg.gx) % sg.gy);
-    const int bz = (int)(lb / ((int64_t)sg.gx * sg.gy));
+    // (the grid is a multiple of 8 workgroups, so items 8 apart share an XCD)
+    const GroupTile g = group_tile(item - sg.item0, sg.gx, sg.gy, sg.gz, sg.ngrp, D == 1);
+    const int t0 = sg.t0 + g.grp * G;
+    const int64_t region0 = sg.region0 + g.grp * sg.gstride;
     if (D == 0 && b.xwpb == 0)  // uniform over the workgroup
-      stream_body<D, G, 0>(b.f[par], b.f[par ^ 1], b.s[D], b.fmix, b.bits, write_cc, sg.t0, b.nx, b.ny, b.nz,
-                           b.words, chunk, b.list[nxt], b.counts[nxt], sg.region0, rsize, bx, by, bz, sg.gx, sg.gy);
+      stream_body<D, G, 0>(b.f[par], b.f[par ^ 1], b.s[D], b.fmix, b.bits, write_cc, t0, b.nx, b.ny, b.nz, b.words,
+                           chunk, b.list[nxt], b.counts[nxt], region0, rsize, g.bx, g.by, g.bz, sg.gx, sg.gy);
     else
-      stream_body<D, G>(b.f[par], b.f[par ^ 1], b.s[D], b.fmix, b.bits, write_cc, sg.t0, b.nx, b.ny, b.nz, b.words,
-                        chunk, b.list[nxt], b.counts[nxt], sg.region0, rsize, bx, by, bz, sg.gx, sg.gy);
+      stream_body<D, G>(b.f[par], b.f[par ^ 1], b.s[D], b.fmix, b.bits, write_cc, t0, b.nx, b.ny, b.nz, b.words,
+                        chunk, b.list[nxt], b.counts[nxt], region0, rsize, g.bx, g.by, g.bz, sg.gx, sg.gy);
   }
 }
 
@@ -240,24 +243,31 @@ static size_t plan_layout(const vofmt_box *boxes, int nboxes, int chunk, Plan &p
         const Tiles tg = stream_tiles(d, b.nx, b.ny, b.nz, chunk, xw);
         const int gx = tg.gx, gy = tg.gy, gz = tg.gz;
         const int64_t per = stream_waves(d, b.nx, b.ny, b.nz, chunk, xw);
+        // all full groups of the box in one run of items, then one run per
+        // group of 2 or 1 (list regions in group order, as in the plain path)
+        const int nfull = b.ntracers / kMaxGroup;
         int64_t region0 = 0;
         for (int t = 0; t < b.ntracers;) {
           const int g = group_size(b.ntracers - t);
+          const int ng = (g == kMaxGroup) ? nfull : 1;
           if (kind_of(g) == kind) {
             Seg s{};
             s.item0 = pl.items_stream[d][kind];
-            s.nitems = (int64_t)gx * gy * gz;
+            s.nitems = (int64_t)gx * gy * gz * ng;
             s.box = i;
             s.t0 = t;
             s.region0 = region0;
             s.gx = gx;
             s.gy = gy;
+            s.gz = gz;
+            s.ngrp = ng;
+            s.gstride = per;
             seg_all.push_back(s);
             pl.items_stream[d][kind] += s.nitems;
             ++pl.n_stream[d][kind];
           }
-          t += g;
-          region0 += per;
+          t += g * ng;
+          region0 += per * ng;
         }
       }
     }
