@@ -30,7 +30,9 @@ the advected field (labelling, moments, shapes, recolouring in both
 near-contact modes, pair statistics with M, R, A and the densities, height-
 function and learned curvature of every tracer with their agreement, the
 surface-tension force, network training, the tracer count N(t) over the
-256^3 workload and batched advection of 32 uneven boxes), and under
+256^3 workload and batched advection of 32 uneven boxes; labelling, moments,
+shapes, recolouring, pair statistics and the force are the median of 5 timed
+calls, their times in `runs_ms`), and under
 `cpu_baseline` the CPU oracle timed on a bounded sample, multi- and
 single-threaded.
 
@@ -82,6 +84,18 @@ def timed(torch, stream, fn):
     b.record(stream)
     torch.cuda.synchronize()
     return a.elapsed_time(b), r
+
+
+def timed_median(torch, stream, fn, runs=5, prepare=None):
+    """Median over `runs` timed calls of fn (each after an untimed prepare(), if given), the
+    list of times, and the last call's result."""
+    ts, r = [], None
+    for _ in range(runs):
+        if prepare is not None:
+            prepare()
+        ms, r = timed(torch, stream, fn)
+        ts.append(ms)
+    return statistics.median(ts), ts, r
 
 
 def cpu_info():
@@ -136,17 +150,17 @@ def rows_bench(torch, np, ctx, stream, c, w, n, ntr):
     # ---- labelling and moments
     lab = torch.zeros(c.shape, dtype=torch.int32, device=dev)
     ctx.label_drops(c, lab)  # warm
-    ms, nd = timed(torch, stream, lambda: ctx.label_drops(c, lab))
+    ms, runs, nd = timed_median(torch, stream, lambda: ctx.label_drops(c, lab))
     D = int(nd.sum())
     lab_bytes = n3 * ntr * (8.0 + 4.0)  # read c, write the label
-    rows["label_drops"] = dict(ms=ms, drops=D, cells_per_s=n3 * ntr / (ms / 1e3),
+    rows["label_drops"] = dict(ms=ms, runs_ms=runs, drops=D, cells_per_s=n3 * ntr / (ms / 1e3),
                                hbm_frac=lab_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS)
     log(f"label_drops: {ms:.2f} ms, {D} drops")
     vol = torch.zeros(D, dtype=torch.float64, device=dev)
     xyz = torch.zeros((D, 3), dtype=torch.float64, device=dev)
     ctx.drop_moments(c, lab, nd, vol, xyz)
-    ms, _ = timed(torch, stream, lambda: ctx.drop_moments(c, lab, nd, vol, xyz))
-    rows["drop_moments"] = dict(ms=ms)
+    ms, runs, _ = timed_median(torch, stream, lambda: ctx.drop_moments(c, lab, nd, vol, xyz))
+    rows["drop_moments"] = dict(ms=ms, runs_ms=runs)
     log(f"drop_moments: {ms:.2f} ms")
     # ---- drop shapes: inertia tensors, aspect ratios and mean velocities
     sv = [torch.from_numpy(w[k]).to(dev) for k in ("sx", "sy", "sz")]
@@ -154,30 +168,37 @@ def rows_bench(torch, np, ctx, stream, c, w, n, ntr):
     chi = torch.zeros(D, dtype=torch.float64, device=dev)
     velo = torch.zeros((D, 3), dtype=torch.float64, device=dev)
     ctx.drop_shapes(c, lab, nd, inertia, chi, sv, velo)
-    ms, _ = timed(torch, stream, lambda: ctx.drop_shapes(c, lab, nd, inertia, chi, sv, velo))
-    rows["drop_shapes"] = dict(ms=ms, drops=D, chi_mean=float(chi.mean().item()),
+    ms, runs, _ = timed_median(torch, stream, lambda: ctx.drop_shapes(c, lab, nd, inertia, chi, sv, velo))
+    rows["drop_shapes"] = dict(ms=ms, runs_ms=runs, drops=D, chi_mean=float(chi.mean().item()),
                                chi_max=float(chi.max().item()))
     log(f"drop_shapes: {ms:.2f} ms, mean aspect ratio {rows['drop_shapes']['chi_mean']:.4f}")
     ctx.drop_moments_shapes(c, lab, nd, vol, xyz, inertia, chi, sv, velo)
-    ms, _ = timed(torch, stream, lambda: ctx.drop_moments_shapes(c, lab, nd, vol, xyz, inertia, chi, sv, velo))
-    rows["drop_moments_shapes"] = dict(ms=ms, separate_ms=rows["drop_moments"]["ms"] + rows["drop_shapes"]["ms"])
+    ms, runs, _ = timed_median(torch, stream,
+                               lambda: ctx.drop_moments_shapes(c, lab, nd, vol, xyz, inertia, chi, sv, velo))
+    rows["drop_moments_shapes"] = dict(ms=ms, runs_ms=runs, separate_ms=rows["drop_moments"]["ms"] + rows["drop_shapes"]["ms"])
     log(f"drop_moments_shapes: {ms:.2f} ms (separately {rows['drop_moments_shapes']['separate_ms']:.2f} ms)")
     del sv, inertia, chi, velo
-    # ---- recolouring in both near-contact modes (each on a fresh copy with room for 2N tracers);
-    # one untimed call first (it sizes the scratch buffers), then the timed call
+    # ---- recolouring in both near-contact modes (each call on a fresh copy with room for 2N
+    # tracers, made outside the timed region); one untimed call first (it sizes the scratch
+    # buffers), then the timed calls
     cap = 2 * ntr
     cr = torch.zeros((cap,) + tuple(c.shape[1:]), dtype=torch.float64, device=dev)
     newt = torch.zeros(max(D, 1), dtype=torch.int32, device=dev)
+
+    def fresh():
+        cr.zero_()
+        cr[:ntr].copy_(c)
+
     for mode in ("tau", "stencil"):
-        for _ in range(2):
-            cr.zero_()
-            cr[:ntr].copy_(c)
-            if mode == "tau":
-                ms, (ntr2, moved) = timed(torch, stream, lambda: ctx.recolor_tracers(cr, ntr, lab, nd, 1.5, newt))
-            else:
-                ms, (ntr2, moved) = timed(torch, stream, lambda: ctx.recolor_tracers_stencil(cr, ntr, lab, nd, newt))
+        if mode == "tau":
+            fn = lambda: ctx.recolor_tracers(cr, ntr, lab, nd, 1.5, newt)
+        else:
+            fn = lambda: ctx.recolor_tracers_stencil(cr, ntr, lab, nd, newt)
+        fresh()
+        fn()
+        ms, runs, (ntr2, moved) = timed_median(torch, stream, fn, prepare=fresh)
         key = "recolor_tracers" if mode == "tau" else "recolor_tracers_stencil"
-        rows[key] = dict(ms=ms, tracers_after=ntr2, drops_moved=moved,
+        rows[key] = dict(ms=ms, runs_ms=runs, tracers_after=ntr2, drops_moved=moved,
                          criterion="distance gap 1.5 cells" if mode == "tau" else "5x5x5 stencil, Steps 1-3")
         log(f"{key}: {ms:.2f} ms, {moved} drops moved, {ntr2} tracers")
     del cr, newt
@@ -194,15 +215,16 @@ def rows_bench(torch, np, ctx, stream, c, w, n, ntr):
     A = torch.zeros(9, dtype=torch.float64, device=dev)
     box = [float(n)] * 3
     ctx.nearest_pair_stats(xyz, box, 2, r2e, ce, idx, ties, hist, M, R, A)
-    ms, _ = timed(torch, stream, lambda: ctx.nearest_pair_stats(xyz, box, 2, r2e, ce, idx, ties, hist, M, R, A))
+    ms, _, _ = timed_median(torch, stream,
+                            lambda: ctx.nearest_pair_stats(xyz, box, 2, r2e, ce, idx, ties, hist, M, R, A))
     P = torch.zeros(nr * nth, dtype=torch.float64, device=dev)
     Pr = torch.zeros(nr, dtype=torch.float64, device=dev)
-    ms_pdf, _ = timed(torch, stream, lambda: ctx.pair_pdfs(r_edges, th_edges, hist, D, P, Pr))
+    ms_pdf, _, _ = timed_median(torch, stream, lambda: ctx.pair_pdfs(r_edges, th_edges, hist, D, P, Pr))
     ms_na = None
     if D <= 8192:
         ctx.nearest_pair_stats_noalloc(xyz, box, 2, r2e, ce, idx, ties, hist, M, R, A)
-        ms_na, _ = timed(torch, stream,
-                         lambda: ctx.nearest_pair_stats_noalloc(xyz, box, 2, r2e, ce, idx, ties, hist, M, R, A))
+        ms_na, _, _ = timed_median(
+            torch, stream, lambda: ctx.nearest_pair_stats_noalloc(xyz, box, 2, r2e, ce, idx, ties, hist, M, R, A))
     Rh = R.cpu().numpy().reshape(3, 3)
     Ah = A.cpu().numpy().reshape(3, 3)
     Prh = Pr.cpu().numpy()
@@ -303,9 +325,9 @@ def rows_bench(torch, np, ctx, stream, c, w, n, ntr):
     del st8
     fxyz = [torch.empty(tuple(c.shape[1:]), dtype=torch.float64, device=dev) for _ in range(3)]
     ctx.csf_force(c, kap8, 1.0, *fxyz)
-    ms, _ = timed(torch, stream, lambda: ctx.csf_force(c, kap8, 1.0, *fxyz))
+    ms, runs, _ = timed_median(torch, stream, lambda: ctx.csf_force(c, kap8, 1.0, *fxyz))
     csf_bytes = n3 * (16.0 * ntr + 24.0)  # every tracer's c and kappa read once, three face arrays written
-    rows["csf_force"] = dict(ms=ms, cells_per_s=n3 / (ms / 1e3), algorithmic_bytes=csf_bytes,
+    rows["csf_force"] = dict(ms=ms, runs_ms=runs, cells_per_s=n3 / (ms / 1e3), algorithmic_bytes=csf_bytes,
                              achieved_gbs=csf_bytes / (ms / 1e3) / 1e9,
                              hbm_frac=csf_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS)
     log(f"csf_force: {ms:.2f} ms, {rows['csf_force']['achieved_gbs']:.0f} GB/s of the method's bytes")
