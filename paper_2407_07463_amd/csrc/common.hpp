@@ -11,7 +11,7 @@
 
 #include "vofmt.h"
 
-enum { kNumSlotsDecl = 25 };
+enum { kNumSlotsDecl = 26 };
 
 // One timed launch: HIP events recorded before and after it on its stream.
 struct ProfRec {
@@ -68,7 +68,8 @@ enum ScratchSlot {
   SLOT_CURV_HF = 22,     // cells handed to the height-function fallback; recolouring: list predicate bits
   SLOT_RECOLOR_LIST = 23,  // recolouring: drop-boundary and shared cells
   SLOT_OCC = 24,           // recolouring, stencil mode: occupancy bits per 64-cell row segment
-  kNumSlots = 25,
+  SLOT_OCC_OTHERS = 25,    // and those of the other tracers
+  kNumSlots = 26,
 };
 static_assert(kNumSlots == kNumSlotsDecl, "scratch slot count");
 

@@ -373,6 +373,94 @@ __global__ __launch_bounds__(kBlock) void k_stencil_edges(const int32_t *__restr
   }
 }
 
+// Occupancy of the other tracers: word (row, w) of others[t] is the OR of
+// that word of occ[u] over every tracer u != t (prefix ORs going up, suffix
+// ORs coming down). nseg1: words per tracer.
+__global__ __launch_bounds__(kBlock) void k_other_tracers(const uint64_t *__restrict__ occ, int64_t nseg1, int ntr,
+                                                          uint64_t *__restrict__ others) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nseg1) return;
+  uint64_t acc = 0;
+  for (int t = 0; t < ntr; ++t) {
+    others[(int64_t)t * nseg1 + i] = acc;
+    acc |= occ[(int64_t)t * nseg1 + i];
+  }
+  acc = 0;
+  for (int t = ntr - 1; t >= 0; --t) {
+    others[(int64_t)t * nseg1 + i] |= acc;
+    acc |= occ[(int64_t)t * nseg1 + i];
+  }
+}
+
+// Stencil mode, contacts across tracers (persistent grid over the listed
+// cells): the pairs k_edges finds with the half cube max|o_a| <= 4, where
+// only drops of different tracers are related. A listed cell p of a single
+// drop a, of tracer t, takes the cube row by row: a 9-bit window of others[t]
+// (cells x-4 .. x+4 of the row; x+1 .. x+4 in its own row) marks the cells
+// that hold a drop of another tracer, and only their owners are loaded. A
+// cell with no other tracer can pair a with no drop of another tracer, so the
+// edges are those of the full scan. Shared cells take the full scan.
+__global__ __launch_bounds__(kBlock) void k_edges_cross(const int32_t *__restrict__ own,
+                                                        const int32_t *__restrict__ lab, const uint64_t *__restrict__ others,
+                                                        int nx, int ny, int nz, int ntr, int xw, TracerOffsets to,
+                                                        const int4 *__restrict__ offs, int noffs, int small_offsets,
+                                                        const int32_t *__restrict__ list,
+                                                        const int32_t *__restrict__ count, uint32_t *__restrict__ adj,
+                                                        int64_t words, FastDiv fnx, FastDiv fny,
+                                                        const int32_t *__restrict__ T0) {
+  const int64_t n3 = (int64_t)nx * ny * nz;
+  const int64_t nseg1 = (int64_t)nz * ny * xw;
+  const int nlist = *count;
+  for (int qi = blockIdx.x * kBlock + threadIdx.x; qi < nlist; qi += gridDim.x * kBlock) {
+    const int64_t p = list[qi];
+    const int32_t a = own[p];
+    if (a < 0) {  // a shared cell
+      edges_of(own, lab, nx, ny, nz, ntr, to, offs, noffs, small_offsets, adj, words, n3, fnx, fny, T0, p);
+      continue;
+    }
+    const uint32_t r = fast_div((uint32_t)p, fnx), zz = fast_div(r, fny);  // cells < 2^31
+    const int x = (int)((uint32_t)p - r * (uint32_t)nx), y = (int)(r - zz * (uint32_t)ny), z = (int)zz;
+    const int ta = T0[a];
+    const uint64_t *ot = others + (int64_t)ta * nseg1;
+    int32_t last_b = -1;
+    auto visit = [&](int64_t q) {
+      const int32_t b = own[q];
+      if (b == -1 || b == last_b) return;
+      if (b >= 0) {
+        if (T0[b] != ta) {
+          set_edge(adj, words, a, b);
+          last_b = b;
+        }
+      } else {
+        for_drops_at(lab, n3, ntr, to, q, [&](int32_t v) {
+          if (T0[v] != ta) set_edge(adj, words, a, v);
+        });
+      }
+    };
+    // the 40 rows of the half cube: (dz, dy) = (0, 1..4) and (1..4, -4..4)
+    for (int dz = 0; dz <= 4; ++dz)
+      for (int dy = (dz == 0 ? 1 : -4); dy <= 4; ++dy) {
+        const int64_t row = (int64_t)wrap_any(z + dz, nz) * ny + wrap_any(y + dy, ny);
+        uint64_t m = row_window(ot + row * xw, nx, x - 4) & 0x1FFull;
+        while (m) {
+          const int i = __ffsll((unsigned long long)m) - 1;
+          m &= m - 1;
+          visit(row * nx + wrap_any(x - 4 + i, nx));
+        }
+      }
+    // the cell's own row: x+1 .. x+4
+    {
+      const int64_t row = (int64_t)z * ny + y;
+      uint64_t m = row_window(ot + row * xw, nx, x + 1) & 0xFull;
+      while (m) {
+        const int i = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        visit(row * nx + wrap_any(x + 1 + i, nx));
+      }
+    }
+  }
+}
+
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
@@ -768,6 +856,8 @@ static int recolor_impl(vofmt_ctx *ctx, const char *fn, int stencil, int32_t nx,
   hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, stream, adj, D * words, 0u);
   // initial tracer of every drop (the stencil mode's cross-tracer filter reads it)
   hipLaunchKernelGGL(k_initial_tracers, dim3(ceil_div(D, 256)), dim3(256), 0, stream, T0, (int32_t)D, ntr, to);
+  uint64_t *others = nullptr;
+  int xw_stencil = 0;
   if (stencil) {
     // Steps 1-3 within every tracer, on occupancy bits per row segment
     const int xw = (int)ceil_div(nx, 64);
@@ -787,6 +877,13 @@ static int recolor_impl(vofmt_ctx *ctx, const char *fn, int stencil, int32_t nx,
     }
     hipLaunchKernelGGL(k_stencil_edges, dim3((unsigned)nblk), dim3(kBlock), 0, stream, labels, occ, nx, ny, nz, ntr,
                        xw, to, make_stencil_pairs(), adj, words);
+    // the other tracers' occupancy, for the contacts across tracers
+    const int64_t nseg1 = rows * xw;
+    others = (uint64_t *)scratch(ctx, SLOT_OCC_OTHERS, sizeof(uint64_t) * (size_t)nseg);
+    if (!others) return VOFMT_E_NOMEM;
+    hipLaunchKernelGGL(k_other_tracers, dim3(ceil_div(nseg1, kBlock)), dim3(kBlock), 0, stream, occ, nseg1, ntr,
+                       others);
+    xw_stencil = xw;
   }
   {
     // the cells that can see a pair, in order, then the pairs they see
@@ -802,9 +899,14 @@ static int recolor_impl(vofmt_ctx *ctx, const char *fn, int stencil, int32_t nx,
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
       cus = 256;
-    hipLaunchKernelGGL(k_edges, dim3(8 * cus), dim3(kBlock), 0, stream, own, labels, nx, ny, nz, ntr, to, doffs,
-                       noffs, small_offsets, srcs, tot + lt, adj, words, make_fastdiv((uint32_t)nx),
-                       make_fastdiv((uint32_t)ny), stencil ? (const int32_t *)T0 : nullptr);
+    if (stencil)
+      hipLaunchKernelGGL(k_edges_cross, dim3(8 * cus), dim3(kBlock), 0, stream, own, labels, others, nx, ny, nz, ntr,
+                         xw_stencil, to, doffs, noffs, small_offsets, srcs, tot + lt, adj, words,
+                         make_fastdiv((uint32_t)nx), make_fastdiv((uint32_t)ny), (const int32_t *)T0);
+    else
+      hipLaunchKernelGGL(k_edges, dim3(8 * cus), dim3(kBlock), 0, stream, own, labels, nx, ny, nz, ntr, to, doffs,
+                         noffs, small_offsets, srcs, tot + lt, adj, words, make_fastdiv((uint32_t)nx),
+                         make_fastdiv((uint32_t)ny), nullptr);
   }
   hipLaunchKernelGGL(k_symmetrise, dim3(ceil_div(D * D, kBlock)), dim3(kBlock), 0, stream, adj, (int32_t)D, words);
   hipLaunchKernelGGL(k_degree, dim3(ceil_div(D, kBlock)), dim3(kBlock), 0, stream, adj, (int32_t)D, words, deg);
