@@ -307,16 +307,21 @@ static StencilPairs make_stencil_pairs() {
 __global__ __launch_bounds__(kBlock) void k_stencil_edges(const int32_t *__restrict__ lab,
                                                           const uint64_t *__restrict__ occ, int nx, int ny, int nz,
                                                           int ntr, int words, TracerOffsets to, StencilPairs sp,
-                                                          uint32_t *__restrict__ adj, int64_t awords) {
+                                                          uint32_t *__restrict__ adj, int64_t awords, FastDiv fw,
+                                                          FastDiv frows, FastDiv fny) {
   const int64_t seg = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   const int64_t rows = (int64_t)nz * ny;
   if (seg >= (int64_t)ntr * rows * words) return;  // whole wavefront
-  const int64_t tr = seg / words;                  // (t, z, y) row of all tracers
-  const int w = (int)(seg - tr * words);
-  const int t = (int)(tr / rows);
-  const int64_t r = tr - (int64_t)t * rows;
-  const int z = (int)(r / ny), y = (int)(r - (int64_t)z * ny);
+  // (t, z, y) row of all tracers and word w: segment counts stay below 2^31,
+  // so the divisions are 32-bit multiply-shifts
+  const uint32_t tr = fast_div((uint32_t)seg, fw);
+  const int w = (int)((uint32_t)seg - tr * (uint32_t)words);
+  const uint32_t t32 = fast_div(tr, frows);
+  const int t = (int)t32;
+  const int64_t r = (int64_t)(tr - t32 * (uint32_t)rows);
+  const uint32_t z32 = fast_div((uint32_t)r, fny);
+  const int z = (int)z32, y = (int)((uint32_t)r - z32 * (uint32_t)ny);
   const uint64_t *occ_t = occ + (int64_t)t * rows * words;
   const int x0 = 64 * w;
   // offsets reach 2 cells: one conditional wrap when the axis has 3 cells or more
@@ -866,7 +871,7 @@ static int recolor_impl(vofmt_ctx *ctx, const char *fn, int stencil, int32_t nx,
     uint64_t *occ = (uint64_t *)scratch(ctx, SLOT_OCC, sizeof(uint64_t) * (size_t)nseg);
     if (!occ) return VOFMT_E_NOMEM;
     const int64_t nblk = (nseg * 64 + kBlock - 1) / kBlock;
-    if (nblk > INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "%s: grid too large", fn);
+    if (nblk > INT32_MAX || nseg >= INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "%s: grid too large", fn);
     if (nx % 256 == 0 && ((uintptr_t)labels & 15) == 0) {
       const int64_t ngroups = nseg / 4;  // rows of whole 256-cell groups: segment 4g + j is cells 64(4g + j) ..
       hipLaunchKernelGGL(k_occ_words4, dim3((unsigned)((ngroups * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
@@ -876,7 +881,8 @@ static int recolor_impl(vofmt_ctx *ctx, const char *fn, int stencil, int32_t nx,
                          (int64_t)ntr * rows, xw, occ);
     }
     hipLaunchKernelGGL(k_stencil_edges, dim3((unsigned)nblk), dim3(kBlock), 0, stream, labels, occ, nx, ny, nz, ntr,
-                       xw, to, make_stencil_pairs(), adj, words);
+                       xw, to, make_stencil_pairs(), adj, words, make_fastdiv((uint32_t)xw),
+                       make_fastdiv((uint32_t)rows), make_fastdiv((uint32_t)ny));
     // the other tracers' occupancy, for the contacts across tracers
     const int64_t nseg1 = rows * xw;
     others = (uint64_t *)scratch(ctx, SLOT_OCC_OTHERS, sizeof(uint64_t) * (size_t)nseg);
