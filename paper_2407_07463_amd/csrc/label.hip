@@ -484,20 +484,21 @@ __global__ __launch_bounds__(kBlock) void k_label_union_edges(const uint64_t *__
   occ += blockIdx.y * nseg;
   T.P += blockIdx.y * nrun;
   if (i >= nedge) return;
-  const int64_t q = i / words;
-  const int seg = (int)(i - q * words);
-  const int64_t na = (int64_t)e.nzb * ny;
+  // (nedge <= segments < 2^31: 32-bit divisions)
+  const uint32_t q = (uint32_t)i / (uint32_t)words;
+  const int seg = (int)((uint32_t)i - q * (uint32_t)words);
+  const uint32_t na = (uint32_t)e.nzb * (uint32_t)ny;
   int y, z;
   bool do_y, do_z;
   if (q < na) {
-    const int k = (int)(q / ny);
-    y = (int)(q - (int64_t)k * ny);
+    const int k = (int)(q / (uint32_t)ny);
+    y = (int)(q - (uint32_t)k * (uint32_t)ny);
     z = min(k * rt.tz + rt.tz - 1, nz - 1);
     do_z = true;
     do_y = e.nyb > 0 && (y % rt.ty == rt.ty - 1 || y == ny - 1);
   } else {
-    const int64_t qb = q - na;
-    const int kz = (int)(qb / e.nyb), ky = (int)(qb - (int64_t)kz * e.nyb);
+    const uint32_t qb = q - na;
+    const int kz = (int)(qb / (uint32_t)e.nyb), ky = (int)(qb - (uint32_t)kz * (uint32_t)e.nyb);
     y = min(ky * rt.ty + rt.ty - 1, ny - 1);
     // the kz-th plane that is not the top of its z tile
     z = (e.nzb == 0) ? kz : (kz / (rt.tz - 1)) * rt.tz + kz % (rt.tz - 1);

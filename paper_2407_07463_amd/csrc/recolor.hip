@@ -752,9 +752,13 @@ __global__ __launch_bounds__(kSumBlock) void k_sum_retired(const double *__restr
   const int64_t q0 = (int64_t)blockIdx.x * chunk;
   const int64_t q1 = q0 + chunk < total ? q0 + chunk : total;
   double acc = 0.0;
+  int64_t r = (q0 + threadIdx.x) / n3, rend = (r + 1) * n3;  // field of q, and where it ends
   for (int64_t q = q0 + threadIdx.x; q < q1; q += kSumBlock) {
-    const int64_t r = q / n3;
-    acc += c[(int64_t)which[r] * n3 + (q - r * n3)];
+    while (q >= rend) {  // (a field holds at least one cell: n3 >= 1)
+      ++r;
+      rend += n3;
+    }
+    acc += c[(int64_t)which[r] * n3 + (q - (rend - n3))];
   }
   __shared__ double red[kSumBlock];
   red[threadIdx.x] = acc;
