@@ -783,8 +783,16 @@ __device__ __forceinline__ void merge_record(int32_t *key, int32_t *rfirst, int3
 
 // First cell and the frame extents of every drop.
 __global__ __launch_bounds__(kBlock) void k_drop_scan(const int32_t *__restrict__ lab, int64_t n3, int nx, int ny,
-                                                      int nz, FastDiv fnx, FastDiv fny, int32_t K,
+                                                      int nz, FastDiv fnx, FastDiv fny,
+                                                      const int32_t *__restrict__ toff,
                                                       int32_t *__restrict__ first, int32_t *__restrict__ frames) {
+  // field blockIdx.y: its drops are records toff[t] .. toff[t+1]-1
+  const int t = blockIdx.y;
+  const int32_t o = toff[t], K = toff[t + 1] - o;
+  if (K == 0) return;  // (uniform over the workgroup)
+  lab += (int64_t)t * n3;
+  first += o;
+  frames += (int64_t)kFrames * o;
   __shared__ int32_t key[kTable];
   __shared__ int32_t rfirst[kTable];
   __shared__ int32_t rec[kTable][kFrames];
@@ -905,13 +913,26 @@ __global__ void k_drop_box(int32_t K, int nx, int ny, int nz, const int32_t *__r
 // tree); k_drop_finish adds the parts of each drop in order. The result is
 // reproducible bit for bit.
 constexpr int kSumSplit = 8;
+// Field of record g (toff: ntr + 1 increasing offsets) and its label.
+__device__ __forceinline__ int field_of(const int32_t *__restrict__ toff, int32_t g) {
+  int t = 0;
+  while (toff[t + 1] <= g) ++t;
+  return t;
+}
 __global__ __launch_bounds__(kBlock) void k_drop_sums(const double *__restrict__ c, const int32_t *__restrict__ lab,
-                                                      int nx, int ny, int nz, const int32_t *__restrict__ rootpos,
+                                                      int nx, int ny, int nz, const int32_t *__restrict__ toff,
+                                                      const int32_t *__restrict__ rootpos,
                                                       const int32_t *__restrict__ box, double *__restrict__ part,
                                                       int32_t *__restrict__ extent_err) {
-  const int l = blockIdx.x / kSumSplit + 1, sl = blockIdx.x % kSumSplit;
-  const int32_t p0 = rootpos[l - 1];
-  const int32_t *b = box + 6 * (int64_t)(l - 1);
+  const int32_t g = blockIdx.x / kSumSplit;  // record (drop of every field)
+  const int sl = blockIdx.x % kSumSplit;
+  const int t = field_of(toff, g);
+  const int l = g - toff[t] + 1;  // its label in field t
+  const int64_t n3 = (int64_t)nx * ny * nz;
+  c += (int64_t)t * n3;
+  lab += (int64_t)t * n3;
+  const int32_t p0 = rootpos[g];
+  const int32_t *b = box + 6 * (int64_t)g;
   if (p0 == INT32_MAX || b[0] > b[1]) {  // label without cells: inconsistent input
     if (threadIdx.x == 0) atomicOr(extent_err, 2);
     return;
@@ -951,7 +972,7 @@ __global__ __launch_bounds__(kBlock) void k_drop_sums(const double *__restrict__
       for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x < 4) part[((int64_t)(l - 1) * kSumSplit + sl) * 4 + threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x < 4) part[((int64_t)g * kSumSplit + sl) * 4 + threadIdx.x] = red[threadIdx.x][0];
 }
 
 // Volume and periodic centroid of every drop from its kSumSplit parts.
@@ -988,12 +1009,19 @@ constexpr int kShapeSums = 13;
 __global__ __launch_bounds__(kBlock) void k_shape_sums(const double *__restrict__ c, const int32_t *__restrict__ lab,
                                                        const double *__restrict__ sx, const double *__restrict__ sy,
                                                        const double *__restrict__ sz, int nx, int ny, int nz,
+                                                       const int32_t *__restrict__ toff,
                                                        const int32_t *__restrict__ rootpos,
                                                        const int32_t *__restrict__ box, double *__restrict__ part,
                                                        int32_t *__restrict__ extent_err) {
-  const int l = blockIdx.x / kSumSplit + 1, sl = blockIdx.x % kSumSplit;
-  const int32_t p0 = rootpos[l - 1];
-  const int32_t *b = box + 6 * (int64_t)(l - 1);
+  const int32_t g = blockIdx.x / kSumSplit;  // record (drop of every field)
+  const int sl = blockIdx.x % kSumSplit;
+  const int t = field_of(toff, g);
+  const int l = g - toff[t] + 1;  // its label in field t
+  const int64_t n3 = (int64_t)nx * ny * nz;
+  c += (int64_t)t * n3;
+  lab += (int64_t)t * n3;
+  const int32_t p0 = rootpos[g];
+  const int32_t *b = box + 6 * (int64_t)g;
   if (p0 == INT32_MAX || b[0] > b[1]) {  // label without cells: inconsistent input
     if (threadIdx.x == 0) atomicOr(extent_err, 2);
     return;
@@ -1050,7 +1078,7 @@ __global__ __launch_bounds__(kBlock) void k_shape_sums(const double *__restrict_
     __syncthreads();
   }
   if (threadIdx.x < kShapeSums)
-    part[((int64_t)(l - 1) * kSumSplit + sl) * kShapeSums + threadIdx.x] = red[threadIdx.x][0];
+    part[((int64_t)g * kSumSplit + sl) * kShapeSums + threadIdx.x] = red[threadIdx.x][0];
 }
 
 // Inertia tensor about the centroid, aspect ratio and mean velocity of every
@@ -1266,6 +1294,16 @@ extern "C" int vofmt_label_drops(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t
   return VOFMT_OK;
 }
 
+// Offsets of every field's drop records (prefix sums of the drop counts)
+// into device memory, staged in pinned host memory `stage` (ntr + 1 ints,
+// not touched again before the call synchronises).
+static hipError_t upload_offsets(const int32_t *ndrops_host, int ntr, int32_t *stage, int32_t *dev,
+                                 hipStream_t stream) {
+  stage[0] = 0;
+  for (int t = 0; t < ntr; ++t) stage[t + 1] = stage[t] + ndrops_host[t];
+  return hipMemcpyAsync(dev, stage, sizeof(int32_t) * (size_t)(ntr + 1), hipMemcpyHostToDevice, stream);
+}
+
 extern "C" int vofmt_drop_moments(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t ntracers,
                                   const double *c, const int32_t *labels, const int32_t *ndrops_host, double *vol,
                                   double *xyz, hipStream_t stream) {
@@ -1283,35 +1321,29 @@ extern "C" int vofmt_drop_moments(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_
   const int64_t n3 = (int64_t)nx * ny * nz;
   if (n3 >= INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_moments: more than 2^31-1 cells per field");
   VOFMT_HIP(ctx, hipSetDevice(ctx->device));
-  int64_t kmax = 0;
-  for (int t = 0; t < ntracers; ++t) kmax = ndrops_host[t] > kmax ? ndrops_host[t] : kmax;
-  int32_t *rootpos = (int32_t *)scratch(ctx, SLOT_LABEL_C, sizeof(int32_t) * (size_t)(kmax + 1));
-  int32_t *box = (int32_t *)scratch(ctx, SLOT_MISC2, sizeof(int32_t) * (6 + kFrames) * (size_t)(kmax + 1));
-  int32_t *frames = box ? box + 6 * (kmax + 1) : nullptr;
-  int32_t *flags = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * 2);
-  double *part = (double *)scratch(ctx, SLOT_LABEL_A, sizeof(double) * 4 * kSumSplit * (size_t)(kmax + 1));
-  int32_t *fh = (int32_t *)host_scratch(ctx, sizeof(int32_t) * 2);
+  // records of every field's drops, field after field (toff: their offsets)
+  int32_t *rootpos = (int32_t *)scratch(ctx, SLOT_LABEL_C, sizeof(int32_t) * (size_t)(D + 1));
+  int32_t *box = (int32_t *)scratch(ctx, SLOT_MISC2, sizeof(int32_t) * (6 + kFrames) * (size_t)(D + 1));
+  int32_t *frames = box ? box + 6 * (D + 1) : nullptr;
+  int32_t *flags = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * (size_t)(2 + ntracers + 1));
+  int32_t *toff = flags ? flags + 2 : nullptr;
+  double *part = (double *)scratch(ctx, SLOT_LABEL_A, sizeof(double) * 4 * kSumSplit * (size_t)(D + 1));
+  int32_t *fh = (int32_t *)host_scratch(ctx, sizeof(int32_t) * (size_t)(2 + ntracers + 1));
   if (!rootpos || !box || !flags || !part || !fh) return VOFMT_E_NOMEM;
+  VOFMT_HIP(ctx, upload_offsets(ndrops_host, ntracers, fh + 2, toff, stream));
   VOFMT_HIP(ctx, hipMemsetAsync(flags, 0, sizeof(int32_t) * 2, stream));
   const FastDiv fnx = make_fastdiv((uint32_t)nx), fny = make_fastdiv((uint32_t)ny);
-  const unsigned nbc = ceil_div(n3, kChunk);  // workgroups of the per-drop reductions
-  int64_t off = 0;
-  for (int t = 0; t < ntracers; ++t) {
-    const int32_t K = ndrops_host[t];
-    if (K == 0) continue;
-    const int32_t *lab = labels + (int64_t)t * n3;
-    hipLaunchKernelGGL(k_scan_init, dim3(ceil_div(kFrames * (int64_t)K, 256)), dim3(256), 0, stream, rootpos, frames,
-                       (int64_t)K);
-    hipLaunchKernelGGL(k_drop_scan, dim3(nbc), dim3(kBlock), 0, stream, lab, n3, nx, ny, nz, fnx, fny, K, rootpos,
-                       frames);
-    hipLaunchKernelGGL(k_drop_box, dim3(ceil_div(K, 256)), dim3(256), 0, stream, K, nx, ny, nz, rootpos, frames, box);
-    hipLaunchKernelGGL(k_drop_sums, dim3((unsigned)(K * kSumSplit)), dim3(kBlock), 0, stream, c + (int64_t)t * n3, lab,
-                       nx, ny, nz, rootpos, box, part, flags);
-    hipLaunchKernelGGL(k_drop_finish, dim3(ceil_div(K, 256)), dim3(256), 0, stream, K, nx, ny, nz, rootpos, box, part,
-                       vol + off, xyz + 3 * off, flags);
-    VOFMT_HIP(ctx, hipGetLastError());
-    off += K;
-  }
+  const unsigned nbc = ceil_div(n3, kChunk);  // workgroups of the per-drop reductions, per field
+  hipLaunchKernelGGL(k_scan_init, dim3(ceil_div(kFrames * D, 256)), dim3(256), 0, stream, rootpos, frames, D);
+  hipLaunchKernelGGL(k_drop_scan, dim3(nbc, ntracers), dim3(kBlock), 0, stream, labels, n3, nx, ny, nz, fnx, fny, toff,
+                     rootpos, frames);
+  hipLaunchKernelGGL(k_drop_box, dim3(ceil_div(D, 256)), dim3(256), 0, stream, (int32_t)D, nx, ny, nz, rootpos, frames,
+                     box);
+  hipLaunchKernelGGL(k_drop_sums, dim3((unsigned)(D * kSumSplit)), dim3(kBlock), 0, stream, c, labels, nx, ny, nz, toff,
+                     rootpos, box, part, flags);
+  hipLaunchKernelGGL(k_drop_finish, dim3(ceil_div(D, 256)), dim3(256), 0, stream, (int32_t)D, nx, ny, nz, rootpos, box,
+                     part, vol, xyz, flags);
+  VOFMT_HIP(ctx, hipGetLastError());
   VOFMT_HIP(ctx, hipMemcpyAsync(fh, flags, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, stream));
   VOFMT_HIP(ctx, hipStreamSynchronize(stream));
   if (fh[0] & 2) return set_err(ctx, VOFMT_E_ARG, "vofmt_drop_moments: labels do not match ndrops_host");
@@ -1343,36 +1375,29 @@ static int drop_shapes_impl(vofmt_ctx *ctx, const char *fn, bool moments, int32_
   const int64_t n3 = (int64_t)nx * ny * nz;
   if (n3 >= INT32_MAX) return set_err(ctx, VOFMT_E_ARG, "%s: more than 2^31-1 cells per field", fn);
   VOFMT_HIP(ctx, hipSetDevice(ctx->device));
-  int64_t kmax = 0;
-  for (int t = 0; t < ntracers; ++t) kmax = ndrops_host[t] > kmax ? ndrops_host[t] : kmax;
-  int32_t *rootpos = (int32_t *)scratch(ctx, SLOT_LABEL_C, sizeof(int32_t) * (size_t)(kmax + 1));
-  int32_t *box = (int32_t *)scratch(ctx, SLOT_MISC2, sizeof(int32_t) * (6 + kFrames) * (size_t)(kmax + 1));
-  int32_t *frames = box ? box + 6 * (kmax + 1) : nullptr;
-  int32_t *flags = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * 2);
-  double *part = (double *)scratch(ctx, SLOT_LABEL_A, sizeof(double) * kShapeSums * kSumSplit * (size_t)(kmax + 1));
-  int32_t *fh = (int32_t *)host_scratch(ctx, sizeof(int32_t) * 2);
+  // records of every field's drops, field after field (toff: their offsets)
+  int32_t *rootpos = (int32_t *)scratch(ctx, SLOT_LABEL_C, sizeof(int32_t) * (size_t)(D + 1));
+  int32_t *box = (int32_t *)scratch(ctx, SLOT_MISC2, sizeof(int32_t) * (6 + kFrames) * (size_t)(D + 1));
+  int32_t *frames = box ? box + 6 * (D + 1) : nullptr;
+  int32_t *flags = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * (size_t)(2 + ntracers + 1));
+  int32_t *toff = flags ? flags + 2 : nullptr;
+  double *part = (double *)scratch(ctx, SLOT_LABEL_A, sizeof(double) * kShapeSums * kSumSplit * (size_t)(D + 1));
+  int32_t *fh = (int32_t *)host_scratch(ctx, sizeof(int32_t) * (size_t)(2 + ntracers + 1));
   if (!rootpos || !box || !flags || !part || !fh) return VOFMT_E_NOMEM;
+  VOFMT_HIP(ctx, upload_offsets(ndrops_host, ntracers, fh + 2, toff, stream));
   VOFMT_HIP(ctx, hipMemsetAsync(flags, 0, sizeof(int32_t) * 2, stream));
   const FastDiv fnx = make_fastdiv((uint32_t)nx), fny = make_fastdiv((uint32_t)ny);
   const unsigned nbc = ceil_div(n3, kChunk);
-  int64_t off = 0;
-  for (int t = 0; t < ntracers; ++t) {
-    const int32_t K = ndrops_host[t];
-    if (K == 0) continue;
-    const int32_t *lab = labels + (int64_t)t * n3;
-    hipLaunchKernelGGL(k_scan_init, dim3(ceil_div(kFrames * (int64_t)K, 256)), dim3(256), 0, stream, rootpos, frames,
-                       (int64_t)K);
-    hipLaunchKernelGGL(k_drop_scan, dim3(nbc), dim3(kBlock), 0, stream, lab, n3, nx, ny, nz, fnx, fny, K, rootpos,
-                       frames);
-    hipLaunchKernelGGL(k_drop_box, dim3(ceil_div(K, 256)), dim3(256), 0, stream, K, nx, ny, nz, rootpos, frames, box);
-    hipLaunchKernelGGL(k_shape_sums, dim3((unsigned)(K * kSumSplit)), dim3(kBlock), 0, stream, c + (int64_t)t * n3,
-                       lab, sx, sy, sz, nx, ny, nz, rootpos, box, part, flags);
-    hipLaunchKernelGGL(k_shape_finish, dim3(ceil_div(K, 256)), dim3(256), 0, stream, K, nx, ny, nz, rootpos, box,
-                       part, inertia + 6 * off, chi + off, withu ? vel + 3 * off : nullptr,
-                       vol ? vol + off : nullptr, xyz ? xyz + 3 * off : nullptr, flags);
-    VOFMT_HIP(ctx, hipGetLastError());
-    off += K;
-  }
+  hipLaunchKernelGGL(k_scan_init, dim3(ceil_div(kFrames * D, 256)), dim3(256), 0, stream, rootpos, frames, D);
+  hipLaunchKernelGGL(k_drop_scan, dim3(nbc, ntracers), dim3(kBlock), 0, stream, labels, n3, nx, ny, nz, fnx, fny, toff,
+                     rootpos, frames);
+  hipLaunchKernelGGL(k_drop_box, dim3(ceil_div(D, 256)), dim3(256), 0, stream, (int32_t)D, nx, ny, nz, rootpos, frames,
+                     box);
+  hipLaunchKernelGGL(k_shape_sums, dim3((unsigned)(D * kSumSplit)), dim3(kBlock), 0, stream, c, labels, sx, sy, sz, nx,
+                     ny, nz, toff, rootpos, box, part, flags);
+  hipLaunchKernelGGL(k_shape_finish, dim3(ceil_div(D, 256)), dim3(256), 0, stream, (int32_t)D, nx, ny, nz, rootpos,
+                     box, part, inertia, chi, withu ? vel : nullptr, vol, xyz, flags);
+  VOFMT_HIP(ctx, hipGetLastError());
   VOFMT_HIP(ctx, hipMemcpyAsync(fh, flags, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, stream));
   VOFMT_HIP(ctx, hipStreamSynchronize(stream));
   if (fh[0] & 2) return set_err(ctx, VOFMT_E_ARG, "%s: labels do not match ndrops_host", fn);
