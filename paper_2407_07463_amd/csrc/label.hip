@@ -22,8 +22,9 @@
 //               the periodic boundary); a union hooks the larger root under
 //               the smaller, so every component ends rooted at its first
 //               run, whatever the order of the unions. The unions inside
-//               tiles of whole rows are made in LDS, one workgroup per tile
-//               (2a), then those across tile boundaries on the run table (2b);
+//               tiles of whole rows are made in LDS, each tile by one
+//               workgroup (2a), then those across tile boundaries on the run
+//               table (2b);
 //   3. flatten: every run points at its root; roots counted per workgroup;
 //   4. rank:    the counts are scanned and each root's entry becomes
 //               -(1 + number of roots before it);
