@@ -523,19 +523,30 @@ __device__ __forceinline__ int count_roots(const RunTable &T, uint64_t m, int64_
   return n;
 }
 
+// Passes 3-5 take kSegT segments per thread: round k of wavefront w of a
+// workgroup covers the 64 consecutive segments 64 (kSegT w + k) .. + 63 of
+// the workgroup's kBlock * kSegT, one per lane, so the segments of a
+// workgroup are in (wavefront, round, lane) order, their linear order.
+constexpr int kSegT = 4;  // (flatten + rank + resolve at 512^3 x 8: 1: 0.196 ms, 2: 0.178, 4: 0.166, 8: 0.186)
+__device__ __forceinline__ int64_t pass_segment(int k) {
+  return ((int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63)) * kSegT + 64 * k + (threadIdx.x & 63);
+}
+
 // Pass 3: every run points at its root; roots counted per workgroup.
 __global__ __launch_bounds__(kBlock) void k_label_flatten(const uint64_t *__restrict__ occ, RunTable T, int64_t nseg,
                                                           uint32_t *__restrict__ blockcount, int64_t nrun) {
-  const int64_t sgi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   occ += blockIdx.y * nseg;
   T.P += blockIdx.y * nrun;
   blockcount += blockIdx.y * gridDim.x;
+  uint64_t m[kSegT];
+#pragma unroll
+  for (int k = 0; k < kSegT; ++k) m[k] = (pass_segment(k) < nseg) ? occ[pass_segment(k)] : 0ull;
   uint32_t nroot = 0;
-  if (sgi < nseg) {
-    const uint64_t m = occ[sgi];
-    const int nr = __popcll(m & ~(m << 1));
+#pragma unroll
+  for (int k = 0; k < kSegT; ++k) {
+    const int nr = __popcll(m[k] & ~(m[k] << 1));
     for (int r = 0; r < nr; ++r) {
-      const int32_t id = (int32_t)((sgi << T.shift) + r);
+      const int32_t id = (int32_t)((pass_segment(k) << T.shift) + r);
       const int32_t root = find_root(T, id);
       if (root == id) ++nroot;
       else *T.at(id) = root;
@@ -546,9 +557,9 @@ __global__ __launch_bounds__(kBlock) void k_label_flatten(const uint64_t *__rest
   if ((threadIdx.x & 63) == 0) wcount[threadIdx.x >> 6] = nroot;
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t s = 0;
-    for (int w = 0; w < kBlock / 64; ++w) s += wcount[w];
-    blockcount[blockIdx.x] = s;
+    uint32_t sum = 0;
+    for (int w = 0; w < kBlock / 64; ++w) sum += wcount[w];
+    blockcount[blockIdx.x] = sum;
   }
 }
 
@@ -560,36 +571,48 @@ __global__ void k_copy_total(const int32_t *__restrict__ tot, int64_t ntiles, in
 }
 
 // Pass 4: each root's entry becomes -(1 + number of roots before it), in
-// run order. blockoff: per-block exclusive offsets within tiles of
-// compact::kTile blocks, tileoff: exclusive offsets of the tiles.
+// linear order: the workgroup's offset from the scanned block counts, then
+// within the workgroup the roots of earlier wavefronts, earlier rounds and
+// lower lanes.
 __global__ __launch_bounds__(kBlock) void k_label_rank(const uint64_t *__restrict__ occ, RunTable T, int64_t nseg,
                                                        const int32_t *__restrict__ blockoff,
                                                        const int32_t *__restrict__ tileoff, int64_t nrun,
                                                        int64_t tstride) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t sgi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   occ += blockIdx.y * nseg;
   T.P += blockIdx.y * nrun;
   blockoff += blockIdx.y * gridDim.x;
   tileoff += blockIdx.y * tstride;
-  const uint64_t m = (sgi < nseg) ? occ[sgi] : 0ull;
-  const int mine = (sgi < nseg) ? count_roots(T, m, sgi) : 0;
-  // exclusive prefix of the counts over the workgroup's threads
-  int incl = mine;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int v = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += v;
+  uint64_t m[kSegT];
+#pragma unroll
+  for (int k = 0; k < kSegT; ++k) m[k] = (pass_segment(k) < nseg) ? occ[pass_segment(k)] : 0ull;
+  int excl[kSegT];  // roots of the wavefront before this lane's segment of round k
+  int wtotal = 0;   // roots of the wavefront
+#pragma unroll
+  for (int k = 0; k < kSegT; ++k) {
+    const int mine = m[k] ? count_roots(T, m[k], pass_segment(k)) : 0;
+    int incl = mine;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    excl[k] = wtotal + incl - mine;
+    wtotal += __shfl(incl, 63, 64);
   }
   __shared__ int wtot[kBlock / 64];
-  if (lane == 63) wtot[w] = incl;
+  if (lane == 0) wtot[w] = wtotal;
   __syncthreads();
-  int before = blockoff[blockIdx.x] + tileoff[blockIdx.x / compact::kTile] + incl - mine;
-  for (int k = 0; k < w; ++k) before += wtot[k];
-  if (mine == 0) return;
-  const int nr = __popcll(m & ~(m << 1));
-  for (int r = 0; r < nr; ++r) {
-    const int32_t id = (int32_t)((sgi << T.shift) + r);
-    if (*T.at(id) == id) *T.at(id) = -(++before);
+  int base = blockoff[blockIdx.x] + tileoff[blockIdx.x / compact::kTile];
+  for (int k = 0; k < w; ++k) base += wtot[k];
+#pragma unroll
+  for (int k = 0; k < kSegT; ++k) {
+    if (!m[k]) continue;
+    int before = base + excl[k];
+    const int nr = __popcll(m[k] & ~(m[k] << 1));
+    for (int r = 0; r < nr; ++r) {
+      const int32_t id = (int32_t)((pass_segment(k) << T.shift) + r);
+      if (*T.at(id) == id) *T.at(id) = -(++before);
+    }
   }
 }
 
@@ -597,16 +620,19 @@ __global__ __launch_bounds__(kBlock) void k_label_rank(const uint64_t *__restric
 // label); roots are only read.
 __global__ __launch_bounds__(kBlock) void k_label_resolve(const uint64_t *__restrict__ occ, RunTable T, int64_t nseg,
                                                           int64_t nrun) {
-  const int64_t sgi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   occ += blockIdx.y * nseg;
   T.P += blockIdx.y * nrun;
-  if (sgi >= nseg) return;
-  const uint64_t m = occ[sgi];
-  const int nr = __popcll(m & ~(m << 1));
-  for (int r = 0; r < nr; ++r) {
-    int32_t *e = T.at((int32_t)((sgi << T.shift) + r));
-    const int32_t v = *e;
-    if (v >= 0) *e = *T.at(v);
+  uint64_t m[kSegT];
+#pragma unroll
+  for (int k = 0; k < kSegT; ++k) m[k] = (pass_segment(k) < nseg) ? occ[pass_segment(k)] : 0ull;
+#pragma unroll
+  for (int k = 0; k < kSegT; ++k) {
+    const int nr = __popcll(m[k] & ~(m[k] << 1));
+    for (int r = 0; r < nr; ++r) {
+      int32_t *e = T.at((int32_t)((pass_segment(k) << T.shift) + r));
+      const int32_t v = *e;
+      if (v >= 0) *e = *T.at(v);
+    }
   }
 }
 
@@ -1237,17 +1263,18 @@ static int label_all(vofmt_ctx *ctx, int nx, int ny, int nz, int T, const double
   } else {
     hipLaunchKernelGGL(k_label_union, dim3(nbs, nt), dim3(kBlock), 0, stream, occ, R, nx, ny, nz, words, dv, nrun);
   }
-  hipLaunchKernelGGL(k_label_flatten, dim3(nbs, nt), dim3(kBlock), 0, stream, occ, R, nseg, blockcount, nrun);
+  const unsigned nbg = (unsigned)ceil_div(nseg, (int64_t)kBlock * kSegT);  // passes 3-5 (<= nbs)
+  hipLaunchKernelGGL(k_label_flatten, dim3(nbg, nt), dim3(kBlock), 0, stream, occ, R, nseg, blockcount, nrun);
   static_assert(kBlock == compact::kBlock, "block counts and the tiled scan share the block size");
-  const int64_t ntiles = (nbs + compact::kTile - 1) / compact::kTile;
+  const int64_t ntiles = (nbg + compact::kTile - 1) / compact::kTile;
   int32_t *bc = (int32_t *)blockcount;
   hipLaunchKernelGGL(compact::k_scan_tile, dim3((unsigned)ntiles, nt), dim3(compact::kTile), 0, stream, bc,
-                     (int64_t)nbs, tileoff, (int64_t)nbs, tstride);
+                     (int64_t)nbg, tileoff, (int64_t)nbg, tstride);
   hipLaunchKernelGGL(compact::k_scan_totals, dim3(1, nt), dim3(compact::kTile), 0, stream, tileoff, ntiles, tstride);
   hipLaunchKernelGGL(k_copy_total, dim3(1), dim3(64 * ((T + 63) / 64)), 0, stream, tileoff, ntiles, tstride, T,
                      k_dev);
-  hipLaunchKernelGGL(k_label_rank, dim3(nbs, nt), dim3(kBlock), 0, stream, occ, R, nseg, bc, tileoff, nrun, tstride);
-  hipLaunchKernelGGL(k_label_resolve, dim3(nbs, nt), dim3(kBlock), 0, stream, occ, R, nseg, nrun);
+  hipLaunchKernelGGL(k_label_rank, dim3(nbg, nt), dim3(kBlock), 0, stream, occ, R, nseg, bc, tileoff, nrun, tstride);
+  hipLaunchKernelGGL(k_label_resolve, dim3(nbg, nt), dim3(kBlock), 0, stream, occ, R, nseg, nrun);
   if (nx % 256 == 0 && ((uintptr_t)lab & 15) == 0) {
     const int64_t ngroups = nseg / 4;  // whole 256-cell groups: segment s is cells 64 s .. 64 s + 63
     const int64_t per = (int64_t)(kBlock / 64) * kGroupsW;
