@@ -256,25 +256,44 @@ __global__ __launch_bounds__(kBlock) void k_label_local(const uint64_t *__restri
     t.nls = t.tze * t.rw;
     return t;
   };
-  auto gseg = [&](const Tile &t, int ls) -> int64_t {
+  // (lz, ly, x segment) of a local segment: the thread's first one by
+  // division, the next ones by counting on
+  struct Loc {
+    int lz, ly, sx;
+  };
+  auto locate = [&](const Tile &t, int ls) -> Loc {
     const int lz = ls / t.rw, rem = ls - lz * t.rw;
-    const int ly = rem / words, sgx = rem - ly * words;
-    return ((int64_t)(t.z0 + lz) * ny + (t.y0 + ly)) * words + sgx;
+    const int ly = rem / words;
+    return Loc{lz, ly, rem - ly * words};
+  };
+  auto next = [&](const Tile &t, Loc l) -> Loc {
+    if (++l.sx == words) {
+      l.sx = 0;
+      if (++l.ly == t.tye) {
+        l.ly = 0;
+        ++l.lz;
+      }
+    }
+    return l;
+  };
+  auto gseg = [&](const Tile &t, const Loc &l) -> int64_t {
+    return ((int64_t)(t.z0 + l.lz) * ny + (t.y0 + l.ly)) * words + l.sx;
   };
   auto load = [&](int tl, uint64_t *w) {
     const Tile t = tile_of(tl);
+    Loc l = locate(t, (int)threadIdx.x * PER);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int ls = (int)threadIdx.x * PER + k;
-      w[k] = (ls < t.nls) ? occ[gseg(t, ls)] : 0ull;
+      w[k] = (ls < t.nls) ? occ[gseg(t, l)] : 0ull;
+      l = next(t, l);
     }
   };
   // the pairs of runs of the tile to unite: -x neighbour of the first cell,
   // overlaps with the +y and +z rows inside the tile (through the periodic
   // boundary when the tile spans the whole axis); f(ls, r, ls2, r2)
-  auto tile_pairs = [&](const Tile &t, int ls, uint64_t m, auto &&f) {
-    const int lz = ls / t.rw, rem = ls - lz * t.rw;
-    const int ly = rem / words, sgx = rem - ly * words;
+  auto tile_pairs = [&](const Tile &t, int ls, const Loc &lc, uint64_t m, auto &&f) {
+    const int lz = lc.lz, ly = lc.ly, sgx = lc.sx;
     if (m & 1ull) {
       const int lsl = (sgx > 0) ? ls - 1 : ls + words - 1;
       const int lbit = (sgx > 0) ? 63 : (nx - 1) - 64 * (words - 1);
@@ -310,6 +329,10 @@ __global__ __launch_bounds__(kBlock) void k_label_local(const uint64_t *__restri
   if ((int)blockIdx.x < ntile) load(blockIdx.x, nxt);
   for (int tl = blockIdx.x; tl < ntile; tl += gridDim.x) {  // workgroup-uniform
     const Tile t = tile_of(tl);
+    Loc loc[PER];
+    loc[0] = locate(t, (int)threadIdx.x * PER);
+#pragma unroll
+    for (int k = 1; k < PER; ++k) loc[k] = next(t, loc[k - 1]);
     uint64_t cur[PER];
     int cnt = 0;
 #pragma unroll
@@ -352,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_label_local(const uint64_t *__restri
       for (int k = 0; k < PER; ++k) {
         const int ls = (int)threadIdx.x * PER + k;
         if (ls >= t.nls || cur[k] == 0) continue;
-        tile_pairs(t, ls, cur[k], [&](int l1, int r1, int l2, int r2) {
+        tile_pairs(t, ls, loc[k], cur[k], [&](int l1, int r1, int l2, int r2) {
           unite_lds(par, first[l1] + r1, first[l2] + r2);
         });
       }
@@ -365,12 +388,11 @@ __global__ __launch_bounds__(kBlock) void k_label_local(const uint64_t *__restri
         int o = off;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-          const int ls = (int)threadIdx.x * PER + k;
           const int nr = __popcll(cur[k] & ~(cur[k] << 1));
           isroot[k] = 0;
           for (int r = 0; r < nr; ++r) isroot[k] |= (par[o + r] == o + r) ? (1u << r) : 0u;
           if (isroot[k]) {
-            const int64_t g = gseg(t, ls);
+            const int64_t g = gseg(t, loc[k]);
             for (int r = 0; r < nr; ++r)
               if ((isroot[k] >> r) & 1u) par[o + r] = ~(int32_t)((g << sh) + r);
           }
@@ -384,10 +406,9 @@ __global__ __launch_bounds__(kBlock) void k_label_local(const uint64_t *__restri
         int o = off;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-          const int ls = (int)threadIdx.x * PER + k;
           const int nr = __popcll(cur[k] & ~(cur[k] << 1));
           if (nr > 0) {
-            const int64_t g = gseg(t, ls);
+            const int64_t g = gseg(t, loc[k]);
             for (int r = 0; r < nr; ++r) {
               if ((isroot[k] >> r) & 1u) continue;
               int v = par[o + r];
@@ -403,8 +424,8 @@ __global__ __launch_bounds__(kBlock) void k_label_local(const uint64_t *__restri
       for (int k = 0; k < PER; ++k) {
         const int ls = (int)threadIdx.x * PER + k;
         if (ls >= t.nls || cur[k] == 0) continue;
-        tile_pairs(t, ls, cur[k], [&](int l1, int r1, int l2, int r2) {
-          unite(T, (int32_t)((gseg(t, l1) << sh) + r1), (int32_t)((gseg(t, l2) << sh) + r2));
+        tile_pairs(t, ls, loc[k], cur[k], [&](int l1, int r1, int l2, int r2) {
+          unite(T, (int32_t)((gseg(t, locate(t, l1)) << sh) + r1), (int32_t)((gseg(t, locate(t, l2)) << sh) + r2));
         });
       }
     }
