@@ -869,14 +869,21 @@ __global__ __launch_bounds__(kBlock) void k_drop_scan(const int32_t *__restrict_
       const bool valid = l > 0 && l <= K;
       uint64_t todo = __ballot(valid);
       if (!todo) continue;  // wave-uniform
-      // coordinates of this lane's cell and of the wavefront's first cell
-      const uint32_t pc = valid ? (uint32_t)p : (uint32_t)pw;
-      const uint32_t r = fast_div(pc, fnx), zz = fast_div(r, fny);
-      const int c[3] = {(int)(pc - r * (uint32_t)nx), (int)(r - zz * (uint32_t)ny), (int)zz};
-      const uint32_t rw = fast_div((uint32_t)pw, fnx);
-      const uint32_t rl = fast_div((uint32_t)(pw + 63 < n3 ? pw + 63 : n3 - 1), fnx);
-      const bool one_row = (rw == rl);  // wave-uniform: cell x = x of the first cell + lane
-      const int xw = (int)((uint32_t)pw - rw * (uint32_t)nx);
+      // row of the wavefront's first and last cells (wave-uniform, scalar)
+      const uint32_t pw32 = __builtin_amdgcn_readfirstlane((uint32_t)pw);
+      const uint32_t rw = fast_div(pw32, fnx);
+      const uint32_t rl = fast_div((uint32_t)(pw32 + 63 < n3 ? pw32 + 63 : n3 - 1), fnx);
+      const bool one_row = (rw == rl);  // cell x = x of the first cell + lane
+      const int xw = (int)(pw32 - rw * (uint32_t)nx);
+      // coordinates of this lane's cell (needed only when the cells span two rows)
+      int c[3] = {0, 0, 0};
+      if (!one_row) {
+        const uint32_t pc = valid ? (uint32_t)p : pw32;
+        const uint32_t r = fast_div(pc, fnx), zz = fast_div(r, fny);
+        c[0] = (int)(pc - r * (uint32_t)nx);
+        c[1] = (int)(r - zz * (uint32_t)ny);
+        c[2] = (int)zz;
+      }
       while (todo) {
         const int leader = __ffsll((unsigned long long)todo) - 1;
         const int32_t lv = __shfl(l, leader, 64);
@@ -893,7 +900,7 @@ __global__ __launch_bounds__(kBlock) void k_drop_scan(const int32_t *__restrict_
           e[2] = mhi ? xw + (__ffsll((unsigned long long)mhi) - 1) - (nx - h[0]) : xw + lo + h[0];
           e[3] = mlo ? xw + (63 - __clzll(mlo)) + h[0] : xw + hi - (nx - h[0]);
           // y and z are those of the row
-          const int yr = __shfl(c[1], leader, 64), zr = __shfl(c[2], leader, 64);
+          const int zr = (int)fast_div(rw, fny), yr = (int)(rw - (uint32_t)zr * (uint32_t)ny);
           e[4] = e[5] = yr;
           e[6] = e[7] = (yr + h[1] >= ny) ? yr + h[1] - ny : yr + h[1];
           e[8] = e[9] = zr;
