@@ -11,7 +11,7 @@
 
 #include "vofmt.h"
 
-enum { kNumSlotsDecl = 26 };
+enum { kNumSlotsDecl = 27 };
 
 // One timed launch: HIP events recorded before and after it on its stream.
 struct ProfRec {
@@ -69,7 +69,8 @@ enum ScratchSlot {
   SLOT_RECOLOR_LIST = 23,  // recolouring: drop-boundary and shared cells
   SLOT_OCC = 24,           // recolouring, stencil mode: occupancy bits per 64-cell row segment
   SLOT_OCC_OTHERS = 25,    // and those of the other tracers
-  kNumSlots = 26,
+  SLOT_LIST_BITS = 26,     // interface-cell lists: one bit per cell from the counting pass
+  kNumSlots = 27,
 };
 static_assert(kNumSlots == kNumSlotsDecl, "scratch slot count");
 

@@ -1,5 +1,6 @@
 // Lists of the interface (mixed) cells of one field in increasing cell order:
-// block counts, a tiled scan, then a second pass that writes the list. No
+// block counts (with one bit per cell), a tiled scan, then a second pass that
+// writes the list from the bits. No
 // atomics, so the order is fixed. A cell is an interface cell when its value
 // lies more than 1e-12 inside (0, 1); round-off residues of pure cells are not.
 #pragma once
@@ -23,16 +24,23 @@ __device__ __forceinline__ bool is_mixed(double v) { return v > kResidue && v < 
 constexpr int kPer = 8;
 constexpr int64_t kCells = (int64_t)kBlock * kPer;
 
-// Mixed cells per block of kCells cells.
+// Mixed cells per block of kCells cells, and the mixed-cell bits: word
+// p / 64 of `bits` for the 64 cells p of a wavefront's sub-chunk (64-aligned).
 __global__ __launch_bounds__(kBlock) void k_block_counts(const double *__restrict__ c, int64_t n3,
-                                                         int32_t *__restrict__ bc) {
+                                                         int32_t *__restrict__ bc, uint64_t *__restrict__ bits) {
   const int64_t p0 = (int64_t)blockIdx.x * kCells + threadIdx.x;
   double v[kPer];
 #pragma unroll
   for (int k = 0; k < kPer; ++k) v[k] = (p0 + k * kBlock < n3) ? c[p0 + k * kBlock] : 0.0;
   int n = 0;  // wavefront-uniform
+  const int64_t pw0 = p0 - (threadIdx.x & 63);  // the wavefront's first cell of sub-chunk 0
 #pragma unroll
-  for (int k = 0; k < kPer; ++k) n += (int)__popcll(__ballot(p0 + k * kBlock < n3 && is_mixed(v[k])));
+  for (int k = 0; k < kPer; ++k) {
+    const uint64_t mk = __ballot(p0 + k * kBlock < n3 && is_mixed(v[k]));
+    n += (int)__popcll(mk);
+    const int64_t pw = pw0 + k * kBlock;
+    if ((threadIdx.x & 63) == 0 && pw < n3) bits[pw >> 6] = mk;
+  }
   __shared__ int wc[kBlock / 64];
   if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = n;
   __syncthreads();
@@ -93,24 +101,26 @@ __global__ __launch_bounds__(kTile) void k_scan_totals(int32_t *__restrict__ tot
 }
 
 // Ordered list: block b writes its mixed cells from bc[b] + tot[b / kTile],
-// sub-chunk by sub-chunk, wavefront by wavefront. With kappa/status given,
+// sub-chunk by sub-chunk, wavefront by wavefront, from the bits of the
+// counting pass (the field is not read again). With kappa/status given,
 // also writes NaN / 0 into every cell that is not mixed.
-__global__ __launch_bounds__(kBlock) void k_write_ordered(const double *__restrict__ c, int64_t n3,
+__global__ __launch_bounds__(kBlock) void k_write_ordered(const uint64_t *__restrict__ bits, int64_t n3,
                                                           const int32_t *__restrict__ bc,
                                                           const int32_t *__restrict__ tot, int32_t *__restrict__ list,
                                                           double *__restrict__ kappa, uint8_t *__restrict__ status) {
   const int64_t p0 = (int64_t)blockIdx.x * kCells + threadIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  double v[kPer];
+  const int64_t pw0 = p0 - lane;
+  uint64_t wd[kPer];
 #pragma unroll
-  for (int k = 0; k < kPer; ++k) v[k] = (p0 + k * kBlock < n3) ? c[p0 + k * kBlock] : 0.0;
+  for (int k = 0; k < kPer; ++k) wd[k] = (pw0 + k * kBlock < n3) ? bits[(pw0 + k * kBlock) >> 6] : 0ull;
   __shared__ int wc[kPer][kBlock / 64];
   uint64_t mk[kPer];
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     const int64_t p = p0 + k * kBlock;
     const bool inside = p < n3;
-    const bool mixed = inside && is_mixed(v[k]);
+    const bool mixed = inside && ((wd[k] >> lane) & 1ull);
     if (inside && !mixed && kappa) {
       kappa[p] = __builtin_nan("");
       status[p] = 0;
@@ -132,15 +142,16 @@ __global__ __launch_bounds__(kBlock) void k_write_ordered(const double *__restri
 
 // The ordered list of the mixed cells of c into `list` (capacity n3), its
 // length into tot[ntiles] on the device. bc: ceil(n3 / kBlock) ints of
-// scratch; tot: ntiles + 1 ints, ntiles = ceil(bc length / kTile).
+// scratch; tot: ntiles + 1 ints, ntiles = ceil(bc length / kTile); bits:
+// ceil(n3 / 64) words of scratch.
 inline void launch_ordered_list(const double *c, int64_t n3, int32_t *bc, int32_t *tot, int32_t *list, double *kappa,
-                                uint8_t *status, hipStream_t stream) {
+                                uint8_t *status, uint64_t *bits, hipStream_t stream) {
   const int64_t nb = (n3 + kCells - 1) / kCells;
   const int64_t ntiles = (nb + kTile - 1) / kTile;
-  hipLaunchKernelGGL(k_block_counts, dim3((unsigned)nb), dim3(kBlock), 0, stream, c, n3, bc);
+  hipLaunchKernelGGL(k_block_counts, dim3((unsigned)nb), dim3(kBlock), 0, stream, c, n3, bc, bits);
   hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)ntiles), dim3(kTile), 0, stream, bc, nb, tot, (int64_t)0, (int64_t)0);
   hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kTile), 0, stream, tot, ntiles, (int64_t)0);
-  hipLaunchKernelGGL(k_write_ordered, dim3((unsigned)nb), dim3(kBlock), 0, stream, c, n3, bc, tot, list, kappa,
+  hipLaunchKernelGGL(k_write_ordered, dim3((unsigned)nb), dim3(kBlock), 0, stream, bits, n3, bc, tot, list, kappa,
                      status);
 }
 

@@ -58,9 +58,10 @@ extern "C" int vofmt_curvature_hf(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_
   int32_t *list = (int32_t *)scratch(ctx, SLOT_CURV_LIST, sizeof(int32_t) * (size_t)n3);
   int32_t *bc = (int32_t *)scratch(ctx, SLOT_MISC, sizeof(int32_t) * (size_t)ceil_div(n3, compact::kBlock));
   int32_t *tot = (int32_t *)scratch(ctx, SLOT_CURV_COUNT, sizeof(int32_t) * (size_t)(ntiles + 1));
-  if (!list || !bc || !tot) return VOFMT_E_NOMEM;
+  uint64_t *bits = (uint64_t *)scratch(ctx, SLOT_LIST_BITS, sizeof(uint64_t) * (size_t)ceil_div(n3, 64));
+  if (!list || !bc || !tot || !bits) return VOFMT_E_NOMEM;
   int rec = prof_begin(ctx, "mixed_list", stream);
-  compact::launch_ordered_list(c, n3, bc, tot, list, kappa, status, stream);
+  compact::launch_ordered_list(c, n3, bc, tot, list, kappa, status, bits, stream);
   prof_end(ctx, rec, stream);
   const int32_t *count = tot + ntiles;
   rec = prof_begin(ctx, "k_curv_hf_list", stream);

@@ -908,8 +908,9 @@ extern "C" int vofmt_mlp_stencils(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32_
   int32_t *tot = (int32_t *)scratch(ctx, SLOT_MISC2, sizeof(int32_t) * (size_t)(ntiles + 1));
   int32_t *list = (int32_t *)scratch(ctx, SLOT_CURV_LIST, sizeof(int32_t) * (size_t)n3);
   int32_t *hc = (int32_t *)host_scratch(ctx, sizeof(int32_t) * 2);
-  if (!bc || !tot || !list || !hc) return VOFMT_E_NOMEM;
-  compact::launch_ordered_list(c, n3, bc, tot, list, (double *)nullptr, (uint8_t *)nullptr, stream);
+  uint64_t *bits = (uint64_t *)scratch(ctx, SLOT_LIST_BITS, sizeof(uint64_t) * (size_t)ceil_div(n3, 64));
+  if (!bc || !tot || !list || !hc || !bits) return VOFMT_E_NOMEM;
+  compact::launch_ordered_list(c, n3, bc, tot, list, (double *)nullptr, (uint8_t *)nullptr, bits, stream);
   VOFMT_HIP(ctx, hipGetLastError());
   VOFMT_HIP(ctx, hipMemcpyAsync(hc, tot + ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
   VOFMT_HIP(ctx, hipStreamSynchronize(stream));
@@ -940,10 +941,11 @@ extern "C" int vofmt_curvature_mlp(vofmt_ctx *ctx, int32_t nx, int32_t ny, int32
   const int fgrid_max = persistent_grid(ctx, k_curv_fused, FWAVES, INT32_MAX);
   int32_t *tot = (int32_t *)scratch(ctx, SLOT_CURV_COUNT, sizeof(int32_t) * (size_t)(lt + 1 + fgrid_max));
   int32_t *hc = (int32_t *)host_scratch(ctx, sizeof(int32_t) * 2);
-  if (!list || !bc || !tot || !hc) return VOFMT_E_NOMEM;
+  uint64_t *bits = (uint64_t *)scratch(ctx, SLOT_LIST_BITS, sizeof(uint64_t) * (size_t)ceil_div(n3, 64));
+  if (!list || !bc || !tot || !hc || !bits) return VOFMT_E_NOMEM;
   int32_t *hf_counts = tot + lt + 1;  // fallback cells per workgroup of the fused kernel
   int rec = prof_begin(ctx, "mixed_list", stream);
-  compact::launch_ordered_list(c, n3, bc, tot, list, kappa, status, stream);
+  compact::launch_ordered_list(c, n3, bc, tot, list, kappa, status, bits, stream);
   prof_end(ctx, rec, stream);
   VOFMT_HIP(ctx, hipGetLastError());
   VOFMT_HIP(ctx, hipMemcpyAsync(hc, tot + lt, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
