@@ -160,56 +160,32 @@ inline int64_t list_tiles(int64_t n3) { return ((n3 + kCells - 1) / kCells + kTi
 // Scan tiles of a predicate list of n cells (one block count per kBlock cells).
 inline int64_t list_tiles_if(int64_t n) { return ((n + kBlock - 1) / kBlock + kTile - 1) / kTile; }
 
-// The same for any predicate pr(p) over cells 0..n-1. The counting pass also
-// stores the predicate as one bit per cell (`bits`, one 64-bit word per
-// wavefront of cells), so the writing pass reads the bits instead of
-// evaluating the predicate again.
-template <class Pred>
-__global__ __launch_bounds__(kBlock) void k_block_counts_if(int64_t n, Pred pr, int32_t *__restrict__ bc,
-                                                            uint64_t *__restrict__ bits) {
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool hit = p < n && pr(p);
-  __shared__ int wc[kBlock / 64];
-  const uint64_t mask = __ballot(hit);
-  if ((threadIdx.x & 63) == 0) {
-    wc[threadIdx.x >> 6] = (int)__popcll(mask);
-    if (p < n) bits[p >> 6] = mask;  // (a wavefront wholly past n has no word)
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int t = 0;
-    for (int w = 0; w < kBlock / 64; ++w) t += wc[w];
-    bc[blockIdx.x] = t;
-  }
-}
+// Ordered lists of the cells p < n of a predicate whose counting pass stores
+// it as one bit per cell (one 64-bit word per wavefront of cells) and one
+// count per kBlock cells: the writing pass reads the bits.
+// One wavefront per block of kBlock cells (its kBlock / 64 words), four
+// blocks per workgroup: word j's set bits are written in round j, after the
+// block's offset and the bits of its earlier words.
 __global__ __launch_bounds__(kBlock) void k_write_ordered_bits(int64_t n, const uint64_t *__restrict__ bits,
                                                                const int32_t *__restrict__ bc,
                                                                const int32_t *__restrict__ tot,
                                                                int32_t *__restrict__ list) {
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __shared__ uint64_t wm[kBlock / 64];
-  if (lane == 0) wm[w] = (p < n) ? bits[p >> 6] : 0ull;
-  __syncthreads();
-  const uint64_t mask = wm[w];
-  if (!((mask >> lane) & 1ull)) return;
-  int idx = bc[blockIdx.x] + tot[blockIdx.x / kTile];
-  for (int k = 0; k < w; ++k) idx += (int)__popcll(wm[k]);
-  idx += (int)__popcll(mask & ((1ull << lane) - 1));
-  list[idx] = (int32_t)p;
-}
-
-// Ordered list of the cells p < n with pr(p); its length into tot[list_tiles_if(n)].
-// bits: scratch of (n + 63) / 64 words.
-template <class Pred>
-inline void launch_ordered_list_if(int64_t n, Pred pr, int32_t *bc, int32_t *tot, int32_t *list, uint64_t *bits,
-                                   hipStream_t stream) {
+  constexpr int kWords = kBlock / 64;
+  const int lane = threadIdx.x & 63;
+  const int64_t b = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);  // this wavefront's block
   const int64_t nb = (n + kBlock - 1) / kBlock;
-  const int64_t ntiles = (nb + kTile - 1) / kTile;
-  hipLaunchKernelGGL(k_block_counts_if<Pred>, dim3((unsigned)nb), dim3(kBlock), 0, stream, n, pr, bc, bits);
-  hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)ntiles), dim3(kTile), 0, stream, bc, nb, tot, (int64_t)0, (int64_t)0);
-  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kTile), 0, stream, tot, ntiles, (int64_t)0);
-  hipLaunchKernelGGL(k_write_ordered_bits, dim3((unsigned)nb), dim3(kBlock), 0, stream, n, bits, bc, tot, list);
+  if (b >= nb) return;  // whole wavefront
+  const int64_t c0 = b * kBlock;
+  uint64_t wm[kWords];
+#pragma unroll
+  for (int j = 0; j < kWords; ++j) wm[j] = (c0 + 64 * j < n) ? bits[(c0 >> 6) + j] : 0ull;
+  int idx = bc[b] + tot[b / kTile];
+  const uint64_t below = (1ull << lane) - 1;
+#pragma unroll
+  for (int j = 0; j < kWords; ++j) {
+    if ((wm[j] >> lane) & 1ull) list[idx + (int)__popcll(wm[j] & below)] = (int32_t)(c0 + 64 * j + lane);
+    idx += (int)__popcll(wm[j]);
+  }
 }
 
 }  // namespace

@@ -171,24 +171,53 @@ __device__ __forceinline__ void edges_of(const int32_t *__restrict__ own, const 
 // a boundary cell of its drop does not: a lattice path from it towards any
 // other drop's cell, one axis step at a time, only gets closer and leaves the
 // drop through a boundary cell.
-struct PairSources {
-  const int32_t *own;
-  int nx, ny, nz;
-  FastDiv fnx, fny;  // cells < 2^31: multiply-shift division
-  __device__ bool operator()(int64_t p) const {
-    const int32_t a = own[p];
-    if (a == -1) return false;
-    if (a == -2) return true;
-    const uint32_t r = fast_div((uint32_t)p, fnx), zz = fast_div(r, fny);
-    const int x = (int)((uint32_t)p - r * (uint32_t)nx), y = (int)(r - zz * (uint32_t)ny), z = (int)zz;
-    const int64_t row = (int64_t)y * nx, plane = (int64_t)z * ny * nx;
-    return !(own[plane + row + wrap_dec(x, nx)] == a && own[plane + row + wrap_inc(x, nx)] == a &&
-             own[plane + (int64_t)wrap_dec(y, ny) * nx + x] == a &&
-             own[plane + (int64_t)wrap_inc(y, ny) * nx + x] == a &&
-             own[(int64_t)wrap_dec(z, nz) * ny * nx + row + x] == a &&
-             own[(int64_t)wrap_inc(z, nz) * ny * nx + row + x] == a);
+// The owner array (-1 empty, -2 shared, else the drop) of every cell gives
+// the predicate: a shared cell, or a cell of one drop with a six-neighbour
+// not owned by it. Block counts (kBlock cells) and one bit per cell, for
+// compact::k_write_ordered_bits: lane l of a wavefront holds cell p (64
+// consecutive cells), its x neighbours come from the lanes beside it, and
+// only a row's end cells and the wavefront's edge lanes load theirs. The y
+// and z neighbours are loaded for cells of one drop only.
+__global__ __launch_bounds__(kBlock) void k_pair_source_counts(const int32_t *__restrict__ own, int nx, int ny,
+                                                               int nz, FastDiv fnx, FastDiv fny, int64_t n,
+                                                               int32_t *__restrict__ bc, uint64_t *__restrict__ bits) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool in = p < n;
+  const int64_t pc = in ? p : n - 1;  // (a lane past the end shadows the last cell)
+  const int32_t a = own[pc];
+  const uint32_t r = fast_div((uint32_t)pc, fnx), zz = fast_div(r, fny);
+  const int x = (int)((uint32_t)pc - r * (uint32_t)nx), y = (int)(r - zz * (uint32_t)ny), z = (int)zz;
+  const int64_t row = (int64_t)r * nx;
+  // x neighbours: from the lanes beside, unless across the wavefront's edge or the row's end
+  int32_t am = __shfl_up(a, 1, 64), ap = __shfl_down(a, 1, 64);
+  const bool load_m = lane == 0 || x == 0, load_p = lane == 63 || x == nx - 1;
+  if (a >= 0 && load_m) am = own[row + wrap_dec(x, nx)];
+  if (a >= 0 && load_p) ap = own[row + wrap_inc(x, nx)];
+  bool hit = false;
+  if (a == -2) {
+    hit = true;
+  } else if (a >= 0) {
+    const int64_t plane = (int64_t)ny * nx, zr = (int64_t)z * plane;
+    const int32_t ym = own[zr + (int64_t)wrap_dec(y, ny) * nx + x], yp = own[zr + (int64_t)wrap_inc(y, ny) * nx + x];
+    const int32_t zm = own[(int64_t)wrap_dec(z, nz) * plane + (int64_t)y * nx + x];
+    const int32_t zp = own[(int64_t)wrap_inc(z, nz) * plane + (int64_t)y * nx + x];
+    hit = !(am == a && ap == a && ym == a && yp == a && zm == a && zp == a);
   }
-};
+  hit = hit && in;
+  __shared__ int wc[kBlock / 64];
+  const uint64_t mask = __ballot(hit);
+  if (lane == 0) {
+    wc[threadIdx.x >> 6] = (int)__popcll(mask);
+    if (in) bits[p >> 6] = mask;  // (a wavefront wholly past n has no word)
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < kBlock / 64; ++w) t += wc[w];
+    bc[blockIdx.x] = t;
+  }
+}
 
 // Near-contact pairs seen from the listed cells (persistent grid).
 __global__ __launch_bounds__(kBlock) void k_edges(const int32_t *__restrict__ own, const int32_t *__restrict__ lab,
@@ -903,9 +932,18 @@ static int recolor_impl(vofmt_ctx *ctx, const char *fn, int stencil, int32_t nx,
     int32_t *tot = (int32_t *)scratch(ctx, SLOT_CURV_COUNT, sizeof(int32_t) * (size_t)(lt + 2));
     uint64_t *pbits = (uint64_t *)scratch(ctx, SLOT_CURV_HF, sizeof(uint64_t) * (size_t)((n3 + 63) / 64));
     if (!srcs || !bc || !tot || !pbits) return VOFMT_E_NOMEM;
-    compact::launch_ordered_list_if(
-        n3, PairSources{own, nx, ny, nz, make_fastdiv((uint32_t)nx), make_fastdiv((uint32_t)ny)}, bc, tot, srcs,
-        pbits, stream);
+    {
+      // the ordered list of those cells: counts and bits, the tiled scan, the list from the bits
+      const int64_t nb = (n3 + kBlock - 1) / kBlock, nt = (nb + compact::kTile - 1) / compact::kTile;
+      static_assert(kBlock == compact::kBlock, "block counts and the tiled scan share the block size");
+      hipLaunchKernelGGL(k_pair_source_counts, dim3((unsigned)nb), dim3(kBlock), 0, stream, own, nx, ny, nz,
+                         make_fastdiv((uint32_t)nx), make_fastdiv((uint32_t)ny), n3, bc, pbits);
+      hipLaunchKernelGGL(compact::k_scan_tile, dim3((unsigned)nt), dim3(compact::kTile), 0, stream, bc, nb, tot,
+                         (int64_t)0, (int64_t)0);
+      hipLaunchKernelGGL(compact::k_scan_totals, dim3(1), dim3(compact::kTile), 0, stream, tot, nt, (int64_t)0);
+      hipLaunchKernelGGL(compact::k_write_ordered_bits, dim3((unsigned)((nb + kBlock / 64 - 1) / (kBlock / 64))),
+                         dim3(kBlock), 0, stream, n3, pbits, bc, tot, srcs);
+    }
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
       cus = 256;
