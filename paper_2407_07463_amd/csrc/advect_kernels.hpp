@@ -59,7 +59,11 @@ struct Tiles {
   int gx, gy, gz;
 };
 __host__ __device__ inline int x_segments_per_row(int words, int wpb) { return words < wpb ? words : wpb; }
-__host__ __device__ inline int x_row_positions(int words, int chunk) { return chunk / words > 0 ? chunk / words : 1; }
+// Planes per whole-row x-sweep wavefront: half a chunk's cells (two 512-cell
+// rows at chunk 32; four measured 2% slower on that sweep).
+__host__ __device__ inline int x_row_positions(int words, int chunk) {
+  return (chunk / 2) / words > 0 ? (chunk / 2) / words : 1;
+}
 __host__ __device__ inline Tiles stream_tiles(int d, int nx, int ny, int nz, int chunk, int wpb = 4) {
   const int words = (nx + 63) / 64;
   if (d == 0 && wpb == 0) {
