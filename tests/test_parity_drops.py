@@ -125,6 +125,24 @@ def test_labels_dense_runs(ctx):
         assert np.array_equal(lab[t], ol)
 
 
+def test_labels_dense_tile_beside_local_tiles(ctx):
+    """A tile over the LDS capacity (2 runs per segment) next to tiles under it: at 40 x 70 x 64
+    (tiles of 32 x 64 rows), even-x columns over z = 29..32 hold 32 runs per segment in the
+    z = 0..31, y = 0..63 tile only, and join it through the y and z tile boundaries to the
+    tiles beside it, with blobs on the far side."""
+    shape = (40, 70, 64)
+    rng = np.random.default_rng(40)
+    c = random_blobs(rng, shape, 2, 12, 1.5, 4.0)
+    c[0, 29:33, :, ::2] = 0.7
+    c[1, 29:33, 60:70, ::2] = 0.7
+    note("label dense tile beside local tiles")
+    lab, nd = _gpu_labels(ctx, c)
+    for t in range(2):
+        ol, k = oracle.label(c[t])
+        assert nd[t] == k
+        assert np.array_equal(lab[t], ol)
+
+
 def test_labels_long_runs_and_wrap(ctx):
     # runs crossing 64-cell segment boundaries, spirals and full rows
     c = np.zeros((1, 9, 7, 200))
