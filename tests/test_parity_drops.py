@@ -364,11 +364,13 @@ def test_recolour_stencil_figure(ctx):
 
 @pytest.mark.parametrize("seed,ntr,shape", [(0, 3, (21, 26, 33)), (1, 3, (21, 26, 33)), (2, 8, (21, 26, 33)),
                                             (3, 2, (9, 70, 130)), (4, 5, (40, 7, 66)), (5, 1, (30, 30, 30)),
-                                            (6, 3, (10, 12, 256)), (7, 4, (6, 9, 512))])
+                                            (6, 3, (10, 12, 256)), (7, 4, (6, 9, 512)), (8, 4, (7, 6, 5)),
+                                            (9, 3, (12, 5, 8))])
 def test_recolour_stencil_random(ctx, seed, ntr, shape):
     """Dense random drops on ragged grids: rows shorter and longer than one 64-cell segment,
     thin axes (the stencil wraps around a 7-cell axis), one to eight tracers; rows of 256 and
-    512 cells take the occupancy words from 16-byte label loads."""
+    512 cells take the occupancy words from 16-byte label loads; rows and columns shorter than
+    the contact cube's 9 cells, whose windows wrap more than once."""
     rng = np.random.default_rng(500 + seed)
     maxt = 12
     c = np.zeros((maxt,) + shape)
